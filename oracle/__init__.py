@@ -1,0 +1,234 @@
+"""CPU oracle for the CSR SpMV / Jacobi-PCG path -- TEST INFRASTRUCTURE ONLY.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package.  The product library
+(``paper_2011_00715_amd``) never imports it, and the two share no code: the
+oracle is plain serial C (``oracle.c``, built with gcc ``-O2
+-ffp-contract=off``) reached through ctypes.  Inputs come from ``spkgen``.
+
+Every function here is pinned by CPU tests (``tests/test_oracle_pins.py``)
+against results fixed by mathematics -- closed-form Laplacian eigenpairs, exact
+integer arithmetic, brute-force dense solves, finite termination of CG -- and
+not against itself.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+REASONS = {
+    1: "CONVERGED_RTOL",
+    2: "CONVERGED_ATOL",
+    -1: "DIVERGED_ITS",
+    -2: "DIVERGED_INDEFINITE_MAT",
+    -3: "DIVERGED_INDEFINITE_PC",
+    -4: "DIVERGED_NANORINF",
+    -5: "DIVERGED_BREAKDOWN",
+}
+
+
+def build(extra_flags=()) -> str:
+    """Compile liboracle.so with gcc (always recompiles)."""
+    cmd = ["gcc", "-O2", "-ffp-contract=off", "-fPIC", "-shared", "-std=c11",
+           *extra_flags, _SRC, "-o", _LIB, "-lm"]
+    subprocess.run(cmd, check=True, cwd=_HERE)
+    return _LIB
+
+
+class _PcgResult(ctypes.Structure):
+    _fields_ = [
+        ("reason", ctypes.c_int32),
+        ("iterations", ctypes.c_int32),
+        ("restarts", ctypes.c_int32),
+        ("pad_", ctypes.c_int32),
+        ("rnorm0", ctypes.c_double),
+        ("rnorm", ctypes.c_double),
+        ("bnorm", ctypes.c_double),
+        ("true_rel_residual", ctypes.c_double),
+    ]
+
+
+_lib = None
+
+
+def load(path: str | None = None):
+    """Load liboracle.so, building it first only if it does not exist."""
+    global _lib
+    if _lib is not None and path is None:
+        return _lib
+    p = path or _LIB
+    if not os.path.exists(p):
+        build()
+    lib = ctypes.CDLL(p)
+    P = ctypes.c_void_p
+    i32 = ctypes.c_int32
+    d = ctypes.c_double
+    lib.orc_spmv.argtypes = [i32, P, P, P, P, P]
+    lib.orc_spmv_f32.argtypes = [i32, P, P, P, P, P]
+    lib.orc_spmv_abs.argtypes = [i32, P, P, P, P, P]
+    lib.orc_spmv_rows.argtypes = [i32, P, P, P, P, P, P, P]
+    lib.orc_dot.argtypes = [i32, P, P]
+    lib.orc_dot.restype = d
+    lib.orc_nrm2.argtypes = [i32, P]
+    lib.orc_nrm2.restype = d
+    lib.orc_axpy.argtypes = [i32, d, P, P]
+    lib.orc_aypx.argtypes = [i32, d, P, P]
+    lib.orc_diag_inv.argtypes = [i32, P, P, P, P]
+    lib.orc_diag_inv.restype = ctypes.c_int
+    lib.orc_jacobi_apply.argtypes = [i32, P, P, P]
+    lib.orc_pcg.argtypes = [i32, P, P, P, P, P, d, d, i32, i32, P, i32,
+                            ctypes.POINTER(_PcgResult)]
+    lib.orc_pcg.restype = ctypes.c_int
+    lib.orc_dense_cholesky_solve.argtypes = [i32, P, P]
+    lib.orc_dense_cholesky_solve.restype = ctypes.c_int
+    if path is None:
+        _lib = lib
+    return lib
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _c(a, dtype):
+    return np.ascontiguousarray(a, dtype=dtype)
+
+
+def _csr(A):
+    return _c(A.rowptr, np.int32), _c(A.col, np.int32)
+
+
+def spmv(A, x, lib=None) -> np.ndarray:
+    """y = A x in FP64 (long-double accumulation, rounded once)."""
+    lib = lib or load()
+    rp, ci = _csr(A)
+    v = _c(A.val, np.float64)
+    x = _c(x, np.float64)
+    y = np.empty(A.n, dtype=np.float64)
+    lib.orc_spmv(A.n, _ptr(rp), _ptr(ci), _ptr(v), _ptr(x), _ptr(y))
+    return y
+
+
+def spmv_f32(A, x32, val32=None, lib=None) -> np.ndarray:
+    """y = A32 x32 with FP32 values and x, exact sum rounded to FP32 once."""
+    lib = lib or load()
+    rp, ci = _csr(A)
+    v = _c(A.val if val32 is None else val32, np.float32)
+    x = _c(x32, np.float32)
+    y = np.empty(A.n, dtype=np.float32)
+    lib.orc_spmv_f32(A.n, _ptr(rp), _ptr(ci), _ptr(v), _ptr(x), _ptr(y))
+    return y
+
+
+def spmv_abs(A, x, lib=None) -> np.ndarray:
+    """sum_j |a_ij x_j| per row (the scale of the per-entry tolerance)."""
+    lib = lib or load()
+    rp, ci = _csr(A)
+    v = _c(A.val, np.float64)
+    x = _c(x, np.float64)
+    y = np.empty(A.n, dtype=np.float64)
+    lib.orc_spmv_abs(A.n, _ptr(rp), _ptr(ci), _ptr(v), _ptr(x), _ptr(y))
+    return y
+
+
+def spmv_rows(A, x, rows, lib=None):
+    """(A x)_i and sum_j |a_ij x_j| for the selected rows only."""
+    lib = lib or load()
+    rp, ci = _csr(A)
+    v = _c(A.val, np.float64)
+    x = _c(x, np.float64)
+    rows = _c(rows, np.int32)
+    y = np.empty(rows.size, dtype=np.float64)
+    ya = np.empty(rows.size, dtype=np.float64)
+    lib.orc_spmv_rows(rows.size, _ptr(rows), _ptr(rp), _ptr(ci), _ptr(v), _ptr(x),
+                      _ptr(y), _ptr(ya))
+    return y, ya
+
+
+def dot(x, y, lib=None) -> float:
+    lib = lib or load()
+    x = _c(x, np.float64)
+    y = _c(y, np.float64)
+    return lib.orc_dot(x.size, _ptr(x), _ptr(y))
+
+
+def nrm2(x, lib=None) -> float:
+    lib = lib or load()
+    x = _c(x, np.float64)
+    return lib.orc_nrm2(x.size, _ptr(x))
+
+
+def axpy(alpha, x, y, lib=None) -> np.ndarray:
+    """Returns alpha x + y (exact, rounded once)."""
+    lib = lib or load()
+    x = _c(x, np.float64)
+    out = np.array(y, dtype=np.float64, copy=True)
+    lib.orc_axpy(x.size, float(alpha), _ptr(x), _ptr(out))
+    return out
+
+
+def aypx(beta, x, y, lib=None) -> np.ndarray:
+    """Returns x + beta y (exact, rounded once)."""
+    lib = lib or load()
+    x = _c(x, np.float64)
+    out = np.array(y, dtype=np.float64, copy=True)
+    lib.orc_aypx(x.size, float(beta), _ptr(x), _ptr(out))
+    return out
+
+
+def diag_inv(A, lib=None):
+    lib = lib or load()
+    rp, ci = _csr(A)
+    v = _c(A.val, np.float64)
+    out = np.empty(A.n, dtype=np.float64)
+    st = lib.orc_diag_inv(A.n, _ptr(rp), _ptr(ci), _ptr(v), _ptr(out))
+    if st:
+        raise ValueError("zero or missing diagonal")
+    return out
+
+
+def jacobi_apply(dinv, r, lib=None) -> np.ndarray:
+    lib = lib or load()
+    dinv = _c(dinv, np.float64)
+    r = _c(r, np.float64)
+    z = np.empty_like(r)
+    lib.orc_jacobi_apply(r.size, _ptr(dinv), _ptr(r), _ptr(z))
+    return z
+
+
+def pcg(A, b, x0=None, rtol=1e-8, atol=0.0, maxit=10000, hist_len=0, lib=None):
+    """FP64 Jacobi-PCG.  Returns (x, result dict, history array or None)."""
+    lib = lib or load()
+    rp, ci = _csr(A)
+    v = _c(A.val, np.float64)
+    b = _c(b, np.float64)
+    x = np.zeros(A.n) if x0 is None else np.array(x0, dtype=np.float64, copy=True)
+    hist = np.full(max(hist_len, 1), np.nan)
+    res = _PcgResult()
+    st = lib.orc_pcg(A.n, _ptr(rp), _ptr(ci), _ptr(v), _ptr(b), _ptr(x), float(rtol),
+                     float(atol), int(maxit), int(x0 is not None),
+                     _ptr(hist) if hist_len > 0 else None, int(hist_len), ctypes.byref(res))
+    if st:
+        raise ValueError(f"oracle pcg failed with status {st}")
+    out = {f: getattr(res, f) for f, _ in _PcgResult._fields_ if f != "pad_"}
+    out["reason_str"] = REASONS.get(res.reason, str(res.reason))
+    return x, out, (hist[: res.iterations + 1] if hist_len > 0 else None)
+
+
+def dense_cholesky_solve(D, b, lib=None):
+    """Solve D x = b for dense SPD D; raises if D is not positive definite."""
+    lib = lib or load()
+    A = np.array(D, dtype=np.float64, copy=True, order="C")
+    x = np.array(b, dtype=np.float64, copy=True)
+    st = lib.orc_dense_cholesky_solve(A.shape[0], _ptr(A), _ptr(x))
+    if st:
+        raise ValueError("matrix is not positive definite")
+    return x

@@ -1,0 +1,303 @@
+/*
+ * CPU oracle for the CSR SpMV / Jacobi-PCG path -- TEST INFRASTRUCTURE ONLY.
+ *
+ * Only the test suite, the smoke check and the bench's CPU-baseline leg may
+ * load this library.  The product library never links, loads or calls it, and
+ * it shares no source, header, table or helper with the HIP implementation.
+ *
+ * Plain, serial, slow and obviously correct.  Build with -O2 -ffp-contract=off
+ * so that the compiler never fuses a multiply and an add on its own; the only
+ * fused operations are the explicit fma() calls in the vector updates, where
+ * the plain definition is "exact result, rounded once".
+ *
+ * Precision: sums are accumulated in long double (x87 80-bit, 64-bit
+ * significand) and rounded to double once, so the oracle's own rounding error
+ * is far below the GPU tolerance and the whole tolerance budget belongs to the
+ * GPU side.
+ *
+ * What each function follows:
+ *  - The matrix is CSR ("compressed sparse row", the MATAIJ type of the
+ *    paper's Sec. 4, with 32-bit column indices and the per-nonzero byte
+ *    count of Challenge A7 in Sec. 3).
+ *  - The vector operations are the Vec operations of Sec. 5.1 (VecAXPY
+ *    y <- alpha x + y) and the inner products / norms of Sec. 4 (Response F3,
+ *    Response A1).
+ *  - The solver is the conjugate gradient method with a pointwise Jacobi
+ *    preconditioner (CG is named in Sec. 5.5, Jacobi in Sec. 5.3).  The paper
+ *    prints no CG algorithm, so this is the textbook preconditioned CG
+ *    (Hestenes & Stiefel 1952), with the readings listed at orc_pcg().
+ *
+ * Every function is pinned by CPU tests against values fixed by mathematics
+ * (closed-form eigenpairs, exact integer arithmetic, brute-force dense solves,
+ * finite termination), not against itself.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include "oracle.h"
+
+/* y_i = sum_k val[k] * x[col[k]] over k in [rowptr[i], rowptr[i+1]). */
+void orc_spmv(int32_t n, const int32_t *rowptr, const int32_t *col,
+              const double *val, const double *x, double *y)
+{
+    for (int32_t i = 0; i < n; ++i) {
+        long double s = 0.0L;
+        for (int32_t k = rowptr[i]; k < rowptr[i + 1]; ++k)
+            s += (long double)val[k] * (long double)x[col[k]];
+        y[i] = (double)s;
+    }
+}
+
+/* Same product for FP32 values and FP32 x: the product of two floats is exact
+ * in long double, the sum is accumulated in long double and rounded to float
+ * once (the reference the FP32-value kernels are judged against). */
+void orc_spmv_f32(int32_t n, const int32_t *rowptr, const int32_t *col,
+                  const float *val, const float *x, float *y)
+{
+    for (int32_t i = 0; i < n; ++i) {
+        long double s = 0.0L;
+        for (int32_t k = rowptr[i]; k < rowptr[i + 1]; ++k)
+            s += (long double)val[k] * (long double)x[col[k]];
+        y[i] = (float)s;
+    }
+}
+
+/* sum_i |val| * |x| per row: the scale the per-entry SpMV tolerance uses. */
+void orc_spmv_abs(int32_t n, const int32_t *rowptr, const int32_t *col,
+                  const double *val, const double *x, double *y)
+{
+    for (int32_t i = 0; i < n; ++i) {
+        long double s = 0.0L;
+        for (int32_t k = rowptr[i]; k < rowptr[i + 1]; ++k)
+            s += fabsl((long double)val[k] * (long double)x[col[k]]);
+        y[i] = (double)s;
+    }
+}
+
+/* Selected rows only: y[j] = (A x)_{rows[j]} (for spot checks at full size). */
+void orc_spmv_rows(int32_t nrows, const int32_t *rows, const int32_t *rowptr,
+                   const int32_t *col, const double *val, const double *x,
+                   double *y, double *yabs)
+{
+    for (int32_t j = 0; j < nrows; ++j) {
+        int32_t i = rows[j];
+        long double s = 0.0L, a = 0.0L;
+        for (int32_t k = rowptr[i]; k < rowptr[i + 1]; ++k) {
+            long double t = (long double)val[k] * (long double)x[col[k]];
+            s += t;
+            a += fabsl(t);
+        }
+        y[j] = (double)s;
+        if (yabs) yabs[j] = (double)a;
+    }
+}
+
+double orc_dot(int32_t n, const double *x, const double *y)
+{
+    long double s = 0.0L;
+    for (int32_t i = 0; i < n; ++i)
+        s += (long double)x[i] * (long double)y[i];
+    return (double)s;
+}
+
+double orc_nrm2(int32_t n, const double *x)
+{
+    long double s = 0.0L;
+    for (int32_t i = 0; i < n; ++i)
+        s += (long double)x[i] * (long double)x[i];
+    return (double)sqrtl(s);
+}
+
+/* y <- alpha x + y, exact product-plus-sum rounded once. */
+void orc_axpy(int32_t n, double alpha, const double *x, double *y)
+{
+    for (int32_t i = 0; i < n; ++i)
+        y[i] = fma(alpha, x[i], y[i]);
+}
+
+/* y <- x + beta y, exact product-plus-sum rounded once. */
+void orc_aypx(int32_t n, double beta, const double *x, double *y)
+{
+    for (int32_t i = 0; i < n; ++i)
+        y[i] = fma(beta, y[i], x[i]);
+}
+
+/* Jacobi preconditioner setup: dinv_i = 1 / a_ii.  Returns 0, or -4 if some
+ * row has no stored diagonal or a zero diagonal. */
+int orc_diag_inv(int32_t n, const int32_t *rowptr, const int32_t *col,
+                 const double *val, double *dinv)
+{
+    for (int32_t i = 0; i < n; ++i) {
+        double d = 0.0;
+        for (int32_t k = rowptr[i]; k < rowptr[i + 1]; ++k)
+            if (col[k] == i) d += val[k];
+        if (d == 0.0) return ORC_EZERODIAG;
+        dinv[i] = 1.0 / d;
+    }
+    return 0;
+}
+
+/* Jacobi PCApply: z_i = dinv_i * r_i. */
+void orc_jacobi_apply(int32_t n, const double *dinv, const double *r, double *z)
+{
+    for (int32_t i = 0; i < n; ++i) z[i] = dinv[i] * r[i];
+}
+
+static int finite_d(double v) { return isfinite(v); }
+
+/*
+ * Jacobi-preconditioned conjugate gradient, FP64.
+ *
+ * Readings (the paper prints no algorithm and no stopping rule):
+ *  - x0 = 0 unless x0_nonzero; r = b - A x0.
+ *  - Convergence on the unpreconditioned recursive residual:
+ *    ||r_k||_2 <= max(rtol ||b||_2, atol).  Reason RTOL if ||r_k|| <= rtol ||b||,
+ *    otherwise ATOL.  ||b|| = 0 returns x = 0, CONVERGED_ATOL, 0 iterations.
+ *  - When the recursive test passes, the true residual b - A x is formed; if
+ *    it fails the same test, CG restarts from the current x with the true
+ *    residual (p = z); after 3 such restarts the solve stops with BREAKDOWN.
+ *  - eta = p.Ap <= 0 -> INDEFINITE_MAT (x not updated); rho' = r.z < 0 ->
+ *    INDEFINITE_PC; rho' = 0 -> BREAKDOWN; any non-finite scalar -> NANORINF.
+ *  - k reaching maxit without convergence -> DIVERGED_ITS.
+ * hist (if not NULL, hist_len entries) receives ||r_k|| for k = 0.. .
+ */
+int orc_pcg(int32_t n, const int32_t *rowptr, const int32_t *col,
+            const double *val, const double *b, double *x, double rtol,
+            double atol, int32_t maxit, int32_t x0_nonzero, double *hist,
+            int32_t hist_len, orc_pcg_result *res)
+{
+    memset(res, 0, sizeof(*res));
+    double *dinv = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    double *r = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    double *z = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    double *p = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    double *q = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    int status = 0;
+    if (!dinv || !r || !z || !p || !q) { status = ORC_ENOMEM; goto done; }
+    status = orc_diag_inv(n, rowptr, col, val, dinv);
+    if (status) goto done;
+
+    double bnorm = orc_nrm2(n, b);
+    res->bnorm = bnorm;
+    double thresh = rtol * bnorm > atol ? rtol * bnorm : atol;
+    if (bnorm == 0.0) {
+        for (int32_t i = 0; i < n; ++i) x[i] = 0.0;
+        res->reason = ORC_CONVERGED_ATOL;
+        if (hist && hist_len > 0) hist[0] = 0.0;
+        goto done;
+    }
+    if (x0_nonzero) {
+        orc_spmv(n, rowptr, col, val, x, q);
+        for (int32_t i = 0; i < n; ++i) r[i] = b[i] - q[i];
+    } else {
+        for (int32_t i = 0; i < n; ++i) { x[i] = 0.0; r[i] = b[i]; }
+    }
+    double rnorm = orc_nrm2(n, r);
+    res->rnorm0 = rnorm;
+    if (hist && hist_len > 0) hist[0] = rnorm;
+    int32_t k = 0;
+    int restarts = 0;
+    double rho = 0.0;
+
+    for (;;) { /* (re)start from the current x with a true residual in r */
+        if (!finite_d(rnorm)) { res->reason = ORC_DIVERGED_NANORINF; break; }
+        if (rnorm <= thresh) {
+            res->reason = rnorm <= rtol * bnorm ? ORC_CONVERGED_RTOL : ORC_CONVERGED_ATOL;
+            break;
+        }
+        orc_jacobi_apply(n, dinv, r, z);
+        rho = orc_dot(n, r, z);
+        if (!finite_d(rho)) { res->reason = ORC_DIVERGED_NANORINF; break; }
+        if (rho < 0.0) { res->reason = ORC_DIVERGED_INDEFINITE_PC; break; }
+        if (rho == 0.0) { res->reason = ORC_DIVERGED_BREAKDOWN; break; }
+        memcpy(p, z, sizeof(double) * (size_t)n);
+
+        int restart = 0;
+        while (!res->reason && !restart) {
+            if (k >= maxit) { res->reason = ORC_DIVERGED_ITS; break; }
+            orc_spmv(n, rowptr, col, val, p, q);
+            double eta = orc_dot(n, p, q);
+            if (!finite_d(eta)) { res->reason = ORC_DIVERGED_NANORINF; break; }
+            if (eta <= 0.0) { res->reason = ORC_DIVERGED_INDEFINITE_MAT; break; }
+            double alpha = rho / eta;
+            orc_axpy(n, alpha, p, x);
+            orc_axpy(n, -alpha, q, r);
+            ++k;
+            rnorm = orc_nrm2(n, r);
+            if (hist && k < hist_len) hist[k] = rnorm;
+            if (!finite_d(rnorm)) { res->reason = ORC_DIVERGED_NANORINF; break; }
+            if (rnorm <= thresh) {
+                /* recursive test passed: confirm with the true residual */
+                orc_spmv(n, rowptr, col, val, x, q);
+                for (int32_t i = 0; i < n; ++i) r[i] = b[i] - q[i];
+                double tn = orc_nrm2(n, r);
+                if (tn <= thresh) {
+                    rnorm = tn;
+                    res->reason = tn <= rtol * bnorm ? ORC_CONVERGED_RTOL : ORC_CONVERGED_ATOL;
+                    break;
+                }
+                if (restarts == 3) { rnorm = tn; res->reason = ORC_DIVERGED_BREAKDOWN; break; }
+                ++restarts;
+                rnorm = tn;
+                restart = 1;
+                break;
+            }
+            if (k >= maxit) { res->reason = ORC_DIVERGED_ITS; break; }
+            orc_jacobi_apply(n, dinv, r, z);
+            double rho_new = orc_dot(n, r, z);
+            if (!finite_d(rho_new)) { res->reason = ORC_DIVERGED_NANORINF; break; }
+            if (rho_new < 0.0) { res->reason = ORC_DIVERGED_INDEFINITE_PC; break; }
+            if (rho_new == 0.0) { res->reason = ORC_DIVERGED_BREAKDOWN; break; }
+            double beta = rho_new / rho;
+            orc_aypx(n, beta, z, p);
+            rho = rho_new;
+        }
+        if (res->reason) break;
+    }
+    res->iterations = k;
+    res->restarts = restarts;
+    res->rnorm = rnorm;
+    /* report the true relative residual from a fresh accurate product */
+    orc_spmv(n, rowptr, col, val, x, q);
+    for (int32_t i = 0; i < n; ++i) r[i] = b[i] - q[i];
+    res->true_rel_residual = orc_nrm2(n, r) / bnorm;
+
+done:
+    free(dinv); free(r); free(z); free(p); free(q);
+    return status;
+}
+
+/* Dense SPD solve by Cholesky factorisation A = L L^T (brute-force check for
+ * small systems).  A is n*n row-major and is overwritten by L; b is
+ * overwritten by the solution.  Returns 0, or -1 if A is not positive
+ * definite. */
+int orc_dense_cholesky_solve(int32_t n, double *A, double *b)
+{
+    for (int32_t j = 0; j < n; ++j) {
+        long double s = A[(size_t)j * n + j];
+        for (int32_t k = 0; k < j; ++k)
+            s -= (long double)A[(size_t)j * n + k] * A[(size_t)j * n + k];
+        if (!(s > 0.0L)) return -1;
+        double ljj = (double)sqrtl(s);
+        A[(size_t)j * n + j] = ljj;
+        for (int32_t i = j + 1; i < n; ++i) {
+            long double t = A[(size_t)i * n + j];
+            for (int32_t k = 0; k < j; ++k)
+                t -= (long double)A[(size_t)i * n + k] * A[(size_t)j * n + k];
+            A[(size_t)i * n + j] = (double)(t / ljj);
+        }
+    }
+    for (int32_t i = 0; i < n; ++i) { /* L y = b */
+        long double t = b[i];
+        for (int32_t k = 0; k < i; ++k) t -= (long double)A[(size_t)i * n + k] * b[k];
+        b[i] = (double)(t / A[(size_t)i * n + i]);
+    }
+    for (int32_t i = n - 1; i >= 0; --i) { /* L^T x = y */
+        long double t = b[i];
+        for (int32_t k = i + 1; k < n; ++k) t -= (long double)A[(size_t)k * n + i] * b[k];
+        b[i] = (double)(t / A[(size_t)i * n + i]);
+    }
+    return 0;
+}
