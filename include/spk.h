@@ -1,0 +1,281 @@
+/*
+ * spk -- CSR sparse matrix-vector product and Jacobi-preconditioned conjugate
+ * gradient for AMD MI355X (gfx950).  C ABI of libspk.so.
+ *
+ * The problem statement follows the paper (arXiv 2011.00715, Sec. 5.5
+ * "OpenFOAM: An application perspective"): the application assembles a matrix
+ * and vectors, hands them to the library, and the library solves A x = b with
+ * a Krylov method that runs entirely on the GPU.  The API style follows Sec. 4:
+ *  - plain pointers with an explicit memory type instead of pointer-attribute
+ *    queries (Response A5 "Multiple memory types"; Challenge A5 notes the cost
+ *    of such queries);
+ *  - read-only inputs are `const`, outputs are write-only (the read/write
+ *    accessor model of Response A4);
+ *  - every call takes the caller's stream, so that the library and the
+ *    application share one queue (Challenge / Response A6);
+ *  - no call synchronises the device, and only the solve calls wait for their
+ *    own stream, once per batch of iterations (Response A1).
+ *
+ * Conventions for every entry point:
+ *  - `stream` is a hipStream_t passed as `void*`; NULL means the null stream.
+ *  - Device pointers must be device memory of the current HIP device and must
+ *    stay valid until the work queued on `stream` has finished.
+ *  - Return value: SPK_OK (0) or a negative SPK_E* status.  Nothing aborts and
+ *    nothing throws across the ABI.  spk_last_error() gives a thread-local
+ *    message for the last failing call on the calling thread.
+ *  - The caller owns every pointer it passes; the library never frees caller
+ *    memory.  Handles own what they allocate and free it in *_destroy.
+ *  - A handle may be used from one thread / one stream at a time.
+ */
+#ifndef SPK_H
+#define SPK_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct spk_mat spk_mat;
+typedef struct spk_server spk_server;
+
+/* memory types of caller buffers */
+enum { SPK_MEM_HOST = 0, SPK_MEM_DEVICE = 1 };
+
+/* solve precision (Challenge A7 / Response A7: per-solve precision flag) */
+enum { SPK_PREC_FP64 = 0, SPK_PREC_MIXED = 1 };
+
+/* spk_mat_create_csr flags */
+enum {
+    SPK_MAT_MIXED = 1,     /* also keep an FP32 copy of the values (needed by
+                              spk_mat_mult_f32 and mixed-precision solves) */
+    SPK_MAT_VALIDATE = 2,  /* check the CSR on the device (monotone rowptr,
+                              columns in range and strictly ascending) */
+    SPK_MAT_BORROW = 4     /* SPK_MEM_DEVICE only: keep the caller's rowptr,
+                              col and values instead of copying them; the
+                              caller keeps them alive and unchanged until
+                              spk_mat_destroy */
+};
+
+/* SpMV kernel families (selected from row-length statistics at create) */
+enum {
+    SPK_KERNEL_AUTO = 0,
+    SPK_KERNEL_STREAM = 1,  /* block-tile CSR stream: coalesced column/value
+                               streams staged through LDS, short rows */
+    SPK_KERNEL_VECTOR = 2,  /* L lanes per row (L = 64: one row per wavefront),
+                               wavefront-shuffle reduction */
+    SPK_KERNEL_MERGE = 3    /* merge-path over rows + nonzeros, equal work per
+                               tile, deterministic carry fix-up */
+};
+
+/* status codes */
+enum {
+    SPK_OK = 0,
+    SPK_EINVAL = -1,     /* invalid argument or malformed CSR */
+    SPK_ENOMEM = -2,     /* device or pinned host allocation failed */
+    SPK_EHIP = -3,       /* a HIP runtime call failed (text in spk_last_error) */
+    SPK_EZERODIAG = -4,  /* a row has no stored or a zero diagonal */
+    SPK_EBUSY = -5,      /* server: request still in flight */
+    SPK_EBUDGET = -6,    /* server: request can never fit the HBM budget */
+    SPK_ENOTFOUND = -7   /* server: unknown or already collected ticket */
+};
+
+/* solver reasons (separate from the status: a solve that does not converge
+ * returns SPK_OK with a negative reason) */
+enum {
+    SPK_CONVERGED_RTOL = 1,
+    SPK_CONVERGED_ATOL = 2,
+    SPK_RUNNING = 0,
+    SPK_DIVERGED_ITS = -1,
+    SPK_DIVERGED_INDEFINITE_MAT = -2,
+    SPK_DIVERGED_INDEFINITE_PC = -3,
+    SPK_DIVERGED_NANORINF = -4,
+    SPK_DIVERGED_BREAKDOWN = -5,
+    SPK_DIVERGED_STAGNATION = -6
+};
+
+typedef struct {
+    int32_t n;
+    int32_t kernel;          /* SPK_KERNEL_* in use */
+    int64_t nnz;
+    int32_t lanes;           /* VECTOR: lanes per row; STREAM: rows per tile;
+                                MERGE: items per tile */
+    int32_t has_f32;         /* FP32 value copy present */
+    int32_t row_min, row_max;
+    int32_t row_p50, row_p99;  /* upper bounds from a log2 histogram */
+    double row_mean, row_cv;
+    int64_t bytes_spmv_f64;  /* algorithmic bytes of one FP64 SpMV:
+                                12 nnz + 4 (n+1) + 16 n */
+    int64_t bytes_spmv_f32;  /* FP32 values and vectors: 8 nnz + 4 (n+1) + 8 n */
+    int64_t bytes_pcg_iter_f64;  /* one FP64 PCG iteration as implemented:
+                                    12 nnz + 4 (n+1) + 96 n */
+    int64_t bytes_pcg_iter_f32;  /* one FP32 inner iteration: 8 nnz + 4 (n+1) + 48 n */
+    int64_t device_bytes;    /* device memory held by the handle */
+    int32_t zero_diag_rows;  /* rows without a nonzero diagonal */
+    int32_t pad_;
+} spk_mat_info;
+
+/*
+ * Create a matrix from CSR arrays (the MATAIJ format of Sec. 4; 32-bit column
+ * indices and FP64 values, the byte count of Challenge A7).
+ *   n       rows = columns, 0 <= n < 2^31
+ *   nnz     stored entries, 0 <= nnz < 2^31
+ *   rowptr  int32[n+1], rowptr[0] = 0, non-decreasing, rowptr[n] = nnz
+ *   colind  int32[nnz], 0 <= col < n; ascending within a row is required only
+ *           with SPK_MAT_VALIDATE (the products do not depend on it)
+ *   values  double[nnz]
+ *   memtype SPK_MEM_HOST (copied through pinned staging) or SPK_MEM_DEVICE
+ *   flags   SPK_MAT_* bits
+ * The structure is always checked on the device before any other kernel
+ * reads it (rowptr[0] = 0, non-decreasing, rowptr[n] = nnz, 0 <= col < n):
+ * SPK_EINVAL with a message.  Rows without a nonzero diagonal are counted
+ * (spk_mat_info.zero_diag_rows); the Jacobi preconditioner (Sec. 5.3, the
+ * Jacobi smoother) needs 1/a_ii, so spk_pc_jacobi_apply and spk_ksp_solve
+ * return SPK_EZERODIAG for such a matrix, while SpMV works on any matrix.
+ * Work is queued on `stream`; the call returns after the setup has finished
+ * (it reads a few bytes of row statistics back to choose the kernel).
+ */
+int spk_mat_create_csr(int32_t n, int64_t nnz, const int32_t *rowptr,
+                       const int32_t *colind, const double *values, int memtype,
+                       uint32_t flags, void *stream, spk_mat **out);
+
+/* Force an SpMV kernel family (testing and A/B runs).  param: lanes per row
+ * for VECTOR (1..64, power of two), rows per tile for STREAM (0 = automatic),
+ * ignored for MERGE.  Invalidates cached solver graphs. */
+int spk_mat_set_kernel(spk_mat *A, int kernel, int32_t param);
+
+/* y = A x (Sec. 4: MatMult on an AIJ matrix).  x, y: device double[n],
+ * must not overlap.  Queued on `stream`; no synchronisation. */
+int spk_mat_mult(const spk_mat *A, const double *x, double *y, void *stream);
+
+/* y = A32 x with FP32 values, FP32 x and y and FP32 accumulation (Challenge
+ * A7: 64 instead of 96 bits per nonzero).  Needs SPK_MAT_MIXED. */
+int spk_mat_mult_f32(const spk_mat *A, const float *x, float *y, void *stream);
+
+int spk_mat_get_info(const spk_mat *A, spk_mat_info *info);
+
+/* Jacobi preconditioner apply, z_i = r_i / a_ii (PCApply of the Jacobi
+ * smoother, Sec. 5.3).  Device double[n]. */
+int spk_pc_jacobi_apply(const spk_mat *A, const double *r, double *z, void *stream);
+
+/* Waits for the handle's queued work, then frees everything it owns. */
+int spk_mat_destroy(spk_mat *A);
+
+/* ---------------------------------------------------------------- vectors
+ * The Krylov vector kernels (Sec. 5.1: VecAXPY, 2 flops and 3 memory
+ * accesses per entry; Sec. 4 Response F3: fused multiple inner products).
+ * All are device double arrays of length n, queued on `stream`.  Reductions
+ * write their result to device memory (`result`, 1 or 2 doubles) so that no
+ * host synchronisation is needed; they are deterministic (fixed reduction
+ * tree, no floating-point atomics). */
+int spk_vec_axpy(int32_t n, double alpha, const double *x, double *y, void *stream);   /* y = a x + y */
+int spk_vec_aypx(int32_t n, double beta, const double *x, double *y, void *stream);    /* y = x + b y */
+int spk_vec_dot(int32_t n, const double *x, const double *y, double *result, void *stream);
+int spk_vec_dot2(int32_t n, const double *x, const double *y, const double *w,
+                 double *result, void *stream); /* result[0] = x.y, result[1] = x.w, one pass */
+int spk_vec_nrm2(int32_t n, const double *x, double *result, void *stream);
+
+/* ---------------------------------------------------------------- solver */
+typedef struct {
+    double rtol;          /* default 1e-8 */
+    double atol;          /* default 0 */
+    int32_t maxit;        /* default 10000 (FP64 iterations, or inner
+                             iterations in total for mixed) */
+    int32_t precision;    /* SPK_PREC_FP64 (default) or SPK_PREC_MIXED */
+    int32_t x0_nonzero;   /* 0: start from x = 0 (default); 1: from x */
+    int32_t graph_k;      /* iterations per captured graph (default 8) */
+    double inner_rtol;    /* mixed: inner FP32 tolerance (default 1e-4) */
+    int32_t inner_maxit;  /* mixed: per inner solve (default 10000) */
+    int32_t max_outer;    /* mixed: refinement steps (default 20) */
+    double *hist;         /* optional host double[hist_len]: ||r_k||_2 of the
+                             recursive residual, k = 0..iterations */
+    int32_t hist_len;
+    int32_t pad_;
+} spk_ksp_opts;
+
+void spk_ksp_opts_default(spk_ksp_opts *o);
+
+typedef struct {
+    int32_t reason;            /* SPK_CONVERGED_* or SPK_DIVERGED_* */
+    int32_t iterations;        /* FP64 iterations (all, incl. fallback) */
+    int32_t inner_iterations;  /* mixed: FP32 inner iterations in total */
+    int32_t outer_steps;       /* mixed: refinement steps */
+    int32_t restarts;          /* true-residual restarts */
+    int32_t fallback_fp64;     /* mixed: finished in FP64 after stagnation */
+    double rnorm0, rnorm, bnorm;
+    double true_rel_residual;  /* ||b - A x|| / ||b|| from a fresh FP64 SpMV */
+    double seconds;            /* host wall time of the call */
+} spk_ksp_result;
+
+/*
+ * Solve A x = b with Jacobi-preconditioned CG (Sec. 5.5 uses CG; Sec. 5.3
+ * the Jacobi smoother).  b: device double[n], read only.  x: device
+ * double[n], initial guess if opts->x0_nonzero, solution on return.
+ * Convergence: ||r_k||_2 <= max(rtol ||b||_2, atol) on the recursive
+ * residual, confirmed by the true residual (restart from it, at most 3
+ * times, else BREAKDOWN).  MIXED runs FP32 inner CG on the FP32 values with
+ * FP64 iterative refinement (residual, update and test in FP64).
+ * Queued on `stream`; returns when the result is known (waits for the
+ * stream about once per graph_k iterations, with two batches in flight).
+ * opts may be NULL (defaults).  res must not be NULL.
+ */
+int spk_ksp_solve(spk_mat *A, const double *b, double *x, const spk_ksp_opts *opts,
+                  spk_ksp_result *res, void *stream);
+
+/* ---------------------------------------------------------------- server
+ * Continuous-batching solve server (Response A6: many different-size
+ * problems solved simultaneously on the GPU).  Requests are admitted while
+ * slots and the HBM budget allow; all active systems advance together in
+ * batched kernels (one launch serves every system, per-system reductions),
+ * so a system's result does not depend on what else is in the batch. */
+typedef struct {
+    int64_t hbm_budget_bytes;  /* device arena size (default 8 GiB) */
+    int32_t max_slots;         /* concurrent systems (default 64) */
+    int32_t graph_k;           /* iterations per batched step (default 8) */
+    int32_t max_blocks_per_system;  /* default 256 */
+    int32_t pad_;
+} spk_server_opts;
+
+void spk_server_opts_default(spk_server_opts *o);
+
+int spk_server_create(const spk_server_opts *o, void *stream, spk_server **out);
+
+/* Submit A x = b from host CSR (copied before return).  opts may be NULL.
+ * ticket: out, identifies the request.  SPK_EBUDGET if it can never fit. */
+int spk_server_submit(spk_server *s, int32_t n, int64_t nnz, const int32_t *rowptr,
+                      const int32_t *colind, const double *values, const double *b,
+                      const spk_ksp_opts *opts, uint64_t *ticket);
+
+/* Admit queued requests, run up to max_steps batched steps, retire finished
+ * systems.  Returns the number of active + queued requests (>= 0) or a
+ * status. */
+int spk_server_progress(spk_server *s, int32_t max_steps);
+
+/* Collect a finished request: copies x (host double[n]) and the result.
+ * SPK_EBUSY while in flight; the ticket is released on success.
+ * done_time (may be NULL): host monotonic time of retirement, seconds. */
+int spk_server_poll(spk_server *s, uint64_t ticket, double *x_host, spk_ksp_result *res,
+                    double *done_time);
+
+int spk_server_destroy(spk_server *s);
+
+/* ---------------------------------------------------------------- misc */
+const char *spk_status_str(int status);
+const char *spk_reason_str(int reason);
+const char *spk_last_error(void);
+/* host monotonic clock, seconds (same clock as done_time) */
+double spk_now(void);
+/* HIP runtime version the library is running on */
+int spk_runtime_version(void);
+
+/* Measurement helpers (Sec. 5.1: work-time spectrum of vector copies):
+ * stream-copy n doubles from src to dst, and write `bytes` of scratch to
+ * evict the Infinity Cache before a cold measurement. */
+int spk_bw_copy(int64_t n, const double *src, double *dst, void *stream);
+int spk_cache_flush(void *scratch, int64_t bytes, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SPK_H */

@@ -1,0 +1,195 @@
+// Internal definitions shared by the HIP translation units of libspk.so.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "spk.h"
+
+namespace spk {
+
+// ------------------------------------------------------------------ launch shape
+constexpr int kBlock = 256;              // threads per block (4 wavefronts of 64)
+constexpr int kWave = 64;
+constexpr int kXcd = 8;                  // MI355X: 8 accelerator complex dies
+constexpr int kMaxBlocksSingle = 2048;   // 256 CUs x 8 resident blocks
+constexpr int kTileBytes = 16384;        // LDS bytes for one tile of products
+constexpr int kMergeItems = 2048;        // merge-path items per tile (256 x 8)
+constexpr int kMergeIpt = kMergeItems / kBlock;
+
+// ------------------------------------------------------------------ solver state
+// Phase of a system inside a solve (FP64 solves stay in kPhaseInner).
+enum : int32_t {
+    kPhaseInner = 0,   // Krylov iterations (FP64, or FP32 inner for mixed)
+    kPhaseResid = 1,   // mixed: form r = b - A x in FP64
+    kPhaseSetup = 2,   // mixed: scale/cast r, start the FP32 inner solve
+    kPhaseUpdate = 3,  // mixed: x += s d, then kPhaseResid
+};
+
+// Last-block counters, one per kernel kind.
+enum { kCntPq = 0, kCntUpd = 1, kCntPx = 2, kCntRes = 3, kCntSet = 4, kNumCnt = 6 };
+
+// Slots of the per-block partial sums (each B doubles).
+enum { kPartPq = 0, kPartRz = 1, kPartRr = 2, kPartBb = 3, kNumPart = 4 };
+
+// Device-resident scalars of one system.  Written only by the last block of a
+// kernel (or by the one-thread init kernel); read by every block of the next
+// kernels, which turn into no-ops once `status` is no longer SPK_RUNNING.
+struct SysState {
+    int32_t status;       // SPK_RUNNING or a reason
+    int32_t phase;        // kPhase*
+    int32_t iter;         // Krylov iterations done (inner ones for mixed)
+    int32_t inner_iter;   // iterations of the current inner solve
+    int32_t outer;        // mixed: refinement steps done
+    int32_t x_pending;    // the last iteration's x (or d) update is still due
+    int32_t maxit;
+    int32_t inner_maxit;
+    int32_t max_outer;
+    int32_t stagnant;     // mixed: consecutive weak outer reductions
+    int32_t mixed;        // 1: mixed-precision solve
+    int32_t hist_len;
+    uint32_t counter[kNumCnt];
+    double rho, alpha, beta, eta;
+    double rnorm, rnorm0, bnorm, thresh, rtol, atol;
+    double inner_rtol, inner_thresh;
+    double s;             // mixed: ||r|| of the current outer residual
+    double s_prev;        // mixed: previous outer ||r||
+    double rnorm_true;    // result of the last true-residual kernel
+};
+
+// One linear system as seen by the batched kernels.
+struct SysDesc {
+    int32_t n;
+    int32_t R;            // rows per tile
+    int32_t ntiles;
+    int32_t nblk;         // logical blocks (a multiple of kXcd when >= kXcd)
+    const int32_t *rowptr;
+    const int32_t *col;
+    const double *val;
+    const float *val32;
+    const double *dinv;
+    const float *dinv32;
+    const double *b;
+    double *x;
+    double *r, *z, *p, *q;            // FP64 Krylov vectors
+    float *r32, *z32, *p32, *q32, *d32;  // FP32 inner vectors (mixed)
+    double *partials;                 // kNumPart * nblk
+    SysState *st;
+    double *hist;                     // device history (hist_len) or null
+};
+
+// ------------------------------------------------------------------ host helpers
+void set_error(const char *fmt, ...);
+int hip_fail(hipError_t e, const char *what, const char *file, int line);
+
+#define SPK_HIP(call)                                                        \
+    do {                                                                     \
+        hipError_t e_ = (call);                                              \
+        if (e_ != hipSuccess) return ::spk::hip_fail(e_, #call, __FILE__, __LINE__); \
+    } while (0)
+
+inline int ceil_div(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
+
+// Logical blocks for a system of `ntiles` tiles, at most `maxb`: a multiple of
+// kXcd when there are at least kXcd tiles, so that the XCD-aware remap below
+// is a bijection.
+inline int pick_nblk(int ntiles, int maxb)
+{
+    if (ntiles <= 0) return 0;
+    if (ntiles < kXcd) return ntiles;
+    int b = ntiles < maxb ? ntiles : maxb;
+    return b - b % kXcd;
+}
+
+// ------------------------------------------------------------------ device helpers
+// Workgroups are dispatched round-robin over the 8 XCDs.  Physical block `l`
+// of a system therefore runs on XCD l % 8; give XCD x the contiguous logical
+// range [x*B/8, (x+1)*B/8) so each XCD's L2 sees a contiguous band of rows
+// (and of the gathered x window of banded matrices).
+__device__ __forceinline__ int xcd_remap(int l, int nblk)
+{
+    if (nblk < kXcd || (nblk % kXcd) != 0) return l;
+    return (l % kXcd) * (nblk / kXcd) + l / kXcd;
+}
+
+// Tiles handled by logical block j of nblk: a balanced contiguous chunk.
+__device__ __forceinline__ void block_tiles(int j, int nblk, int ntiles, int &t0, int &t1)
+{
+    t0 = (int)(((int64_t)j * ntiles) / nblk);
+    t1 = (int)(((int64_t)(j + 1) * ntiles) / nblk);
+}
+
+// Find the system of physical block b: blk_start is ascending, nsys+1 entries.
+__device__ __forceinline__ int find_sys(const int32_t *blk_start, int nsys, int b)
+{
+    int lo = 0, hi = nsys - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (blk_start[mid] <= b) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Butterfly sum over a wavefront; every lane ends with the same bits
+// (each level adds two values whose sum is commutative, hence identical).
+template <class T>
+__device__ __forceinline__ T wave_sum(T v)
+{
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+    return v;
+}
+
+// Deterministic block sum: wave butterflies, then wave 0..3 in order.
+// Result valid in every thread.  `sh` holds kBlock/kWave values.
+template <class T>
+__device__ __forceinline__ T block_sum(T v, T *sh)
+{
+    v = wave_sum(v);
+    const int w = threadIdx.x / kWave;
+    __syncthreads();
+    if ((threadIdx.x & (kWave - 1)) == 0) sh[w] = v;
+    __syncthreads();
+    T s = sh[0];
+#pragma unroll
+    for (int i = 1; i < kBlock / kWave; ++i) s += sh[i];
+    return s;
+}
+
+// Last-block-done: every block arrives once; returns true in all threads of
+// the block that arrives last.  Partial sums written before the call are
+// visible to that block after it returns.  The counter is reset for the next
+// launch.  No floating-point atomics are involved: the final reduction is
+// done by the last block in a fixed order.
+__device__ __forceinline__ bool last_block_arrive(uint32_t *counter, uint32_t total)
+{
+    __shared__ int am_last;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        uint32_t prev = atomicAdd(counter, 1u);
+        am_last = (prev == total - 1);
+        if (am_last) atomicExch(counter, 0u);
+    }
+    __syncthreads();
+    if (am_last) __threadfence();
+    return am_last != 0;
+}
+
+// Fixed-order sum of nblk partials by one block (all threads get the result).
+__device__ __forceinline__ double reduce_partials(const double *part, int nblk, double *sh)
+{
+    double s = 0.0;
+    for (int i = threadIdx.x; i < nblk; i += kBlock) s += part[i];
+    return block_sum(s, sh);
+}
+
+template <class T>
+__device__ __forceinline__ T ld_stream(const T *p)
+{
+    return __builtin_nontemporal_load(p);
+}
+
+}  // namespace spk

@@ -1,0 +1,458 @@
+// Jacobi-PCG solve driver: workspace, captured iteration graphs, pipelined
+// convergence polling, FP64 and mixed-precision (FP32 inner CG + FP64
+// iterative refinement) solves.
+#include <string.h>
+
+#include <algorithm>
+
+#include "krylov.hpp"
+#include "runtime.hpp"
+
+namespace spk {
+
+void free_workspace(spk_mat *A)
+{
+    Workspace *w = A->ws;
+    if (!w) return;
+    hipDeviceSynchronize();
+    if (w->g64) hipGraphExecDestroy(w->g64);
+    if (w->gmix) hipGraphExecDestroy(w->gmix);
+    for (auto &e : w->ev)
+        if (e) hipEventDestroy(e);
+    if (w->cap) hipStreamDestroy(w->cap);
+    hipFree(w->ddesc);
+    hipFree(w->blk_start);
+    hipFree(w->st);
+    hipFree(w->partials);
+    hipFree(w->hist);
+    hipFree(w->r);
+    hipFree(w->z);
+    hipFree(w->p);
+    hipFree(w->q);
+    hipFree(w->x);
+    hipFree(w->r32);
+    hipFree(w->z32);
+    hipFree(w->p32);
+    hipFree(w->q32);
+    hipFree(w->d32);
+    hipHostFree(w->pdesc);
+    hipHostFree(w->pst);
+    hipHostFree(w->pstatus);
+    delete w;
+    A->ws = nullptr;
+}
+
+template <class T>
+static int dalloc(T **p, int64_t count, Workspace *w)
+{
+    const size_t b = sizeof(T) * (size_t)(count > 0 ? count : 1);
+    SPK_HIP(hipMalloc((void **)p, b));
+    w->bytes += (int64_t)b;
+    return SPK_OK;
+}
+
+#define SPK_TRY(x)                  \
+    do {                            \
+        const int rc_ = (x);        \
+        if (rc_ != SPK_OK) return rc_; \
+    } while (0)
+
+static int get_workspace(spk_mat *A, bool mixed, Workspace **out)
+{
+    Workspace *w = A->ws;
+    if (!w) {
+        w = new (std::nothrow) Workspace();
+        if (!w) { set_error("out of host memory"); return SPK_ENOMEM; }
+        A->ws = w;
+        w->n = A->n;
+        SPK_TRY(dalloc(&w->ddesc, 1, w));
+        SPK_TRY(dalloc(&w->blk_start, 2, w));
+        SPK_TRY(dalloc(&w->st, 1, w));
+        SPK_TRY(dalloc(&w->partials, (int64_t)kNumPart * std::max(A->nblk, 1), w));
+        SPK_TRY(dalloc(&w->r, A->n, w));
+        SPK_TRY(dalloc(&w->z, A->n, w));
+        SPK_TRY(dalloc(&w->p, A->n, w));
+        SPK_TRY(dalloc(&w->q, A->n, w));
+        SPK_TRY(dalloc(&w->x, A->n, w));
+        SPK_HIP(hipHostMalloc((void **)&w->pdesc, sizeof(SysDesc), hipHostMallocDefault));
+        SPK_HIP(hipHostMalloc((void **)&w->pst, sizeof(SysState), hipHostMallocDefault));
+        SPK_HIP(hipHostMalloc((void **)&w->pstatus, sizeof(int32_t) * 8, hipHostMallocDefault));
+        for (auto &e : w->ev) SPK_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        SPK_HIP(hipStreamCreateWithFlags(&w->cap, hipStreamNonBlocking));
+        const int32_t bs[2] = {0, A->nblk};
+        SPK_HIP(hipMemcpy(w->blk_start, bs, sizeof(bs), hipMemcpyHostToDevice));
+        SPK_HIP(hipMemset(w->st, 0, sizeof(SysState)));
+        SysDesc &d = w->hdesc;
+        d.n = A->n;
+        d.R = A->R;
+        d.ntiles = A->ntiles;
+        d.nblk = A->nblk;
+        d.rowptr = A->rowptr;
+        d.col = A->col;
+        d.val = A->val;
+        d.dinv = A->dinv;
+        d.x = w->x;
+        d.r = w->r;
+        d.z = w->z;
+        d.p = w->p;
+        d.q = w->q;
+        d.partials = w->partials;
+        d.st = w->st;
+    }
+    if (mixed && !w->has_mixed) {
+        SPK_TRY(dalloc(&w->r32, A->n, w));
+        SPK_TRY(dalloc(&w->z32, A->n, w));
+        SPK_TRY(dalloc(&w->p32, A->n, w));
+        SPK_TRY(dalloc(&w->q32, A->n, w));
+        SPK_TRY(dalloc(&w->d32, A->n, w));
+        w->has_mixed = 1;
+        SysDesc &d = w->hdesc;
+        d.val32 = A->val32;
+        d.dinv32 = A->dinv32;
+        d.r32 = w->r32;
+        d.z32 = w->z32;
+        d.p32 = w->p32;
+        d.q32 = w->q32;
+        d.d32 = w->d32;
+    }
+    *out = w;
+    return SPK_OK;
+}
+
+static int upload_desc(Workspace *w, const double *b, bool with_hist, hipStream_t s)
+{
+    w->hdesc.b = b;
+    w->hdesc.hist = with_hist ? w->hist : nullptr;
+    *w->pdesc = w->hdesc;
+    SPK_HIP(hipMemcpyAsync(w->ddesc, w->pdesc, sizeof(SysDesc), hipMemcpyHostToDevice, s));
+    return SPK_OK;
+}
+
+static Batch batch_of(Workspace *w) { return Batch{w->ddesc, w->blk_start, 1}; }
+
+// r = b - A x for the handle's kernel family.
+static int launch_resid(spk_mat *A, Workspace *w, int purpose, bool gated, hipStream_t s)
+{
+    const Batch b = batch_of(w);
+    const dim3 g(A->nblk), t(kBlock);
+    if (A->kernel == SPK_KERNEL_STREAM) {
+        if (gated) hipLaunchKernelGGL(k_resid_stream<kGateResid>, g, t, 0, s, b, purpose);
+        else hipLaunchKernelGGL(k_resid_stream<kGateNone>, g, t, 0, s, b, purpose);
+    } else {
+        SPK_TRY(launch_spmv<double>(A, A->val, w->x, w->r, s, gated ? w->st : nullptr,
+                                    gated ? kGateResid : kGateNone));
+        if (gated) hipLaunchKernelGGL(k_resid_finish<kGateResid>, g, t, 0, s, b, purpose);
+        else hipLaunchKernelGGL(k_resid_finish<kGateNone>, g, t, 0, s, b, purpose);
+    }
+    SPK_HIP(hipGetLastError());
+    return SPK_OK;
+}
+
+template <class V>
+static int enqueue_iteration(spk_mat *A, Workspace *w, hipStream_t s)
+{
+    const Batch b = batch_of(w);
+    const dim3 g(A->nblk), t(kBlock);
+    if (A->kernel == SPK_KERNEL_STREAM) {
+        hipLaunchKernelGGL(k_pcg_spmv_stream<V>, g, t, 0, s, b);
+    } else {
+        const V *val = std::is_same<V, double>::value ? (const V *)A->val : (const V *)A->val32;
+        V *p = std::is_same<V, double>::value ? (V *)w->p : (V *)w->p32;
+        V *q = std::is_same<V, double>::value ? (V *)w->q : (V *)w->q32;
+        SPK_TRY(launch_spmv<V>(A, val, p, q, s, w->st, Vecs<V>::gate));
+        hipLaunchKernelGGL(k_pcg_pq<V>, g, t, 0, s, b);
+    }
+    hipLaunchKernelGGL(k_pcg_update<V>, g, t, 0, s, b);
+    hipLaunchKernelGGL(k_pcg_px<V>, g, t, 0, s, b);
+    SPK_HIP(hipGetLastError());
+    return SPK_OK;
+}
+
+// One batch of K iterations (mixed: preceded by the refinement kernels).
+static int enqueue_batch(spk_mat *A, Workspace *w, bool mixed, int K, hipStream_t s)
+{
+    if (mixed) {
+        const Batch b = batch_of(w);
+        hipLaunchKernelGGL(k_update_x, dim3(A->nblk), dim3(kBlock), 0, s, b);
+        SPK_TRY(launch_resid(A, w, kResOuter, true, s));
+        hipLaunchKernelGGL(k_setup32, dim3(A->nblk), dim3(kBlock), 0, s, b);
+        for (int k = 0; k < K; ++k) SPK_TRY(enqueue_iteration<float>(A, w, s));
+    } else {
+        for (int k = 0; k < K; ++k) SPK_TRY(enqueue_iteration<double>(A, w, s));
+    }
+    SPK_HIP(hipGetLastError());
+    return SPK_OK;
+}
+
+static int get_graph(spk_mat *A, Workspace *w, bool mixed, int K, hipGraphExec_t *out)
+{
+    hipGraphExec_t &g = mixed ? w->gmix : w->g64;
+    int &gk = mixed ? w->gmix_k : w->g64_k;
+    if (g && gk == K) { *out = g; return SPK_OK; }
+    if (g) { hipGraphExecDestroy(g); g = nullptr; }
+    hipGraph_t graph = nullptr;
+    SPK_HIP(hipStreamBeginCapture(w->cap, hipStreamCaptureModeThreadLocal));
+    const int rc = enqueue_batch(A, w, mixed, K, w->cap);
+    const hipError_t e = hipStreamEndCapture(w->cap, &graph);
+    if (rc) { if (graph) hipGraphDestroy(graph); return rc; }
+    if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture", __FILE__, __LINE__);
+    const hipError_t e2 = hipGraphInstantiate(&g, graph, nullptr, nullptr, 0);
+    hipGraphDestroy(graph);
+    if (e2 != hipSuccess) { g = nullptr; return hip_fail(e2, "hipGraphInstantiate", __FILE__, __LINE__); }
+    gk = K;
+    *out = g;
+    return SPK_OK;
+}
+
+// Replays batches until the device reports that the solve stopped.  Two
+// batches stay queued, so the GPU never waits for the host's status check
+// (Challenge A1: keep the stream queue from draining).
+static int run_batches(spk_mat *A, Workspace *w, bool mixed, int K, bool use_graph,
+                       int max_batches, hipStream_t s)
+{
+    hipGraphExec_t g = nullptr;
+    if (use_graph) SPK_TRY(get_graph(A, w, mixed, K, &g));
+    constexpr int kDepth = 2;
+    int launched = 0, checked = 0;
+    for (;;) {
+        if (launched - checked < kDepth && launched < max_batches) {
+            if (use_graph) SPK_HIP(hipGraphLaunch(g, s));
+            else SPK_TRY(enqueue_batch(A, w, mixed, K, s));
+            const int slot = launched % 4;
+            SPK_HIP(hipMemcpyAsync(&w->pstatus[2 * slot], &w->st->status, 2 * sizeof(int32_t),
+                                   hipMemcpyDeviceToHost, s));
+            SPK_HIP(hipEventRecord(w->ev[slot], s));
+            ++launched;
+            continue;
+        }
+        if (checked == launched) {
+            SPK_HIP(hipStreamSynchronize(s));
+            set_error("solver did not stop within %d batches of %d iterations", max_batches, K);
+            return SPK_EHIP;
+        }
+        const int slot = checked % 4;
+        SPK_HIP(hipEventSynchronize(w->ev[slot]));
+        ++checked;
+        if (w->pstatus[2 * slot] != SPK_RUNNING) break;
+    }
+    SPK_HIP(hipStreamSynchronize(s));
+    return SPK_OK;
+}
+
+static int read_state(Workspace *w, hipStream_t s)
+{
+    SPK_HIP(hipMemcpyAsync(w->pst, w->st, sizeof(SysState), hipMemcpyDeviceToHost, s));
+    SPK_HIP(hipStreamSynchronize(s));
+    return SPK_OK;
+}
+
+static void fill_zero(double *p, int64_t n, hipStream_t s);
+
+struct SolveOut {
+    int reason = 0, iterations = 0, restarts = 0;
+    double rnorm0 = 0, rnorm = 0, bnorm = 0, rnorm_true = 0;
+};
+
+// FP64 Jacobi-PCG on w->x (already initialised).
+static int solve64(spk_mat *A, Workspace *w, const spk_ksp_opts &o, bool x_given_residual,
+                   int hist_len, hipStream_t s, SolveOut *out)
+{
+    (void)x_given_residual;
+    const int K = o.graph_k > 0 ? o.graph_k : 8;
+    const bool use_graph = o.graph_k > 0;
+    hipLaunchKernelGGL(k_state_init, dim3(1), dim3(64), 0, s, w->st, o.rtol, o.atol, o.maxit, 0,
+                       o.inner_rtol, o.inner_maxit, o.max_outer, hist_len);
+    SPK_TRY(launch_resid(A, w, kResSetup, false, s));
+    hipLaunchKernelGGL(k_setup64, dim3(A->nblk), dim3(kBlock), 0, s, batch_of(w));
+    SPK_HIP(hipGetLastError());
+    int restarts = 0;
+    for (;;) {
+        SPK_TRY(read_state(w, s));
+        const int done_iter = w->pst->iter;
+        const int max_batches = (std::max(o.maxit - done_iter, 0) + K - 1) / K + 2;
+        if (w->pst->status == SPK_RUNNING) SPK_TRY(run_batches(A, w, false, K, use_graph, max_batches, s));
+        SPK_TRY(launch_resid(A, w, kResTrue, false, s));
+        SPK_TRY(read_state(w, s));
+        const SysState &S = *w->pst;
+        const bool conv = S.status == SPK_CONVERGED_RTOL || S.status == SPK_CONVERGED_ATOL;
+        if (conv && S.bnorm > 0 && S.iter > 0 && S.rnorm_true > S.thresh) {
+            if (restarts == 3) {
+                out->reason = SPK_DIVERGED_BREAKDOWN;
+                break;
+            }
+            ++restarts;
+            hipLaunchKernelGGL(k_state_restart, dim3(1), dim3(64), 0, s, w->st);
+            hipLaunchKernelGGL(k_setup64, dim3(A->nblk), dim3(kBlock), 0, s, batch_of(w));
+            SPK_HIP(hipGetLastError());
+            continue;
+        }
+        out->reason = S.status;
+        if (conv && S.iter > 0)  // reason from the confirmed true residual
+            out->reason = S.rnorm_true <= S.rtol * S.bnorm ? SPK_CONVERGED_RTOL : SPK_CONVERGED_ATOL;
+        break;
+    }
+    const SysState &S = *w->pst;
+    out->iterations = S.iter;
+    out->restarts = restarts;
+    out->rnorm0 = S.rnorm0;
+    out->rnorm = (S.status == SPK_CONVERGED_RTOL || S.status == SPK_CONVERGED_ATOL) && S.iter > 0
+                     ? S.rnorm_true : S.rnorm;
+    out->bnorm = S.bnorm;
+    out->rnorm_true = S.rnorm_true;
+    if (S.bnorm == 0.0) {
+        fill_zero(w->x, A->n, s);
+        out->rnorm_true = 0.0;
+        out->rnorm = 0.0;
+    }
+    return SPK_OK;
+}
+
+static int solve_mixed(spk_mat *A, Workspace *w, const spk_ksp_opts &o, int hist_len,
+                       hipStream_t s, SolveOut *out, int *inner, int *outer)
+{
+    const int K = o.graph_k > 0 ? o.graph_k : 8;
+    const bool use_graph = o.graph_k > 0;
+    hipLaunchKernelGGL(k_state_init, dim3(1), dim3(64), 0, s, w->st, o.rtol, o.atol, o.maxit, 1,
+                       o.inner_rtol, o.inner_maxit, o.max_outer, hist_len);
+    SPK_HIP(hipGetLastError());
+    const int max_batches = (o.maxit + K - 1) / K + 2 * (o.max_outer + 2);
+    SPK_TRY(run_batches(A, w, true, K, use_graph, max_batches, s));
+    SPK_TRY(launch_resid(A, w, kResTrue, false, s));
+    SPK_TRY(read_state(w, s));
+    const SysState &S = *w->pst;
+    out->reason = S.status;
+    out->iterations = 0;
+    out->rnorm0 = S.rnorm0;
+    out->rnorm = S.rnorm_true;
+    out->bnorm = S.bnorm;
+    out->rnorm_true = S.rnorm_true;
+    *inner = S.iter;
+    *outer = S.outer;
+    if (S.bnorm == 0.0) {
+        fill_zero(w->x, A->n, s);
+        out->rnorm_true = out->rnorm = 0.0;
+    }
+    return SPK_OK;
+}
+
+__global__ void k_zero64(int64_t m, double *__restrict__ a)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < m;
+         i += (int64_t)gridDim.x * blockDim.x)
+        a[i] = 0.0;
+}
+
+static void fill_zero(double *p, int64_t n, hipStream_t s)
+{
+    if (n <= 0) return;
+    int64_t g = (n + kBlock - 1) / kBlock;
+    if (g > kMaxBlocksSingle) g = kMaxBlocksSingle;
+    hipLaunchKernelGGL(k_zero64, dim3((int)g), dim3(kBlock), 0, s, n, p);
+}
+
+}  // namespace spk
+
+using namespace spk;
+
+extern "C" {
+
+void spk_ksp_opts_default(spk_ksp_opts *o)
+{
+    if (!o) return;
+    memset(o, 0, sizeof(*o));
+    o->rtol = 1e-8;
+    o->atol = 0.0;
+    o->maxit = 10000;
+    o->precision = SPK_PREC_FP64;
+    o->x0_nonzero = 0;
+    o->graph_k = 8;
+    o->inner_rtol = 1e-4;
+    o->inner_maxit = 10000;
+    o->max_outer = 20;
+    o->hist = nullptr;
+    o->hist_len = 0;
+}
+
+int spk_ksp_solve(spk_mat *A, const double *b, double *x, const spk_ksp_opts *opts,
+                  spk_ksp_result *res, void *stream)
+{
+    const double t0 = spk_now();
+    if (!A || !res) { set_error("NULL argument"); return SPK_EINVAL; }
+    memset(res, 0, sizeof(*res));
+    spk_ksp_opts o;
+    if (opts) o = *opts;
+    else spk_ksp_opts_default(&o);
+    if (A->n > 0 && (!b || !x)) { set_error("NULL b or x"); return SPK_EINVAL; }
+    if (!(o.rtol >= 0) || !(o.atol >= 0) || o.maxit < 0 || o.graph_k < 0 || o.graph_k > 1024 ||
+        (o.precision != SPK_PREC_FP64 && o.precision != SPK_PREC_MIXED) || o.hist_len < 0 ||
+        (o.hist_len > 0 && !o.hist) || !(o.inner_rtol > 0) || o.inner_maxit < 1 || o.max_outer < 0) {
+        set_error("invalid solver options");
+        return SPK_EINVAL;
+    }
+    if (A->stats.zero_diag) {
+        set_error("%d rows have no stored or a zero diagonal (Jacobi needs 1/a_ii)",
+                  A->stats.zero_diag);
+        return SPK_EZERODIAG;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    if (A->n == 0) {
+        res->reason = SPK_CONVERGED_ATOL;
+        res->seconds = spk_now() - t0;
+        return SPK_OK;
+    }
+    const bool mixed = o.precision == SPK_PREC_MIXED;
+    if (mixed) SPK_TRY(ensure_f32(A, s));
+    Workspace *w = nullptr;
+    SPK_TRY(get_workspace(A, mixed, &w));
+    if (o.hist_len > w->hist_cap) {
+        if (w->hist) hipFree(w->hist);
+        w->hist = nullptr;
+        SPK_HIP(hipMalloc(&w->hist, sizeof(double) * o.hist_len));
+        w->hist_cap = o.hist_len;
+        w->bytes += 8 * (int64_t)o.hist_len;
+    }
+    if (w->hist && o.hist_len > 0) SPK_HIP(hipMemsetAsync(w->hist, 0xff, sizeof(double) * o.hist_len, s));
+    SPK_TRY(upload_desc(w, b, o.hist_len > 0, s));
+    if (o.x0_nonzero) SPK_HIP(hipMemcpyAsync(w->x, x, sizeof(double) * A->n, hipMemcpyDeviceToDevice, s));
+    else fill_zero(w->x, A->n, s);
+    SPK_HIP(hipGetLastError());
+
+    SolveOut out;
+    int inner = 0, outer = 0, fallback = 0;
+    if (mixed) {
+        SPK_TRY(solve_mixed(A, w, o, o.hist_len, s, &out, &inner, &outer));
+        if (out.reason == SPK_DIVERGED_STAGNATION) {
+            // finish in FP64 from the current x
+            fallback = 1;
+            if (o.hist_len > 0) SPK_HIP(hipMemcpyAsync(o.hist, w->hist, sizeof(double) * o.hist_len,
+                                                      hipMemcpyDeviceToHost, s));
+            SolveOut o64;
+            spk_ksp_opts o2 = o;
+            o2.maxit = std::max(o.maxit - inner, 1);
+            SPK_TRY(solve64(A, w, o2, true, 0, s, &o64));
+            const double r0 = out.rnorm0;
+            out = o64;
+            out.rnorm0 = r0;
+        }
+    } else {
+        SPK_TRY(solve64(A, w, o, false, o.hist_len, s, &out));
+    }
+    SPK_HIP(hipMemcpyAsync(x, w->x, sizeof(double) * A->n, hipMemcpyDeviceToDevice, s));
+    if (o.hist_len > 0 && !fallback)
+        SPK_HIP(hipMemcpyAsync(o.hist, w->hist, sizeof(double) * o.hist_len, hipMemcpyDeviceToHost, s));
+    SPK_HIP(hipStreamSynchronize(s));
+    res->reason = out.reason;
+    res->iterations = out.iterations;
+    res->inner_iterations = inner;
+    res->outer_steps = outer;
+    res->restarts = out.restarts;
+    res->fallback_fp64 = fallback;
+    res->rnorm0 = out.rnorm0;
+    res->rnorm = out.rnorm;
+    res->bnorm = out.bnorm;
+    res->true_rel_residual = out.bnorm > 0 ? out.rnorm_true / out.bnorm : 0.0;
+    res->seconds = spk_now() - t0;
+    return SPK_OK;
+}
+
+}  // extern "C"

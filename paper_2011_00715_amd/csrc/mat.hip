@@ -1,0 +1,813 @@
+// Matrix handle, SpMV dispatch, vector kernels and utilities of libspk.so.
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+#include <time.h>
+
+#include <algorithm>
+#include <map>
+#include <mutex>
+
+#include "runtime.hpp"
+#include "spmv.hpp"
+
+namespace spk {
+
+// ------------------------------------------------------------------ errors
+static thread_local char g_err[512] = "";
+
+void set_error(const char *fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+}
+
+int hip_fail(hipError_t e, const char *what, const char *file, int line)
+{
+    set_error("%s failed: %s (%s:%d)", what, hipGetErrorString(e), file, line);
+    return e == hipErrorOutOfMemory ? SPK_ENOMEM : SPK_EHIP;
+}
+
+// ------------------------------------------------------------------ analysis kernels
+__global__ void k_row_stats(int n, int64_t nnz, const int32_t *__restrict__ rowptr,
+                            RowStats *__restrict__ out)
+{
+    __shared__ int32_t hist[33];
+    __shared__ unsigned long long s1, s2;
+    __shared__ int32_t mx, mn, bad, tmax[6];
+    if (threadIdx.x < 33) hist[threadIdx.x] = 0;
+    if (threadIdx.x == 0) { s1 = 0; s2 = 0; mx = 0; mn = 0x7fffffff; bad = 0; }
+    if (threadIdx.x < 6) tmax[threadIdx.x] = 0;
+    __syncthreads();
+    unsigned long long a1 = 0, a2 = 0;
+    int amx = 0, amn = 0x7fffffff, abad = 0;
+    int at[6] = {0, 0, 0, 0, 0, 0};
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const int64_t a = rowptr[i], e = rowptr[i + 1];
+        if (e < a || a < 0 || e > nnz || (i == 0 && a != 0) || (i == n - 1 && e != nnz)) {
+            ++abad;
+            continue;
+        }
+        const int len = (int)(e - a);
+        a1 += (unsigned long long)len;
+        a2 += (unsigned long long)len * (unsigned long long)len;
+        amx = max(amx, len);
+        amn = min(amn, len);
+        const int bin = len == 0 ? 0 : 32 - __clz(len);
+        atomicAdd(&hist[bin], 1);
+#pragma unroll
+        for (int t = 0; t < 6; ++t) {
+            const int R = t == 0 ? 256 : (t == 1 ? 128 : (t == 2 ? 64 : (t == 3 ? 32 : (t == 4 ? 16 : 8))));
+            if (i % R == 0) {
+                const int ie = min(i + R, n);
+                const int64_t te = rowptr[ie];
+                if (te >= a && te <= nnz) at[t] = max(at[t], (int)(te - a));
+            }
+        }
+    }
+    atomicAdd(&s1, a1);
+    atomicAdd(&s2, a2);
+    atomicMax(&mx, amx);
+    atomicMin(&mn, amn);
+    atomicAdd(&bad, abad);
+#pragma unroll
+    for (int t = 0; t < 6; ++t) atomicMax(&tmax[t], at[t]);
+    __syncthreads();
+    if (threadIdx.x < 33 && hist[threadIdx.x]) atomicAdd(&out->hist[threadIdx.x], hist[threadIdx.x]);
+    if (threadIdx.x < 6) atomicMax(&out->tile_max[threadIdx.x], tmax[threadIdx.x]);
+    if (threadIdx.x == 0) {
+        atomicAdd(&out->sum_len, s1);
+        atomicAdd(&out->sum_len2, s2);
+        atomicMax(&out->max_len, mx);
+        atomicMin(&out->min_len, mn);
+        atomicAdd(&out->bad_rowptr, bad);
+    }
+}
+
+// Column range and (optionally) strict ascending order; needs a valid rowptr.
+__global__ void k_check_cols(int n, const int32_t *__restrict__ rowptr,
+                             const int32_t *__restrict__ col, int check_sorted,
+                             RowStats *__restrict__ out)
+{
+    int badc = 0, uns = 0;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        int prev = -1;
+        for (int k = rowptr[i]; k < rowptr[i + 1]; ++k) {
+            const int c = col[k];
+            if (c < 0 || c >= n) ++badc;
+            if (check_sorted && c <= prev) ++uns;
+            prev = c;
+        }
+    }
+    if (badc) atomicAdd(&out->bad_col, badc);
+    if (uns) atomicAdd(&out->unsorted, uns);
+}
+
+// dinv_i = 1 / a_ii (duplicates of the diagonal are summed).
+__global__ void k_diag_inv(int n, const int32_t *__restrict__ rowptr, const int32_t *__restrict__ col,
+                           const double *__restrict__ val, double *__restrict__ dinv,
+                           RowStats *__restrict__ out)
+{
+    int bad = 0;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        double d = 0.0;
+        for (int k = rowptr[i]; k < rowptr[i + 1]; ++k)
+            if (col[k] == i) d += val[k];
+        if (d == 0.0) { ++bad; dinv[i] = 0.0; }
+        else dinv[i] = 1.0 / d;
+    }
+    if (bad) atomicAdd(&out->zero_diag, bad);
+}
+
+__global__ void k_to_f32(int64_t m, const double *__restrict__ a, float *__restrict__ b)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < m;
+         i += (int64_t)gridDim.x * blockDim.x)
+        b[i] = (float)a[i];
+}
+
+// ------------------------------------------------------------------ vector kernels
+__global__ void k_fill0(int64_t m, double *__restrict__ a)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < m;
+         i += (int64_t)gridDim.x * blockDim.x)
+        a[i] = 0.0;
+}
+
+__global__ void k_axpy(int n, double alpha, const double *__restrict__ x, double *__restrict__ y)
+{
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+        y[i] = fma(alpha, x[i], y[i]);
+}
+
+__global__ void k_aypx(int n, double beta, const double *__restrict__ x, double *__restrict__ y)
+{
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+        y[i] = fma(beta, y[i], x[i]);
+}
+
+__global__ void k_pmul(int n, const double *__restrict__ d, const double *__restrict__ r,
+                       double *__restrict__ z)
+{
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+        z[i] = d[i] * r[i];
+}
+
+// Single-pass dots: result[0] = x.y, result[1] = x.w (if w), or ||x|| (mode 2).
+// Contiguous chunk per block, fixed-order reduction by the last block.
+__global__ __launch_bounds__(kBlock) void k_dot(int n, const double *__restrict__ x,
+                                                const double *__restrict__ y,
+                                                const double *__restrict__ w, int mode,
+                                                double *__restrict__ part, uint32_t *counter,
+                                                double *__restrict__ result)
+{
+    __shared__ double red[kBlock / kWave];
+    const int nb = gridDim.x;
+    const int j = xcd_remap(blockIdx.x, nb);
+    const int64_t chunk = ((int64_t)n + nb - 1) / nb;
+    const int rb = (int)min((int64_t)n, j * chunk);
+    const int re = (int)min((int64_t)n, (j + 1) * chunk);
+    double a = 0.0, b = 0.0;
+    for (int i = rb + (int)threadIdx.x; i < re; i += kBlock) {
+        const double xi = x[i];
+        a = fma(xi, y[i], a);
+        if (w) b = fma(xi, w[i], b);
+    }
+    a = block_sum(a, red);
+    if (w) b = block_sum(b, red);
+    if (threadIdx.x == 0) { part[j] = a; part[nb + j] = b; }
+    if (last_block_arrive(counter, nb)) {
+        const double A = reduce_partials(part, nb, red);
+        const double B = w ? reduce_partials(part + nb, nb, red) : 0.0;
+        if (threadIdx.x == 0) {
+            if (mode == 2) result[0] = sqrt(A);
+            else {
+                result[0] = A;
+                if (w) result[1] = B;
+            }
+        }
+    }
+}
+
+typedef double dvec2 __attribute__((ext_vector_type(2)));
+
+// Bandwidth calibration: plain stream copy (2 accesses per entry, Sec. 5.1).
+__global__ __launch_bounds__(kBlock) void k_copy(int64_t m, const dvec2 *__restrict__ a,
+                                                 dvec2 *__restrict__ b)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < m;
+         i += (int64_t)gridDim.x * blockDim.x)
+        b[i] = __builtin_nontemporal_load(a + i);
+}
+
+__global__ __launch_bounds__(kBlock) void k_scribble(int64_t m, dvec2 *__restrict__ b, double v)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < m;
+         i += (int64_t)gridDim.x * blockDim.x)
+        b[i] = dvec2{v, v};
+}
+
+// ------------------------------------------------------------------ SpMV dispatch
+template <class V, int L>
+static void launch_vector_l(const spk_mat *A, const V *val, const V *x, V *y, hipStream_t s,
+                            const SysState *gst, int gmode)
+{
+    constexpr int rpb = kBlock / L;
+    int grid = ceil_div(A->n, rpb);
+    if (grid > kMaxBlocksSingle) grid = kMaxBlocksSingle;
+    if (grid >= kXcd) grid -= grid % kXcd;
+    hipLaunchKernelGGL((k_spmv_vector<V, L>), dim3(grid), dim3(kBlock), 0, s, A->n, A->rowptr,
+                       A->col, val, x, y, gst, gmode);
+}
+
+template <class V>
+int launch_spmv(const spk_mat *A, const V *val, const V *x, V *y, hipStream_t s,
+                const SysState *gst, int gmode)
+{
+    if (A->n == 0) return SPK_OK;
+    switch (A->kernel) {
+    case SPK_KERNEL_STREAM:
+        if (gst) {
+            set_error("internal: gated stream SpMV");
+            return SPK_EINVAL;
+        }
+        hipLaunchKernelGGL((k_spmv_stream<V>), dim3(A->nblk), dim3(kBlock), 0, s, A->n, A->R,
+                           A->ntiles, A->nblk, A->rowptr, A->col, val, x, y);
+        break;
+    case SPK_KERNEL_VECTOR:
+        switch (A->lanes) {
+        case 1: launch_vector_l<V, 1>(A, val, x, y, s, gst, gmode); break;
+        case 2: launch_vector_l<V, 2>(A, val, x, y, s, gst, gmode); break;
+        case 4: launch_vector_l<V, 4>(A, val, x, y, s, gst, gmode); break;
+        case 8: launch_vector_l<V, 8>(A, val, x, y, s, gst, gmode); break;
+        case 16: launch_vector_l<V, 16>(A, val, x, y, s, gst, gmode); break;
+        case 32: launch_vector_l<V, 32>(A, val, x, y, s, gst, gmode); break;
+        default: launch_vector_l<V, 64>(A, val, x, y, s, gst, gmode); break;
+        }
+        break;
+    case SPK_KERNEL_MERGE: {
+        V *cv = reinterpret_cast<V *>(A->carry_val);
+        hipLaunchKernelGGL((k_spmv_merge<V>), dim3(A->mtiles), dim3(kBlock), 0, s, A->n,
+                           (int)A->nnz, A->rowptr, A->col, val, x, y, A->tile_row, A->tile_k,
+                           A->carry_row, cv, gst, gmode);
+        hipLaunchKernelGGL((k_merge_fixup<V>), dim3(ceil_div(A->mtiles, kBlock)), dim3(kBlock), 0,
+                           s, A->n, A->mtiles, A->carry_row, (const V *)cv, y, gst, gmode);
+        break;
+    }
+    default:
+        set_error("internal: unknown kernel %d", A->kernel);
+        return SPK_EINVAL;
+    }
+    SPK_HIP(hipGetLastError());
+    return SPK_OK;
+}
+
+template int launch_spmv<double>(const spk_mat *, const double *, const double *, double *,
+                                 hipStream_t, const SysState *, int);
+template int launch_spmv<float>(const spk_mat *, const float *, const float *, float *,
+                                hipStream_t, const SysState *, int);
+
+static int grid_for(int64_t m)
+{
+    int64_t g = (m + kBlock - 1) / kBlock;
+    if (g > kMaxBlocksSingle) g = kMaxBlocksSingle;
+    if (g < 1) g = 1;
+    return (int)g;
+}
+
+void update_info(spk_mat *A)
+{
+    spk_mat_info &I = A->info;
+    const RowStats &S = A->stats;
+    I.n = A->n;
+    I.nnz = A->nnz;
+    I.kernel = A->kernel;
+    I.lanes = A->kernel == SPK_KERNEL_VECTOR ? A->lanes
+              : A->kernel == SPK_KERNEL_STREAM ? A->R : kMergeItems;
+    I.has_f32 = A->val32 != nullptr;
+    I.row_min = A->n ? S.min_len : 0;
+    I.row_max = S.max_len;
+    const double n = A->n > 0 ? (double)A->n : 1.0;
+    I.row_mean = (double)S.sum_len / n;
+    const double var = (double)S.sum_len2 / n - I.row_mean * I.row_mean;
+    I.row_cv = I.row_mean > 0 ? sqrt(var > 0 ? var : 0) / I.row_mean : 0.0;
+    // percentiles: upper bound of the log2 bin holding the 50% / 99% rank
+    int64_t acc = 0;
+    I.row_p50 = I.row_p99 = 0;
+    bool got50 = false;
+    for (int b = 0; b < 33; ++b) {
+        acc += S.hist[b];
+        const int ub = b == 0 ? 0 : (int)((1ll << b) - 1);
+        if (!got50 && acc * 2 >= A->n) { I.row_p50 = std::min(ub, S.max_len); got50 = true; }
+        if (acc * 100 >= (int64_t)A->n * 99) { I.row_p99 = std::min(ub, S.max_len); break; }
+    }
+    const int64_t nn = A->n, nz = A->nnz;
+    I.bytes_spmv_f64 = 12 * nz + 4 * (nn + 1) + 16 * nn;
+    I.bytes_spmv_f32 = 8 * nz + 4 * (nn + 1) + 8 * nn;
+    I.bytes_pcg_iter_f64 = 12 * nz + 4 * (nn + 1) + 96 * nn;
+    I.bytes_pcg_iter_f32 = 8 * nz + 4 * (nn + 1) + 48 * nn;
+    I.device_bytes = A->bytes + (A->ws ? A->ws->bytes : 0);
+    I.zero_diag_rows = S.zero_diag;
+}
+
+int ensure_f32(spk_mat *A, hipStream_t s)
+{
+    if (A->val32 || A->n == 0) return SPK_OK;
+    SPK_HIP(hipMalloc(&A->val32, sizeof(float) * (A->nnz > 0 ? A->nnz : 1)));
+    SPK_HIP(hipMalloc(&A->dinv32, sizeof(float) * A->n));
+    A->bytes += 4 * A->nnz + 4 * (int64_t)A->n;
+    if (A->nnz > 0)
+        hipLaunchKernelGGL(k_to_f32, dim3(grid_for(A->nnz)), dim3(kBlock), 0, s, A->nnz, A->val,
+                           A->val32);
+    hipLaunchKernelGGL(k_to_f32, dim3(grid_for(A->n)), dim3(kBlock), 0, s, (int64_t)A->n, A->dinv,
+                       A->dinv32);
+    SPK_HIP(hipGetLastError());
+    return SPK_OK;
+}
+
+static int pow2_ceil(double v)
+{
+    int L = 1;
+    while (L < v && L < 64) L <<= 1;
+    return L;
+}
+
+// Merge-path diagonals are int32: n + nnz must stay below 2^31.
+static bool merge_fits(const spk_mat *A) { return (int64_t)A->n + A->nnz < 0x7fff0000LL; }
+
+// Row-length statistics -> kernel family (stream for short, even rows; vector
+// for long, even rows; merge-path for skewed lengths).
+static void choose_kernel(spk_mat *A)
+{
+    const RowStats &S = A->stats;
+    const double mean = A->n ? (double)S.sum_len / A->n : 0.0;
+    const int cap = TileLds<double>::kCap;
+    int R = 0;
+    for (int t = 0; t < 6; ++t)
+        if (S.tile_max[t] <= cap) { R = kTileRs[t]; break; }
+    if (S.max_len <= 64 && R >= 32) {
+        A->kernel = SPK_KERNEL_STREAM;
+        A->R = R;
+    } else if ((mean >= 8 && S.max_len <= 8 * mean + 8) || !merge_fits(A)) {
+        A->kernel = SPK_KERNEL_VECTOR;
+        A->lanes = pow2_ceil(mean < 2 ? 2 : mean);
+        A->R = 256;
+    } else {
+        A->kernel = SPK_KERNEL_MERGE;
+        A->R = 256;
+    }
+}
+
+static int apply_partition(spk_mat *A)
+{
+    A->ntiles = ceil_div(A->n, A->R);
+    A->nblk = pick_nblk(A->ntiles, kMaxBlocksSingle);
+    return SPK_OK;
+}
+
+static int setup_merge(spk_mat *A, hipStream_t s)
+{
+    if (A->tile_row) return SPK_OK;
+    const int64_t items = (int64_t)A->n + A->nnz;
+    A->mtiles = (int)((items + kMergeItems - 1) / kMergeItems);
+    const int mt = A->mtiles > 0 ? A->mtiles : 1;
+    SPK_HIP(hipMalloc(&A->tile_row, sizeof(int32_t) * (mt + 1)));
+    SPK_HIP(hipMalloc(&A->tile_k, sizeof(int32_t) * (mt + 1)));
+    SPK_HIP(hipMalloc(&A->carry_row, sizeof(int32_t) * mt));
+    SPK_HIP(hipMalloc(&A->carry_val, sizeof(double) * mt));
+    A->bytes += (int64_t)mt * 20 + 8;
+    hipLaunchKernelGGL(k_merge_partition, dim3(ceil_div(A->mtiles + 1, kBlock)), dim3(kBlock), 0, s,
+                       A->n, (int)A->nnz, A->rowptr, A->mtiles, A->tile_row, A->tile_k);
+    SPK_HIP(hipGetLastError());
+    return SPK_OK;
+}
+
+void free_workspace(spk_mat *A);
+
+}  // namespace spk
+
+using namespace spk;
+
+// ================================================================== C ABI
+extern "C" {
+
+const char *spk_last_error(void) { return g_err; }
+
+const char *spk_status_str(int st)
+{
+    switch (st) {
+    case SPK_OK: return "SPK_OK";
+    case SPK_EINVAL: return "SPK_EINVAL";
+    case SPK_ENOMEM: return "SPK_ENOMEM";
+    case SPK_EHIP: return "SPK_EHIP";
+    case SPK_EZERODIAG: return "SPK_EZERODIAG";
+    case SPK_EBUSY: return "SPK_EBUSY";
+    case SPK_EBUDGET: return "SPK_EBUDGET";
+    case SPK_ENOTFOUND: return "SPK_ENOTFOUND";
+    }
+    return "SPK_UNKNOWN_STATUS";
+}
+
+const char *spk_reason_str(int r)
+{
+    switch (r) {
+    case SPK_CONVERGED_RTOL: return "CONVERGED_RTOL";
+    case SPK_CONVERGED_ATOL: return "CONVERGED_ATOL";
+    case SPK_RUNNING: return "RUNNING";
+    case SPK_DIVERGED_ITS: return "DIVERGED_ITS";
+    case SPK_DIVERGED_INDEFINITE_MAT: return "DIVERGED_INDEFINITE_MAT";
+    case SPK_DIVERGED_INDEFINITE_PC: return "DIVERGED_INDEFINITE_PC";
+    case SPK_DIVERGED_NANORINF: return "DIVERGED_NANORINF";
+    case SPK_DIVERGED_BREAKDOWN: return "DIVERGED_BREAKDOWN";
+    case SPK_DIVERGED_STAGNATION: return "DIVERGED_STAGNATION";
+    }
+    return "UNKNOWN_REASON";
+}
+
+double spk_now(void)
+{
+    struct timespec ts;
+    clock_gettime(CLOCK_MONOTONIC, &ts);
+    return (double)ts.tv_sec + 1e-9 * (double)ts.tv_nsec;
+}
+
+int spk_runtime_version(void)
+{
+    int v = 0;
+    if (hipRuntimeGetVersion(&v) != hipSuccess) return -1;
+    return v;
+}
+
+static int create_impl(int32_t n, int64_t nnz, const int32_t *rowptr, const int32_t *colind,
+                       const double *values, int memtype, uint32_t flags, hipStream_t s,
+                       spk_mat *A)
+{
+    A->n = n;
+    A->nnz = nnz;
+    SPK_HIP(hipGetDevice(&A->device));
+    const bool borrow = (flags & SPK_MAT_BORROW) != 0;
+    const size_t nzb = nnz > 0 ? (size_t)nnz : 1;
+    if (borrow) {
+        A->own_csr = false;
+        A->rowptr = const_cast<int32_t *>(rowptr);
+        A->col = const_cast<int32_t *>(colind);
+        A->val = const_cast<double *>(values);
+    } else {
+        SPK_HIP(hipMalloc(&A->rowptr, sizeof(int32_t) * ((size_t)n + 1)));
+        SPK_HIP(hipMalloc(&A->col, sizeof(int32_t) * nzb));
+        SPK_HIP(hipMalloc(&A->val, sizeof(double) * nzb));
+        A->bytes += 4 * ((int64_t)n + 1) + 12 * nnz;
+        const hipMemcpyKind kind = memtype == SPK_MEM_HOST ? hipMemcpyHostToDevice
+                                                           : hipMemcpyDeviceToDevice;
+        if (memtype == SPK_MEM_HOST) {
+            // stage through pinned memory in chunks (Response A4: pinned transfers)
+            const size_t chunk = 64u << 20;
+            char *pin = nullptr;
+            SPK_HIP(hipHostMalloc((void **)&pin, chunk, hipHostMallocDefault));
+            struct Part { void *dst; const void *src; size_t bytes; } parts[3] = {
+                {A->rowptr, rowptr, sizeof(int32_t) * ((size_t)n + 1)},
+                {A->col, colind, sizeof(int32_t) * (size_t)nnz},
+                {A->val, values, sizeof(double) * (size_t)nnz}};
+            int rc = SPK_OK;
+            for (auto &pt : parts) {
+                for (size_t off = 0; off < pt.bytes && rc == SPK_OK; off += chunk) {
+                    const size_t len = std::min(chunk, pt.bytes - off);
+                    memcpy(pin, (const char *)pt.src + off, len);
+                    hipError_t e = hipMemcpyAsync((char *)pt.dst + off, pin, len,
+                                                  hipMemcpyHostToDevice, s);
+                    if (e == hipSuccess) e = hipStreamSynchronize(s);
+                    if (e != hipSuccess) rc = hip_fail(e, "pinned upload", __FILE__, __LINE__);
+                }
+            }
+            hipHostFree(pin);
+            if (rc) return rc;
+        } else {
+            SPK_HIP(hipMemcpyAsync(A->rowptr, rowptr, sizeof(int32_t) * ((size_t)n + 1), kind, s));
+            if (nnz > 0) {
+                SPK_HIP(hipMemcpyAsync(A->col, colind, sizeof(int32_t) * nnz, kind, s));
+                SPK_HIP(hipMemcpyAsync(A->val, values, sizeof(double) * nnz, kind, s));
+            }
+        }
+    }
+    SPK_HIP(hipMalloc(&A->dinv, sizeof(double) * (n > 0 ? n : 1)));
+    A->bytes += 8 * (int64_t)n;
+
+    // statistics + structural checks (memory safety of every later kernel)
+    RowStats *dst = nullptr, *hst = nullptr;
+    SPK_HIP(hipMalloc(&dst, sizeof(RowStats)));
+    SPK_HIP(hipHostMalloc((void **)&hst, sizeof(RowStats), hipHostMallocDefault));
+    RowStats init{};
+    init.min_len = 0x7fffffff;
+    int rc = SPK_OK;
+    auto fail = [&](int code) { rc = code; };
+    do {
+        hipError_t e = hipMemcpyAsync(dst, &init, sizeof(RowStats), hipMemcpyHostToDevice, s);
+        if (e != hipSuccess) { fail(hip_fail(e, "stats init", __FILE__, __LINE__)); break; }
+        if (n > 0)
+            hipLaunchKernelGGL(k_row_stats, dim3(grid_for(n)), dim3(kBlock), 0, s, n, nnz, A->rowptr,
+                               dst);
+        e = hipMemcpyAsync(hst, dst, sizeof(RowStats), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) { fail(hip_fail(e, "row statistics", __FILE__, __LINE__)); break; }
+        if (hst->bad_rowptr) {
+            set_error("malformed rowptr: %d rows out of order or outside [0, nnz] "
+                      "(rowptr[0] must be 0 and rowptr[n] = nnz)", hst->bad_rowptr);
+            fail(SPK_EINVAL);
+            break;
+        }
+        if (n > 0) {
+            hipLaunchKernelGGL(k_check_cols, dim3(grid_for(n)), dim3(kBlock), 0, s, n, A->rowptr,
+                               A->col, (flags & SPK_MAT_VALIDATE) ? 1 : 0, dst);
+            hipLaunchKernelGGL(k_diag_inv, dim3(grid_for(n)), dim3(kBlock), 0, s, n, A->rowptr,
+                               A->col, A->val, A->dinv, dst);
+        }
+        e = hipMemcpyAsync(hst, dst, sizeof(RowStats), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) { fail(hip_fail(e, "column checks", __FILE__, __LINE__)); break; }
+        if (hst->bad_col) {
+            set_error("%d column indices outside [0, n)", hst->bad_col);
+            fail(SPK_EINVAL);
+            break;
+        }
+        if (hst->unsorted) {
+            set_error("%d entries not strictly ascending within their row", hst->unsorted);
+            fail(SPK_EINVAL);
+            break;
+        }
+        A->stats = *hst;
+    } while (0);
+    hipFree(dst);
+    hipHostFree(hst);
+    if (rc) return rc;
+
+    choose_kernel(A);
+    if (const char *f = getenv("SPK_FORCE_KERNEL")) {
+        if (!strncmp(f, "stream", 6)) A->kernel = SPK_KERNEL_STREAM;
+        else if (!strncmp(f, "merge", 5) && merge_fits(A)) A->kernel = SPK_KERNEL_MERGE;
+        else if (!strncmp(f, "vector", 6)) {
+            A->kernel = SPK_KERNEL_VECTOR;
+            const char *c = strchr(f, ':');
+            A->lanes = c ? atoi(c + 1) : 32;
+        }
+    }
+    if (A->kernel != SPK_KERNEL_STREAM) A->R = 256;
+    if (A->kernel == SPK_KERNEL_STREAM && A->R == 0) A->R = 32;
+    apply_partition(A);
+    if (A->kernel == SPK_KERNEL_MERGE) {
+        rc = setup_merge(A, s);
+        if (rc) return rc;
+    }
+    if (flags & SPK_MAT_MIXED) {
+        rc = ensure_f32(A, s);
+        if (rc) return rc;
+    }
+    SPK_HIP(hipStreamSynchronize(s));
+    update_info(A);
+    return SPK_OK;
+}
+
+int spk_mat_create_csr(int32_t n, int64_t nnz, const int32_t *rowptr, const int32_t *colind,
+                       const double *values, int memtype, uint32_t flags, void *stream,
+                       spk_mat **out)
+{
+    if (!out) { set_error("out is NULL"); return SPK_EINVAL; }
+    *out = nullptr;
+    if (n < 0 || nnz < 0 || nnz > 0x7fffffffLL) {
+        set_error("n = %d, nnz = %lld: need 0 <= n and 0 <= nnz < 2^31", n, (long long)nnz);
+        return SPK_EINVAL;
+    }
+    if (!rowptr || (nnz > 0 && (!colind || !values))) { set_error("NULL array"); return SPK_EINVAL; }
+    if (memtype != SPK_MEM_HOST && memtype != SPK_MEM_DEVICE) {
+        set_error("memtype %d", memtype);
+        return SPK_EINVAL;
+    }
+    if ((flags & SPK_MAT_BORROW) && memtype != SPK_MEM_DEVICE) {
+        set_error("SPK_MAT_BORROW needs SPK_MEM_DEVICE");
+        return SPK_EINVAL;
+    }
+    if (flags & ~(uint32_t)(SPK_MAT_MIXED | SPK_MAT_VALIDATE | SPK_MAT_BORROW)) {
+        set_error("unknown flags 0x%x", flags);
+        return SPK_EINVAL;
+    }
+    if (memtype == SPK_MEM_HOST) {
+        if (rowptr[0] != 0 || rowptr[n] != nnz) {
+            set_error("rowptr[0] = %d, rowptr[n] = %d, nnz = %lld", rowptr[0], rowptr[n],
+                      (long long)nnz);
+            return SPK_EINVAL;
+        }
+    }
+    spk_mat *A = new (std::nothrow) spk_mat();
+    if (!A) { set_error("out of host memory"); return SPK_ENOMEM; }
+    const int rc = create_impl(n, nnz, rowptr, colind, values, memtype, flags,
+                               (hipStream_t)stream, A);
+    if (rc) {
+        spk_mat_destroy(A);
+        return rc;
+    }
+    *out = A;
+    return SPK_OK;
+}
+
+int spk_mat_set_kernel(spk_mat *A, int kernel, int32_t param)
+{
+    if (!A) { set_error("A is NULL"); return SPK_EINVAL; }
+    switch (kernel) {
+    case SPK_KERNEL_AUTO: choose_kernel(A); break;
+    case SPK_KERNEL_STREAM: {
+        int R = param;
+        if (R == 0) {
+            for (int t = 0; t < 6; ++t)
+                if (A->stats.tile_max[t] <= TileLds<double>::kCap) { R = kTileRs[t]; break; }
+            if (R == 0) R = 8;
+        }
+        if (R < 1 || R > kBlock) { set_error("stream rows per tile %d not in [1, 256]", R); return SPK_EINVAL; }
+        A->kernel = SPK_KERNEL_STREAM;
+        A->R = R;
+        break;
+    }
+    case SPK_KERNEL_VECTOR:
+        if (param < 1 || param > 64 || (param & (param - 1))) {
+            set_error("lanes %d not a power of two in [1, 64]", param);
+            return SPK_EINVAL;
+        }
+        A->kernel = SPK_KERNEL_VECTOR;
+        A->lanes = param;
+        A->R = 256;
+        break;
+    case SPK_KERNEL_MERGE:
+        if (!merge_fits(A)) { set_error("merge path needs n + nnz < 2^31"); return SPK_EINVAL; }
+        A->kernel = SPK_KERNEL_MERGE;
+        A->R = 256;
+        break;
+    default:
+        set_error("unknown kernel %d", kernel);
+        return SPK_EINVAL;
+    }
+    if (A->kernel == SPK_KERNEL_MERGE) {
+        const int rc = setup_merge(A, nullptr);
+        if (rc) return rc;
+        SPK_HIP(hipStreamSynchronize(nullptr));
+    }
+    apply_partition(A);
+    free_workspace(A);  // graphs and partials depend on the partition
+    update_info(A);
+    return SPK_OK;
+}
+
+int spk_mat_mult(const spk_mat *A, const double *x, double *y, void *stream)
+{
+    if (!A || (A->n > 0 && (!x || !y))) { set_error("NULL argument"); return SPK_EINVAL; }
+    if (x == y && A->n > 0) { set_error("x and y must not alias"); return SPK_EINVAL; }
+    return launch_spmv<double>(A, A->val, x, y, (hipStream_t)stream, nullptr, 0);
+}
+
+int spk_mat_mult_f32(const spk_mat *A, const float *x, float *y, void *stream)
+{
+    if (!A || (A->n > 0 && (!x || !y))) { set_error("NULL argument"); return SPK_EINVAL; }
+    if (x == y && A->n > 0) { set_error("x and y must not alias"); return SPK_EINVAL; }
+    if (!A->val32 && A->n > 0) { set_error("matrix has no FP32 values (create with SPK_MAT_MIXED)"); return SPK_EINVAL; }
+    return launch_spmv<float>(A, A->val32, x, y, (hipStream_t)stream, nullptr, 0);
+}
+
+int spk_mat_get_info(const spk_mat *A, spk_mat_info *info)
+{
+    if (!A || !info) { set_error("NULL argument"); return SPK_EINVAL; }
+    update_info(const_cast<spk_mat *>(A));
+    *info = A->info;
+    return SPK_OK;
+}
+
+int spk_pc_jacobi_apply(const spk_mat *A, const double *r, double *z, void *stream)
+{
+    if (!A || (A->n > 0 && (!r || !z))) { set_error("NULL argument"); return SPK_EINVAL; }
+    if (A->n == 0) return SPK_OK;
+    if (A->stats.zero_diag) {
+        set_error("%d rows have no stored or a zero diagonal", A->stats.zero_diag);
+        return SPK_EZERODIAG;
+    }
+    hipLaunchKernelGGL(k_pmul, dim3(grid_for(A->n)), dim3(kBlock), 0, (hipStream_t)stream, A->n,
+                       A->dinv, r, z);
+    SPK_HIP(hipGetLastError());
+    return SPK_OK;
+}
+
+int spk_mat_destroy(spk_mat *A)
+{
+    if (!A) return SPK_OK;
+    hipDeviceSynchronize();
+    free_workspace(A);
+    if (A->own_csr) {
+        hipFree(A->rowptr);
+        hipFree(A->col);
+        hipFree(A->val);
+    }
+    hipFree(A->val32);
+    hipFree(A->dinv);
+    hipFree(A->dinv32);
+    hipFree(A->tile_row);
+    hipFree(A->tile_k);
+    hipFree(A->carry_row);
+    hipFree(A->carry_val);
+    delete A;
+    return SPK_OK;
+}
+
+// ------------------------------------------------------------------ vectors
+int spk_vec_axpy(int32_t n, double alpha, const double *x, double *y, void *stream)
+{
+    if (n < 0 || (n > 0 && (!x || !y))) { set_error("bad argument"); return SPK_EINVAL; }
+    if (n == 0) return SPK_OK;
+    hipLaunchKernelGGL(k_axpy, dim3(grid_for(n)), dim3(kBlock), 0, (hipStream_t)stream, n, alpha, x, y);
+    SPK_HIP(hipGetLastError());
+    return SPK_OK;
+}
+
+int spk_vec_aypx(int32_t n, double beta, const double *x, double *y, void *stream)
+{
+    if (n < 0 || (n > 0 && (!x || !y))) { set_error("bad argument"); return SPK_EINVAL; }
+    if (n == 0) return SPK_OK;
+    hipLaunchKernelGGL(k_aypx, dim3(grid_for(n)), dim3(kBlock), 0, (hipStream_t)stream, n, beta, x, y);
+    SPK_HIP(hipGetLastError());
+    return SPK_OK;
+}
+
+// Per-stream reduction scratch (partials + counter), created on first use.
+struct DotScratch {
+    double *part = nullptr;
+    uint32_t *counter = nullptr;
+};
+static std::mutex g_dot_mu;
+static std::map<std::pair<int, void *>, DotScratch> g_dot;
+
+static int dot_launch(int32_t n, const double *x, const double *y, const double *w, int mode,
+                      double *result, void *stream)
+{
+    if (n < 0 || !x || !result || (mode != 2 && !y)) { set_error("bad argument"); return SPK_EINVAL; }
+    int dev = 0;
+    SPK_HIP(hipGetDevice(&dev));
+    DotScratch sc;
+    {
+        std::lock_guard<std::mutex> lk(g_dot_mu);
+        auto it = g_dot.find({dev, stream});
+        if (it == g_dot.end()) {
+            SPK_HIP(hipMalloc(&sc.part, sizeof(double) * 2 * kMaxBlocksSingle));
+            SPK_HIP(hipMalloc(&sc.counter, sizeof(uint32_t)));
+            SPK_HIP(hipMemset(sc.counter, 0, sizeof(uint32_t)));
+            g_dot[{dev, stream}] = sc;
+        } else {
+            sc = it->second;
+        }
+    }
+    int grid = grid_for(n > 0 ? n : 1);
+    if (grid >= kXcd) grid -= grid % kXcd;
+    hipLaunchKernelGGL(k_dot, dim3(grid), dim3(kBlock), 0, (hipStream_t)stream, n, x,
+                       mode == 2 ? x : y, w, mode, sc.part, sc.counter, result);
+    SPK_HIP(hipGetLastError());
+    return SPK_OK;
+}
+
+int spk_vec_dot(int32_t n, const double *x, const double *y, double *result, void *stream)
+{
+    return dot_launch(n, x, y, nullptr, 0, result, stream);
+}
+
+int spk_vec_dot2(int32_t n, const double *x, const double *y, const double *w, double *result,
+                 void *stream)
+{
+    if (!w) { set_error("w is NULL"); return SPK_EINVAL; }
+    return dot_launch(n, x, y, w, 1, result, stream);
+}
+
+int spk_vec_nrm2(int32_t n, const double *x, double *result, void *stream)
+{
+    return dot_launch(n, x, nullptr, nullptr, 2, result, stream);
+}
+
+int spk_bw_copy(int64_t n, const double *src, double *dst, void *stream)
+{
+    if (n < 0 || (n & 1) || (n > 0 && (!src || !dst))) { set_error("n must be even and >= 0"); return SPK_EINVAL; }
+    if (n == 0) return SPK_OK;
+    const int64_t m = n / 2;
+    int64_t g = (m + kBlock - 1) / kBlock;
+    if (g > 8192) g = 8192;
+    hipLaunchKernelGGL(k_copy, dim3((int)g), dim3(kBlock), 0, (hipStream_t)stream, m,
+                       (const dvec2 *)src, (dvec2 *)dst);
+    SPK_HIP(hipGetLastError());
+    return SPK_OK;
+}
+
+int spk_cache_flush(void *scratch, int64_t bytes, void *stream)
+{
+    if (!scratch || bytes < 16) { set_error("bad argument"); return SPK_EINVAL; }
+    const int64_t m = bytes / 16;
+    int64_t g = (m + kBlock - 1) / kBlock;
+    if (g > 8192) g = 8192;
+    hipLaunchKernelGGL(k_scribble, dim3((int)g), dim3(kBlock), 0, (hipStream_t)stream, m,
+                       (dvec2 *)scratch, 1.0);
+    SPK_HIP(hipGetLastError());
+    return SPK_OK;
+}
+
+}  // extern "C"

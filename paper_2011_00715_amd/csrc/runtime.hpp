@@ -1,0 +1,89 @@
+// Host-side runtime structures of libspk.so.
+#pragma once
+
+#include <mutex>
+
+#include "common.hpp"
+
+namespace spk {
+
+struct RowStats {
+    unsigned long long sum_len;
+    unsigned long long sum_len2;
+    int32_t max_len;
+    int32_t min_len;
+    int32_t bad_rowptr;      // rows with rowptr[i+1] < rowptr[i] or out of [0, nnz]
+    int32_t bad_col;         // entries with col outside [0, n)
+    int32_t unsorted;        // rows whose columns are not strictly ascending
+    int32_t zero_diag;       // rows without a nonzero diagonal
+    int32_t tile_max[6];     // max nonzeros in an aligned tile of 256,128,64,32,16,8 rows
+    int32_t hist[33];        // rows by bit length of their length
+};
+
+constexpr int kTileRs[6] = {256, 128, 64, 32, 16, 8};
+
+// Solver workspace of one matrix (allocated on the first solve).
+struct Workspace {
+    int n = 0;
+    int has_mixed = 0;
+    SysDesc hdesc{};              // host copy of the descriptor
+    SysDesc *ddesc = nullptr;     // device descriptor (read by the kernels)
+    SysDesc *pdesc = nullptr;     // pinned staging for descriptor updates
+    int32_t *blk_start = nullptr; // device {0, nblk}
+    SysState *st = nullptr;       // device scalars
+    SysState *pst = nullptr;      // pinned host copy
+    int32_t *pstatus = nullptr;   // pinned ring of (status, phase) pairs
+    hipEvent_t ev[4] = {};
+    double *hist = nullptr;
+    int hist_cap = 0;
+    double *partials = nullptr;
+    double *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr;
+    double *x = nullptr;          // the solve's iterate (copied in and out)
+    float *r32 = nullptr, *z32 = nullptr, *p32 = nullptr, *q32 = nullptr, *d32 = nullptr;
+    hipStream_t cap = nullptr;    // private stream used only to capture graphs
+    hipGraphExec_t g64 = nullptr, gmix = nullptr;
+    int g64_k = 0, gmix_k = 0;
+    int64_t bytes = 0;
+};
+
+}  // namespace spk
+
+struct spk_mat {
+    int32_t n = 0;
+    int64_t nnz = 0;
+    int device = 0;
+    int32_t *rowptr = nullptr;
+    int32_t *col = nullptr;
+    double *val = nullptr;
+    float *val32 = nullptr;
+    double *dinv = nullptr;
+    float *dinv32 = nullptr;
+    bool own_csr = true;
+    spk::RowStats stats{};
+    spk_mat_info info{};
+    // SpMV selection
+    int kernel = SPK_KERNEL_STREAM;
+    int lanes = 0;          // VECTOR: lanes per row
+    int R = 256;            // rows per tile (stream kernel and solver row partition)
+    int ntiles = 0;
+    int nblk = 0;
+    // merge path
+    int mtiles = 0;
+    int32_t *tile_row = nullptr, *tile_k = nullptr, *carry_row = nullptr;
+    double *carry_val = nullptr;
+    spk::Workspace *ws = nullptr;
+    int64_t bytes = 0;
+};
+
+namespace spk {
+
+// y = A x with the handle's kernel (V = double or float); optional gate for
+// launches inside captured solver graphs.
+template <class V>
+int launch_spmv(const spk_mat *A, const V *val, const V *x, V *y, hipStream_t s,
+                const SysState *gate_st, int gate_mode);
+
+void update_info(spk_mat *A);
+int ensure_f32(spk_mat *A, hipStream_t s);
+
+}  // namespace spk

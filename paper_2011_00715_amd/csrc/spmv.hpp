@@ -1,0 +1,294 @@
+// CSR SpMV kernels for gfx950 (y = A x, the MatMult on AIJ of Sec. 4).
+//
+// Three families, chosen from row-length statistics at matrix creation:
+//  * stream : a block owns a tile of R consecutive rows.  All 256 lanes read
+//             the tile's column and value streams contiguously (non-temporal,
+//             so x stays in cache), gather x, and stage the products in LDS;
+//             then one lane per row sums its products in order.  Every lane is
+//             busy during the loads even for 5..27-entry rows.
+//  * vector : L lanes per row (L = 64 is one row per wavefront), lane-strided
+//             FMA partial sums, butterfly shuffle reduction inside the group.
+//  * merge  : merge-path over the sequence of (row ends + nonzeros), split into
+//             equal tiles of 2048 items; each lane walks 8 items, a segmented
+//             scan in LDS combines rows split across lanes, and a fix-up pass
+//             adds rows split across tiles in tile order (no atomics, so the
+//             result is reproducible bit for bit).
+#pragma once
+
+#include "common.hpp"
+
+namespace spk {
+
+enum { kGateNone = 0, kGateInner64 = 1, kGateInner32 = 2, kGateResid = 3 };
+
+// Whether a solver kernel launched inside a captured graph should run.
+__device__ __forceinline__ bool gate_open(const SysState *st, int mode)
+{
+    switch (mode) {
+    case kGateNone: return true;
+    case kGateInner64:
+        return st->status == SPK_RUNNING && st->phase == kPhaseInner && st->mixed == 0;
+    case kGateInner32:
+        return st->status == SPK_RUNNING && st->phase == kPhaseInner && st->mixed == 1;
+    case kGateResid:
+        return st->status == SPK_RUNNING && st->mixed == 1 &&
+               (st->phase == kPhaseResid || st->phase == kPhaseUpdate);
+    }
+    return false;
+}
+
+template <class V>
+struct TileLds {
+    static constexpr int kCap = kTileBytes / (int)sizeof(V);
+    V prod[kCap];
+    int32_t rp[kBlock + 1];
+    V red[kBlock / kWave];
+};
+
+// One tile of rows [r0, r1) (r1 - r0 <= kBlock).  fn(row, value) is called
+// once per row, by the lane that owns it.  Products are rounded to V and
+// summed in V in column order.  Tiles with more than kCap nonzeros take the
+// block-per-row path (block-wide FMA partials and a fixed-order block sum).
+template <class V, class Fn>
+__device__ __forceinline__ void stream_tile(int r0, int r1, const int32_t *__restrict__ rowptr,
+                                            const int32_t *__restrict__ col,
+                                            const V *__restrict__ val, const V *__restrict__ x,
+                                            TileLds<V> &sm, Fn &&fn)
+{
+    const int nr = r1 - r0;
+    for (int i = threadIdx.x; i <= nr; i += kBlock) sm.rp[i] = rowptr[r0 + i];
+    __syncthreads();
+    const int k0 = sm.rp[0];
+    const int k1 = sm.rp[nr];
+    if (k1 - k0 <= TileLds<V>::kCap) {
+        constexpr int U = 4;
+        for (int kb = k0 + (int)threadIdx.x; kb < k1; kb += kBlock * U) {
+            int c[U];
+            V v[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int k = kb + u * kBlock;
+                const int kc = k < k1 ? k : k1 - 1;
+                c[u] = ld_stream(col + kc);
+                v[u] = ld_stream(val + kc);
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int k = kb + u * kBlock;
+                const V xv = x[c[u]];
+                if (k < k1) sm.prod[k - k0] = v[u] * xv;
+            }
+        }
+        __syncthreads();
+        if ((int)threadIdx.x < nr) {
+            const int a = sm.rp[threadIdx.x] - k0;
+            const int e = sm.rp[threadIdx.x + 1] - k0;
+            V s = V(0);
+            for (int k = a; k < e; ++k) s += sm.prod[k];
+            fn(r0 + (int)threadIdx.x, s);
+        }
+    } else {
+        for (int i = 0; i < nr; ++i) {
+            const int a = sm.rp[i];
+            const int e = sm.rp[i + 1];
+            V s = V(0);
+            for (int k = a + (int)threadIdx.x; k < e; k += kBlock)
+                s = fma(ld_stream(val + k), x[ld_stream(col + k)], s);
+            s = block_sum(s, sm.red);
+            if (threadIdx.x == 0) fn(r0 + i, s);
+            __syncthreads();
+        }
+    }
+    __syncthreads();
+}
+
+// Standalone stream SpMV: grid = nblk logical blocks, each a contiguous chunk
+// of tiles (XCD-aware).
+template <class V>
+__global__ __launch_bounds__(kBlock) void k_spmv_stream(int n, int R, int ntiles, int nblk,
+                                                        const int32_t *__restrict__ rowptr,
+                                                        const int32_t *__restrict__ col,
+                                                        const V *__restrict__ val,
+                                                        const V *__restrict__ x, V *__restrict__ y)
+{
+    __shared__ TileLds<V> sm;
+    const int j = xcd_remap(blockIdx.x, nblk);
+    int t0, t1;
+    block_tiles(j, nblk, ntiles, t0, t1);
+    for (int t = t0; t < t1; ++t) {
+        const int r0 = t * R;
+        const int r1 = min(r0 + R, n);
+        stream_tile<V>(r0, r1, rowptr, col, val, x, sm, [&](int i, V s) { y[i] = s; });
+    }
+}
+
+// Vector CSR: L lanes per row, rows of a block contiguous (XCD-aware chunks).
+template <class V, int L>
+__global__ __launch_bounds__(kBlock) void k_spmv_vector(int n, const int32_t *__restrict__ rowptr,
+                                                        const int32_t *__restrict__ col,
+                                                        const V *__restrict__ val,
+                                                        const V *__restrict__ x, V *__restrict__ y,
+                                                        const SysState *gate_st, int gate_mode)
+{
+    if (gate_st && !gate_open(gate_st, gate_mode)) return;
+    const int nb = gridDim.x;
+    const int j = xcd_remap(blockIdx.x, nb);
+    constexpr int RPB = kBlock / L;  // rows per block pass
+    const int64_t rows_per_blk = (((int64_t)n + nb - 1) / nb + RPB - 1) / RPB * RPB;
+    const int rb = (int)min((int64_t)n, (int64_t)j * rows_per_blk);
+    const int re = (int)min((int64_t)n, (int64_t)(j + 1) * rows_per_blk);
+    const int lane = threadIdx.x % L;
+    for (int row = rb + (int)threadIdx.x / L; row < re; row += RPB) {
+        const int a = rowptr[row];
+        const int e = rowptr[row + 1];
+        V s = V(0);
+        for (int k = a + lane; k < e; k += L) s = fma(ld_stream(val + k), x[ld_stream(col + k)], s);
+#pragma unroll
+        for (int off = L / 2; off > 0; off >>= 1) s += __shfl_xor(s, off, L);
+        if (lane == 0) y[row] = s;
+    }
+}
+
+// ------------------------------------------------------------------ merge path
+// Split point of diagonal d on the merge of row ends (rowptr[i+1]) with
+// nonzero indices: (i, d - i) with i the number of completed rows.
+static __global__ void k_merge_partition(int n, int nnz, const int32_t *__restrict__ rowptr, int ntiles,
+                                  int32_t *__restrict__ tile_row, int32_t *__restrict__ tile_k)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t > ntiles) return;
+    const int64_t total = (int64_t)n + nnz;
+    const int64_t d64 = min((int64_t)t * kMergeItems, total);
+    const int d = (int)d64;
+    int lo = d > nnz ? d - nnz : 0;
+    int hi = d < n ? d : n;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (rowptr[mid + 1] <= d - mid - 1) lo = mid + 1; else hi = mid;
+    }
+    tile_row[t] = lo;
+    tile_k[t] = d - lo;
+}
+
+template <class V>
+struct MergeLds {
+    V prod[kMergeItems];
+    int32_t rend[kMergeItems + 1];
+    V sv[2][kBlock];
+    int32_t sk[kBlock];
+};
+
+// One merge-path tile per block.  Rows that end inside the tile are written
+// (complete rows directly, rows split across lanes after a segmented scan);
+// the partial of the row still open at the tile end goes to carry_{row,val}.
+template <class V>
+__global__ __launch_bounds__(kBlock) void k_spmv_merge(int n, int nnz,
+                                                       const int32_t *__restrict__ rowptr,
+                                                       const int32_t *__restrict__ col,
+                                                       const V *__restrict__ val,
+                                                       const V *__restrict__ x, V *__restrict__ y,
+                                                       const int32_t *__restrict__ tile_row,
+                                                       const int32_t *__restrict__ tile_k,
+                                                       int32_t *__restrict__ carry_row,
+                                                       V *__restrict__ carry_val,
+                                                       const SysState *gate_st, int gate_mode)
+{
+    if (gate_st && !gate_open(gate_st, gate_mode)) return;
+    __shared__ MergeLds<V> sm;
+    const int t = blockIdx.x;
+    const int i0 = tile_row[t], k0 = tile_k[t];
+    const int i1 = tile_row[t + 1], k1 = tile_k[t + 1];
+    const int nrows = i1 - i0;   // row ends inside the tile
+    const int nk = k1 - k0;      // nonzeros inside the tile
+    for (int r = threadIdx.x; r <= nrows; r += kBlock)
+        sm.rend[r] = (i0 + r < n) ? rowptr[i0 + r + 1] - k0 : nk;
+    {
+        constexpr int U = 4;
+        for (int kb = k0 + (int)threadIdx.x; kb < k1; kb += kBlock * U) {
+            int c[U];
+            V v[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int k = kb + u * kBlock;
+                const int kc = k < k1 ? k : k1 - 1;
+                c[u] = ld_stream(col + kc);
+                v[u] = ld_stream(val + kc);
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int k = kb + u * kBlock;
+                const V xv = x[c[u]];
+                if (k < k1) sm.prod[k - k0] = v[u] * xv;
+            }
+        }
+    }
+    __syncthreads();
+    // this lane's start on the tile-local merge path
+    const int total = nrows + nk;
+    const int dd = min((int)threadIdx.x * kMergeIpt, total);
+    int lo = dd > nk ? dd - nk : 0;
+    int hi = dd < nrows ? dd : nrows;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (sm.rend[mid] <= dd - mid - 1) lo = mid + 1; else hi = mid;
+    }
+    int r = lo;
+    int kk = dd - lo;
+    const int items = min(kMergeIpt, total - dd);
+    V acc = V(0);
+    V head = V(0);
+    int head_row = -1;
+    for (int it = 0; it < items; ++it) {
+        if (kk < nk && kk < sm.rend[r]) {
+            acc += sm.prod[kk];
+            ++kk;
+        } else {
+            if (r >= nrows || i0 + r >= n) break;  // never taken on a consistent path
+            if (head_row < 0) { head = acc; head_row = r; }
+            else y[i0 + r] = acc;
+            acc = V(0);
+            ++r;
+        }
+    }
+    // inclusive segmented scan of (carry row, carry value) over the lanes
+    sm.sk[threadIdx.x] = r;
+    sm.sv[0][threadIdx.x] = acc;
+    __syncthreads();
+    int cur = 0;
+#pragma unroll
+    for (int off = 1; off < kBlock; off <<= 1) {
+        V v = sm.sv[cur][threadIdx.x];
+        if ((int)threadIdx.x >= off && sm.sk[threadIdx.x - off] == r)
+            v = sm.sv[cur][threadIdx.x - off] + v;
+        sm.sv[cur ^ 1][threadIdx.x] = v;
+        cur ^= 1;
+        __syncthreads();
+    }
+    if (head_row >= 0) {
+        const V cin = threadIdx.x > 0 ? sm.sv[cur][threadIdx.x - 1] : V(0);
+        y[i0 + head_row] = cin + head;
+    }
+    if (threadIdx.x == kBlock - 1) {
+        carry_row[t] = i0 + r;
+        carry_val[t] = sm.sv[cur][threadIdx.x];
+    }
+}
+
+// Adds the carries of rows that span tiles, in tile order; one lane per chain.
+template <class V>
+__global__ void k_merge_fixup(int n, int ntiles, const int32_t *__restrict__ carry_row,
+                              const V *__restrict__ carry_val, V *__restrict__ y,
+                              const SysState *gate_st, int gate_mode)
+{
+    if (gate_st && !gate_open(gate_st, gate_mode)) return;
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= ntiles) return;
+    const int c = carry_row[t];
+    if (c >= n) return;
+    if (t > 0 && carry_row[t - 1] == c) return;
+    V s = carry_val[t];
+    for (int u = t + 1; u < ntiles && carry_row[u] == c; ++u) s += carry_val[u];
+    y[c] += s;
+}
+
+}  // namespace spk

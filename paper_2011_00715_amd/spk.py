@@ -1,0 +1,434 @@
+"""ctypes binding of libspk.so (argument marshalling only).
+
+Every function has the name of the C entry point without the ``spk_`` prefix
+and takes torch tensors where the C call takes device pointers; the tensor's
+data pointer and the current torch stream are passed through.  There is no
+fallback of any kind: if the HIP library is not built, importing this module
+raises.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch  # loads the HIP runtime that libspk.so then shares
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libspk.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(
+        f"{LIB_PATH} is missing: build the HIP library first "
+        "(python -m paper_2011_00715_amd.build or __graft_entry__.build())")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+P = ctypes.c_void_p
+i32 = ctypes.c_int32
+i64 = ctypes.c_int64
+u32 = ctypes.c_uint32
+u64 = ctypes.c_uint64
+dbl = ctypes.c_double
+
+# ------------------------------------------------------------------ constants
+MEM_HOST, MEM_DEVICE = 0, 1
+PREC_FP64, PREC_MIXED = 0, 1
+MAT_MIXED, MAT_VALIDATE, MAT_BORROW = 1, 2, 4
+KERNEL_AUTO, KERNEL_STREAM, KERNEL_VECTOR, KERNEL_MERGE = 0, 1, 2, 3
+KERNEL_NAMES = {1: "stream", 2: "vector", 3: "merge"}
+OK, EINVAL, ENOMEM, EHIP, EZERODIAG, EBUSY, EBUDGET, ENOTFOUND = 0, -1, -2, -3, -4, -5, -6, -7
+CONVERGED_RTOL, CONVERGED_ATOL = 1, 2
+DIVERGED_ITS, DIVERGED_INDEFINITE_MAT, DIVERGED_INDEFINITE_PC = -1, -2, -3
+DIVERGED_NANORINF, DIVERGED_BREAKDOWN, DIVERGED_STAGNATION = -4, -5, -6
+
+
+class MatInfo(ctypes.Structure):
+    _fields_ = [
+        ("n", i32), ("kernel", i32), ("nnz", i64), ("lanes", i32), ("has_f32", i32),
+        ("row_min", i32), ("row_max", i32), ("row_p50", i32), ("row_p99", i32),
+        ("row_mean", dbl), ("row_cv", dbl),
+        ("bytes_spmv_f64", i64), ("bytes_spmv_f32", i64),
+        ("bytes_pcg_iter_f64", i64), ("bytes_pcg_iter_f32", i64),
+        ("device_bytes", i64), ("zero_diag_rows", i32), ("pad_", i32),
+    ]
+
+
+class KspOpts(ctypes.Structure):
+    _fields_ = [
+        ("rtol", dbl), ("atol", dbl), ("maxit", i32), ("precision", i32),
+        ("x0_nonzero", i32), ("graph_k", i32), ("inner_rtol", dbl),
+        ("inner_maxit", i32), ("max_outer", i32),
+        ("hist", ctypes.POINTER(dbl)), ("hist_len", i32), ("pad_", i32),
+    ]
+
+
+class KspResult(ctypes.Structure):
+    _fields_ = [
+        ("reason", i32), ("iterations", i32), ("inner_iterations", i32),
+        ("outer_steps", i32), ("restarts", i32), ("fallback_fp64", i32),
+        ("rnorm0", dbl), ("rnorm", dbl), ("bnorm", dbl),
+        ("true_rel_residual", dbl), ("seconds", dbl),
+    ]
+
+    def as_dict(self):
+        d = {f: getattr(self, f) for f, _ in self._fields_}
+        d["reason_str"] = reason_str(self.reason)
+        return d
+
+
+class ServerOpts(ctypes.Structure):
+    _fields_ = [
+        ("hbm_budget_bytes", i64), ("max_slots", i32), ("graph_k", i32),
+        ("max_blocks_per_system", i32), ("pad_", i32),
+    ]
+
+
+def _sig(name, res, args):
+    f = getattr(_lib, name)
+    f.restype = res
+    f.argtypes = args
+    return f
+
+
+_sig("spk_mat_create_csr", ctypes.c_int, [i32, i64, P, P, P, ctypes.c_int, u32, P,
+                                          ctypes.POINTER(P)])
+_sig("spk_mat_set_kernel", ctypes.c_int, [P, ctypes.c_int, i32])
+_sig("spk_mat_mult", ctypes.c_int, [P, P, P, P])
+_sig("spk_mat_mult_f32", ctypes.c_int, [P, P, P, P])
+_sig("spk_mat_get_info", ctypes.c_int, [P, ctypes.POINTER(MatInfo)])
+_sig("spk_pc_jacobi_apply", ctypes.c_int, [P, P, P, P])
+_sig("spk_mat_destroy", ctypes.c_int, [P])
+_sig("spk_vec_axpy", ctypes.c_int, [i32, dbl, P, P, P])
+_sig("spk_vec_aypx", ctypes.c_int, [i32, dbl, P, P, P])
+_sig("spk_vec_dot", ctypes.c_int, [i32, P, P, P, P])
+_sig("spk_vec_dot2", ctypes.c_int, [i32, P, P, P, P, P])
+_sig("spk_vec_nrm2", ctypes.c_int, [i32, P, P, P])
+_sig("spk_ksp_opts_default", None, [ctypes.POINTER(KspOpts)])
+_sig("spk_ksp_solve", ctypes.c_int, [P, P, P, ctypes.POINTER(KspOpts),
+                                     ctypes.POINTER(KspResult), P])
+_sig("spk_server_opts_default", None, [ctypes.POINTER(ServerOpts)])
+_sig("spk_server_create", ctypes.c_int, [ctypes.POINTER(ServerOpts), P, ctypes.POINTER(P)])
+_sig("spk_server_submit", ctypes.c_int, [P, i32, i64, P, P, P, P, ctypes.POINTER(KspOpts),
+                                         ctypes.POINTER(u64)])
+_sig("spk_server_progress", ctypes.c_int, [P, i32])
+_sig("spk_server_poll", ctypes.c_int, [P, u64, P, ctypes.POINTER(KspResult),
+                                       ctypes.POINTER(dbl)])
+_sig("spk_server_destroy", ctypes.c_int, [P])
+_sig("spk_status_str", ctypes.c_char_p, [ctypes.c_int])
+_sig("spk_reason_str", ctypes.c_char_p, [ctypes.c_int])
+_sig("spk_last_error", ctypes.c_char_p, [])
+_sig("spk_now", dbl, [])
+_sig("spk_runtime_version", ctypes.c_int, [])
+_sig("spk_bw_copy", ctypes.c_int, [i64, P, P, P])
+_sig("spk_cache_flush", ctypes.c_int, [P, i64, P])
+
+EXPORTS = [
+    "spk_mat_create_csr", "spk_mat_set_kernel", "spk_mat_mult", "spk_mat_mult_f32",
+    "spk_mat_get_info", "spk_pc_jacobi_apply", "spk_mat_destroy", "spk_vec_axpy",
+    "spk_vec_aypx", "spk_vec_dot", "spk_vec_dot2", "spk_vec_nrm2", "spk_ksp_opts_default",
+    "spk_ksp_solve", "spk_server_opts_default", "spk_server_create", "spk_server_submit",
+    "spk_server_progress", "spk_server_poll", "spk_server_destroy", "spk_status_str",
+    "spk_reason_str", "spk_last_error", "spk_now", "spk_runtime_version", "spk_bw_copy",
+    "spk_cache_flush",
+]
+
+
+class SpkError(RuntimeError):
+    def __init__(self, status, where):
+        self.status = status
+        super().__init__(f"{where}: {status_str(status)} ({last_error()})")
+
+
+def _check(rc, where):
+    if rc != OK:
+        raise SpkError(rc, where)
+    return rc
+
+
+def status_str(s: int) -> str:
+    return _lib.spk_status_str(s).decode()
+
+
+def reason_str(r: int) -> str:
+    return _lib.spk_reason_str(r).decode()
+
+
+def last_error() -> str:
+    return _lib.spk_last_error().decode()
+
+
+def now() -> float:
+    return _lib.spk_now()
+
+
+def runtime_version() -> int:
+    return _lib.spk_runtime_version()
+
+
+def _stream(stream=None):
+    if stream is None:
+        return P(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, torch.cuda.Stream):
+        return P(stream.cuda_stream)
+    return P(int(stream))
+
+
+def _dev(t: torch.Tensor, dtype, n=None, name="tensor"):
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if n is not None and t.numel() != n:
+        raise ValueError(f"{name} must have {n} elements, got {t.numel()}")
+    return P(t.data_ptr())
+
+
+# ------------------------------------------------------------------ matrix
+class Mat:
+    """Owns an spk_mat handle (and, for borrowed CSR, the device arrays)."""
+
+    def __init__(self, handle: int, keep=()):
+        self.handle = P(handle)
+        self._keep = keep
+        self.info = mat_get_info(self)
+        self.n = self.info.n
+        self.nnz = self.info.nnz
+
+    def close(self):
+        if self.handle:
+            mat_destroy(self)
+            self.handle = P()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+
+def mat_create_csr(rowptr, colind, values, flags: int = 0, stream=None) -> Mat:
+    """Create from torch tensors (all on the GPU: SPK_MEM_DEVICE) or NumPy
+    arrays (host: SPK_MEM_HOST, copied through pinned staging)."""
+    import numpy as np
+
+    out = P()
+    keep = ()
+    if isinstance(rowptr, torch.Tensor):
+        n = rowptr.numel() - 1
+        nnz = colind.numel()
+        args = (_dev(rowptr, torch.int32, name="rowptr"), _dev(colind, torch.int32, name="colind"),
+                _dev(values, torch.float64, name="values"))
+        mem = MEM_DEVICE
+        if flags & MAT_BORROW:
+            keep = (rowptr, colind, values)
+    else:
+        rowptr = np.ascontiguousarray(rowptr, dtype=np.int32)
+        colind = np.ascontiguousarray(colind, dtype=np.int32)
+        values = np.ascontiguousarray(values, dtype=np.float64)
+        n = rowptr.size - 1
+        nnz = colind.size
+        args = tuple(P(a.ctypes.data) for a in (rowptr, colind, values))
+        mem = MEM_HOST
+    _check(_lib.spk_mat_create_csr(n, nnz, *args, mem, flags, _stream(stream), ctypes.byref(out)),
+           "spk_mat_create_csr")
+    return Mat(out.value, keep)
+
+
+def mat_set_kernel(A: Mat, kernel: int, param: int = 0):
+    _check(_lib.spk_mat_set_kernel(A.handle, kernel, param), "spk_mat_set_kernel")
+    A.info = mat_get_info(A)
+
+
+def mat_mult(A: Mat, x: torch.Tensor, y: torch.Tensor, stream=None):
+    _check(_lib.spk_mat_mult(A.handle, _dev(x, torch.float64, A.n, "x"),
+                             _dev(y, torch.float64, A.n, "y"), _stream(stream)), "spk_mat_mult")
+
+
+def mat_mult_f32(A: Mat, x: torch.Tensor, y: torch.Tensor, stream=None):
+    _check(_lib.spk_mat_mult_f32(A.handle, _dev(x, torch.float32, A.n, "x"),
+                                 _dev(y, torch.float32, A.n, "y"), _stream(stream)),
+           "spk_mat_mult_f32")
+
+
+def mat_get_info(A: Mat) -> MatInfo:
+    info = MatInfo()
+    _check(_lib.spk_mat_get_info(A.handle, ctypes.byref(info)), "spk_mat_get_info")
+    return info
+
+
+def pc_jacobi_apply(A: Mat, r: torch.Tensor, z: torch.Tensor, stream=None):
+    _check(_lib.spk_pc_jacobi_apply(A.handle, _dev(r, torch.float64, A.n, "r"),
+                                    _dev(z, torch.float64, A.n, "z"), _stream(stream)),
+           "spk_pc_jacobi_apply")
+
+
+def mat_destroy(A: Mat):
+    _check(_lib.spk_mat_destroy(A.handle), "spk_mat_destroy")
+
+
+# ------------------------------------------------------------------ vectors
+def vec_axpy(alpha: float, x, y, stream=None):
+    n = x.numel()
+    _check(_lib.spk_vec_axpy(n, float(alpha), _dev(x, torch.float64, n, "x"),
+                             _dev(y, torch.float64, n, "y"), _stream(stream)), "spk_vec_axpy")
+
+
+def vec_aypx(beta: float, x, y, stream=None):
+    n = x.numel()
+    _check(_lib.spk_vec_aypx(n, float(beta), _dev(x, torch.float64, n, "x"),
+                             _dev(y, torch.float64, n, "y"), _stream(stream)), "spk_vec_aypx")
+
+
+def vec_dot(x, y, result, stream=None):
+    n = x.numel()
+    _check(_lib.spk_vec_dot(n, _dev(x, torch.float64, n, "x"), _dev(y, torch.float64, n, "y"),
+                            _dev(result, torch.float64, None, "result"), _stream(stream)),
+           "spk_vec_dot")
+
+
+def vec_dot2(x, y, w, result, stream=None):
+    n = x.numel()
+    _check(_lib.spk_vec_dot2(n, _dev(x, torch.float64, n, "x"), _dev(y, torch.float64, n, "y"),
+                             _dev(w, torch.float64, n, "w"),
+                             _dev(result, torch.float64, None, "result"), _stream(stream)),
+           "spk_vec_dot2")
+
+
+def vec_nrm2(x, result, stream=None):
+    n = x.numel()
+    _check(_lib.spk_vec_nrm2(n, _dev(x, torch.float64, n, "x"),
+                             _dev(result, torch.float64, None, "result"), _stream(stream)),
+           "spk_vec_nrm2")
+
+
+# ------------------------------------------------------------------ solver
+def ksp_opts_default() -> KspOpts:
+    o = KspOpts()
+    _lib.spk_ksp_opts_default(ctypes.byref(o))
+    return o
+
+
+def ksp_opts(**kw) -> KspOpts:
+    o = ksp_opts_default()
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise AttributeError(k)
+        setattr(o, k, v)
+    return o
+
+
+def ksp_solve(A: Mat, b, x, opts: KspOpts | None = None, hist=None, stream=None) -> KspResult:
+    """Solve A x = b.  ``hist`` (optional NumPy float64 array) receives the
+    residual history."""
+    o = opts if opts is not None else ksp_opts_default()
+    if hist is not None:
+        import numpy as np
+
+        assert hist.dtype == np.float64 and hist.flags.c_contiguous
+        o.hist = hist.ctypes.data_as(ctypes.POINTER(dbl))
+        o.hist_len = hist.size
+    res = KspResult()
+    _check(_lib.spk_ksp_solve(A.handle, _dev(b, torch.float64, A.n, "b"),
+                              _dev(x, torch.float64, A.n, "x"), ctypes.byref(o),
+                              ctypes.byref(res), _stream(stream)), "spk_ksp_solve")
+    return res
+
+
+# ------------------------------------------------------------------ server
+def server_opts_default() -> ServerOpts:
+    o = ServerOpts()
+    _lib.spk_server_opts_default(ctypes.byref(o))
+    return o
+
+
+class Server:
+    def __init__(self, handle):
+        self.handle = P(handle)
+
+    def close(self):
+        if self.handle:
+            server_destroy(self)
+            self.handle = P()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+
+def server_create(opts: ServerOpts | None = None, stream=None) -> Server:
+    o = opts if opts is not None else server_opts_default()
+    out = P()
+    _check(_lib.spk_server_create(ctypes.byref(o), _stream(stream), ctypes.byref(out)),
+           "spk_server_create")
+    return Server(out.value)
+
+
+def server_submit(S: Server, rowptr, colind, values, b, opts: KspOpts | None = None) -> int:
+    import numpy as np
+
+    rowptr = np.ascontiguousarray(rowptr, dtype=np.int32)
+    colind = np.ascontiguousarray(colind, dtype=np.int32)
+    values = np.ascontiguousarray(values, dtype=np.float64)
+    b = np.ascontiguousarray(b, dtype=np.float64)
+    t = u64()
+    o = ctypes.byref(opts) if opts is not None else None
+    rc = _lib.spk_server_submit(S.handle, rowptr.size - 1, colind.size, P(rowptr.ctypes.data),
+                                P(colind.ctypes.data), P(values.ctypes.data), P(b.ctypes.data),
+                                o, ctypes.byref(t))
+    _check(rc, "spk_server_submit")
+    return t.value
+
+
+def server_progress(S: Server, max_steps: int = 1) -> int:
+    rc = _lib.spk_server_progress(S.handle, max_steps)
+    if rc < 0:
+        raise SpkError(rc, "spk_server_progress")
+    return rc
+
+
+def server_poll(S: Server, ticket: int, x_host):
+    """Returns (KspResult, done_time) when finished, None while in flight."""
+    import numpy as np
+
+    assert x_host.dtype == np.float64 and x_host.flags.c_contiguous
+    res = KspResult()
+    tdone = dbl()
+    rc = _lib.spk_server_poll(S.handle, ticket, P(x_host.ctypes.data), ctypes.byref(res),
+                              ctypes.byref(tdone))
+    if rc == EBUSY:
+        return None
+    _check(rc, "spk_server_poll")
+    return res, tdone.value
+
+
+def server_destroy(S: Server):
+    _check(_lib.spk_server_destroy(S.handle), "spk_server_destroy")
+
+
+# ------------------------------------------------------------------ measurement
+def bw_copy(src: torch.Tensor, dst: torch.Tensor, stream=None):
+    n = src.numel()
+    _check(_lib.spk_bw_copy(n, _dev(src, torch.float64, n, "src"), _dev(dst, torch.float64, n, "dst"),
+                            _stream(stream)), "spk_bw_copy")
+
+
+def cache_flush(scratch: torch.Tensor, stream=None):
+    _check(_lib.spk_cache_flush(P(scratch.data_ptr()), scratch.numel() * scratch.element_size(),
+                                _stream(stream)), "spk_cache_flush")

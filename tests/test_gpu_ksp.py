@@ -1,0 +1,179 @@
+"""Jacobi-PCG parity: the HIP solver against the oracle on the same seeded
+inputs.  CG iterates depend on rounding, so the contract is: the true residual
+meets the tolerance for both, the iteration counts agree within max(2, 1%),
+the first 20 recursive residual norms agree to 1e-10 relative, and the
+solution error against the oracle stays within kappa * rtol."""
+
+import numpy as np
+import pytest
+
+import oracle
+import spkgen
+from gpu_util import mat_on_gpu, need_gpu, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+def _solve(spk, M, b, **kw):
+    import torch
+
+    hist = np.full(kw.pop("hist_len", 64), np.nan)
+    x0 = kw.pop("x0", None)
+    x = to_dev(x0) if x0 is not None else torch.zeros(M.n, dtype=torch.float64, device="cuda")
+    o = spk.ksp_opts(**kw)
+    if x0 is not None:
+        o.x0_nonzero = 1
+    res = spk.ksp_solve(M, to_dev(b), x, o, hist=hist)
+    return x.cpu().numpy(), res, hist
+
+
+def _cases():
+    yield "lap2d_64", spkgen.laplace2d5(64), 0
+    yield "lap3d_24", spkgen.laplace3d7(24), 1
+    yield "diff27_14", spkgen.diffusion3d27_lognormal(14, seed=0), 2
+    yield "powerlaw_20k", spkgen.powerlaw_spd(20000, seed=1), 3
+
+
+@pytest.mark.parametrize("case", ["lap2d_64", "lap3d_24", "diff27_14", "powerlaw_20k"])
+@pytest.mark.parametrize("kernel", ["auto", "vector", "merge"])
+def test_pcg_fp64_parity(case, kernel):
+    spk = need_gpu()
+    name, A, seed = [c for c in _cases() if c[0] == case][0]
+    M = mat_on_gpu(spk, A)
+    if kernel == "vector":
+        spk.mat_set_kernel(M, spk.KERNEL_VECTOR, 8)
+    elif kernel == "merge":
+        spk.mat_set_kernel(M, spk.KERNEL_MERGE, 0)
+    b = spkgen.rhs_uniform(A.n, seed)
+    x, res, hist = _solve(spk, M, b, hist_len=4000)
+    xo, ro, ho = oracle.pcg(A, b, rtol=1e-8, hist_len=4000)
+    assert res.reason == spk.CONVERGED_RTOL, res.as_dict()
+    assert abs(res.iterations - ro["iterations"]) <= max(2, 0.01 * ro["iterations"])
+    k = min(20, res.iterations, ro["iterations"])
+    assert np.allclose(hist[:k + 1], ho[:k + 1], rtol=1e-10, atol=0), (hist[:k + 1], ho[:k + 1])
+    # the oracle recomputes the true residual of the GPU's x
+    r = b - oracle.spmv(A, x)
+    assert oracle.nrm2(r) <= 1e-8 * oracle.nrm2(b) * (1 + 1e-6)
+    assert abs(res.true_rel_residual - oracle.nrm2(r) / oracle.nrm2(b)) <= 1e-12
+    assert res.bnorm == pytest.approx(ro["bnorm"], rel=1e-14)
+    err = np.linalg.norm(x - xo) / np.linalg.norm(xo)
+    assert err <= 1e-5, err  # both within kappa * 1e-8 of the solution
+
+
+def test_pcg_graph_and_direct_launch_identical():
+    spk = need_gpu()
+    A = spkgen.diffusion3d27_lognormal(12, seed=3)
+    M = mat_on_gpu(spk, A)
+    b = spkgen.rhs_uniform(A.n, 0)
+    outs = []
+    for gk in (8, 0, 3, 8):
+        x, res, _ = _solve(spk, M, b, graph_k=gk)
+        outs.append((x, res.iterations, res.rnorm))
+    for x, it, rn in outs[1:]:
+        assert np.array_equal(x, outs[0][0]) and it == outs[0][1] and rn == outs[0][2]
+
+
+def test_pcg_reasons():
+    spk = need_gpu()
+    A = spkgen.laplace2d5(10)
+    M = mat_on_gpu(spk, A)
+    b = spkgen.rhs_uniform(A.n, 0)
+    x, res, _ = _solve(spk, M, b, maxit=3)
+    xo, ro, _ = oracle.pcg(A, b, maxit=3)
+    assert res.reason == spk.DIVERGED_ITS and res.iterations == 3
+    assert np.allclose(x, xo, rtol=1e-12, atol=1e-14)
+    x, res, _ = _solve(spk, M, b, maxit=0)
+    assert res.reason == spk.DIVERGED_ITS and res.iterations == 0 and not x.any()
+    x, res, _ = _solve(spk, M, np.zeros(A.n))
+    assert res.reason == spk.CONVERGED_ATOL and res.iterations == 0 and not x.any()
+    x, res, _ = _solve(spk, M, np.zeros(A.n), x0=np.ones(A.n))
+    assert res.reason == spk.CONVERGED_ATOL and not x.any()
+    bn = b.copy()
+    bn[3] = np.nan
+    _, res, _ = _solve(spk, M, bn)
+    assert res.reason == spk.DIVERGED_NANORINF
+    An = spkgen.CSR(A.n, A.rowptr, A.col, -A.val)
+    _, res, _ = _solve(spk, mat_on_gpu(spk, An), b)
+    assert res.reason == spk.DIVERGED_INDEFINITE_PC
+    Ai = spkgen.dense_to_csr(np.array([[1.0, 2.0], [2.0, 1.0]]))
+    x, res, _ = _solve(spk, mat_on_gpu(spk, Ai), np.array([1.0, -1.0]))
+    assert res.reason == spk.DIVERGED_INDEFINITE_MAT and res.iterations == 0 and not x.any()
+    _, res, _ = _solve(spk, M, b, rtol=0.0, atol=1e-3)
+    _, ro, _ = oracle.pcg(A, b, rtol=0.0, atol=1e-3)
+    assert res.reason == spk.CONVERGED_ATOL and res.iterations == ro["iterations"]
+    xs = np.linalg.solve(spkgen.to_dense(A), b)
+    _, res, _ = _solve(spk, M, b, x0=xs)
+    assert res.iterations == 0 and res.reason > 0
+    Z = spkgen.dense_to_csr(np.array([[1.0, 2.0], [2.0, 0.0]]))
+    MZ = mat_on_gpu(spk, Z)
+    with pytest.raises(spk.SpkError) as e:
+        _solve(spk, MZ, np.ones(2))
+    assert e.value.status == spk.EZERODIAG
+
+
+def test_pcg_x0_nonzero_matches_oracle():
+    spk = need_gpu()
+    A = spkgen.laplace3d7(16)
+    M = mat_on_gpu(spk, A)
+    b = spkgen.rhs_uniform(A.n, 2)
+    x0 = spkgen.rhs_uniform(A.n, 3)
+    x, res, hist = _solve(spk, M, b, x0=x0, hist_len=400)
+    xo, ro, ho = oracle.pcg(A, b, x0=x0, hist_len=400)
+    assert abs(res.iterations - ro["iterations"]) <= 2
+    assert np.allclose(hist[:21], ho[:21], rtol=1e-10)
+
+
+def test_pcg_true_residual_restart_rule():
+    spk = need_gpu()
+    A = spkgen.laplace2d5(32)
+    M = mat_on_gpu(spk, A)
+    b = spkgen.rhs_uniform(A.n, 0)
+    _, res, _ = _solve(spk, M, b, rtol=1e-17, maxit=100000)
+    assert res.reason in (spk.DIVERGED_BREAKDOWN, spk.CONVERGED_RTOL)
+    if res.reason == spk.DIVERGED_BREAKDOWN:
+        assert res.restarts == 3
+    assert res.true_rel_residual < 1e-13
+
+
+@pytest.mark.parametrize("case", ["lap2d_64", "diff27_14", "powerlaw_20k"])
+def test_pcg_mixed_precision(case):
+    spk = need_gpu()
+    name, A, seed = [c for c in _cases() if c[0] == case][0]
+    M = mat_on_gpu(spk, A, flags=spk.MAT_MIXED)
+    b = spkgen.rhs_uniform(A.n, seed)
+    x, res, hist = _solve(spk, M, b, precision=spk.PREC_MIXED)
+    assert res.reason == spk.CONVERGED_RTOL, res.as_dict()
+    assert res.outer_steps >= 1 and res.inner_iterations > 0
+    r = b - oracle.spmv(A, x)
+    rel = oracle.nrm2(r) / oracle.nrm2(b)
+    assert rel <= 1e-8 * (1 + 1e-6), rel
+    xo, _, _ = oracle.pcg(A, b, rtol=1e-8)
+    err = np.linalg.norm(x - xo) / np.linalg.norm(xo)
+    assert err <= 1e-5, err
+    # outer residuals decrease
+    h = hist[: res.outer_steps + 1]
+    assert np.all(np.diff(h) < 0)
+
+
+def test_pcg_mixed_without_flag_converts_lazily():
+    spk = need_gpu()
+    A = spkgen.laplace2d5(40)
+    M = mat_on_gpu(spk, A)
+    assert M.info.has_f32 == 0
+    b = spkgen.rhs_uniform(A.n, 0)
+    _, res, _ = _solve(spk, M, b, precision=spk.PREC_MIXED)
+    assert res.reason == spk.CONVERGED_RTOL
+    assert spk.mat_get_info(M).has_f32 == 1
+
+
+def test_pcg_repeat_bitwise():
+    spk = need_gpu()
+    A = spkgen.powerlaw_spd(20000, seed=2)
+    M = mat_on_gpu(spk, A)
+    b = spkgen.rhs_uniform(A.n, 9)
+    x1, r1, _ = _solve(spk, M, b)
+    x2, r2, _ = _solve(spk, M, b)
+    assert np.array_equal(x1, x2) and r1.iterations == r2.iterations
+    x3, r3, _ = _solve(spk, M, b, precision=spk.PREC_MIXED)
+    x4, r4, _ = _solve(spk, M, b, precision=spk.PREC_MIXED)
+    assert np.array_equal(x3, x4) and r3.inner_iterations == r4.inner_iterations

@@ -1,0 +1,229 @@
+"""SpMV parity: every kernel family against the oracle on the same seeded
+inputs (bit-exact on integer data; per-row bound elsewhere, 1e-14 of
+sum_j |a_ij x_j| for the kernels the library selects)."""
+
+import numpy as np
+import pytest
+
+import oracle
+import spkgen
+from gpu_util import U32, U64, check_spmv, mat_on_gpu, need_gpu, spmv_bound_rows, to_dev
+
+pytestmark = pytest.mark.gpu
+
+KERNELS = [("auto", 0), ("stream", 0), ("stream", 64), ("stream", 8), ("merge", 0)] + [
+    ("vector", L) for L in (1, 2, 4, 8, 16, 32, 64)]
+
+
+def _set(spk, M, kernel, param):
+    if kernel == "auto":
+        return spk.KERNEL_NAMES[M.info.kernel], M.info.lanes
+    k = {"stream": spk.KERNEL_STREAM, "vector": spk.KERNEL_VECTOR, "merge": spk.KERNEL_MERGE}[kernel]
+    spk.mat_set_kernel(M, k, param)
+    return kernel, M.info.lanes
+
+
+def _matrices():
+    rng = np.random.default_rng(7)
+    D = rng.integers(-9, 10, size=(300, 300)) * (rng.random((300, 300)) < 0.05)
+    D[5] = 0  # an empty row
+    D[:, 7] = 0
+    yield "int_random_300", spkgen.dense_to_csr(D.astype(np.float64)), True
+    yield "lap2d_64", spkgen.laplace2d5(64), True
+    yield "lap2d_61_ragged", spkgen.laplace2d5(61), True
+    yield "lap3d_23", spkgen.laplace3d7(23), True
+    yield "diff27_13", spkgen.diffusion3d27_lognormal(13, seed=1), False
+    yield "powerlaw_30k", spkgen.powerlaw_spd(30000, seed=3), False
+
+
+@pytest.mark.parametrize("kernel,param", KERNELS)
+def test_spmv_parity_fp64(kernel, param):
+    spk = need_gpu()
+    for name, A, integer in _matrices():
+        M = mat_on_gpu(spk, A)
+        kname, lanes = _set(spk, M, kernel, param)
+        if integer:
+            x = np.random.default_rng(1).integers(-50, 50, size=A.n).astype(np.float64)
+        else:
+            x = spkgen.rhs_uniform(A.n, 2)
+        y = to_dev(np.full(A.n, np.nan))
+        spk.mat_mult(M, to_dev(x), y)
+        y = y.cpu().numpy()
+        ref = oracle.spmv(A, x)
+        if integer:
+            assert np.array_equal(y, ref), f"{name} {kname}: not bit-exact"
+        else:
+            scale = oracle.spmv_abs(A, x)
+            bound = np.maximum(spmv_bound_rows(A, kname, lanes, U64), 0.0)
+            if kernel == "auto":
+                bound = np.minimum(bound, 1e-14)  # the selected kernel meets 1e-14
+            check_spmv(y, ref, scale, bound, f"{name} {kname}/{lanes}")
+        M.close()
+
+
+@pytest.mark.parametrize("kernel,param", [("auto", 0), ("stream", 0), ("merge", 0), ("vector", 4),
+                                          ("vector", 64)])
+def test_spmv_parity_fp32(kernel, param):
+    spk = need_gpu()
+    for name, A, integer in _matrices():
+        M = mat_on_gpu(spk, A, flags=spk.MAT_MIXED)
+        kname, lanes = _set(spk, M, kernel, param)
+        if integer:
+            x = np.random.default_rng(1).integers(-50, 50, size=A.n).astype(np.float32)
+        else:
+            x = spkgen.rhs_uniform(A.n, 2).astype(np.float32)
+        y = to_dev(np.full(A.n, np.nan, dtype=np.float32))
+        spk.mat_mult_f32(M, to_dev(x), y)
+        y = y.cpu().numpy()
+        v32 = A.val.astype(np.float32)
+        ref = oracle.spmv_f32(A, x, val32=v32)
+        if integer:
+            assert np.array_equal(y, ref), f"{name} {kname}: FP32 not bit-exact"
+        else:
+            Af = spkgen.CSR(A.n, A.rowptr, A.col, v32.astype(np.float64))
+            scale = oracle.spmv_abs(Af, x.astype(np.float64))
+            bound = spmv_bound_rows(A, kname, lanes, U32) + U32  # + final rounding
+            check_spmv(y.astype(np.float64), ref.astype(np.float64), scale, bound,
+                       f"fp32 {name} {kname}/{lanes}")
+        M.close()
+
+
+def test_spmv_degenerate_sizes():
+    spk = need_gpu()
+    import torch
+
+    # n = 1
+    A = spkgen.dense_to_csr(np.array([[3.0]]))
+    M = mat_on_gpu(spk, A)
+    y = torch.zeros(1, dtype=torch.float64, device="cuda")
+    spk.mat_mult(M, to_dev(np.array([2.0])), y)
+    assert y.item() == 6.0
+    # n = 0
+    E = spkgen.CSR(0, np.zeros(1, np.int32), np.zeros(0, np.int32), np.zeros(0))
+    M0 = mat_on_gpu(spk, E)
+    e = torch.zeros(0, dtype=torch.float64, device="cuda")
+    spk.mat_mult(M0, e, e.clone())
+    # all rows empty
+    Z = spkgen.CSR(1000, np.zeros(1001, np.int32), np.zeros(0, np.int32), np.zeros(0))
+    for k in (spk.KERNEL_STREAM, spk.KERNEL_MERGE, spk.KERNEL_VECTOR):
+        MZ = mat_on_gpu(spk, Z)
+        spk.mat_set_kernel(MZ, k, 8 if k == spk.KERNEL_VECTOR else 0)
+        y = torch.full((1000,), 5.0, dtype=torch.float64, device="cuda")
+        spk.mat_mult(MZ, torch.ones(1000, dtype=torch.float64, device="cuda"), y)
+        assert (y == 0).all()
+
+
+def test_spmv_one_long_row():
+    """A dense row of 100k entries (beyond every tile), plus short rows."""
+    spk = need_gpu()
+    n = 100000
+    rows = [np.arange(n, dtype=np.int32)] + [np.array([i], dtype=np.int32) for i in range(1, 3000)]
+    cols = np.concatenate(rows)
+    rowptr = np.zeros(3001, np.int32)
+    rowptr[1:] = np.cumsum([r.size for r in rows])
+    rowptr_full = np.concatenate([rowptr, np.full(n - 3000, rowptr[-1], np.int32)])
+    vals = np.random.default_rng(0).integers(-3, 4, size=cols.size).astype(np.float64)
+    A = spkgen.CSR(n, rowptr_full, cols, vals)
+    x = np.random.default_rng(1).integers(-3, 4, size=n).astype(np.float64)
+    ref = oracle.spmv(A, x)
+    for k, p in ((spk.KERNEL_AUTO, 0), (spk.KERNEL_STREAM, 256), (spk.KERNEL_MERGE, 0),
+                 (spk.KERNEL_VECTOR, 64)):
+        M = mat_on_gpu(spk, A)
+        spk.mat_set_kernel(M, k, p)
+        y = to_dev(np.zeros(n))
+        spk.mat_mult(M, to_dev(x), y)
+        assert np.array_equal(y.cpu().numpy(), ref)
+
+
+def test_kernel_selection():
+    spk = need_gpu()
+    sel = {}
+    for name, A, _ in _matrices():
+        M = mat_on_gpu(spk, A)
+        sel[name] = spk.KERNEL_NAMES[M.info.kernel]
+    assert sel["lap3d_23"] == "stream" and sel["diff27_13"] == "stream"
+    assert sel["powerlaw_30k"] == "merge"
+
+
+def test_invalid_csr_rejected():
+    spk = need_gpu()
+    A = spkgen.laplace2d5(8)
+    bad = A.col.copy()
+    bad[10] = 64  # out of range
+    with pytest.raises(spk.SpkError) as e:
+        spk.mat_create_csr(to_dev(A.rowptr), to_dev(bad), to_dev(A.val))
+    assert e.value.status == spk.EINVAL
+    rp = A.rowptr.copy()
+    rp[5], rp[6] = rp[6], rp[5]  # not monotone
+    with pytest.raises(spk.SpkError):
+        spk.mat_create_csr(to_dev(rp), to_dev(A.col), to_dev(A.val))
+    uns = A.col.copy()
+    uns[0], uns[1] = uns[1], uns[0]
+    with pytest.raises(spk.SpkError):
+        spk.mat_create_csr(to_dev(A.rowptr), to_dev(uns), to_dev(A.val), flags=spk.MAT_VALIDATE)
+    # host path checks rowptr[n] on the host
+    with pytest.raises(spk.SpkError):
+        spk.mat_create_csr(A.rowptr[:-1], A.col, A.val)
+
+
+def test_host_memtype_and_borrow_match():
+    spk = need_gpu()
+    A = spkgen.diffusion3d27_lognormal(9, seed=2)
+    x = to_dev(spkgen.rhs_uniform(A.n, 0))
+    M1 = spk.mat_create_csr(A.rowptr, A.col, A.val)  # host arrays
+    M2 = spk.mat_create_csr(to_dev(A.rowptr), to_dev(A.col), to_dev(A.val), flags=spk.MAT_BORROW)
+    y1 = to_dev(np.zeros(A.n))
+    y2 = to_dev(np.zeros(A.n))
+    spk.mat_mult(M1, x, y1)
+    spk.mat_mult(M2, x, y2)
+    assert np.array_equal(y1.cpu().numpy(), y2.cpu().numpy())
+
+
+def test_spmv_deterministic_repeat():
+    spk = need_gpu()
+    A = spkgen.powerlaw_spd(20000, seed=5)
+    M = mat_on_gpu(spk, A)
+    x = to_dev(spkgen.rhs_uniform(A.n, 5))
+    ys = []
+    for _ in range(3):
+        y = to_dev(np.zeros(A.n))
+        spk.mat_mult(M, x, y)
+        ys.append(y.cpu().numpy())
+    assert np.array_equal(ys[0], ys[1]) and np.array_equal(ys[0], ys[2])
+
+
+def test_jacobi_and_vector_kernels():
+    spk = need_gpu()
+    import torch
+
+    A = spkgen.diffusion3d27_lognormal(10, seed=4)
+    M = mat_on_gpu(spk, A)
+    r = spkgen.rhs_uniform(A.n, 1)
+    z = to_dev(np.zeros(A.n))
+    spk.pc_jacobi_apply(M, to_dev(r), z)
+    dinv = oracle.diag_inv(A)
+    assert np.array_equal(z.cpu().numpy(), oracle.jacobi_apply(dinv, r))
+    n = 1_000_003
+    x = spkgen.rhs_uniform(n, 10)
+    y = spkgen.rhs_uniform(n, 11)
+    w = spkgen.rhs_uniform(n, 12)
+    yd = to_dev(y)
+    spk.vec_axpy(0.37, to_dev(x), yd)
+    assert np.array_equal(yd.cpu().numpy(), oracle.axpy(0.37, x, y))
+    yd = to_dev(y)
+    spk.vec_aypx(-1.25, to_dev(x), yd)
+    assert np.array_equal(yd.cpu().numpy(), oracle.aypx(-1.25, x, y))
+    res = torch.zeros(2, dtype=torch.float64, device="cuda")
+    spk.vec_dot(to_dev(x), to_dev(y), res)
+    d = res[0].item()
+    assert abs(d - oracle.dot(x, y)) <= 1e-13 * np.abs(x * y).sum()
+    spk.vec_dot2(to_dev(x), to_dev(y), to_dev(w), res)
+    r2 = res.cpu().numpy()
+    assert r2[0] == d  # same reduction tree
+    assert abs(r2[1] - oracle.dot(x, w)) <= 1e-13 * np.abs(x * w).sum()
+    spk.vec_nrm2(to_dev(x), res)
+    assert abs(res[0].item() - oracle.nrm2(x)) <= 1e-14 * oracle.nrm2(x)
+    # integer vectors: exact
+    xi = np.random.default_rng(3).integers(-1000, 1000, size=n).astype(np.float64)
+    spk.vec_dot(to_dev(xi), to_dev(xi), res)
+    assert res[0].item() == oracle.dot(xi, xi)
