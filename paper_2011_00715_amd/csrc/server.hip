@@ -1,10 +1,523 @@
-// Continuous-batching solve server (entry points; the batched implementation
-// follows).
+// Continuous-batching solve server (Response A6 of Sec. 4: many
+// different-size problems solved simultaneously on one GPU).
+//
+//  * Requests are copied at submit and queued (FIFO).  Between batched steps,
+//    queued requests are admitted while a slot and room in the device arena
+//    (the HBM budget) are free; the upload goes through pinned staging
+//    (Response A4).
+//  * Every active system stays resident (matrix, FP32 copy, Krylov vectors,
+//    scalars) until it finishes.  One batched step runs K iterations of every
+//    active system: each kernel launch serves the whole slot table, and each
+//    system reduces over its own blocks only, so a system's bits do not depend
+//    on its neighbours in the batch.
+//  * Statuses come back with one small copy per step, two steps in flight;
+//    finished systems are retired asynchronously (true residual, x download).
 #include <string.h>
 
+#include <algorithm>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <vector>
+
+#include "krylov.hpp"
 #include "runtime.hpp"
 
+namespace spk {
+
+enum : int { kQueued = 0, kActive = 1, kRetiring = 2, kDone = 3 };
+
+struct Request {
+    uint64_t ticket = 0;
+    int32_t n = 0;
+    int64_t nnz = 0;
+    std::vector<int32_t> rowptr, col;
+    std::vector<double> val, b;
+    spk_ksp_opts opts{};
+    int mixed = 0;
+    int R = 256, ntiles = 0, nblk = 0;
+    int64_t bytes = 0;
+    int state = kQueued;
+    int slot = -1;
+    std::vector<double> x;
+    spk_ksp_result res{};
+    double t_submit = 0, t_done = 0;
+};
+
+// First-fit allocator over [0, size) with 256-byte granules.
+class Arena {
+  public:
+    void init(int64_t size) { free_[0] = size; total_ = size; }
+    int64_t alloc(int64_t bytes)
+    {
+        bytes = (bytes + 255) & ~int64_t(255);
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second >= bytes) {
+                const int64_t off = it->first, len = it->second;
+                free_.erase(it);
+                if (len > bytes) free_[off + bytes] = len - bytes;
+                used_ += bytes;
+                return off;
+            }
+        }
+        return -1;
+    }
+    void release(int64_t off, int64_t bytes)
+    {
+        bytes = (bytes + 255) & ~int64_t(255);
+        used_ -= bytes;
+        auto it = free_.emplace(off, bytes).first;
+        auto nx = std::next(it);
+        if (nx != free_.end() && it->first + it->second == nx->first) {
+            it->second += nx->second;
+            free_.erase(nx);
+        }
+        if (it != free_.begin()) {
+            auto pv = std::prev(it);
+            if (pv->first + pv->second == it->first) {
+                pv->second += it->second;
+                free_.erase(it);
+            }
+        }
+    }
+    int64_t used() const { return used_; }
+    int64_t total() const { return total_; }
+
+  private:
+    std::map<int64_t, int64_t> free_;
+    int64_t used_ = 0, total_ = 0;
+};
+
+struct Slot {
+    Request *req = nullptr;
+    int64_t off = -1, len = 0;
+    SysDesc desc{};
+    int restarts = 0;
+    int fallback = 0;
+    int mixed = 0;
+    double *px = nullptr;  // pinned download buffer
+    int64_t px_cap = 0;
+    hipEvent_t ev = nullptr;
+    int64_t first_step = 0;  // first batched step that includes this system
+};
+
+#define SPK_TRY_RC(x)                  \
+    do {                               \
+        const int rc_ = (x);           \
+        if (rc_ != SPK_OK) return rc_; \
+    } while (0)
+
+constexpr int kTableRing = 4;
+
+constexpr int64_t kStageBytes = 16ll << 20;
+
+}  // namespace spk
+
 using namespace spk;
+
+struct spk_server {
+    spk_server_opts o{};
+    hipStream_t s = nullptr;
+    int dev = 0;
+    char *arena_base = nullptr;
+    Arena arena;
+    std::vector<Slot> slots;
+    SysState *d_states = nullptr;             // one per slot
+    SysState *p_states[2] = {nullptr, nullptr};  // snapshots of in-flight steps
+    hipEvent_t ev_step[2] = {nullptr, nullptr};
+    std::deque<int> inflight;                 // snapshot buffers of queued steps
+    SysDesc *d_slotdesc = nullptr;            // per-slot descriptor (single launches)
+    int32_t *d_slotblk = nullptr;             // per-slot {0, nblk}
+    SysDesc *p_slotdesc = nullptr;            // pinned source of d_slotdesc
+    int32_t *p_slotblk = nullptr;
+    SysState *p_slotstate = nullptr;          // pinned state copy taken at retirement
+    SysDesc *d_table = nullptr;               // batched table
+    int32_t *d_blk = nullptr;
+    SysDesc *p_table[kTableRing] = {};
+    int32_t *p_blk[kTableRing] = {};
+    hipEvent_t ev_table[kTableRing] = {};
+    int table_buf = 0;
+    hipStream_t cs = nullptr;                 // copy stream for uploads
+    hipEvent_t ev_up = nullptr;
+    int64_t step_id = 0;                      // id of the next batched step
+    std::deque<int64_t> inflight_id;
+    bool table_dirty = true;
+    int nsys = 0, nblocks = 0, n_mixed = 0, n_fp64 = 0;
+    char *stage[2] = {nullptr, nullptr};
+    hipEvent_t ev_stage[2] = {nullptr, nullptr};
+    int stage_i = 0;
+    std::deque<Request *> queue;
+    std::map<uint64_t, Request *> tickets;
+    uint64_t next_ticket = 1;
+    std::mutex mu;
+};
+
+namespace spk {
+
+static int64_t align256(int64_t b) { return (b + 255) & ~int64_t(255); }
+
+// Device bytes a request occupies in the arena.
+static int64_t request_bytes(const Request &q)
+{
+    const int64_t n = q.n, nz = q.nnz;
+    int64_t b = align256(4 * (n + 1)) + align256(4 * nz) + align256(8 * nz) + align256(8 * n) /*dinv*/ +
+                align256(8 * n) /*b*/ + align256(8 * n) /*x*/ + 4 * align256(8 * n) /*r z p q*/ +
+                align256(8 * kNumPart * (int64_t)std::max(q.nblk, 1));
+    if (q.mixed) b += align256(4 * nz) + align256(4 * n) + 5 * align256(4 * n);
+    return b;
+}
+
+static int upload(spk_server *S, void *dst, const void *src, size_t bytes)
+{
+    for (size_t off = 0; off < bytes; off += kStageBytes) {
+        const size_t len = std::min((size_t)kStageBytes, bytes - off);
+        const int i = S->stage_i;
+        S->stage_i ^= 1;
+        SPK_HIP(hipEventSynchronize(S->ev_stage[i]));
+        memcpy(S->stage[i], (const char *)src + off, len);
+        SPK_HIP(hipMemcpyAsync((char *)dst + off, S->stage[i], len, hipMemcpyHostToDevice, S->cs));
+        SPK_HIP(hipEventRecord(S->ev_stage[i], S->cs));
+    }
+    return SPK_OK;
+}
+
+static Batch slot_batch(spk_server *S, int k)
+{
+    return Batch{S->d_slotdesc + k, S->d_slotblk + 2 * k, 1};
+}
+
+// Start an FP64 solve of slot k from the x in its buffer (setup residual).
+static int start_fp64(spk_server *S, int k, const spk_ksp_opts &o, bool init_state)
+{
+    Slot &sl = S->slots[k];
+    const Batch b = slot_batch(S, k);
+    if (init_state)
+        hipLaunchKernelGGL(k_state_init, dim3(1), dim3(64), 0, S->s, sl.desc.st, o.rtol, o.atol,
+                           o.maxit, 0, o.inner_rtol, o.inner_maxit, o.max_outer, 0);
+    hipLaunchKernelGGL(k_resid_stream<kGateNone>, dim3(sl.desc.nblk), dim3(kBlock), 0, S->s, b,
+                       (int)kResSetup);
+    hipLaunchKernelGGL(k_setup64, dim3(sl.desc.nblk), dim3(kBlock), 0, S->s, b);
+    SPK_HIP(hipGetLastError());
+    return SPK_OK;
+}
+
+static __global__ void k_srv_zero(int64_t m, double *__restrict__ a)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < m;
+         i += (int64_t)gridDim.x * blockDim.x)
+        a[i] = 0.0;
+}
+
+static __global__ void k_srv_diag(int n, const int32_t *__restrict__ rowptr, const int32_t *__restrict__ col,
+                           const double *__restrict__ val, double *__restrict__ dinv,
+                           float *__restrict__ dinv32)
+{
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        double d = 0.0;
+        for (int k = rowptr[i]; k < rowptr[i + 1]; ++k)
+            if (col[k] == i) d += val[k];
+        const double v = 1.0 / d;  // nonzero: checked on the host at submit
+        dinv[i] = v;
+        if (dinv32) dinv32[i] = (float)v;
+    }
+}
+
+static __global__ void k_srv_f32(int64_t m, const double *__restrict__ a, float *__restrict__ b)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < m;
+         i += (int64_t)gridDim.x * blockDim.x)
+        b[i] = (float)a[i];
+}
+
+static int grid1(int64_t m)
+{
+    int64_t g = (m + kBlock - 1) / kBlock;
+    return (int)std::max<int64_t>(1, std::min<int64_t>(g, 1024));
+}
+
+// Place request q in free slot k (arena space already reserved at sl.off).
+static int admit(spk_server *S, Request *q, int k, int64_t off)
+{
+    Slot &sl = S->slots[k];
+    sl.req = q;
+    sl.off = off;
+    sl.len = q->bytes;
+    sl.restarts = 0;
+    sl.fallback = 0;
+    sl.mixed = q->mixed;
+    char *p = S->arena_base + off;
+    auto take = [&](int64_t bytes) {
+        char *r = p;
+        p += align256(bytes);
+        return r;
+    };
+    const int64_t n = q->n, nz = q->nnz;
+    SysDesc &d = sl.desc;
+    d = SysDesc{};
+    d.n = q->n;
+    d.R = q->R;
+    d.ntiles = q->ntiles;
+    d.nblk = q->nblk;
+    int32_t *rowptr = (int32_t *)take(4 * (n + 1));
+    int32_t *col = (int32_t *)take(4 * nz);
+    double *val = (double *)take(8 * nz);
+    double *dinv = (double *)take(8 * n);
+    double *b = (double *)take(8 * n);
+    d.x = (double *)take(8 * n);
+    d.r = (double *)take(8 * n);
+    d.z = (double *)take(8 * n);
+    d.p = (double *)take(8 * n);
+    d.q = (double *)take(8 * n);
+    d.partials = (double *)take(8 * kNumPart * (int64_t)std::max(q->nblk, 1));
+    float *val32 = nullptr, *dinv32 = nullptr;
+    if (q->mixed) {
+        val32 = (float *)take(4 * nz);
+        dinv32 = (float *)take(4 * n);
+        d.r32 = (float *)take(4 * n);
+        d.z32 = (float *)take(4 * n);
+        d.p32 = (float *)take(4 * n);
+        d.q32 = (float *)take(4 * n);
+        d.d32 = (float *)take(4 * n);
+    }
+    d.rowptr = rowptr;
+    d.col = col;
+    d.val = val;
+    d.val32 = val32;
+    d.dinv = dinv;
+    d.dinv32 = dinv32;
+    d.b = b;
+    d.st = S->d_states + k;
+    d.hist = nullptr;
+    // uploads run on the copy stream and overlap the batched steps already
+    // queued on the compute stream; the compute stream waits for them
+    SPK_TRY_RC(upload(S, rowptr, q->rowptr.data(), 4 * (n + 1)));
+    if (nz) SPK_TRY_RC(upload(S, col, q->col.data(), 4 * nz));
+    if (nz) SPK_TRY_RC(upload(S, val, q->val.data(), 8 * nz));
+    SPK_TRY_RC(upload(S, b, q->b.data(), 8 * n));
+    // per-slot descriptor and block table for the single-system launches (the
+    // pinned source of slot k is only rewritten after its previous occupant
+    // retired, i.e. after this copy of the previous admission completed)
+    S->p_slotdesc[k] = d;
+    S->p_slotblk[2 * k] = 0;
+    S->p_slotblk[2 * k + 1] = q->nblk;
+    SPK_HIP(hipMemcpyAsync(S->d_slotdesc + k, S->p_slotdesc + k, sizeof(SysDesc), hipMemcpyHostToDevice, S->cs));
+    SPK_HIP(hipMemcpyAsync(S->d_slotblk + 2 * k, S->p_slotblk + 2 * k, 2 * sizeof(int32_t),
+                           hipMemcpyHostToDevice, S->cs));
+    SPK_HIP(hipEventRecord(S->ev_up, S->cs));
+    SPK_HIP(hipStreamWaitEvent(S->s, S->ev_up, 0));
+    hipLaunchKernelGGL(k_srv_diag, dim3(grid1(n)), dim3(kBlock), 0, S->s, q->n, rowptr, col, val,
+                       dinv, dinv32);
+    if (q->mixed && nz)
+        hipLaunchKernelGGL(k_srv_f32, dim3(grid1(nz)), dim3(kBlock), 0, S->s, nz, val, val32);
+    hipLaunchKernelGGL(k_srv_zero, dim3(grid1(n)), dim3(kBlock), 0, S->s, n, d.x);
+    SPK_HIP(hipGetLastError());
+    const spk_ksp_opts &o = q->opts;
+    if (q->mixed) {
+        hipLaunchKernelGGL(k_state_init, dim3(1), dim3(64), 0, S->s, d.st, o.rtol, o.atol, o.maxit, 1,
+                           o.inner_rtol, o.inner_maxit, o.max_outer, 0);
+        SPK_HIP(hipGetLastError());
+    } else {
+        const int rc = start_fp64(S, k, o, true);
+        if (rc) return rc;
+    }
+    q->state = kActive;
+    q->slot = k;
+    sl.first_step = S->step_id;
+    // host copies are no longer needed once the staging buffers are drained
+    SPK_HIP(hipEventSynchronize(S->ev_stage[0]));
+    SPK_HIP(hipEventSynchronize(S->ev_stage[1]));
+    std::vector<int32_t>().swap(q->rowptr);
+    std::vector<int32_t>().swap(q->col);
+    std::vector<double>().swap(q->val);
+    std::vector<double>().swap(q->b);
+    S->table_dirty = true;
+    return SPK_OK;
+}
+
+static int admit_queued(spk_server *S)
+{
+    while (!S->queue.empty()) {
+        Request *q = S->queue.front();
+        int k = -1;
+        for (int i = 0; i < (int)S->slots.size(); ++i)
+            if (!S->slots[i].req) { k = i; break; }
+        if (k < 0) break;
+        const int64_t off = S->arena.alloc(q->bytes);
+        if (off < 0) break;  // FIFO: wait until the head fits
+        S->queue.pop_front();
+        const int rc = admit(S, q, k, off);
+        if (rc) return rc;
+    }
+    return SPK_OK;
+}
+
+static int rebuild_table(spk_server *S)
+{
+    const int i = S->table_buf;
+    S->table_buf = (S->table_buf + 1) % kTableRing;
+    SPK_HIP(hipEventSynchronize(S->ev_table[i]));
+    SysDesc *pt = S->p_table[i];
+    int32_t *pb = S->p_blk[i];
+    int ns = 0, nb = 0, nm = 0, nf = 0;
+    for (int k = 0; k < (int)S->slots.size(); ++k) {
+        const Slot &sl = S->slots[k];
+        if (!sl.req || sl.req->state != kActive) continue;
+        pt[ns] = sl.desc;
+        pb[ns] = nb;
+        nb += (sl.desc.nblk + kXcd - 1) / kXcd * kXcd;  // XCD-aligned start of the next system
+        ++ns;
+        if (sl.mixed) ++nm; else ++nf;
+    }
+    pb[ns] = nb;
+    S->nsys = ns;
+    S->nblocks = nb;
+    S->n_mixed = nm;
+    S->n_fp64 = nf;
+    if (ns) {
+        SPK_HIP(hipMemcpyAsync(S->d_table, pt, sizeof(SysDesc) * ns, hipMemcpyHostToDevice, S->s));
+        SPK_HIP(hipMemcpyAsync(S->d_blk, pb, sizeof(int32_t) * (ns + 1), hipMemcpyHostToDevice, S->s));
+    }
+    SPK_HIP(hipEventRecord(S->ev_table[i], S->s));
+    S->table_dirty = false;
+    return SPK_OK;
+}
+
+// One batched step: K iterations of every active system.
+static int enqueue_step(spk_server *S)
+{
+    const Batch b{S->d_table, S->d_blk, S->nsys};
+    const dim3 g(S->nblocks), t(kBlock);
+    const int K = S->o.graph_k > 0 ? S->o.graph_k : 8;
+    if (S->n_mixed) {
+        hipLaunchKernelGGL(k_update_x, g, t, 0, S->s, b);
+        hipLaunchKernelGGL(k_resid_stream<kGateResid>, g, t, 0, S->s, b, (int)kResOuter);
+        hipLaunchKernelGGL(k_setup32, g, t, 0, S->s, b);
+    }
+    for (int k = 0; k < K; ++k) {
+        if (S->n_fp64) {
+            hipLaunchKernelGGL(k_pcg_spmv_stream<double>, g, t, 0, S->s, b);
+            hipLaunchKernelGGL(k_pcg_update<double>, g, t, 0, S->s, b);
+            hipLaunchKernelGGL(k_pcg_px<double>, g, t, 0, S->s, b);
+        }
+        if (S->n_mixed) {
+            hipLaunchKernelGGL(k_pcg_spmv_stream<float>, g, t, 0, S->s, b);
+            hipLaunchKernelGGL(k_pcg_update<float>, g, t, 0, S->s, b);
+            hipLaunchKernelGGL(k_pcg_px<float>, g, t, 0, S->s, b);
+        }
+    }
+    SPK_HIP(hipGetLastError());
+    return SPK_OK;
+}
+
+static int begin_retire(spk_server *S, int k)
+{
+    Slot &sl = S->slots[k];
+    Request *q = sl.req;
+    const Batch b = slot_batch(S, k);
+    hipLaunchKernelGGL(k_resid_stream<kGateNone>, dim3(sl.desc.nblk), dim3(kBlock), 0, S->s, b,
+                       (int)kResTrue);
+    SPK_HIP(hipGetLastError());
+    if (sl.px_cap < q->n) {
+        if (sl.px) hipHostFree(sl.px);
+        sl.px = nullptr;
+        const int64_t cap = std::max<int64_t>(q->n, 1 << 16);
+        SPK_HIP(hipHostMalloc((void **)&sl.px, sizeof(double) * cap, hipHostMallocDefault));
+        sl.px_cap = cap;
+    }
+    SPK_HIP(hipMemcpyAsync(sl.px, sl.desc.x, sizeof(double) * q->n, hipMemcpyDeviceToHost, S->s));
+    SPK_HIP(hipMemcpyAsync(S->p_slotstate + k, S->d_states + k, sizeof(SysState), hipMemcpyDeviceToHost, S->s));
+    SPK_HIP(hipEventRecord(sl.ev, S->s));
+    q->state = kRetiring;
+    S->table_dirty = true;
+    return SPK_OK;
+}
+
+// Slot k's retirement copies have landed: check the true residual, then
+// finish the request or restart / fall back.
+static int end_retire(spk_server *S, int k, const SysState &st)
+{
+    Slot &sl = S->slots[k];
+    Request *q = sl.req;
+    const bool conv = st.status == SPK_CONVERGED_RTOL || st.status == SPK_CONVERGED_ATOL;
+    if (!sl.mixed && conv && st.bnorm > 0 && st.iter > 0 && st.rnorm_true > st.thresh &&
+        sl.restarts < 3) {
+        ++sl.restarts;  // true residual drifted: restart from it
+        hipLaunchKernelGGL(k_state_restart, dim3(1), dim3(64), 0, S->s, sl.desc.st);
+        hipLaunchKernelGGL(k_setup64, dim3(sl.desc.nblk), dim3(kBlock), 0, S->s, slot_batch(S, k));
+        SPK_HIP(hipGetLastError());
+        q->state = kActive;
+        sl.first_step = S->step_id;
+        S->table_dirty = true;
+        return SPK_OK;
+    }
+    if (sl.mixed && st.status == SPK_DIVERGED_STAGNATION) {
+        // finish in FP64 from the current x
+        sl.mixed = 0;
+        sl.fallback = 1;
+        q->res.inner_iterations = st.iter;
+        q->res.outer_steps = st.outer;
+        q->res.rnorm0 = st.rnorm0;
+        spk_ksp_opts o = q->opts;
+        o.maxit = std::max(o.maxit - st.iter, 1);
+        const int rc = start_fp64(S, k, o, true);
+        if (rc) return rc;
+        q->state = kActive;
+        sl.first_step = S->step_id;
+        S->table_dirty = true;
+        return SPK_OK;
+    }
+    q->x.assign(sl.px, sl.px + q->n);
+    spk_ksp_result &r = q->res;
+    r.reason = st.status;
+    if (!sl.mixed && conv && st.iter > 0 && st.rnorm_true > st.thresh) r.reason = SPK_DIVERGED_BREAKDOWN;
+    if (sl.fallback) {
+        r.iterations = st.iter;
+        r.fallback_fp64 = 1;
+    } else if (sl.mixed) {
+        r.inner_iterations = st.iter;
+        r.outer_steps = st.outer;
+        r.rnorm0 = st.rnorm0;
+    } else {
+        r.iterations = st.iter;
+        r.rnorm0 = st.rnorm0;
+    }
+    r.restarts = sl.restarts;
+    r.bnorm = st.bnorm;
+    r.rnorm = st.rnorm_true;
+    r.true_rel_residual = st.bnorm > 0 ? st.rnorm_true / st.bnorm : 0.0;
+    if (st.bnorm == 0.0) {
+        std::fill(q->x.begin(), q->x.end(), 0.0);
+        r.rnorm = r.true_rel_residual = 0.0;
+    }
+    q->t_done = spk_now();
+    r.seconds = q->t_done - q->t_submit;
+    q->state = kDone;
+    q->slot = -1;
+    S->arena.release(sl.off, sl.len);
+    sl.req = nullptr;
+    sl.off = -1;
+    return SPK_OK;
+}
+
+// Read the state snapshot of the oldest queued step.
+static int drain_one_step(spk_server *S)
+{
+    const int i = S->inflight.front();
+    const int64_t id = S->inflight_id.front();
+    S->inflight.pop_front();
+    S->inflight_id.pop_front();
+    SPK_HIP(hipEventSynchronize(S->ev_step[i]));
+    const SysState *snap = S->p_states[i];
+    for (int k = 0; k < (int)S->slots.size(); ++k) {
+        Slot &sl = S->slots[k];
+        if (!sl.req || sl.req->state != kActive) continue;
+        if (sl.first_step > id) continue;  // joined after this snapshot
+        if (snap[k].status != SPK_RUNNING) SPK_TRY_RC(begin_retire(S, k));
+    }
+    return SPK_OK;
+}
+
+}  // namespace spk
 
 extern "C" {
 
@@ -18,32 +531,243 @@ void spk_server_opts_default(spk_server_opts *o)
     o->max_blocks_per_system = 256;
 }
 
-int spk_server_create(const spk_server_opts *, void *, spk_server **out)
+int spk_server_destroy(spk_server *S);
+
+int spk_server_create(const spk_server_opts *opts, void *stream, spk_server **out)
 {
-    if (out) *out = nullptr;
-    set_error("server not available in this build");
-    return SPK_EINVAL;
+    if (!out) { set_error("out is NULL"); return SPK_EINVAL; }
+    *out = nullptr;
+    spk_server_opts o;
+    if (opts) o = *opts;
+    else spk_server_opts_default(&o);
+    if (o.hbm_budget_bytes < (1 << 20) || o.max_slots < 1 || o.max_slots > 4096 || o.graph_k < 1 ||
+        o.graph_k > 256 || o.max_blocks_per_system < 1 || o.max_blocks_per_system > 8192) {
+        set_error("invalid server options");
+        return SPK_EINVAL;
+    }
+    spk_server *S = new (std::nothrow) spk_server();
+    if (!S) { set_error("out of host memory"); return SPK_ENOMEM; }
+    S->o = o;
+    S->s = (hipStream_t)stream;
+    int rc = SPK_OK;
+    auto chk = [&](hipError_t e, const char *what) {
+        if (e != hipSuccess && rc == SPK_OK) rc = hip_fail(e, what, __FILE__, __LINE__);
+    };
+    chk(hipGetDevice(&S->dev), "hipGetDevice");
+    chk(hipMalloc(&S->arena_base, o.hbm_budget_bytes), "arena hipMalloc");
+    S->arena.init(o.hbm_budget_bytes);
+    S->slots.resize(o.max_slots);
+    const size_t ms = o.max_slots;
+    chk(hipMalloc(&S->d_states, sizeof(SysState) * ms), "states");
+    chk(hipMalloc(&S->d_slotdesc, sizeof(SysDesc) * ms), "slot descs");
+    chk(hipMalloc(&S->d_slotblk, sizeof(int32_t) * 2 * ms), "slot blocks");
+    chk(hipMalloc(&S->d_table, sizeof(SysDesc) * ms), "table");
+    chk(hipMalloc(&S->d_blk, sizeof(int32_t) * (ms + 1)), "table blocks");
+    chk(hipHostMalloc((void **)&S->p_slotdesc, sizeof(SysDesc) * ms, hipHostMallocDefault), "pinned descs");
+    chk(hipHostMalloc((void **)&S->p_slotblk, sizeof(int32_t) * 2 * ms, hipHostMallocDefault), "pinned blocks");
+    chk(hipHostMalloc((void **)&S->p_slotstate, sizeof(SysState) * ms, hipHostMallocDefault), "pinned states");
+    chk(hipStreamCreateWithFlags(&S->cs, hipStreamNonBlocking), "copy stream");
+    chk(hipEventCreateWithFlags(&S->ev_up, hipEventDisableTiming), "event");
+    for (int i = 0; i < 2; ++i) {
+        chk(hipHostMalloc((void **)&S->p_states[i], sizeof(SysState) * ms, hipHostMallocDefault), "pinned states");
+        chk(hipHostMalloc((void **)&S->stage[i], kStageBytes, hipHostMallocDefault), "pinned staging");
+        chk(hipEventCreateWithFlags(&S->ev_step[i], hipEventDisableTiming), "event");
+        chk(hipEventCreateWithFlags(&S->ev_stage[i], hipEventDisableTiming), "event");
+    }
+    for (int i = 0; i < kTableRing; ++i) {
+        chk(hipHostMalloc((void **)&S->p_table[i], sizeof(SysDesc) * ms, hipHostMallocDefault), "pinned table");
+        chk(hipHostMalloc((void **)&S->p_blk[i], sizeof(int32_t) * (ms + 1), hipHostMallocDefault), "pinned blocks");
+        chk(hipEventCreateWithFlags(&S->ev_table[i], hipEventDisableTiming), "event");
+    }
+    for (auto &sl : S->slots) chk(hipEventCreateWithFlags(&sl.ev, hipEventDisableTiming), "event");
+    if (rc == SPK_OK) {
+        for (int i = 0; i < kTableRing; ++i) chk(hipEventRecord(S->ev_table[i], S->s), "event record");
+        for (int i = 0; i < 2; ++i) chk(hipEventRecord(S->ev_stage[i], S->cs), "event record");
+        chk(hipMemsetAsync(S->d_states, 0, sizeof(SysState) * ms, S->s), "memset");
+        chk(hipStreamSynchronize(S->s), "sync");
+    }
+    if (rc != SPK_OK) {
+        spk_server_destroy(S);
+        return rc;
+    }
+    *out = S;
+    return SPK_OK;
 }
 
-int spk_server_submit(spk_server *, int32_t, int64_t, const int32_t *, const int32_t *,
-                      const double *, const double *, const spk_ksp_opts *, uint64_t *)
+int spk_server_submit(spk_server *S, int32_t n, int64_t nnz, const int32_t *rowptr,
+                      const int32_t *colind, const double *values, const double *b,
+                      const spk_ksp_opts *opts, uint64_t *ticket)
 {
-    set_error("server not available in this build");
-    return SPK_EINVAL;
+    if (!S || !ticket) { set_error("NULL argument"); return SPK_EINVAL; }
+    if (n < 1 || nnz < 0 || nnz > 0x7fffffffLL || !rowptr || !b || (nnz > 0 && (!colind || !values))) {
+        set_error("invalid system (n = %d, nnz = %lld)", n, (long long)nnz);
+        return SPK_EINVAL;
+    }
+    spk_ksp_opts o;
+    if (opts) o = *opts;
+    else spk_ksp_opts_default(&o);
+    if (!(o.rtol >= 0) || !(o.atol >= 0) || o.maxit < 0 || !(o.inner_rtol > 0) || o.inner_maxit < 1 ||
+        o.max_outer < 0 || (o.precision != SPK_PREC_FP64 && o.precision != SPK_PREC_MIXED)) {
+        set_error("invalid solver options");
+        return SPK_EINVAL;
+    }
+    // host-side structure checks: everything the kernels index with
+    if (rowptr[0] != 0 || rowptr[n] != nnz) {
+        set_error("rowptr[0] must be 0 and rowptr[n] = nnz");
+        return SPK_EINVAL;
+    }
+    int64_t maxtile[6] = {0, 0, 0, 0, 0, 0};
+    for (int32_t i = 0; i < n; ++i) {
+        const int32_t a = rowptr[i], e = rowptr[i + 1];
+        if (e < a || e > nnz) { set_error("rowptr not monotone at row %d", i); return SPK_EINVAL; }
+        double d = 0.0;
+        for (int32_t k = a; k < e; ++k) {
+            const int32_t c = colind[k];
+            if (c < 0 || c >= n) { set_error("column %d out of range in row %d", c, i); return SPK_EINVAL; }
+            if (c == i) d += values[k];
+        }
+        if (d == 0.0) { set_error("row %d has no stored or a zero diagonal", i); return SPK_EZERODIAG; }
+    }
+    for (int t = 0; t < 6; ++t)
+        for (int64_t r0 = 0; r0 < n; r0 += kTileRs[t])
+            maxtile[t] = std::max<int64_t>(maxtile[t], rowptr[std::min<int64_t>(r0 + kTileRs[t], n)] - rowptr[r0]);
+    Request *q = new (std::nothrow) Request();
+    if (!q) { set_error("out of host memory"); return SPK_ENOMEM; }
+    q->n = n;
+    q->nnz = nnz;
+    q->opts = o;
+    q->mixed = o.precision == SPK_PREC_MIXED;
+    q->R = 8;
+    for (int t = 0; t < 6; ++t)
+        if (maxtile[t] <= TileLds<double>::kCap) { q->R = kTileRs[t]; break; }
+    q->ntiles = ceil_div(n, q->R);
+    q->nblk = pick_nblk(q->ntiles, S->o.max_blocks_per_system);
+    q->bytes = request_bytes(*q);
+    if (q->bytes > S->o.hbm_budget_bytes) {
+        set_error("system needs %lld bytes, budget is %lld", (long long)q->bytes,
+                  (long long)S->o.hbm_budget_bytes);
+        delete q;
+        return SPK_EBUDGET;
+    }
+    try {
+        q->rowptr.assign(rowptr, rowptr + n + 1);
+        q->col.assign(colind, colind + nnz);
+        q->val.assign(values, values + nnz);
+        q->b.assign(b, b + n);
+    } catch (...) {
+        delete q;
+        set_error("out of host memory");
+        return SPK_ENOMEM;
+    }
+    q->t_submit = spk_now();
+    std::lock_guard<std::mutex> lk(S->mu);
+    q->ticket = S->next_ticket++;
+    S->tickets[q->ticket] = q;
+    S->queue.push_back(q);
+    *ticket = q->ticket;
+    return SPK_OK;
 }
 
-int spk_server_progress(spk_server *, int32_t)
+int spk_server_progress(spk_server *S, int32_t max_steps)
 {
-    set_error("server not available in this build");
-    return SPK_EINVAL;
+    if (!S || max_steps < 0) { set_error("bad argument"); return SPK_EINVAL; }
+    std::lock_guard<std::mutex> lk(S->mu);
+    constexpr int kDepth = 2;
+    for (int step = 0; step <= max_steps; ++step) {
+        // finish retirements whose copies have landed
+        for (int k = 0; k < (int)S->slots.size(); ++k) {
+            Slot &sl = S->slots[k];
+            if (!sl.req || sl.req->state != kRetiring) continue;
+            const hipError_t e = hipEventQuery(sl.ev);
+            if (e == hipErrorNotReady) continue;
+            if (e != hipSuccess) return hip_fail(e, "retire event", __FILE__, __LINE__);
+            const SysState st = S->p_slotstate[k];
+            SPK_TRY_RC(end_retire(S, k, st));
+        }
+        if (step == max_steps) break;
+        SPK_TRY_RC(admit_queued(S));
+        if (S->table_dirty) SPK_TRY_RC(rebuild_table(S));
+        if (S->nsys > 0) {
+            const int i = S->inflight.empty() ? 0 : (S->inflight.back() ^ 1);
+            if ((int)S->inflight.size() >= kDepth) SPK_TRY_RC(drain_one_step(S));
+            SPK_TRY_RC(enqueue_step(S));
+            const hipError_t e = hipMemcpyAsync(S->p_states[i], S->d_states,
+                                                sizeof(SysState) * S->slots.size(),
+                                                hipMemcpyDeviceToHost, S->s);
+            if (e != hipSuccess) return hip_fail(e, "state snapshot", __FILE__, __LINE__);
+            const hipError_t e2 = hipEventRecord(S->ev_step[i], S->s);
+            if (e2 != hipSuccess) return hip_fail(e2, "event", __FILE__, __LINE__);
+            S->inflight.push_back(i);
+            S->inflight_id.push_back(S->step_id++);
+        } else {
+            while (!S->inflight.empty()) SPK_TRY_RC(drain_one_step(S));
+            bool retiring = false;
+            for (auto &sl : S->slots)
+                if (sl.req && sl.req->state == kRetiring) retiring = true;
+            if (!retiring && S->queue.empty()) break;
+            if (retiring) {
+                const hipError_t e = hipStreamSynchronize(S->s);
+                if (e != hipSuccess) return hip_fail(e, "sync", __FILE__, __LINE__);
+            }
+        }
+    }
+    int pending = (int)S->queue.size();
+    for (auto &sl : S->slots)
+        if (sl.req) ++pending;
+    return pending;
 }
 
-int spk_server_poll(spk_server *, uint64_t, double *, spk_ksp_result *, double *)
+int spk_server_poll(spk_server *S, uint64_t ticket, double *x_host, spk_ksp_result *res,
+                    double *done_time)
 {
-    set_error("server not available in this build");
-    return SPK_EINVAL;
+    if (!S) { set_error("NULL server"); return SPK_EINVAL; }
+    std::lock_guard<std::mutex> lk(S->mu);
+    auto it = S->tickets.find(ticket);
+    if (it == S->tickets.end()) { set_error("unknown ticket %llu", (unsigned long long)ticket); return SPK_ENOTFOUND; }
+    Request *q = it->second;
+    if (q->state != kDone) return SPK_EBUSY;
+    if (x_host) memcpy(x_host, q->x.data(), sizeof(double) * q->n);
+    if (res) *res = q->res;
+    if (done_time) *done_time = q->t_done;
+    S->tickets.erase(it);
+    delete q;
+    return SPK_OK;
 }
 
-int spk_server_destroy(spk_server *) { return SPK_OK; }
+int spk_server_destroy(spk_server *S)
+{
+    if (!S) return SPK_OK;
+    hipStreamSynchronize(S->s);
+    if (S->cs) hipStreamSynchronize(S->cs);
+    for (auto &kv : S->tickets) delete kv.second;
+    for (auto &sl : S->slots) {
+        if (sl.px) hipHostFree(sl.px);
+        if (sl.ev) hipEventDestroy(sl.ev);
+    }
+    for (int i = 0; i < 2; ++i) {
+        hipHostFree(S->p_states[i]);
+        hipHostFree(S->stage[i]);
+        if (S->ev_step[i]) hipEventDestroy(S->ev_step[i]);
+        if (S->ev_stage[i]) hipEventDestroy(S->ev_stage[i]);
+    }
+    for (int i = 0; i < kTableRing; ++i) {
+        hipHostFree(S->p_table[i]);
+        hipHostFree(S->p_blk[i]);
+        if (S->ev_table[i]) hipEventDestroy(S->ev_table[i]);
+    }
+    hipHostFree(S->p_slotdesc);
+    hipHostFree(S->p_slotblk);
+    hipHostFree(S->p_slotstate);
+    if (S->ev_up) hipEventDestroy(S->ev_up);
+    if (S->cs) hipStreamDestroy(S->cs);
+    hipFree(S->arena_base);
+    hipFree(S->d_states);
+    hipFree(S->d_slotdesc);
+    hipFree(S->d_slotblk);
+    hipFree(S->d_table);
+    hipFree(S->d_blk);
+    delete S;
+    return SPK_OK;
+}
 
 }  // extern "C"

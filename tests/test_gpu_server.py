@@ -1,0 +1,128 @@
+"""Continuous-batching server: each request's result matches the oracle, is
+bitwise the same alone and inside a mixed batch, and admission honours the
+HBM budget."""
+
+import numpy as np
+import pytest
+
+import oracle
+import spkgen
+from gpu_util import need_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+def _requests(count, seed=0):
+    reqs = spkgen.serve_stream(seed=seed, count=count, side2d=(8, 40), side3d=(6, 14))
+    out = []
+    for r in reqs:
+        A = spkgen.serve_matrix(r)
+        out.append((r, A, spkgen.rhs_uniform(A.n, r.rhs_seed % (2**31))))
+    return out
+
+
+def _run(spk, S, items, prec, max_rounds=100000):
+    tickets = []
+    for _, A, b in items:
+        o = spk.ksp_opts(precision=prec)
+        tickets.append(spk.server_submit(S, A.rowptr, A.col, A.val, b, o))
+    results = [None] * len(items)
+    rounds = 0
+    while any(r is None for r in results):
+        spk.server_progress(S, 4)
+        for i, t in enumerate(tickets):
+            if results[i] is None:
+                x = np.empty(items[i][1].n)
+                got = spk.server_poll(S, t, x)
+                if got is not None:
+                    results[i] = (x, got[0])
+        rounds += 1
+        assert rounds < max_rounds
+    return results
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_server_results_match_oracle(prec):
+    spk = need_gpu()
+    p = spk.PREC_FP64 if prec == "fp64" else spk.PREC_MIXED
+    items = _requests(12, seed=1)
+    opts = spk.server_opts_default()
+    opts.max_slots = 5  # fewer slots than requests: continuous admission
+    opts.graph_k = 4
+    S = spk.server_create(opts)
+    results = _run(spk, S, items, p)
+    for (req, A, b), (x, res) in zip(items, results):
+        assert res.reason == spk.CONVERGED_RTOL, (req, res.as_dict())
+        rel = oracle.nrm2(b - oracle.spmv(A, x)) / oracle.nrm2(b)
+        assert rel <= 1e-8 * (1 + 1e-6), (req, rel)
+        assert res.true_rel_residual == pytest.approx(rel, rel=1e-6, abs=1e-16)
+        xo, ro, _ = oracle.pcg(A, b, rtol=1e-8)
+        assert np.linalg.norm(x - xo) <= 1e-5 * np.linalg.norm(xo)
+        if p == spk.PREC_FP64:
+            assert abs(res.iterations - ro["iterations"]) <= max(2, 0.01 * ro["iterations"])
+    S.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_server_alone_equals_mixed_batch(prec):
+    spk = need_gpu()
+    p = spk.PREC_FP64 if prec == "fp64" else spk.PREC_MIXED
+    items = _requests(8, seed=2)
+    S = spk.server_create()
+    mixed = _run(spk, S, items, p)
+    S.close()
+    for i, item in enumerate(items):
+        S1 = spk.server_create()
+        (x1, r1), = _run(spk, S1, [item], p)
+        S1.close()
+        x, r = mixed[i]
+        assert np.array_equal(x1, x), f"request {i} differs alone vs in the batch"
+        assert (r1.iterations, r1.inner_iterations, r1.outer_steps) == \
+            (r.iterations, r.inner_iterations, r.outer_steps)
+
+
+def test_server_budget_and_errors():
+    spk = need_gpu()
+    opts = spk.server_opts_default()
+    opts.hbm_budget_bytes = 4 << 20
+    S = spk.server_create(opts)
+    big = spkgen.laplace3d7(40)  # ~64k rows: does not fit 4 MiB
+    with pytest.raises(spk.SpkError) as e:
+        spk.server_submit(S, big.rowptr, big.col, big.val, np.ones(big.n))
+    assert e.value.status == spk.EBUDGET
+    # requests that fit only one or two at a time still all complete (queueing)
+    items = [(None, spkgen.laplace2d5(100), spkgen.rhs_uniform(10000, s)) for s in range(4)]
+    results = _run(spk, S, items, spk.PREC_FP64)
+    for (_, A, b), (x, res) in zip(items, results):
+        assert res.reason == spk.CONVERGED_RTOL
+    Z = spkgen.dense_to_csr(np.array([[1.0, 2.0], [2.0, 0.0]]))
+    with pytest.raises(spk.SpkError) as e:
+        spk.server_submit(S, Z.rowptr, Z.col, Z.val, np.ones(2))
+    assert e.value.status == spk.EZERODIAG
+    A = spkgen.laplace2d5(5)
+    bad = A.col.copy()
+    bad[3] = 99
+    with pytest.raises(spk.SpkError) as e:
+        spk.server_submit(S, A.rowptr, bad, A.val, np.ones(A.n))
+    assert e.value.status == spk.EINVAL
+    with pytest.raises(spk.SpkError) as e:
+        spk.server_poll(S, 123456789, np.empty(1))
+    assert e.value.status == spk.ENOTFOUND
+    S.close()
+
+
+def test_server_failure_isolated():
+    """A failing system (indefinite) finishes with its reason while the other
+    systems of the batch converge unaffected."""
+    spk = need_gpu()
+    good = [(None, spkgen.laplace2d5(30), spkgen.rhs_uniform(900, 1)),
+            (None, spkgen.laplace3d7(9), spkgen.rhs_uniform(729, 2))]
+    A = spkgen.laplace2d5(20)
+    bad = (None, spkgen.CSR(A.n, A.rowptr, A.col, -A.val), spkgen.rhs_uniform(A.n, 3))
+    S = spk.server_create()
+    res = _run(spk, S, [good[0], bad, good[1]], spk.PREC_FP64)
+    assert res[1][1].reason == spk.DIVERGED_INDEFINITE_PC
+    assert res[0][1].reason == spk.CONVERGED_RTOL and res[2][1].reason == spk.CONVERGED_RTOL
+    S1 = spk.server_create()
+    alone = _run(spk, S1, [good[0]], spk.PREC_FP64)
+    assert np.array_equal(alone[0][0], res[0][0])
