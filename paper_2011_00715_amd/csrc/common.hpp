@@ -28,29 +28,26 @@ enum : int32_t {
     kPhaseUpdate = 3,  // mixed: x += s d, then kPhaseResid
 };
 
-// Last-block counters, one per kernel kind.
-enum { kCntPq = 0, kCntUpd = 1, kCntPx = 2, kCntRes = 3, kCntSet = 4, kNumCnt = 6 };
-
 // Slots of the per-block partial sums (each B doubles).
 enum { kPartPq = 0, kPartRz = 1, kPartRr = 2, kPartBb = 3, kNumPart = 4 };
 
-// Device-resident scalars of one system.  Written only by the last block of a
-// kernel (or by the one-thread init kernel); read by every block of the next
-// kernels, which turn into no-ops once `status` is no longer SPK_RUNNING.
+// Device-resident scalars of one system.  Written only by the one-block
+// finalize kernels (and the one-thread init kernel); read by every block of
+// the next kernels, which turn into no-ops once `status` is no longer
+// SPK_RUNNING.
 struct SysState {
     int32_t status;       // SPK_RUNNING or a reason
     int32_t phase;        // kPhase*
     int32_t iter;         // Krylov iterations done (inner ones for mixed)
     int32_t inner_iter;   // iterations of the current inner solve
     int32_t outer;        // mixed: refinement steps done
-    int32_t x_pending;    // the last iteration's x (or d) update is still due
+    int32_t cmode;        // next x/p update: 2 both, 1 x only (last), 0 none
     int32_t maxit;
     int32_t inner_maxit;
     int32_t max_outer;
     int32_t stagnant;     // mixed: consecutive weak outer reductions
     int32_t mixed;        // 1: mixed-precision solve
     int32_t hist_len;
-    uint32_t counter[kNumCnt];
     double rho, alpha, beta, eta;
     double rnorm, rnorm0, bnorm, thresh, rtol, atol;
     double inner_rtol, inner_thresh;
@@ -156,26 +153,6 @@ __device__ __forceinline__ T block_sum(T v, T *sh)
 #pragma unroll
     for (int i = 1; i < kBlock / kWave; ++i) s += sh[i];
     return s;
-}
-
-// Last-block-done: every block arrives once; returns true in all threads of
-// the block that arrives last.  Partial sums written before the call are
-// visible to that block after it returns.  The counter is reset for the next
-// launch.  No floating-point atomics are involved: the final reduction is
-// done by the last block in a fixed order.
-__device__ __forceinline__ bool last_block_arrive(uint32_t *counter, uint32_t total)
-{
-    __shared__ int am_last;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        __threadfence();
-        uint32_t prev = atomicAdd(counter, 1u);
-        am_last = (prev == total - 1);
-        if (am_last) atomicExch(counter, 0u);
-    }
-    __syncthreads();
-    if (am_last) __threadfence();
-    return am_last != 0;
 }
 
 // Fixed-order sum of nblk partials by one block (all threads get the result).

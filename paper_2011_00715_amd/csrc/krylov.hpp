@@ -1,19 +1,23 @@
 // Batched Jacobi-PCG kernels.  Every kernel serves a table of systems: block b
 // belongs to system s (binary search over blk_start), and the system's
 // logical block j (XCD-aware) owns the same contiguous run of tiles/rows in
-// every kernel.  Per-system reductions are per-block partials reduced by the
-// system's last-arriving block in a fixed order, so the result of a system
-// does not depend on which other systems share the launch.
+// every kernel.  Reductions write one partial per block; a finalize kernel
+// with one block per system then sums the partials in a fixed order and
+// updates the system's scalars.  No kernel synchronises across its own
+// blocks (a device-scope fence writes back and invalidates the XCD's L2), and
+// there are no floating-point atomics, so a system's bits depend only on the
+// system itself, never on the rest of the batch.
 //
 // One PCG iteration (textbook preconditioned CG; the paper names CG in
-// Sec. 5.5 and the Jacobi smoother in Sec. 5.3) is three kernels:
-//   A  q = A p and p.q            -> last block: eta, alpha = rho / eta
-//   B  r -= alpha q, z = D^-1 r,  r.z and r.r (one pass, Sec. 4 Response F3:
-//      several inner products fused)  -> last block: convergence test, beta
-//   C  x += alpha p, p = z + beta p
-// The scalars live on the device, and every kernel becomes a no-op once the
-// system has stopped, so a captured graph of many iterations can be replayed
-// without host round trips (Challenge A1: kernel fusion, graphs, pipelining).
+// Sec. 5.5 and the Jacobi smoother in Sec. 5.3):
+//   A   q = A p, per-block p.q           F_A  eta = p.q, alpha = rho / eta
+//   B   r -= alpha q, z = D^-1 r,        F_B  convergence test, beta, and
+//       per-block r.z and r.r (one pass,      what C must do next
+//       Sec. 4 Response F3: fused inner products)
+//   C   x += alpha p, p = z + beta p
+// Scalars live on the device and every kernel is a no-op once its system has
+// stopped, so a captured graph of many iterations replays without host round
+// trips (Challenge A1: fusion, graphs, pipelining).
 #pragma once
 
 #include "spmv.hpp"
@@ -36,6 +40,7 @@ template <> struct Vecs<double> {
     __device__ static double *q(const SysDesc &d) { return d.q; }
     __device__ static double *x(const SysDesc &d) { return d.x; }
     static constexpr int gate = kGateInner64;
+    static constexpr int mixed = 0;
 };
 template <> struct Vecs<float> {
     __device__ static const float *val(const SysDesc &d) { return d.val32; }
@@ -46,16 +51,18 @@ template <> struct Vecs<float> {
     __device__ static float *q(const SysDesc &d) { return d.q32; }
     __device__ static float *x(const SysDesc &d) { return d.d32; }
     static constexpr int gate = kGateInner32;
+    static constexpr int mixed = 1;
 };
 
-// Block -> (system, logical block).  False for padding blocks.
-__device__ __forceinline__ bool locate(const Batch &a, int &s, int &j)
+// Block -> (system, logical block); the descriptor is copied into registers
+// (stores through the system's vectors cannot alias it).  False for padding.
+__device__ __forceinline__ bool locate(const Batch &a, int &j, SysDesc &d)
 {
-    s = find_sys(a.blk_start, a.nsys, blockIdx.x);
+    const int s = find_sys(a.blk_start, a.nsys, blockIdx.x);
     const int l = blockIdx.x - a.blk_start[s];
-    const int nb = a.sys[s].nblk;
-    if (l >= nb) return false;
-    j = xcd_remap(l, nb);
+    d = a.sys[s];
+    if (l >= d.nblk) return false;
+    j = xcd_remap(l, d.nblk);
     return true;
 }
 
@@ -69,10 +76,25 @@ __device__ __forceinline__ void row_range(const SysDesc &d, int j, int &rb, int 
 
 __device__ __forceinline__ bool finite(double v) { return isfinite(v); }
 
+// Loop over [rb, re) with 4 independent rows per lane in flight.
+template <class F>
+__device__ __forceinline__ void rows_unrolled(int rb, int re, F &&f)
+{
+    constexpr int U = 4;
+    for (int i0 = rb + (int)threadIdx.x; i0 < re; i0 += kBlock * U) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int i = i0 + u * kBlock;
+            if (i < re) f(i);
+        }
+    }
+}
+
 // ------------------------------------------------------------------ state init
-// One thread per system: reset the scalars for a new solve.
+// One thread: reset the scalars of one system for a new solve.
 static __global__ void k_state_init(SysState *st, double rtol, double atol, int maxit, int mixed,
-                             double inner_rtol, int inner_maxit, int max_outer, int hist_len)
+                                    double inner_rtol, int inner_maxit, int max_outer,
+                                    int hist_len)
 {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
     st->status = SPK_RUNNING;
@@ -80,14 +102,13 @@ static __global__ void k_state_init(SysState *st, double rtol, double atol, int 
     st->iter = 0;
     st->inner_iter = 0;
     st->outer = 0;
-    st->x_pending = 0;
+    st->cmode = 0;
     st->maxit = maxit;
     st->inner_maxit = inner_maxit;
     st->max_outer = max_outer;
     st->stagnant = 0;
     st->mixed = mixed;
     st->hist_len = hist_len;
-    for (int i = 0; i < kNumCnt; ++i) st->counter[i] = 0;
     st->rho = st->alpha = st->beta = st->eta = 0.0;
     st->rnorm = st->rnorm0 = st->bnorm = st->thresh = 0.0;
     st->rtol = rtol;
@@ -104,17 +125,95 @@ static __global__ void k_state_restart(SysState *st)
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
     st->status = SPK_RUNNING;
     st->phase = kPhaseInner;
-    st->x_pending = 0;
+    st->cmode = 0;
+}
+
+// Finalize kernels run one block per system: blockIdx.x = system.
+__device__ __forceinline__ bool fin_locate(const Batch &a, SysDesc &d)
+{
+    if ((int)blockIdx.x >= a.nsys) return false;
+    d = a.sys[blockIdx.x];
+    return true;
 }
 
 // ------------------------------------------------------------------ residual
 // Purpose of a residual launch.
 enum { kResSetup = 0, kResTrue = 1, kResOuter = 2 };
 
-__device__ __forceinline__ void resid_finish_scalars(const SysDesc &d, double rr, double bb,
-                                                     int purpose)
+// r = b - A x in FP64 with the stream tile kernel, per-block r.r and b.b.
+template <int kGate>
+__global__ __launch_bounds__(kBlock) void k_resid_stream(Batch a)
 {
+    __shared__ TileLds<double> sm;
+    __shared__ double red[kBlock / kWave];
+    int j;
+    SysDesc d;
+    if (!locate(a, j, d)) return;
+    if (kGate != kGateNone && !gate_open(d.st, kGate)) return;
+    int t0, t1;
+    block_tiles(j, d.nblk, d.ntiles, t0, t1);
+    const double *__restrict__ b = d.b;
+    double *__restrict__ r = d.r;
+    double rr = 0.0, bb = 0.0;
+    for (int t = t0; t < t1; ++t) {
+        const int r0 = t * d.R;
+        const int r1 = min(r0 + d.R, d.n);
+        stream_tile<double>(r0, r1, d.rowptr, d.col, d.val, d.x, sm, [&](int i, double y) {
+            const double bi = b[i];
+            const double ri = bi - y;
+            r[i] = ri;
+            rr = fma(ri, ri, rr);
+            bb = fma(bi, bi, bb);
+        });
+    }
+    rr = block_sum(rr, red);
+    bb = block_sum(bb, red);
+    if (threadIdx.x == 0) {
+        d.partials[kPartRr * d.nblk + j] = rr;
+        d.partials[kPartBb * d.nblk + j] = bb;
+    }
+}
+
+// r = b - y where y = A x was written into r by a standalone SpMV kernel.
+template <int kGate>
+__global__ __launch_bounds__(kBlock) void k_resid_combine(Batch a)
+{
+    __shared__ double red[kBlock / kWave];
+    int j;
+    SysDesc d;
+    if (!locate(a, j, d)) return;
+    if (kGate != kGateNone && !gate_open(d.st, kGate)) return;
+    int rb, re;
+    row_range(d, j, rb, re);
+    const double *__restrict__ b = d.b;
+    double *__restrict__ r = d.r;
+    double rr = 0.0, bb = 0.0;
+    rows_unrolled(rb, re, [&](int i) {
+        const double bi = b[i];
+        const double ri = bi - r[i];
+        r[i] = ri;
+        rr = fma(ri, ri, rr);
+        bb = fma(bi, bi, bb);
+    });
+    rr = block_sum(rr, red);
+    bb = block_sum(bb, red);
+    if (threadIdx.x == 0) {
+        d.partials[kPartRr * d.nblk + j] = rr;
+        d.partials[kPartBb * d.nblk + j] = bb;
+    }
+}
+
+template <int kGate>
+__global__ __launch_bounds__(kBlock) void k_fin_resid(Batch a, int purpose)
+{
+    __shared__ double red[kBlock / kWave];
+    SysDesc d;
+    if (!fin_locate(a, d)) return;
     SysState *st = d.st;
+    if (kGate != kGateNone && !gate_open(st, kGate)) return;
+    const double rr = reduce_partials(d.partials + kPartRr * d.nblk, d.nblk, red);
+    const double bb = reduce_partials(d.partials + kPartBb * d.nblk, d.nblk, red);
+    if (threadIdx.x != 0) return;
     const double rn = sqrt(rr);
     if (purpose == kResTrue) {
         st->rnorm_true = rn;
@@ -156,324 +255,294 @@ __device__ __forceinline__ void resid_finish_scalars(const SysDesc &d, double rr
     st->phase = kPhaseSetup;
 }
 
-// r = b - A x in FP64 with the stream tile kernel, r.r and b.b fused.
-template <int kGate>
-__global__ __launch_bounds__(kBlock) void k_resid_stream(Batch a, int purpose)
-{
-    __shared__ TileLds<double> sm;
-    __shared__ double red[kBlock / kWave];
-    int s, j;
-    if (!locate(a, s, j)) return;
-    const SysDesc &d = a.sys[s];
-    if (kGate != kGateNone && !gate_open(d.st, kGate)) return;
-    int t0, t1;
-    block_tiles(j, d.nblk, d.ntiles, t0, t1);
-    const double *b = d.b;
-    double *r = d.r;
-    double rr = 0.0, bb = 0.0;
-    for (int t = t0; t < t1; ++t) {
-        const int r0 = t * d.R;
-        const int r1 = min(r0 + d.R, d.n);
-        stream_tile<double>(r0, r1, d.rowptr, d.col, d.val, d.x, sm, [&](int i, double y) {
-            const double bi = b[i];
-            const double ri = bi - y;
-            r[i] = ri;
-            rr = fma(ri, ri, rr);
-            bb = fma(bi, bi, bb);
-        });
-    }
-    rr = block_sum(rr, red);
-    bb = block_sum(bb, red);
-    if (threadIdx.x == 0) {
-        d.partials[kPartRr * d.nblk + j] = rr;
-        d.partials[kPartBb * d.nblk + j] = bb;
-    }
-    if (last_block_arrive(&d.st->counter[kCntRes], d.nblk)) {
-        const double RR = reduce_partials(d.partials + kPartRr * d.nblk, d.nblk, red);
-        const double BB = reduce_partials(d.partials + kPartBb * d.nblk, d.nblk, red);
-        if (threadIdx.x == 0) resid_finish_scalars(d, RR, BB, purpose);
-    }
-}
-
-// r = b - y where y = A x was written into r by a standalone SpMV kernel.
-template <int kGate>
-__global__ __launch_bounds__(kBlock) void k_resid_finish(Batch a, int purpose)
-{
-    __shared__ double red[kBlock / kWave];
-    int s, j;
-    if (!locate(a, s, j)) return;
-    const SysDesc &d = a.sys[s];
-    if (kGate != kGateNone && !gate_open(d.st, kGate)) return;
-    int rb, re;
-    row_range(d, j, rb, re);
-    double rr = 0.0, bb = 0.0;
-    for (int i = rb + (int)threadIdx.x; i < re; i += kBlock) {
-        const double bi = d.b[i];
-        const double ri = bi - d.r[i];
-        d.r[i] = ri;
-        rr = fma(ri, ri, rr);
-        bb = fma(bi, bi, bb);
-    }
-    rr = block_sum(rr, red);
-    bb = block_sum(bb, red);
-    if (threadIdx.x == 0) {
-        d.partials[kPartRr * d.nblk + j] = rr;
-        d.partials[kPartBb * d.nblk + j] = bb;
-    }
-    if (last_block_arrive(&d.st->counter[kCntRes], d.nblk)) {
-        const double RR = reduce_partials(d.partials + kPartRr * d.nblk, d.nblk, red);
-        const double BB = reduce_partials(d.partials + kPartBb * d.nblk, d.nblk, red);
-        if (threadIdx.x == 0) resid_finish_scalars(d, RR, BB, purpose);
-    }
-}
-
 // ------------------------------------------------------------------ setup
-// FP64 start / restart from the residual in r: z = D^-1 r, p = z, rho = r.z.
+// FP64 start / restart from the residual in r: z = D^-1 r, p = z, per-block r.z.
 static __global__ __launch_bounds__(kBlock) void k_setup64(Batch a)
 {
     __shared__ double red[kBlock / kWave];
-    int s, j;
-    if (!locate(a, s, j)) return;
-    const SysDesc &d = a.sys[s];
+    int j;
+    SysDesc d;
+    if (!locate(a, j, d)) return;
     if (d.st->status != SPK_RUNNING) return;
     int rb, re;
     row_range(d, j, rb, re);
+    const double *__restrict__ r = d.r;
+    const double *__restrict__ dinv = d.dinv;
+    double *__restrict__ z = d.z;
+    double *__restrict__ p = d.p;
     double rz = 0.0;
-    for (int i = rb + (int)threadIdx.x; i < re; i += kBlock) {
-        const double ri = d.r[i];
-        const double zi = d.dinv[i] * ri;
-        d.z[i] = zi;
-        d.p[i] = zi;
+    rows_unrolled(rb, re, [&](int i) {
+        const double ri = r[i];
+        const double zi = dinv[i] * ri;
+        z[i] = zi;
+        p[i] = zi;
         rz = fma(ri, zi, rz);
-    }
+    });
     rz = block_sum(rz, red);
     if (threadIdx.x == 0) d.partials[kPartRz * d.nblk + j] = rz;
-    if (last_block_arrive(&d.st->counter[kCntSet], d.nblk)) {
-        const double RZ = reduce_partials(d.partials + kPartRz * d.nblk, d.nblk, red);
-        if (threadIdx.x == 0) {
-            SysState *st = d.st;
-            if (!finite(RZ)) st->status = SPK_DIVERGED_NANORINF;
-            else if (RZ < 0.0) st->status = SPK_DIVERGED_INDEFINITE_PC;
-            else if (RZ == 0.0) st->status = SPK_DIVERGED_BREAKDOWN;
-            else if (st->iter >= st->maxit) { st->status = SPK_DIVERGED_ITS; st->rho = RZ; }
-            else st->rho = RZ;
-        }
-    }
+}
+
+static __global__ __launch_bounds__(kBlock) void k_fin_setup64(Batch a)
+{
+    __shared__ double red[kBlock / kWave];
+    SysDesc d;
+    if (!fin_locate(a, d)) return;
+    SysState *st = d.st;
+    if (st->status != SPK_RUNNING) return;
+    const double RZ = reduce_partials(d.partials + kPartRz * d.nblk, d.nblk, red);
+    if (threadIdx.x != 0) return;
+    if (!finite(RZ)) st->status = SPK_DIVERGED_NANORINF;
+    else if (RZ < 0.0) st->status = SPK_DIVERGED_INDEFINITE_PC;
+    else if (RZ == 0.0) st->status = SPK_DIVERGED_BREAKDOWN;
+    else if (st->iter >= st->maxit) { st->status = SPK_DIVERGED_ITS; st->rho = RZ; }
+    else st->rho = RZ;
+}
+
+__device__ __forceinline__ bool in_phase(const SysState *st, int phase)
+{
+    return st->status == SPK_RUNNING && st->mixed == 1 && st->phase == phase;
 }
 
 // Mixed: start an FP32 inner solve on r32 = r / s (unit norm):
-// z32 = dinv32 r32, p32 = z32, d32 = 0, rho = r32.z32.
+// z32 = dinv32 r32, p32 = z32, d32 = 0, per-block r32.z32 and r32.r32.
 static __global__ __launch_bounds__(kBlock) void k_setup32(Batch a)
 {
     __shared__ double red[kBlock / kWave];
-    int s, j;
-    if (!locate(a, s, j)) return;
-    const SysDesc &d = a.sys[s];
-    SysState *st = d.st;
-    if (!(st->status == SPK_RUNNING && st->mixed == 1 && st->phase == kPhaseSetup)) return;
+    int j;
+    SysDesc d;
+    if (!locate(a, j, d)) return;
+    const SysState *st = d.st;
+    if (!in_phase(st, kPhaseSetup)) return;
     int rb, re;
     row_range(d, j, rb, re);
     const double inv = 1.0 / st->s;
+    const double *__restrict__ r = d.r;
+    const float *__restrict__ dinv = d.dinv32;
+    float *__restrict__ r32 = d.r32;
+    float *__restrict__ z32 = d.z32;
+    float *__restrict__ p32 = d.p32;
+    float *__restrict__ d32 = d.d32;
     float rz = 0.f, rr = 0.f;
-    for (int i = rb + (int)threadIdx.x; i < re; i += kBlock) {
-        const float ri = (float)(d.r[i] * inv);
-        const float zi = d.dinv32[i] * ri;
-        d.r32[i] = ri;
-        d.z32[i] = zi;
-        d.p32[i] = zi;
-        d.d32[i] = 0.f;
+    rows_unrolled(rb, re, [&](int i) {
+        const float ri = (float)(r[i] * inv);
+        const float zi = dinv[i] * ri;
+        r32[i] = ri;
+        z32[i] = zi;
+        p32[i] = zi;
+        d32[i] = 0.f;
         rz = fmaf(ri, zi, rz);
         rr = fmaf(ri, ri, rr);
-    }
+    });
     const double RZb = block_sum((double)rz, red);
     const double RRb = block_sum((double)rr, red);
     if (threadIdx.x == 0) {
         d.partials[kPartRz * d.nblk + j] = RZb;
         d.partials[kPartRr * d.nblk + j] = RRb;
     }
-    if (last_block_arrive(&st->counter[kCntSet], d.nblk)) {
-        const double RZ = reduce_partials(d.partials + kPartRz * d.nblk, d.nblk, red);
-        const double RR = reduce_partials(d.partials + kPartRr * d.nblk, d.nblk, red);
-        if (threadIdx.x == 0) {
-            st->inner_iter = 0;
-            st->inner_thresh = st->inner_rtol * sqrt(RR);
-            if (!finite(RZ) || !finite(RR)) st->status = SPK_DIVERGED_NANORINF;
-            else if (RZ < 0.0) st->status = SPK_DIVERGED_INDEFINITE_PC;
-            else if (RZ == 0.0) st->status = SPK_DIVERGED_BREAKDOWN;
-            else { st->rho = RZ; st->phase = kPhaseInner; }
-        }
-    }
+}
+
+static __global__ __launch_bounds__(kBlock) void k_fin_setup32(Batch a)
+{
+    __shared__ double red[kBlock / kWave];
+    SysDesc d;
+    if (!fin_locate(a, d)) return;
+    SysState *st = d.st;
+    if (!in_phase(st, kPhaseSetup)) return;
+    const double RZ = reduce_partials(d.partials + kPartRz * d.nblk, d.nblk, red);
+    const double RR = reduce_partials(d.partials + kPartRr * d.nblk, d.nblk, red);
+    if (threadIdx.x != 0) return;
+    st->inner_iter = 0;
+    st->inner_thresh = st->inner_rtol * sqrt(RR);
+    if (!finite(RZ) || !finite(RR)) st->status = SPK_DIVERGED_NANORINF;
+    else if (RZ < 0.0) st->status = SPK_DIVERGED_INDEFINITE_PC;
+    else if (RZ == 0.0) st->status = SPK_DIVERGED_BREAKDOWN;
+    else { st->rho = RZ; st->phase = kPhaseInner; }
 }
 
 // Mixed: x += s d (FP64 update from the FP32 correction).
 static __global__ __launch_bounds__(kBlock) void k_update_x(Batch a)
 {
-    int s, j;
-    if (!locate(a, s, j)) return;
-    const SysDesc &d = a.sys[s];
+    int j;
+    SysDesc d;
+    if (!locate(a, j, d)) return;
     const SysState *st = d.st;
-    if (!(st->status == SPK_RUNNING && st->mixed == 1 && st->phase == kPhaseUpdate)) return;
+    if (!in_phase(st, kPhaseUpdate)) return;
     int rb, re;
     row_range(d, j, rb, re);
     const double sc = st->s;
-    for (int i = rb + (int)threadIdx.x; i < re; i += kBlock)
-        d.x[i] = fma(sc, (double)d.d32[i], d.x[i]);
+    const float *__restrict__ d32 = d.d32;
+    double *__restrict__ x = d.x;
+    rows_unrolled(rb, re, [&](int i) { x[i] = fma(sc, (double)d32[i], x[i]); });
 }
 
 // ------------------------------------------------------------------ iteration
-__device__ __forceinline__ void pq_finish_scalars(SysState *st, double eta)
-{
-    st->eta = eta;
-    if (!finite(eta)) st->status = SPK_DIVERGED_NANORINF;
-    else if (eta <= 0.0) {
-        if (st->mixed) { st->phase = kPhaseUpdate; }  // inner breakdown: refine
-        else st->status = SPK_DIVERGED_INDEFINITE_MAT;
-    } else st->alpha = st->rho / eta;
-}
-
 // A: q = A p with the stream tile kernel, p.q fused into the row epilogue.
 template <class V>
 __global__ __launch_bounds__(kBlock) void k_pcg_spmv_stream(Batch a)
 {
     __shared__ TileLds<V> sm;
     __shared__ double red[kBlock / kWave];
-    int s, j;
-    if (!locate(a, s, j)) return;
-    const SysDesc &d = a.sys[s];
+    int j;
+    SysDesc d;
+    if (!locate(a, j, d)) return;
     if (!gate_open(d.st, Vecs<V>::gate)) return;
     int t0, t1;
     block_tiles(j, d.nblk, d.ntiles, t0, t1);
-    const V *p = Vecs<V>::p(d);
-    V *q = Vecs<V>::q(d);
+    const V *__restrict__ p = Vecs<V>::p(d);
+    V *__restrict__ q = Vecs<V>::q(d);
+    const V *__restrict__ val = Vecs<V>::val(d);
     V acc = V(0);
     for (int t = t0; t < t1; ++t) {
         const int r0 = t * d.R;
         const int r1 = min(r0 + d.R, d.n);
-        stream_tile<V>(r0, r1, d.rowptr, d.col, Vecs<V>::val(d), p, sm, [&](int i, V y) {
+        stream_tile<V>(r0, r1, d.rowptr, d.col, val, p, sm, [&](int i, V y) {
             q[i] = y;
             acc = fma(y, p[i], acc);
         });
     }
     const double blk = block_sum((double)acc, red);
     if (threadIdx.x == 0) d.partials[kPartPq * d.nblk + j] = blk;
-    if (last_block_arrive(&d.st->counter[kCntPq], d.nblk)) {
-        const double eta = reduce_partials(d.partials + kPartPq * d.nblk, d.nblk, red);
-        if (threadIdx.x == 0) pq_finish_scalars(d.st, eta);
-    }
 }
 
-// A (other SpMV kernels): q already holds A p; form p.q.
+// A (other SpMV kernels): q already holds A p; per-block p.q.
 template <class V>
 __global__ __launch_bounds__(kBlock) void k_pcg_pq(Batch a)
 {
     __shared__ double red[kBlock / kWave];
-    int s, j;
-    if (!locate(a, s, j)) return;
-    const SysDesc &d = a.sys[s];
+    int j;
+    SysDesc d;
+    if (!locate(a, j, d)) return;
     if (!gate_open(d.st, Vecs<V>::gate)) return;
     int rb, re;
     row_range(d, j, rb, re);
-    const V *p = Vecs<V>::p(d);
-    const V *q = Vecs<V>::q(d);
+    const V *__restrict__ p = Vecs<V>::p(d);
+    const V *__restrict__ q = Vecs<V>::q(d);
     V acc = V(0);
-    for (int i = rb + (int)threadIdx.x; i < re; i += kBlock) acc = fma(q[i], p[i], acc);
+    rows_unrolled(rb, re, [&](int i) { acc = fma(q[i], p[i], acc); });
     const double blk = block_sum((double)acc, red);
     if (threadIdx.x == 0) d.partials[kPartPq * d.nblk + j] = blk;
-    if (last_block_arrive(&d.st->counter[kCntPq], d.nblk)) {
-        const double eta = reduce_partials(d.partials + kPartPq * d.nblk, d.nblk, red);
-        if (threadIdx.x == 0) pq_finish_scalars(d.st, eta);
-    }
 }
 
-// B: r -= alpha q, z = D^-1 r, r.z and r.r in one pass.
+// F_A: eta = p.q, alpha = rho / eta.
+template <class V>
+__global__ __launch_bounds__(kBlock) void k_fin_pq(Batch a)
+{
+    __shared__ double red[kBlock / kWave];
+    SysDesc d;
+    if (!fin_locate(a, d)) return;
+    SysState *st = d.st;
+    if (!gate_open(st, Vecs<V>::gate)) return;
+    const double eta = reduce_partials(d.partials + kPartPq * d.nblk, d.nblk, red);
+    if (threadIdx.x != 0) return;
+    st->eta = eta;
+    if (!finite(eta)) st->status = SPK_DIVERGED_NANORINF;
+    else if (eta <= 0.0) {
+        if (st->mixed) st->phase = kPhaseUpdate;  // inner breakdown: refine from here
+        else st->status = SPK_DIVERGED_INDEFINITE_MAT;
+    } else st->alpha = st->rho / eta;
+}
+
+// B: r -= alpha q, z = D^-1 r, per-block r.z and r.r.
 template <class V>
 __global__ __launch_bounds__(kBlock) void k_pcg_update(Batch a)
 {
     __shared__ double red[kBlock / kWave];
-    int s, j;
-    if (!locate(a, s, j)) return;
-    const SysDesc &d = a.sys[s];
-    SysState *st = d.st;
+    int j;
+    SysDesc d;
+    if (!locate(a, j, d)) return;
+    const SysState *st = d.st;
     if (!gate_open(st, Vecs<V>::gate)) return;
     int rb, re;
     row_range(d, j, rb, re);
     const V nalpha = (V)(-st->alpha);
-    V *r = Vecs<V>::r(d);
-    V *z = Vecs<V>::z(d);
-    const V *q = Vecs<V>::q(d);
-    const V *dinv = Vecs<V>::dinv(d);
+    V *__restrict__ r = Vecs<V>::r(d);
+    V *__restrict__ z = Vecs<V>::z(d);
+    const V *__restrict__ q = Vecs<V>::q(d);
+    const V *__restrict__ dinv = Vecs<V>::dinv(d);
     V rz = V(0), rr = V(0);
-    for (int i = rb + (int)threadIdx.x; i < re; i += kBlock) {
+    rows_unrolled(rb, re, [&](int i) {
         const V ri = fma(nalpha, q[i], r[i]);
         const V zi = dinv[i] * ri;
         r[i] = ri;
         z[i] = zi;
         rz = fma(ri, zi, rz);
         rr = fma(ri, ri, rr);
-    }
+    });
     const double RZb = block_sum((double)rz, red);
     const double RRb = block_sum((double)rr, red);
     if (threadIdx.x == 0) {
         d.partials[kPartRz * d.nblk + j] = RZb;
         d.partials[kPartRr * d.nblk + j] = RRb;
     }
-    if (last_block_arrive(&st->counter[kCntUpd], d.nblk)) {
-        const double RZ = reduce_partials(d.partials + kPartRz * d.nblk, d.nblk, red);
-        const double RR = reduce_partials(d.partials + kPartRr * d.nblk, d.nblk, red);
-        if (threadIdx.x == 0) {
-            const int k = ++st->iter;
-            const double rn = sqrt(RR);
-            st->x_pending = 1;  // cleared below if the iteration continues
-            if (!st->mixed) {
-                st->rnorm = rn;
-                if (d.hist && k < st->hist_len) d.hist[k] = rn;
-                if (!finite(rn)) st->status = SPK_DIVERGED_NANORINF;
-                else if (rn <= st->thresh)
-                    st->status = rn <= st->rtol * st->bnorm ? SPK_CONVERGED_RTOL : SPK_CONVERGED_ATOL;
-                else if (k >= st->maxit) st->status = SPK_DIVERGED_ITS;
-                else if (!finite(RZ)) st->status = SPK_DIVERGED_NANORINF;
-                else if (RZ < 0.0) st->status = SPK_DIVERGED_INDEFINITE_PC;
-                else if (RZ == 0.0) st->status = SPK_DIVERGED_BREAKDOWN;
-                else { st->beta = RZ / st->rho; st->rho = RZ; st->x_pending = 0; }
-            } else {
-                const int ki = ++st->inner_iter;
-                if (!finite(rn) || !finite(RZ)) st->status = SPK_DIVERGED_NANORINF;
-                else if (rn <= st->inner_thresh || ki >= st->inner_maxit || k >= st->maxit || RZ <= 0.0)
-                    st->phase = kPhaseUpdate;
-                else { st->beta = RZ / st->rho; st->rho = RZ; st->x_pending = 0; }
-            }
-        }
+}
+
+// F_B: convergence test and beta; cmode tells C what to do: 2 = x and p
+// updates, 1 = the last x update only, 0 = nothing.  F_B runs every
+// iteration so that it can reset cmode after the last update.
+template <class V>
+__global__ __launch_bounds__(kBlock) void k_fin_update(Batch a)
+{
+    __shared__ double red[kBlock / kWave];
+    SysDesc d;
+    if (!fin_locate(a, d)) return;
+    SysState *st = d.st;
+    if (st->mixed != Vecs<V>::mixed) return;
+    if (!gate_open(st, Vecs<V>::gate)) {
+        if (threadIdx.x == 0) st->cmode = 0;
+        return;
+    }
+    const double RZ = reduce_partials(d.partials + kPartRz * d.nblk, d.nblk, red);
+    const double RR = reduce_partials(d.partials + kPartRr * d.nblk, d.nblk, red);
+    if (threadIdx.x != 0) return;
+    const int k = ++st->iter;
+    const double rn = sqrt(RR);
+    st->cmode = 1;  // stop unless the tests below continue
+    if (!st->mixed) {
+        st->rnorm = rn;
+        if (d.hist && k < st->hist_len) d.hist[k] = rn;
+        if (!finite(rn)) st->status = SPK_DIVERGED_NANORINF;
+        else if (rn <= st->thresh)
+            st->status = rn <= st->rtol * st->bnorm ? SPK_CONVERGED_RTOL : SPK_CONVERGED_ATOL;
+        else if (k >= st->maxit) st->status = SPK_DIVERGED_ITS;
+        else if (!finite(RZ)) st->status = SPK_DIVERGED_NANORINF;
+        else if (RZ < 0.0) st->status = SPK_DIVERGED_INDEFINITE_PC;
+        else if (RZ == 0.0) st->status = SPK_DIVERGED_BREAKDOWN;
+        else { st->beta = RZ / st->rho; st->rho = RZ; st->cmode = 2; }
+    } else {
+        const int ki = ++st->inner_iter;
+        if (!finite(rn) || !finite(RZ)) st->status = SPK_DIVERGED_NANORINF;
+        else if (rn <= st->inner_thresh || ki >= st->inner_maxit || k >= st->maxit || RZ <= 0.0)
+            st->phase = kPhaseUpdate;
+        else { st->beta = RZ / st->rho; st->rho = RZ; st->cmode = 2; }
     }
 }
 
-// C: x += alpha p (d for mixed), and p = z + beta p while iterating.
+// C: x += alpha p (d for mixed) and, while iterating, p = z + beta p.
 template <class V>
 __global__ __launch_bounds__(kBlock) void k_pcg_px(Batch a)
 {
-    int s, j;
-    if (!locate(a, s, j)) return;
-    const SysDesc &d = a.sys[s];
-    SysState *st = d.st;
-    const bool iterating = gate_open(st, Vecs<V>::gate);
-    const bool pending = st->x_pending && st->mixed == (Vecs<V>::gate == kGateInner32 ? 1 : 0);
-    if (!iterating && !pending) return;
+    int j;
+    SysDesc d;
+    if (!locate(a, j, d)) return;
+    const SysState *st = d.st;
+    if (st->mixed != Vecs<V>::mixed) return;
+    const int cm = st->cmode;
+    if (cm == 0) return;
     int rb, re;
     row_range(d, j, rb, re);
     const V alpha = (V)st->alpha;
     const V beta = (V)st->beta;
-    V *x = Vecs<V>::x(d);
-    V *p = Vecs<V>::p(d);
-    const V *z = Vecs<V>::z(d);
-    if (iterating && !pending) {
-        for (int i = rb + (int)threadIdx.x; i < re; i += kBlock) {
+    V *__restrict__ x = Vecs<V>::x(d);
+    V *__restrict__ p = Vecs<V>::p(d);
+    const V *__restrict__ z = Vecs<V>::z(d);
+    if (cm == 2) {
+        rows_unrolled(rb, re, [&](int i) {
             const V pi = p[i];
             x[i] = fma(alpha, pi, x[i]);
             p[i] = fma(beta, pi, z[i]);
-        }
+        });
     } else {
-        for (int i = rb + (int)threadIdx.x; i < re; i += kBlock) x[i] = fma(alpha, p[i], x[i]);
-        if (last_block_arrive(&st->counter[kCntPx], d.nblk))
-            if (threadIdx.x == 0) st->x_pending = 0;
+        rows_unrolled(rb, re, [&](int i) { x[i] = fma(alpha, p[i], x[i]); });
     }
 }
 

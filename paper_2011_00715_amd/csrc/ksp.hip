@@ -134,16 +134,18 @@ static Batch batch_of(Workspace *w) { return Batch{w->ddesc, w->blk_start, 1}; }
 static int launch_resid(spk_mat *A, Workspace *w, int purpose, bool gated, hipStream_t s)
 {
     const Batch b = batch_of(w);
-    const dim3 g(A->nblk), t(kBlock);
+    const dim3 g(A->nblk), t(kBlock), one(1);
     if (A->kernel == SPK_KERNEL_STREAM) {
-        if (gated) hipLaunchKernelGGL(k_resid_stream<kGateResid>, g, t, 0, s, b, purpose);
-        else hipLaunchKernelGGL(k_resid_stream<kGateNone>, g, t, 0, s, b, purpose);
+        if (gated) hipLaunchKernelGGL(k_resid_stream<kGateResid>, g, t, 0, s, b);
+        else hipLaunchKernelGGL(k_resid_stream<kGateNone>, g, t, 0, s, b);
     } else {
         SPK_TRY(launch_spmv<double>(A, A->val, w->x, w->r, s, gated ? w->st : nullptr,
                                     gated ? kGateResid : kGateNone));
-        if (gated) hipLaunchKernelGGL(k_resid_finish<kGateResid>, g, t, 0, s, b, purpose);
-        else hipLaunchKernelGGL(k_resid_finish<kGateNone>, g, t, 0, s, b, purpose);
+        if (gated) hipLaunchKernelGGL(k_resid_combine<kGateResid>, g, t, 0, s, b);
+        else hipLaunchKernelGGL(k_resid_combine<kGateNone>, g, t, 0, s, b);
     }
+    if (gated) hipLaunchKernelGGL(k_fin_resid<kGateResid>, one, t, 0, s, b, purpose);
+    else hipLaunchKernelGGL(k_fin_resid<kGateNone>, one, t, 0, s, b, purpose);
     SPK_HIP(hipGetLastError());
     return SPK_OK;
 }
@@ -152,7 +154,7 @@ template <class V>
 static int enqueue_iteration(spk_mat *A, Workspace *w, hipStream_t s)
 {
     const Batch b = batch_of(w);
-    const dim3 g(A->nblk), t(kBlock);
+    const dim3 g(A->nblk), t(kBlock), one(1);
     if (A->kernel == SPK_KERNEL_STREAM) {
         hipLaunchKernelGGL(k_pcg_spmv_stream<V>, g, t, 0, s, b);
     } else {
@@ -162,7 +164,9 @@ static int enqueue_iteration(spk_mat *A, Workspace *w, hipStream_t s)
         SPK_TRY(launch_spmv<V>(A, val, p, q, s, w->st, Vecs<V>::gate));
         hipLaunchKernelGGL(k_pcg_pq<V>, g, t, 0, s, b);
     }
+    hipLaunchKernelGGL(k_fin_pq<V>, one, t, 0, s, b);
     hipLaunchKernelGGL(k_pcg_update<V>, g, t, 0, s, b);
+    hipLaunchKernelGGL(k_fin_update<V>, one, t, 0, s, b);
     hipLaunchKernelGGL(k_pcg_px<V>, g, t, 0, s, b);
     SPK_HIP(hipGetLastError());
     return SPK_OK;
@@ -176,6 +180,7 @@ static int enqueue_batch(spk_mat *A, Workspace *w, bool mixed, int K, hipStream_
         hipLaunchKernelGGL(k_update_x, dim3(A->nblk), dim3(kBlock), 0, s, b);
         SPK_TRY(launch_resid(A, w, kResOuter, true, s));
         hipLaunchKernelGGL(k_setup32, dim3(A->nblk), dim3(kBlock), 0, s, b);
+        hipLaunchKernelGGL(k_fin_setup32, dim3(1), dim3(kBlock), 0, s, b);
         for (int k = 0; k < K; ++k) SPK_TRY(enqueue_iteration<float>(A, w, s));
     } else {
         for (int k = 0; k < K; ++k) SPK_TRY(enqueue_iteration<double>(A, w, s));
@@ -264,6 +269,7 @@ static int solve64(spk_mat *A, Workspace *w, const spk_ksp_opts &o, bool x_given
                        o.inner_rtol, o.inner_maxit, o.max_outer, hist_len);
     SPK_TRY(launch_resid(A, w, kResSetup, false, s));
     hipLaunchKernelGGL(k_setup64, dim3(A->nblk), dim3(kBlock), 0, s, batch_of(w));
+    hipLaunchKernelGGL(k_fin_setup64, dim3(1), dim3(kBlock), 0, s, batch_of(w));
     SPK_HIP(hipGetLastError());
     int restarts = 0;
     for (;;) {
@@ -283,6 +289,7 @@ static int solve64(spk_mat *A, Workspace *w, const spk_ksp_opts &o, bool x_given
             ++restarts;
             hipLaunchKernelGGL(k_state_restart, dim3(1), dim3(64), 0, s, w->st);
             hipLaunchKernelGGL(k_setup64, dim3(A->nblk), dim3(kBlock), 0, s, batch_of(w));
+            hipLaunchKernelGGL(k_fin_setup64, dim3(1), dim3(kBlock), 0, s, batch_of(w));
             SPK_HIP(hipGetLastError());
             continue;
         }

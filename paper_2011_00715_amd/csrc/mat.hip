@@ -155,13 +155,12 @@ __global__ void k_pmul(int n, const double *__restrict__ d, const double *__rest
         z[i] = d[i] * r[i];
 }
 
-// Single-pass dots: result[0] = x.y, result[1] = x.w (if w), or ||x|| (mode 2).
-// Contiguous chunk per block, fixed-order reduction by the last block.
+// Single-pass dots: per-block partials of x.y (and x.w) over a contiguous
+// chunk per block; k_dot_fin sums them in a fixed order.
 __global__ __launch_bounds__(kBlock) void k_dot(int n, const double *__restrict__ x,
                                                 const double *__restrict__ y,
-                                                const double *__restrict__ w, int mode,
-                                                double *__restrict__ part, uint32_t *counter,
-                                                double *__restrict__ result)
+                                                const double *__restrict__ w,
+                                                double *__restrict__ part)
 {
     __shared__ double red[kBlock / kWave];
     const int nb = gridDim.x;
@@ -178,15 +177,21 @@ __global__ __launch_bounds__(kBlock) void k_dot(int n, const double *__restrict_
     a = block_sum(a, red);
     if (w) b = block_sum(b, red);
     if (threadIdx.x == 0) { part[j] = a; part[nb + j] = b; }
-    if (last_block_arrive(counter, nb)) {
-        const double A = reduce_partials(part, nb, red);
-        const double B = w ? reduce_partials(part + nb, nb, red) : 0.0;
-        if (threadIdx.x == 0) {
-            if (mode == 2) result[0] = sqrt(A);
-            else {
-                result[0] = A;
-                if (w) result[1] = B;
-            }
+}
+
+// result[0] = x.y, result[1] = x.w (if two), or ||x|| (mode 2).
+__global__ __launch_bounds__(kBlock) void k_dot_fin(int nb, int two, int mode,
+                                                    const double *__restrict__ part,
+                                                    double *__restrict__ result)
+{
+    __shared__ double red[kBlock / kWave];
+    const double A = reduce_partials(part, nb, red);
+    const double B = two ? reduce_partials(part + nb, nb, red) : 0.0;
+    if (threadIdx.x == 0) {
+        if (mode == 2) result[0] = sqrt(A);
+        else {
+            result[0] = A;
+            if (two) result[1] = B;
         }
     }
 }
@@ -197,9 +202,21 @@ typedef double dvec2 __attribute__((ext_vector_type(2)));
 __global__ __launch_bounds__(kBlock) void k_copy(int64_t m, const dvec2 *__restrict__ a,
                                                  dvec2 *__restrict__ b)
 {
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < m;
-         i += (int64_t)gridDim.x * blockDim.x)
-        b[i] = __builtin_nontemporal_load(a + i);
+    constexpr int U = 4;  // 64 bytes per lane in flight
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i0 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i0 < m; i0 += stride * U) {
+        dvec2 v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t i = i0 + u * stride;
+            if (i < m) v[u] = __builtin_nontemporal_load(a + i);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t i = i0 + u * stride;
+            if (i < m) __builtin_nontemporal_store(v[u], b + i);
+        }
+    }
 }
 
 __global__ __launch_bounds__(kBlock) void k_scribble(int64_t m, dvec2 *__restrict__ b, double v)
@@ -736,7 +753,6 @@ int spk_vec_aypx(int32_t n, double beta, const double *x, double *y, void *strea
 // Per-stream reduction scratch (partials + counter), created on first use.
 struct DotScratch {
     double *part = nullptr;
-    uint32_t *counter = nullptr;
 };
 static std::mutex g_dot_mu;
 static std::map<std::pair<int, void *>, DotScratch> g_dot;
@@ -753,8 +769,6 @@ static int dot_launch(int32_t n, const double *x, const double *y, const double 
         auto it = g_dot.find({dev, stream});
         if (it == g_dot.end()) {
             SPK_HIP(hipMalloc(&sc.part, sizeof(double) * 2 * kMaxBlocksSingle));
-            SPK_HIP(hipMalloc(&sc.counter, sizeof(uint32_t)));
-            SPK_HIP(hipMemset(sc.counter, 0, sizeof(uint32_t)));
             g_dot[{dev, stream}] = sc;
         } else {
             sc = it->second;
@@ -763,7 +777,9 @@ static int dot_launch(int32_t n, const double *x, const double *y, const double 
     int grid = grid_for(n > 0 ? n : 1);
     if (grid >= kXcd) grid -= grid % kXcd;
     hipLaunchKernelGGL(k_dot, dim3(grid), dim3(kBlock), 0, (hipStream_t)stream, n, x,
-                       mode == 2 ? x : y, w, mode, sc.part, sc.counter, result);
+                       mode == 2 ? x : y, w, sc.part);
+    hipLaunchKernelGGL(k_dot_fin, dim3(1), dim3(kBlock), 0, (hipStream_t)stream, grid,
+                       w ? 1 : 0, mode, sc.part, result);
     SPK_HIP(hipGetLastError());
     return SPK_OK;
 }

@@ -194,9 +194,10 @@ static int start_fp64(spk_server *S, int k, const spk_ksp_opts &o, bool init_sta
     if (init_state)
         hipLaunchKernelGGL(k_state_init, dim3(1), dim3(64), 0, S->s, sl.desc.st, o.rtol, o.atol,
                            o.maxit, 0, o.inner_rtol, o.inner_maxit, o.max_outer, 0);
-    hipLaunchKernelGGL(k_resid_stream<kGateNone>, dim3(sl.desc.nblk), dim3(kBlock), 0, S->s, b,
-                       (int)kResSetup);
+    hipLaunchKernelGGL(k_resid_stream<kGateNone>, dim3(sl.desc.nblk), dim3(kBlock), 0, S->s, b);
+    hipLaunchKernelGGL(k_fin_resid<kGateNone>, dim3(1), dim3(kBlock), 0, S->s, b, (int)kResSetup);
     hipLaunchKernelGGL(k_setup64, dim3(sl.desc.nblk), dim3(kBlock), 0, S->s, b);
+    hipLaunchKernelGGL(k_fin_setup64, dim3(1), dim3(kBlock), 0, S->s, b);
     SPK_HIP(hipGetLastError());
     return SPK_OK;
 }
@@ -386,22 +387,28 @@ static int rebuild_table(spk_server *S)
 static int enqueue_step(spk_server *S)
 {
     const Batch b{S->d_table, S->d_blk, S->nsys};
-    const dim3 g(S->nblocks), t(kBlock);
+    const dim3 g(S->nblocks), t(kBlock), f(S->nsys);
     const int K = S->o.graph_k > 0 ? S->o.graph_k : 8;
     if (S->n_mixed) {
         hipLaunchKernelGGL(k_update_x, g, t, 0, S->s, b);
-        hipLaunchKernelGGL(k_resid_stream<kGateResid>, g, t, 0, S->s, b, (int)kResOuter);
+        hipLaunchKernelGGL(k_resid_stream<kGateResid>, g, t, 0, S->s, b);
+        hipLaunchKernelGGL(k_fin_resid<kGateResid>, f, t, 0, S->s, b, (int)kResOuter);
         hipLaunchKernelGGL(k_setup32, g, t, 0, S->s, b);
+        hipLaunchKernelGGL(k_fin_setup32, f, t, 0, S->s, b);
     }
     for (int k = 0; k < K; ++k) {
         if (S->n_fp64) {
             hipLaunchKernelGGL(k_pcg_spmv_stream<double>, g, t, 0, S->s, b);
+            hipLaunchKernelGGL(k_fin_pq<double>, f, t, 0, S->s, b);
             hipLaunchKernelGGL(k_pcg_update<double>, g, t, 0, S->s, b);
+            hipLaunchKernelGGL(k_fin_update<double>, f, t, 0, S->s, b);
             hipLaunchKernelGGL(k_pcg_px<double>, g, t, 0, S->s, b);
         }
         if (S->n_mixed) {
             hipLaunchKernelGGL(k_pcg_spmv_stream<float>, g, t, 0, S->s, b);
+            hipLaunchKernelGGL(k_fin_pq<float>, f, t, 0, S->s, b);
             hipLaunchKernelGGL(k_pcg_update<float>, g, t, 0, S->s, b);
+            hipLaunchKernelGGL(k_fin_update<float>, f, t, 0, S->s, b);
             hipLaunchKernelGGL(k_pcg_px<float>, g, t, 0, S->s, b);
         }
     }
@@ -414,8 +421,8 @@ static int begin_retire(spk_server *S, int k)
     Slot &sl = S->slots[k];
     Request *q = sl.req;
     const Batch b = slot_batch(S, k);
-    hipLaunchKernelGGL(k_resid_stream<kGateNone>, dim3(sl.desc.nblk), dim3(kBlock), 0, S->s, b,
-                       (int)kResTrue);
+    hipLaunchKernelGGL(k_resid_stream<kGateNone>, dim3(sl.desc.nblk), dim3(kBlock), 0, S->s, b);
+    hipLaunchKernelGGL(k_fin_resid<kGateNone>, dim3(1), dim3(kBlock), 0, S->s, b, (int)kResTrue);
     SPK_HIP(hipGetLastError());
     if (sl.px_cap < q->n) {
         if (sl.px) hipHostFree(sl.px);
@@ -444,6 +451,7 @@ static int end_retire(spk_server *S, int k, const SysState &st)
         ++sl.restarts;  // true residual drifted: restart from it
         hipLaunchKernelGGL(k_state_restart, dim3(1), dim3(64), 0, S->s, sl.desc.st);
         hipLaunchKernelGGL(k_setup64, dim3(sl.desc.nblk), dim3(kBlock), 0, S->s, slot_batch(S, k));
+        hipLaunchKernelGGL(k_fin_setup64, dim3(1), dim3(kBlock), 0, S->s, slot_batch(S, k));
         SPK_HIP(hipGetLastError());
         q->state = kActive;
         sl.first_step = S->step_id;

@@ -65,24 +65,32 @@ def _stencil_csr(N: int, dim: int, offsets, weights) -> CSR:
     sorted by their linear displacement so that columns come out ascending.
     """
     n = N ** dim
+    if n >= 2**31:
+        raise ValueError("n does not fit int32 indices")
     lin = [sum(o[d] * N ** d for d in range(dim)) for o in offsets]
     order = np.argsort(lin, kind="stable")
-    idx = np.arange(n, dtype=np.int64)
-    coord = [(idx // N ** d) % N for d in range(dim)]
     m = len(offsets)
+    shape = (N,) * dim  # C order: the last axis is x (fastest)
     mask = np.empty((n, m), dtype=bool)
     cols = np.empty((n, m), dtype=np.int32)
     vals = np.empty((n, m), dtype=np.float64)
+    idx = np.arange(n, dtype=np.int32)
     for slot, o_i in enumerate(order):
         o = offsets[o_i]
-        ok = np.ones(n, dtype=bool)
+        ok = np.ones(shape, dtype=bool)
         for d in range(dim):
-            c = coord[d] + o[d]
-            ok &= (c >= 0) & (c < N)
-        mask[:, slot] = ok
-        cols[:, slot] = (idx + lin[o_i]).astype(np.int32, copy=False) if n < 2**31 else 0
-        w = weights[o_i]
-        vals[:, slot] = w
+            ax = dim - 1 - d
+            sl = [slice(None)] * dim
+            if o[d] > 0:
+                sl[ax] = slice(N - o[d], None)
+            elif o[d] < 0:
+                sl[ax] = slice(0, -o[d])
+            else:
+                continue
+            ok[tuple(sl)] = False
+        mask[:, slot] = ok.ravel()
+        np.add(idx, np.int32(lin[o_i]), out=cols[:, slot])
+        vals[:, slot] = weights[o_i]
     counts = mask.sum(axis=1)
     rowptr = np.zeros(n + 1, dtype=np.int64)
     np.cumsum(counts, out=rowptr[1:])
