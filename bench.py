@@ -49,6 +49,10 @@ def parse():
     return p.parse_args()
 
 
+def log(msg):
+    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
+
+
 def pct(a, q):
     import numpy as np
 
@@ -129,6 +133,7 @@ def bench_c2(args):
     from paper_2011_00715_amd import spk
 
     N = 128
+    log("generating 7-point 128^3")
     A = spkgen.laplace3d7(N)
     b = spkgen.rhs_uniform(A.n, 0)
     M = spk.mat_create_csr(dev(A.rowptr), dev(A.col), dev(A.val), flags=spk.MAT_MIXED)
@@ -154,9 +159,11 @@ def bench_c2(args):
                 ev[i][1].record()
         return r64, rmx
 
+    log("warmup")
     for _ in range(args.warmup):
         step(False)
     torch.cuda.synchronize()
+    log("timed steps")
     step_ms, t64, tmx, spmv_us = [], [], [], []
     bytes_total = 0
     r64 = rmx = None
@@ -233,9 +240,208 @@ def bench_c2(args):
         },
     }
     if not args.no_cpu_baseline:
+        log("cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(A, b, info, args.cpu_iters)
     M.close()
     return out
+
+
+def calibration_copy():
+    """One plain copy of 256 MiB (known traffic: 256 MiB read + 256 MiB
+    written), so PMC byte counters can be scaled against it."""
+    import torch
+
+    from paper_2011_00715_amd import spk
+
+    n = (256 << 20) // 8
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    c = torch.empty_like(a)
+    spk.bw_copy(a, c)
+    torch.cuda.synchronize()
+    del a, c
+
+
+def solve_pair(spk, M, bd, graph_k):
+    import torch
+
+    x64 = torch.zeros_like(bd)
+    xmx = torch.zeros_like(bd)
+    r64 = spk.ksp_solve(M, bd, x64, spk.ksp_opts(graph_k=graph_k))
+    rmx = spk.ksp_solve(M, bd, xmx, spk.ksp_opts(graph_k=graph_k, precision=spk.PREC_MIXED))
+    return x64, r64, xmx, rmx
+
+
+def bench_c3(args):
+    """27-point lognormal diffusion 160^3: FP64 vs mixed-precision solves."""
+    import numpy as np
+    import torch
+
+    import oracle
+    import spkgen
+    from paper_2011_00715_amd import spk
+
+    log("generating 27-point lognormal 160^3")
+    A = spkgen.diffusion3d27_lognormal(160, seed=0)
+    b = spkgen.rhs_uniform(A.n, 0)
+    log("solving")
+    M = spk.mat_create_csr(dev(A.rowptr), dev(A.col), dev(A.val), flags=spk.MAT_MIXED)
+    info = M.info
+    bd = dev(b)
+    for _ in range(args.warmup):
+        solve_pair(spk, M, bd, args.graph_k)
+    t64, tmx = [], []
+    for _ in range(args.steps):
+        x64, r64, xmx, rmx = solve_pair(spk, M, bd, args.graph_k)
+        t64.append(r64.seconds)
+        tmx.append(rmx.seconds)
+    xg, xm = x64.cpu().numpy(), xmx.cpu().numpy()
+    bn = oracle.nrm2(b)
+    rel64 = oracle.nrm2(b - oracle.spmv(A, xg)) / bn
+    relmx = oracle.nrm2(b - oracle.spmv(A, xm)) / bn
+    m64, mmx = float(np.median(t64)), float(np.median(tmx))
+    out = {
+        "metric": "PCG solves/s to rtol 1e-8, FP64 vs mixed",
+        "value": 1.0 / mmx, "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": (m64 + mmx) * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32 inner / f64 outer", "data": "synthetic",
+        "config": {"workload": "3D 27-point lognormal diffusion 160^3 (n=4096000, nnz=109215352), "
+                               "rhs uniform seed 0; mixed CG (FP32 values/accumulate inside, FP64 "
+                               "residual/update/test) vs FP64", "kernel": spk.KERNEL_NAMES[info.kernel],
+                   "rows_per_tile": info.lanes},
+        "fp64": {"solves_per_s": 1 / m64, "ms": m64 * 1e3, "iterations": r64.iterations,
+                 "us_per_iter": m64 * 1e6 / max(r64.iterations, 1),
+                 "gbps": solve_bytes(info, r64) / m64 / 1e9, "true_rel_residual_oracle": rel64},
+        "mixed": {"solves_per_s": 1 / mmx, "ms": mmx * 1e3, "inner_iterations": rmx.inner_iterations,
+                  "outer_steps": rmx.outer_steps, "fallback_fp64": rmx.fallback_fp64,
+                  "us_per_inner_iter": mmx * 1e6 / max(rmx.inner_iterations, 1),
+                  "gbps": solve_bytes(info, rmx) / mmx / 1e9, "true_rel_residual_oracle": relmx,
+                  "error_vs_fp64": float(np.linalg.norm(xm - xg) / np.linalg.norm(xg))},
+        "speedup_mixed_vs_fp64": m64 / mmx,
+    }
+    M.close()
+    return out
+
+
+def bench_c4(args):
+    """Power-law SPD n = 4M: FP64 and FP32-value SpMV per kernel family."""
+    import numpy as np
+    import torch
+
+    import oracle
+    import spkgen
+    from paper_2011_00715_amd import spk
+
+    log("generating power-law n=4M")
+    A = spkgen.powerlaw_spd(4_000_000, seed=0)
+    log(f"nnz {A.nnz}; timing kernels")
+    M = spk.mat_create_csr(dev(A.rowptr), dev(A.col), dev(A.val), flags=spk.MAT_MIXED)
+    info = M.info
+    auto = spk.KERNEL_NAMES[info.kernel]
+    xh = spkgen.rhs_uniform(A.n, 0)
+    x = dev(xh)
+    y = torch.empty_like(x)
+    x32 = x.float()
+    y32 = torch.empty_like(x32)
+    rows = np.random.default_rng(0).integers(0, A.n, 2000)
+    yo, ya = oracle.spmv_rows(A, xh, rows)
+    res = {}
+    for name, k, p in [("merge", spk.KERNEL_MERGE, 0), ("vector32", spk.KERNEL_VECTOR, 32),
+                       ("vector8", spk.KERNEL_VECTOR, 8), ("stream", spk.KERNEL_STREAM, 0)]:
+        spk.mat_set_kernel(M, k, p)
+        for _ in range(args.warmup + 1):
+            spk.mat_mult(M, x, y)
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(args.steps)]
+        for e0, e1 in ev:
+            e0.record()
+            spk.mat_mult(M, x, y)
+            e1.record()
+        torch.cuda.synchronize()
+        us = float(np.median([e0.elapsed_time(e1) * 1e3 for e0, e1 in ev]))
+        err = float(np.max(np.abs(y.cpu().numpy()[rows] - yo) / ya))
+        for _ in range(args.warmup + 1):
+            spk.mat_mult_f32(M, x32, y32)
+        for e0, e1 in ev:
+            e0.record()
+            spk.mat_mult_f32(M, x32, y32)
+            e1.record()
+        torch.cuda.synchronize()
+        us32 = float(np.median([e0.elapsed_time(e1) * 1e3 for e0, e1 in ev]))
+        res[name] = {"us": us, "gbps": info.bytes_spmv_f64 / us / 1e3, "max_err_rel_abs_sum": err,
+                     "f32_us": us32, "f32_gbps": info.bytes_spmv_f32 / us32 / 1e3}
+    out = {
+        "metric": "CSR SpMV HBM GB/s (algorithmic), power-law rows",
+        "value": res["merge"]["gbps"], "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": res["merge"]["us"] / 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"random SPD, n=4000000, nnz={info.nnz}, Zipf(1.8) row picks clipped "
+                               "to [3,4000], symmetric pattern", "auto_kernel": auto,
+                   "row_mean": info.row_mean, "row_max": info.row_max, "row_cv": info.row_cv},
+        "kernels": res,
+        "bytes_f64": info.bytes_spmv_f64, "bytes_f32": info.bytes_spmv_f32,
+    }
+    M.close()
+    return out
+
+
+def bench_serve(args):
+    """Served solve stream: Poisson arrivals of shifted 2D/3D Laplacians."""
+    import numpy as np
+
+    import spkgen
+    from paper_2011_00715_amd import spk
+
+    reqs = spkgen.serve_stream(seed=0, rate=args.serve_rate, duration=args.serve_seconds,
+                               count=args.serve_closed or None)
+    log(f"{len(reqs)} requests; building patterns")
+    for r in reqs:  # build the patterns before the clock starts
+        spkgen.serve_matrix(r)
+    log("serving")
+    opts = spk.server_opts_default()
+    opts.hbm_budget_bytes = 32 << 30
+    opts.max_slots = 64
+    opts.graph_k = args.graph_k
+    S = spk.server_create(opts)
+    o = spk.ksp_opts(precision=spk.PREC_MIXED)
+    pending = {}
+    lat, iters = [], []
+    worst_rel = 0.0
+    t0 = spk.now()
+    i = 0
+    closed = bool(args.serve_closed)
+    while i < len(reqs) or pending:
+        now = spk.now() - t0
+        while i < len(reqs) and (closed or reqs[i].t_arrival <= now):
+            r = reqs[i]
+            A = spkgen.serve_matrix(r)
+            b = spkgen.rhs_uniform(A.n, r.rhs_seed % (2**31))
+            t_arr = t0 + (0.0 if closed else r.t_arrival)
+            pending[spk.server_submit(S, A.rowptr, A.col, A.val, b, o)] = (t_arr, A.n)
+            i += 1
+        spk.server_progress(S, 1)
+        for t, (t_arr, n) in list(pending.items()):
+            got = spk.server_poll(S, t, np.empty(n))
+            if got is not None:
+                res, tdone = got
+                lat.append(tdone - t_arr)
+                iters.append(res.inner_iterations + res.iterations)
+                worst_rel = max(worst_rel, res.true_rel_residual)
+                assert res.reason > 0, spk.reason_str(res.reason)
+                del pending[t]
+    elapsed = spk.now() - t0
+    S.close()
+    return {
+        "metric": "served PCG solves/s to rtol 1e-8; p50/p99 latency",
+        "value": len(lat) / elapsed, "unit": "solves/s", "n_gpus": 1, "steps": len(lat),
+        "warmup": 0, "ms_per_step": elapsed * 1e3 / max(len(lat), 1), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32 inner / f64 outer", "data": "synthetic",
+        "config": {"workload": ("closed loop: %d requests queued at t=0" % len(reqs)) if closed else
+                   f"open loop: Poisson {args.serve_rate:g} req/s for {args.serve_seconds:g} s",
+                   "requests": len(reqs), "mix": "2D 5-point side 32-256 / 3D 7-point side 16-96, "
+                   "diagonal shift U[0,1), rhs U[-1,1)", "graph_k": args.graph_k},
+        "latency_ms": {"p50": pct(lat, 50) * 1e3, "p99": pct(lat, 99) * 1e3, "max": max(lat) * 1e3},
+        "iterations_mean": float(np.mean(iters)), "worst_true_rel_residual": worst_rel,
+    }
 
 
 def main():
@@ -250,10 +456,9 @@ def main():
         print(json.dumps({"error": "no GPU visible"}))
         sys.exit(1)
     torch.cuda.set_device(0)
-    if args.workload == "c2":
-        out = bench_c2(args)
-    else:
-        out = {"error": f"workload {args.workload} not available"}
+    calibration_copy()
+    fn = {"c2": bench_c2, "c3": bench_c3, "c4": bench_c4, "serve": bench_serve}[args.workload]
+    out = fn(args)
     print(json.dumps(out), flush=True)
 
 
