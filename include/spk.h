@@ -42,8 +42,15 @@ typedef struct spk_server spk_server;
 /* memory types of caller buffers */
 enum { SPK_MEM_HOST = 0, SPK_MEM_DEVICE = 1 };
 
-/* solve precision (Challenge A7 / Response A7: per-solve precision flag) */
-enum { SPK_PREC_FP64 = 0, SPK_PREC_MIXED = 1 };
+/* solve precision (Challenge A7 / Response A7: per-solve precision flag).
+ * Both mixed modes run FP32 inner CG on the FP32 values and keep the
+ * residual r = b - A x, the update of x and the convergence test in FP64:
+ *   SPK_PREC_MIXED     refinement by reliable updates: the FP32 search
+ *                      direction is kept across refinements (CG continues
+ *                      with the true residual), default trigger 0.05
+ *   SPK_PREC_MIXED_IR  restarted iterative refinement: each refinement
+ *                      solves A d = r / ||r|| from scratch to 1e-4 */
+enum { SPK_PREC_FP64 = 0, SPK_PREC_MIXED = 1, SPK_PREC_MIXED_IR = 2 };
 
 /* spk_mat_create_csr flags */
 enum {
@@ -184,9 +191,11 @@ typedef struct {
     int32_t precision;    /* SPK_PREC_FP64 (default) or SPK_PREC_MIXED */
     int32_t x0_nonzero;   /* 0: start from x = 0 (default); 1: from x */
     int32_t graph_k;      /* iterations per captured graph (default 8) */
-    double inner_rtol;    /* mixed: inner FP32 tolerance (default 1e-4) */
+    double inner_rtol;    /* mixed: refine once the FP32 residual fell by this
+                             factor since the last refinement; 0 (default)
+                             selects 0.05 for MIXED and 1e-4 for MIXED_IR */
     int32_t inner_maxit;  /* mixed: per inner solve (default 10000) */
-    int32_t max_outer;    /* mixed: refinement steps (default 20) */
+    int32_t max_outer;    /* mixed: refinement steps (default 100) */
     double *hist;         /* optional host double[hist_len]: ||r_k||_2 of the
                              recursive residual, k = 0..iterations */
     int32_t hist_len;

@@ -48,6 +48,9 @@ struct SysState {
     int32_t stagnant;     // mixed: consecutive weak outer reductions
     int32_t mixed;        // 1: mixed-precision solve
     int32_t hist_len;
+    int32_t ru;           // mixed: 1 keeps p across refinements (reliable updates)
+    int32_t fresh_p;      // mixed: the next refinement starts p from z
+    double scale;         // mixed: r32 = r / scale, x += scale d
     double rho, alpha, beta, eta;
     double rnorm, rnorm0, bnorm, thresh, rtol, atol;
     double inner_rtol, inner_thresh;
@@ -156,11 +159,47 @@ __device__ __forceinline__ T block_sum(T v, T *sh)
 }
 
 // Fixed-order sum of nblk partials by one block (all threads get the result).
+// Each lane sums part[tid], part[tid + 256], ... in that order; the loads of a
+// chunk are issued together so the reduction costs one memory latency.
 __device__ __forceinline__ double reduce_partials(const double *part, int nblk, double *sh)
 {
+    constexpr int U = 8;
     double s = 0.0;
-    for (int i = threadIdx.x; i < nblk; i += kBlock) s += part[i];
+    for (int i0 = threadIdx.x; i0 < nblk; i0 += kBlock * U) {
+        double v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int i = i0 + u * kBlock;
+            v[u] = i < nblk ? part[i] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) s += v[u];
+    }
     return block_sum(s, sh);
+}
+
+// Two partial arrays reduced together (same order as reduce_partials).
+__device__ __forceinline__ void reduce_partials2(const double *pa, const double *pb, int nblk,
+                                                 double *sh, double &A, double &B)
+{
+    constexpr int U = 8;
+    double s = 0.0, t = 0.0;
+    for (int i0 = threadIdx.x; i0 < nblk; i0 += kBlock * U) {
+        double v[U], w[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int i = i0 + u * kBlock;
+            v[u] = i < nblk ? pa[i] : 0.0;
+            w[u] = i < nblk ? pb[i] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            s += v[u];
+            t += w[u];
+        }
+    }
+    A = block_sum(s, sh);
+    B = block_sum(t, sh);
 }
 
 template <class T>

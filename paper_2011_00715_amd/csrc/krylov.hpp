@@ -24,10 +24,17 @@
 
 namespace spk {
 
+// The systems of one launch: `Batch` is a device table (the batched server);
+// `One` carries a single system's descriptor by value in the kernel
+// arguments, so that every field is a uniform scalar and no block pays
+// dependent global loads to find its system.
 struct Batch {
     const SysDesc *sys;
     const int32_t *blk_start;  // nsys + 1 entries
     int nsys;
+};
+struct One {
+    SysDesc d;
 };
 
 template <class V> struct Vecs;
@@ -66,6 +73,14 @@ __device__ __forceinline__ bool locate(const Batch &a, int &j, SysDesc &d)
     return true;
 }
 
+__device__ __forceinline__ bool locate(const One &a, int &j, SysDesc &d)
+{
+    d = a.d;
+    if ((int)blockIdx.x >= d.nblk) return false;
+    j = xcd_remap(blockIdx.x, d.nblk);
+    return true;
+}
+
 __device__ __forceinline__ void row_range(const SysDesc &d, int j, int &rb, int &re)
 {
     int t0, t1;
@@ -92,11 +107,16 @@ __device__ __forceinline__ void rows_unrolled(int rb, int re, F &&f)
 
 // ------------------------------------------------------------------ state init
 // One thread: reset the scalars of one system for a new solve.
+// mixed: 0 FP64, 1 FP32 inner with reliable updates, 2 FP32 inner restarted.
 static __global__ void k_state_init(SysState *st, double rtol, double atol, int maxit, int mixed,
                                     double inner_rtol, int inner_maxit, int max_outer,
                                     int hist_len)
 {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    st->ru = mixed == 1;
+    st->fresh_p = 1;
+    st->scale = 1.0;
+    mixed = mixed != 0;
     st->status = SPK_RUNNING;
     st->phase = mixed ? kPhaseResid : kPhaseInner;
     st->iter = 0;
@@ -136,13 +156,19 @@ __device__ __forceinline__ bool fin_locate(const Batch &a, SysDesc &d)
     return true;
 }
 
+__device__ __forceinline__ bool fin_locate(const One &a, SysDesc &d)
+{
+    d = a.d;
+    return blockIdx.x == 0;
+}
+
 // ------------------------------------------------------------------ residual
 // Purpose of a residual launch.
 enum { kResSetup = 0, kResTrue = 1, kResOuter = 2 };
 
 // r = b - A x in FP64 with the stream tile kernel, per-block r.r and b.b.
-template <int kGate>
-__global__ __launch_bounds__(kBlock) void k_resid_stream(Batch a)
+template <int kGate, class B>
+__global__ __launch_bounds__(kBlock) void k_resid_stream(B a)
 {
     __shared__ TileLds<double> sm;
     __shared__ double red[kBlock / kWave];
@@ -175,8 +201,8 @@ __global__ __launch_bounds__(kBlock) void k_resid_stream(Batch a)
 }
 
 // r = b - y where y = A x was written into r by a standalone SpMV kernel.
-template <int kGate>
-__global__ __launch_bounds__(kBlock) void k_resid_combine(Batch a)
+template <int kGate, class B>
+__global__ __launch_bounds__(kBlock) void k_resid_combine(B a)
 {
     __shared__ double red[kBlock / kWave];
     int j;
@@ -203,16 +229,17 @@ __global__ __launch_bounds__(kBlock) void k_resid_combine(Batch a)
     }
 }
 
-template <int kGate>
-__global__ __launch_bounds__(kBlock) void k_fin_resid(Batch a, int purpose)
+template <int kGate, class B>
+__global__ __launch_bounds__(kBlock) void k_fin_resid(B a, int purpose)
 {
     __shared__ double red[kBlock / kWave];
     SysDesc d;
     if (!fin_locate(a, d)) return;
     SysState *st = d.st;
     if (kGate != kGateNone && !gate_open(st, kGate)) return;
-    const double rr = reduce_partials(d.partials + kPartRr * d.nblk, d.nblk, red);
-    const double bb = reduce_partials(d.partials + kPartBb * d.nblk, d.nblk, red);
+    double rr, bb;
+    reduce_partials2(d.partials + kPartRr * d.nblk, d.partials + kPartBb * d.nblk, d.nblk, red,
+                     rr, bb);
     if (threadIdx.x != 0) return;
     const double rn = sqrt(rr);
     if (purpose == kResTrue) {
@@ -239,6 +266,9 @@ __global__ __launch_bounds__(kBlock) void k_fin_resid(Batch a, int purpose)
     if (d.hist && k < st->hist_len) d.hist[k] = rn;
     st->rnorm = rn;
     st->s = rn;
+    // restarted refinement solves each correction at unit scale; reliable
+    // updates keep the first scale so that p stays valid across refinements
+    if (k == 0 || !st->ru) st->scale = rn > 0.0 ? rn : 1.0;
     if (bn == 0.0) { st->status = SPK_CONVERGED_ATOL; return; }
     if (!finite(rn) || !finite(bn)) { st->status = SPK_DIVERGED_NANORINF; return; }
     if (rn <= st->thresh) {
@@ -257,7 +287,8 @@ __global__ __launch_bounds__(kBlock) void k_fin_resid(Batch a, int purpose)
 
 // ------------------------------------------------------------------ setup
 // FP64 start / restart from the residual in r: z = D^-1 r, p = z, per-block r.z.
-static __global__ __launch_bounds__(kBlock) void k_setup64(Batch a)
+template <class B>
+__global__ __launch_bounds__(kBlock) void k_setup64(B a)
 {
     __shared__ double red[kBlock / kWave];
     int j;
@@ -282,7 +313,8 @@ static __global__ __launch_bounds__(kBlock) void k_setup64(Batch a)
     if (threadIdx.x == 0) d.partials[kPartRz * d.nblk + j] = rz;
 }
 
-static __global__ __launch_bounds__(kBlock) void k_fin_setup64(Batch a)
+template <class B>
+__global__ __launch_bounds__(kBlock) void k_fin_setup64(B a)
 {
     __shared__ double red[kBlock / kWave];
     SysDesc d;
@@ -303,9 +335,12 @@ __device__ __forceinline__ bool in_phase(const SysState *st, int phase)
     return st->status == SPK_RUNNING && st->mixed == 1 && st->phase == phase;
 }
 
-// Mixed: start an FP32 inner solve on r32 = r / s (unit norm):
-// z32 = dinv32 r32, p32 = z32, d32 = 0, per-block r32.z32 and r32.r32.
-static __global__ __launch_bounds__(kBlock) void k_setup32(Batch a)
+// Mixed: (re)start the FP32 inner iteration on the FP64 residual,
+// r32 = r / scale, z32 = dinv32 r32, d32 = 0, per-block r32.z32 and r32.r32.
+// p32 = z32 for a restarted refinement (or the first one); with reliable
+// updates p32 is kept and p32 = z32 + beta p32 follows once beta is known.
+template <class B>
+__global__ __launch_bounds__(kBlock) void k_setup32(B a)
 {
     __shared__ double red[kBlock / kWave];
     int j;
@@ -315,7 +350,8 @@ static __global__ __launch_bounds__(kBlock) void k_setup32(Batch a)
     if (!in_phase(st, kPhaseSetup)) return;
     int rb, re;
     row_range(d, j, rb, re);
-    const double inv = 1.0 / st->s;
+    const double inv = 1.0 / st->scale;
+    const bool fresh = !st->ru || st->fresh_p;
     const double *__restrict__ r = d.r;
     const float *__restrict__ dinv = d.dinv32;
     float *__restrict__ r32 = d.r32;
@@ -328,7 +364,7 @@ static __global__ __launch_bounds__(kBlock) void k_setup32(Batch a)
         const float zi = dinv[i] * ri;
         r32[i] = ri;
         z32[i] = zi;
-        p32[i] = zi;
+        if (fresh) p32[i] = zi;
         d32[i] = 0.f;
         rz = fmaf(ri, zi, rz);
         rr = fmaf(ri, ri, rr);
@@ -341,26 +377,41 @@ static __global__ __launch_bounds__(kBlock) void k_setup32(Batch a)
     }
 }
 
-static __global__ __launch_bounds__(kBlock) void k_fin_setup32(Batch a)
+template <class B>
+__global__ __launch_bounds__(kBlock) void k_fin_setup32(B a)
 {
     __shared__ double red[kBlock / kWave];
     SysDesc d;
     if (!fin_locate(a, d)) return;
     SysState *st = d.st;
     if (!in_phase(st, kPhaseSetup)) return;
-    const double RZ = reduce_partials(d.partials + kPartRz * d.nblk, d.nblk, red);
-    const double RR = reduce_partials(d.partials + kPartRr * d.nblk, d.nblk, red);
+    double RZ, RR;
+    reduce_partials2(d.partials + kPartRz * d.nblk, d.partials + kPartRr * d.nblk, d.nblk, red,
+                     RZ, RR);
     if (threadIdx.x != 0) return;
     st->inner_iter = 0;
-    st->inner_thresh = st->inner_rtol * sqrt(RR);
+    // refine again once the inner residual fell by inner_rtol, or as soon as it
+    // predicts that the target is met
+    st->inner_thresh = fmax(st->inner_rtol * sqrt(RR), st->thresh / st->scale);
+    st->cmode = 0;
     if (!finite(RZ) || !finite(RR)) st->status = SPK_DIVERGED_NANORINF;
     else if (RZ < 0.0) st->status = SPK_DIVERGED_INDEFINITE_PC;
     else if (RZ == 0.0) st->status = SPK_DIVERGED_BREAKDOWN;
-    else { st->rho = RZ; st->phase = kPhaseInner; }
+    else {
+        if (st->ru && !st->fresh_p) {
+            // reliable update: continue the same CG with the true residual
+            st->beta = RZ / st->rho;
+            st->cmode = 3;  // p32 = z32 + beta p32 before the next SpMV
+        }
+        st->fresh_p = 0;
+        st->rho = RZ;
+        st->phase = kPhaseInner;
+    }
 }
 
 // Mixed: x += s d (FP64 update from the FP32 correction).
-static __global__ __launch_bounds__(kBlock) void k_update_x(Batch a)
+template <class B>
+__global__ __launch_bounds__(kBlock) void k_update_x(B a)
 {
     int j;
     SysDesc d;
@@ -369,7 +420,7 @@ static __global__ __launch_bounds__(kBlock) void k_update_x(Batch a)
     if (!in_phase(st, kPhaseUpdate)) return;
     int rb, re;
     row_range(d, j, rb, re);
-    const double sc = st->s;
+    const double sc = st->scale;
     const float *__restrict__ d32 = d.d32;
     double *__restrict__ x = d.x;
     rows_unrolled(rb, re, [&](int i) { x[i] = fma(sc, (double)d32[i], x[i]); });
@@ -377,8 +428,8 @@ static __global__ __launch_bounds__(kBlock) void k_update_x(Batch a)
 
 // ------------------------------------------------------------------ iteration
 // A: q = A p with the stream tile kernel, p.q fused into the row epilogue.
-template <class V>
-__global__ __launch_bounds__(kBlock) void k_pcg_spmv_stream(Batch a)
+template <class V, class B>
+__global__ __launch_bounds__(kBlock) void k_pcg_spmv_stream(B a)
 {
     __shared__ TileLds<V> sm;
     __shared__ double red[kBlock / kWave];
@@ -405,8 +456,8 @@ __global__ __launch_bounds__(kBlock) void k_pcg_spmv_stream(Batch a)
 }
 
 // A (other SpMV kernels): q already holds A p; per-block p.q.
-template <class V>
-__global__ __launch_bounds__(kBlock) void k_pcg_pq(Batch a)
+template <class V, class B>
+__global__ __launch_bounds__(kBlock) void k_pcg_pq(B a)
 {
     __shared__ double red[kBlock / kWave];
     int j;
@@ -424,8 +475,8 @@ __global__ __launch_bounds__(kBlock) void k_pcg_pq(Batch a)
 }
 
 // F_A: eta = p.q, alpha = rho / eta.
-template <class V>
-__global__ __launch_bounds__(kBlock) void k_fin_pq(Batch a)
+template <class V, class B>
+__global__ __launch_bounds__(kBlock) void k_fin_pq(B a)
 {
     __shared__ double red[kBlock / kWave];
     SysDesc d;
@@ -437,14 +488,16 @@ __global__ __launch_bounds__(kBlock) void k_fin_pq(Batch a)
     st->eta = eta;
     if (!finite(eta)) st->status = SPK_DIVERGED_NANORINF;
     else if (eta <= 0.0) {
-        if (st->mixed) st->phase = kPhaseUpdate;  // inner breakdown: refine from here
-        else st->status = SPK_DIVERGED_INDEFINITE_MAT;
+        if (st->mixed) {  // inner breakdown: refine from here with a fresh p
+            st->phase = kPhaseUpdate;
+            st->fresh_p = 1;
+        } else st->status = SPK_DIVERGED_INDEFINITE_MAT;
     } else st->alpha = st->rho / eta;
 }
 
 // B: r -= alpha q, z = D^-1 r, per-block r.z and r.r.
-template <class V>
-__global__ __launch_bounds__(kBlock) void k_pcg_update(Batch a)
+template <class V, class B>
+__global__ __launch_bounds__(kBlock) void k_pcg_update(B a)
 {
     __shared__ double red[kBlock / kWave];
     int j;
@@ -479,8 +532,8 @@ __global__ __launch_bounds__(kBlock) void k_pcg_update(Batch a)
 // F_B: convergence test and beta; cmode tells C what to do: 2 = x and p
 // updates, 1 = the last x update only, 0 = nothing.  F_B runs every
 // iteration so that it can reset cmode after the last update.
-template <class V>
-__global__ __launch_bounds__(kBlock) void k_fin_update(Batch a)
+template <class V, class B>
+__global__ __launch_bounds__(kBlock) void k_fin_update(B a)
 {
     __shared__ double red[kBlock / kWave];
     SysDesc d;
@@ -491,8 +544,9 @@ __global__ __launch_bounds__(kBlock) void k_fin_update(Batch a)
         if (threadIdx.x == 0) st->cmode = 0;
         return;
     }
-    const double RZ = reduce_partials(d.partials + kPartRz * d.nblk, d.nblk, red);
-    const double RR = reduce_partials(d.partials + kPartRr * d.nblk, d.nblk, red);
+    double RZ, RR;
+    reduce_partials2(d.partials + kPartRz * d.nblk, d.partials + kPartRr * d.nblk, d.nblk, red,
+                     RZ, RR);
     if (threadIdx.x != 0) return;
     const int k = ++st->iter;
     const double rn = sqrt(RR);
@@ -511,15 +565,18 @@ __global__ __launch_bounds__(kBlock) void k_fin_update(Batch a)
     } else {
         const int ki = ++st->inner_iter;
         if (!finite(rn) || !finite(RZ)) st->status = SPK_DIVERGED_NANORINF;
-        else if (rn <= st->inner_thresh || ki >= st->inner_maxit || k >= st->maxit || RZ <= 0.0)
+        else if (rn <= st->inner_thresh || ki >= st->inner_maxit || k >= st->maxit || RZ <= 0.0) {
             st->phase = kPhaseUpdate;
-        else { st->beta = RZ / st->rho; st->rho = RZ; st->cmode = 2; }
+            if (RZ <= 0.0) st->fresh_p = 1;
+        } else { st->beta = RZ / st->rho; st->rho = RZ; st->cmode = 2; }
     }
 }
 
 // C: x += alpha p (d for mixed) and, while iterating, p = z + beta p.
-template <class V>
-__global__ __launch_bounds__(kBlock) void k_pcg_px(Batch a)
+// With `prelude` set it only serves cmode 3 (the p update that continues CG
+// after a reliable update); otherwise it serves cmodes 1 and 2.
+template <class V, class B>
+__global__ __launch_bounds__(kBlock) void k_pcg_px(B a, int prelude)
 {
     int j;
     SysDesc d;
@@ -527,7 +584,16 @@ __global__ __launch_bounds__(kBlock) void k_pcg_px(Batch a)
     const SysState *st = d.st;
     if (st->mixed != Vecs<V>::mixed) return;
     const int cm = st->cmode;
-    if (cm == 0) return;
+    if (cm == 0 || (cm == 3) != (prelude != 0)) return;
+    if (cm == 3) {
+        int rb, re;
+        row_range(d, j, rb, re);
+        const V beta = (V)st->beta;
+        V *__restrict__ p = Vecs<V>::p(d);
+        const V *__restrict__ z = Vecs<V>::z(d);
+        rows_unrolled(rb, re, [&](int i) { p[i] = fma(beta, p[i], z[i]); });
+        return;
+    }
     int rb, re;
     row_range(d, j, rb, re);
     const V alpha = (V)st->alpha;

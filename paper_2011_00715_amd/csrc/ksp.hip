@@ -30,6 +30,7 @@ void free_workspace(spk_mat *A)
     hipFree(w->p);
     hipFree(w->q);
     hipFree(w->x);
+    hipFree(w->b);
     hipFree(w->r32);
     hipFree(w->z32);
     hipFree(w->p32);
@@ -74,6 +75,7 @@ static int get_workspace(spk_mat *A, bool mixed, Workspace **out)
         SPK_TRY(dalloc(&w->p, A->n, w));
         SPK_TRY(dalloc(&w->q, A->n, w));
         SPK_TRY(dalloc(&w->x, A->n, w));
+        SPK_TRY(dalloc(&w->b, A->n, w));
         SPK_HIP(hipHostMalloc((void **)&w->pdesc, sizeof(SysDesc), hipHostMallocDefault));
         SPK_HIP(hipHostMalloc((void **)&w->pst, sizeof(SysState), hipHostMallocDefault));
         SPK_HIP(hipHostMalloc((void **)&w->pstatus, sizeof(int32_t) * 8, hipHostMallocDefault));
@@ -92,6 +94,7 @@ static int get_workspace(spk_mat *A, bool mixed, Workspace **out)
         d.val = A->val;
         d.dinv = A->dinv;
         d.x = w->x;
+        d.b = w->b;
         d.r = w->r;
         d.z = w->z;
         d.p = w->p;
@@ -119,33 +122,27 @@ static int get_workspace(spk_mat *A, bool mixed, Workspace **out)
     return SPK_OK;
 }
 
-static int upload_desc(Workspace *w, const double *b, bool with_hist, hipStream_t s)
-{
-    w->hdesc.b = b;
-    w->hdesc.hist = with_hist ? w->hist : nullptr;
-    *w->pdesc = w->hdesc;
-    SPK_HIP(hipMemcpyAsync(w->ddesc, w->pdesc, sizeof(SysDesc), hipMemcpyHostToDevice, s));
-    return SPK_OK;
-}
-
-static Batch batch_of(Workspace *w) { return Batch{w->ddesc, w->blk_start, 1}; }
+// Every pointer of the descriptor is owned by the workspace (b is copied in),
+// so the descriptor travels by value in the kernel arguments and captured
+// graphs stay valid from one solve to the next.
+static One batch_of(Workspace *w) { return One{w->hdesc}; }
 
 // r = b - A x for the handle's kernel family.
 static int launch_resid(spk_mat *A, Workspace *w, int purpose, bool gated, hipStream_t s)
 {
-    const Batch b = batch_of(w);
+    const One b = batch_of(w);
     const dim3 g(A->nblk), t(kBlock), one(1);
     if (A->kernel == SPK_KERNEL_STREAM) {
-        if (gated) hipLaunchKernelGGL(k_resid_stream<kGateResid>, g, t, 0, s, b);
-        else hipLaunchKernelGGL(k_resid_stream<kGateNone>, g, t, 0, s, b);
+        if (gated) hipLaunchKernelGGL((k_resid_stream<kGateResid, One>), g, t, 0, s, b);
+        else hipLaunchKernelGGL((k_resid_stream<kGateNone, One>), g, t, 0, s, b);
     } else {
         SPK_TRY(launch_spmv<double>(A, A->val, w->x, w->r, s, gated ? w->st : nullptr,
                                     gated ? kGateResid : kGateNone));
-        if (gated) hipLaunchKernelGGL(k_resid_combine<kGateResid>, g, t, 0, s, b);
-        else hipLaunchKernelGGL(k_resid_combine<kGateNone>, g, t, 0, s, b);
+        if (gated) hipLaunchKernelGGL((k_resid_combine<kGateResid, One>), g, t, 0, s, b);
+        else hipLaunchKernelGGL((k_resid_combine<kGateNone, One>), g, t, 0, s, b);
     }
-    if (gated) hipLaunchKernelGGL(k_fin_resid<kGateResid>, one, t, 0, s, b, purpose);
-    else hipLaunchKernelGGL(k_fin_resid<kGateNone>, one, t, 0, s, b, purpose);
+    if (gated) hipLaunchKernelGGL((k_fin_resid<kGateResid, One>), one, t, 0, s, b, purpose);
+    else hipLaunchKernelGGL((k_fin_resid<kGateNone, One>), one, t, 0, s, b, purpose);
     SPK_HIP(hipGetLastError());
     return SPK_OK;
 }
@@ -153,21 +150,21 @@ static int launch_resid(spk_mat *A, Workspace *w, int purpose, bool gated, hipSt
 template <class V>
 static int enqueue_iteration(spk_mat *A, Workspace *w, hipStream_t s)
 {
-    const Batch b = batch_of(w);
+    const One b = batch_of(w);
     const dim3 g(A->nblk), t(kBlock), one(1);
     if (A->kernel == SPK_KERNEL_STREAM) {
-        hipLaunchKernelGGL(k_pcg_spmv_stream<V>, g, t, 0, s, b);
+        hipLaunchKernelGGL((k_pcg_spmv_stream<V, One>), g, t, 0, s, b);
     } else {
         const V *val = std::is_same<V, double>::value ? (const V *)A->val : (const V *)A->val32;
         V *p = std::is_same<V, double>::value ? (V *)w->p : (V *)w->p32;
         V *q = std::is_same<V, double>::value ? (V *)w->q : (V *)w->q32;
         SPK_TRY(launch_spmv<V>(A, val, p, q, s, w->st, Vecs<V>::gate));
-        hipLaunchKernelGGL(k_pcg_pq<V>, g, t, 0, s, b);
+        hipLaunchKernelGGL((k_pcg_pq<V, One>), g, t, 0, s, b);
     }
-    hipLaunchKernelGGL(k_fin_pq<V>, one, t, 0, s, b);
-    hipLaunchKernelGGL(k_pcg_update<V>, g, t, 0, s, b);
-    hipLaunchKernelGGL(k_fin_update<V>, one, t, 0, s, b);
-    hipLaunchKernelGGL(k_pcg_px<V>, g, t, 0, s, b);
+    hipLaunchKernelGGL((k_fin_pq<V, One>), one, t, 0, s, b);
+    hipLaunchKernelGGL((k_pcg_update<V, One>), g, t, 0, s, b);
+    hipLaunchKernelGGL((k_fin_update<V, One>), one, t, 0, s, b);
+    hipLaunchKernelGGL((k_pcg_px<V, One>), g, t, 0, s, b, 0);
     SPK_HIP(hipGetLastError());
     return SPK_OK;
 }
@@ -176,11 +173,12 @@ static int enqueue_iteration(spk_mat *A, Workspace *w, hipStream_t s)
 static int enqueue_batch(spk_mat *A, Workspace *w, bool mixed, int K, hipStream_t s)
 {
     if (mixed) {
-        const Batch b = batch_of(w);
-        hipLaunchKernelGGL(k_update_x, dim3(A->nblk), dim3(kBlock), 0, s, b);
+        const One b = batch_of(w);
+        hipLaunchKernelGGL(k_update_x<One>, dim3(A->nblk), dim3(kBlock), 0, s, b);
         SPK_TRY(launch_resid(A, w, kResOuter, true, s));
-        hipLaunchKernelGGL(k_setup32, dim3(A->nblk), dim3(kBlock), 0, s, b);
-        hipLaunchKernelGGL(k_fin_setup32, dim3(1), dim3(kBlock), 0, s, b);
+        hipLaunchKernelGGL(k_setup32<One>, dim3(A->nblk), dim3(kBlock), 0, s, b);
+        hipLaunchKernelGGL(k_fin_setup32<One>, dim3(1), dim3(kBlock), 0, s, b);
+        hipLaunchKernelGGL((k_pcg_px<float, One>), dim3(A->nblk), dim3(kBlock), 0, s, b, 1);
         for (int k = 0; k < K; ++k) SPK_TRY(enqueue_iteration<float>(A, w, s));
     } else {
         for (int k = 0; k < K; ++k) SPK_TRY(enqueue_iteration<double>(A, w, s));
@@ -253,6 +251,14 @@ static int read_state(Workspace *w, hipStream_t s)
 
 static void fill_zero(double *p, int64_t n, hipStream_t s);
 
+// Inner tolerance of a mixed solve: a refinement is due once the FP32
+// residual fell by this factor since the last one.
+double inner_rtol_of(const spk_ksp_opts &o)
+{
+    if (o.inner_rtol > 0) return o.inner_rtol;
+    return o.precision == SPK_PREC_MIXED_IR ? 1e-4 : kRuDelta;
+}
+
 struct SolveOut {
     int reason = 0, iterations = 0, restarts = 0;
     double rnorm0 = 0, rnorm = 0, bnorm = 0, rnorm_true = 0;
@@ -268,8 +274,8 @@ static int solve64(spk_mat *A, Workspace *w, const spk_ksp_opts &o, bool x_given
     hipLaunchKernelGGL(k_state_init, dim3(1), dim3(64), 0, s, w->st, o.rtol, o.atol, o.maxit, 0,
                        o.inner_rtol, o.inner_maxit, o.max_outer, hist_len);
     SPK_TRY(launch_resid(A, w, kResSetup, false, s));
-    hipLaunchKernelGGL(k_setup64, dim3(A->nblk), dim3(kBlock), 0, s, batch_of(w));
-    hipLaunchKernelGGL(k_fin_setup64, dim3(1), dim3(kBlock), 0, s, batch_of(w));
+    hipLaunchKernelGGL(k_setup64<One>, dim3(A->nblk), dim3(kBlock), 0, s, batch_of(w));
+    hipLaunchKernelGGL(k_fin_setup64<One>, dim3(1), dim3(kBlock), 0, s, batch_of(w));
     SPK_HIP(hipGetLastError());
     int restarts = 0;
     for (;;) {
@@ -288,8 +294,8 @@ static int solve64(spk_mat *A, Workspace *w, const spk_ksp_opts &o, bool x_given
             }
             ++restarts;
             hipLaunchKernelGGL(k_state_restart, dim3(1), dim3(64), 0, s, w->st);
-            hipLaunchKernelGGL(k_setup64, dim3(A->nblk), dim3(kBlock), 0, s, batch_of(w));
-            hipLaunchKernelGGL(k_fin_setup64, dim3(1), dim3(kBlock), 0, s, batch_of(w));
+            hipLaunchKernelGGL(k_setup64<One>, dim3(A->nblk), dim3(kBlock), 0, s, batch_of(w));
+            hipLaunchKernelGGL(k_fin_setup64<One>, dim3(1), dim3(kBlock), 0, s, batch_of(w));
             SPK_HIP(hipGetLastError());
             continue;
         }
@@ -319,8 +325,8 @@ static int solve_mixed(spk_mat *A, Workspace *w, const spk_ksp_opts &o, int hist
 {
     const int K = o.graph_k > 0 ? o.graph_k : 8;
     const bool use_graph = o.graph_k > 0;
-    hipLaunchKernelGGL(k_state_init, dim3(1), dim3(64), 0, s, w->st, o.rtol, o.atol, o.maxit, 1,
-                       o.inner_rtol, o.inner_maxit, o.max_outer, hist_len);
+    hipLaunchKernelGGL(k_state_init, dim3(1), dim3(64), 0, s, w->st, o.rtol, o.atol, o.maxit,
+                       o.precision, inner_rtol_of(o), o.inner_maxit, o.max_outer, hist_len);
     SPK_HIP(hipGetLastError());
     const int max_batches = (o.maxit + K - 1) / K + 2 * (o.max_outer + 2);
     SPK_TRY(run_batches(A, w, true, K, use_graph, max_batches, s));
@@ -373,9 +379,9 @@ void spk_ksp_opts_default(spk_ksp_opts *o)
     o->precision = SPK_PREC_FP64;
     o->x0_nonzero = 0;
     o->graph_k = 8;
-    o->inner_rtol = 1e-4;
+    o->inner_rtol = 0.0;  // automatic: see inner_rtol_of()
     o->inner_maxit = 10000;
-    o->max_outer = 20;
+    o->max_outer = 100;
     o->hist = nullptr;
     o->hist_len = 0;
 }
@@ -391,8 +397,8 @@ int spk_ksp_solve(spk_mat *A, const double *b, double *x, const spk_ksp_opts *op
     else spk_ksp_opts_default(&o);
     if (A->n > 0 && (!b || !x)) { set_error("NULL b or x"); return SPK_EINVAL; }
     if (!(o.rtol >= 0) || !(o.atol >= 0) || o.maxit < 0 || o.graph_k < 0 || o.graph_k > 1024 ||
-        (o.precision != SPK_PREC_FP64 && o.precision != SPK_PREC_MIXED) || o.hist_len < 0 ||
-        (o.hist_len > 0 && !o.hist) || !(o.inner_rtol > 0) || o.inner_maxit < 1 || o.max_outer < 0) {
+        o.precision < SPK_PREC_FP64 || o.precision > SPK_PREC_MIXED_IR || o.hist_len < 0 ||
+        (o.hist_len > 0 && !o.hist) || !(o.inner_rtol >= 0 && o.inner_rtol < 1) || o.inner_maxit < 1 || o.max_outer < 0) {
         set_error("invalid solver options");
         return SPK_EINVAL;
     }
@@ -407,19 +413,24 @@ int spk_ksp_solve(spk_mat *A, const double *b, double *x, const spk_ksp_opts *op
         res->seconds = spk_now() - t0;
         return SPK_OK;
     }
-    const bool mixed = o.precision == SPK_PREC_MIXED;
+    const bool mixed = o.precision != SPK_PREC_FP64;
     if (mixed) SPK_TRY(ensure_f32(A, s));
     Workspace *w = nullptr;
     SPK_TRY(get_workspace(A, mixed, &w));
     if (o.hist_len > w->hist_cap) {
+        // the history buffer is part of the descriptor baked into the graphs
+        SPK_HIP(hipStreamSynchronize(s));
+        if (w->g64) { hipGraphExecDestroy(w->g64); w->g64 = nullptr; }
+        if (w->gmix) { hipGraphExecDestroy(w->gmix); w->gmix = nullptr; }
         if (w->hist) hipFree(w->hist);
         w->hist = nullptr;
         SPK_HIP(hipMalloc(&w->hist, sizeof(double) * o.hist_len));
+        w->bytes += 8 * (int64_t)(o.hist_len - w->hist_cap);
         w->hist_cap = o.hist_len;
-        w->bytes += 8 * (int64_t)o.hist_len;
+        w->hdesc.hist = w->hist;
     }
     if (w->hist && o.hist_len > 0) SPK_HIP(hipMemsetAsync(w->hist, 0xff, sizeof(double) * o.hist_len, s));
-    SPK_TRY(upload_desc(w, b, o.hist_len > 0, s));
+    SPK_HIP(hipMemcpyAsync(w->b, b, sizeof(double) * A->n, hipMemcpyDeviceToDevice, s));
     if (o.x0_nonzero) SPK_HIP(hipMemcpyAsync(w->x, x, sizeof(double) * A->n, hipMemcpyDeviceToDevice, s));
     else fill_zero(w->x, A->n, s);
     SPK_HIP(hipGetLastError());

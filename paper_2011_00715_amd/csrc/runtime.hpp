@@ -39,6 +39,7 @@ struct Workspace {
     double *partials = nullptr;
     double *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr;
     double *x = nullptr;          // the solve's iterate (copied in and out)
+    double *b = nullptr;          // the solve's right-hand side (copied in)
     float *r32 = nullptr, *z32 = nullptr, *p32 = nullptr, *q32 = nullptr, *d32 = nullptr;
     hipStream_t cap = nullptr;    // private stream used only to capture graphs
     hipGraphExec_t g64 = nullptr, gmix = nullptr;
@@ -84,6 +85,8 @@ int launch_spmv(const spk_mat *A, const V *val, const V *x, V *y, hipStream_t s,
                 const SysState *gate_st, int gate_mode);
 
 void update_info(spk_mat *A);
+constexpr double kRuDelta = 0.05;  // default refinement trigger with reliable updates
+double inner_rtol_of(const spk_ksp_opts &o);
 int ensure_f32(spk_mat *A, hipStream_t s);
 
 }  // namespace spk

@@ -181,23 +181,20 @@ static int upload(spk_server *S, void *dst, const void *src, size_t bytes)
     return SPK_OK;
 }
 
-static Batch slot_batch(spk_server *S, int k)
-{
-    return Batch{S->d_slotdesc + k, S->d_slotblk + 2 * k, 1};
-}
+static One slot_batch(spk_server *S, int k) { return One{S->slots[k].desc}; }
 
 // Start an FP64 solve of slot k from the x in its buffer (setup residual).
 static int start_fp64(spk_server *S, int k, const spk_ksp_opts &o, bool init_state)
 {
     Slot &sl = S->slots[k];
-    const Batch b = slot_batch(S, k);
+    const One b = slot_batch(S, k);
     if (init_state)
         hipLaunchKernelGGL(k_state_init, dim3(1), dim3(64), 0, S->s, sl.desc.st, o.rtol, o.atol,
                            o.maxit, 0, o.inner_rtol, o.inner_maxit, o.max_outer, 0);
-    hipLaunchKernelGGL(k_resid_stream<kGateNone>, dim3(sl.desc.nblk), dim3(kBlock), 0, S->s, b);
-    hipLaunchKernelGGL(k_fin_resid<kGateNone>, dim3(1), dim3(kBlock), 0, S->s, b, (int)kResSetup);
-    hipLaunchKernelGGL(k_setup64, dim3(sl.desc.nblk), dim3(kBlock), 0, S->s, b);
-    hipLaunchKernelGGL(k_fin_setup64, dim3(1), dim3(kBlock), 0, S->s, b);
+    hipLaunchKernelGGL((k_resid_stream<kGateNone, One>), dim3(sl.desc.nblk), dim3(kBlock), 0, S->s, b);
+    hipLaunchKernelGGL((k_fin_resid<kGateNone, One>), dim3(1), dim3(kBlock), 0, S->s, b, (int)kResSetup);
+    hipLaunchKernelGGL(k_setup64<One>, dim3(sl.desc.nblk), dim3(kBlock), 0, S->s, b);
+    hipLaunchKernelGGL(k_fin_setup64<One>, dim3(1), dim3(kBlock), 0, S->s, b);
     SPK_HIP(hipGetLastError());
     return SPK_OK;
 }
@@ -314,8 +311,8 @@ static int admit(spk_server *S, Request *q, int k, int64_t off)
     SPK_HIP(hipGetLastError());
     const spk_ksp_opts &o = q->opts;
     if (q->mixed) {
-        hipLaunchKernelGGL(k_state_init, dim3(1), dim3(64), 0, S->s, d.st, o.rtol, o.atol, o.maxit, 1,
-                           o.inner_rtol, o.inner_maxit, o.max_outer, 0);
+        hipLaunchKernelGGL(k_state_init, dim3(1), dim3(64), 0, S->s, d.st, o.rtol, o.atol, o.maxit,
+                           o.precision, inner_rtol_of(o), o.inner_maxit, o.max_outer, 0);
         SPK_HIP(hipGetLastError());
     } else {
         const int rc = start_fp64(S, k, o, true);
@@ -390,26 +387,27 @@ static int enqueue_step(spk_server *S)
     const dim3 g(S->nblocks), t(kBlock), f(S->nsys);
     const int K = S->o.graph_k > 0 ? S->o.graph_k : 8;
     if (S->n_mixed) {
-        hipLaunchKernelGGL(k_update_x, g, t, 0, S->s, b);
-        hipLaunchKernelGGL(k_resid_stream<kGateResid>, g, t, 0, S->s, b);
-        hipLaunchKernelGGL(k_fin_resid<kGateResid>, f, t, 0, S->s, b, (int)kResOuter);
-        hipLaunchKernelGGL(k_setup32, g, t, 0, S->s, b);
-        hipLaunchKernelGGL(k_fin_setup32, f, t, 0, S->s, b);
+        hipLaunchKernelGGL(k_update_x<Batch>, g, t, 0, S->s, b);
+        hipLaunchKernelGGL((k_resid_stream<kGateResid, Batch>), g, t, 0, S->s, b);
+        hipLaunchKernelGGL((k_fin_resid<kGateResid, Batch>), f, t, 0, S->s, b, (int)kResOuter);
+        hipLaunchKernelGGL(k_setup32<Batch>, g, t, 0, S->s, b);
+        hipLaunchKernelGGL(k_fin_setup32<Batch>, f, t, 0, S->s, b);
+        hipLaunchKernelGGL((k_pcg_px<float, Batch>), g, t, 0, S->s, b, 1);
     }
     for (int k = 0; k < K; ++k) {
         if (S->n_fp64) {
-            hipLaunchKernelGGL(k_pcg_spmv_stream<double>, g, t, 0, S->s, b);
-            hipLaunchKernelGGL(k_fin_pq<double>, f, t, 0, S->s, b);
-            hipLaunchKernelGGL(k_pcg_update<double>, g, t, 0, S->s, b);
-            hipLaunchKernelGGL(k_fin_update<double>, f, t, 0, S->s, b);
-            hipLaunchKernelGGL(k_pcg_px<double>, g, t, 0, S->s, b);
+            hipLaunchKernelGGL((k_pcg_spmv_stream<double, Batch>), g, t, 0, S->s, b);
+            hipLaunchKernelGGL((k_fin_pq<double, Batch>), f, t, 0, S->s, b);
+            hipLaunchKernelGGL((k_pcg_update<double, Batch>), g, t, 0, S->s, b);
+            hipLaunchKernelGGL((k_fin_update<double, Batch>), f, t, 0, S->s, b);
+            hipLaunchKernelGGL((k_pcg_px<double, Batch>), g, t, 0, S->s, b, 0);
         }
         if (S->n_mixed) {
-            hipLaunchKernelGGL(k_pcg_spmv_stream<float>, g, t, 0, S->s, b);
-            hipLaunchKernelGGL(k_fin_pq<float>, f, t, 0, S->s, b);
-            hipLaunchKernelGGL(k_pcg_update<float>, g, t, 0, S->s, b);
-            hipLaunchKernelGGL(k_fin_update<float>, f, t, 0, S->s, b);
-            hipLaunchKernelGGL(k_pcg_px<float>, g, t, 0, S->s, b);
+            hipLaunchKernelGGL((k_pcg_spmv_stream<float, Batch>), g, t, 0, S->s, b);
+            hipLaunchKernelGGL((k_fin_pq<float, Batch>), f, t, 0, S->s, b);
+            hipLaunchKernelGGL((k_pcg_update<float, Batch>), g, t, 0, S->s, b);
+            hipLaunchKernelGGL((k_fin_update<float, Batch>), f, t, 0, S->s, b);
+            hipLaunchKernelGGL((k_pcg_px<float, Batch>), g, t, 0, S->s, b, 0);
         }
     }
     SPK_HIP(hipGetLastError());
@@ -420,9 +418,9 @@ static int begin_retire(spk_server *S, int k)
 {
     Slot &sl = S->slots[k];
     Request *q = sl.req;
-    const Batch b = slot_batch(S, k);
-    hipLaunchKernelGGL(k_resid_stream<kGateNone>, dim3(sl.desc.nblk), dim3(kBlock), 0, S->s, b);
-    hipLaunchKernelGGL(k_fin_resid<kGateNone>, dim3(1), dim3(kBlock), 0, S->s, b, (int)kResTrue);
+    const One b = slot_batch(S, k);
+    hipLaunchKernelGGL((k_resid_stream<kGateNone, One>), dim3(sl.desc.nblk), dim3(kBlock), 0, S->s, b);
+    hipLaunchKernelGGL((k_fin_resid<kGateNone, One>), dim3(1), dim3(kBlock), 0, S->s, b, (int)kResTrue);
     SPK_HIP(hipGetLastError());
     if (sl.px_cap < q->n) {
         if (sl.px) hipHostFree(sl.px);
@@ -450,8 +448,8 @@ static int end_retire(spk_server *S, int k, const SysState &st)
         sl.restarts < 3) {
         ++sl.restarts;  // true residual drifted: restart from it
         hipLaunchKernelGGL(k_state_restart, dim3(1), dim3(64), 0, S->s, sl.desc.st);
-        hipLaunchKernelGGL(k_setup64, dim3(sl.desc.nblk), dim3(kBlock), 0, S->s, slot_batch(S, k));
-        hipLaunchKernelGGL(k_fin_setup64, dim3(1), dim3(kBlock), 0, S->s, slot_batch(S, k));
+        hipLaunchKernelGGL(k_setup64<One>, dim3(sl.desc.nblk), dim3(kBlock), 0, S->s, slot_batch(S, k));
+        hipLaunchKernelGGL(k_fin_setup64<One>, dim3(1), dim3(kBlock), 0, S->s, slot_batch(S, k));
         SPK_HIP(hipGetLastError());
         q->state = kActive;
         sl.first_step = S->step_id;
@@ -614,8 +612,8 @@ int spk_server_submit(spk_server *S, int32_t n, int64_t nnz, const int32_t *rowp
     spk_ksp_opts o;
     if (opts) o = *opts;
     else spk_ksp_opts_default(&o);
-    if (!(o.rtol >= 0) || !(o.atol >= 0) || o.maxit < 0 || !(o.inner_rtol > 0) || o.inner_maxit < 1 ||
-        o.max_outer < 0 || (o.precision != SPK_PREC_FP64 && o.precision != SPK_PREC_MIXED)) {
+    if (!(o.rtol >= 0) || !(o.atol >= 0) || o.maxit < 0 || !(o.inner_rtol >= 0 && o.inner_rtol < 1) || o.inner_maxit < 1 ||
+        o.max_outer < 0 || o.precision < SPK_PREC_FP64 || o.precision > SPK_PREC_MIXED_IR) {
         set_error("invalid solver options");
         return SPK_EINVAL;
     }
@@ -644,7 +642,7 @@ int spk_server_submit(spk_server *S, int32_t n, int64_t nnz, const int32_t *rowp
     q->n = n;
     q->nnz = nnz;
     q->opts = o;
-    q->mixed = o.precision == SPK_PREC_MIXED;
+    q->mixed = o.precision != SPK_PREC_FP64;
     q->R = 8;
     for (int t = 0; t < 6; ++t)
         if (maxtile[t] <= TileLds<double>::kCap) { q->R = kTileRs[t]; break; }

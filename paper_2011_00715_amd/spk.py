@@ -33,7 +33,7 @@ dbl = ctypes.c_double
 
 # ------------------------------------------------------------------ constants
 MEM_HOST, MEM_DEVICE = 0, 1
-PREC_FP64, PREC_MIXED = 0, 1
+PREC_FP64, PREC_MIXED, PREC_MIXED_IR = 0, 1, 2
 MAT_MIXED, MAT_VALIDATE, MAT_BORROW = 1, 2, 4
 KERNEL_AUTO, KERNEL_STREAM, KERNEL_VECTOR, KERNEL_MERGE = 0, 1, 2, 3
 KERNEL_NAMES = {1: "stream", 2: "vector", 3: "merge"}

@@ -136,13 +136,19 @@ def test_pcg_true_residual_restart_rule():
 
 
 @pytest.mark.parametrize("case", ["lap2d_64", "diff27_14", "powerlaw_20k"])
-def test_pcg_mixed_precision(case):
+@pytest.mark.parametrize("mode", ["mixed", "mixed_ir"])
+def test_pcg_mixed_precision(case, mode):
     spk = need_gpu()
     name, A, seed = [c for c in _cases() if c[0] == case][0]
     M = mat_on_gpu(spk, A, flags=spk.MAT_MIXED)
     b = spkgen.rhs_uniform(A.n, seed)
-    x, res, hist = _solve(spk, M, b, precision=spk.PREC_MIXED)
+    prec = spk.PREC_MIXED if mode == "mixed" else spk.PREC_MIXED_IR
+    x, res, hist = _solve(spk, M, b, precision=prec)
     assert res.reason == spk.CONVERGED_RTOL, res.as_dict()
+    assert res.fallback_fp64 == 0
+    if mode == "mixed":  # reliable updates keep CG's iteration count close to FP64's
+        _, ro, _ = oracle.pcg(A, b, rtol=1e-8)
+        assert res.inner_iterations <= 1.25 * ro["iterations"] + 10, (res.inner_iterations, ro["iterations"])
     assert res.outer_steps >= 1 and res.inner_iterations > 0
     r = b - oracle.spmv(A, x)
     rel = oracle.nrm2(r) / oracle.nrm2(b)
