@@ -243,6 +243,8 @@ typedef struct {
     int32_t graph_k;           /* iterations per batched step (default 8) */
     int32_t max_blocks_per_system;  /* default 256 */
     int32_t pad_;
+    int64_t pinned_bytes;      /* pinned host pool for submitted systems
+                                  (default 1 GiB; 0 = pageable staging only) */
 } spk_server_opts;
 
 void spk_server_opts_default(spk_server_opts *o);

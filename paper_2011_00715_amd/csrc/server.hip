@@ -31,6 +31,12 @@ struct Request {
     uint64_t ticket = 0;
     int32_t n = 0;
     int64_t nnz = 0;
+    // host copy of the system: in the pinned pool when it has room (the
+    // upload is then a plain DMA), otherwise in pageable vectors that go
+    // through the staging buffers
+    int64_t pin_off = -1, pin_len = 0;
+    int32_t *h_rowptr = nullptr, *h_col = nullptr;
+    double *h_val = nullptr, *h_b = nullptr;
     std::vector<int32_t> rowptr, col;
     std::vector<double> val, b;
     spk_ksp_opts opts{};
@@ -99,6 +105,8 @@ struct Slot {
     int64_t px_cap = 0;
     hipEvent_t ev = nullptr;
     int64_t first_step = 0;  // first batched step that includes this system
+    hipEvent_t ev_up = nullptr;      // upload from the pinned pool done
+    int64_t pin_off = -1, pin_len = 0;  // pinned block to release after ev_up
 };
 
 #define SPK_TRY_RC(x)                  \
@@ -146,6 +154,8 @@ struct spk_server {
     char *stage[2] = {nullptr, nullptr};
     hipEvent_t ev_stage[2] = {nullptr, nullptr};
     int stage_i = 0;
+    char *pin_base = nullptr;                 // pinned pool for submitted systems
+    Arena pin_arena;
     std::deque<Request *> queue;
     std::map<uint64_t, Request *> tickets;
     uint64_t next_ticket = 1;
@@ -288,10 +298,21 @@ static int admit(spk_server *S, Request *q, int k, int64_t off)
     d.hist = nullptr;
     // uploads run on the copy stream and overlap the batched steps already
     // queued on the compute stream; the compute stream waits for them
-    SPK_TRY_RC(upload(S, rowptr, q->rowptr.data(), 4 * (n + 1)));
-    if (nz) SPK_TRY_RC(upload(S, col, q->col.data(), 4 * nz));
-    if (nz) SPK_TRY_RC(upload(S, val, q->val.data(), 8 * nz));
-    SPK_TRY_RC(upload(S, b, q->b.data(), 8 * n));
+    if (q->pin_off >= 0) {
+        SPK_HIP(hipMemcpyAsync(rowptr, q->h_rowptr, 4 * (n + 1), hipMemcpyHostToDevice, S->cs));
+        if (nz) SPK_HIP(hipMemcpyAsync(col, q->h_col, 4 * nz, hipMemcpyHostToDevice, S->cs));
+        if (nz) SPK_HIP(hipMemcpyAsync(val, q->h_val, 8 * nz, hipMemcpyHostToDevice, S->cs));
+        SPK_HIP(hipMemcpyAsync(b, q->h_b, 8 * n, hipMemcpyHostToDevice, S->cs));
+        SPK_HIP(hipEventRecord(sl.ev_up, S->cs));
+        sl.pin_off = q->pin_off;  // released once ev_up has completed
+        sl.pin_len = q->pin_len;
+        q->pin_off = -1;
+    } else {
+        SPK_TRY_RC(upload(S, rowptr, q->h_rowptr, 4 * (n + 1)));
+        if (nz) SPK_TRY_RC(upload(S, col, q->h_col, 4 * nz));
+        if (nz) SPK_TRY_RC(upload(S, val, q->h_val, 8 * nz));
+        SPK_TRY_RC(upload(S, b, q->h_b, 8 * n));
+    }
     // per-slot descriptor and block table for the single-system launches (the
     // pinned source of slot k is only rewritten after its previous occupant
     // retired, i.e. after this copy of the previous admission completed)
@@ -321,9 +342,14 @@ static int admit(spk_server *S, Request *q, int k, int64_t off)
     q->state = kActive;
     q->slot = k;
     sl.first_step = S->step_id;
-    // host copies are no longer needed once the staging buffers are drained
-    SPK_HIP(hipEventSynchronize(S->ev_stage[0]));
-    SPK_HIP(hipEventSynchronize(S->ev_stage[1]));
+    // pageable host copies are no longer needed once the staging buffers are
+    // drained (pinned blocks are released in progress when ev_up completes)
+    if (!q->rowptr.empty()) {
+        SPK_HIP(hipEventSynchronize(S->ev_stage[0]));
+        SPK_HIP(hipEventSynchronize(S->ev_stage[1]));
+    }
+    q->h_rowptr = q->h_col = nullptr;
+    q->h_val = q->h_b = nullptr;
     std::vector<int32_t>().swap(q->rowptr);
     std::vector<int32_t>().swap(q->col);
     std::vector<double>().swap(q->val);
@@ -535,6 +561,7 @@ void spk_server_opts_default(spk_server_opts *o)
     o->max_slots = 64;
     o->graph_k = 8;
     o->max_blocks_per_system = 256;
+    o->pinned_bytes = 1ll << 30;
 }
 
 int spk_server_destroy(spk_server *S);
@@ -547,7 +574,8 @@ int spk_server_create(const spk_server_opts *opts, void *stream, spk_server **ou
     if (opts) o = *opts;
     else spk_server_opts_default(&o);
     if (o.hbm_budget_bytes < (1 << 20) || o.max_slots < 1 || o.max_slots > 4096 || o.graph_k < 1 ||
-        o.graph_k > 256 || o.max_blocks_per_system < 1 || o.max_blocks_per_system > 8192) {
+        o.graph_k > 256 || o.max_blocks_per_system < 1 || o.max_blocks_per_system > 8192 ||
+        o.pinned_bytes < 0) {
         set_error("invalid server options");
         return SPK_EINVAL;
     }
@@ -585,7 +613,17 @@ int spk_server_create(const spk_server_opts *opts, void *stream, spk_server **ou
         chk(hipHostMalloc((void **)&S->p_blk[i], sizeof(int32_t) * (ms + 1), hipHostMallocDefault), "pinned blocks");
         chk(hipEventCreateWithFlags(&S->ev_table[i], hipEventDisableTiming), "event");
     }
-    for (auto &sl : S->slots) chk(hipEventCreateWithFlags(&sl.ev, hipEventDisableTiming), "event");
+    for (auto &sl : S->slots) {
+        chk(hipEventCreateWithFlags(&sl.ev, hipEventDisableTiming), "event");
+        chk(hipEventCreateWithFlags(&sl.ev_up, hipEventDisableTiming), "event");
+    }
+    if (o.pinned_bytes > 0 && rc == SPK_OK) {
+        // best effort: without the pool, submissions use pageable memory
+        if (hipHostMalloc((void **)&S->pin_base, o.pinned_bytes, hipHostMallocDefault) == hipSuccess)
+            S->pin_arena.init(o.pinned_bytes);
+        else
+            S->pin_base = nullptr;
+    }
     if (rc == SPK_OK) {
         for (int i = 0; i < kTableRing; ++i) chk(hipEventRecord(S->ev_table[i], S->s), "event record");
         for (int i = 0; i < 2; ++i) chk(hipEventRecord(S->ev_stage[i], S->cs), "event record");
@@ -622,18 +660,9 @@ int spk_server_submit(spk_server *S, int32_t n, int64_t nnz, const int32_t *rowp
         set_error("rowptr[0] must be 0 and rowptr[n] = nnz");
         return SPK_EINVAL;
     }
+    for (int32_t i = 0; i < n; ++i)
+        if (rowptr[i + 1] < rowptr[i]) { set_error("rowptr not monotone at row %d", i); return SPK_EINVAL; }
     int64_t maxtile[6] = {0, 0, 0, 0, 0, 0};
-    for (int32_t i = 0; i < n; ++i) {
-        const int32_t a = rowptr[i], e = rowptr[i + 1];
-        if (e < a || e > nnz) { set_error("rowptr not monotone at row %d", i); return SPK_EINVAL; }
-        double d = 0.0;
-        for (int32_t k = a; k < e; ++k) {
-            const int32_t c = colind[k];
-            if (c < 0 || c >= n) { set_error("column %d out of range in row %d", c, i); return SPK_EINVAL; }
-            if (c == i) d += values[k];
-        }
-        if (d == 0.0) { set_error("row %d has no stored or a zero diagonal", i); return SPK_EZERODIAG; }
-    }
     for (int t = 0; t < 6; ++t)
         for (int64_t r0 = 0; r0 < n; r0 += kTileRs[t])
             maxtile[t] = std::max<int64_t>(maxtile[t], rowptr[std::min<int64_t>(r0 + kTileRs[t], n)] - rowptr[r0]);
@@ -655,16 +684,72 @@ int spk_server_submit(spk_server *S, int32_t n, int64_t nnz, const int32_t *rowp
         delete q;
         return SPK_EBUDGET;
     }
+    // host copy: pinned pool if it has room, else pageable memory
+    const int64_t hb = align256(4 * ((int64_t)n + 1)) + align256(4 * nnz) + align256(8 * nnz) +
+                       align256(8 * (int64_t)n);
+    int64_t off = -1;
+    if (S->pin_base) {
+        std::lock_guard<std::mutex> lk(S->mu);
+        off = S->pin_arena.alloc(hb);
+    }
     try {
-        q->rowptr.assign(rowptr, rowptr + n + 1);
-        q->col.assign(colind, colind + nnz);
-        q->val.assign(values, values + nnz);
-        q->b.assign(b, b + n);
+        if (off >= 0) {
+            q->pin_off = off;
+            q->pin_len = hb;
+            char *p = S->pin_base + off;
+            q->h_rowptr = (int32_t *)p;
+            p += align256(4 * ((int64_t)n + 1));
+            q->h_col = (int32_t *)p;
+            p += align256(4 * nnz);
+            q->h_val = (double *)p;
+            p += align256(8 * nnz);
+            q->h_b = (double *)p;
+        } else {
+            q->rowptr.resize((size_t)n + 1);
+            q->col.resize((size_t)nnz);
+            q->val.resize((size_t)nnz);
+            q->b.resize((size_t)n);
+            q->h_rowptr = q->rowptr.data();
+            q->h_col = q->col.data();
+            q->h_val = q->val.data();
+            q->h_b = q->b.data();
+        }
     } catch (...) {
         delete q;
         set_error("out of host memory");
         return SPK_ENOMEM;
     }
+    // one pass over the nonzeros: copy, check the columns, find the diagonal
+    int rc = SPK_OK;
+    memcpy(q->h_rowptr, rowptr, sizeof(int32_t) * ((size_t)n + 1));
+    for (int32_t i = 0; i < n && rc == SPK_OK; ++i) {
+        double d = 0.0;
+        for (int32_t k = rowptr[i]; k < rowptr[i + 1]; ++k) {
+            const int32_t c = colind[k];
+            const double v = values[k];
+            if (c < 0 || c >= n) {
+                set_error("column %d out of range in row %d", c, i);
+                rc = SPK_EINVAL;
+                break;
+            }
+            q->h_col[k] = c;
+            q->h_val[k] = v;
+            if (c == i) d += v;
+        }
+        if (rc == SPK_OK && d == 0.0) {
+            set_error("row %d has no stored or a zero diagonal", i);
+            rc = SPK_EZERODIAG;
+        }
+    }
+    if (rc != SPK_OK) {
+        if (q->pin_off >= 0) {
+            std::lock_guard<std::mutex> lk(S->mu);
+            S->pin_arena.release(q->pin_off, q->pin_len);
+        }
+        delete q;
+        return rc;
+    }
+    memcpy(q->h_b, b, sizeof(double) * (size_t)n);
     q->t_submit = spk_now();
     std::lock_guard<std::mutex> lk(S->mu);
     q->ticket = S->next_ticket++;
@@ -680,9 +765,19 @@ int spk_server_progress(spk_server *S, int32_t max_steps)
     std::lock_guard<std::mutex> lk(S->mu);
     constexpr int kDepth = 2;
     for (int step = 0; step <= max_steps; ++step) {
-        // finish retirements whose copies have landed
         for (int k = 0; k < (int)S->slots.size(); ++k) {
             Slot &sl = S->slots[k];
+            // return pinned host blocks whose upload has completed
+            if (sl.pin_off >= 0) {
+                const hipError_t e = hipEventQuery(sl.ev_up);
+                if (e == hipSuccess) {
+                    S->pin_arena.release(sl.pin_off, sl.pin_len);
+                    sl.pin_off = -1;
+                } else if (e != hipErrorNotReady) {
+                    return hip_fail(e, "upload event", __FILE__, __LINE__);
+                }
+            }
+            // finish retirements whose copies have landed
             if (!sl.req || sl.req->state != kRetiring) continue;
             const hipError_t e = hipEventQuery(sl.ev);
             if (e == hipErrorNotReady) continue;
@@ -749,6 +844,7 @@ int spk_server_destroy(spk_server *S)
     for (auto &sl : S->slots) {
         if (sl.px) hipHostFree(sl.px);
         if (sl.ev) hipEventDestroy(sl.ev);
+        if (sl.ev_up) hipEventDestroy(sl.ev_up);
     }
     for (int i = 0; i < 2; ++i) {
         hipHostFree(S->p_states[i]);
@@ -767,6 +863,7 @@ int spk_server_destroy(spk_server *S)
     if (S->ev_up) hipEventDestroy(S->ev_up);
     if (S->cs) hipStreamDestroy(S->cs);
     hipFree(S->arena_base);
+    if (S->pin_base) hipHostFree(S->pin_base);
     hipFree(S->d_states);
     hipFree(S->d_slotdesc);
     hipFree(S->d_slotblk);

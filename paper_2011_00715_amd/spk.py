@@ -80,7 +80,7 @@ class KspResult(ctypes.Structure):
 class ServerOpts(ctypes.Structure):
     _fields_ = [
         ("hbm_budget_bytes", i64), ("max_slots", i32), ("graph_k", i32),
-        ("max_blocks_per_system", i32), ("pad_", i32),
+        ("max_blocks_per_system", i32), ("pad_", i32), ("pinned_bytes", i64),
     ]
 
 

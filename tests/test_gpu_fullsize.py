@@ -1,0 +1,152 @@
+"""Parity at the configurations' full sizes, in the launch configuration the
+bench times: SpMV checked on sampled rows the oracle computes one by one,
+solves checked through the oracle's own true residual of the GPU solution and
+its FP64 iteration counts."""
+
+import numpy as np
+import pytest
+
+import oracle
+import spkgen
+from gpu_util import mat_on_gpu, need_gpu, to_dev
+
+pytestmark = [pytest.mark.gpu, pytest.mark.slow]
+
+ROWS = 4096
+
+
+def _sample_rows(n, seed=0):
+    rows = np.random.default_rng(seed).integers(0, n, ROWS)
+    return np.unique(np.concatenate([rows, [0, n - 1]]))
+
+
+def _spmv_sampled(spk, M, A, x, rows, tol=1e-14):
+    import torch
+
+    y = torch.empty(A.n, dtype=torch.float64, device="cuda")
+    spk.mat_mult(M, to_dev(x), y)
+    yg = y.cpu().numpy()[rows]
+    yo, ya = oracle.spmv_rows(A, x, rows)
+    assert np.all(np.abs(yg - yo) <= tol * ya), float(np.max(np.abs(yg - yo) / ya))
+    return yg, yo
+
+
+def _solve(spk, M, b, **kw):
+    import torch
+
+    x = torch.zeros(M.n, dtype=torch.float64, device="cuda")
+    res = spk.ksp_solve(M, to_dev(b), x, spk.ksp_opts(**kw))
+    return x.cpu().numpy(), res
+
+
+@pytest.mark.parametrize("seed", range(5))
+def test_c1_all_seeds(seed):
+    spk = need_gpu()
+    A = spkgen.laplace2d5(64)
+    M = mat_on_gpu(spk, A)
+    b = spkgen.rhs_uniform(A.n, seed)
+    x, res = _solve(spk, M, b)
+    _, ro, _ = oracle.pcg(A, b)
+    assert res.reason == spk.CONVERGED_RTOL
+    assert abs(res.iterations - ro["iterations"]) <= 2
+    assert oracle.nrm2(b - oracle.spmv(A, x)) <= 1e-8 * oracle.nrm2(b) * (1 + 1e-6)
+
+
+def test_c2_spmv_and_pcg():
+    spk = need_gpu()
+    A = spkgen.laplace3d7(128)
+    assert (A.n, A.nnz) == (2097152, 14581760)
+    M = mat_on_gpu(spk, A, flags=spk.MAT_MIXED)
+    assert spk.KERNEL_NAMES[M.info.kernel] == "stream" and M.info.lanes == 256
+    rows = _sample_rows(A.n)
+    # bit-exact on integer data, 1e-14 on the bench's x (rhs of seed 0)
+    xi = np.random.default_rng(3).integers(-100, 100, A.n).astype(np.float64)
+    yg, yo = _spmv_sampled(spk, M, A, xi, rows, tol=0.0)
+    assert np.array_equal(yg, yo)
+    b = spkgen.rhs_uniform(A.n, 0)
+    _spmv_sampled(spk, M, A, b, rows)
+    x64, r64 = _solve(spk, M, b)
+    xo, ro, ho = oracle.pcg(A, b, hist_len=40)
+    assert r64.reason == spk.CONVERGED_RTOL
+    assert abs(r64.iterations - ro["iterations"]) <= max(2, 0.01 * ro["iterations"])
+    bn = oracle.nrm2(b)
+    assert oracle.nrm2(b - oracle.spmv(A, x64)) <= 1e-8 * bn * (1 + 1e-6)
+    assert np.linalg.norm(x64 - xo) <= 1e-5 * np.linalg.norm(xo)
+    xm, rm = _solve(spk, M, b, precision=spk.PREC_MIXED)
+    assert rm.reason == spk.CONVERGED_RTOL and rm.fallback_fp64 == 0
+    assert oracle.nrm2(b - oracle.spmv(A, xm)) <= 1e-8 * bn * (1 + 1e-6)
+    assert rm.inner_iterations <= 1.1 * ro["iterations"]
+
+
+def test_c3_fp64_and_mixed():
+    spk = need_gpu()
+    A = spkgen.diffusion3d27_lognormal(160, seed=0)
+    assert (A.n, A.nnz) == (4096000, 109215352)
+    M = mat_on_gpu(spk, A, flags=spk.MAT_MIXED)
+    assert spk.KERNEL_NAMES[M.info.kernel] == "stream"
+    b = spkgen.rhs_uniform(A.n, 0)
+    _spmv_sampled(spk, M, A, b, _sample_rows(A.n, 1))
+    bn = oracle.nrm2(b)
+    x64, r64 = _solve(spk, M, b)
+    xm, rm = _solve(spk, M, b, precision=spk.PREC_MIXED)
+    for x, r in ((x64, r64), (xm, rm)):
+        assert r.reason == spk.CONVERGED_RTOL
+        assert oracle.nrm2(b - oracle.spmv(A, x)) <= 1e-8 * bn * (1 + 1e-6)
+    assert rm.inner_iterations <= 1.1 * r64.iterations
+    assert np.linalg.norm(xm - x64) <= 1e-5 * np.linalg.norm(x64)
+
+
+def test_c4_powerlaw_spmv_all_kernels():
+    spk = need_gpu()
+    import torch
+
+    A = spkgen.powerlaw_spd(4_000_000, seed=0)
+    M = mat_on_gpu(spk, A, flags=spk.MAT_MIXED)
+    assert spk.KERNEL_NAMES[M.info.kernel] == "merge"
+    assert M.info.row_max == A.row_lengths().max()
+    rows = _sample_rows(A.n, 2)
+    x = spkgen.rhs_uniform(A.n, 0)
+    _spmv_sampled(spk, M, A, x, rows)  # the selected kernel meets 1e-14
+    for k, p, tol in ((spk.KERNEL_VECTOR, 32, 1e-14), (spk.KERNEL_VECTOR, 64, 1e-14)):
+        spk.mat_set_kernel(M, k, p)
+        _spmv_sampled(spk, M, A, x, rows, tol)
+    # FP32 values: per-row bound of the merge order in FP32
+    spk.mat_set_kernel(M, spk.KERNEL_MERGE, 0)
+    x32 = x.astype(np.float32)
+    y32 = torch.empty(A.n, dtype=torch.float32, device="cuda")
+    spk.mat_mult_f32(M, to_dev(x32), y32)
+    v32 = A.val.astype(np.float32)
+    Af = spkgen.CSR(A.n, A.rowptr, A.col, v32.astype(np.float64))
+    yo, ya = oracle.spmv_rows(Af, x32.astype(np.float64), rows)
+    err = np.abs(y32.cpu().numpy()[rows].astype(np.float64) - yo)
+    assert np.all(err <= 30 * 2.0 ** -24 * ya)
+
+
+def test_c5_served_requests_full_sizes():
+    """The first 16 requests of the seed-0 stream at their real sizes."""
+    spk = need_gpu()
+    reqs = spkgen.serve_stream(seed=0, count=16)
+    S = spk.server_create()
+    o = spk.ksp_opts(precision=spk.PREC_MIXED)
+    items = []
+    for r in reqs:
+        A = spkgen.serve_matrix(r)
+        b = spkgen.rhs_uniform(A.n, r.rhs_seed % (2**31))
+        items.append((A, b, spk.server_submit(S, A.rowptr, A.col, A.val, b, o)))
+    done = {}
+    for _ in range(100000):
+        spk.server_progress(S, 4)
+        for A, b, t in items:
+            if t not in done:
+                x = np.empty(A.n)
+                got = spk.server_poll(S, t, x)
+                if got is not None:
+                    done[t] = (x, got[0])
+        if len(done) == len(items):
+            break
+    assert len(done) == len(items)
+    for A, b, t in items:
+        x, res = done[t]
+        assert res.reason == spk.CONVERGED_RTOL
+        assert oracle.nrm2(b - oracle.spmv(A, x)) <= 1e-8 * oracle.nrm2(b) * (1 + 1e-6)
+    S.close()
