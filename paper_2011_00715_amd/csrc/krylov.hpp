@@ -10,10 +10,11 @@
 //
 // One PCG iteration (textbook preconditioned CG; the paper names CG in
 // Sec. 5.5 and the Jacobi smoother in Sec. 5.3):
-//   A   q = A p, per-block p.q           F_A  eta = p.q, alpha = rho / eta
-//   B   r -= alpha q, z = D^-1 r,        F_B  convergence test, beta, and
-//       per-block r.z and r.r (one pass,      what C must do next
-//       Sec. 4 Response F3: fused inner products)
+//   A   q = A p, per-block p.q
+//   B   eta = p.q and alpha = rho / eta    F_B  breakdown and convergence
+//       (each block sums A's partials),         tests, beta, and what C
+//       r -= alpha q, z = D^-1 r, per-block     must do next
+//       r.z and r.r (one pass; Sec. 4 Response F3: fused inner products)
 //   C   x += alpha p, p = z + beta p
 // Scalars live on the device and every kernel is a no-op once its system has
 // stopped, so a captured graph of many iterations replays without host round
@@ -474,28 +475,10 @@ __global__ __launch_bounds__(kBlock) void k_pcg_pq(B a)
     if (threadIdx.x == 0) d.partials[kPartPq * d.nblk + j] = blk;
 }
 
-// F_A: eta = p.q, alpha = rho / eta.
-template <class V, class B>
-__global__ __launch_bounds__(kBlock) void k_fin_pq(B a)
-{
-    __shared__ double red[kBlock / kWave];
-    SysDesc d;
-    if (!fin_locate(a, d)) return;
-    SysState *st = d.st;
-    if (!gate_open(st, Vecs<V>::gate)) return;
-    const double eta = reduce_partials(d.partials + kPartPq * d.nblk, d.nblk, red);
-    if (threadIdx.x != 0) return;
-    st->eta = eta;
-    if (!finite(eta)) st->status = SPK_DIVERGED_NANORINF;
-    else if (eta <= 0.0) {
-        if (st->mixed) {  // inner breakdown: refine from here with a fresh p
-            st->phase = kPhaseUpdate;
-            st->fresh_p = 1;
-        } else st->status = SPK_DIVERGED_INDEFINITE_MAT;
-    } else st->alpha = st->rho / eta;
-}
-
-// B: r -= alpha q, z = D^-1 r, per-block r.z and r.r.
+// B: eta = p.q and alpha = rho / eta (every block sums the p.q partials
+// itself, in the same fixed order, so all blocks hold the same bits), then
+// r -= alpha q, z = D^-1 r, per-block r.z and r.r.  With eta <= 0 or not
+// finite the block changes nothing; F_B records the reason.
 template <class V, class B>
 __global__ __launch_bounds__(kBlock) void k_pcg_update(B a)
 {
@@ -505,9 +488,11 @@ __global__ __launch_bounds__(kBlock) void k_pcg_update(B a)
     if (!locate(a, j, d)) return;
     const SysState *st = d.st;
     if (!gate_open(st, Vecs<V>::gate)) return;
+    const double eta = reduce_partials(d.partials + kPartPq * d.nblk, d.nblk, red);
+    if (!(eta > 0.0) || !finite(eta)) return;
     int rb, re;
     row_range(d, j, rb, re);
-    const V nalpha = (V)(-st->alpha);
+    const V nalpha = (V)(-(st->rho / eta));
     V *__restrict__ r = Vecs<V>::r(d);
     V *__restrict__ z = Vecs<V>::z(d);
     const V *__restrict__ q = Vecs<V>::q(d);
@@ -544,10 +529,22 @@ __global__ __launch_bounds__(kBlock) void k_fin_update(B a)
         if (threadIdx.x == 0) st->cmode = 0;
         return;
     }
+    const double eta = reduce_partials(d.partials + kPartPq * d.nblk, d.nblk, red);
     double RZ, RR;
     reduce_partials2(d.partials + kPartRz * d.nblk, d.partials + kPartRr * d.nblk, d.nblk, red,
                      RZ, RR);
     if (threadIdx.x != 0) return;
+    st->eta = eta;
+    st->cmode = 0;
+    if (!finite(eta)) { st->status = SPK_DIVERGED_NANORINF; return; }
+    if (eta <= 0.0) {
+        if (st->mixed) {  // inner breakdown: refine from here with a fresh p
+            st->phase = kPhaseUpdate;
+            st->fresh_p = 1;
+        } else st->status = SPK_DIVERGED_INDEFINITE_MAT;
+        return;
+    }
+    st->alpha = st->rho / eta;
     const int k = ++st->iter;
     const double rn = sqrt(RR);
     st->cmode = 1;  // stop unless the tests below continue

@@ -161,7 +161,6 @@ static int enqueue_iteration(spk_mat *A, Workspace *w, hipStream_t s)
         SPK_TRY(launch_spmv<V>(A, val, p, q, s, w->st, Vecs<V>::gate));
         hipLaunchKernelGGL((k_pcg_pq<V, One>), g, t, 0, s, b);
     }
-    hipLaunchKernelGGL((k_fin_pq<V, One>), one, t, 0, s, b);
     hipLaunchKernelGGL((k_pcg_update<V, One>), g, t, 0, s, b);
     hipLaunchKernelGGL((k_fin_update<V, One>), one, t, 0, s, b);
     hipLaunchKernelGGL((k_pcg_px<V, One>), g, t, 0, s, b, 0);

@@ -423,14 +423,12 @@ static int enqueue_step(spk_server *S)
     for (int k = 0; k < K; ++k) {
         if (S->n_fp64) {
             hipLaunchKernelGGL((k_pcg_spmv_stream<double, Batch>), g, t, 0, S->s, b);
-            hipLaunchKernelGGL((k_fin_pq<double, Batch>), f, t, 0, S->s, b);
             hipLaunchKernelGGL((k_pcg_update<double, Batch>), g, t, 0, S->s, b);
             hipLaunchKernelGGL((k_fin_update<double, Batch>), f, t, 0, S->s, b);
             hipLaunchKernelGGL((k_pcg_px<double, Batch>), g, t, 0, S->s, b, 0);
         }
         if (S->n_mixed) {
             hipLaunchKernelGGL((k_pcg_spmv_stream<float, Batch>), g, t, 0, S->s, b);
-            hipLaunchKernelGGL((k_fin_pq<float, Batch>), f, t, 0, S->s, b);
             hipLaunchKernelGGL((k_pcg_update<float, Batch>), g, t, 0, S->s, b);
             hipLaunchKernelGGL((k_fin_update<float, Batch>), f, t, 0, S->s, b);
             hipLaunchKernelGGL((k_pcg_px<float, Batch>), g, t, 0, S->s, b, 0);
