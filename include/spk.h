@@ -71,8 +71,12 @@ enum {
                                streams staged through LDS, short rows */
     SPK_KERNEL_VECTOR = 2,  /* L lanes per row (L = 64: one row per wavefront),
                                wavefront-shuffle reduction */
-    SPK_KERNEL_MERGE = 3    /* merge-path over rows + nonzeros, equal work per
+    SPK_KERNEL_MERGE = 3,   /* merge-path over rows + nonzeros, equal work per
                                tile, deterministic carry fix-up */
+    SPK_KERNEL_SELL = 4     /* sliced ELLPACK, 64-row slices (one per
+                               wavefront), row-relative int16 column offsets
+                               when they fit (10 instead of 12 bytes per FP64
+                               nonzero); built from the CSR at selection */
 };
 
 /* status codes */
@@ -120,6 +124,13 @@ typedef struct {
     int64_t device_bytes;    /* device memory held by the handle */
     int32_t zero_diag_rows;  /* rows without a nonzero diagonal */
     int32_t pad_;
+    int64_t format_bytes_spmv_f64;  /* algorithmic bytes of one FP64 SpMV in the
+                                       storage the selected kernel reads (equal
+                                       to bytes_spmv_f64 except for SELL:
+                                       (8 + w) padded_nnz + 4 slices + n + 16 n,
+                                       w = 2 or 4 bytes per column offset) */
+    int64_t format_bytes_spmv_f32;  /* same for FP32 values and vectors */
+    int64_t stored_nnz;             /* entries the kernel reads, padding included */
 } spk_mat_info;
 
 /*

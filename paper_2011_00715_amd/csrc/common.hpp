@@ -78,6 +78,13 @@ struct SysDesc {
     double *partials;                 // kNumPart * nblk
     SysState *st;
     double *hist;                     // device history (hist_len) or null
+    // SELL-64 copy of the matrix (used when `sell_cw` is nonzero)
+    int32_t sell_cw;
+    const int32_t *sell_ptr;
+    const void *sell_col;
+    const uint8_t *sell_len;
+    const double *sell_val;
+    const float *sell_val32;
 };
 
 // ------------------------------------------------------------------ host helpers

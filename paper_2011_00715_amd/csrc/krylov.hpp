@@ -201,6 +201,40 @@ __global__ __launch_bounds__(kBlock) void k_resid_stream(B a)
     }
 }
 
+template <class V> __device__ __forceinline__ const V *sell_vals(const SysDesc &d);
+template <> __device__ __forceinline__ const double *sell_vals<double>(const SysDesc &d) { return d.sell_val; }
+template <> __device__ __forceinline__ const float *sell_vals<float>(const SysDesc &d) { return d.sell_val32; }
+
+// r = b - A x in FP64 with the SELL-64 layout, per-block r.r and b.b.
+template <int kGate, class CI, class B>
+__global__ __launch_bounds__(kBlock) void k_resid_sell(B a)
+{
+    __shared__ double red[kBlock / kWave];
+    int j;
+    SysDesc d;
+    if (!locate(a, j, d)) return;
+    if (kGate != kGateNone && !gate_open(d.st, kGate)) return;
+    int rb, re;
+    row_range(d, j, rb, re);
+    const double *__restrict__ b = d.b;
+    double *__restrict__ r = d.r;
+    const SellView sv{d.sell_ptr, d.sell_col, d.sell_len};
+    double rr = 0.0, bb = 0.0;
+    sell_rows<double, CI>(rb, re, sv, d.sell_val, d.x, [&](int i, double y) {
+        const double bi = b[i];
+        const double ri = bi - y;
+        r[i] = ri;
+        rr = fma(ri, ri, rr);
+        bb = fma(bi, bi, bb);
+    });
+    rr = block_sum(rr, red);
+    bb = block_sum(bb, red);
+    if (threadIdx.x == 0) {
+        d.partials[kPartRr * d.nblk + j] = rr;
+        d.partials[kPartBb * d.nblk + j] = bb;
+    }
+}
+
 // r = b - y where y = A x was written into r by a standalone SpMV kernel.
 template <int kGate, class B>
 __global__ __launch_bounds__(kBlock) void k_resid_combine(B a)
@@ -452,6 +486,30 @@ __global__ __launch_bounds__(kBlock) void k_pcg_spmv_stream(B a)
             acc = fma(y, p[i], acc);
         });
     }
+    const double blk = block_sum((double)acc, red);
+    if (threadIdx.x == 0) d.partials[kPartPq * d.nblk + j] = blk;
+}
+
+// A with the SELL-64 layout: one slice of 64 rows per wavefront, p.q fused.
+template <class V, class CI, class B>
+__global__ __launch_bounds__(kBlock) void k_pcg_spmv_sell(B a)
+{
+    __shared__ double red[kBlock / kWave];
+    int j;
+    SysDesc d;
+    if (!locate(a, j, d)) return;
+    if (!gate_open(d.st, Vecs<V>::gate)) return;
+    int rb, re;
+    row_range(d, j, rb, re);
+    const V *__restrict__ p = Vecs<V>::p(d);
+    V *__restrict__ q = Vecs<V>::q(d);
+    const V *__restrict__ val = sell_vals<V>(d);
+    const SellView sv{d.sell_ptr, d.sell_col, d.sell_len};
+    V acc = V(0);
+    sell_rows<V, CI>(rb, re, sv, val, p, [&](int i, V y) {
+        q[i] = y;
+        acc = fma(y, p[i], acc);
+    });
     const double blk = block_sum((double)acc, red);
     if (threadIdx.x == 0) d.partials[kPartPq * d.nblk + j] = blk;
 }

@@ -101,6 +101,11 @@ static int get_workspace(spk_mat *A, bool mixed, Workspace **out)
         d.q = w->q;
         d.partials = w->partials;
         d.st = w->st;
+        d.sell_cw = A->kernel == SPK_KERNEL_SELL ? A->sell_cw : 0;
+        d.sell_ptr = A->sell_ptr;
+        d.sell_col = A->sell_col;
+        d.sell_len = A->sell_len;
+        d.sell_val = A->sell_val;
     }
     if (mixed && !w->has_mixed) {
         SPK_TRY(dalloc(&w->r32, A->n, w));
@@ -117,6 +122,7 @@ static int get_workspace(spk_mat *A, bool mixed, Workspace **out)
         d.p32 = w->p32;
         d.q32 = w->q32;
         d.d32 = w->d32;
+        d.sell_val32 = A->sell_val32;
     }
     *out = w;
     return SPK_OK;
@@ -135,6 +141,14 @@ static int launch_resid(spk_mat *A, Workspace *w, int purpose, bool gated, hipSt
     if (A->kernel == SPK_KERNEL_STREAM) {
         if (gated) hipLaunchKernelGGL((k_resid_stream<kGateResid, One>), g, t, 0, s, b);
         else hipLaunchKernelGGL((k_resid_stream<kGateNone, One>), g, t, 0, s, b);
+    } else if (A->kernel == SPK_KERNEL_SELL) {
+        if (A->sell_cw == 2) {
+            if (gated) hipLaunchKernelGGL((k_resid_sell<kGateResid, int16_t, One>), g, t, 0, s, b);
+            else hipLaunchKernelGGL((k_resid_sell<kGateNone, int16_t, One>), g, t, 0, s, b);
+        } else {
+            if (gated) hipLaunchKernelGGL((k_resid_sell<kGateResid, int32_t, One>), g, t, 0, s, b);
+            else hipLaunchKernelGGL((k_resid_sell<kGateNone, int32_t, One>), g, t, 0, s, b);
+        }
     } else {
         SPK_TRY(launch_spmv<double>(A, A->val, w->x, w->r, s, gated ? w->st : nullptr,
                                     gated ? kGateResid : kGateNone));
@@ -154,6 +168,9 @@ static int enqueue_iteration(spk_mat *A, Workspace *w, hipStream_t s)
     const dim3 g(A->nblk), t(kBlock), one(1);
     if (A->kernel == SPK_KERNEL_STREAM) {
         hipLaunchKernelGGL((k_pcg_spmv_stream<V, One>), g, t, 0, s, b);
+    } else if (A->kernel == SPK_KERNEL_SELL) {
+        if (A->sell_cw == 2) hipLaunchKernelGGL((k_pcg_spmv_sell<V, int16_t, One>), g, t, 0, s, b);
+        else hipLaunchKernelGGL((k_pcg_spmv_sell<V, int32_t, One>), g, t, 0, s, b);
     } else {
         const V *val = std::is_same<V, double>::value ? (const V *)A->val : (const V *)A->val32;
         V *p = std::is_same<V, double>::value ? (V *)w->p : (V *)w->p32;

@@ -91,7 +91,7 @@ __global__ void k_check_cols(int n, const int32_t *__restrict__ rowptr,
                              const int32_t *__restrict__ col, int check_sorted,
                              RowStats *__restrict__ out)
 {
-    int badc = 0, uns = 0;
+    int badc = 0, uns = 0, md = 0;
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
         int prev = -1;
         for (int k = rowptr[i]; k < rowptr[i + 1]; ++k) {
@@ -99,10 +99,12 @@ __global__ void k_check_cols(int n, const int32_t *__restrict__ rowptr,
             if (c < 0 || c >= n) ++badc;
             if (check_sorted && c <= prev) ++uns;
             prev = c;
+            md = max(md, abs(c - i));
         }
     }
     if (badc) atomicAdd(&out->bad_col, badc);
     if (uns) atomicAdd(&out->unsorted, uns);
+    if (md) atomicMax(&out->max_delta, md);
 }
 
 // dinv_i = 1 / a_ii (duplicates of the diagonal are summed).
@@ -264,6 +266,22 @@ int launch_spmv(const spk_mat *A, const V *val, const V *x, V *y, hipStream_t s,
         default: launch_vector_l<V, 64>(A, val, x, y, s, gst, gmode); break;
         }
         break;
+    case SPK_KERNEL_SELL: {
+        if (gst) {
+            set_error("internal: gated SELL SpMV");
+            return SPK_EINVAL;
+        }
+        const SellView sv{A->sell_ptr, A->sell_col, A->sell_len};
+        const V *sval = std::is_same<V, double>::value ? (const V *)A->sell_val : (const V *)A->sell_val32;
+        (void)val;
+        if (A->sell_cw == 2)
+            hipLaunchKernelGGL((k_spmv_sell<V, int16_t>), dim3(A->nblk), dim3(kBlock), 0, s, A->n, A->R,
+                               A->ntiles, A->nblk, sv, sval, x, y);
+        else
+            hipLaunchKernelGGL((k_spmv_sell<V, int32_t>), dim3(A->nblk), dim3(kBlock), 0, s, A->n, A->R,
+                               A->ntiles, A->nblk, sv, sval, x, y);
+        break;
+    }
     case SPK_KERNEL_MERGE: {
         V *cv = reinterpret_cast<V *>(A->carry_val);
         hipLaunchKernelGGL((k_spmv_merge<V>), dim3(A->mtiles), dim3(kBlock), 0, s, A->n,
@@ -302,7 +320,8 @@ void update_info(spk_mat *A)
     I.nnz = A->nnz;
     I.kernel = A->kernel;
     I.lanes = A->kernel == SPK_KERNEL_VECTOR ? A->lanes
-              : A->kernel == SPK_KERNEL_STREAM ? A->R : kMergeItems;
+              : A->kernel == SPK_KERNEL_STREAM ? A->R
+              : A->kernel == SPK_KERNEL_SELL ? 8 * A->sell_cw : kMergeItems;
     I.has_f32 = A->val32 != nullptr;
     I.row_min = A->n ? S.min_len : 0;
     I.row_max = S.max_len;
@@ -327,10 +346,27 @@ void update_info(spk_mat *A)
     I.bytes_pcg_iter_f32 = 8 * nz + 4 * (nn + 1) + 48 * nn;
     I.device_bytes = A->bytes + (A->ws ? A->ws->bytes : 0);
     I.zero_diag_rows = S.zero_diag;
+    if (A->kernel == SPK_KERNEL_SELL && A->sell_cw) {
+        const int64_t ns = (nn + kSell - 1) / kSell;
+        I.stored_nnz = A->sell_nnz;
+        I.format_bytes_spmv_f64 = (8 + A->sell_cw) * A->sell_nnz + 4 * (ns + 1) + nn + 16 * nn;
+        I.format_bytes_spmv_f32 = (4 + A->sell_cw) * A->sell_nnz + 4 * (ns + 1) + nn + 8 * nn;
+    } else {
+        I.stored_nnz = nz;
+        I.format_bytes_spmv_f64 = I.bytes_spmv_f64;
+        I.format_bytes_spmv_f32 = I.bytes_spmv_f32;
+    }
 }
 
 int ensure_f32(spk_mat *A, hipStream_t s)
 {
+    if (A->sell_cw && !A->sell_val32 && A->sell_nnz > 0) {
+        SPK_HIP(hipMalloc(&A->sell_val32, sizeof(float) * A->sell_nnz));
+        hipLaunchKernelGGL(k_to_f32, dim3(grid_for(A->sell_nnz)), dim3(kBlock), 0, s, A->sell_nnz,
+                           A->sell_val, A->sell_val32);
+        SPK_HIP(hipGetLastError());
+        A->bytes += 4 * A->sell_nnz;
+    }
     if (A->val32 || A->n == 0) return SPK_OK;
     SPK_HIP(hipMalloc(&A->val32, sizeof(float) * (A->nnz > 0 ? A->nnz : 1)));
     SPK_HIP(hipMalloc(&A->dinv32, sizeof(float) * A->n));
@@ -402,6 +438,80 @@ static int setup_merge(spk_mat *A, hipStream_t s)
 }
 
 void free_workspace(spk_mat *A);
+
+static void free_sell(spk_mat *A)
+{
+    hipFree(A->sell_ptr);
+    hipFree(A->sell_col);
+    hipFree(A->sell_len);
+    hipFree(A->sell_val);
+    hipFree(A->sell_val32);
+    A->sell_ptr = nullptr;
+    A->sell_col = nullptr;
+    A->sell_len = nullptr;
+    A->sell_val = nullptr;
+    A->sell_val32 = nullptr;
+    A->sell_cw = 0;
+    A->sell_nnz = 0;
+}
+
+// Build the SELL-64 copy: slice widths from rowptr on the host (setup only),
+// entries filled by one device lane per row.  cw: 2 (int16 offsets), 4 (int32)
+// or 0 (int16 when every |col - row| fits).
+static int setup_sell(spk_mat *A, hipStream_t s, int cw)
+{
+    if (cw == 0) cw = A->stats.max_delta <= 32767 ? 2 : 4;
+    if (A->sell_cw == cw) return SPK_OK;
+    if (cw == 2 && A->stats.max_delta > 32767) {
+        set_error("column offsets up to %d do not fit int16", A->stats.max_delta);
+        return SPK_EINVAL;
+    }
+    if (A->stats.max_len > 255) {
+        set_error("SELL needs rows of at most 255 entries (max %d)", A->stats.max_len);
+        return SPK_EINVAL;
+    }
+    free_sell(A);
+    const int n = A->n;
+    std::vector<int32_t> rp((size_t)n + 1);
+    SPK_HIP(hipMemcpyAsync(rp.data(), A->rowptr, sizeof(int32_t) * ((size_t)n + 1), hipMemcpyDeviceToHost, s));
+    SPK_HIP(hipStreamSynchronize(s));
+    const int ns = ceil_div(n, kSell);
+    std::vector<int32_t> sp((size_t)ns + 1);
+    int64_t acc = 0;
+    for (int k = 0; k < ns; ++k) {
+        int mx = 0;
+        for (int i = k * kSell; i < std::min(n, (k + 1) * kSell); ++i) mx = std::max(mx, rp[i + 1] - rp[i]);
+        sp[k] = (int32_t)acc;
+        acc += (int64_t)kSell * mx;
+        if (acc > 0x7fffffffLL) { set_error("SELL layout exceeds 2^31 entries"); return SPK_EINVAL; }
+    }
+    sp[ns] = (int32_t)acc;
+    const size_t m = acc > 0 ? (size_t)acc : 1;
+    SPK_HIP(hipMalloc(&A->sell_ptr, sizeof(int32_t) * ((size_t)ns + 1)));
+    SPK_HIP(hipMalloc(&A->sell_col, (size_t)cw * m));
+    SPK_HIP(hipMalloc(&A->sell_len, (size_t)(n > 0 ? n : 1)));
+    SPK_HIP(hipMalloc(&A->sell_val, sizeof(double) * m));
+    SPK_HIP(hipMemcpyAsync(A->sell_ptr, sp.data(), sizeof(int32_t) * ((size_t)ns + 1), hipMemcpyHostToDevice, s));
+    if (cw == 2)
+        hipLaunchKernelGGL(k_sell_fill<int16_t>, dim3(grid_for(n)), dim3(kBlock), 0, s, n, A->rowptr, A->col,
+                           A->val, A->sell_ptr, (int16_t *)A->sell_col, A->sell_val, A->sell_len);
+    else
+        hipLaunchKernelGGL(k_sell_fill<int32_t>, dim3(grid_for(n)), dim3(kBlock), 0, s, n, A->rowptr, A->col,
+                           A->val, A->sell_ptr, (int32_t *)A->sell_col, A->sell_val, A->sell_len);
+    SPK_HIP(hipGetLastError());
+    A->sell_cw = cw;
+    A->sell_nnz = acc;
+    A->bytes += 4 * ((int64_t)ns + 1) + (int64_t)(cw + 8) * acc + n;
+    if (A->val32) {
+        SPK_HIP(hipMalloc(&A->sell_val32, sizeof(float) * m));
+        hipLaunchKernelGGL(k_to_f32, dim3(grid_for((int64_t)m)), dim3(kBlock), 0, s, (int64_t)m, A->sell_val,
+                           A->sell_val32);
+        SPK_HIP(hipGetLastError());
+        A->bytes += 4 * acc;
+    }
+    SPK_HIP(hipStreamSynchronize(s));
+    return SPK_OK;
+}
 
 }  // namespace spk
 
@@ -563,6 +673,7 @@ static int create_impl(int32_t n, int64_t nnz, const int32_t *rowptr, const int3
     if (const char *f = getenv("SPK_FORCE_KERNEL")) {
         if (!strncmp(f, "stream", 6)) A->kernel = SPK_KERNEL_STREAM;
         else if (!strncmp(f, "merge", 5) && merge_fits(A)) A->kernel = SPK_KERNEL_MERGE;
+        else if (!strncmp(f, "sell", 4) && A->stats.max_len <= 255) A->kernel = SPK_KERNEL_SELL;
         else if (!strncmp(f, "vector", 6)) {
             A->kernel = SPK_KERNEL_VECTOR;
             const char *c = strchr(f, ':');
@@ -574,6 +685,10 @@ static int create_impl(int32_t n, int64_t nnz, const int32_t *rowptr, const int3
     apply_partition(A);
     if (A->kernel == SPK_KERNEL_MERGE) {
         rc = setup_merge(A, s);
+        if (rc) return rc;
+    }
+    if (A->kernel == SPK_KERNEL_SELL) {
+        rc = setup_sell(A, s, 0);
         if (rc) return rc;
     }
     if (flags & SPK_MAT_MIXED) {
@@ -658,6 +773,22 @@ int spk_mat_set_kernel(spk_mat *A, int kernel, int32_t param)
         A->kernel = SPK_KERNEL_MERGE;
         A->R = 256;
         break;
+    case SPK_KERNEL_SELL: {
+        if (param != 0 && param != 16 && param != 32) {
+            set_error("SELL column width %d not in {0, 16, 32}", param);
+            return SPK_EINVAL;
+        }
+        const int rc = setup_sell(A, nullptr, param / 8);
+        if (rc) return rc;
+        if (A->val32) {
+            const int r2 = ensure_f32(A, nullptr);
+            if (r2) return r2;
+            SPK_HIP(hipStreamSynchronize(nullptr));
+        }
+        A->kernel = SPK_KERNEL_SELL;
+        A->R = 256;
+        break;
+    }
     default:
         set_error("unknown kernel %d", kernel);
         return SPK_EINVAL;
@@ -727,6 +858,7 @@ int spk_mat_destroy(spk_mat *A)
     hipFree(A->tile_k);
     hipFree(A->carry_row);
     hipFree(A->carry_val);
+    free_sell(A);
     delete A;
     return SPK_OK;
 }

@@ -15,6 +15,7 @@ struct RowStats {
     int32_t bad_rowptr;      // rows with rowptr[i+1] < rowptr[i] or out of [0, nnz]
     int32_t bad_col;         // entries with col outside [0, n)
     int32_t unsorted;        // rows whose columns are not strictly ascending
+    int32_t max_delta;       // max |col - row| over the stored entries
     int32_t zero_diag;       // rows without a nonzero diagonal
     int32_t tile_max[6];     // max nonzeros in an aligned tile of 256,128,64,32,16,8 rows
     int32_t hist[33];        // rows by bit length of their length
@@ -72,6 +73,14 @@ struct spk_mat {
     int mtiles = 0;
     int32_t *tile_row = nullptr, *tile_k = nullptr, *carry_row = nullptr;
     double *carry_val = nullptr;
+    // SELL-64 copy (built when the SELL family is selected)
+    int sell_cw = 0;           // column offset width: 2 (int16) or 4 (int32), 0 = none
+    int64_t sell_nnz = 0;      // stored entries including padding
+    int32_t *sell_ptr = nullptr;
+    void *sell_col = nullptr;
+    uint8_t *sell_len = nullptr;
+    double *sell_val = nullptr;
+    float *sell_val32 = nullptr;
     spk::Workspace *ws = nullptr;
     int64_t bytes = 0;
 };

@@ -149,6 +149,98 @@ __global__ __launch_bounds__(kBlock) void k_spmv_vector(int n, const int32_t *__
     }
 }
 
+// ------------------------------------------------------------------ SELL-64
+// Sliced ELLPACK with one slice of 64 consecutive rows per wavefront: entry j
+// of the slice's rows is stored contiguously (column-major inside the slice),
+// so lane l streams row (64 s + l) with fully coalesced loads and no LDS, no
+// barrier and no cross-lane reduction.  Columns are stored as offsets from the
+// row (int16 when every |col - row| < 2^15, which holds for stencils), so an
+// FP64 nonzero costs 10 bytes instead of CSR's 12 (FP32: 6 instead of 8);
+// this is the index compression Challenge A7 points to.  Rows shorter than
+// their slice are padded; padding is never multiplied (per-row length test).
+constexpr int kSell = 64;
+
+struct SellView {
+    const int32_t *ptr;    // element offset of each slice (nslices + 1)
+    const void *col;       // int16 or int32 row-relative column offsets
+    const uint8_t *len;    // row lengths
+};
+
+// Row sum of lane `lane` in slice s; entries in column order, FMA.
+template <class V, class CI, int U = 8>
+__device__ __forceinline__ V sell_row(const SellView &sv, const V *__restrict__ val,
+                                      const V *__restrict__ x, int s, int lane, int row)
+{
+    const int32_t b = sv.ptr[s];
+    const int slen = (sv.ptr[s + 1] - b) / kSell;
+    const int rlen = sv.len[row];
+    const CI *__restrict__ col = reinterpret_cast<const CI *>(sv.col) + b + lane;
+    const V *__restrict__ v = val + b + lane;
+    V acc = V(0);
+    for (int j0 = 0; j0 < slen; j0 += U) {
+        CI c[U];
+        V a[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int j = j0 + u < slen ? j0 + u : slen - 1;
+            c[u] = ld_stream(col + (size_t)j * kSell);
+            a[u] = ld_stream(v + (size_t)j * kSell);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (j0 + u < rlen) acc = fma(a[u], x[row + (int)c[u]], acc);
+    }
+    return acc;
+}
+
+// Rows [r0, r1) of a tile range, one slice per wavefront at a time; fn(row, y)
+// is called by the lane that owns the row.  r0 is a multiple of 64.
+template <class V, class CI, class Fn>
+__device__ __forceinline__ void sell_rows(int r0, int r1, const SellView &sv,
+                                          const V *__restrict__ val, const V *__restrict__ x,
+                                          Fn &&fn)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    const int w = threadIdx.x / kWave;
+    for (int s = r0 / kSell + w; s * kSell < r1; s += kBlock / kWave) {
+        const int row = s * kSell + lane;
+        if (row < r1) fn(row, sell_row<V, CI>(sv, val, x, s, lane, row));
+    }
+}
+
+template <class V, class CI>
+__global__ __launch_bounds__(kBlock) void k_spmv_sell(int n, int R, int ntiles, int nblk,
+                                                      SellView sv, const V *__restrict__ val,
+                                                      const V *__restrict__ x, V *__restrict__ y)
+{
+    const int j = xcd_remap(blockIdx.x, nblk);
+    int t0, t1;
+    block_tiles(j, nblk, ntiles, t0, t1);
+    sell_rows<V, CI>(t0 * R, min(t1 * R, n), sv, val, x, [&](int i, V s) { y[i] = s; });
+}
+
+// Layout fill: one lane per row writes its entries and the slice padding.
+template <class CI>
+__global__ void k_sell_fill(int n, const int32_t *__restrict__ rowptr,
+                            const int32_t *__restrict__ col, const double *__restrict__ val,
+                            const int32_t *__restrict__ sptr, CI *__restrict__ scol,
+                            double *__restrict__ sval, uint8_t *__restrict__ slen)
+{
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const int s = i / kSell, lane = i % kSell;
+        const int b = sptr[s];
+        const int len = (sptr[s + 1] - b) / kSell;
+        const int a = rowptr[i], e = rowptr[i + 1];
+        slen[i] = (uint8_t)(e - a);
+        for (int j = 0; j < len; ++j) {
+            const size_t d = (size_t)b + (size_t)j * kSell + lane;
+            const bool real = a + j < e;
+            scol[d] = real ? (CI)(col[a + j] - i) : (CI)0;
+            sval[d] = real ? val[a + j] : 0.0;
+        }
+    }
+}
+
 // ------------------------------------------------------------------ merge path
 // Split point of diagonal d on the merge of row ends (rowptr[i+1]) with
 // nonzero indices: (i, d - i) with i the number of completed rows.

@@ -35,7 +35,7 @@ def _cases():
 
 
 @pytest.mark.parametrize("case", ["lap2d_64", "lap3d_24", "diff27_14", "powerlaw_20k"])
-@pytest.mark.parametrize("kernel", ["auto", "vector", "merge"])
+@pytest.mark.parametrize("kernel", ["auto", "vector", "merge", "sell"])
 def test_pcg_fp64_parity(case, kernel):
     spk = need_gpu()
     name, A, seed = [c for c in _cases() if c[0] == case][0]
@@ -44,6 +44,10 @@ def test_pcg_fp64_parity(case, kernel):
         spk.mat_set_kernel(M, spk.KERNEL_VECTOR, 8)
     elif kernel == "merge":
         spk.mat_set_kernel(M, spk.KERNEL_MERGE, 0)
+    elif kernel == "sell":
+        if M.info.row_max > 255:
+            pytest.skip("SELL stores row lengths in one byte (rows of at most 255 entries)")
+        spk.mat_set_kernel(M, spk.KERNEL_SELL, 0)
     b = spkgen.rhs_uniform(A.n, seed)
     x, res, hist = _solve(spk, M, b, hist_len=4000)
     xo, ro, ho = oracle.pcg(A, b, rtol=1e-8, hist_len=4000)
@@ -135,12 +139,15 @@ def test_pcg_true_residual_restart_rule():
     assert res.true_rel_residual < 1e-13
 
 
-@pytest.mark.parametrize("case", ["lap2d_64", "diff27_14", "powerlaw_20k"])
+@pytest.mark.parametrize("case", ["lap2d_64", "diff27_14", "powerlaw_20k", "diff27_14/sell"])
 @pytest.mark.parametrize("mode", ["mixed", "mixed_ir"])
 def test_pcg_mixed_precision(case, mode):
     spk = need_gpu()
+    case, _, kern = case.partition("/")
     name, A, seed = [c for c in _cases() if c[0] == case][0]
     M = mat_on_gpu(spk, A, flags=spk.MAT_MIXED)
+    if kern == "sell":
+        spk.mat_set_kernel(M, spk.KERNEL_SELL, 0)
     b = spkgen.rhs_uniform(A.n, seed)
     prec = spk.PREC_MIXED if mode == "mixed" else spk.PREC_MIXED_IR
     x, res, hist = _solve(spk, M, b, precision=prec)
@@ -161,10 +168,15 @@ def test_pcg_mixed_precision(case, mode):
     assert np.all(np.diff(h) < 0)
 
 
-def test_pcg_mixed_without_flag_converts_lazily():
+@pytest.mark.parametrize("kernel", ["auto", "sell"])
+def test_pcg_mixed_without_flag_converts_lazily(kernel):
     spk = need_gpu()
     A = spkgen.laplace2d5(40)
     M = mat_on_gpu(spk, A)
+    if kernel == "sell":
+        spk.mat_set_kernel(M, spk.KERNEL_SELL, 0)
+        _, r64, _ = _solve(spk, M, spkgen.rhs_uniform(A.n, 0))  # FP64 workspace first
+        assert r64.reason == spk.CONVERGED_RTOL
     assert M.info.has_f32 == 0
     b = spkgen.rhs_uniform(A.n, 0)
     _, res, _ = _solve(spk, M, b, precision=spk.PREC_MIXED)

@@ -11,14 +11,20 @@ from gpu_util import U32, U64, check_spmv, mat_on_gpu, need_gpu, spmv_bound_rows
 
 pytestmark = pytest.mark.gpu
 
-KERNELS = [("auto", 0), ("stream", 0), ("stream", 64), ("stream", 8), ("merge", 0)] + [
-    ("vector", L) for L in (1, 2, 4, 8, 16, 32, 64)]
+KERNELS = [("auto", 0), ("stream", 0), ("stream", 64), ("stream", 8), ("merge", 0), ("sell", 0),
+           ("sell", 32)] + [("vector", L) for L in (1, 2, 4, 8, 16, 32, 64)]
 
 
 def _set(spk, M, kernel, param):
     if kernel == "auto":
         return spk.KERNEL_NAMES[M.info.kernel], M.info.lanes
-    k = {"stream": spk.KERNEL_STREAM, "vector": spk.KERNEL_VECTOR, "merge": spk.KERNEL_MERGE}[kernel]
+    k = {"stream": spk.KERNEL_STREAM, "vector": spk.KERNEL_VECTOR, "merge": spk.KERNEL_MERGE,
+         "sell": spk.KERNEL_SELL}[kernel]
+    if kernel == "sell" and M.info.row_max > 255:
+        # SELL stores row lengths in one byte: the library refuses such rows
+        with pytest.raises(spk.SpkError, match="255"):
+            spk.mat_set_kernel(M, k, param)
+        return None, None
     spk.mat_set_kernel(M, k, param)
     return kernel, M.info.lanes
 
@@ -42,6 +48,9 @@ def test_spmv_parity_fp64(kernel, param):
     for name, A, integer in _matrices():
         M = mat_on_gpu(spk, A)
         kname, lanes = _set(spk, M, kernel, param)
+        if kname is None:
+            M.close()
+            continue
         if integer:
             x = np.random.default_rng(1).integers(-50, 50, size=A.n).astype(np.float64)
         else:
@@ -62,12 +71,15 @@ def test_spmv_parity_fp64(kernel, param):
 
 
 @pytest.mark.parametrize("kernel,param", [("auto", 0), ("stream", 0), ("merge", 0), ("vector", 4),
-                                          ("vector", 64)])
+                                          ("vector", 64), ("sell", 0)])
 def test_spmv_parity_fp32(kernel, param):
     spk = need_gpu()
     for name, A, integer in _matrices():
         M = mat_on_gpu(spk, A, flags=spk.MAT_MIXED)
         kname, lanes = _set(spk, M, kernel, param)
+        if kname is None:
+            M.close()
+            continue
         if integer:
             x = np.random.default_rng(1).integers(-50, 50, size=A.n).astype(np.float32)
         else:
@@ -105,7 +117,7 @@ def test_spmv_degenerate_sizes():
     spk.mat_mult(M0, e, e.clone())
     # all rows empty
     Z = spkgen.CSR(1000, np.zeros(1001, np.int32), np.zeros(0, np.int32), np.zeros(0))
-    for k in (spk.KERNEL_STREAM, spk.KERNEL_MERGE, spk.KERNEL_VECTOR):
+    for k in (spk.KERNEL_STREAM, spk.KERNEL_MERGE, spk.KERNEL_VECTOR, spk.KERNEL_SELL):
         MZ = mat_on_gpu(spk, Z)
         spk.mat_set_kernel(MZ, k, 8 if k == spk.KERNEL_VECTOR else 0)
         y = torch.full((1000,), 5.0, dtype=torch.float64, device="cuda")
@@ -133,6 +145,50 @@ def test_spmv_one_long_row():
         y = to_dev(np.zeros(n))
         spk.mat_mult(M, to_dev(x), y)
         assert np.array_equal(y.cpu().numpy(), ref)
+
+
+def _sell_stored(A):
+    lens = np.diff(A.rowptr)
+    pad = (-A.n) % 64
+    return int(np.pad(lens, (0, pad)).reshape(-1, 64).max(axis=1).sum()) * 64
+
+
+def test_spmv_sell_layout_and_offsets():
+    """SELL-64: int16 offsets when every |col - row| < 2^15, int32 otherwise
+    (int16 refused then); padding never enters a sum; bit-exact on integers."""
+    spk = need_gpu()
+    rng = np.random.default_rng(11)
+    n = 70001  # ragged last slice
+    lens = rng.integers(0, 10, size=n)
+    lens[64:128] = 0  # an all-empty slice
+    lens[1000] = 255  # the longest row SELL stores
+    rowptr = np.zeros(n + 1, np.int64)
+    rowptr[1:] = np.cumsum(lens)
+    far = [np.sort(rng.choice(n, size=k, replace=False)) for k in lens]
+    near = []
+    for i, k in enumerate(lens):
+        lo, hi = max(0, i - 30000), min(n, i + 30000)
+        near.append(np.sort(rng.choice(np.arange(lo, hi), size=k, replace=False)))
+    vals = rng.integers(-4, 5, size=int(rowptr[-1])).astype(np.float64)
+    x = rng.integers(-4, 5, size=n).astype(np.float64)
+    for cols, width in ((far, 32), (near, 16)):
+        A = spkgen.CSR(n, rowptr.astype(np.int32), np.concatenate(cols).astype(np.int32), vals)
+        M = mat_on_gpu(spk, A)
+        if width == 32:
+            with pytest.raises(spk.SpkError):
+                spk.mat_set_kernel(M, spk.KERNEL_SELL, 16)
+        spk.mat_set_kernel(M, spk.KERNEL_SELL, 0)
+        info = M.info
+        assert spk.KERNEL_NAMES[info.kernel] == "sell" and info.lanes == width
+        stored = _sell_stored(A)
+        assert info.stored_nnz == stored
+        cw = width // 8
+        ns = (n + 63) // 64
+        assert info.format_bytes_spmv_f64 == (8 + cw) * stored + 4 * (ns + 1) + n + 16 * n
+        y = to_dev(np.full(n, np.nan))
+        spk.mat_mult(M, to_dev(x), y)
+        assert np.array_equal(y.cpu().numpy(), oracle.spmv(A, x))
+        M.close()
 
 
 def test_kernel_selection():
