@@ -185,6 +185,35 @@ __device__ __forceinline__ double reduce_partials(const double *part, int nblk, 
     return block_sum(s, sh);
 }
 
+// Three partial arrays reduced together (same order as reduce_partials); all
+// loads of a chunk are in flight at once.
+__device__ __forceinline__ void reduce_partials3(const double *pa, const double *pb,
+                                                 const double *pc, int nblk, double *sh,
+                                                 double &A, double &B, double &C)
+{
+    constexpr int U = 8;
+    double s = 0.0, t = 0.0, w = 0.0;
+    for (int i0 = threadIdx.x; i0 < nblk; i0 += kBlock * U) {
+        double u0[U], u1[U], u2[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int i = i0 + u * kBlock;
+            u0[u] = i < nblk ? pa[i] : 0.0;
+            u1[u] = i < nblk ? pb[i] : 0.0;
+            u2[u] = i < nblk ? pc[i] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            s += u0[u];
+            t += u1[u];
+            w += u2[u];
+        }
+    }
+    A = block_sum(s, sh);
+    B = block_sum(t, sh);
+    C = block_sum(w, sh);
+}
+
 // Two partial arrays reduced together (same order as reduce_partials).
 __device__ __forceinline__ void reduce_partials2(const double *pa, const double *pb, int nblk,
                                                  double *sh, double &A, double &B)

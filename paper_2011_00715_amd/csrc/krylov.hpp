@@ -545,12 +545,14 @@ __global__ __launch_bounds__(kBlock) void k_pcg_update(B a)
     SysDesc d;
     if (!locate(a, j, d)) return;
     const SysState *st = d.st;
-    if (!gate_open(st, Vecs<V>::gate)) return;
+    const Gate g = load_gate(st);
+    const double rho = st->rho;
     const double eta = reduce_partials(d.partials + kPartPq * d.nblk, d.nblk, red);
+    if (!gate_ok(g, Vecs<V>::gate)) return;
     if (!(eta > 0.0) || !finite(eta)) return;
     int rb, re;
     row_range(d, j, rb, re);
-    const V nalpha = (V)(-(st->rho / eta));
+    const V nalpha = (V)(-(rho / eta));
     V *__restrict__ r = Vecs<V>::r(d);
     V *__restrict__ z = Vecs<V>::z(d);
     const V *__restrict__ q = Vecs<V>::q(d);
@@ -582,48 +584,55 @@ __global__ __launch_bounds__(kBlock) void k_fin_update(B a)
     SysDesc d;
     if (!fin_locate(a, d)) return;
     SysState *st = d.st;
-    if (st->mixed != Vecs<V>::mixed) return;
-    if (!gate_open(st, Vecs<V>::gate)) {
+    // the state and the three partial arrays are loaded in one round trip
+    const Gate g = load_gate(st);
+    const double rho = st->rho, thresh = st->thresh, rtol = st->rtol, bnorm = st->bnorm;
+    const double inner_thresh = st->inner_thresh;
+    const int iter = st->iter, inner_iter = st->inner_iter, maxit = st->maxit;
+    const int inner_maxit = st->inner_maxit, hist_len = st->hist_len;
+    double eta, RZ, RR;
+    reduce_partials3(d.partials + kPartPq * d.nblk, d.partials + kPartRz * d.nblk,
+                     d.partials + kPartRr * d.nblk, d.nblk, red, eta, RZ, RR);
+    if (g.mixed != Vecs<V>::mixed) return;
+    if (!gate_ok(g, Vecs<V>::gate)) {
         if (threadIdx.x == 0) st->cmode = 0;
         return;
     }
-    const double eta = reduce_partials(d.partials + kPartPq * d.nblk, d.nblk, red);
-    double RZ, RR;
-    reduce_partials2(d.partials + kPartRz * d.nblk, d.partials + kPartRr * d.nblk, d.nblk, red,
-                     RZ, RR);
     if (threadIdx.x != 0) return;
     st->eta = eta;
     st->cmode = 0;
     if (!finite(eta)) { st->status = SPK_DIVERGED_NANORINF; return; }
     if (eta <= 0.0) {
-        if (st->mixed) {  // inner breakdown: refine from here with a fresh p
+        if (g.mixed) {  // inner breakdown: refine from here with a fresh p
             st->phase = kPhaseUpdate;
             st->fresh_p = 1;
         } else st->status = SPK_DIVERGED_INDEFINITE_MAT;
         return;
     }
-    st->alpha = st->rho / eta;
-    const int k = ++st->iter;
+    st->alpha = rho / eta;
+    const int k = iter + 1;
+    st->iter = k;
     const double rn = sqrt(RR);
     st->cmode = 1;  // stop unless the tests below continue
-    if (!st->mixed) {
+    if (!g.mixed) {
         st->rnorm = rn;
-        if (d.hist && k < st->hist_len) d.hist[k] = rn;
+        if (d.hist && k < hist_len) d.hist[k] = rn;
         if (!finite(rn)) st->status = SPK_DIVERGED_NANORINF;
-        else if (rn <= st->thresh)
-            st->status = rn <= st->rtol * st->bnorm ? SPK_CONVERGED_RTOL : SPK_CONVERGED_ATOL;
-        else if (k >= st->maxit) st->status = SPK_DIVERGED_ITS;
+        else if (rn <= thresh)
+            st->status = rn <= rtol * bnorm ? SPK_CONVERGED_RTOL : SPK_CONVERGED_ATOL;
+        else if (k >= maxit) st->status = SPK_DIVERGED_ITS;
         else if (!finite(RZ)) st->status = SPK_DIVERGED_NANORINF;
         else if (RZ < 0.0) st->status = SPK_DIVERGED_INDEFINITE_PC;
         else if (RZ == 0.0) st->status = SPK_DIVERGED_BREAKDOWN;
-        else { st->beta = RZ / st->rho; st->rho = RZ; st->cmode = 2; }
+        else { st->beta = RZ / rho; st->rho = RZ; st->cmode = 2; }
     } else {
-        const int ki = ++st->inner_iter;
+        const int ki = inner_iter + 1;
+        st->inner_iter = ki;
         if (!finite(rn) || !finite(RZ)) st->status = SPK_DIVERGED_NANORINF;
-        else if (rn <= st->inner_thresh || ki >= st->inner_maxit || k >= st->maxit || RZ <= 0.0) {
+        else if (rn <= inner_thresh || ki >= inner_maxit || k >= maxit || RZ <= 0.0) {
             st->phase = kPhaseUpdate;
             if (RZ <= 0.0) st->fresh_p = 1;
-        } else { st->beta = RZ / st->rho; st->rho = RZ; st->cmode = 2; }
+        } else { st->beta = RZ / rho; st->rho = RZ; st->cmode = 2; }
     }
 }
 
@@ -637,13 +646,15 @@ __global__ __launch_bounds__(kBlock) void k_pcg_px(B a, int prelude)
     SysDesc d;
     if (!locate(a, j, d)) return;
     const SysState *st = d.st;
-    if (st->mixed != Vecs<V>::mixed) return;
+    const int mixed = st->mixed;
     const int cm = st->cmode;
+    const double alpha64 = st->alpha, beta64 = st->beta;
+    if (mixed != Vecs<V>::mixed) return;
     if (cm == 0 || (cm == 3) != (prelude != 0)) return;
     if (cm == 3) {
         int rb, re;
         row_range(d, j, rb, re);
-        const V beta = (V)st->beta;
+        const V beta = (V)beta64;
         V *__restrict__ p = Vecs<V>::p(d);
         const V *__restrict__ z = Vecs<V>::z(d);
         rows_unrolled(rb, re, [&](int i) { p[i] = fma(beta, p[i], z[i]); });
@@ -651,8 +662,8 @@ __global__ __launch_bounds__(kBlock) void k_pcg_px(B a, int prelude)
     }
     int rb, re;
     row_range(d, j, rb, re);
-    const V alpha = (V)st->alpha;
-    const V beta = (V)st->beta;
+    const V alpha = (V)alpha64;
+    const V beta = (V)beta64;
     V *__restrict__ x = Vecs<V>::x(d);
     V *__restrict__ p = Vecs<V>::p(d);
     const V *__restrict__ z = Vecs<V>::z(d);

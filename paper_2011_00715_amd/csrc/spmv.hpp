@@ -21,20 +21,37 @@ namespace spk {
 
 enum { kGateNone = 0, kGateInner64 = 1, kGateInner32 = 2, kGateResid = 3 };
 
+// The state fields that decide whether a solver kernel runs.  Kernels load
+// them together with their first operands (one memory round trip) and test
+// them afterwards.
+struct Gate {
+    int32_t status, phase, mixed;
+};
+
+__device__ __forceinline__ Gate load_gate(const SysState *st)
+{
+    return Gate{st->status, st->phase, st->mixed};
+}
+
 // Whether a solver kernel launched inside a captured graph should run.
-__device__ __forceinline__ bool gate_open(const SysState *st, int mode)
+__device__ __forceinline__ bool gate_ok(const Gate &g, int mode)
 {
     switch (mode) {
     case kGateNone: return true;
     case kGateInner64:
-        return st->status == SPK_RUNNING && st->phase == kPhaseInner && st->mixed == 0;
+        return g.status == SPK_RUNNING && g.phase == kPhaseInner && g.mixed == 0;
     case kGateInner32:
-        return st->status == SPK_RUNNING && st->phase == kPhaseInner && st->mixed == 1;
+        return g.status == SPK_RUNNING && g.phase == kPhaseInner && g.mixed == 1;
     case kGateResid:
-        return st->status == SPK_RUNNING && st->mixed == 1 &&
-               (st->phase == kPhaseResid || st->phase == kPhaseUpdate);
+        return g.status == SPK_RUNNING && g.mixed == 1 &&
+               (g.phase == kPhaseResid || g.phase == kPhaseUpdate);
     }
     return false;
+}
+
+__device__ __forceinline__ bool gate_open(const SysState *st, int mode)
+{
+    return mode == kGateNone || gate_ok(load_gate(st), mode);
 }
 
 template <class V>
