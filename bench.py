@@ -29,7 +29,13 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
-SPMV_KERNEL = "k_spmv_stream<double>"
+# rocprofv3 names of the standalone FP64 SpMV kernel of each family
+SPMV_KERNELS = {
+    "stream": "k_spmv_stream<double>",
+    "sell": "k_spmv_sell<double, short>",
+    "vector": "k_spmv_vector<double, L>",
+    "merge": "k_spmv_merge<double> + k_merge_fixup<double>",
+}
 
 
 def parse():
@@ -39,6 +45,8 @@ def parse():
     p.add_argument("--warmup", type=int, default=2)
     p.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "serve"])
     p.add_argument("--spmvs", type=int, default=100)
+    p.add_argument("--cold-spmvs", type=int, default=20,
+                   help="SpMVs timed after evicting the Infinity Cache (after the timed steps)")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-iters", type=int, default=200)
     p.add_argument("--graph-k", type=int, default=8)
@@ -191,7 +199,24 @@ def bench_c2(args):
     relmx = oracle.nrm2(b - oracle.spmv(A, xm)) / bn
     spmv_avg_us = float(np.mean(spmv_us))
     achieved = info.bytes_spmv_f64 / (spmv_avg_us * 1e-6) / 1e9
-    traffic = traffic_from_profiles(SPMV_KERNEL + "@c2", info.bytes_spmv_f64)
+    kname = spk.KERNEL_NAMES[info.kernel]
+    spmv_kernel = SPMV_KERNELS[kname]
+    traffic = traffic_from_profiles(spmv_kernel + "@c2", info.bytes_spmv_f64)
+
+    # cold Infinity Cache: each SpMV after writing 1 GiB of scratch (outside
+    # the timed steps; events bracket the SpMV only)
+    scratch = torch.empty((1 << 30) // 8, dtype=torch.float64, device="cuda")
+    cold_us = []
+    for _ in range(args.cold_spmvs):
+        spk.cache_flush(scratch)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        spk.mat_mult(M, xs, ys)
+        e1.record()
+        torch.cuda.synchronize()
+        cold_us.append(e0.elapsed_time(e1) * 1e3)
+    del scratch
+    cold_avg = float(np.mean(cold_us)) if cold_us else float("nan")
 
     out = {
         "metric": "CSR SpMV HBM GB/s; PCG solves/s to rtol 1e-8, FP64 vs mixed; p50/p99 lat",
@@ -210,12 +235,18 @@ def bench_c2(args):
             "workload": "3D 7-point Laplacian 128^3 (n=2097152, nnz=14581760), FP64 CSR int32, "
                         "rhs uniform[-1,1) seed 0; step = FP64 Jacobi-PCG + mixed Jacobi-PCG to "
                         f"rtol 1e-8 + {S} standalone SpMVs",
-            "n": info.n, "nnz": info.nnz, "spmv_kernel": spk.KERNEL_NAMES[info.kernel],
-            "rows_per_tile": info.lanes, "graph_k": args.graph_k,
+            "n": info.n, "nnz": info.nnz, "spmv_kernel": kname,
+            "kernel_param": info.lanes, "graph_k": args.graph_k,
         },
         "spmv": {
             "us_avg": spmv_avg_us, "us_p50": pct(spmv_us, 50), "us_p99": pct(spmv_us, 99),
             "gbps": achieved, "bytes": info.bytes_spmv_f64,
+            "format_bytes": info.format_bytes_spmv_f64,
+            "format_gbps": info.format_bytes_spmv_f64 / (spmv_avg_us * 1e-6) / 1e9,
+            "stored_nnz": info.stored_nnz,
+            "cold_us_avg": cold_avg,
+            "cold_gbps": info.bytes_spmv_f64 / (cold_avg * 1e-6) / 1e9,
+            "cold_format_gbps": info.format_bytes_spmv_f64 / (cold_avg * 1e-6) / 1e9,
         },
         "pcg_fp64": {
             "solves_per_s": 1e3 / float(np.median(t64)), "ms_p50": pct(t64, 50), "ms_p99": pct(t64, 99),
@@ -232,11 +263,15 @@ def bench_c2(args):
             "speedup_vs_fp64": float(np.median(t64)) / float(np.median(tmx)),
         },
         "roofline": {
-            "kernel": SPMV_KERNEL, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+            "kernel": spmv_kernel, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
             "bytes_per_launch": info.bytes_spmv_f64,
-            "note": "12 nnz + 4 (n+1) + 16 n algorithmic bytes per launch; back-to-back launches, "
-                    "so the 217 MB working set can be partly served by the 256 MB Infinity Cache",
+            "format_bytes_per_launch": info.format_bytes_spmv_f64,
+            "note": "achieved = 12 nnz + 4 (n+1) + 16 n algorithmic (CSR, FP64) bytes per launch / "
+                    "event-timed average of the back-to-back launches of the timed steps; the "
+                    "kernel reads format_bytes_per_launch from its own storage, and its working "
+                    "set can be partly served by the 256 MB Infinity Cache (spmv.cold_* gives "
+                    "the same launch after evicting it)",
         },
     }
     if not args.no_cpu_baseline:
@@ -307,7 +342,7 @@ def bench_c3(args):
         "config": {"workload": "3D 27-point lognormal diffusion 160^3 (n=4096000, nnz=109215352), "
                                "rhs uniform seed 0; mixed CG (FP32 values/accumulate inside, FP64 "
                                "residual/update/test) vs FP64", "kernel": spk.KERNEL_NAMES[info.kernel],
-                   "rows_per_tile": info.lanes},
+                   "kernel_param": info.lanes},
         "fp64": {"solves_per_s": 1 / m64, "ms": m64 * 1e3, "iterations": r64.iterations,
                  "us_per_iter": m64 * 1e6 / max(r64.iterations, 1),
                  "gbps": solve_bytes(info, r64) / m64 / 1e9, "true_rel_residual_oracle": rel64},

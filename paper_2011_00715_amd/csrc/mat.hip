@@ -87,6 +87,26 @@ __global__ void k_row_stats(int n, int64_t nnz, const int32_t *__restrict__ rowp
 }
 
 // Column range and (optionally) strict ascending order; needs a valid rowptr.
+// Entries of a SELL-64 layout: one thread per slice of 64 rows adds 64 x the
+// slice's longest row (rowptr already validated).
+__global__ void k_slice_pad(int n, const int32_t *__restrict__ rowptr, RowStats *__restrict__ out)
+{
+    const int ns = (n + 63) / 64;
+    unsigned long long acc = 0;
+    for (int s = blockIdx.x * blockDim.x + threadIdx.x; s < ns; s += gridDim.x * blockDim.x) {
+        const int r0 = s * 64, r1 = min(r0 + 64, n);
+        int mx = 0;
+        int prev = rowptr[r0];
+        for (int i = r0; i < r1; ++i) {
+            const int e = rowptr[i + 1];
+            mx = max(mx, e - prev);
+            prev = e;
+        }
+        acc += 64ULL * (unsigned long long)mx;
+    }
+    if (acc) atomicAdd(&out->sell_padded, acc);
+}
+
 __global__ void k_check_cols(int n, const int32_t *__restrict__ rowptr,
                              const int32_t *__restrict__ col, int check_sorted,
                              RowStats *__restrict__ out)
@@ -267,8 +287,8 @@ int launch_spmv(const spk_mat *A, const V *val, const V *x, V *y, hipStream_t s,
         }
         break;
     case SPK_KERNEL_SELL: {
-        if (gst) {
-            set_error("internal: gated SELL SpMV");
+        if (gst || !A->sell_cw) {
+            set_error("internal: gated SELL SpMV or no SELL layout");
             return SPK_EINVAL;
         }
         const SellView sv{A->sell_ptr, A->sell_col, A->sell_len};
@@ -392,7 +412,7 @@ static bool merge_fits(const spk_mat *A) { return (int64_t)A->n + A->nnz < 0x7ff
 
 // Row-length statistics -> kernel family (stream for short, even rows; vector
 // for long, even rows; merge-path for skewed lengths).
-static void choose_kernel(spk_mat *A)
+static void choose_kernel(spk_mat *A, bool allow_sell = true)
 {
     const RowStats &S = A->stats;
     const double mean = A->n ? (double)S.sum_len / A->n : 0.0;
@@ -400,7 +420,16 @@ static void choose_kernel(spk_mat *A)
     int R = 0;
     for (int t = 0; t < 6; ++t)
         if (S.tile_max[t] <= cap) { R = kTileRs[t]; break; }
-    if (S.max_len <= 64 && R >= 32) {
+    // SELL-64 with int16 offsets: short rows of similar length within each
+    // slice and a band of +-32767 (stencils); it reads 10 bytes per FP64
+    // nonzero instead of 12 and needs no LDS staging
+    const bool sell_ok = allow_sell && A->n >= kSell && S.max_len <= 64 && S.max_delta <= 32767 &&
+                         (double)S.sell_padded <= 1.15 * (double)A->nnz &&
+                         S.sell_padded < 0x7fff0000ULL;
+    if (sell_ok) {
+        A->kernel = SPK_KERNEL_SELL;
+        A->R = 256;
+    } else if (S.max_len <= 64 && R >= 32) {
         A->kernel = SPK_KERNEL_STREAM;
         A->R = R;
     } else if ((mean >= 8 && S.max_len <= 8 * mean + 8) || !merge_fits(A)) {
@@ -441,6 +470,11 @@ void free_workspace(spk_mat *A);
 
 static void free_sell(spk_mat *A)
 {
+    if (A->sell_cw) {
+        const int64_t ns = (A->n + kSell - 1) / kSell;
+        A->bytes -= 4 * (ns + 1) + (int64_t)(A->sell_cw + 8) * A->sell_nnz + A->n;
+        if (A->sell_val32) A->bytes -= 4 * A->sell_nnz;
+    }
     hipFree(A->sell_ptr);
     hipFree(A->sell_col);
     hipFree(A->sell_len);
@@ -645,6 +679,8 @@ static int create_impl(int32_t n, int64_t nnz, const int32_t *rowptr, const int3
             break;
         }
         if (n > 0) {
+            hipLaunchKernelGGL(k_slice_pad, dim3(grid_for(ceil_div(n, 64))), dim3(kBlock), 0, s, n,
+                               A->rowptr, dst);
             hipLaunchKernelGGL(k_check_cols, dim3(grid_for(n)), dim3(kBlock), 0, s, n, A->rowptr,
                                A->col, (flags & SPK_MAT_VALIDATE) ? 1 : 0, dst);
             hipLaunchKernelGGL(k_diag_inv, dim3(grid_for(n)), dim3(kBlock), 0, s, n, A->rowptr,
@@ -689,7 +725,17 @@ static int create_impl(int32_t n, int64_t nnz, const int32_t *rowptr, const int3
     }
     if (A->kernel == SPK_KERNEL_SELL) {
         rc = setup_sell(A, s, 0);
-        if (rc) return rc;
+        if (rc) {
+            if (getenv("SPK_FORCE_KERNEL")) return rc;
+            free_sell(A);  // the layout did not fit: take the next family
+            choose_kernel(A, false);
+            if (A->kernel != SPK_KERNEL_STREAM) A->R = 256;
+            apply_partition(A);
+            if (A->kernel == SPK_KERNEL_MERGE) {
+                rc = setup_merge(A, s);
+                if (rc) return rc;
+            }
+        }
     }
     if (flags & SPK_MAT_MIXED) {
         rc = ensure_f32(A, s);
@@ -797,6 +843,20 @@ int spk_mat_set_kernel(spk_mat *A, int kernel, int32_t param)
         const int rc = setup_merge(A, nullptr);
         if (rc) return rc;
         SPK_HIP(hipStreamSynchronize(nullptr));
+    }
+    if (kernel == SPK_KERNEL_AUTO && A->kernel == SPK_KERNEL_SELL) {
+        int rc = setup_sell(A, nullptr, 0);
+        if (rc == SPK_OK && A->val32) rc = ensure_f32(A, nullptr);
+        if (rc == SPK_OK) rc = hipStreamSynchronize(nullptr) == hipSuccess ? SPK_OK : SPK_EHIP;
+        if (rc) {
+            free_sell(A);
+            choose_kernel(A, false);
+            if (A->kernel == SPK_KERNEL_MERGE) {
+                const int r2 = setup_merge(A, nullptr);
+                if (r2) return r2;
+                SPK_HIP(hipStreamSynchronize(nullptr));
+            }
+        }
     }
     apply_partition(A);
     free_workspace(A);  // graphs and partials depend on the partition

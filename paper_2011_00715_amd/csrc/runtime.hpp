@@ -18,6 +18,7 @@ struct RowStats {
     int32_t max_delta;       // max |col - row| over the stored entries
     int32_t zero_diag;       // rows without a nonzero diagonal
     int32_t tile_max[6];     // max nonzeros in an aligned tile of 256,128,64,32,16,8 rows
+    unsigned long long sell_padded;  // entries of a SELL-64 layout (64 x longest row per slice)
     int32_t hist[33];        // rows by bit length of their length
 };
 

@@ -57,7 +57,7 @@ def test_c2_spmv_and_pcg():
     A = spkgen.laplace3d7(128)
     assert (A.n, A.nnz) == (2097152, 14581760)
     M = mat_on_gpu(spk, A, flags=spk.MAT_MIXED)
-    assert spk.KERNEL_NAMES[M.info.kernel] == "stream" and M.info.lanes == 256
+    assert spk.KERNEL_NAMES[M.info.kernel] == "sell" and M.info.lanes == 16  # int16 offsets
     rows = _sample_rows(A.n)
     # bit-exact on integer data, 1e-14 on the bench's x (rhs of seed 0)
     xi = np.random.default_rng(3).integers(-100, 100, A.n).astype(np.float64)
@@ -65,6 +65,12 @@ def test_c2_spmv_and_pcg():
     assert np.array_equal(yg, yo)
     b = spkgen.rhs_uniform(A.n, 0)
     _spmv_sampled(spk, M, A, b, rows)
+    # the stream family on the same matrix, then back to the selected one
+    spk.mat_set_kernel(M, spk.KERNEL_STREAM, 0)
+    assert np.array_equal(_spmv_sampled(spk, M, A, xi, rows, tol=0.0)[0], yo)
+    _spmv_sampled(spk, M, A, b, rows)
+    spk.mat_set_kernel(M, spk.KERNEL_AUTO, 0)
+    assert spk.KERNEL_NAMES[M.info.kernel] == "sell"
     x64, r64 = _solve(spk, M, b)
     xo, ro, ho = oracle.pcg(A, b, hist_len=40)
     assert r64.reason == spk.CONVERGED_RTOL
@@ -83,7 +89,7 @@ def test_c3_fp64_and_mixed():
     A = spkgen.diffusion3d27_lognormal(160, seed=0)
     assert (A.n, A.nnz) == (4096000, 109215352)
     M = mat_on_gpu(spk, A, flags=spk.MAT_MIXED)
-    assert spk.KERNEL_NAMES[M.info.kernel] == "stream"
+    assert spk.KERNEL_NAMES[M.info.kernel] == "sell"
     b = spkgen.rhs_uniform(A.n, 0)
     _spmv_sampled(spk, M, A, b, _sample_rows(A.n, 1))
     bn = oracle.nrm2(b)

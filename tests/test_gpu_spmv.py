@@ -197,7 +197,9 @@ def test_kernel_selection():
     for name, A, _ in _matrices():
         M = mat_on_gpu(spk, A)
         sel[name] = spk.KERNEL_NAMES[M.info.kernel]
-    assert sel["lap3d_23"] == "stream" and sel["diff27_13"] == "stream"
+    # banded short rows: SELL-64 with int16 offsets; skewed rows: merge path
+    assert sel["lap3d_23"] == "sell" and sel["diff27_13"] == "sell"
+    assert sel["lap2d_64"] == "sell" and sel["int_random_300"] != "sell"
     assert sel["powerlaw_30k"] == "merge"
 
 
