@@ -267,6 +267,8 @@ def bench_c2(args):
             "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
             "bytes_per_launch": info.bytes_spmv_f64,
             "format_bytes_per_launch": info.format_bytes_spmv_f64,
+            "achieved_cold": info.bytes_spmv_f64 / (cold_avg * 1e-6) / 1e9,
+            "frac_cold": info.bytes_spmv_f64 / (cold_avg * 1e-6) / 1e9 / HBM_PEAK_GBS,
             "note": "achieved = 12 nnz + 4 (n+1) + 16 n algorithmic (CSR, FP64) bytes per launch / "
                     "event-timed average of the back-to-back launches of the timed steps; the "
                     "kernel reads format_bytes_per_launch from its own storage, and its working "
