@@ -47,6 +47,7 @@ template <> struct Vecs<double> {
     __device__ static double *p(const SysDesc &d) { return d.p; }
     __device__ static double *q(const SysDesc &d) { return d.q; }
     __device__ static double *x(const SysDesc &d) { return d.x; }
+    __device__ static bool present(const SysDesc &) { return true; }
     static constexpr int gate = kGateInner64;
     static constexpr int mixed = 0;
 };
@@ -58,6 +59,8 @@ template <> struct Vecs<float> {
     __device__ static float *p(const SysDesc &d) { return d.p32; }
     __device__ static float *q(const SysDesc &d) { return d.q32; }
     __device__ static float *x(const SysDesc &d) { return d.d32; }
+    // FP64 systems of a mixed batch have no FP32 vectors
+    __device__ static bool present(const SysDesc &d) { return d.r32 != nullptr; }
     static constexpr int gate = kGateInner32;
     static constexpr int mixed = 1;
 };
@@ -105,6 +108,43 @@ __device__ __forceinline__ void rows_unrolled(int rb, int re, F &&f)
         }
     }
 }
+
+// Like rows_unrolled, but the loads of the first chunk are issued before
+// `mid()` runs, so that the latency of mid's own loads (state, partial sums)
+// overlaps them.  mid runs once in every thread (it may hold barriers) and
+// returns false to stop before anything is stored.
+template <class L, class Mid, class F>
+__device__ __forceinline__ void rows_prefetched(int rb, int re, L &&load, Mid &&mid, F &&use)
+{
+    constexpr int U = 4;
+    using T = decltype(load(0));
+    T v[U];
+    int i0 = rb + (int)threadIdx.x;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int i = i0 + u * kBlock;
+        if (i < re) v[u] = load(i);
+    }
+    if (!mid()) return;
+    while (i0 < re) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int i = i0 + u * kBlock;
+            if (i < re) use(i, v[u]);
+        }
+        i0 += kBlock * U;
+        if (i0 >= re) break;
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int i = i0 + u * kBlock;
+            if (i < re) v[u] = load(i);
+        }
+    }
+}
+
+template <class V> struct Trio {
+    V a, b, c;
+};
 
 // ------------------------------------------------------------------ state init
 // One thread: reset the scalars of one system for a new solve.
@@ -220,7 +260,7 @@ __global__ __launch_bounds__(kBlock) void k_resid_sell(B a)
     double *__restrict__ r = d.r;
     const SellView sv{d.sell_ptr, d.sell_col, d.sell_len};
     double rr = 0.0, bb = 0.0;
-    sell_rows<double, CI>(rb, re, sv, d.sell_val, d.x, [&](int i, double y) {
+    sell_rows<double, CI>(rb, re, sv, d.sell_val, d.x, [] { return true; }, [&](int i, double y) {
         const double bi = b[i];
         const double ri = bi - y;
         r[i] = ri;
@@ -498,7 +538,7 @@ __global__ __launch_bounds__(kBlock) void k_pcg_spmv_sell(B a)
     int j;
     SysDesc d;
     if (!locate(a, j, d)) return;
-    if (!gate_open(d.st, Vecs<V>::gate)) return;
+    const Gate g = load_gate(d.st);
     int rb, re;
     row_range(d, j, rb, re);
     const V *__restrict__ p = Vecs<V>::p(d);
@@ -506,10 +546,14 @@ __global__ __launch_bounds__(kBlock) void k_pcg_spmv_sell(B a)
     const V *__restrict__ val = sell_vals<V>(d);
     const SellView sv{d.sell_ptr, d.sell_col, d.sell_len};
     V acc = V(0);
-    sell_rows<V, CI>(rb, re, sv, val, p, [&](int i, V y) {
-        q[i] = y;
-        acc = fma(y, p[i], acc);
-    });
+    const bool run = gate_ok(g, Vecs<V>::gate);
+    sell_rows<V, CI>(
+        rb, re, sv, val, p, [&] { return run; },
+        [&](int i, V y) {
+            q[i] = y;
+            acc = fma(y, p[i], acc);
+        });
+    if (!run) return;
     const double blk = block_sum((double)acc, red);
     if (threadIdx.x == 0) d.partials[kPartPq * d.nblk + j] = blk;
 }
@@ -544,28 +588,37 @@ __global__ __launch_bounds__(kBlock) void k_pcg_update(B a)
     int j;
     SysDesc d;
     if (!locate(a, j, d)) return;
+    if (!Vecs<V>::present(d)) return;
     const SysState *st = d.st;
-    const Gate g = load_gate(st);
-    const double rho = st->rho;
-    const double eta = reduce_partials(d.partials + kPartPq * d.nblk, d.nblk, red);
-    if (!gate_ok(g, Vecs<V>::gate)) return;
-    if (!(eta > 0.0) || !finite(eta)) return;
     int rb, re;
     row_range(d, j, rb, re);
-    const V nalpha = (V)(-(rho / eta));
     V *__restrict__ r = Vecs<V>::r(d);
     V *__restrict__ z = Vecs<V>::z(d);
     const V *__restrict__ q = Vecs<V>::q(d);
     const V *__restrict__ dinv = Vecs<V>::dinv(d);
+    V nalpha = V(0);
     V rz = V(0), rr = V(0);
-    rows_unrolled(rb, re, [&](int i) {
-        const V ri = fma(nalpha, q[i], r[i]);
-        const V zi = dinv[i] * ri;
-        r[i] = ri;
-        z[i] = zi;
-        rz = fma(ri, zi, rz);
-        rr = fma(ri, ri, rr);
-    });
+    bool run = false;
+    rows_prefetched(
+        rb, re, [&](int i) { return Trio<V>{r[i], q[i], dinv[i]}; },
+        [&]() {
+            const Gate g = load_gate(st);
+            const double rho = st->rho;
+            const double eta = reduce_partials(d.partials + kPartPq * d.nblk, d.nblk, red);
+            if (!gate_ok(g, Vecs<V>::gate) || !(eta > 0.0) || !finite(eta)) return false;
+            nalpha = (V)(-(rho / eta));
+            run = true;
+            return true;
+        },
+        [&](int i, const Trio<V> &v) {
+            const V ri = fma(nalpha, v.b, v.a);
+            const V zi = v.c * ri;
+            r[i] = ri;
+            z[i] = zi;
+            rz = fma(ri, zi, rz);
+            rr = fma(ri, ri, rr);
+        });
+    if (!run) return;
     const double RZb = block_sum((double)rz, red);
     const double RRb = block_sum((double)rr, red);
     if (threadIdx.x == 0) {
@@ -645,37 +698,33 @@ __global__ __launch_bounds__(kBlock) void k_pcg_px(B a, int prelude)
     int j;
     SysDesc d;
     if (!locate(a, j, d)) return;
+    if (!Vecs<V>::present(d)) return;
     const SysState *st = d.st;
-    const int mixed = st->mixed;
-    const int cm = st->cmode;
-    const double alpha64 = st->alpha, beta64 = st->beta;
-    if (mixed != Vecs<V>::mixed) return;
-    if (cm == 0 || (cm == 3) != (prelude != 0)) return;
-    if (cm == 3) {
-        int rb, re;
-        row_range(d, j, rb, re);
-        const V beta = (V)beta64;
-        V *__restrict__ p = Vecs<V>::p(d);
-        const V *__restrict__ z = Vecs<V>::z(d);
-        rows_unrolled(rb, re, [&](int i) { p[i] = fma(beta, p[i], z[i]); });
-        return;
-    }
     int rb, re;
     row_range(d, j, rb, re);
-    const V alpha = (V)alpha64;
-    const V beta = (V)beta64;
     V *__restrict__ x = Vecs<V>::x(d);
     V *__restrict__ p = Vecs<V>::p(d);
     const V *__restrict__ z = Vecs<V>::z(d);
-    if (cm == 2) {
-        rows_unrolled(rb, re, [&](int i) {
-            const V pi = p[i];
-            x[i] = fma(alpha, pi, x[i]);
-            p[i] = fma(beta, pi, z[i]);
+    int cm = 0;
+    V alpha = V(0), beta = V(0);
+    rows_prefetched(
+        rb, re, [&](int i) { return Trio<V>{p[i], z[i], x[i]}; },
+        [&]() {
+            const int mixed = st->mixed;
+            cm = st->cmode;
+            alpha = (V)st->alpha;
+            beta = (V)st->beta;
+            if (mixed != Vecs<V>::mixed) return false;
+            return cm != 0 && (cm == 3) == (prelude != 0);
+        },
+        [&](int i, const Trio<V> &v) {
+            if (cm == 3) {  // p only: CG continues after a reliable update
+                p[i] = fma(beta, v.a, v.b);
+            } else {
+                x[i] = fma(alpha, v.a, v.c);
+                if (cm == 2) p[i] = fma(beta, v.a, v.b);
+            }
         });
-    } else {
-        rows_unrolled(rb, re, [&](int i) { x[i] = fma(alpha, p[i], x[i]); });
-    }
 }
 
 }  // namespace spk

@@ -183,14 +183,13 @@ struct SellView {
     const uint8_t *len;    // row lengths
 };
 
-// Row sum of lane `lane` in slice s; entries in column order, FMA.
+// Row sum of lane `lane` of the slice starting at element b with slen
+// entries per row; the row has rlen of them.  Entries in column order, FMA.
 template <class V, class CI, int U = 8>
 __device__ __forceinline__ V sell_row(const SellView &sv, const V *__restrict__ val,
-                                      const V *__restrict__ x, int s, int lane, int row)
+                                      const V *__restrict__ x, int32_t b, int slen, int rlen,
+                                      int lane, int row)
 {
-    const int32_t b = sv.ptr[s];
-    const int slen = (sv.ptr[s + 1] - b) / kSell;
-    const int rlen = sv.len[row];
     const CI *__restrict__ col = reinterpret_cast<const CI *>(sv.col) + b + lane;
     const V *__restrict__ v = val + b + lane;
     V acc = V(0);
@@ -211,17 +210,36 @@ __device__ __forceinline__ V sell_row(const SellView &sv, const V *__restrict__ 
 }
 
 // Rows [r0, r1) of a tile range, one slice per wavefront at a time; fn(row, y)
-// is called by the lane that owns the row.  r0 is a multiple of 64.
-template <class V, class CI, class Fn>
+// is called by the lane that owns the row.  r0 is a multiple of 64.  The
+// first slice's header is loaded before go() is asked whether to run (go
+// holds no barrier: the waves of a block may own different slice counts).
+template <class V, class CI, class Go, class Fn>
 __device__ __forceinline__ void sell_rows(int r0, int r1, const SellView &sv,
                                           const V *__restrict__ val, const V *__restrict__ x,
-                                          Fn &&fn)
+                                          Go &&go, Fn &&fn)
 {
     const int lane = threadIdx.x & (kWave - 1);
     const int w = threadIdx.x / kWave;
-    for (int s = r0 / kSell + w; s * kSell < r1; s += kBlock / kWave) {
+    int s = r0 / kSell + w;
+    int32_t b = 0, e = 0;
+    int rlen = 0;
+    if (s * kSell < r1) {
+        b = sv.ptr[s];
+        e = sv.ptr[s + 1];
         const int row = s * kSell + lane;
-        if (row < r1) fn(row, sell_row<V, CI>(sv, val, x, s, lane, row));
+        rlen = row < r1 ? sv.len[row] : 0;
+    }
+    if (!go()) return;
+    while (s * kSell < r1) {
+        const int row = s * kSell + lane;
+        const int slen = (e - b) / kSell;
+        if (row < r1) fn(row, sell_row<V, CI>(sv, val, x, b, slen, rlen, lane, row));
+        s += kBlock / kWave;
+        if (s * kSell >= r1) break;
+        b = sv.ptr[s];
+        e = sv.ptr[s + 1];
+        const int nrow = s * kSell + lane;
+        rlen = nrow < r1 ? sv.len[nrow] : 0;
     }
 }
 
@@ -233,7 +251,8 @@ __global__ __launch_bounds__(kBlock) void k_spmv_sell(int n, int R, int ntiles, 
     const int j = xcd_remap(blockIdx.x, nblk);
     int t0, t1;
     block_tiles(j, nblk, ntiles, t0, t1);
-    sell_rows<V, CI>(t0 * R, min(t1 * R, n), sv, val, x, [&](int i, V s) { y[i] = s; });
+    sell_rows<V, CI>(t0 * R, min(t1 * R, n), sv, val, x, [] { return true; },
+                     [&](int i, V s) { y[i] = s; });
 }
 
 // Layout fill: one lane per row writes its entries and the slice padding.
