@@ -406,6 +406,14 @@ static int rebuild_table(spk_server *S)
     return SPK_OK;
 }
 
+static_assert(sizeof(SysState) % sizeof(int2) == 0, "SysState is copied as 8-byte words");
+
+static __global__ void k_snapshot(const int2 *__restrict__ src, int2 *__restrict__ dst, int words)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < words) dst[i] = src[i];
+}
+
 // One batched step: K iterations of every active system.
 static int enqueue_step(spk_server *S)
 {
@@ -790,9 +798,12 @@ int spk_server_progress(spk_server *S, int32_t max_steps)
             const int i = S->inflight.empty() ? 0 : (S->inflight.back() ^ 1);
             if ((int)S->inflight.size() >= kDepth) SPK_TRY_RC(drain_one_step(S));
             SPK_TRY_RC(enqueue_step(S));
-            const hipError_t e = hipMemcpyAsync(S->p_states[i], S->d_states,
-                                                sizeof(SysState) * S->slots.size(),
-                                                hipMemcpyDeviceToHost, S->s);
+            // snapshot of every slot's state into pinned host memory (a
+            // kernel's stores: a device-to-host copy would run as a blit)
+            const int words = (int)(sizeof(SysState) * S->slots.size() / sizeof(int2));
+            hipLaunchKernelGGL(k_snapshot, dim3(ceil_div(words, kBlock)), dim3(kBlock), 0, S->s,
+                               (const int2 *)S->d_states, (int2 *)S->p_states[i], words);
+            const hipError_t e = hipGetLastError();
             if (e != hipSuccess) return hip_fail(e, "state snapshot", __FILE__, __LINE__);
             const hipError_t e2 = hipEventRecord(S->ev_step[i], S->s);
             if (e2 != hipSuccess) return hip_fail(e2, "event", __FILE__, __LINE__);
