@@ -41,9 +41,7 @@ struct SysState {
     int32_t iter;         // Krylov iterations done (inner ones for mixed)
     int32_t inner_iter;   // iterations of the current inner solve
     int32_t outer;        // mixed: refinement steps done
-    int32_t cmode;        // update pending from the last iteration, applied at the
-                          // start of the next one (or by the finish / refinement
-                          // kernels): 2 x and p, 3 p only, 1 x only, 0 none
+    int32_t cmode;        // next x/p update: 2 both, 1 x only (last), 0 none
     int32_t maxit;
     int32_t inner_maxit;
     int32_t max_outer;
@@ -52,8 +50,6 @@ struct SysState {
     int32_t hist_len;
     int32_t ru;           // mixed: 1 keeps p across refinements (reliable updates)
     int32_t fresh_p;      // mixed: the next refinement starts p from z
-    int32_t pbuf;         // which of the two p buffers holds the current p
-    int32_t pad_;
     double scale;         // mixed: r32 = r / scale, x += scale d
     double rho, alpha, beta, eta;
     double rnorm, rnorm0, bnorm, thresh, rtol, atol;
@@ -79,10 +75,6 @@ struct SysDesc {
     double *x;
     double *r, *z, *p, *q;            // FP64 Krylov vectors
     float *r32, *z32, *p32, *q32, *d32;  // FP32 inner vectors (mixed)
-    double *p1;                       // second p buffer (fused SpMV kernels)
-    float *p32_1;
-    int32_t fused;                    // 1: the SpMV kernel applies the pending x/p
-                                      // update and writes the new p to the other buffer
     double *partials;                 // kNumPart * nblk
     SysState *st;
     double *hist;                     // device history (hist_len) or null

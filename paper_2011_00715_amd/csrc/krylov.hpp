@@ -10,21 +10,15 @@
 //
 // One PCG iteration (textbook preconditioned CG; the paper names CG in
 // Sec. 5.5 and the Jacobi smoother in Sec. 5.3):
-//   A   apply the update left pending by the last iteration (x += alpha p,
-//       p = z + beta p), q = A p, per-block p.q.  The stream and SELL
-//       kernels fuse the update into the SpMV: every gathered p_j is formed
-//       on the fly as z_j + beta p_j (the same bits as the stored value) and
-//       the new p goes to the other of two buffers; the other families run
-//       it as a separate pass before the SpMV.
-//   B   eta = p.q and alpha = rho / eta (each block sums A's partials),
-//       r -= alpha q, z = D^-1 r, per-block r.z and r.r (one pass; Sec. 4
-//       Response F3: fused inner products)
-//   F_B breakdown and convergence tests, beta, and the pending update
+//   A   q = A p, per-block p.q
+//   B   eta = p.q and alpha = rho / eta    F_B  breakdown and convergence
+//       (each block sums A's partials),         tests, beta, and what C
+//       r -= alpha q, z = D^-1 r, per-block     must do next
+//       r.z and r.r (one pass; Sec. 4 Response F3: fused inner products)
+//   C   x += alpha p, p = z + beta p
 // Scalars live on the device and every kernel is a no-op once its system has
 // stopped, so a captured graph of many iterations replays without host round
-// trips (Challenge A1: fusion, graphs, pipelining).  The update pending when
-// a solve stops is applied by k_pcg_finish (FP64) or by the refinement step
-// (mixed).
+// trips (Challenge A1: fusion, graphs, pipelining).
 #pragma once
 
 #include "spmv.hpp"
@@ -53,7 +47,6 @@ template <> struct Vecs<double> {
     __device__ static double *p(const SysDesc &d) { return d.p; }
     __device__ static double *q(const SysDesc &d) { return d.q; }
     __device__ static double *x(const SysDesc &d) { return d.x; }
-    __device__ static double *pb(const SysDesc &d, int k) { return k ? d.p1 : d.p; }
     __device__ static bool present(const SysDesc &) { return true; }
     static constexpr int gate = kGateInner64;
     static constexpr int mixed = 0;
@@ -66,7 +59,6 @@ template <> struct Vecs<float> {
     __device__ static float *p(const SysDesc &d) { return d.p32; }
     __device__ static float *q(const SysDesc &d) { return d.q32; }
     __device__ static float *x(const SysDesc &d) { return d.d32; }
-    __device__ static float *pb(const SysDesc &d, int k) { return k ? d.p32_1 : d.p32; }
     // FP64 systems of a mixed batch have no FP32 vectors
     __device__ static bool present(const SysDesc &d) { return d.r32 != nullptr; }
     static constexpr int gate = kGateInner32;
@@ -164,7 +156,6 @@ static __global__ void k_state_init(SysState *st, double rtol, double atol, int 
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
     st->ru = mixed == 1;
     st->fresh_p = 1;
-    st->pbuf = 0;
     st->scale = 1.0;
     mixed = mixed != 0;
     st->status = SPK_RUNNING;
@@ -328,7 +319,6 @@ __global__ __launch_bounds__(kBlock) void k_fin_resid(B a, int purpose)
     const double rn = sqrt(rr);
     if (purpose == kResTrue) {
         st->rnorm_true = rn;
-        st->cmode = 0;  // k_pcg_finish already applied a pending x update
         return;
     }
     const double bn = sqrt(bb);
@@ -346,7 +336,6 @@ __global__ __launch_bounds__(kBlock) void k_fin_resid(B a, int purpose)
     // kResOuter: one FP64 refinement residual of a mixed solve (after the
     // update x += s d when coming from kPhaseUpdate)
     if (st->phase == kPhaseUpdate) ++st->outer;
-    st->cmode = 0;  // k_update_x applied the inner solve's last update
     const int k = st->outer;
     if (k == 0) st->rnorm0 = rn;
     if (d.hist && k < st->hist_len) d.hist[k] = rn;
@@ -386,7 +375,7 @@ __global__ __launch_bounds__(kBlock) void k_setup64(B a)
     const double *__restrict__ r = d.r;
     const double *__restrict__ dinv = d.dinv;
     double *__restrict__ z = d.z;
-    double *__restrict__ p = Vecs<double>::pb(d, d.st->pbuf);
+    double *__restrict__ p = d.p;
     double rz = 0.0;
     rows_unrolled(rb, re, [&](int i) {
         const double ri = r[i];
@@ -409,7 +398,6 @@ __global__ __launch_bounds__(kBlock) void k_fin_setup64(B a)
     if (st->status != SPK_RUNNING) return;
     const double RZ = reduce_partials(d.partials + kPartRz * d.nblk, d.nblk, red);
     if (threadIdx.x != 0) return;
-    st->cmode = 0;  // p = z was stored by k_setup64
     if (!finite(RZ)) st->status = SPK_DIVERGED_NANORINF;
     else if (RZ < 0.0) st->status = SPK_DIVERGED_INDEFINITE_PC;
     else if (RZ == 0.0) st->status = SPK_DIVERGED_BREAKDOWN;
@@ -443,7 +431,7 @@ __global__ __launch_bounds__(kBlock) void k_setup32(B a)
     const float *__restrict__ dinv = d.dinv32;
     float *__restrict__ r32 = d.r32;
     float *__restrict__ z32 = d.z32;
-    float *__restrict__ p32 = Vecs<float>::pb(d, st->pbuf);
+    float *__restrict__ p32 = d.p32;
     float *__restrict__ d32 = d.d32;
     float rz = 0.f, rr = 0.f;
     rows_unrolled(rb, re, [&](int i) {
@@ -488,7 +476,7 @@ __global__ __launch_bounds__(kBlock) void k_fin_setup32(B a)
         if (st->ru && !st->fresh_p) {
             // reliable update: continue the same CG with the true residual
             st->beta = RZ / st->rho;
-            st->cmode = 3;  // p32 = z32 + beta p32 at the next iteration
+            st->cmode = 3;  // p32 = z32 + beta p32 before the next SpMV
         }
         st->fresh_p = 0;
         st->rho = RZ;
@@ -510,58 +498,11 @@ __global__ __launch_bounds__(kBlock) void k_update_x(B a)
     const double sc = st->scale;
     const float *__restrict__ d32 = d.d32;
     double *__restrict__ x = d.x;
-    if (st->cmode == 1) {  // the inner solve's last d += alpha p is still pending
-        const float alpha = (float)st->alpha;
-        const float *__restrict__ p32 = Vecs<float>::pb(d, st->pbuf);
-        rows_unrolled(rb, re, [&](int i) {
-            const float di = fmaf(alpha, p32[i], d32[i]);
-            x[i] = fma(sc, (double)di, x[i]);
-        });
-    } else {
-        rows_unrolled(rb, re, [&](int i) { x[i] = fma(sc, (double)d32[i], x[i]); });
-    }
+    rows_unrolled(rb, re, [&](int i) { x[i] = fma(sc, (double)d32[i], x[i]); });
 }
 
 // ------------------------------------------------------------------ iteration
-// Gather of p for the fused kernels: the new p_j = z_j + beta p_j formed on
-// the fly from the previous p, or the stored p after a (re)start.
-template <class V>
-struct PGather {
-    const V *__restrict__ pp;
-    const V *__restrict__ z;
-    V beta;
-    __device__ __forceinline__ V operator()(int c) const { return fma(beta, pp[c], z[c]); }
-};
-
-// Pending update of the fused A kernels, read once per block.
-template <class V>
-struct Pending {
-    int run;          // gate open
-    int cm;           // cmode at the start of the iteration
-    V alpha, beta;
-    const V *pp;      // current p (previous iteration's)
-    V *pn;            // the other buffer: receives the new p
-};
-
-template <class V>
-__device__ __forceinline__ Pending<V> load_pending(const SysDesc &d)
-{
-    const SysState *st = d.st;
-    const Gate g = load_gate(st);
-    const int cm = st->cmode, pb = st->pbuf;
-    const double alpha = st->alpha, beta = st->beta;
-    Pending<V> P;
-    P.run = gate_ok(g, Vecs<V>::gate);
-    P.cm = cm;
-    P.alpha = (V)alpha;
-    P.beta = (V)beta;
-    P.pp = Vecs<V>::pb(d, pb);
-    P.pn = Vecs<V>::pb(d, pb ^ 1);
-    return P;
-}
-
-// A, stream tile kernel: pending update fused into the gather and the row
-// epilogue, q = A p, per-block p.q.
+// A: q = A p with the stream tile kernel, p.q fused into the row epilogue.
 template <class V, class B>
 __global__ __launch_bounds__(kBlock) void k_pcg_spmv_stream(B a)
 {
@@ -570,48 +511,26 @@ __global__ __launch_bounds__(kBlock) void k_pcg_spmv_stream(B a)
     int j;
     SysDesc d;
     if (!locate(a, j, d)) return;
-    if (!Vecs<V>::present(d)) return;
-    const Pending<V> P = load_pending<V>(d);
-    if (!P.run) return;
+    if (!gate_open(d.st, Vecs<V>::gate)) return;
     int t0, t1;
     block_tiles(j, d.nblk, d.ntiles, t0, t1);
+    const V *__restrict__ p = Vecs<V>::p(d);
     V *__restrict__ q = Vecs<V>::q(d);
-    V *__restrict__ x = Vecs<V>::x(d);
-    const V *__restrict__ z = Vecs<V>::z(d);
     const V *__restrict__ val = Vecs<V>::val(d);
     V acc = V(0);
-    if (P.cm >= 2) {
-        const PGather<V> gx{P.pp, z, P.beta};
-        V *__restrict__ pn = P.pn;
-        const V *__restrict__ pp = P.pp;
-        for (int t = t0; t < t1; ++t) {
-            const int r0 = t * d.R;
-            const int r1 = min(r0 + d.R, d.n);
-            stream_tile_g<V>(r0, r1, d.rowptr, d.col, val, gx, sm, [&](int i, V y) {
-                const V pi = gx(i);
-                pn[i] = pi;
-                if (P.cm == 2) x[i] = fma(P.alpha, pp[i], x[i]);
-                q[i] = y;
-                acc = fma(y, pi, acc);
-            });
-        }
-    } else {
-        const V *__restrict__ p = P.pp;
-        for (int t = t0; t < t1; ++t) {
-            const int r0 = t * d.R;
-            const int r1 = min(r0 + d.R, d.n);
-            stream_tile<V>(r0, r1, d.rowptr, d.col, val, p, sm, [&](int i, V y) {
-                q[i] = y;
-                acc = fma(y, p[i], acc);
-            });
-        }
+    for (int t = t0; t < t1; ++t) {
+        const int r0 = t * d.R;
+        const int r1 = min(r0 + d.R, d.n);
+        stream_tile<V>(r0, r1, d.rowptr, d.col, val, p, sm, [&](int i, V y) {
+            q[i] = y;
+            acc = fma(y, p[i], acc);
+        });
     }
     const double blk = block_sum((double)acc, red);
     if (threadIdx.x == 0) d.partials[kPartPq * d.nblk + j] = blk;
 }
 
-// A, SELL-64 layout (one slice of 64 rows per wavefront): pending update
-// fused as in the stream kernel, q = A p, per-block p.q.
+// A with the SELL-64 layout: one slice of 64 rows per wavefront, p.q fused.
 template <class V, class CI, class B>
 __global__ __launch_bounds__(kBlock) void k_pcg_spmv_sell(B a)
 {
@@ -619,73 +538,24 @@ __global__ __launch_bounds__(kBlock) void k_pcg_spmv_sell(B a)
     int j;
     SysDesc d;
     if (!locate(a, j, d)) return;
-    if (!Vecs<V>::present(d)) return;
-    const Pending<V> P = load_pending<V>(d);
+    const Gate g = load_gate(d.st);
     int rb, re;
     row_range(d, j, rb, re);
+    const V *__restrict__ p = Vecs<V>::p(d);
     V *__restrict__ q = Vecs<V>::q(d);
-    V *__restrict__ x = Vecs<V>::x(d);
-    const V *__restrict__ z = Vecs<V>::z(d);
     const V *__restrict__ val = sell_vals<V>(d);
     const SellView sv{d.sell_ptr, d.sell_col, d.sell_len};
     V acc = V(0);
-    if (P.cm >= 2) {
-        const PGather<V> gx{P.pp, z, P.beta};
-        V *__restrict__ pn = P.pn;
-        const V *__restrict__ pp = P.pp;
-        sell_rows_g<V, CI>(
-            rb, re, sv, val, gx, [&] { return P.run != 0; },
-            [&](int i, V y) {
-                const V pi = gx(i);
-                pn[i] = pi;
-                if (P.cm == 2) x[i] = fma(P.alpha, pp[i], x[i]);
-                q[i] = y;
-                acc = fma(y, pi, acc);
-            });
-    } else {
-        const V *__restrict__ p = P.pp;
-        sell_rows<V, CI>(
-            rb, re, sv, val, p, [&] { return P.run != 0; },
-            [&](int i, V y) {
-                q[i] = y;
-                acc = fma(y, p[i], acc);
-            });
-    }
-    if (!P.run) return;
+    const bool run = gate_ok(g, Vecs<V>::gate);
+    sell_rows<V, CI>(
+        rb, re, sv, val, p, [&] { return run; },
+        [&](int i, V y) {
+            q[i] = y;
+            acc = fma(y, p[i], acc);
+        });
+    if (!run) return;
     const double blk = block_sum((double)acc, red);
     if (threadIdx.x == 0) d.partials[kPartPq * d.nblk + j] = blk;
-}
-
-// A, other SpMV families (not fused): the pending update as its own pass,
-// in place (these families keep p in the first buffer).
-template <class V, class B>
-__global__ __launch_bounds__(kBlock) void k_pcg_pre(B a)
-{
-    int j;
-    SysDesc d;
-    if (!locate(a, j, d)) return;
-    if (!Vecs<V>::present(d)) return;
-    const SysState *st = d.st;
-    int rb, re;
-    row_range(d, j, rb, re);
-    V *__restrict__ x = Vecs<V>::x(d);
-    V *__restrict__ p = Vecs<V>::p(d);
-    const V *__restrict__ z = Vecs<V>::z(d);
-    int cm = 0;
-    V alpha = V(0), beta = V(0);
-    rows_prefetched(
-        rb, re, [&](int i) { return Trio<V>{p[i], z[i], x[i]}; },
-        [&]() {
-            const Gate g = load_gate(st);
-            cm = st->cmode;
-            alpha = (V)st->alpha;
-            beta = (V)st->beta;
-            return gate_ok(g, Vecs<V>::gate) && cm >= 2;
-        },
-        [&](int i, const Trio<V> &v) {
-            if (cm == 2) x[i] = fma(alpha, v.a, v.c);
-            p[i] = fma(beta, v.a, v.b);
-        });
 }
 
 // A (other SpMV kernels): q already holds A p; per-block p.q.
@@ -757,9 +627,9 @@ __global__ __launch_bounds__(kBlock) void k_pcg_update(B a)
     }
 }
 
-// F_B: convergence test and beta; cmode records the update that the next
-// iteration's A kernel (or k_pcg_finish, or the refinement step) applies:
-// 2 = x and p, 1 = the last x update only, 0 = nothing.
+// F_B: convergence test and beta; cmode tells C what to do: 2 = x and p
+// updates, 1 = the last x update only, 0 = nothing.  F_B runs every
+// iteration so that it can reset cmode after the last update.
 template <class V, class B>
 __global__ __launch_bounds__(kBlock) void k_fin_update(B a)
 {
@@ -773,16 +643,15 @@ __global__ __launch_bounds__(kBlock) void k_fin_update(B a)
     const double inner_thresh = st->inner_thresh;
     const int iter = st->iter, inner_iter = st->inner_iter, maxit = st->maxit;
     const int inner_maxit = st->inner_maxit, hist_len = st->hist_len;
-    const int cm0 = st->cmode, pbuf = st->pbuf;
     double eta, RZ, RR;
     reduce_partials3(d.partials + kPartPq * d.nblk, d.partials + kPartRz * d.nblk,
                      d.partials + kPartRr * d.nblk, d.nblk, red, eta, RZ, RR);
     if (g.mixed != Vecs<V>::mixed) return;
-    // a stopped system keeps its pending update for the finishing kernels
-    if (!gate_ok(g, Vecs<V>::gate)) return;
+    if (!gate_ok(g, Vecs<V>::gate)) {
+        if (threadIdx.x == 0) st->cmode = 0;
+        return;
+    }
     if (threadIdx.x != 0) return;
-    // the fused A kernel of this iteration wrote the new p to the other buffer
-    if (d.fused && cm0 >= 2) st->pbuf = pbuf ^ 1;
     st->eta = eta;
     st->cmode = 0;
     if (!finite(eta)) { st->status = SPK_DIVERGED_NANORINF; return; }
@@ -820,22 +689,42 @@ __global__ __launch_bounds__(kBlock) void k_fin_update(B a)
     }
 }
 
-// Finish an FP64 solve that stopped with the last x += alpha p pending
-// (launched once, after the host saw the stop).
-template <class B>
-__global__ __launch_bounds__(kBlock) void k_pcg_finish(B a)
+// C: x += alpha p (d for mixed) and, while iterating, p = z + beta p.
+// With `prelude` set it only serves cmode 3 (the p update that continues CG
+// after a reliable update); otherwise it serves cmodes 1 and 2.
+template <class V, class B>
+__global__ __launch_bounds__(kBlock) void k_pcg_px(B a, int prelude)
 {
     int j;
     SysDesc d;
     if (!locate(a, j, d)) return;
+    if (!Vecs<V>::present(d)) return;
     const SysState *st = d.st;
-    if (st->mixed != 0 || st->status == SPK_RUNNING || st->cmode != 1) return;
     int rb, re;
     row_range(d, j, rb, re);
-    const double alpha = st->alpha;
-    const double *__restrict__ p = Vecs<double>::pb(d, st->pbuf);
-    double *__restrict__ x = d.x;
-    rows_unrolled(rb, re, [&](int i) { x[i] = fma(alpha, p[i], x[i]); });
+    V *__restrict__ x = Vecs<V>::x(d);
+    V *__restrict__ p = Vecs<V>::p(d);
+    const V *__restrict__ z = Vecs<V>::z(d);
+    int cm = 0;
+    V alpha = V(0), beta = V(0);
+    rows_prefetched(
+        rb, re, [&](int i) { return Trio<V>{p[i], z[i], x[i]}; },
+        [&]() {
+            const int mixed = st->mixed;
+            cm = st->cmode;
+            alpha = (V)st->alpha;
+            beta = (V)st->beta;
+            if (mixed != Vecs<V>::mixed) return false;
+            return cm != 0 && (cm == 3) == (prelude != 0);
+        },
+        [&](int i, const Trio<V> &v) {
+            if (cm == 3) {  // p only: CG continues after a reliable update
+                p[i] = fma(beta, v.a, v.b);
+            } else {
+                x[i] = fma(alpha, v.a, v.c);
+                if (cm == 2) p[i] = fma(beta, v.a, v.b);
+            }
+        });
 }
 
 }  // namespace spk

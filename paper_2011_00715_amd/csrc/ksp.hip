@@ -29,7 +29,6 @@ void free_workspace(spk_mat *A)
     hipFree(w->z);
     hipFree(w->p);
     hipFree(w->q);
-    hipFree(w->p1);
     hipFree(w->x);
     hipFree(w->b);
     hipFree(w->r32);
@@ -37,7 +36,6 @@ void free_workspace(spk_mat *A)
     hipFree(w->p32);
     hipFree(w->q32);
     hipFree(w->d32);
-    hipFree(w->p32_1);
     hipHostFree(w->pdesc);
     hipHostFree(w->pst);
     hipHostFree(w->pstatus);
@@ -76,7 +74,6 @@ static int get_workspace(spk_mat *A, bool mixed, Workspace **out)
         SPK_TRY(dalloc(&w->z, A->n, w));
         SPK_TRY(dalloc(&w->p, A->n, w));
         SPK_TRY(dalloc(&w->q, A->n, w));
-        SPK_TRY(dalloc(&w->p1, A->n, w));
         SPK_TRY(dalloc(&w->x, A->n, w));
         SPK_TRY(dalloc(&w->b, A->n, w));
         SPK_HIP(hipHostMalloc((void **)&w->pdesc, sizeof(SysDesc), hipHostMallocDefault));
@@ -102,9 +99,6 @@ static int get_workspace(spk_mat *A, bool mixed, Workspace **out)
         d.z = w->z;
         d.p = w->p;
         d.q = w->q;
-        d.p1 = w->p1;
-        // the stream and SELL A kernels apply the pending update themselves
-        d.fused = A->kernel == SPK_KERNEL_STREAM || A->kernel == SPK_KERNEL_SELL;
         d.partials = w->partials;
         d.st = w->st;
         d.sell_cw = A->kernel == SPK_KERNEL_SELL ? A->sell_cw : 0;
@@ -119,7 +113,6 @@ static int get_workspace(spk_mat *A, bool mixed, Workspace **out)
         SPK_TRY(dalloc(&w->p32, A->n, w));
         SPK_TRY(dalloc(&w->q32, A->n, w));
         SPK_TRY(dalloc(&w->d32, A->n, w));
-        SPK_TRY(dalloc(&w->p32_1, A->n, w));
         w->has_mixed = 1;
         SysDesc &d = w->hdesc;
         d.val32 = A->val32;
@@ -129,7 +122,6 @@ static int get_workspace(spk_mat *A, bool mixed, Workspace **out)
         d.p32 = w->p32;
         d.q32 = w->q32;
         d.d32 = w->d32;
-        d.p32_1 = w->p32_1;
         d.sell_val32 = A->sell_val32;
     }
     *out = w;
@@ -183,12 +175,12 @@ static int enqueue_iteration(spk_mat *A, Workspace *w, hipStream_t s)
         const V *val = std::is_same<V, double>::value ? (const V *)A->val : (const V *)A->val32;
         V *p = std::is_same<V, double>::value ? (V *)w->p : (V *)w->p32;
         V *q = std::is_same<V, double>::value ? (V *)w->q : (V *)w->q32;
-        hipLaunchKernelGGL((k_pcg_pre<V, One>), g, t, 0, s, b);
         SPK_TRY(launch_spmv<V>(A, val, p, q, s, w->st, Vecs<V>::gate));
         hipLaunchKernelGGL((k_pcg_pq<V, One>), g, t, 0, s, b);
     }
     hipLaunchKernelGGL((k_pcg_update<V, One>), g, t, 0, s, b);
     hipLaunchKernelGGL((k_fin_update<V, One>), one, t, 0, s, b);
+    hipLaunchKernelGGL((k_pcg_px<V, One>), g, t, 0, s, b, 0);
     SPK_HIP(hipGetLastError());
     return SPK_OK;
 }
@@ -202,6 +194,7 @@ static int enqueue_batch(spk_mat *A, Workspace *w, bool mixed, int K, hipStream_
         SPK_TRY(launch_resid(A, w, kResOuter, true, s));
         hipLaunchKernelGGL(k_setup32<One>, dim3(A->nblk), dim3(kBlock), 0, s, b);
         hipLaunchKernelGGL(k_fin_setup32<One>, dim3(1), dim3(kBlock), 0, s, b);
+        hipLaunchKernelGGL((k_pcg_px<float, One>), dim3(A->nblk), dim3(kBlock), 0, s, b, 1);
         for (int k = 0; k < K; ++k) SPK_TRY(enqueue_iteration<float>(A, w, s));
     } else {
         for (int k = 0; k < K; ++k) SPK_TRY(enqueue_iteration<double>(A, w, s));
@@ -315,7 +308,6 @@ static int solve64(spk_mat *A, Workspace *w, const spk_ksp_opts &o, bool x_given
         const int done_iter = w->pst->iter;
         const int max_batches = (std::max(o.maxit - done_iter, 0) + K - 1) / K + 2;
         if (w->pst->status == SPK_RUNNING) SPK_TRY(run_batches(A, w, false, K, use_graph, max_batches, s));
-        hipLaunchKernelGGL(k_pcg_finish<One>, dim3(A->nblk), dim3(kBlock), 0, s, batch_of(w));
         SPK_TRY(launch_resid(A, w, kResTrue, false, s));
         SPK_TRY(read_state(w, s));
         const SysState &S = *w->pst;

@@ -39,11 +39,10 @@ struct Workspace {
     double *hist = nullptr;
     int hist_cap = 0;
     double *partials = nullptr;
-    double *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr, *p1 = nullptr;
+    double *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr;
     double *x = nullptr;          // the solve's iterate (copied in and out)
     double *b = nullptr;          // the solve's right-hand side (copied in)
     float *r32 = nullptr, *z32 = nullptr, *p32 = nullptr, *q32 = nullptr, *d32 = nullptr;
-    float *p32_1 = nullptr;
     hipStream_t cap = nullptr;    // private stream used only to capture graphs
     hipGraphExec_t g64 = nullptr, gmix = nullptr;
     int g64_k = 0, gmix_k = 0;

@@ -171,9 +171,9 @@ static int64_t request_bytes(const Request &q)
 {
     const int64_t n = q.n, nz = q.nnz;
     int64_t b = align256(4 * (n + 1)) + align256(4 * nz) + align256(8 * nz) + align256(8 * n) /*dinv*/ +
-                align256(8 * n) /*b*/ + align256(8 * n) /*x*/ + 5 * align256(8 * n) /*r z p q p1*/ +
+                align256(8 * n) /*b*/ + align256(8 * n) /*x*/ + 4 * align256(8 * n) /*r z p q*/ +
                 align256(8 * kNumPart * (int64_t)std::max(q.nblk, 1));
-    if (q.mixed) b += align256(4 * nz) + align256(4 * n) + 6 * align256(4 * n);
+    if (q.mixed) b += align256(4 * nz) + align256(4 * n) + 5 * align256(4 * n);
     return b;
 }
 
@@ -276,8 +276,6 @@ static int admit(spk_server *S, Request *q, int k, int64_t off)
     d.z = (double *)take(8 * n);
     d.p = (double *)take(8 * n);
     d.q = (double *)take(8 * n);
-    d.p1 = (double *)take(8 * n);
-    d.fused = 1;  // stream kernels: the SpMV applies the pending x/p update
     d.partials = (double *)take(8 * kNumPart * (int64_t)std::max(q->nblk, 1));
     float *val32 = nullptr, *dinv32 = nullptr;
     if (q->mixed) {
@@ -288,11 +286,6 @@ static int admit(spk_server *S, Request *q, int k, int64_t off)
         d.p32 = (float *)take(4 * n);
         d.q32 = (float *)take(4 * n);
         d.d32 = (float *)take(4 * n);
-        d.p32_1 = (float *)take(4 * n);
-    }
-    if (p - (S->arena_base + off) > q->bytes) {
-        set_error("internal: slot layout exceeds its arena block");
-        return SPK_EINVAL;
     }
     d.rowptr = rowptr;
     d.col = col;
@@ -433,17 +426,20 @@ static int enqueue_step(spk_server *S)
         hipLaunchKernelGGL((k_fin_resid<kGateResid, Batch>), f, t, 0, S->s, b, (int)kResOuter);
         hipLaunchKernelGGL(k_setup32<Batch>, g, t, 0, S->s, b);
         hipLaunchKernelGGL(k_fin_setup32<Batch>, f, t, 0, S->s, b);
+        hipLaunchKernelGGL((k_pcg_px<float, Batch>), g, t, 0, S->s, b, 1);
     }
     for (int k = 0; k < K; ++k) {
         if (S->n_fp64) {
             hipLaunchKernelGGL((k_pcg_spmv_stream<double, Batch>), g, t, 0, S->s, b);
             hipLaunchKernelGGL((k_pcg_update<double, Batch>), g, t, 0, S->s, b);
             hipLaunchKernelGGL((k_fin_update<double, Batch>), f, t, 0, S->s, b);
+            hipLaunchKernelGGL((k_pcg_px<double, Batch>), g, t, 0, S->s, b, 0);
         }
         if (S->n_mixed) {
             hipLaunchKernelGGL((k_pcg_spmv_stream<float, Batch>), g, t, 0, S->s, b);
             hipLaunchKernelGGL((k_pcg_update<float, Batch>), g, t, 0, S->s, b);
             hipLaunchKernelGGL((k_fin_update<float, Batch>), f, t, 0, S->s, b);
+            hipLaunchKernelGGL((k_pcg_px<float, Batch>), g, t, 0, S->s, b, 0);
         }
     }
     SPK_HIP(hipGetLastError());
@@ -455,8 +451,6 @@ static int begin_retire(spk_server *S, int k)
     Slot &sl = S->slots[k];
     Request *q = sl.req;
     const One b = slot_batch(S, k);
-    // an FP64 solve may stop with its last x update pending
-    hipLaunchKernelGGL(k_pcg_finish<One>, dim3(sl.desc.nblk), dim3(kBlock), 0, S->s, b);
     hipLaunchKernelGGL((k_resid_stream<kGateNone, One>), dim3(sl.desc.nblk), dim3(kBlock), 0, S->s, b);
     hipLaunchKernelGGL((k_fin_resid<kGateNone, One>), dim3(1), dim3(kBlock), 0, S->s, b, (int)kResTrue);
     SPK_HIP(hipGetLastError());

@@ -62,23 +62,15 @@ struct TileLds {
     V red[kBlock / kWave];
 };
 
-// Gather of the input vector: x[c], or a value formed on the fly from
-// several vectors (the fused PCG kernels gather p = z + beta p_prev).
-template <class V>
-struct PlainGather {
-    const V *__restrict__ x;
-    __device__ __forceinline__ V operator()(int c) const { return x[c]; }
-};
-
 // One tile of rows [r0, r1) (r1 - r0 <= kBlock).  fn(row, value) is called
 // once per row, by the lane that owns it.  Products are rounded to V and
 // summed in V in column order.  Tiles with more than kCap nonzeros take the
 // block-per-row path (block-wide FMA partials and a fixed-order block sum).
-template <class V, class G, class Fn>
-__device__ __forceinline__ void stream_tile_g(int r0, int r1, const int32_t *__restrict__ rowptr,
-                                              const int32_t *__restrict__ col,
-                                              const V *__restrict__ val, const G &gx,
-                                              TileLds<V> &sm, Fn &&fn)
+template <class V, class Fn>
+__device__ __forceinline__ void stream_tile(int r0, int r1, const int32_t *__restrict__ rowptr,
+                                            const int32_t *__restrict__ col,
+                                            const V *__restrict__ val, const V *__restrict__ x,
+                                            TileLds<V> &sm, Fn &&fn)
 {
     const int nr = r1 - r0;
     for (int i = threadIdx.x; i <= nr; i += kBlock) sm.rp[i] = rowptr[r0 + i];
@@ -100,7 +92,7 @@ __device__ __forceinline__ void stream_tile_g(int r0, int r1, const int32_t *__r
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 const int k = kb + u * kBlock;
-                const V xv = gx(c[u]);
+                const V xv = x[c[u]];
                 if (k < k1) sm.prod[k - k0] = v[u] * xv;
             }
         }
@@ -118,22 +110,13 @@ __device__ __forceinline__ void stream_tile_g(int r0, int r1, const int32_t *__r
             const int e = sm.rp[i + 1];
             V s = V(0);
             for (int k = a + (int)threadIdx.x; k < e; k += kBlock)
-                s = fma(ld_stream(val + k), gx(ld_stream(col + k)), s);
+                s = fma(ld_stream(val + k), x[ld_stream(col + k)], s);
             s = block_sum(s, sm.red);
             if (threadIdx.x == 0) fn(r0 + i, s);
             __syncthreads();
         }
     }
     __syncthreads();
-}
-
-template <class V, class Fn>
-__device__ __forceinline__ void stream_tile(int r0, int r1, const int32_t *__restrict__ rowptr,
-                                            const int32_t *__restrict__ col,
-                                            const V *__restrict__ val, const V *__restrict__ x,
-                                            TileLds<V> &sm, Fn &&fn)
-{
-    stream_tile_g<V>(r0, r1, rowptr, col, val, PlainGather<V>{x}, sm, static_cast<Fn &&>(fn));
 }
 
 // Standalone stream SpMV: grid = nblk logical blocks, each a contiguous chunk
@@ -202,9 +185,9 @@ struct SellView {
 
 // Row sum of lane `lane` of the slice starting at element b with slen
 // entries per row; the row has rlen of them.  Entries in column order, FMA.
-template <class V, class CI, class G, int U = 8>
+template <class V, class CI, int U = 8>
 __device__ __forceinline__ V sell_row(const SellView &sv, const V *__restrict__ val,
-                                      const G &gx, int32_t b, int slen, int rlen,
+                                      const V *__restrict__ x, int32_t b, int slen, int rlen,
                                       int lane, int row)
 {
     const CI *__restrict__ col = reinterpret_cast<const CI *>(sv.col) + b + lane;
@@ -221,7 +204,7 @@ __device__ __forceinline__ V sell_row(const SellView &sv, const V *__restrict__ 
         }
 #pragma unroll
         for (int u = 0; u < U; ++u)
-            if (j0 + u < rlen) acc = fma(a[u], gx(row + (int)c[u]), acc);
+            if (j0 + u < rlen) acc = fma(a[u], x[row + (int)c[u]], acc);
     }
     return acc;
 }
@@ -230,10 +213,10 @@ __device__ __forceinline__ V sell_row(const SellView &sv, const V *__restrict__ 
 // is called by the lane that owns the row.  r0 is a multiple of 64.  The
 // first slice's header is loaded before go() is asked whether to run (go
 // holds no barrier: the waves of a block may own different slice counts).
-template <class V, class CI, class G, class Go, class Fn>
-__device__ __forceinline__ void sell_rows_g(int r0, int r1, const SellView &sv,
-                                            const V *__restrict__ val, const G &gx,
-                                            Go &&go, Fn &&fn)
+template <class V, class CI, class Go, class Fn>
+__device__ __forceinline__ void sell_rows(int r0, int r1, const SellView &sv,
+                                          const V *__restrict__ val, const V *__restrict__ x,
+                                          Go &&go, Fn &&fn)
 {
     const int lane = threadIdx.x & (kWave - 1);
     const int w = threadIdx.x / kWave;
@@ -250,7 +233,7 @@ __device__ __forceinline__ void sell_rows_g(int r0, int r1, const SellView &sv,
     while (s * kSell < r1) {
         const int row = s * kSell + lane;
         const int slen = (e - b) / kSell;
-        if (row < r1) fn(row, sell_row<V, CI>(sv, val, gx, b, slen, rlen, lane, row));
+        if (row < r1) fn(row, sell_row<V, CI>(sv, val, x, b, slen, rlen, lane, row));
         s += kBlock / kWave;
         if (s * kSell >= r1) break;
         b = sv.ptr[s];
@@ -258,15 +241,6 @@ __device__ __forceinline__ void sell_rows_g(int r0, int r1, const SellView &sv,
         const int nrow = s * kSell + lane;
         rlen = nrow < r1 ? sv.len[nrow] : 0;
     }
-}
-
-template <class V, class CI, class Go, class Fn>
-__device__ __forceinline__ void sell_rows(int r0, int r1, const SellView &sv,
-                                          const V *__restrict__ val, const V *__restrict__ x,
-                                          Go &&go, Fn &&fn)
-{
-    sell_rows_g<V, CI>(r0, r1, sv, val, PlainGather<V>{x}, static_cast<Go &&>(go),
-                       static_cast<Fn &&>(fn));
 }
 
 template <class V, class CI>
