@@ -89,6 +89,10 @@ def load(path: str | None = None):
     lib.orc_pcg.restype = ctypes.c_int
     lib.orc_dense_cholesky_solve.argtypes = [i32, P, P]
     lib.orc_dense_cholesky_solve.restype = ctypes.c_int
+    lib.orc_chebyshev.argtypes = [i32, P, P, P, P, P, P, i32, d, d, i32]
+    lib.orc_chebyshev.restype = ctypes.c_int
+    lib.orc_gershgorin.argtypes = [i32, P, P, P, P]
+    lib.orc_gershgorin.restype = ctypes.c_int
     if path is None:
         _lib = lib
     return lib
@@ -232,3 +236,31 @@ def dense_cholesky_solve(D, b, lib=None):
     if st:
         raise ValueError("matrix is not positive definite")
     return x
+
+
+def chebyshev(A, b, steps, emin, emax, x0=None, lib=None):
+    """Jacobi-preconditioned Chebyshev iteration (`steps` steps on the
+    spectral interval [emin, emax] of D^-1 A).  Returns (x, r)."""
+    lib = lib or load()
+    rp, ci = _csr(A)
+    v = _c(A.val, np.float64)
+    b = _c(b, np.float64)
+    x = np.zeros(A.n) if x0 is None else np.array(x0, dtype=np.float64, copy=True)
+    r = np.empty(A.n)
+    st = lib.orc_chebyshev(A.n, _ptr(rp), _ptr(ci), _ptr(v), _ptr(b), _ptr(x), _ptr(r), int(steps),
+                           float(emin), float(emax), int(x0 is not None))
+    if st:
+        raise ValueError(f"oracle chebyshev failed with status {st}")
+    return x, r
+
+
+def gershgorin(A, lib=None) -> float:
+    """max_i sum_j |a_ij| / |a_ii|: a bound on the spectrum of D^-1 A."""
+    lib = lib or load()
+    rp, ci = _csr(A)
+    v = _c(A.val, np.float64)
+    out = ctypes.c_double(0.0)
+    st = lib.orc_gershgorin(A.n, _ptr(rp), _ptr(ci), _ptr(v), ctypes.byref(out))
+    if st:
+        raise ValueError("zero or missing diagonal")
+    return out.value

@@ -273,6 +273,104 @@ done:
  * small systems).  A is n*n row-major and is overwritten by L; b is
  * overwritten by the solution.  Returns 0, or -1 if A is not positive
  * definite. */
+/*
+ * Chebyshev acceleration of the Jacobi iteration: the smoother that the
+ * paper's geometric multigrid runs on every level but the coarsest (Sec. 5.3,
+ * "Jacobi-preconditioned Chebyshev smoothers").  The paper gives no formulas;
+ * this is the textbook three-term Chebyshev iteration for the preconditioned
+ * system D^-1 A x = D^-1 b (D = diag(A)) on a spectral interval [emin, emax]
+ * of D^-1 A (Saad, Iterative Methods for Sparse Linear Systems, 2nd ed.,
+ * Sec. 12.3, Chebyshev acceleration):
+ *
+ *   theta = (emax + emin) / 2, delta = (emax - emin) / 2, sigma = theta / delta
+ *   r_0 = b - A x_0,  rho_0 = 1 / sigma,  d_0 = D^-1 r_0 / theta
+ *   for k = 0 .. steps-1:
+ *       x_{k+1} = x_k + d_k
+ *       r_{k+1} = r_k - A d_k
+ *       rho_{k+1} = 1 / (2 sigma - rho_k)
+ *       d_{k+1} = rho_{k+1} rho_k d_k + (2 rho_{k+1} / delta) D^-1 r_{k+1}
+ *
+ * The error after k steps is P_k(D^-1 A) e_0 with
+ * P_k(t) = T_k((theta - t) / delta) / T_k(sigma), T_k the Chebyshev
+ * polynomial of the first kind.  x (in: x_0 when x0_nonzero, else ignored and
+ * taken as 0; out: x_steps); r_out (optional) receives r_steps.
+ * Returns 0, ORC_EZERODIAG, ORC_ENOMEM, or -1 for emin/emax outside
+ * 0 < emin < emax.
+ */
+int orc_chebyshev(int32_t n, const int32_t *rowptr, const int32_t *col,
+                  const double *val, const double *b, double *x, double *r_out,
+                  int32_t steps, double emin, double emax, int32_t x0_nonzero)
+{
+    if (!(emin > 0.0) || !(emax > emin)) return -1;
+    const size_t bytes = sizeof(double) * (size_t)(n > 0 ? n : 1);
+    double *dinv = (double *)malloc(bytes);
+    double *r = (double *)malloc(bytes);
+    double *d = (double *)malloc(bytes);
+    double *ad = (double *)malloc(bytes);
+    if (!dinv || !r || !d || !ad) {
+        free(dinv); free(r); free(d); free(ad);
+        return ORC_ENOMEM;
+    }
+    int rc = orc_diag_inv(n, rowptr, col, val, dinv);
+    if (rc) {
+        free(dinv); free(r); free(d); free(ad);
+        return rc;
+    }
+    const double theta = 0.5 * (emax + emin);
+    const double delta = 0.5 * (emax - emin);
+    const double sigma = theta / delta;
+    if (x0_nonzero) {
+        orc_spmv(n, rowptr, col, val, x, ad);
+        for (int32_t i = 0; i < n; ++i) r[i] = b[i] - ad[i];
+    } else {
+        for (int32_t i = 0; i < n; ++i) {
+            x[i] = 0.0;
+            r[i] = b[i];
+        }
+    }
+    double rho = 1.0 / sigma;
+    for (int32_t i = 0; i < n; ++i) d[i] = dinv[i] * r[i] / theta;
+    for (int32_t k = 0; k < steps; ++k) {
+        for (int32_t i = 0; i < n; ++i) x[i] = x[i] + d[i];
+        orc_spmv(n, rowptr, col, val, d, ad);
+        for (int32_t i = 0; i < n; ++i) r[i] = r[i] - ad[i];
+        const double rho_next = 1.0 / (2.0 * sigma - rho);
+        const double c1 = rho_next * rho;
+        const double c2 = 2.0 * rho_next / delta;
+        for (int32_t i = 0; i < n; ++i) d[i] = c1 * d[i] + c2 * (dinv[i] * r[i]);
+        rho = rho_next;
+    }
+    if (r_out) memcpy(r_out, r, sizeof(double) * (size_t)n);
+    free(dinv); free(r); free(d); free(ad);
+    return 0;
+}
+
+/* Gershgorin bound on the spectrum of D^-1 A:
+ * max_i sum_j |a_ij| / |a_ii| (an upper bound on |lambda| for every
+ * eigenvalue).  Returns ORC_EZERODIAG (and sets *bound to 0) when a row has
+ * no nonzero diagonal. */
+int orc_gershgorin(int32_t n, const int32_t *rowptr, const int32_t *col,
+                   const double *val, double *bound)
+{
+    double m = 0.0;
+    for (int32_t i = 0; i < n; ++i) {
+        double diag = 0.0;
+        long double s = 0.0L;
+        for (int32_t k = rowptr[i]; k < rowptr[i + 1]; ++k) {
+            s += fabsl((long double)val[k]);
+            if (col[k] == i) diag = val[k];
+        }
+        if (diag == 0.0) {
+            *bound = 0.0;
+            return ORC_EZERODIAG;
+        }
+        const double g = (double)(s / fabsl((long double)diag));
+        if (g > m) m = g;
+    }
+    *bound = m;
+    return 0;
+}
+
 int orc_dense_cholesky_solve(int32_t n, double *A, double *b)
 {
     for (int32_t j = 0; j < n; ++j) {

@@ -415,3 +415,113 @@ def test_pcg_true_residual_restart_rule(orc):
     if res["reason_str"] == "DIVERGED_BREAKDOWN":
         assert res["restarts"] == 3
     assert res["true_rel_residual"] < 1e-13
+
+
+# ---------------------------------------------------------------- Chebyshev smoother
+
+def cheb_T(k, y):
+    """Chebyshev polynomial of the first kind, T_k(y), from its closed forms
+    (cos(k arccos y) inside [-1, 1], cosh(k arccosh |y|) with sign (+-1)^k
+    outside)."""
+    if abs(y) <= 1.0:
+        return math.cos(k * math.acos(y))
+    v = math.cosh(k * math.acosh(abs(y)))
+    return v if y > 0 or k % 2 == 0 else -v
+
+
+def cheb_P(k, t, emin, emax):
+    """Error polynomial of k Chebyshev steps on [emin, emax]:
+    T_k((theta - t)/delta) / T_k(theta/delta)."""
+    theta, delta = (emax + emin) / 2, (emax - emin) / 2
+    return cheb_T(k, (theta - t) / delta) / cheb_T(k, theta / delta)
+
+
+@pytest.mark.parametrize("steps", [1, 2, 3, 5, 8])
+@pytest.mark.parametrize("ks", [(1, 1), (3, 5), (10, 2), (16, 16)])
+def test_chebyshev_eigenvector_error_polynomial(orc, steps, ks):
+    """With b = A v for an eigenvector v of D^-1 A (constant diagonal) and
+    x0 = 0, the error after k steps is exactly P_k(mu) v, so x_k =
+    (1 - P_k(mu)) v; mu inside and outside [emin, emax]."""
+    N = 16
+    A = spkgen.laplace2d5(N)
+    v, lam = lap_eigpair(N, 2, ks)
+    mu = lam / 4.0
+    b = spkgen.to_dense(A) @ v
+    emin, emax = 0.3, 1.9
+    x, r = oracle.chebyshev(A, b, steps, emin, emax)
+    expect = (1.0 - cheb_P(steps, mu, emin, emax)) * v
+    assert np.allclose(x, expect, rtol=0, atol=1e-13 * (1 + abs(cheb_P(steps, mu, emin, emax))))
+    # the recursive residual is the true one
+    assert np.allclose(r, b - spkgen.to_dense(A) @ x, rtol=0, atol=1e-12)
+
+
+def test_chebyshev_linear_in_eigencomponents(orc):
+    N = 12
+    A = spkgen.laplace2d5(N, 0.5)
+    Ad = spkgen.to_dense(A)
+    comps = [lap_eigpair(N, 2, ks, shift=0.5) for ks in ((1, 2), (6, 6), (12, 11))]
+    v = sum(c[0] for c in comps)
+    b = Ad @ v
+    emin, emax = 0.25, 2.2
+    x, _ = oracle.chebyshev(A, b, 4, emin, emax)
+    expect = sum((1 - cheb_P(4, lam / 4.5, emin, emax)) * w for w, lam in comps)
+    assert np.allclose(x, expect, rtol=0, atol=1e-12)
+
+
+def test_chebyshev_one_step_is_damped_jacobi(orc):
+    A, _ = random_int_csr(40, 3)
+    b = spkgen.rhs_uniform(A.n, 1)
+    d = np.diag(spkgen.to_dense(A))
+    x, r = oracle.chebyshev(A, b, 1, 0.5, 1.5)
+    assert np.allclose(x, b / d / 1.0, rtol=1e-15, atol=0)  # theta = (0.5 + 1.5) / 2 = 1
+    x, r = oracle.chebyshev(A, b, 0, 0.5, 1.5)
+    assert np.array_equal(x, np.zeros(A.n)) and np.array_equal(r, b)
+
+
+def test_chebyshev_exact_start_stays_exact(orc):
+    """x0 = integer exact solution of an integer system: r0 = 0 exactly and
+    every step adds exact zeros."""
+    A = spkgen.laplace3d7(6)
+    xs = np.random.default_rng(0).integers(-20, 20, A.n).astype(np.float64)
+    b = spkgen.to_dense(A) @ xs
+    x, r = oracle.chebyshev(A, b, 5, 0.1, 2.0, x0=xs)
+    assert np.array_equal(x, xs) and not r.any()
+
+
+def test_chebyshev_converges_at_chebyshev_rate(orc):
+    """On the exact spectral interval [mu_min, mu_max] every eigencomponent
+    of the error shrinks by at least 1/T_k(sigma), hence so does the
+    Euclidean error norm (A symmetric, D constant)."""
+    N = 10
+    A = spkgen.laplace2d5(N)
+    Ad = spkgen.to_dense(A)
+    mus = np.linalg.eigvalsh(Ad) / 4.0
+    emin, emax = float(mus.min()), float(mus.max())
+    xs = spkgen.rhs_uniform(A.n, 4)
+    b = Ad @ xs
+    for k in (2, 5, 9):
+        x, _ = oracle.chebyshev(A, b, k, emin, emax)
+        bound = 1.0 / cheb_T(k, (emax + emin) / (emax - emin))
+        assert np.linalg.norm(x - xs) <= bound * np.linalg.norm(xs) * (1 + 1e-9)
+
+
+def test_chebyshev_rejects_bad_interval(orc):
+    A = spkgen.laplace2d5(4)
+    b = np.ones(A.n)
+    for emin, emax in ((0.0, 1.0), (1.0, 1.0), (2.0, 1.0), (-1.0, 1.0)):
+        with pytest.raises(ValueError):
+            oracle.chebyshev(A, b, 2, emin, emax)
+
+
+def test_gershgorin_bound(orc):
+    A = spkgen.laplace2d5(9)
+    assert oracle.gershgorin(A) == 2.0  # interior rows: (4 + 4) / 4
+    for seed in range(3):
+        A, D = random_int_csr(30, seed)
+        direct = max(np.abs(D[i]).sum() / abs(D[i, i]) for i in range(30))
+        g = oracle.gershgorin(A)
+        assert g == pytest.approx(direct, rel=1e-15)
+        M = D / np.diag(D)[:, None]
+        assert np.abs(np.linalg.eigvals(M)).max() <= g * (1 + 1e-12)
+    A = spkgen.diffusion3d27_lognormal(6, seed=1)
+    assert 1.0 < oracle.gershgorin(A) <= 2.0 + 1e-15
