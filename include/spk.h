@@ -131,6 +131,8 @@ typedef struct {
                                        w = 2 or 4 bytes per column offset) */
     int64_t format_bytes_spmv_f32;  /* same for FP32 values and vectors */
     int64_t stored_nnz;             /* entries the kernel reads, padding included */
+    double gershgorin;              /* max_i sum_j |a_ij| / |a_ii|: a bound on the
+                                       spectrum of D^-1 A (0 with a zero diagonal) */
 } spk_mat_info;
 
 /*
@@ -159,7 +161,9 @@ int spk_mat_create_csr(int32_t n, int64_t nnz, const int32_t *rowptr,
 
 /* Force an SpMV kernel family (testing and A/B runs).  param: lanes per row
  * for VECTOR (1..64, power of two), rows per tile for STREAM (0 = automatic),
- * ignored for MERGE.  Invalidates cached solver graphs. */
+ * column-offset bits for SELL (0 = automatic, 16 or 32; SPK_EINVAL when the
+ * rows exceed 255 entries or the offsets do not fit), ignored for MERGE.
+ * Invalidates cached solver graphs. */
 int spk_mat_set_kernel(spk_mat *A, int kernel, int32_t param);
 
 /* y = A x (Sec. 4: MatMult on an AIJ matrix).  x, y: device double[n],
@@ -175,6 +179,33 @@ int spk_mat_get_info(const spk_mat *A, spk_mat_info *info);
 /* Jacobi preconditioner apply, z_i = r_i / a_ii (PCApply of the Jacobi
  * smoother, Sec. 5.3).  Device double[n]. */
 int spk_pc_jacobi_apply(const spk_mat *A, const double *r, double *z, void *stream);
+
+/*
+ * Jacobi-preconditioned Chebyshev smoother (Sec. 5.3: the geometric multigrid
+ * of the driven-cavity study smooths every level but the coarsest with it).
+ * `steps` steps of Chebyshev acceleration on D^-1 A x = D^-1 b over the
+ * spectral interval [emin, emax] of D^-1 A, D = diag(A):
+ *   theta = (emax + emin)/2, delta = (emax - emin)/2, sigma = theta/delta
+ *   r = b - A x (x = 0 unless x0_nonzero), d = D^-1 r / theta, rho = 1/sigma
+ *   steps times: x += d; r -= A d; rho' = 1/(2 sigma - rho);
+ *                d = rho' rho d + (2 rho'/delta) D^-1 r; rho = rho'
+ * The coefficients are known in advance, so a step is one fused SpMV + update
+ * pass with no inner product and no host round trip (the error after k steps
+ * is T_k((theta - t)/delta) / T_k(sigma) on each eigencomponent t).
+ *   b      device double[n], read only
+ *   x      device double[n]: x0 in when x0_nonzero (else overwritten), result out
+ *   r_out  optional device double[n] receiving the recursive residual
+ *          b - A x_steps; with r_out NULL the last step skips its SpMV
+ *   emax <= 0 takes the Gershgorin bound of D^-1 A (spk_mat_info.gershgorin);
+ *   emin <= 0 takes emax / 10 (the smoother damps the upper 90 % of the
+ *   interval)
+ * Uses the handle's solver workspace (allocated on first use).  Errors:
+ * SPK_EINVAL (NULL pointer, steps < 0, not 0 < emin < emax after the
+ * defaults, b or r_out overlapping x), SPK_EZERODIAG.  Queued on `stream`.
+ */
+int spk_pc_chebyshev(const spk_mat *A, const double *b, double *x, double *r_out,
+                     int32_t steps, double emin, double emax, int32_t x0_nonzero,
+                     void *stream);
 
 /* Waits for the handle's queued work, then frees everything it owns. */
 int spk_mat_destroy(spk_mat *A);

@@ -1,0 +1,94 @@
+// Jacobi-preconditioned Chebyshev smoother kernels (the multigrid smoother of
+// Sec. 5.3).  The three-term recurrence has coefficients known before the
+// first step, so each step is one pass with no inner product:
+//   x += d_k;  r -= A d_k;  d_{k+1} = c1 d_k + c2 D^-1 r
+// For the SELL and stream families that pass is a single kernel (the update
+// runs in the SpMV's row epilogue); d is double-buffered because every block
+// gathers d_k while it writes d_{k+1} for its own rows.
+#pragma once
+
+#include "spmv.hpp"
+
+namespace spk {
+
+struct ChebStep {
+    const double *dk;  // d_k (gathered)
+    double *dn;        // d_{k+1}, or null on the last step
+    double *r;
+    double *x;
+    const double *dinv;
+    double c1, c2;
+};
+
+__device__ __forceinline__ void cheb_row(const ChebStep &c, int i, double y)
+{
+    const double ri = c.r[i] - y;
+    c.r[i] = ri;
+    const double di = c.dk[i];
+    c.x[i] = c.x[i] + di;
+    if (c.dn) c.dn[i] = fma(c.c1, di, c.c2 * (c.dinv[i] * ri));
+}
+
+template <class CI>
+__global__ __launch_bounds__(kBlock) void k_cheb_sell(int n, int R, int ntiles, int nblk, SellView sv,
+                                                      const double *__restrict__ val, ChebStep c)
+{
+    const int j = xcd_remap(blockIdx.x, nblk);
+    int t0, t1;
+    block_tiles(j, nblk, ntiles, t0, t1);
+    sell_rows<double, CI>(t0 * R, min(t1 * R, n), sv, val, c.dk, [] { return true; },
+                          [&](int i, double y) { cheb_row(c, i, y); });
+}
+
+static __global__ __launch_bounds__(kBlock) void k_cheb_stream(int n, int R, int ntiles, int nblk,
+                                                               const int32_t *__restrict__ rowptr,
+                                                               const int32_t *__restrict__ col,
+                                                               const double *__restrict__ val,
+                                                               ChebStep c)
+{
+    __shared__ TileLds<double> sm;
+    const int j = xcd_remap(blockIdx.x, nblk);
+    int t0, t1;
+    block_tiles(j, nblk, ntiles, t0, t1);
+    for (int t = t0; t < t1; ++t) {
+        const int r0 = t * R;
+        const int r1 = min(r0 + R, n);
+        stream_tile<double>(r0, r1, rowptr, col, val, c.dk, sm,
+                            [&](int i, double y) { cheb_row(c, i, y); });
+    }
+}
+
+// Other families: y = A d_k was written by the standalone SpMV.
+static __global__ void k_cheb_update(int n, const double *__restrict__ y, ChebStep c)
+{
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+        cheb_row(c, i, y[i]);
+}
+
+// r = b - A x (ax holds A x; null for x = 0, which is then stored), and
+// d_0 = D^-1 r / theta.
+static __global__ void k_cheb_init(int n, const double *__restrict__ b, const double *__restrict__ ax,
+                                   double *__restrict__ x, double *__restrict__ r,
+                                   double *__restrict__ d0, const double *__restrict__ dinv,
+                                   double inv_theta)
+{
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        double ri;
+        if (ax) ri = b[i] - ax[i];
+        else {
+            ri = b[i];
+            x[i] = 0.0;
+        }
+        r[i] = ri;
+        d0[i] = dinv[i] * ri * inv_theta;
+    }
+}
+
+// The last step without a residual: x += d.
+static __global__ void k_cheb_last(int n, const double *__restrict__ d, double *__restrict__ x)
+{
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+        x[i] = x[i] + d[i];
+}
+
+}  // namespace spk

@@ -3,8 +3,11 @@
 // iterative refinement) solves.
 #include <string.h>
 
+#include <cmath>
+
 #include <algorithm>
 
+#include "cheb.hpp"
 #include "krylov.hpp"
 #include "runtime.hpp"
 
@@ -388,11 +391,102 @@ static void fill_zero(double *p, int64_t n, hipStream_t s)
     hipLaunchKernelGGL(k_zero64, dim3((int)g), dim3(kBlock), 0, s, n, p);
 }
 
+static int grid_n(int64_t n)
+{
+    int64_t g = (n + kBlock - 1) / kBlock;
+    if (g > kMaxBlocksSingle) g = kMaxBlocksSingle;
+    return (int)(g < 1 ? 1 : g);
+}
+
+// One Chebyshev step: fused SpMV + update for the SELL and stream families,
+// SpMV into tmp then the update pass for the others.
+static int cheb_step(spk_mat *A, const ChebStep &c, double *tmp, hipStream_t s)
+{
+    const dim3 g(A->nblk), t(kBlock);
+    if (A->kernel == SPK_KERNEL_SELL) {
+        const SellView sv{A->sell_ptr, A->sell_col, A->sell_len};
+        if (A->sell_cw == 2)
+            hipLaunchKernelGGL((k_cheb_sell<int16_t>), g, t, 0, s, A->n, A->R, A->ntiles, A->nblk, sv,
+                               (const double *)A->sell_val, c);
+        else
+            hipLaunchKernelGGL((k_cheb_sell<int32_t>), g, t, 0, s, A->n, A->R, A->ntiles, A->nblk, sv,
+                               (const double *)A->sell_val, c);
+    } else if (A->kernel == SPK_KERNEL_STREAM) {
+        hipLaunchKernelGGL(k_cheb_stream, g, t, 0, s, A->n, A->R, A->ntiles, A->nblk, A->rowptr, A->col,
+                           (const double *)A->val, c);
+    } else {
+        SPK_TRY(launch_spmv<double>(A, A->val, c.dk, tmp, s, nullptr, kGateNone));
+        hipLaunchKernelGGL(k_cheb_update, dim3(grid_n(A->n)), t, 0, s, A->n, (const double *)tmp, c);
+    }
+    SPK_HIP(hipGetLastError());
+    return SPK_OK;
+}
+
 }  // namespace spk
 
 using namespace spk;
 
 extern "C" {
+
+int spk_pc_chebyshev(const spk_mat *Ac, const double *b, double *x, double *r_out, int32_t steps,
+                     double emin, double emax, int32_t x0_nonzero, void *stream)
+{
+    spk_mat *A = const_cast<spk_mat *>(Ac);
+    if (!A) { set_error("A is NULL"); return SPK_EINVAL; }
+    const int64_t n = A->n;
+    if (n > 0 && (!b || !x)) { set_error("NULL b or x"); return SPK_EINVAL; }
+    if (steps < 0) { set_error("steps = %d < 0", steps); return SPK_EINVAL; }
+    auto overlap = [n](const double *a, const double *c) { return a && c && a < c + n && c < a + n; };
+    if (n > 0 && (overlap(b, x) || overlap(r_out, x) || overlap(r_out, b))) {
+        set_error("b, x and r_out must not overlap");
+        return SPK_EINVAL;
+    }
+    if (A->stats.zero_diag) {
+        set_error("%d rows without a nonzero diagonal", A->stats.zero_diag);
+        return SPK_EZERODIAG;
+    }
+    if (!(emax > 0.0)) emax = A->info.gershgorin;
+    if (!(emin > 0.0)) emin = emax / 10.0;
+    if (!(emin > 0.0) || !(emax > emin) || !std::isfinite(emax)) {
+        set_error("spectral interval [%g, %g]: need 0 < emin < emax", emin, emax);
+        return SPK_EINVAL;
+    }
+    if (n == 0) return SPK_OK;
+    hipStream_t s = (hipStream_t)stream;
+    Workspace *w = nullptr;
+    SPK_TRY(get_workspace(A, false, &w));
+    const double theta = 0.5 * (emax + emin), delta = 0.5 * (emax - emin), sigma = theta / delta;
+    double *r = r_out ? r_out : w->r;
+    double *dbuf[2] = {w->z, w->p};
+    double *tmp = w->q;
+    if (x0_nonzero) SPK_TRY(launch_spmv<double>(A, A->val, x, tmp, s, nullptr, kGateNone));
+    hipLaunchKernelGGL(k_cheb_init, dim3(grid_n(n)), dim3(kBlock), 0, s, (int)n, b,
+                       x0_nonzero ? (const double *)tmp : nullptr, x, r, dbuf[0], (const double *)A->dinv,
+                       1.0 / theta);
+    SPK_HIP(hipGetLastError());
+    double rho = 1.0 / sigma;
+    for (int k = 0; k < steps; ++k) {
+        const bool last = k == steps - 1;
+        if (last && !r_out) {  // the residual is not wanted: skip the last SpMV
+            hipLaunchKernelGGL(k_cheb_last, dim3(grid_n(n)), dim3(kBlock), 0, s, (int)n,
+                               (const double *)dbuf[k & 1], x);
+            SPK_HIP(hipGetLastError());
+            break;
+        }
+        const double rho_next = 1.0 / (2.0 * sigma - rho);
+        ChebStep c;
+        c.dk = dbuf[k & 1];
+        c.dn = last ? nullptr : dbuf[(k + 1) & 1];
+        c.r = r;
+        c.x = x;
+        c.dinv = A->dinv;
+        c.c1 = rho_next * rho;
+        c.c2 = 2.0 * rho_next / delta;
+        SPK_TRY(cheb_step(A, c, tmp, s));
+        rho = rho_next;
+    }
+    return SPK_OK;
+}
 
 void spk_ksp_opts_default(spk_ksp_opts *o)
 {

@@ -133,14 +133,27 @@ __global__ void k_diag_inv(int n, const int32_t *__restrict__ rowptr, const int3
                            RowStats *__restrict__ out)
 {
     int bad = 0;
+    double gmax = 0.0;  // Gershgorin bound of D^-1 A: max_i sum_j |a_ij| / |a_ii|
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-        double d = 0.0;
-        for (int k = rowptr[i]; k < rowptr[i + 1]; ++k)
-            if (col[k] == i) d += val[k];
+        double d = 0.0, sabs = 0.0;
+        for (int k = rowptr[i]; k < rowptr[i + 1]; ++k) {
+            const double v = val[k];
+            sabs += fabs(v);
+            if (col[k] == i) d += v;
+        }
         if (d == 0.0) { ++bad; dinv[i] = 0.0; }
-        else dinv[i] = 1.0 / d;
+        else {
+            dinv[i] = 1.0 / d;
+            gmax = fmax(gmax, sabs / fabs(d));
+        }
     }
     if (bad) atomicAdd(&out->zero_diag, bad);
+    // non-negative doubles order like their bit patterns: one atomic per wave
+    gmax = fmax(gmax, 0.0);
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) gmax = fmax(gmax, __shfl_xor(gmax, off, kWave));
+    if ((threadIdx.x & (kWave - 1)) == 0 && gmax > 0.0)
+        atomicMax(&out->gersh_bits, (unsigned long long)__double_as_longlong(gmax));
 }
 
 __global__ void k_to_f32(int64_t m, const double *__restrict__ a, float *__restrict__ b)
@@ -366,6 +379,9 @@ void update_info(spk_mat *A)
     I.bytes_pcg_iter_f32 = 8 * nz + 4 * (nn + 1) + 48 * nn;
     I.device_bytes = A->bytes + (A->ws ? A->ws->bytes : 0);
     I.zero_diag_rows = S.zero_diag;
+    double g = 0.0;
+    memcpy(&g, &S.gersh_bits, sizeof g);  // bits of a non-negative double
+    I.gershgorin = S.zero_diag ? 0.0 : g;
     if (A->kernel == SPK_KERNEL_SELL && A->sell_cw) {
         const int64_t ns = (nn + kSell - 1) / kSell;
         I.stored_nnz = A->sell_nnz;

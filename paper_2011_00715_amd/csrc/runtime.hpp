@@ -19,6 +19,7 @@ struct RowStats {
     int32_t zero_diag;       // rows without a nonzero diagonal
     int32_t tile_max[6];     // max nonzeros in an aligned tile of 256,128,64,32,16,8 rows
     unsigned long long sell_padded;  // entries of a SELL-64 layout (64 x longest row per slice)
+    unsigned long long gersh_bits;   // bits of max_i sum_j |a_ij| / |a_ii| (non-negative double)
     int32_t hist[33];        // rows by bit length of their length
 };
 

@@ -52,6 +52,7 @@ class MatInfo(ctypes.Structure):
         ("bytes_pcg_iter_f64", i64), ("bytes_pcg_iter_f32", i64),
         ("device_bytes", i64), ("zero_diag_rows", i32), ("pad_", i32),
         ("format_bytes_spmv_f64", i64), ("format_bytes_spmv_f32", i64), ("stored_nnz", i64),
+        ("gershgorin", dbl),
     ]
 
 
@@ -99,6 +100,7 @@ _sig("spk_mat_mult", ctypes.c_int, [P, P, P, P])
 _sig("spk_mat_mult_f32", ctypes.c_int, [P, P, P, P])
 _sig("spk_mat_get_info", ctypes.c_int, [P, ctypes.POINTER(MatInfo)])
 _sig("spk_pc_jacobi_apply", ctypes.c_int, [P, P, P, P])
+_sig("spk_pc_chebyshev", ctypes.c_int, [P, P, P, P, i32, dbl, dbl, i32, P])
 _sig("spk_mat_destroy", ctypes.c_int, [P])
 _sig("spk_vec_axpy", ctypes.c_int, [i32, dbl, P, P, P])
 _sig("spk_vec_aypx", ctypes.c_int, [i32, dbl, P, P, P])
@@ -126,7 +128,7 @@ _sig("spk_cache_flush", ctypes.c_int, [P, i64, P])
 
 EXPORTS = [
     "spk_mat_create_csr", "spk_mat_set_kernel", "spk_mat_mult", "spk_mat_mult_f32",
-    "spk_mat_get_info", "spk_pc_jacobi_apply", "spk_mat_destroy", "spk_vec_axpy",
+    "spk_mat_get_info", "spk_pc_jacobi_apply", "spk_pc_chebyshev", "spk_mat_destroy", "spk_vec_axpy",
     "spk_vec_aypx", "spk_vec_dot", "spk_vec_dot2", "spk_vec_nrm2", "spk_ksp_opts_default",
     "spk_ksp_solve", "spk_server_opts_default", "spk_server_create", "spk_server_submit",
     "spk_server_progress", "spk_server_poll", "spk_server_destroy", "spk_status_str",
@@ -270,6 +272,17 @@ def pc_jacobi_apply(A: Mat, r: torch.Tensor, z: torch.Tensor, stream=None):
     _check(_lib.spk_pc_jacobi_apply(A.handle, _dev(r, torch.float64, A.n, "r"),
                                     _dev(z, torch.float64, A.n, "z"), _stream(stream)),
            "spk_pc_jacobi_apply")
+
+
+def pc_chebyshev(A: Mat, b: torch.Tensor, x: torch.Tensor, steps: int, emin: float = 0.0,
+                 emax: float = 0.0, r_out: torch.Tensor = None, x0_nonzero: bool = False,
+                 stream=None):
+    _check(_lib.spk_pc_chebyshev(A.handle, _dev(b, torch.float64, A.n, "b"),
+                                 _dev(x, torch.float64, A.n, "x"),
+                                 _dev(r_out, torch.float64, A.n, "r_out") if r_out is not None else None,
+                                 int(steps), float(emin), float(emax), int(bool(x0_nonzero)),
+                                 _stream(stream)),
+           "spk_pc_chebyshev")
 
 
 def mat_destroy(A: Mat):

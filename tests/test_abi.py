@@ -61,3 +61,6 @@ def test_host_side_validation_without_gpu(lib):
     so = spk.server_opts_default()
     assert so.max_slots > 0 and so.hbm_budget_bytes > 0
     assert spk.now() > 0
+    # the smoother rejects a NULL handle before touching the device
+    assert spk._lib.spk_pc_chebyshev(None, None, None, None, 2, 0.0, 0.0, 0, None) == spk.EINVAL
+    assert "NULL" in spk.last_error()
