@@ -218,6 +218,26 @@ def bench_c2(args):
     del scratch
     cold_avg = float(np.mean(cold_us)) if cold_us else float("nan")
 
+    # Chebyshev-Jacobi smoother (multigrid smoothing of Sec. 5.3), default
+    # interval [g/10, g] from the Gershgorin bound; outside the timed steps
+    cheb = {}
+    xc = torch.zeros_like(xs)
+    mat_bytes = 12 * info.nnz + 4 * (info.n + 1)
+    for steps in (2, 8):
+        us = []
+        for _ in range(20):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            spk.pc_chebyshev(M, bd, xc, steps)
+            e1.record()
+            torch.cuda.synchronize()
+            us.append(e0.elapsed_time(e1) * 1e3)
+        nb = 40 * info.n + (steps - 1) * (mat_bytes + 56 * info.n) + 24 * info.n
+        t = float(np.median(us))
+        cheb[f"steps_{steps}"] = {"us_p50": t, "bytes": nb, "gbps": nb / (t * 1e-6) / 1e9}
+    cheb["note"] = ("x0 = 0, no residual output: 40n (init) + (steps-1) x (12 nnz + 4(n+1) + 56n) "
+                    "fused SpMV+update passes + 24n (last x += d)")
+
     out = {
         "metric": "CSR SpMV HBM GB/s; PCG solves/s to rtol 1e-8, FP64 vs mixed; p50/p99 lat",
         "value": bytes_total / elapsed / 1e9,
@@ -254,6 +274,7 @@ def bench_c2(args):
             "gbps": solve_bytes(info, r64) / (float(np.median(t64)) * 1e-3) / 1e9,
             "true_rel_residual_oracle": rel64, "reason": spk.reason_str(r64.reason),
         },
+        "chebyshev": cheb,
         "pcg_mixed": {
             "solves_per_s": 1e3 / float(np.median(tmx)), "ms_p50": pct(tmx, 50), "ms_p99": pct(tmx, 99),
             "inner_iterations": rmx.inner_iterations, "outer_steps": rmx.outer_steps,
