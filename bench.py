@@ -43,7 +43,7 @@ def parse():
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=10)
     p.add_argument("--warmup", type=int, default=2)
-    p.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "serve"])
+    p.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "serve", "spectrum"])
     p.add_argument("--spmvs", type=int, default=100)
     p.add_argument("--cold-spmvs", type=int, default=20,
                    help="SpMVs timed after evicting the Infinity Cache (after the timed steps)")
@@ -513,6 +513,27 @@ def bench_serve(args):
                 del pending[t]
     elapsed = spk.now() - t0
     S.close()
+    seq = None
+    if closed:
+        # the same requests one at a time through spk_ksp_solve (matrix
+        # upload, mixed solve, x back to the host), for the batching gain
+        import torch
+
+        log("sequential baseline")
+        tseq = 0.0
+        for r in reqs:
+            A = spkgen.serve_matrix(r)  # input formation is not timed (as for the server)
+            b = spkgen.rhs_uniform(A.n, r.rhs_seed % (2**31))
+            ts = spk.now()
+            M = spk.mat_create_csr(A.rowptr, A.col, A.val, flags=spk.MAT_MIXED)
+            x = torch.zeros(A.n, dtype=torch.float64, device="cuda")
+            res = spk.ksp_solve(M, dev(b), x, o)
+            x.cpu()
+            M.close()
+            tseq += spk.now() - ts
+            assert res.reason > 0
+        seq = {"solves_per_s": len(reqs) / tseq, "seconds": tseq,
+               "batching_gain": (len(lat) / elapsed) / (len(reqs) / tseq)}
     return {
         "metric": "served PCG solves/s to rtol 1e-8; p50/p99 latency",
         "value": len(lat) / elapsed, "unit": "solves/s", "n_gpus": 1, "steps": len(lat),
@@ -524,14 +545,86 @@ def bench_serve(args):
                    "diagonal shift U[0,1), rhs U[-1,1)", "graph_k": args.graph_k},
         "latency_ms": {"p50": pct(lat, 50) * 1e3, "p99": pct(lat, 99) * 1e3, "max": max(lat) * 1e3},
         "iterations_mean": float(np.mean(iters)), "worst_true_rel_residual": worst_rel,
+        "sequential": seq,
+    }
+
+
+def bench_spectrum(args):
+    """Work-time spectrum (Sec. 5.1): time per operation against the work it
+    moves, from latency-bound to bandwidth-bound sizes, for VecAXPY
+    (3 accesses per entry), a streaming copy (2), the FP64 SpMV and a
+    Jacobi-PCG iteration on 3D 7-point Laplacians."""
+    import numpy as np
+    import torch
+
+    import spkgen
+    from paper_2011_00715_amd import spk
+
+    def timed(fn, reps=20):
+        us = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn()
+            e1.record()
+            torch.cuda.synchronize()
+            us.append(e0.elapsed_time(e1) * 1e3)
+        return float(np.median(us))
+
+    vec = []
+    for e in range(6, 17):  # n = 10^3 ... 10^8 in half decades
+        n = int(round(10 ** (e / 2)))
+        x = torch.ones(n, dtype=torch.float64, device="cuda")
+        y = torch.ones(n, dtype=torch.float64, device="cuda")
+        fn_axpy = lambda: spk.vec_axpy(0.5, x, y)  # noqa: E731
+        fn_copy = lambda: spk.bw_copy(x, y)  # noqa: E731
+        fn_axpy(), fn_copy()
+        ta, tc = timed(fn_axpy), timed(fn_copy)
+        vec.append({"n": n, "axpy_us": ta, "axpy_gbps": 24 * n / ta / 1e3,
+                    "copy_us": tc, "copy_gbps": 16 * n / tc / 1e3})
+        log(f"vec n={n}: axpy {ta:.2f} us, copy {tc:.2f} us")
+        del x, y
+    mat = []
+    for N in (10, 16, 25, 40, 64, 100, 128, 160, 200):
+        A = spkgen.laplace3d7(N)
+        M = spk.mat_create_csr(dev(A.rowptr), dev(A.col), dev(A.val))
+        info = M.info
+        xs = dev(spkgen.rhs_uniform(A.n, 0))
+        ys = torch.empty_like(xs)
+        spk.mat_mult(M, xs, ys)
+        t_spmv = timed(lambda: spk.mat_mult(M, xs, ys))
+        b = xs
+        xx = torch.zeros_like(xs)
+        secs = {}
+        for its in (20, 60):
+            o = spk.ksp_opts(rtol=0.0, atol=0.0, maxit=its, graph_k=args.graph_k)
+            spk.ksp_solve(M, b, xx, o)
+            secs[its] = float(np.median([spk.ksp_solve(M, b, xx, o).seconds for _ in range(5)]))
+        t_it = (secs[60] - secs[20]) / 40 * 1e6
+        mat.append({"N": N, "n": info.n, "nnz": info.nnz, "kernel": spk.KERNEL_NAMES[info.kernel],
+                    "spmv_us": t_spmv, "spmv_gbps": info.bytes_spmv_f64 / t_spmv / 1e3,
+                    "pcg_iter_us": t_it, "pcg_iter_gbps": info.bytes_pcg_iter_f64 / t_it / 1e3})
+        log(f"3D {N}^3: spmv {t_spmv:.2f} us, pcg iteration {t_it:.2f} us")
+        M.close()
+    big = mat[-1]
+    return {
+        "metric": "work-time spectrum: time per operation vs bytes moved (latency and asymptotic bandwidth)",
+        "value": big["spmv_gbps"], "unit": "GB/s", "n_gpus": 1, "steps": len(vec) + len(mat),
+        "warmup": 1, "ms_per_step": None, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "VecAXPY / copy n = 10^3..10^8; 3D 7-point Laplacian N^3, N = 10..200 "
+                               "(SpMV, and Jacobi-PCG iterations from (t(60 its) - t(20 its)) / 40)"},
+        "vectors": vec, "laplace3d": mat,
+        "latency_us": {"axpy": vec[0]["axpy_us"], "copy": vec[0]["copy_us"], "spmv": mat[0]["spmv_us"],
+                       "pcg_iter": mat[0]["pcg_iter_us"]},
     }
 
 
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
-                          "(the multi-GPU sharding is described in DESIGN.md, not built)"}))
+        print(json.dumps({"error": "one GPU only: --gpus must be 1 (sharding the path across "
+                          "GPUs is not built)"}))
         sys.exit(2)
     import torch
 
@@ -540,7 +633,8 @@ def main():
         sys.exit(1)
     torch.cuda.set_device(0)
     calibration_copy()
-    fn = {"c2": bench_c2, "c3": bench_c3, "c4": bench_c4, "serve": bench_serve}[args.workload]
+    fn = {"c2": bench_c2, "c3": bench_c3, "c4": bench_c4, "serve": bench_serve,
+          "spectrum": bench_spectrum}[args.workload]
     out = fn(args)
     print(json.dumps(out), flush=True)
 
