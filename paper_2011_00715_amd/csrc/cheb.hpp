@@ -29,15 +29,13 @@ __device__ __forceinline__ void cheb_row(const ChebStep &c, int i, double y)
     if (c.dn) c.dn[i] = fma(c.c1, di, c.c2 * (c.dinv[i] * ri));
 }
 
-template <class CI>
-__global__ __launch_bounds__(kBlock) void k_cheb_sell(int n, int R, int ntiles, int nblk, SellView sv,
-                                                      const double *__restrict__ val, ChebStep c)
+template <class CI, int U>
+__global__ __launch_bounds__(kBlock) void k_cheb_sell(int n, SellView sv, const double *__restrict__ val,
+                                                      ChebStep c)
 {
-    const int j = xcd_remap(blockIdx.x, nblk);
-    int t0, t1;
-    block_tiles(j, nblk, ntiles, t0, t1);
-    sell_rows<double, CI>(t0 * R, min(t1 * R, n), sv, val, c.dk, [] { return true; },
-                          [&](int i, double y) { cheb_row(c, i, y); });
+    sell_slices<double, CI, U>(n, blockIdx.x * (kBlock / kWave) + (int)threadIdx.x / kWave,
+                               gridDim.x * (kBlock / kWave), sv, val, c.dk, [] { return true; },
+                               [&](int i, double y) { cheb_row(c, i, y); });
 }
 
 static __global__ __launch_bounds__(kBlock) void k_cheb_stream(int n, int R, int ntiles, int nblk,

@@ -85,6 +85,14 @@ __device__ __forceinline__ bool locate(const One &a, int &j, SysDesc &d)
     return true;
 }
 
+// Physical block index within its system (the SELL kernels walk slices in
+// physical block order).
+__device__ __forceinline__ int local_block(const Batch &a)
+{
+    return (int)blockIdx.x - a.blk_start[find_sys(a.blk_start, a.nsys, blockIdx.x)];
+}
+__device__ __forceinline__ int local_block(const One &) { return (int)blockIdx.x; }
+
 __device__ __forceinline__ void row_range(const SysDesc &d, int j, int &rb, int &re)
 {
     int t0, t1;
@@ -245,8 +253,11 @@ template <class V> __device__ __forceinline__ const V *sell_vals(const SysDesc &
 template <> __device__ __forceinline__ const double *sell_vals<double>(const SysDesc &d) { return d.sell_val; }
 template <> __device__ __forceinline__ const float *sell_vals<float>(const SysDesc &d) { return d.sell_val32; }
 
+// SELL slices of a block: 4 (block) + wave, stride 4 nblk.
+__device__ __forceinline__ int sell_first(int l) { return l * (kBlock / kWave) + (int)threadIdx.x / kWave; }
+
 // r = b - A x in FP64 with the SELL-64 layout, per-block r.r and b.b.
-template <int kGate, class CI, class B>
+template <int kGate, class CI, int U, class B>
 __global__ __launch_bounds__(kBlock) void k_resid_sell(B a)
 {
     __shared__ double red[kBlock / kWave];
@@ -254,13 +265,12 @@ __global__ __launch_bounds__(kBlock) void k_resid_sell(B a)
     SysDesc d;
     if (!locate(a, j, d)) return;
     if (kGate != kGateNone && !gate_open(d.st, kGate)) return;
-    int rb, re;
-    row_range(d, j, rb, re);
     const double *__restrict__ b = d.b;
     double *__restrict__ r = d.r;
     const SellView sv{d.sell_ptr, d.sell_col, d.sell_len};
     double rr = 0.0, bb = 0.0;
-    sell_rows<double, CI>(rb, re, sv, d.sell_val, d.x, [] { return true; }, [&](int i, double y) {
+    sell_slices<double, CI, U>(d.n, sell_first(local_block(a)), d.nblk * (kBlock / kWave), sv,
+                               d.sell_val, d.x, [] { return true; }, [&](int i, double y) {
         const double bi = b[i];
         const double ri = bi - y;
         r[i] = ri;
@@ -531,7 +541,7 @@ __global__ __launch_bounds__(kBlock) void k_pcg_spmv_stream(B a)
 }
 
 // A with the SELL-64 layout: one slice of 64 rows per wavefront, p.q fused.
-template <class V, class CI, class B>
+template <class V, class CI, int U, class B>
 __global__ __launch_bounds__(kBlock) void k_pcg_spmv_sell(B a)
 {
     __shared__ double red[kBlock / kWave];
@@ -539,16 +549,14 @@ __global__ __launch_bounds__(kBlock) void k_pcg_spmv_sell(B a)
     SysDesc d;
     if (!locate(a, j, d)) return;
     const Gate g = load_gate(d.st);
-    int rb, re;
-    row_range(d, j, rb, re);
     const V *__restrict__ p = Vecs<V>::p(d);
     V *__restrict__ q = Vecs<V>::q(d);
     const V *__restrict__ val = sell_vals<V>(d);
     const SellView sv{d.sell_ptr, d.sell_col, d.sell_len};
     V acc = V(0);
     const bool run = gate_ok(g, Vecs<V>::gate);
-    sell_rows<V, CI>(
-        rb, re, sv, val, p, [&] { return run; },
+    sell_slices<V, CI, U>(
+        d.n, sell_first(local_block(a)), d.nblk * (kBlock / kWave), sv, val, p, [&] { return run; },
         [&](int i, V y) {
             q[i] = y;
             acc = fma(y, p[i], acc);

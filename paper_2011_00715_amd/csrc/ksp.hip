@@ -145,13 +145,16 @@ static int launch_resid(spk_mat *A, Workspace *w, int purpose, bool gated, hipSt
         if (gated) hipLaunchKernelGGL((k_resid_stream<kGateResid, One>), g, t, 0, s, b);
         else hipLaunchKernelGGL((k_resid_stream<kGateNone, One>), g, t, 0, s, b);
     } else if (A->kernel == SPK_KERNEL_SELL) {
-        if (A->sell_cw == 2) {
-            if (gated) hipLaunchKernelGGL((k_resid_sell<kGateResid, int16_t, One>), g, t, 0, s, b);
-            else hipLaunchKernelGGL((k_resid_sell<kGateNone, int16_t, One>), g, t, 0, s, b);
-        } else {
-            if (gated) hipLaunchKernelGGL((k_resid_sell<kGateResid, int32_t, One>), g, t, 0, s, b);
-            else hipLaunchKernelGGL((k_resid_sell<kGateNone, int32_t, One>), g, t, 0, s, b);
-        }
+        with_sell_u(A->sell_u, [&](auto uc) {
+            constexpr int U = decltype(uc)::value;
+            if (A->sell_cw == 2) {
+                if (gated) hipLaunchKernelGGL((k_resid_sell<kGateResid, int16_t, U, One>), g, t, 0, s, b);
+                else hipLaunchKernelGGL((k_resid_sell<kGateNone, int16_t, U, One>), g, t, 0, s, b);
+            } else {
+                if (gated) hipLaunchKernelGGL((k_resid_sell<kGateResid, int32_t, U, One>), g, t, 0, s, b);
+                else hipLaunchKernelGGL((k_resid_sell<kGateNone, int32_t, U, One>), g, t, 0, s, b);
+            }
+        });
     } else {
         SPK_TRY(launch_spmv<double>(A, A->val, w->x, w->r, s, gated ? w->st : nullptr,
                                     gated ? kGateResid : kGateNone));
@@ -172,8 +175,11 @@ static int enqueue_iteration(spk_mat *A, Workspace *w, hipStream_t s)
     if (A->kernel == SPK_KERNEL_STREAM) {
         hipLaunchKernelGGL((k_pcg_spmv_stream<V, One>), g, t, 0, s, b);
     } else if (A->kernel == SPK_KERNEL_SELL) {
-        if (A->sell_cw == 2) hipLaunchKernelGGL((k_pcg_spmv_sell<V, int16_t, One>), g, t, 0, s, b);
-        else hipLaunchKernelGGL((k_pcg_spmv_sell<V, int32_t, One>), g, t, 0, s, b);
+        with_sell_u(A->sell_u, [&](auto uc) {
+            constexpr int U = decltype(uc)::value;
+            if (A->sell_cw == 2) hipLaunchKernelGGL((k_pcg_spmv_sell<V, int16_t, U, One>), g, t, 0, s, b);
+            else hipLaunchKernelGGL((k_pcg_spmv_sell<V, int32_t, U, One>), g, t, 0, s, b);
+        });
     } else {
         const V *val = std::is_same<V, double>::value ? (const V *)A->val : (const V *)A->val32;
         V *p = std::is_same<V, double>::value ? (V *)w->p : (V *)w->p32;
@@ -405,12 +411,15 @@ static int cheb_step(spk_mat *A, const ChebStep &c, double *tmp, hipStream_t s)
     const dim3 g(A->nblk), t(kBlock);
     if (A->kernel == SPK_KERNEL_SELL) {
         const SellView sv{A->sell_ptr, A->sell_col, A->sell_len};
-        if (A->sell_cw == 2)
-            hipLaunchKernelGGL((k_cheb_sell<int16_t>), g, t, 0, s, A->n, A->R, A->ntiles, A->nblk, sv,
-                               (const double *)A->sell_val, c);
-        else
-            hipLaunchKernelGGL((k_cheb_sell<int32_t>), g, t, 0, s, A->n, A->R, A->ntiles, A->nblk, sv,
-                               (const double *)A->sell_val, c);
+        // up to one wavefront per slice (no partial sums to keep per block)
+        const dim3 gs(std::max(1, std::min(ceil_div(ceil_div(A->n, kSell), kBlock / kWave), 16384)));
+        const int n = A->n;
+        const double *sval = A->sell_val;
+        with_sell_u(A->sell_u, [&](auto uc) {
+            constexpr int U = decltype(uc)::value;
+            if (A->sell_cw == 2) hipLaunchKernelGGL((k_cheb_sell<int16_t, U>), gs, t, 0, s, n, sv, sval, c);
+            else hipLaunchKernelGGL((k_cheb_sell<int32_t, U>), gs, t, 0, s, n, sv, sval, c);
+        });
     } else if (A->kernel == SPK_KERNEL_STREAM) {
         hipLaunchKernelGGL(k_cheb_stream, g, t, 0, s, A->n, A->R, A->ntiles, A->nblk, A->rowptr, A->col,
                            (const double *)A->val, c);

@@ -307,12 +307,16 @@ int launch_spmv(const spk_mat *A, const V *val, const V *x, V *y, hipStream_t s,
         const SellView sv{A->sell_ptr, A->sell_col, A->sell_len};
         const V *sval = std::is_same<V, double>::value ? (const V *)A->sell_val : (const V *)A->sell_val32;
         (void)val;
-        if (A->sell_cw == 2)
-            hipLaunchKernelGGL((k_spmv_sell<V, int16_t>), dim3(A->nblk), dim3(kBlock), 0, s, A->n, A->R,
-                               A->ntiles, A->nblk, sv, sval, x, y);
-        else
-            hipLaunchKernelGGL((k_spmv_sell<V, int32_t>), dim3(A->nblk), dim3(kBlock), 0, s, A->n, A->R,
-                               A->ntiles, A->nblk, sv, sval, x, y);
+        // up to one wavefront per slice
+        const dim3 grid(std::max(1, std::min(ceil_div(ceil_div(A->n, kSell), kBlock / kWave), 16384)));
+        const int n = A->n;
+        with_sell_u(A->sell_u, [&](auto uc) {
+            constexpr int U = decltype(uc)::value;
+            if (A->sell_cw == 2)
+                hipLaunchKernelGGL((k_spmv_sell<V, int16_t, U>), grid, dim3(kBlock), 0, s, n, sv, sval, x, y);
+            else
+                hipLaunchKernelGGL((k_spmv_sell<V, int32_t, U>), grid, dim3(kBlock), 0, s, n, sv, sval, x, y);
+        });
         break;
     }
     case SPK_KERNEL_MERGE: {
@@ -529,9 +533,11 @@ static int setup_sell(spk_mat *A, hipStream_t s, int cw)
     const int ns = ceil_div(n, kSell);
     std::vector<int32_t> sp((size_t)ns + 1);
     int64_t acc = 0;
+    int wmax = 0;
     for (int k = 0; k < ns; ++k) {
         int mx = 0;
         for (int i = k * kSell; i < std::min(n, (k + 1) * kSell); ++i) mx = std::max(mx, rp[i + 1] - rp[i]);
+        wmax = std::max(wmax, mx);
         sp[k] = (int32_t)acc;
         acc += (int64_t)kSell * mx;
         if (acc > 0x7fffffffLL) { set_error("SELL layout exceeds 2^31 entries"); return SPK_EINVAL; }
@@ -551,6 +557,7 @@ static int setup_sell(spk_mat *A, hipStream_t s, int cw)
                            A->val, A->sell_ptr, (int32_t *)A->sell_col, A->sell_val, A->sell_len);
     SPK_HIP(hipGetLastError());
     A->sell_cw = cw;
+    A->sell_u = pick_sell_u(wmax);
     A->sell_nnz = acc;
     A->bytes += 4 * ((int64_t)ns + 1) + (int64_t)(cw + 8) * acc + n;
     if (A->val32) {

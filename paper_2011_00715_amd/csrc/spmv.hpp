@@ -15,6 +15,8 @@
 //             result is reproducible bit for bit).
 #pragma once
 
+#include <type_traits>
+
 #include "common.hpp"
 
 namespace spk {
@@ -185,7 +187,13 @@ struct SellView {
 
 // Row sum of lane `lane` of the slice starting at element b with slen
 // entries per row; the row has rlen of them.  Entries in column order, FMA.
-template <class V, class CI, int U = 8>
+// U entries per round: the round's offsets and values are loaded together,
+// then all U gathers of x are issued before the first FMA, so a round costs
+// one memory latency, not U.  Entries past the slice width repeat its last
+// entry and padding has offset 0, so every gather reads a valid element of
+// x; only the row's own entries are multiplied.  U is chosen per matrix from
+// the widest slice (7 for a 7-point stencil: no wasted load).
+template <class V, class CI, int U>
 __device__ __forceinline__ V sell_row(const SellView &sv, const V *__restrict__ val,
                                       const V *__restrict__ x, int32_t b, int slen, int rlen,
                                       int lane, int row)
@@ -202,57 +210,89 @@ __device__ __forceinline__ V sell_row(const SellView &sv, const V *__restrict__ 
             c[u] = ld_stream(col + (size_t)j * kSell);
             a[u] = ld_stream(v + (size_t)j * kSell);
         }
+        V xv[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) xv[u] = x[row + (int)c[u]];
 #pragma unroll
         for (int u = 0; u < U; ++u)
-            if (j0 + u < rlen) acc = fma(a[u], x[row + (int)c[u]], acc);
+            if (j0 + u < rlen) acc = fma(a[u], xv[u], acc);
     }
     return acc;
 }
 
-// Rows [r0, r1) of a tile range, one slice per wavefront at a time; fn(row, y)
-// is called by the lane that owns the row.  r0 is a multiple of 64.  The
-// first slice's header is loaded before go() is asked whether to run (go
-// holds no barrier: the waves of a block may own different slice counts).
-template <class V, class CI, class Go, class Fn>
-__device__ __forceinline__ void sell_rows(int r0, int r1, const SellView &sv,
-                                          const V *__restrict__ val, const V *__restrict__ x,
-                                          Go &&go, Fn &&fn)
+// Slices s, s + stride, ... below ceil(n/64), one per wavefront at a time;
+// fn(row, y) is called by the lane that owns row (< n).  Callers pass
+// s = 4 * (physical block) + wave and stride = 4 * (blocks), so the slices in
+// flight at any moment are adjacent in memory (one DRAM stream front rather
+// than one per block).  The first slice's header is loaded before go() is
+// asked whether to run (go holds no barrier: waves may own different counts).
+template <class V, class CI, int U, class Go, class Fn>
+__device__ __forceinline__ void sell_slices(int n, int s, int stride, const SellView &sv,
+                                            const V *__restrict__ val, const V *__restrict__ x,
+                                            Go &&go, Fn &&fn)
 {
     const int lane = threadIdx.x & (kWave - 1);
-    const int w = threadIdx.x / kWave;
-    int s = r0 / kSell + w;
+    const int ns = (n + kSell - 1) / kSell;
     int32_t b = 0, e = 0;
     int rlen = 0;
-    if (s * kSell < r1) {
+    if (s < ns) {
         b = sv.ptr[s];
         e = sv.ptr[s + 1];
         const int row = s * kSell + lane;
-        rlen = row < r1 ? sv.len[row] : 0;
+        rlen = row < n ? sv.len[row] : 0;
     }
     if (!go()) return;
-    while (s * kSell < r1) {
+    while (s < ns) {
         const int row = s * kSell + lane;
         const int slen = (e - b) / kSell;
-        if (row < r1) fn(row, sell_row<V, CI>(sv, val, x, b, slen, rlen, lane, row));
-        s += kBlock / kWave;
-        if (s * kSell >= r1) break;
+        if (row < n) fn(row, sell_row<V, CI, U>(sv, val, x, b, slen, rlen, lane, row));
+        s += stride;
+        if (s >= ns) break;
         b = sv.ptr[s];
         e = sv.ptr[s + 1];
         const int nrow = s * kSell + lane;
-        rlen = nrow < r1 ? sv.len[nrow] : 0;
+        rlen = nrow < n ? sv.len[nrow] : 0;
     }
 }
 
-template <class V, class CI>
-__global__ __launch_bounds__(kBlock) void k_spmv_sell(int n, int R, int ntiles, int nblk,
-                                                      SellView sv, const V *__restrict__ val,
+// Standalone SELL SpMV; the grid has up to one wavefront per slice.
+template <class V, class CI, int U>
+__global__ __launch_bounds__(kBlock) void k_spmv_sell(int n, SellView sv, const V *__restrict__ val,
                                                       const V *__restrict__ x, V *__restrict__ y)
 {
-    const int j = xcd_remap(blockIdx.x, nblk);
-    int t0, t1;
-    block_tiles(j, nblk, ntiles, t0, t1);
-    sell_rows<V, CI>(t0 * R, min(t1 * R, n), sv, val, x, [] { return true; },
-                     [&](int i, V s) { y[i] = s; });
+    sell_slices<V, CI, U>(n, blockIdx.x * (kBlock / kWave) + (int)threadIdx.x / kWave,
+                          gridDim.x * (kBlock / kWave), sv, val, x, [] { return true; },
+                          [&](int i, V s) { y[i] = s; });
+}
+
+// Widths U the SELL kernels are built for, and the launch helper: calls
+// f(std::integral_constant<int, U>) for the handle's U.
+constexpr int kSellUMin = 4, kSellUMax = 9;
+
+template <class F>
+inline void with_sell_u(int u, F &&f)
+{
+    switch (u) {
+    case 4: f(std::integral_constant<int, 4>{}); break;
+    case 5: f(std::integral_constant<int, 5>{}); break;
+    case 6: f(std::integral_constant<int, 6>{}); break;
+    case 7: f(std::integral_constant<int, 7>{}); break;
+    case 9: f(std::integral_constant<int, 9>{}); break;
+    default: f(std::integral_constant<int, 8>{}); break;
+    }
+}
+
+// U for a matrix whose widest slice has w entries per row: w itself up to 9
+// (at least 4), else the U in [5, 9] that wastes the fewest loads.
+inline int pick_sell_u(int w)
+{
+    if (w <= kSellUMax) return w < kSellUMin ? kSellUMin : w;
+    int best = 8, waste = 1 << 30;
+    for (int u = kSellUMax; u >= 5; --u) {
+        const int wst = (w + u - 1) / u * u - w;
+        if (wst < waste) { waste = wst; best = u; }
+    }
+    return best;
 }
 
 // Layout fill: one lane per row writes its entries and the slice padding.
