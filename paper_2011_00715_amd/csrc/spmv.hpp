@@ -56,6 +56,33 @@ __device__ __forceinline__ bool gate_open(const SysState *st, int mode)
     return mode == kGateNone || gate_ok(load_gate(st), mode);
 }
 
+// sum over k = k0, k0 + L, ... below e of val[k] x[col[k]] in that order
+// (FMA), four entries per round with their gathers issued together.
+template <class V, int L>
+__device__ __forceinline__ V strided_dot(int k0, int e, const int32_t *__restrict__ col,
+                                         const V *__restrict__ val, const V *__restrict__ x)
+{
+    constexpr int U = 4;
+    V s = V(0);
+    for (int kb = k0; kb < e; kb += L * U) {
+        int c[U];
+        V v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int k = kb + u * L < e ? kb + u * L : e - 1;
+            c[u] = ld_stream(col + k);
+            v[u] = ld_stream(val + k);
+        }
+        V xv[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) xv[u] = x[c[u]];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (kb + u * L < e) s = fma(v[u], xv[u], s);
+    }
+    return s;
+}
+
 template <class V>
 struct TileLds {
     static constexpr int kCap = kTileBytes / (int)sizeof(V);
@@ -91,11 +118,14 @@ __device__ __forceinline__ void stream_tile(int r0, int r1, const int32_t *__res
                 c[u] = ld_stream(col + kc);
                 v[u] = ld_stream(val + kc);
             }
+            // all gathers before the first store: one latency per round
+            V xv[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) xv[u] = x[c[u]];
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 const int k = kb + u * kBlock;
-                const V xv = x[c[u]];
-                if (k < k1) sm.prod[k - k0] = v[u] * xv;
+                if (k < k1) sm.prod[k - k0] = v[u] * xv[u];
             }
         }
         __syncthreads();
@@ -110,10 +140,7 @@ __device__ __forceinline__ void stream_tile(int r0, int r1, const int32_t *__res
         for (int i = 0; i < nr; ++i) {
             const int a = sm.rp[i];
             const int e = sm.rp[i + 1];
-            V s = V(0);
-            for (int k = a + (int)threadIdx.x; k < e; k += kBlock)
-                s = fma(ld_stream(val + k), x[ld_stream(col + k)], s);
-            s = block_sum(s, sm.red);
+            const V s = block_sum(strided_dot<V, kBlock>(a + (int)threadIdx.x, e, col, val, x), sm.red);
             if (threadIdx.x == 0) fn(r0 + i, s);
             __syncthreads();
         }
@@ -160,8 +187,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv_vector(int n, const int32_t *__
     for (int row = rb + (int)threadIdx.x / L; row < re; row += RPB) {
         const int a = rowptr[row];
         const int e = rowptr[row + 1];
-        V s = V(0);
-        for (int k = a + lane; k < e; k += L) s = fma(ld_stream(val + k), x[ld_stream(col + k)], s);
+        V s = strided_dot<V, L>(a + lane, e, col, val, x);
 #pragma unroll
         for (int off = L / 2; off > 0; off >>= 1) s += __shfl_xor(s, off, L);
         if (lane == 0) y[row] = s;
@@ -382,11 +408,13 @@ __global__ __launch_bounds__(kBlock) void k_spmv_merge(int n, int nnz,
                 c[u] = ld_stream(col + kc);
                 v[u] = ld_stream(val + kc);
             }
+            V xv[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) xv[u] = x[c[u]];
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 const int k = kb + u * kBlock;
-                const V xv = x[c[u]];
-                if (k < k1) sm.prod[k - k0] = v[u] * xv;
+                if (k < k1) sm.prod[k - k0] = v[u] * xv[u];
             }
         }
     }
