@@ -273,6 +273,28 @@ typedef struct {
 int spk_ksp_solve(spk_mat *A, const double *b, double *x, const spk_ksp_opts *opts,
                   spk_ksp_result *res, void *stream);
 
+/*
+ * Multiple right-hand sides (Sec. 4 Response F3: Krylov methods with several
+ * right-hand sides read the matrix once for all of them and fuse the outer
+ * loops of their solves).  Blocks of k vectors are row-major n x k device
+ * double arrays: entry (i, j) at [i * k + j].  k must be 1, 2, 4, 8 or 16.
+ */
+
+/* Y = A X for k columns.  X, Y must not overlap.  SPK_EINVAL for a bad k or
+ * NULL.  Queued on `stream`. */
+int spk_mat_mult_multi(const spk_mat *A, int32_t k, const double *X, double *Y, void *stream);
+
+/* k independent FP64 Jacobi-PCG solves A x_j = b_j sharing every SpMM: each
+ * column keeps its own scalars, stopping test, true-residual restarts and
+ * result, exactly as spk_ksp_solve on that column (hist is not recorded).
+ * B: device n x k, read only; X: device n x k, initial guesses when
+ * opts->x0_nonzero, solutions on return.  res: host spk_ksp_result[k].
+ * SPK_EINVAL for a bad k, a mixed precision, NULL or overlapping B and X;
+ * SPK_EZERODIAG.  The workspace (6 n k doubles) is kept on the handle for
+ * the next call with the same k.  Returns when every column is done. */
+int spk_ksp_solve_multi(spk_mat *A, int32_t k, const double *B, double *X,
+                        const spk_ksp_opts *opts, spk_ksp_result *res, void *stream);
+
 /* ---------------------------------------------------------------- server
  * Continuous-batching solve server (Response A6: many different-size
  * problems solved simultaneously on the GPU).  Requests are admitted while

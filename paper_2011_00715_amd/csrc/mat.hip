@@ -884,6 +884,7 @@ int spk_mat_set_kernel(spk_mat *A, int kernel, int32_t param)
     }
     apply_partition(A);
     free_workspace(A);  // graphs and partials depend on the partition
+    free_multi(A);
     update_info(A);
     return SPK_OK;
 }
@@ -930,6 +931,7 @@ int spk_mat_destroy(spk_mat *A)
     if (!A) return SPK_OK;
     hipDeviceSynchronize();
     free_workspace(A);
+    free_multi(A);
     if (A->own_csr) {
         hipFree(A->rowptr);
         hipFree(A->col);

@@ -1,0 +1,506 @@
+// Multiple right-hand sides (Sec. 4 Response F3: Krylov methods with several
+// right-hand sides read the matrix once for all of them and fuse their outer
+// loops).  Vectors are row-major n x K (entry (i, j) at i K + j), so a gather
+// of row c fetches the K values of all columns with one or two vector loads.
+//
+//   k_spmm_*        Y = A X
+//   k_m_*           K independent Jacobi-PCG recurrences that share every
+//                   SpMM: per-column scalars and stopping tests, per-column
+//                   per-block partial sums reduced in a fixed order by
+//                   one-block finalize kernels, so each column's iterates are
+//                   those of its own single-right-hand-side solve up to the
+//                   rounding order of the SpMV and the dots.
+#pragma once
+
+#include "spmv.hpp"
+
+namespace spk {
+
+constexpr int kMultiMax = 16;
+
+// Purpose of a residual launch: the setup of a solve, or the true residual.
+enum { kMultiSetup = 0, kMultiTrue = 1 };
+
+// Columns still iterating (bit j), written by the finalize kernels.
+struct MultiCtl {
+    int32_t mask;
+    int32_t pad_;
+};
+
+struct MultiDesc {
+    int32_t n, K, nblk, R, ntiles;
+    int32_t sell;                // 1: the SELL layout drives the row walk
+    const int32_t *rowptr;
+    const int32_t *col;
+    const double *val;
+    const double *dinv;
+    SellView sv;
+    const double *sell_val;
+    const double *B;
+    double *X, *Rv, *Z, *P, *Q;  // n x K each
+    double *partials;            // [kNumPart][K][nblk]
+    SysState *st;                // K states
+    MultiCtl *ctl;
+};
+
+// Y-rows = A X-rows for one row, K columns, entries [a, e) of CSR; U
+// entries per round with their gathers issued together.
+template <int K>
+__device__ __forceinline__ void csr_row_multi(int a, int e, const int32_t *__restrict__ col,
+                                              const double *__restrict__ val,
+                                              const double *__restrict__ X, double acc[K])
+{
+    constexpr int U = K >= 8 ? 1 : 8 / K;
+#pragma unroll
+    for (int q = 0; q < K; ++q) acc[q] = 0.0;
+    for (int k0 = a; k0 < e; k0 += U) {
+        int c[U];
+        double v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int k = k0 + u < e ? k0 + u : e - 1;
+            c[u] = ld_stream(col + k);
+            v[u] = ld_stream(val + k);
+        }
+        double xv[U][K];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int q = 0; q < K; ++q) xv[u][q] = X[(size_t)c[u] * K + q];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (k0 + u < e)
+#pragma unroll
+                for (int q = 0; q < K; ++q) acc[q] = fma(v[u], xv[u][q], acc[q]);
+    }
+}
+
+// Same for lane `lane` of a SELL slice (b, slen), the row having rlen entries.
+template <class CI, int K>
+__device__ __forceinline__ void sell_row_multi(const SellView &sv, const double *__restrict__ val,
+                                               const double *__restrict__ X, int32_t b, int slen,
+                                               int rlen, int lane, int row, double acc[K])
+{
+    constexpr int U = K >= 8 ? 1 : 8 / K;
+    const CI *__restrict__ col = reinterpret_cast<const CI *>(sv.col) + b + lane;
+    const double *__restrict__ v = val + b + lane;
+#pragma unroll
+    for (int q = 0; q < K; ++q) acc[q] = 0.0;
+    for (int j0 = 0; j0 < slen; j0 += U) {
+        CI c[U];
+        double a[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int j = j0 + u < slen ? j0 + u : slen - 1;
+            c[u] = ld_stream(col + (size_t)j * kSell);
+            a[u] = ld_stream(v + (size_t)j * kSell);
+        }
+        double xv[U][K];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int q = 0; q < K; ++q) xv[u][q] = X[(size_t)(row + (int)c[u]) * K + q];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (j0 + u < rlen)
+#pragma unroll
+                for (int q = 0; q < K; ++q) acc[q] = fma(a[u], xv[u][q], acc[q]);
+    }
+}
+
+// Row walk of block l (of nblk) of a multi kernel: SELL slices in
+// round-robin order, or CSR rows of the block's contiguous tile range with
+// one row per lane.  fn(row, acc) gets the K products of the row.
+template <class CI, int K, class Fn>
+__device__ __forceinline__ void multi_rows(const MultiDesc &d, int l, int j, const double *__restrict__ X,
+                                           Fn &&fn)
+{
+    double acc[K];
+    if (d.sell) {
+        const int lane = threadIdx.x & (kWave - 1);
+        const int ns = (d.n + kSell - 1) / kSell;
+        for (int s = l * (kBlock / kWave) + (int)threadIdx.x / kWave; s < ns; s += d.nblk * (kBlock / kWave)) {
+            const int32_t b = d.sv.ptr[s], e = d.sv.ptr[s + 1];
+            const int row = s * kSell + lane;
+            if (row < d.n) {
+                sell_row_multi<CI, K>(d.sv, d.sell_val, X, b, (e - b) / kSell, d.sv.len[row], lane, row, acc);
+                fn(row, acc);
+            }
+        }
+    } else {
+        int t0, t1;
+        block_tiles(j, d.nblk, d.ntiles, t0, t1);
+        const int rb = t0 * d.R, re = min(t1 * d.R, d.n);
+        for (int row = rb + (int)threadIdx.x; row < re; row += kBlock) {
+            csr_row_multi<K>(d.rowptr[row], d.rowptr[row + 1], d.col, d.val, X, acc);
+            fn(row, acc);
+        }
+    }
+}
+
+// Block sums of K per-lane values, one partial per column: part[q * nblk + j].
+template <int K>
+__device__ __forceinline__ void block_partials(double v[K], double *sh /* [4][K] */, double *part,
+                                               int nblk, int j)
+{
+#pragma unroll
+    for (int q = 0; q < K; ++q) v[q] = wave_sum(v[q]);
+    const int w = threadIdx.x / kWave;
+    __syncthreads();
+    if ((threadIdx.x & (kWave - 1)) == 0)
+#pragma unroll
+        for (int q = 0; q < K; ++q) sh[w * K + q] = v[q];
+    __syncthreads();
+    if ((int)threadIdx.x < K) {
+        const int q = threadIdx.x;
+        double s = sh[q];
+#pragma unroll
+        for (int ww = 1; ww < kBlock / kWave; ++ww) s += sh[ww * K + q];
+        part[(size_t)q * nblk + j] = s;
+    }
+}
+
+__device__ __forceinline__ int multi_block(const MultiDesc &d, int &j)
+{
+    if ((int)blockIdx.x >= d.nblk) return -1;
+    j = xcd_remap(blockIdx.x, d.nblk);
+    return blockIdx.x;
+}
+
+// ------------------------------------------------------------------ SpMM
+template <class CI, int K>
+__global__ __launch_bounds__(kBlock) void k_spmm(MultiDesc d, const double *__restrict__ X, double *__restrict__ Y)
+{
+    int j;
+    const int l = multi_block(d, j);
+    if (l < 0) return;
+    multi_rows<CI, K>(d, l, j, X, [&](int row, const double *acc) {
+#pragma unroll
+        for (int q = 0; q < K; ++q) Y[(size_t)row * K + q] = acc[q];
+    });
+}
+
+// ------------------------------------------------------------------ residual
+// R = B - A X for the columns in `mask` (others untouched), per-column
+// per-block r.r and b.b.
+template <class CI, int K>
+__global__ __launch_bounds__(kBlock) void k_m_resid(MultiDesc d, int32_t mask)
+{
+    __shared__ double sh[(kBlock / kWave) * K];
+    int j;
+    const int l = multi_block(d, j);
+    if (l < 0) return;
+    double rr[K], bb[K];
+#pragma unroll
+    for (int q = 0; q < K; ++q) rr[q] = bb[q] = 0.0;
+    multi_rows<CI, K>(d, l, j, d.X, [&](int row, const double *acc) {
+#pragma unroll
+        for (int q = 0; q < K; ++q) {
+            if (!((mask >> q) & 1)) continue;
+            const double bi = d.B[(size_t)row * K + q];
+            const double ri = bi - acc[q];
+            d.Rv[(size_t)row * K + q] = ri;
+            rr[q] = fma(ri, ri, rr[q]);
+            bb[q] = fma(bi, bi, bb[q]);
+        }
+    });
+    block_partials<K>(rr, sh, d.partials + (size_t)kPartRr * K * d.nblk, d.nblk, j);
+    block_partials<K>(bb, sh, d.partials + (size_t)kPartBb * K * d.nblk, d.nblk, j);
+}
+
+// Column q's sum of partials part[q * nblk + 0 .. nblk), by one wavefront,
+// in a fixed order (lane-strided, then the butterfly).
+__device__ __forceinline__ double wave_reduce_col(const double *part, int nblk)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    double s = 0.0;
+    for (int i = lane; i < nblk; i += kWave) s += part[i];
+    return wave_sum(s);
+}
+
+__device__ __forceinline__ void publish_mask(const MultiDesc &d)
+{
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int32_t m = 0;
+        for (int q = 0; q < d.K; ++q)
+            if (d.st[q].status == SPK_RUNNING) m |= 1 << q;
+        d.ctl->mask = m;
+    }
+}
+
+// purpose kMultiSetup: norms, thresholds, stop at start; kMultiTrue: store the
+// true residual norm of the columns in mask.
+static __global__ __launch_bounds__(kBlock) void k_m_fin_resid(MultiDesc d, int purpose, int32_t mask)
+{
+    const int w = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
+    for (int q = w; q < d.K; q += kBlock / kWave) {
+        if (!((mask >> q) & 1)) continue;
+        const double RR = wave_reduce_col(d.partials + ((size_t)kPartRr * d.K + q) * d.nblk, d.nblk);
+        const double BB = wave_reduce_col(d.partials + ((size_t)kPartBb * d.K + q) * d.nblk, d.nblk);
+        if (lane != 0) continue;
+        SysState *st = d.st + q;
+        const double rn = sqrt(RR);
+        if (purpose == kMultiTrue) {
+            st->rnorm_true = rn;
+            continue;
+        }
+        const double bn = sqrt(BB);
+        st->bnorm = bn;
+        st->thresh = fmax(st->rtol * bn, st->atol);
+        st->rnorm = rn;
+        st->rnorm0 = rn;
+        if (bn == 0.0) st->status = SPK_CONVERGED_ATOL;
+        else if (!isfinite(rn) || !isfinite(bn)) st->status = SPK_DIVERGED_NANORINF;
+        else if (rn <= st->thresh) st->status = rn <= st->rtol * bn ? SPK_CONVERGED_RTOL : SPK_CONVERGED_ATOL;
+    }
+    publish_mask(d);
+}
+
+// ------------------------------------------------------------------ setup
+// Z = D^-1 R, P = Z for the running columns in mask, per-block r.z.
+template <int K>
+__global__ __launch_bounds__(kBlock) void k_m_setup(MultiDesc d, int32_t mask)
+{
+    __shared__ double sh[(kBlock / kWave) * K];
+    int j;
+    if (multi_block(d, j) < 0) return;
+    int t0, t1;
+    block_tiles(j, d.nblk, d.ntiles, t0, t1);
+    const int rb = t0 * d.R, re = min(t1 * d.R, d.n);
+    int run = 0;
+#pragma unroll
+    for (int q = 0; q < K; ++q) run |= (((mask >> q) & 1) && d.st[q].status == SPK_RUNNING) << q;
+    double rz[K];
+#pragma unroll
+    for (int q = 0; q < K; ++q) rz[q] = 0.0;
+    for (int i = rb + (int)threadIdx.x; i < re; i += kBlock) {
+        const double di = d.dinv[i];
+#pragma unroll
+        for (int q = 0; q < K; ++q) {
+            if (!((run >> q) & 1)) continue;
+            const size_t o = (size_t)i * K + q;
+            const double ri = d.Rv[o];
+            const double zi = di * ri;
+            d.Z[o] = zi;
+            d.P[o] = zi;
+            rz[q] = fma(ri, zi, rz[q]);
+        }
+    }
+    block_partials<K>(rz, sh, d.partials + (size_t)kPartRz * K * d.nblk, d.nblk, j);
+}
+
+static __global__ __launch_bounds__(kBlock) void k_m_fin_setup(MultiDesc d, int32_t mask)
+{
+    const int w = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
+    for (int q = w; q < d.K; q += kBlock / kWave) {
+        if (!((mask >> q) & 1)) continue;
+        SysState *st = d.st + q;
+        if (st->status != SPK_RUNNING) continue;
+        const double RZ = wave_reduce_col(d.partials + ((size_t)kPartRz * d.K + q) * d.nblk, d.nblk);
+        if (lane != 0) continue;
+        st->cmode = 0;
+        if (!isfinite(RZ)) st->status = SPK_DIVERGED_NANORINF;
+        else if (RZ < 0.0) st->status = SPK_DIVERGED_INDEFINITE_PC;
+        else if (RZ == 0.0) st->status = SPK_DIVERGED_BREAKDOWN;
+        else if (st->iter >= st->maxit) { st->status = SPK_DIVERGED_ITS; st->rho = RZ; }
+        else st->rho = RZ;
+    }
+    publish_mask(d);
+}
+
+// Restart the columns in mask from their true residual (already in R).
+static __global__ void k_m_restart(MultiDesc d, int32_t mask)
+{
+    const int q = threadIdx.x;
+    if (q < d.K && ((mask >> q) & 1)) {
+        d.st[q].status = SPK_RUNNING;
+        d.st[q].cmode = 0;
+    }
+}
+
+// ------------------------------------------------------------------ iteration
+// A: Q = A P, per-column per-block p.q (columns that stopped are multiplied
+// too: the matrix is read once either way; their partials are ignored).
+template <class CI, int K>
+__global__ __launch_bounds__(kBlock) void k_m_spmm_pq(MultiDesc d)
+{
+    __shared__ double sh[(kBlock / kWave) * K];
+    int j;
+    const int l = multi_block(d, j);
+    if (l < 0) return;
+    if (d.ctl->mask == 0) return;
+    double pq[K];
+#pragma unroll
+    for (int q = 0; q < K; ++q) pq[q] = 0.0;
+    multi_rows<CI, K>(d, l, j, d.P, [&](int row, const double *acc) {
+#pragma unroll
+        for (int q = 0; q < K; ++q) {
+            const size_t o = (size_t)row * K + q;
+            d.Q[o] = acc[q];
+            pq[q] = fma(acc[q], d.P[o], pq[q]);
+        }
+    });
+    block_partials<K>(pq, sh, d.partials + (size_t)kPartPq * K * d.nblk, d.nblk, j);
+}
+
+// F_A: eta = p.q and alpha per running column; eta <= 0 stops the column.
+static __global__ __launch_bounds__(kBlock) void k_m_fin_pq(MultiDesc d)
+{
+    if (d.ctl->mask == 0) return;
+    const int w = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
+    for (int q = w; q < d.K; q += kBlock / kWave) {
+        SysState *st = d.st + q;
+        if (st->status != SPK_RUNNING) continue;
+        const double eta = wave_reduce_col(d.partials + ((size_t)kPartPq * d.K + q) * d.nblk, d.nblk);
+        if (lane != 0) continue;
+        st->eta = eta;
+        st->cmode = 0;
+        if (!isfinite(eta)) st->status = SPK_DIVERGED_NANORINF;
+        else if (eta <= 0.0) st->status = SPK_DIVERGED_INDEFINITE_MAT;
+        else st->alpha = st->rho / eta;
+    }
+    publish_mask(d);
+}
+
+// B: R -= alpha Q, Z = D^-1 R for the running columns, per-block r.z, r.r.
+template <int K>
+__global__ __launch_bounds__(kBlock) void k_m_update(MultiDesc d)
+{
+    __shared__ double sh[(kBlock / kWave) * K];
+    int j;
+    if (multi_block(d, j) < 0) return;
+    const int mask = d.ctl->mask;
+    if (mask == 0) return;
+    double nal[K];
+#pragma unroll
+    for (int q = 0; q < K; ++q) nal[q] = ((mask >> q) & 1) ? -d.st[q].alpha : 0.0;
+    int t0, t1;
+    block_tiles(j, d.nblk, d.ntiles, t0, t1);
+    const int rb = t0 * d.R, re = min(t1 * d.R, d.n);
+    double rz[K], rr[K];
+#pragma unroll
+    for (int q = 0; q < K; ++q) rz[q] = rr[q] = 0.0;
+    for (int i = rb + (int)threadIdx.x; i < re; i += kBlock) {
+        const double di = d.dinv[i];
+#pragma unroll
+        for (int q = 0; q < K; ++q) {
+            if (!((mask >> q) & 1)) continue;
+            const size_t o = (size_t)i * K + q;
+            const double ri = fma(nal[q], d.Q[o], d.Rv[o]);
+            const double zi = di * ri;
+            d.Rv[o] = ri;
+            d.Z[o] = zi;
+            rz[q] = fma(ri, zi, rz[q]);
+            rr[q] = fma(ri, ri, rr[q]);
+        }
+    }
+    block_partials<K>(rz, sh, d.partials + (size_t)kPartRz * K * d.nblk, d.nblk, j);
+    block_partials<K>(rr, sh, d.partials + (size_t)kPartRr * K * d.nblk, d.nblk, j);
+}
+
+// F_B: per running column: iteration count, convergence, breakdowns, beta;
+// cmode 2 (x and p updates), 1 (last x update), as in the single solve.
+static __global__ __launch_bounds__(kBlock) void k_m_fin_update(MultiDesc d)
+{
+    const int mask0 = d.ctl->mask;
+    if (mask0 == 0) {  // every column has stopped: the p/x kernel does nothing
+        __syncthreads();
+        if (threadIdx.x == 0) d.ctl->pad_ = 0;
+        return;
+    }
+    const int w = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
+    for (int q = w; q < d.K; q += kBlock / kWave) {
+        if (!((mask0 >> q) & 1)) continue;
+        SysState *st = d.st + q;
+        const double RZ = wave_reduce_col(d.partials + ((size_t)kPartRz * d.K + q) * d.nblk, d.nblk);
+        const double RR = wave_reduce_col(d.partials + ((size_t)kPartRr * d.K + q) * d.nblk, d.nblk);
+        if (lane != 0) continue;
+        const int k = ++st->iter;
+        const double rn = sqrt(RR);
+        st->rnorm = rn;
+        st->cmode = 1;
+        if (!isfinite(rn)) st->status = SPK_DIVERGED_NANORINF;
+        else if (rn <= st->thresh)
+            st->status = rn <= st->rtol * st->bnorm ? SPK_CONVERGED_RTOL : SPK_CONVERGED_ATOL;
+        else if (k >= st->maxit) st->status = SPK_DIVERGED_ITS;
+        else if (!isfinite(RZ)) st->status = SPK_DIVERGED_NANORINF;
+        else if (RZ < 0.0) st->status = SPK_DIVERGED_INDEFINITE_PC;
+        else if (RZ == 0.0) st->status = SPK_DIVERGED_BREAKDOWN;
+        else { st->beta = RZ / st->rho; st->rho = RZ; st->cmode = 2; }
+    }
+    __syncthreads();
+    // the p/x kernel needs the pre-update mask (columns stopping now still
+    // take their last x update): keep it in pad_
+    if (threadIdx.x == 0) d.ctl->pad_ = mask0;
+    publish_mask(d);
+}
+
+// C: per column, cmode 2: x += alpha p, p = z + beta p; cmode 1: x += alpha p.
+template <int K>
+__global__ __launch_bounds__(kBlock) void k_m_px(MultiDesc d)
+{
+    int j;
+    if (multi_block(d, j) < 0) return;
+    const int mask0 = d.ctl->pad_;
+    if (mask0 == 0) return;
+    int cm[K];
+    double al[K], be[K];
+#pragma unroll
+    for (int q = 0; q < K; ++q) {
+        cm[q] = ((mask0 >> q) & 1) ? d.st[q].cmode : 0;
+        al[q] = d.st[q].alpha;
+        be[q] = d.st[q].beta;
+    }
+    int t0, t1;
+    block_tiles(j, d.nblk, d.ntiles, t0, t1);
+    const int rb = t0 * d.R, re = min(t1 * d.R, d.n);
+    for (int i = rb + (int)threadIdx.x; i < re; i += kBlock) {
+#pragma unroll
+        for (int q = 0; q < K; ++q) {
+            if (cm[q] == 0) continue;
+            const size_t o = (size_t)i * K + q;
+            const double pi = d.P[o];
+            d.X[o] = fma(al[q], pi, d.X[o]);
+            if (cm[q] == 2) d.P[o] = fma(be[q], pi, d.Z[o]);
+        }
+    }
+}
+
+// Per-column state for a new solve (FP64, one thread per column), all
+// columns running until the setup kernels decide otherwise.
+static __global__ void k_m_init(MultiDesc d, double rtol, double atol, int maxit)
+{
+    const int q = threadIdx.x;
+    if (q < d.K) {
+        SysState *st = d.st + q;
+        *st = SysState{};
+        st->status = SPK_RUNNING;
+        st->phase = kPhaseInner;
+        st->maxit = maxit;
+        st->rtol = rtol;
+        st->atol = atol;
+    }
+    if (q == 0) {
+        d.ctl->mask = (1 << d.K) - 1;
+        d.ctl->pad_ = 0;
+    }
+}
+
+// x = 0 for the columns in mask (right-hand sides that are zero).
+template <int K>
+__global__ void k_m_zero_cols(MultiDesc d, int32_t mask)
+{
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < d.n; i += gridDim.x * blockDim.x)
+#pragma unroll
+        for (int q = 0; q < K; ++q)
+            if ((mask >> q) & 1) d.X[(size_t)i * K + q] = 0.0;
+}
+
+// The running-column mask to pinned host memory (one thread's store).
+static __global__ void k_m_publish(const MultiCtl *ctl, int32_t *host)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) host[0] = ctl->mask;
+}
+
+}  // namespace spk

@@ -52,6 +52,10 @@ struct Workspace {
 
 }  // namespace spk
 
+namespace spk {
+struct MultiWs;
+}
+
 struct spk_mat {
     int32_t n = 0;
     int64_t nnz = 0;
@@ -85,6 +89,7 @@ struct spk_mat {
     double *sell_val = nullptr;
     float *sell_val32 = nullptr;
     spk::Workspace *ws = nullptr;
+    spk::MultiWs *mws = nullptr;  // multi-right-hand-side solver workspace
     int64_t bytes = 0;
 };
 
@@ -100,5 +105,6 @@ void update_info(spk_mat *A);
 constexpr double kRuDelta = 0.05;  // default refinement trigger with reliable updates
 double inner_rtol_of(const spk_ksp_opts &o);
 int ensure_f32(spk_mat *A, hipStream_t s);
+void free_multi(spk_mat *A);
 
 }  // namespace spk

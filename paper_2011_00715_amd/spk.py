@@ -110,6 +110,9 @@ _sig("spk_vec_nrm2", ctypes.c_int, [i32, P, P, P])
 _sig("spk_ksp_opts_default", None, [ctypes.POINTER(KspOpts)])
 _sig("spk_ksp_solve", ctypes.c_int, [P, P, P, ctypes.POINTER(KspOpts),
                                      ctypes.POINTER(KspResult), P])
+_sig("spk_mat_mult_multi", ctypes.c_int, [P, i32, P, P, P])
+_sig("spk_ksp_solve_multi", ctypes.c_int, [P, i32, P, P, ctypes.POINTER(KspOpts),
+                                           ctypes.POINTER(KspResult), P])
 _sig("spk_server_opts_default", None, [ctypes.POINTER(ServerOpts)])
 _sig("spk_server_create", ctypes.c_int, [ctypes.POINTER(ServerOpts), P, ctypes.POINTER(P)])
 _sig("spk_server_submit", ctypes.c_int, [P, i32, i64, P, P, P, P, ctypes.POINTER(KspOpts),
@@ -130,7 +133,7 @@ EXPORTS = [
     "spk_mat_create_csr", "spk_mat_set_kernel", "spk_mat_mult", "spk_mat_mult_f32",
     "spk_mat_get_info", "spk_pc_jacobi_apply", "spk_pc_chebyshev", "spk_mat_destroy", "spk_vec_axpy",
     "spk_vec_aypx", "spk_vec_dot", "spk_vec_dot2", "spk_vec_nrm2", "spk_ksp_opts_default",
-    "spk_ksp_solve", "spk_server_opts_default", "spk_server_create", "spk_server_submit",
+    "spk_ksp_solve", "spk_mat_mult_multi", "spk_ksp_solve_multi", "spk_server_opts_default", "spk_server_create", "spk_server_submit",
     "spk_server_progress", "spk_server_poll", "spk_server_destroy", "spk_status_str",
     "spk_reason_str", "spk_last_error", "spk_now", "spk_runtime_version", "spk_bw_copy",
     "spk_cache_flush",
@@ -338,6 +341,39 @@ def ksp_opts(**kw) -> KspOpts:
             raise AttributeError(k)
         setattr(o, k, v)
     return o
+
+
+def _block(t: torch.Tensor, n: int, name: str):
+    """A row-major n x k float64 CUDA block: (pointer, k)."""
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda" or t.dtype != torch.float64:
+        raise TypeError(f"{name} must be a float64 CUDA tensor")
+    if t.dim() != 2 or t.shape[0] != n or not t.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous ({n}, k) tensor")
+    return P(t.data_ptr()), t.shape[1]
+
+
+def mat_mult_multi(A: Mat, X: torch.Tensor, Y: torch.Tensor, stream=None):
+    """Y = A X for the k columns of the row-major (n, k) blocks X and Y."""
+    px, k = _block(X, A.n, "X")
+    py, k2 = _block(Y, A.n, "Y")
+    if k != k2:
+        raise ValueError("X and Y must have the same number of columns")
+    _check(_lib.spk_mat_mult_multi(A.handle, int(k), px, py, _stream(stream)), "spk_mat_mult_multi")
+
+
+def ksp_solve_multi(A: Mat, B: torch.Tensor, X: torch.Tensor, opts: KspOpts | None = None,
+                    stream=None) -> list:
+    """k independent solves A X[:, j] = B[:, j] sharing every SpMM; returns
+    one KspResult per column."""
+    pb, k = _block(B, A.n, "B")
+    px, k2 = _block(X, A.n, "X")
+    if k != k2:
+        raise ValueError("B and X must have the same number of columns")
+    o = opts if opts is not None else ksp_opts_default()
+    res = (KspResult * k)()
+    _check(_lib.spk_ksp_solve_multi(A.handle, int(k), pb, px, ctypes.byref(o), res, _stream(stream)),
+           "spk_ksp_solve_multi")
+    return list(res)
 
 
 def ksp_solve(A: Mat, b, x, opts: KspOpts | None = None, hist=None, stream=None) -> KspResult:
