@@ -160,6 +160,46 @@ __device__ __forceinline__ void block_partials(double v[K], double *sh /* [4][K]
     }
 }
 
+// Block sums when lane t always holds column t % K (flat n x K element
+// walks with a stride that is a multiple of K): lanes of one column are
+// combined by the butterfly levels at distances >= K, then the waves in order.
+template <int K>
+__device__ __forceinline__ void block_partials_flat(double v, double *sh /* [4][K] */, double *part,
+                                                    int nblk, int j)
+{
+#pragma unroll
+    for (int off = kWave / 2; off >= K; off >>= 1) v += __shfl_xor(v, off, kWave);
+    const int w = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
+    __syncthreads();
+    if (lane < K) sh[w * K + lane] = v;
+    __syncthreads();
+    if ((int)threadIdx.x < K) {
+        const int q = threadIdx.x;
+        double s = sh[q];
+#pragma unroll
+        for (int ww = 1; ww < kBlock / kWave; ++ww) s += sh[ww * K + q];
+        part[(size_t)q * nblk + j] = s;
+    }
+}
+
+// Elements [rb K, re K) of the block's rows in the flat n x K layout, with
+// the lane's fixed column q = threadIdx.x % K; fn(e, i) for element e of row i.
+template <int K, class Fn>
+__device__ __forceinline__ void flat_walk(const MultiDesc &d, int j, Fn &&fn)
+{
+    int t0, t1;
+    block_tiles(j, d.nblk, d.ntiles, t0, t1);
+    const int64_t e0 = (int64_t)t0 * d.R * K, e1 = (int64_t)min(t1 * d.R, d.n) * K;
+    constexpr int U = 4;
+    for (int64_t eb = e0 + threadIdx.x; eb < e1; eb += (int64_t)kBlock * U) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t e = eb + (int64_t)u * kBlock;
+            if (e < e1) fn(e, (int)(e / K));
+        }
+    }
+}
+
 __device__ __forceinline__ int multi_block(const MultiDesc &d, int &j)
 {
     if ((int)blockIdx.x >= d.nblk) return -1;
@@ -265,29 +305,18 @@ __global__ __launch_bounds__(kBlock) void k_m_setup(MultiDesc d, int32_t mask)
     __shared__ double sh[(kBlock / kWave) * K];
     int j;
     if (multi_block(d, j) < 0) return;
-    int t0, t1;
-    block_tiles(j, d.nblk, d.ntiles, t0, t1);
-    const int rb = t0 * d.R, re = min(t1 * d.R, d.n);
-    int run = 0;
-#pragma unroll
-    for (int q = 0; q < K; ++q) run |= (((mask >> q) & 1) && d.st[q].status == SPK_RUNNING) << q;
-    double rz[K];
-#pragma unroll
-    for (int q = 0; q < K; ++q) rz[q] = 0.0;
-    for (int i = rb + (int)threadIdx.x; i < re; i += kBlock) {
-        const double di = d.dinv[i];
-#pragma unroll
-        for (int q = 0; q < K; ++q) {
-            if (!((run >> q) & 1)) continue;
-            const size_t o = (size_t)i * K + q;
-            const double ri = d.Rv[o];
-            const double zi = di * ri;
-            d.Z[o] = zi;
-            d.P[o] = zi;
-            rz[q] = fma(ri, zi, rz[q]);
-        }
-    }
-    block_partials<K>(rz, sh, d.partials + (size_t)kPartRz * K * d.nblk, d.nblk, j);
+    const int q = threadIdx.x % K;
+    const bool run = ((mask >> q) & 1) && d.st[q].status == SPK_RUNNING;
+    double rz = 0.0;
+    if (run)
+        flat_walk<K>(d, j, [&](int64_t e, int i) {
+            const double ri = d.Rv[e];
+            const double zi = d.dinv[i] * ri;
+            d.Z[e] = zi;
+            d.P[e] = zi;
+            rz = fma(ri, zi, rz);
+        });
+    block_partials_flat<K>(rz, sh, d.partials + (size_t)kPartRz * K * d.nblk, d.nblk, j);
 }
 
 static __global__ __launch_bounds__(kBlock) void k_m_fin_setup(MultiDesc d, int32_t mask)
@@ -372,31 +401,21 @@ __global__ __launch_bounds__(kBlock) void k_m_update(MultiDesc d)
     if (multi_block(d, j) < 0) return;
     const int mask = d.ctl->mask;
     if (mask == 0) return;
-    double nal[K];
-#pragma unroll
-    for (int q = 0; q < K; ++q) nal[q] = ((mask >> q) & 1) ? -d.st[q].alpha : 0.0;
-    int t0, t1;
-    block_tiles(j, d.nblk, d.ntiles, t0, t1);
-    const int rb = t0 * d.R, re = min(t1 * d.R, d.n);
-    double rz[K], rr[K];
-#pragma unroll
-    for (int q = 0; q < K; ++q) rz[q] = rr[q] = 0.0;
-    for (int i = rb + (int)threadIdx.x; i < re; i += kBlock) {
-        const double di = d.dinv[i];
-#pragma unroll
-        for (int q = 0; q < K; ++q) {
-            if (!((mask >> q) & 1)) continue;
-            const size_t o = (size_t)i * K + q;
-            const double ri = fma(nal[q], d.Q[o], d.Rv[o]);
-            const double zi = di * ri;
-            d.Rv[o] = ri;
-            d.Z[o] = zi;
-            rz[q] = fma(ri, zi, rz[q]);
-            rr[q] = fma(ri, ri, rr[q]);
-        }
-    }
-    block_partials<K>(rz, sh, d.partials + (size_t)kPartRz * K * d.nblk, d.nblk, j);
-    block_partials<K>(rr, sh, d.partials + (size_t)kPartRr * K * d.nblk, d.nblk, j);
+    const int q = threadIdx.x % K;
+    const bool run = (mask >> q) & 1;
+    const double nal = run ? -d.st[q].alpha : 0.0;
+    double rz = 0.0, rr = 0.0;
+    if (run)
+        flat_walk<K>(d, j, [&](int64_t e, int i) {
+            const double ri = fma(nal, d.Q[e], d.Rv[e]);
+            const double zi = d.dinv[i] * ri;
+            d.Rv[e] = ri;
+            d.Z[e] = zi;
+            rz = fma(ri, zi, rz);
+            rr = fma(ri, ri, rr);
+        });
+    block_partials_flat<K>(rz, sh, d.partials + (size_t)kPartRz * K * d.nblk, d.nblk, j);
+    block_partials_flat<K>(rr, sh, d.partials + (size_t)kPartRr * K * d.nblk, d.nblk, j);
 }
 
 // F_B: per running column: iteration count, convergence, breakdowns, beta;
@@ -444,27 +463,15 @@ __global__ __launch_bounds__(kBlock) void k_m_px(MultiDesc d)
     if (multi_block(d, j) < 0) return;
     const int mask0 = d.ctl->pad_;
     if (mask0 == 0) return;
-    int cm[K];
-    double al[K], be[K];
-#pragma unroll
-    for (int q = 0; q < K; ++q) {
-        cm[q] = ((mask0 >> q) & 1) ? d.st[q].cmode : 0;
-        al[q] = d.st[q].alpha;
-        be[q] = d.st[q].beta;
-    }
-    int t0, t1;
-    block_tiles(j, d.nblk, d.ntiles, t0, t1);
-    const int rb = t0 * d.R, re = min(t1 * d.R, d.n);
-    for (int i = rb + (int)threadIdx.x; i < re; i += kBlock) {
-#pragma unroll
-        for (int q = 0; q < K; ++q) {
-            if (cm[q] == 0) continue;
-            const size_t o = (size_t)i * K + q;
-            const double pi = d.P[o];
-            d.X[o] = fma(al[q], pi, d.X[o]);
-            if (cm[q] == 2) d.P[o] = fma(be[q], pi, d.Z[o]);
-        }
-    }
+    const int q = threadIdx.x % K;
+    const int cm = ((mask0 >> q) & 1) ? d.st[q].cmode : 0;
+    if (cm == 0) return;  // no barrier follows
+    const double al = d.st[q].alpha, be = d.st[q].beta;
+    flat_walk<K>(d, j, [&](int64_t e, int) {
+        const double pi = d.P[e];
+        d.X[e] = fma(al, pi, d.X[e]);
+        if (cm == 2) d.P[e] = fma(be, pi, d.Z[e]);
+    });
 }
 
 // Per-column state for a new solve (FP64, one thread per column), all
