@@ -43,16 +43,18 @@ struct MultiDesc {
     MultiCtl *ctl;
 };
 
-// Y-rows = A X-rows for one row, K columns, entries [a, e) of CSR; U
-// entries per round with their gathers issued together.
+// One (row, column) item per lane: a wavefront takes G = 64 / K consecutive
+// rows and all K columns, lane t holding row t / K and column q = t % K, so
+// the K values gathered for an entry are adjacent lanes' addresses (one
+// contiguous 8K-byte segment per row) and the outputs are lane-contiguous.
+// The lanes of a row load the same offsets and values (a broadcast).
+// Entries in column order, FMA, U per round with the gathers issued together.
 template <int K>
-__device__ __forceinline__ void csr_row_multi(int a, int e, const int32_t *__restrict__ col,
-                                              const double *__restrict__ val,
-                                              const double *__restrict__ X, double acc[K])
+__device__ __forceinline__ double csr_item(int a, int e, int q, const int32_t *__restrict__ col,
+                                           const double *__restrict__ val, const double *__restrict__ X)
 {
-    constexpr int U = K >= 8 ? 1 : 8 / K;
-#pragma unroll
-    for (int q = 0; q < K; ++q) acc[q] = 0.0;
+    constexpr int U = 8;
+    double acc = 0.0;
     for (int k0 = a; k0 < e; k0 += U) {
         int c[U];
         double v[U];
@@ -62,30 +64,25 @@ __device__ __forceinline__ void csr_row_multi(int a, int e, const int32_t *__res
             c[u] = ld_stream(col + k);
             v[u] = ld_stream(val + k);
         }
-        double xv[U][K];
+        double xv[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) xv[u] = X[(size_t)c[u] * K + q];
 #pragma unroll
         for (int u = 0; u < U; ++u)
-#pragma unroll
-            for (int q = 0; q < K; ++q) xv[u][q] = X[(size_t)c[u] * K + q];
-#pragma unroll
-        for (int u = 0; u < U; ++u)
-            if (k0 + u < e)
-#pragma unroll
-                for (int q = 0; q < K; ++q) acc[q] = fma(v[u], xv[u][q], acc[q]);
+            if (k0 + u < e) acc = fma(v[u], xv[u], acc);
     }
+    return acc;
 }
 
-// Same for lane `lane` of a SELL slice (b, slen), the row having rlen entries.
 template <class CI, int K>
-__device__ __forceinline__ void sell_row_multi(const SellView &sv, const double *__restrict__ val,
-                                               const double *__restrict__ X, int32_t b, int slen,
-                                               int rlen, int lane, int row, double acc[K])
+__device__ __forceinline__ double sell_item(const SellView &sv, const double *__restrict__ val,
+                                            const double *__restrict__ X, int32_t b, int slen, int rlen,
+                                            int so, int row, int q)
 {
-    constexpr int U = K >= 8 ? 1 : 8 / K;
-    const CI *__restrict__ col = reinterpret_cast<const CI *>(sv.col) + b + lane;
-    const double *__restrict__ v = val + b + lane;
-#pragma unroll
-    for (int q = 0; q < K; ++q) acc[q] = 0.0;
+    constexpr int U = 8;
+    const CI *__restrict__ col = reinterpret_cast<const CI *>(sv.col) + b + so;
+    const double *__restrict__ v = val + b + so;
+    double acc = 0.0;
     for (int j0 = 0; j0 < slen; j0 += U) {
         CI c[U];
         double a[U];
@@ -95,68 +92,47 @@ __device__ __forceinline__ void sell_row_multi(const SellView &sv, const double 
             c[u] = ld_stream(col + (size_t)j * kSell);
             a[u] = ld_stream(v + (size_t)j * kSell);
         }
-        double xv[U][K];
+        double xv[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) xv[u] = X[(size_t)(row + (int)c[u]) * K + q];
 #pragma unroll
         for (int u = 0; u < U; ++u)
-#pragma unroll
-            for (int q = 0; q < K; ++q) xv[u][q] = X[(size_t)(row + (int)c[u]) * K + q];
-#pragma unroll
-        for (int u = 0; u < U; ++u)
-            if (j0 + u < rlen)
-#pragma unroll
-                for (int q = 0; q < K; ++q) acc[q] = fma(a[u], xv[u][q], acc[q]);
+            if (j0 + u < rlen) acc = fma(a[u], xv[u], acc);
     }
+    return acc;
 }
 
-// Row walk of block l (of nblk) of a multi kernel: SELL slices in
-// round-robin order, or CSR rows of the block's contiguous tile range with
-// one row per lane.  fn(row, acc) gets the K products of the row.
+// Items of block l (of nblk): SELL row groups in round-robin order (slice s
+// has K groups of G rows), or the block's contiguous tile range of CSR rows.
+// fn(e, row, y) for item e = row K + q with y = (A X)[row, q].
 template <class CI, int K, class Fn>
-__device__ __forceinline__ void multi_rows(const MultiDesc &d, int l, int j, const double *__restrict__ X,
-                                           Fn &&fn)
+__device__ __forceinline__ void multi_items(const MultiDesc &d, int l, int j, const double *__restrict__ X,
+                                            Fn &&fn)
 {
-    double acc[K];
+    constexpr int G = kWave / K;
+    const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
+    const int q = lane % K, ro = lane / K;
     if (d.sell) {
-        const int lane = threadIdx.x & (kWave - 1);
         const int ns = (d.n + kSell - 1) / kSell;
-        for (int s = l * (kBlock / kWave) + (int)threadIdx.x / kWave; s < ns; s += d.nblk * (kBlock / kWave)) {
+        const int ngroups = ns * K;
+        for (int g = l * (kBlock / kWave) + wv; g < ngroups; g += d.nblk * (kBlock / kWave)) {
+            const int s = g / K, so = (g % K) * G + ro;
+            const int row = s * kSell + so;
+            if (row >= d.n) continue;
             const int32_t b = d.sv.ptr[s], e = d.sv.ptr[s + 1];
-            const int row = s * kSell + lane;
-            if (row < d.n) {
-                sell_row_multi<CI, K>(d.sv, d.sell_val, X, b, (e - b) / kSell, d.sv.len[row], lane, row, acc);
-                fn(row, acc);
-            }
+            const double y = sell_item<CI, K>(d.sv, d.sell_val, X, b, (e - b) / kSell, d.sv.len[row], so, row, q);
+            fn((int64_t)row * K + q, row, y);
         }
     } else {
         int t0, t1;
         block_tiles(j, d.nblk, d.ntiles, t0, t1);
         const int rb = t0 * d.R, re = min(t1 * d.R, d.n);
-        for (int row = rb + (int)threadIdx.x; row < re; row += kBlock) {
-            csr_row_multi<K>(d.rowptr[row], d.rowptr[row + 1], d.col, d.val, X, acc);
-            fn(row, acc);
+        for (int r0 = rb + wv * G; r0 < re; r0 += (kBlock / kWave) * G) {
+            const int row = r0 + ro;
+            if (row >= re) continue;
+            const double y = csr_item<K>(d.rowptr[row], d.rowptr[row + 1], q, d.col, d.val, X);
+            fn((int64_t)row * K + q, row, y);
         }
-    }
-}
-
-// Block sums of K per-lane values, one partial per column: part[q * nblk + j].
-template <int K>
-__device__ __forceinline__ void block_partials(double v[K], double *sh /* [4][K] */, double *part,
-                                               int nblk, int j)
-{
-#pragma unroll
-    for (int q = 0; q < K; ++q) v[q] = wave_sum(v[q]);
-    const int w = threadIdx.x / kWave;
-    __syncthreads();
-    if ((threadIdx.x & (kWave - 1)) == 0)
-#pragma unroll
-        for (int q = 0; q < K; ++q) sh[w * K + q] = v[q];
-    __syncthreads();
-    if ((int)threadIdx.x < K) {
-        const int q = threadIdx.x;
-        double s = sh[q];
-#pragma unroll
-        for (int ww = 1; ww < kBlock / kWave; ++ww) s += sh[ww * K + q];
-        part[(size_t)q * nblk + j] = s;
     }
 }
 
@@ -214,10 +190,7 @@ __global__ __launch_bounds__(kBlock) void k_spmm(MultiDesc d, const double *__re
     int j;
     const int l = multi_block(d, j);
     if (l < 0) return;
-    multi_rows<CI, K>(d, l, j, X, [&](int row, const double *acc) {
-#pragma unroll
-        for (int q = 0; q < K; ++q) Y[(size_t)row * K + q] = acc[q];
-    });
+    multi_items<CI, K>(d, l, j, X, [&](int64_t e, int, double y) { Y[e] = y; });
 }
 
 // ------------------------------------------------------------------ residual
@@ -230,22 +203,19 @@ __global__ __launch_bounds__(kBlock) void k_m_resid(MultiDesc d, int32_t mask)
     int j;
     const int l = multi_block(d, j);
     if (l < 0) return;
-    double rr[K], bb[K];
-#pragma unroll
-    for (int q = 0; q < K; ++q) rr[q] = bb[q] = 0.0;
-    multi_rows<CI, K>(d, l, j, d.X, [&](int row, const double *acc) {
-#pragma unroll
-        for (int q = 0; q < K; ++q) {
-            if (!((mask >> q) & 1)) continue;
-            const double bi = d.B[(size_t)row * K + q];
-            const double ri = bi - acc[q];
-            d.Rv[(size_t)row * K + q] = ri;
-            rr[q] = fma(ri, ri, rr[q]);
-            bb[q] = fma(bi, bi, bb[q]);
-        }
+    const int q = threadIdx.x % K;
+    const bool on = (mask >> q) & 1;
+    double rr = 0.0, bb = 0.0;
+    multi_items<CI, K>(d, l, j, d.X, [&](int64_t e, int, double y) {
+        if (!on) return;
+        const double bi = d.B[e];
+        const double ri = bi - y;
+        d.Rv[e] = ri;
+        rr = fma(ri, ri, rr);
+        bb = fma(bi, bi, bb);
     });
-    block_partials<K>(rr, sh, d.partials + (size_t)kPartRr * K * d.nblk, d.nblk, j);
-    block_partials<K>(bb, sh, d.partials + (size_t)kPartBb * K * d.nblk, d.nblk, j);
+    block_partials_flat<K>(rr, sh, d.partials + (size_t)kPartRr * K * d.nblk, d.nblk, j);
+    block_partials_flat<K>(bb, sh, d.partials + (size_t)kPartBb * K * d.nblk, d.nblk, j);
 }
 
 // Column q's sum of partials part[q * nblk + 0 .. nblk), by one wavefront,
@@ -359,18 +329,12 @@ __global__ __launch_bounds__(kBlock) void k_m_spmm_pq(MultiDesc d)
     const int l = multi_block(d, j);
     if (l < 0) return;
     if (d.ctl->mask == 0) return;
-    double pq[K];
-#pragma unroll
-    for (int q = 0; q < K; ++q) pq[q] = 0.0;
-    multi_rows<CI, K>(d, l, j, d.P, [&](int row, const double *acc) {
-#pragma unroll
-        for (int q = 0; q < K; ++q) {
-            const size_t o = (size_t)row * K + q;
-            d.Q[o] = acc[q];
-            pq[q] = fma(acc[q], d.P[o], pq[q]);
-        }
+    double pq = 0.0;
+    multi_items<CI, K>(d, l, j, d.P, [&](int64_t e, int, double y) {
+        d.Q[e] = y;
+        pq = fma(y, d.P[e], pq);
     });
-    block_partials<K>(pq, sh, d.partials + (size_t)kPartPq * K * d.nblk, d.nblk, j);
+    block_partials_flat<K>(pq, sh, d.partials + (size_t)kPartPq * K * d.nblk, d.nblk, j);
 }
 
 // F_A: eta = p.q and alpha per running column; eta <= 0 stops the column.
