@@ -128,14 +128,14 @@ static MultiDesc solve_desc(const spk_mat *A, MultiWs *w)
 
 static void enqueue_multi_iter(const spk_mat *A, const MultiDesc &d, hipStream_t s)
 {
-    const dim3 g(A->nblk), t(kBlock), one(1);
+    const dim3 g(A->nblk), t(kBlock), cols(d.K);  // finalize: one block per column
     with_multi(A, d.K, [&](auto ct, auto kc) {
         using CI = decltype(ct);
         constexpr int K = decltype(kc)::value;
         hipLaunchKernelGGL((k_m_spmm_pq<CI, K>), g, t, 0, s, d);
-        hipLaunchKernelGGL(k_m_fin_pq, one, t, 0, s, d);
+        hipLaunchKernelGGL(k_m_fin_pq, cols, t, 0, s, d);
         hipLaunchKernelGGL((k_m_update<K>), g, t, 0, s, d);
-        hipLaunchKernelGGL(k_m_fin_update, one, t, 0, s, d);
+        hipLaunchKernelGGL(k_m_fin_update, cols, t, 0, s, d);
         hipLaunchKernelGGL((k_m_px<K>), g, t, 0, s, d);
     });
 }
@@ -147,7 +147,7 @@ static int multi_resid(const spk_mat *A, const MultiDesc &d, int purpose, int32_
         constexpr int K = decltype(kc)::value;
         hipLaunchKernelGGL((k_m_resid<CI, K>), dim3(A->nblk), dim3(kBlock), 0, s, d, mask);
     });
-    hipLaunchKernelGGL(k_m_fin_resid, dim3(1), dim3(kBlock), 0, s, d, purpose, mask);
+    hipLaunchKernelGGL(k_m_fin_resid, dim3(d.K), dim3(kBlock), 0, s, d, purpose, mask);
     SPK_HIP(hipGetLastError());
     return SPK_OK;
 }
@@ -158,7 +158,7 @@ static int multi_setup(const spk_mat *A, const MultiDesc &d, int32_t mask, hipSt
         constexpr int K = decltype(kc)::value;
         hipLaunchKernelGGL((k_m_setup<K>), dim3(A->nblk), dim3(kBlock), 0, s, d, mask);
     });
-    hipLaunchKernelGGL(k_m_fin_setup, dim3(1), dim3(kBlock), 0, s, d, mask);
+    hipLaunchKernelGGL(k_m_fin_setup, dim3(d.K), dim3(kBlock), 0, s, d, mask);
     SPK_HIP(hipGetLastError());
     return SPK_OK;
 }

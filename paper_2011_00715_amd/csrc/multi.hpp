@@ -43,18 +43,16 @@ struct MultiDesc {
     MultiCtl *ctl;
 };
 
-// One (row, column) item per lane: a wavefront takes G = 64 / K consecutive
-// rows and all K columns, lane t holding row t / K and column q = t % K, so
-// the K values gathered for an entry are adjacent lanes' addresses (one
-// contiguous 8K-byte segment per row) and the outputs are lane-contiguous.
-// The lanes of a row load the same offsets and values (a broadcast).
-// Entries in column order, FMA, U per round with the gathers issued together.
+// Y-rows = A X-rows for one row, K columns, entries [a, e) of CSR; U
+// entries per round with their gathers issued together.
 template <int K>
-__device__ __forceinline__ double csr_item(int a, int e, int q, const int32_t *__restrict__ col,
-                                           const double *__restrict__ val, const double *__restrict__ X)
+__device__ __forceinline__ void csr_row_multi(int a, int e, const int32_t *__restrict__ col,
+                                              const double *__restrict__ val,
+                                              const double *__restrict__ X, double acc[K])
 {
-    constexpr int U = 8;
-    double acc = 0.0;
+    constexpr int U = K >= 8 ? 1 : 8 / K;
+#pragma unroll
+    for (int q = 0; q < K; ++q) acc[q] = 0.0;
     for (int k0 = a; k0 < e; k0 += U) {
         int c[U];
         double v[U];
@@ -64,25 +62,30 @@ __device__ __forceinline__ double csr_item(int a, int e, int q, const int32_t *_
             c[u] = ld_stream(col + k);
             v[u] = ld_stream(val + k);
         }
-        double xv[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) xv[u] = X[(size_t)c[u] * K + q];
+        double xv[U][K];
 #pragma unroll
         for (int u = 0; u < U; ++u)
-            if (k0 + u < e) acc = fma(v[u], xv[u], acc);
+#pragma unroll
+            for (int q = 0; q < K; ++q) xv[u][q] = X[(size_t)c[u] * K + q];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (k0 + u < e)
+#pragma unroll
+                for (int q = 0; q < K; ++q) acc[q] = fma(v[u], xv[u][q], acc[q]);
     }
-    return acc;
 }
 
+// Same for lane `lane` of a SELL slice (b, slen), the row having rlen entries.
 template <class CI, int K>
-__device__ __forceinline__ double sell_item(const SellView &sv, const double *__restrict__ val,
-                                            const double *__restrict__ X, int32_t b, int slen, int rlen,
-                                            int so, int row, int q)
+__device__ __forceinline__ void sell_row_multi(const SellView &sv, const double *__restrict__ val,
+                                               const double *__restrict__ X, int32_t b, int slen,
+                                               int rlen, int lane, int row, double acc[K])
 {
-    constexpr int U = 8;
-    const CI *__restrict__ col = reinterpret_cast<const CI *>(sv.col) + b + so;
-    const double *__restrict__ v = val + b + so;
-    double acc = 0.0;
+    constexpr int U = K >= 8 ? 1 : 8 / K;
+    const CI *__restrict__ col = reinterpret_cast<const CI *>(sv.col) + b + lane;
+    const double *__restrict__ v = val + b + lane;
+#pragma unroll
+    for (int q = 0; q < K; ++q) acc[q] = 0.0;
     for (int j0 = 0; j0 < slen; j0 += U) {
         CI c[U];
         double a[U];
@@ -92,47 +95,68 @@ __device__ __forceinline__ double sell_item(const SellView &sv, const double *__
             c[u] = ld_stream(col + (size_t)j * kSell);
             a[u] = ld_stream(v + (size_t)j * kSell);
         }
-        double xv[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) xv[u] = X[(size_t)(row + (int)c[u]) * K + q];
+        double xv[U][K];
 #pragma unroll
         for (int u = 0; u < U; ++u)
-            if (j0 + u < rlen) acc = fma(a[u], xv[u], acc);
+#pragma unroll
+            for (int q = 0; q < K; ++q) xv[u][q] = X[(size_t)(row + (int)c[u]) * K + q];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (j0 + u < rlen)
+#pragma unroll
+                for (int q = 0; q < K; ++q) acc[q] = fma(a[u], xv[u][q], acc[q]);
     }
-    return acc;
 }
 
-// Items of block l (of nblk): SELL row groups in round-robin order (slice s
-// has K groups of G rows), or the block's contiguous tile range of CSR rows.
-// fn(e, row, y) for item e = row K + q with y = (A X)[row, q].
+// Row walk of block l (of nblk) of a multi kernel: SELL slices in
+// round-robin order, or CSR rows of the block's contiguous tile range with
+// one row per lane.  fn(row, acc) gets the K products of the row.
 template <class CI, int K, class Fn>
-__device__ __forceinline__ void multi_items(const MultiDesc &d, int l, int j, const double *__restrict__ X,
-                                            Fn &&fn)
+__device__ __forceinline__ void multi_rows(const MultiDesc &d, int l, int j, const double *__restrict__ X,
+                                           Fn &&fn)
 {
-    constexpr int G = kWave / K;
-    const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
-    const int q = lane % K, ro = lane / K;
+    double acc[K];
     if (d.sell) {
+        const int lane = threadIdx.x & (kWave - 1);
         const int ns = (d.n + kSell - 1) / kSell;
-        const int ngroups = ns * K;
-        for (int g = l * (kBlock / kWave) + wv; g < ngroups; g += d.nblk * (kBlock / kWave)) {
-            const int s = g / K, so = (g % K) * G + ro;
-            const int row = s * kSell + so;
-            if (row >= d.n) continue;
+        for (int s = l * (kBlock / kWave) + (int)threadIdx.x / kWave; s < ns; s += d.nblk * (kBlock / kWave)) {
             const int32_t b = d.sv.ptr[s], e = d.sv.ptr[s + 1];
-            const double y = sell_item<CI, K>(d.sv, d.sell_val, X, b, (e - b) / kSell, d.sv.len[row], so, row, q);
-            fn((int64_t)row * K + q, row, y);
+            const int row = s * kSell + lane;
+            if (row < d.n) {
+                sell_row_multi<CI, K>(d.sv, d.sell_val, X, b, (e - b) / kSell, d.sv.len[row], lane, row, acc);
+                fn(row, acc);
+            }
         }
     } else {
         int t0, t1;
         block_tiles(j, d.nblk, d.ntiles, t0, t1);
         const int rb = t0 * d.R, re = min(t1 * d.R, d.n);
-        for (int r0 = rb + wv * G; r0 < re; r0 += (kBlock / kWave) * G) {
-            const int row = r0 + ro;
-            if (row >= re) continue;
-            const double y = csr_item<K>(d.rowptr[row], d.rowptr[row + 1], q, d.col, d.val, X);
-            fn((int64_t)row * K + q, row, y);
+        for (int row = rb + (int)threadIdx.x; row < re; row += kBlock) {
+            csr_row_multi<K>(d.rowptr[row], d.rowptr[row + 1], d.col, d.val, X, acc);
+            fn(row, acc);
         }
+    }
+}
+
+// Block sums of K per-lane values, one partial per column: part[q * nblk + j].
+template <int K>
+__device__ __forceinline__ void block_partials(double v[K], double *sh /* [4][K] */, double *part,
+                                               int nblk, int j)
+{
+#pragma unroll
+    for (int q = 0; q < K; ++q) v[q] = wave_sum(v[q]);
+    const int w = threadIdx.x / kWave;
+    __syncthreads();
+    if ((threadIdx.x & (kWave - 1)) == 0)
+#pragma unroll
+        for (int q = 0; q < K; ++q) sh[w * K + q] = v[q];
+    __syncthreads();
+    if ((int)threadIdx.x < K) {
+        const int q = threadIdx.x;
+        double s = sh[q];
+#pragma unroll
+        for (int ww = 1; ww < kBlock / kWave; ++ww) s += sh[ww * K + q];
+        part[(size_t)q * nblk + j] = s;
     }
 }
 
@@ -190,7 +214,10 @@ __global__ __launch_bounds__(kBlock) void k_spmm(MultiDesc d, const double *__re
     int j;
     const int l = multi_block(d, j);
     if (l < 0) return;
-    multi_items<CI, K>(d, l, j, X, [&](int64_t e, int, double y) { Y[e] = y; });
+    multi_rows<CI, K>(d, l, j, X, [&](int row, const double *acc) {
+#pragma unroll
+        for (int q = 0; q < K; ++q) Y[(size_t)row * K + q] = acc[q];
+    });
 }
 
 // ------------------------------------------------------------------ residual
@@ -203,68 +230,63 @@ __global__ __launch_bounds__(kBlock) void k_m_resid(MultiDesc d, int32_t mask)
     int j;
     const int l = multi_block(d, j);
     if (l < 0) return;
-    const int q = threadIdx.x % K;
-    const bool on = (mask >> q) & 1;
-    double rr = 0.0, bb = 0.0;
-    multi_items<CI, K>(d, l, j, d.X, [&](int64_t e, int, double y) {
-        if (!on) return;
-        const double bi = d.B[e];
-        const double ri = bi - y;
-        d.Rv[e] = ri;
-        rr = fma(ri, ri, rr);
-        bb = fma(bi, bi, bb);
+    double rr[K], bb[K];
+#pragma unroll
+    for (int q = 0; q < K; ++q) rr[q] = bb[q] = 0.0;
+    multi_rows<CI, K>(d, l, j, d.X, [&](int row, const double *acc) {
+#pragma unroll
+        for (int q = 0; q < K; ++q) {
+            if (!((mask >> q) & 1)) continue;
+            const double bi = d.B[(size_t)row * K + q];
+            const double ri = bi - acc[q];
+            d.Rv[(size_t)row * K + q] = ri;
+            rr[q] = fma(ri, ri, rr[q]);
+            bb[q] = fma(bi, bi, bb[q]);
+        }
     });
-    block_partials_flat<K>(rr, sh, d.partials + (size_t)kPartRr * K * d.nblk, d.nblk, j);
-    block_partials_flat<K>(bb, sh, d.partials + (size_t)kPartBb * K * d.nblk, d.nblk, j);
+    block_partials<K>(rr, sh, d.partials + (size_t)kPartRr * K * d.nblk, d.nblk, j);
+    block_partials<K>(bb, sh, d.partials + (size_t)kPartBb * K * d.nblk, d.nblk, j);
 }
 
-// Column q's sum of partials part[q * nblk + 0 .. nblk), by one wavefront,
-// in a fixed order (lane-strided, then the butterfly).
-__device__ __forceinline__ double wave_reduce_col(const double *part, int nblk)
+// The finalize kernels run one block per column (q = blockIdx.x): the block
+// sums the column's nblk partials in a fixed order (reduce_partials), thread
+// 0 runs the column's scalar logic, and a column that stops clears its bit
+// of the running mask with an integer atomic (the only cross-block write).
+__device__ __forceinline__ const double *col_part(const MultiDesc &d, int part, int q)
 {
-    const int lane = threadIdx.x & (kWave - 1);
-    double s = 0.0;
-    for (int i = lane; i < nblk; i += kWave) s += part[i];
-    return wave_sum(s);
+    return d.partials + ((size_t)part * d.K + q) * d.nblk;
 }
 
-__device__ __forceinline__ void publish_mask(const MultiDesc &d)
+__device__ __forceinline__ void stop_column(const MultiDesc &d, int q)
 {
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        int32_t m = 0;
-        for (int q = 0; q < d.K; ++q)
-            if (d.st[q].status == SPK_RUNNING) m |= 1 << q;
-        d.ctl->mask = m;
-    }
+    atomicAnd(&d.ctl->mask, ~(1 << q));
 }
 
 // purpose kMultiSetup: norms, thresholds, stop at start; kMultiTrue: store the
 // true residual norm of the columns in mask.
 static __global__ __launch_bounds__(kBlock) void k_m_fin_resid(MultiDesc d, int purpose, int32_t mask)
 {
-    const int w = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
-    for (int q = w; q < d.K; q += kBlock / kWave) {
-        if (!((mask >> q) & 1)) continue;
-        const double RR = wave_reduce_col(d.partials + ((size_t)kPartRr * d.K + q) * d.nblk, d.nblk);
-        const double BB = wave_reduce_col(d.partials + ((size_t)kPartBb * d.K + q) * d.nblk, d.nblk);
-        if (lane != 0) continue;
-        SysState *st = d.st + q;
-        const double rn = sqrt(RR);
-        if (purpose == kMultiTrue) {
-            st->rnorm_true = rn;
-            continue;
-        }
-        const double bn = sqrt(BB);
-        st->bnorm = bn;
-        st->thresh = fmax(st->rtol * bn, st->atol);
-        st->rnorm = rn;
-        st->rnorm0 = rn;
-        if (bn == 0.0) st->status = SPK_CONVERGED_ATOL;
-        else if (!isfinite(rn) || !isfinite(bn)) st->status = SPK_DIVERGED_NANORINF;
-        else if (rn <= st->thresh) st->status = rn <= st->rtol * bn ? SPK_CONVERGED_RTOL : SPK_CONVERGED_ATOL;
+    __shared__ double red[kBlock / kWave];
+    const int q = blockIdx.x;
+    if (q >= d.K || !((mask >> q) & 1)) return;
+    double RR, BB;
+    reduce_partials2(col_part(d, kPartRr, q), col_part(d, kPartBb, q), d.nblk, red, RR, BB);
+    if (threadIdx.x != 0) return;
+    SysState *st = d.st + q;
+    const double rn = sqrt(RR);
+    if (purpose == kMultiTrue) {
+        st->rnorm_true = rn;
+        return;
     }
-    publish_mask(d);
+    const double bn = sqrt(BB);
+    st->bnorm = bn;
+    st->thresh = fmax(st->rtol * bn, st->atol);
+    st->rnorm = rn;
+    st->rnorm0 = rn;
+    if (bn == 0.0) st->status = SPK_CONVERGED_ATOL;
+    else if (!isfinite(rn) || !isfinite(bn)) st->status = SPK_DIVERGED_NANORINF;
+    else if (rn <= st->thresh) st->status = rn <= st->rtol * bn ? SPK_CONVERGED_RTOL : SPK_CONVERGED_ATOL;
+    if (st->status != SPK_RUNNING) stop_column(d, q);
 }
 
 // ------------------------------------------------------------------ setup
@@ -291,21 +313,20 @@ __global__ __launch_bounds__(kBlock) void k_m_setup(MultiDesc d, int32_t mask)
 
 static __global__ __launch_bounds__(kBlock) void k_m_fin_setup(MultiDesc d, int32_t mask)
 {
-    const int w = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
-    for (int q = w; q < d.K; q += kBlock / kWave) {
-        if (!((mask >> q) & 1)) continue;
-        SysState *st = d.st + q;
-        if (st->status != SPK_RUNNING) continue;
-        const double RZ = wave_reduce_col(d.partials + ((size_t)kPartRz * d.K + q) * d.nblk, d.nblk);
-        if (lane != 0) continue;
-        st->cmode = 0;
-        if (!isfinite(RZ)) st->status = SPK_DIVERGED_NANORINF;
-        else if (RZ < 0.0) st->status = SPK_DIVERGED_INDEFINITE_PC;
-        else if (RZ == 0.0) st->status = SPK_DIVERGED_BREAKDOWN;
-        else if (st->iter >= st->maxit) { st->status = SPK_DIVERGED_ITS; st->rho = RZ; }
-        else st->rho = RZ;
-    }
-    publish_mask(d);
+    __shared__ double red[kBlock / kWave];
+    const int q = blockIdx.x;
+    if (q >= d.K || !((mask >> q) & 1)) return;
+    SysState *st = d.st + q;
+    if (st->status != SPK_RUNNING) return;
+    const double RZ = reduce_partials(col_part(d, kPartRz, q), d.nblk, red);
+    if (threadIdx.x != 0) return;
+    st->cmode = 0;
+    if (!isfinite(RZ)) st->status = SPK_DIVERGED_NANORINF;
+    else if (RZ < 0.0) st->status = SPK_DIVERGED_INDEFINITE_PC;
+    else if (RZ == 0.0) st->status = SPK_DIVERGED_BREAKDOWN;
+    else if (st->iter >= st->maxit) { st->status = SPK_DIVERGED_ITS; st->rho = RZ; }
+    else st->rho = RZ;
+    if (st->status != SPK_RUNNING) stop_column(d, q);
 }
 
 // Restart the columns in mask from their true residual (already in R).
@@ -316,6 +337,7 @@ static __global__ void k_m_restart(MultiDesc d, int32_t mask)
         d.st[q].status = SPK_RUNNING;
         d.st[q].cmode = 0;
     }
+    if (q == 0) d.ctl->mask |= mask;
 }
 
 // ------------------------------------------------------------------ iteration
@@ -329,31 +351,36 @@ __global__ __launch_bounds__(kBlock) void k_m_spmm_pq(MultiDesc d)
     const int l = multi_block(d, j);
     if (l < 0) return;
     if (d.ctl->mask == 0) return;
-    double pq = 0.0;
-    multi_items<CI, K>(d, l, j, d.P, [&](int64_t e, int, double y) {
-        d.Q[e] = y;
-        pq = fma(y, d.P[e], pq);
+    double pq[K];
+#pragma unroll
+    for (int q = 0; q < K; ++q) pq[q] = 0.0;
+    multi_rows<CI, K>(d, l, j, d.P, [&](int row, const double *acc) {
+#pragma unroll
+        for (int q = 0; q < K; ++q) {
+            const size_t o = (size_t)row * K + q;
+            d.Q[o] = acc[q];
+            pq[q] = fma(acc[q], d.P[o], pq[q]);
+        }
     });
-    block_partials_flat<K>(pq, sh, d.partials + (size_t)kPartPq * K * d.nblk, d.nblk, j);
+    block_partials<K>(pq, sh, d.partials + (size_t)kPartPq * K * d.nblk, d.nblk, j);
 }
 
 // F_A: eta = p.q and alpha per running column; eta <= 0 stops the column.
 static __global__ __launch_bounds__(kBlock) void k_m_fin_pq(MultiDesc d)
 {
-    if (d.ctl->mask == 0) return;
-    const int w = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
-    for (int q = w; q < d.K; q += kBlock / kWave) {
-        SysState *st = d.st + q;
-        if (st->status != SPK_RUNNING) continue;
-        const double eta = wave_reduce_col(d.partials + ((size_t)kPartPq * d.K + q) * d.nblk, d.nblk);
-        if (lane != 0) continue;
-        st->eta = eta;
-        st->cmode = 0;
-        if (!isfinite(eta)) st->status = SPK_DIVERGED_NANORINF;
-        else if (eta <= 0.0) st->status = SPK_DIVERGED_INDEFINITE_MAT;
-        else st->alpha = st->rho / eta;
-    }
-    publish_mask(d);
+    __shared__ double red[kBlock / kWave];
+    const int q = blockIdx.x;
+    if (q >= d.K) return;
+    SysState *st = d.st + q;
+    if (st->status != SPK_RUNNING) return;
+    const double eta = reduce_partials(col_part(d, kPartPq, q), d.nblk, red);
+    if (threadIdx.x != 0) return;
+    st->eta = eta;
+    st->cmode = 0;
+    if (!isfinite(eta)) st->status = SPK_DIVERGED_NANORINF;
+    else if (eta <= 0.0) st->status = SPK_DIVERGED_INDEFINITE_MAT;
+    else st->alpha = st->rho / eta;
+    if (st->status != SPK_RUNNING) stop_column(d, q);
 }
 
 // B: R -= alpha Q, Z = D^-1 R for the running columns, per-block r.z, r.r.
@@ -383,40 +410,35 @@ __global__ __launch_bounds__(kBlock) void k_m_update(MultiDesc d)
 }
 
 // F_B: per running column: iteration count, convergence, breakdowns, beta;
-// cmode 2 (x and p updates), 1 (last x update), as in the single solve.
+// cmode 2 (x and p updates) or 1 (the last x update), as in the single
+// solve; a column that is not running gets cmode 0, so the p/x kernel of a
+// later replay leaves it alone.
 static __global__ __launch_bounds__(kBlock) void k_m_fin_update(MultiDesc d)
 {
-    const int mask0 = d.ctl->mask;
-    if (mask0 == 0) {  // every column has stopped: the p/x kernel does nothing
-        __syncthreads();
-        if (threadIdx.x == 0) d.ctl->pad_ = 0;
+    __shared__ double red[kBlock / kWave];
+    const int q = blockIdx.x;
+    if (q >= d.K) return;
+    SysState *st = d.st + q;
+    if (st->status != SPK_RUNNING) {
+        if (threadIdx.x == 0) st->cmode = 0;
         return;
     }
-    const int w = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
-    for (int q = w; q < d.K; q += kBlock / kWave) {
-        if (!((mask0 >> q) & 1)) continue;
-        SysState *st = d.st + q;
-        const double RZ = wave_reduce_col(d.partials + ((size_t)kPartRz * d.K + q) * d.nblk, d.nblk);
-        const double RR = wave_reduce_col(d.partials + ((size_t)kPartRr * d.K + q) * d.nblk, d.nblk);
-        if (lane != 0) continue;
-        const int k = ++st->iter;
-        const double rn = sqrt(RR);
-        st->rnorm = rn;
-        st->cmode = 1;
-        if (!isfinite(rn)) st->status = SPK_DIVERGED_NANORINF;
-        else if (rn <= st->thresh)
-            st->status = rn <= st->rtol * st->bnorm ? SPK_CONVERGED_RTOL : SPK_CONVERGED_ATOL;
-        else if (k >= st->maxit) st->status = SPK_DIVERGED_ITS;
-        else if (!isfinite(RZ)) st->status = SPK_DIVERGED_NANORINF;
-        else if (RZ < 0.0) st->status = SPK_DIVERGED_INDEFINITE_PC;
-        else if (RZ == 0.0) st->status = SPK_DIVERGED_BREAKDOWN;
-        else { st->beta = RZ / st->rho; st->rho = RZ; st->cmode = 2; }
-    }
-    __syncthreads();
-    // the p/x kernel needs the pre-update mask (columns stopping now still
-    // take their last x update): keep it in pad_
-    if (threadIdx.x == 0) d.ctl->pad_ = mask0;
-    publish_mask(d);
+    double RZ, RR;
+    reduce_partials2(col_part(d, kPartRz, q), col_part(d, kPartRr, q), d.nblk, red, RZ, RR);
+    if (threadIdx.x != 0) return;
+    const int k = ++st->iter;
+    const double rn = sqrt(RR);
+    st->rnorm = rn;
+    st->cmode = 1;
+    if (!isfinite(rn)) st->status = SPK_DIVERGED_NANORINF;
+    else if (rn <= st->thresh)
+        st->status = rn <= st->rtol * st->bnorm ? SPK_CONVERGED_RTOL : SPK_CONVERGED_ATOL;
+    else if (k >= st->maxit) st->status = SPK_DIVERGED_ITS;
+    else if (!isfinite(RZ)) st->status = SPK_DIVERGED_NANORINF;
+    else if (RZ < 0.0) st->status = SPK_DIVERGED_INDEFINITE_PC;
+    else if (RZ == 0.0) st->status = SPK_DIVERGED_BREAKDOWN;
+    else { st->beta = RZ / st->rho; st->rho = RZ; st->cmode = 2; }
+    if (st->status != SPK_RUNNING) stop_column(d, q);
 }
 
 // C: per column, cmode 2: x += alpha p, p = z + beta p; cmode 1: x += alpha p.
@@ -425,10 +447,8 @@ __global__ __launch_bounds__(kBlock) void k_m_px(MultiDesc d)
 {
     int j;
     if (multi_block(d, j) < 0) return;
-    const int mask0 = d.ctl->pad_;
-    if (mask0 == 0) return;
     const int q = threadIdx.x % K;
-    const int cm = ((mask0 >> q) & 1) ? d.st[q].cmode : 0;
+    const int cm = d.st[q].cmode;
     if (cm == 0) return;  // no barrier follows
     const double al = d.st[q].alpha, be = d.st[q].beta;
     flat_walk<K>(d, j, [&](int64_t e, int) {
@@ -456,6 +476,7 @@ static __global__ void k_m_init(MultiDesc d, double rtol, double atol, int maxit
         d.ctl->mask = (1 << d.K) - 1;
         d.ctl->pad_ = 0;
     }
+    if (q < d.K) d.st[q].cmode = 0;
 }
 
 // x = 0 for the columns in mask (right-hand sides that are zero).
