@@ -230,16 +230,19 @@ __global__ __launch_bounds__(kBlock) void k_m_resid(MultiDesc d, int32_t mask)
     int j;
     const int l = multi_block(d, j);
     if (l < 0) return;
+    const double *__restrict__ X = d.X;
+    const double *__restrict__ Bv = d.B;
+    double *__restrict__ Rv = d.Rv;
     double rr[K], bb[K];
 #pragma unroll
     for (int q = 0; q < K; ++q) rr[q] = bb[q] = 0.0;
-    multi_rows<CI, K>(d, l, j, d.X, [&](int row, const double *acc) {
+    multi_rows<CI, K>(d, l, j, X, [&](int row, const double *acc) {
 #pragma unroll
         for (int q = 0; q < K; ++q) {
             if (!((mask >> q) & 1)) continue;
-            const double bi = d.B[(size_t)row * K + q];
+            const double bi = Bv[(size_t)row * K + q];
             const double ri = bi - acc[q];
-            d.Rv[(size_t)row * K + q] = ri;
+            Rv[(size_t)row * K + q] = ri;
             rr[q] = fma(ri, ri, rr[q]);
             bb[q] = fma(bi, bi, bb[q]);
         }
@@ -299,13 +302,17 @@ __global__ __launch_bounds__(kBlock) void k_m_setup(MultiDesc d, int32_t mask)
     if (multi_block(d, j) < 0) return;
     const int q = threadIdx.x % K;
     const bool run = ((mask >> q) & 1) && d.st[q].status == SPK_RUNNING;
+    const double *__restrict__ Rv = d.Rv;
+    const double *__restrict__ dinv = d.dinv;
+    double *__restrict__ Z = d.Z;
+    double *__restrict__ P = d.P;
     double rz = 0.0;
     if (run)
         flat_walk<K>(d, j, [&](int64_t e, int i) {
-            const double ri = d.Rv[e];
-            const double zi = d.dinv[i] * ri;
-            d.Z[e] = zi;
-            d.P[e] = zi;
+            const double ri = Rv[e];
+            const double zi = dinv[i] * ri;
+            Z[e] = zi;
+            P[e] = zi;
             rz = fma(ri, zi, rz);
         });
     block_partials_flat<K>(rz, sh, d.partials + (size_t)kPartRz * K * d.nblk, d.nblk, j);
@@ -351,15 +358,19 @@ __global__ __launch_bounds__(kBlock) void k_m_spmm_pq(MultiDesc d)
     const int l = multi_block(d, j);
     if (l < 0) return;
     if (d.ctl->mask == 0) return;
+    // Q never aliases P: without the qualifiers the compiler orders every
+    // gather of P behind the stores of Q
+    const double *__restrict__ P = d.P;
+    double *__restrict__ Q = d.Q;
     double pq[K];
 #pragma unroll
     for (int q = 0; q < K; ++q) pq[q] = 0.0;
-    multi_rows<CI, K>(d, l, j, d.P, [&](int row, const double *acc) {
+    multi_rows<CI, K>(d, l, j, P, [&](int row, const double *acc) {
 #pragma unroll
         for (int q = 0; q < K; ++q) {
             const size_t o = (size_t)row * K + q;
-            d.Q[o] = acc[q];
-            pq[q] = fma(acc[q], d.P[o], pq[q]);
+            Q[o] = acc[q];
+            pq[q] = fma(acc[q], P[o], pq[q]);
         }
     });
     block_partials<K>(pq, sh, d.partials + (size_t)kPartPq * K * d.nblk, d.nblk, j);
@@ -395,13 +406,17 @@ __global__ __launch_bounds__(kBlock) void k_m_update(MultiDesc d)
     const int q = threadIdx.x % K;
     const bool run = (mask >> q) & 1;
     const double nal = run ? -d.st[q].alpha : 0.0;
+    const double *__restrict__ Q = d.Q;
+    const double *__restrict__ dinv = d.dinv;
+    double *__restrict__ Rv = d.Rv;
+    double *__restrict__ Z = d.Z;
     double rz = 0.0, rr = 0.0;
     if (run)
         flat_walk<K>(d, j, [&](int64_t e, int i) {
-            const double ri = fma(nal, d.Q[e], d.Rv[e]);
-            const double zi = d.dinv[i] * ri;
-            d.Rv[e] = ri;
-            d.Z[e] = zi;
+            const double ri = fma(nal, Q[e], Rv[e]);
+            const double zi = dinv[i] * ri;
+            Rv[e] = ri;
+            Z[e] = zi;
             rz = fma(ri, zi, rz);
             rr = fma(ri, ri, rr);
         });
@@ -451,10 +466,13 @@ __global__ __launch_bounds__(kBlock) void k_m_px(MultiDesc d)
     const int cm = d.st[q].cmode;
     if (cm == 0) return;  // no barrier follows
     const double al = d.st[q].alpha, be = d.st[q].beta;
+    double *__restrict__ X = d.X;
+    double *__restrict__ P = d.P;
+    const double *__restrict__ Z = d.Z;
     flat_walk<K>(d, j, [&](int64_t e, int) {
-        const double pi = d.P[e];
-        d.X[e] = fma(al, pi, d.X[e]);
-        if (cm == 2) d.P[e] = fma(be, pi, d.Z[e]);
+        const double pi = P[e];
+        X[e] = fma(al, pi, X[e]);
+        if (cm == 2) P[e] = fma(be, pi, Z[e]);
     });
 }
 
