@@ -50,7 +50,7 @@ __device__ __forceinline__ void csr_row_multi(int a, int e, const int32_t *__res
                                               const double *__restrict__ val,
                                               const double *__restrict__ X, double acc[K])
 {
-    constexpr int U = K >= 8 ? 1 : 8 / K;
+    constexpr int U = K >= 16 ? 1 : (K >= 4 ? 2 : 8 / K);
 #pragma unroll
     for (int q = 0; q < K; ++q) acc[q] = 0.0;
     for (int k0 = a; k0 < e; k0 += U) {
@@ -81,7 +81,7 @@ __device__ __forceinline__ void sell_row_multi(const SellView &sv, const double 
                                                const double *__restrict__ X, int32_t b, int slen,
                                                int rlen, int lane, int row, double acc[K])
 {
-    constexpr int U = K >= 8 ? 1 : 8 / K;
+    constexpr int U = K >= 16 ? 1 : (K >= 4 ? 2 : 8 / K);
     const CI *__restrict__ col = reinterpret_cast<const CI *>(sv.col) + b + lane;
     const double *__restrict__ v = val + b + lane;
 #pragma unroll
@@ -237,10 +237,13 @@ __global__ __launch_bounds__(kBlock) void k_m_resid(MultiDesc d, int32_t mask)
 #pragma unroll
     for (int q = 0; q < K; ++q) rr[q] = bb[q] = 0.0;
     multi_rows<CI, K>(d, l, j, X, [&](int row, const double *acc) {
+        double br[K];  // the row of B, loaded before any store of R
+#pragma unroll
+        for (int q = 0; q < K; ++q) br[q] = Bv[(size_t)row * K + q];
 #pragma unroll
         for (int q = 0; q < K; ++q) {
             if (!((mask >> q) & 1)) continue;
-            const double bi = Bv[(size_t)row * K + q];
+            const double bi = br[q];
             const double ri = bi - acc[q];
             Rv[(size_t)row * K + q] = ri;
             rr[q] = fma(ri, ri, rr[q]);
@@ -366,11 +369,13 @@ __global__ __launch_bounds__(kBlock) void k_m_spmm_pq(MultiDesc d)
 #pragma unroll
     for (int q = 0; q < K; ++q) pq[q] = 0.0;
     multi_rows<CI, K>(d, l, j, P, [&](int row, const double *acc) {
+        double pr[K];  // the row of P, loaded before any store of Q
+#pragma unroll
+        for (int q = 0; q < K; ++q) pr[q] = P[(size_t)row * K + q];
 #pragma unroll
         for (int q = 0; q < K; ++q) {
-            const size_t o = (size_t)row * K + q;
-            Q[o] = acc[q];
-            pq[q] = fma(acc[q], P[o], pq[q]);
+            Q[(size_t)row * K + q] = acc[q];
+            pq[q] = fma(acc[q], pr[q], pq[q]);
         }
     });
     block_partials<K>(pq, sh, d.partials + (size_t)kPartPq * K * d.nblk, d.nblk, j);
