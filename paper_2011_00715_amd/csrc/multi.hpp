@@ -50,7 +50,7 @@ __device__ __forceinline__ void csr_row_multi(int a, int e, const int32_t *__res
                                               const double *__restrict__ val,
                                               const double *__restrict__ X, double acc[K])
 {
-    constexpr int U = K >= 16 ? 1 : (K >= 4 ? 2 : 8 / K);
+    constexpr int U = K >= 8 ? 1 : 8 / K;
 #pragma unroll
     for (int q = 0; q < K; ++q) acc[q] = 0.0;
     for (int k0 = a; k0 < e; k0 += U) {
@@ -81,7 +81,7 @@ __device__ __forceinline__ void sell_row_multi(const SellView &sv, const double 
                                                const double *__restrict__ X, int32_t b, int slen,
                                                int rlen, int lane, int row, double acc[K])
 {
-    constexpr int U = K >= 16 ? 1 : (K >= 4 ? 2 : 8 / K);
+    constexpr int U = K >= 8 ? 1 : 8 / K;
     const CI *__restrict__ col = reinterpret_cast<const CI *>(sv.col) + b + lane;
     const double *__restrict__ v = val + b + lane;
 #pragma unroll
