@@ -87,6 +87,9 @@ def load(path: str | None = None):
     lib.orc_pcg.argtypes = [i32, P, P, P, P, P, d, d, i32, i32, P, i32,
                             ctypes.POINTER(_PcgResult)]
     lib.orc_pcg.restype = ctypes.c_int
+    lib.orc_pcg_sr.argtypes = [i32, P, P, P, P, P, d, d, i32, i32, P, i32,
+                               ctypes.POINTER(_PcgResult)]
+    lib.orc_pcg_sr.restype = ctypes.c_int
     lib.orc_dense_cholesky_solve.argtypes = [i32, P, P]
     lib.orc_dense_cholesky_solve.restype = ctypes.c_int
     lib.orc_chebyshev.argtypes = [i32, P, P, P, P, P, P, i32, d, d, i32]
@@ -208,8 +211,10 @@ def jacobi_apply(dinv, r, lib=None) -> np.ndarray:
     return z
 
 
-def pcg(A, b, x0=None, rtol=1e-8, atol=0.0, maxit=10000, hist_len=0, lib=None):
-    """FP64 Jacobi-PCG.  Returns (x, result dict, history array or None)."""
+def pcg(A, b, x0=None, rtol=1e-8, atol=0.0, maxit=10000, hist_len=0, lib=None,
+        single_reduction=False):
+    """FP64 Jacobi-PCG (textbook, or the single-reduction Chronopoulos-Gear
+    form).  Returns (x, result dict, history array or None)."""
     lib = lib or load()
     rp, ci = _csr(A)
     v = _c(A.val, np.float64)
@@ -217,7 +222,8 @@ def pcg(A, b, x0=None, rtol=1e-8, atol=0.0, maxit=10000, hist_len=0, lib=None):
     x = np.zeros(A.n) if x0 is None else np.array(x0, dtype=np.float64, copy=True)
     hist = np.full(max(hist_len, 1), np.nan)
     res = _PcgResult()
-    st = lib.orc_pcg(A.n, _ptr(rp), _ptr(ci), _ptr(v), _ptr(b), _ptr(x), float(rtol),
+    fn = lib.orc_pcg_sr if single_reduction else lib.orc_pcg
+    st = fn(A.n, _ptr(rp), _ptr(ci), _ptr(v), _ptr(b), _ptr(x), float(rtol),
                      float(atol), int(maxit), int(x0 is not None),
                      _ptr(hist) if hist_len > 0 else None, int(hist_len), ctypes.byref(res))
     if st:

@@ -274,6 +274,142 @@ done:
  * overwritten by the solution.  Returns 0, or -1 if A is not positive
  * definite. */
 /*
+ * Single-reduction preconditioned CG (Chronopoulos & Gear, J. Comput. Appl.
+ * Math. 25, 1989): the same Krylov iterates as orc_pcg in exact arithmetic,
+ * but the two inner products of an iteration are formed together, from
+ * u = D^-1 r and w = A u, so a parallel implementation needs one reduction
+ * phase per iteration (Sec. 4, Challenge A1: synchronisation points).  The
+ * recurrences (s = A p carried as a vector):
+ *
+ *   u = D^-1 r, w = A u, gamma = (r, u), delta = (w, u)
+ *   first step:  beta = 0, alpha = gamma / delta
+ *   later steps: beta = gamma / gamma_prev,
+ *                alpha = gamma / (delta - beta gamma / alpha_prev)
+ *   p = u + beta p, s = w + beta s, x += alpha p, r -= alpha s
+ *
+ * Stopping rule, true-residual restarts (a restart starts a new "first
+ * step"), breakdown reasons and results as in orc_pcg; a non-positive
+ * alpha denominator is INDEFINITE_MAT.
+ */
+int orc_pcg_sr(int32_t n, const int32_t *rowptr, const int32_t *col,
+               const double *val, const double *b, double *x, double rtol,
+               double atol, int32_t maxit, int32_t x0_nonzero, double *hist,
+               int32_t hist_len, orc_pcg_result *res)
+{
+    memset(res, 0, sizeof(*res));
+    const size_t bytes = sizeof(double) * (size_t)(n > 0 ? n : 1);
+    double *dinv = (double *)malloc(bytes), *r = (double *)malloc(bytes), *u = (double *)malloc(bytes);
+    double *w = (double *)malloc(bytes), *p = (double *)malloc(bytes), *s = (double *)malloc(bytes);
+    double *t = (double *)malloc(bytes);
+    int status = 0;
+    if (!dinv || !r || !u || !w || !p || !s || !t) { status = ORC_ENOMEM; goto done; }
+    status = orc_diag_inv(n, rowptr, col, val, dinv);
+    if (status) goto done;
+
+    double bnorm = orc_nrm2(n, b);
+    res->bnorm = bnorm;
+    double thresh = rtol * bnorm > atol ? rtol * bnorm : atol;
+    if (bnorm == 0.0) {
+        for (int32_t i = 0; i < n; ++i) x[i] = 0.0;
+        res->reason = ORC_CONVERGED_ATOL;
+        if (hist && hist_len > 0) hist[0] = 0.0;
+        goto done;
+    }
+    if (x0_nonzero) {
+        orc_spmv(n, rowptr, col, val, x, t);
+        for (int32_t i = 0; i < n; ++i) r[i] = b[i] - t[i];
+    } else {
+        for (int32_t i = 0; i < n; ++i) { x[i] = 0.0; r[i] = b[i]; }
+    }
+    double rnorm = orc_nrm2(n, r);
+    res->rnorm0 = rnorm;
+    if (hist && hist_len > 0) hist[0] = rnorm;
+    int32_t k = 0;
+    int restarts = 0;
+
+    for (;;) { /* (re)start from the current x with a true residual in r */
+        if (!finite_d(rnorm)) { res->reason = ORC_DIVERGED_NANORINF; break; }
+        if (rnorm <= thresh) {
+            res->reason = rnorm <= rtol * bnorm ? ORC_CONVERGED_RTOL : ORC_CONVERGED_ATOL;
+            break;
+        }
+        orc_jacobi_apply(n, dinv, r, u);
+        orc_spmv(n, rowptr, col, val, u, w);
+        double gamma = orc_dot(n, r, u);
+        double delta = orc_dot(n, w, u);
+        if (!finite_d(gamma)) { res->reason = ORC_DIVERGED_NANORINF; break; }
+        if (gamma < 0.0) { res->reason = ORC_DIVERGED_INDEFINITE_PC; break; }
+        if (gamma == 0.0) { res->reason = ORC_DIVERGED_BREAKDOWN; break; }
+        int first = 1;
+        double gamma_prev = 0.0, alpha_prev = 0.0;
+        int restart = 0;
+        while (!res->reason && !restart) {
+            if (k >= maxit) { res->reason = ORC_DIVERGED_ITS; break; }
+            double alpha, beta;
+            if (first) {
+                beta = 0.0;
+                if (!finite_d(delta)) { res->reason = ORC_DIVERGED_NANORINF; break; }
+                if (delta <= 0.0) { res->reason = ORC_DIVERGED_INDEFINITE_MAT; break; }
+                alpha = gamma / delta;
+            } else {
+                beta = gamma / gamma_prev;
+                const double den = delta - beta * gamma / alpha_prev;
+                if (!finite_d(den)) { res->reason = ORC_DIVERGED_NANORINF; break; }
+                if (den <= 0.0) { res->reason = ORC_DIVERGED_INDEFINITE_MAT; break; }
+                alpha = gamma / den;
+            }
+            for (int32_t i = 0; i < n; ++i) {
+                p[i] = first ? u[i] : u[i] + beta * p[i];
+                s[i] = first ? w[i] : w[i] + beta * s[i];
+                x[i] = x[i] + alpha * p[i];
+                r[i] = r[i] - alpha * s[i];
+            }
+            first = 0;
+            ++k;
+            rnorm = orc_nrm2(n, r);
+            if (hist && k < hist_len) hist[k] = rnorm;
+            if (!finite_d(rnorm)) { res->reason = ORC_DIVERGED_NANORINF; break; }
+            if (rnorm <= thresh) {
+                orc_spmv(n, rowptr, col, val, x, t);
+                for (int32_t i = 0; i < n; ++i) r[i] = b[i] - t[i];
+                double tn = orc_nrm2(n, r);
+                if (tn <= thresh) {
+                    rnorm = tn;
+                    res->reason = tn <= rtol * bnorm ? ORC_CONVERGED_RTOL : ORC_CONVERGED_ATOL;
+                    break;
+                }
+                if (restarts == 3) { rnorm = tn; res->reason = ORC_DIVERGED_BREAKDOWN; break; }
+                ++restarts;
+                rnorm = tn;
+                restart = 1;
+                break;
+            }
+            if (k >= maxit) { res->reason = ORC_DIVERGED_ITS; break; }
+            orc_jacobi_apply(n, dinv, r, u);
+            orc_spmv(n, rowptr, col, val, u, w);
+            gamma_prev = gamma;
+            alpha_prev = alpha;
+            gamma = orc_dot(n, r, u);
+            delta = orc_dot(n, w, u);
+            if (!finite_d(gamma)) { res->reason = ORC_DIVERGED_NANORINF; break; }
+            if (gamma < 0.0) { res->reason = ORC_DIVERGED_INDEFINITE_PC; break; }
+            if (gamma == 0.0) { res->reason = ORC_DIVERGED_BREAKDOWN; break; }
+        }
+        if (res->reason) break;
+    }
+    res->iterations = k;
+    res->restarts = restarts;
+    res->rnorm = rnorm;
+    orc_spmv(n, rowptr, col, val, x, t);
+    for (int32_t i = 0; i < n; ++i) r[i] = b[i] - t[i];
+    res->true_rel_residual = orc_nrm2(n, r) / bnorm;
+
+done:
+    free(dinv); free(r); free(u); free(w); free(p); free(s); free(t);
+    return status;
+}
+
+/*
  * Chebyshev acceleration of the Jacobi iteration: the smoother that the
  * paper's geometric multigrid runs on every level but the coarsest (Sec. 5.3,
  * "Jacobi-preconditioned Chebyshev smoothers").  The paper gives no formulas;

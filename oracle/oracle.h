@@ -56,6 +56,10 @@ int orc_chebyshev(int32_t n, const int32_t *rowptr, const int32_t *col,
                   int32_t steps, double emin, double emax, int32_t x0_nonzero);
 int orc_gershgorin(int32_t n, const int32_t *rowptr, const int32_t *col,
                    const double *val, double *bound);
+int orc_pcg_sr(int32_t n, const int32_t *rowptr, const int32_t *col,
+               const double *val, const double *b, double *x, double rtol,
+               double atol, int32_t maxit, int32_t x0_nonzero, double *hist,
+               int32_t hist_len, orc_pcg_result *res);
 int orc_dense_cholesky_solve(int32_t n, double *A, double *b);
 
 #endif

@@ -525,3 +525,113 @@ def test_gershgorin_bound(orc):
         assert np.abs(np.linalg.eigvals(M)).max() <= g * (1 + 1e-12)
     A = spkgen.diffusion3d27_lognormal(6, seed=1)
     assert 1.0 < oracle.gershgorin(A) <= 2.0 + 1e-15
+
+
+# ---------------------------------------------------------------- single-reduction PCG
+
+SR = {"single_reduction": True}
+
+
+@pytest.mark.parametrize("dim,N,ks", [(2, 16, (1, 1)), (2, 30, (4, 9)), (3, 8, (2, 3, 5))])
+def test_pcg_sr_eigenvector_rhs_one_iteration(orc, dim, N, ks):
+    A = spkgen.laplace2d5(N) if dim == 2 else spkgen.laplace3d7(N)
+    v, lam = lap_eigpair(N, dim, ks)
+    x, res, _ = oracle.pcg(A, v, rtol=1e-12, hist_len=10, **SR)
+    assert res["reason_str"] == "CONVERGED_RTOL" and res["iterations"] == 1
+    assert np.allclose(x, v / lam, rtol=1e-12, atol=1e-13 * np.abs(v).max() / lam)
+
+
+@pytest.mark.parametrize("m", [2, 3, 5])
+def test_pcg_sr_finite_termination(orc, m):
+    N = 24
+    A = spkgen.laplace2d5(N)
+    ks = [(1, 1), (2, 3), (5, 5), (7, 2), (11, 13)][:m]
+    pairs = [lap_eigpair(N, 2, k) for k in ks]
+    b = sum(v for v, _ in pairs)
+    x, res, hist = oracle.pcg(A, b, rtol=1e-9, hist_len=20, **SR)
+    assert res["reason"] > 0 and res["iterations"] == m
+    assert hist[m] / hist[0] < 1e-9 and hist[m - 1] / hist[0] > 1e-3
+    xs = sum(v / lam for v, lam in pairs)
+    assert np.linalg.norm(x - xs) <= 1e-9 * np.linalg.norm(xs)
+
+
+def test_pcg_sr_exact_rational_iterates(orc):
+    """The single-reduction recurrences produce CG's iterates: compared with
+    Jacobi-PCG carried out in exact rational arithmetic (brute force)."""
+    D = np.array([[4, -1, 0, -2, 0], [-1, 5, -1, 0, 1], [0, -1, 3, -1, 0],
+                  [-2, 0, -1, 6, -1], [0, 1, 0, -1, 2]], dtype=np.float64)
+    n = D.shape[0]
+    b = np.array([1.0, -2.0, 0.5, 3.0, -1.0])
+    A = spkgen.dense_to_csr(D)
+    F = [[Fraction(int(D[i, j])) for j in range(n)] for i in range(n)]
+    x = [Fraction(0)] * n
+    r = [Fraction(v) for v in b]
+    z = [r[i] / F[i][i] for i in range(n)]
+    p = z[:]
+    rho = sum(r[i] * z[i] for i in range(n))
+    ex_x = []
+    for _ in range(n):
+        q = [sum(F[i][j] * p[j] for j in range(n)) for i in range(n)]
+        alpha = rho / sum(p[i] * q[i] for i in range(n))
+        x = [x[i] + alpha * p[i] for i in range(n)]
+        r = [r[i] - alpha * q[i] for i in range(n)]
+        ex_x.append([float(v) for v in x])
+        if all(v == 0 for v in r):
+            break
+        z = [r[i] / F[i][i] for i in range(n)]
+        rho_new = sum(r[i] * z[i] for i in range(n))
+        p = [z[i] + (rho_new / rho) * p[i] for i in range(n)]
+        rho = rho_new
+    for kk in range(1, len(ex_x) + 1):
+        xk, rk, _ = oracle.pcg(A, b, rtol=0.0, maxit=kk, **SR)
+        if rk["reason_str"] != "DIVERGED_ITS":
+            break
+        assert np.allclose(xk, ex_x[kk - 1], rtol=1e-10, atol=1e-12)
+
+
+@pytest.mark.parametrize("case", ["lap2d_64", "lap3d_16", "diff27_8", "powerlaw_3k"])
+def test_pcg_sr_matches_textbook_cg(orc, case):
+    """Same Krylov method: residual histories agree with the (pinned)
+    textbook oracle to 1e-10 for 20 steps, counts within one."""
+    A = {"lap2d_64": lambda: spkgen.laplace2d5(64), "lap3d_16": lambda: spkgen.laplace3d7(16),
+         "diff27_8": lambda: spkgen.diffusion3d27_lognormal(8, seed=3),
+         "powerlaw_3k": lambda: spkgen.powerlaw_spd(3000, seed=2)}[case]()
+    b = spkgen.rhs_uniform(A.n, 1)
+    x1, r1, h1 = oracle.pcg(A, b, hist_len=2000)
+    x2, r2, h2 = oracle.pcg(A, b, hist_len=2000, **SR)
+    assert r1["reason"] == r2["reason"] == 1
+    assert abs(r1["iterations"] - r2["iterations"]) <= 1
+    assert np.allclose(h2[:21], h1[:21], rtol=1e-10, atol=0)
+    assert r2["true_rel_residual"] <= 1e-8
+    assert np.linalg.norm(x1 - x2) <= 1e-6 * np.linalg.norm(x1)
+
+
+def test_pcg_sr_a_norm_error_monotone(orc):
+    A = spkgen.diffusion3d27_lognormal(5, seed=0)
+    D = spkgen.to_dense(A)
+    b = spkgen.rhs_uniform(A.n, 2)
+    xs = np.linalg.solve(D, b)
+    errs = []
+    for k in range(0, 25):
+        xk, _, _ = oracle.pcg(A, b, rtol=0.0, maxit=k, **SR)
+        e = xs - xk
+        errs.append(math.sqrt(e @ D @ e))
+    assert all(errs[i + 1] <= errs[i] * (1 + 1e-12) for i in range(len(errs) - 1))
+    assert errs[-1] < 1e-3 * errs[0]
+
+
+def test_pcg_sr_reasons(orc):
+    A = spkgen.laplace2d5(10)
+    b = spkgen.rhs_uniform(A.n, 0)
+    _, r, _ = oracle.pcg(A, b, maxit=5, **SR)
+    assert r["reason_str"] == "DIVERGED_ITS" and r["iterations"] == 5
+    x, r, _ = oracle.pcg(A, np.zeros(A.n), **SR)
+    assert r["reason_str"] == "CONVERGED_ATOL" and r["iterations"] == 0 and not x.any()
+    xs = np.random.default_rng(0).integers(-5, 5, A.n).astype(np.float64)
+    x, r, _ = oracle.pcg(A, oracle.spmv(A, xs), x0=xs, **SR)
+    assert r["iterations"] == 0 and np.array_equal(x, xs)
+    # symmetric indefinite: negative diagonal entries
+    Dm = spkgen.to_dense(A)
+    Dm[np.arange(0, A.n, 2), np.arange(0, A.n, 2)] *= -1
+    _, r, _ = oracle.pcg(spkgen.dense_to_csr(Dm), b, **SR)
+    assert r["reason_str"] in ("DIVERGED_INDEFINITE_PC", "DIVERGED_INDEFINITE_MAT")
