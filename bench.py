@@ -240,6 +240,18 @@ def bench_c2(args):
     cheb["note"] = ("x0 = 0, no residual output: 40n (init) + (steps-1) x (12 nnz + 4(n+1) + 56n) "
                     "fused SpMV+update passes + 24n (last x += d)")
 
+    # single-reduction (Chronopoulos-Gear) FP64 solve of the same system
+    osr = spk.ksp_opts(graph_k=args.graph_k, single_reduction=1)
+    xsr = torch.zeros_like(xs)
+    rsr = spk.ksp_solve(M, bd, xsr, osr)
+    tsr = []
+    for _ in range(3):
+        rsr = spk.ksp_solve(M, bd, xsr, osr)
+        tsr.append(rsr.seconds)
+    sr = {"solves_per_s": 1.0 / float(np.median(tsr)), "ms_p50": float(np.median(tsr)) * 1e3,
+          "iterations": rsr.iterations, "us_per_iter": float(np.median(tsr)) * 1e6 / max(rsr.iterations, 1),
+          "true_rel_residual": rsr.true_rel_residual, "reason": spk.reason_str(rsr.reason)}
+
     # multiple right-hand sides (k = 8): SpMM, and 8 solves sharing each SpMM
     kk = 8
     Xm = torch.stack([xs] * kk, dim=1).contiguous()
@@ -307,6 +319,7 @@ def bench_c2(args):
             "gbps": solve_bytes(info, r64) / (float(np.median(t64)) * 1e-3) / 1e9,
             "true_rel_residual_oracle": rel64, "reason": spk.reason_str(r64.reason),
         },
+        "pcg_fp64_single_reduction": sr,
         "chebyshev": cheb,
         "multi_rhs": multi,
         "pcg_mixed": {
@@ -630,16 +643,22 @@ def bench_spectrum(args):
         t_spmv = timed(lambda: spk.mat_mult(M, xs, ys))
         b = xs
         xx = torch.zeros_like(xs)
-        secs = {}
-        for its in (20, 60):
-            o = spk.ksp_opts(rtol=0.0, atol=0.0, maxit=its, graph_k=args.graph_k)
-            spk.ksp_solve(M, b, xx, o)
-            secs[its] = float(np.median([spk.ksp_solve(M, b, xx, o).seconds for _ in range(5)]))
-        t_it = (secs[60] - secs[20]) / 40 * 1e6
+        def iter_us(single_reduction):
+            secs = {}
+            for its in (20, 60):
+                o = spk.ksp_opts(rtol=0.0, atol=0.0, maxit=its, graph_k=args.graph_k,
+                                 single_reduction=single_reduction)
+                spk.ksp_solve(M, b, xx, o)
+                secs[its] = float(np.median([spk.ksp_solve(M, b, xx, o).seconds for _ in range(5)]))
+            return (secs[60] - secs[20]) / 40 * 1e6
+
+        t_it = iter_us(0)
+        t_sr = iter_us(1)
         mat.append({"N": N, "n": info.n, "nnz": info.nnz, "kernel": spk.KERNEL_NAMES[info.kernel],
                     "spmv_us": t_spmv, "spmv_gbps": info.bytes_spmv_f64 / t_spmv / 1e3,
-                    "pcg_iter_us": t_it, "pcg_iter_gbps": info.bytes_pcg_iter_f64 / t_it / 1e3})
-        log(f"3D {N}^3: spmv {t_spmv:.2f} us, pcg iteration {t_it:.2f} us")
+                    "pcg_iter_us": t_it, "pcg_iter_gbps": info.bytes_pcg_iter_f64 / t_it / 1e3,
+                    "pcg_sr_iter_us": t_sr})
+        log(f"3D {N}^3: spmv {t_spmv:.2f} us, pcg iteration {t_it:.2f} us, single-reduction {t_sr:.2f} us")
         M.close()
     big = mat[-1]
     return {
@@ -651,7 +670,7 @@ def bench_spectrum(args):
                                "(SpMV, and Jacobi-PCG iterations from (t(60 its) - t(20 its)) / 40)"},
         "vectors": vec, "laplace3d": mat,
         "latency_us": {"axpy": vec[0]["axpy_us"], "copy": vec[0]["copy_us"], "spmv": mat[0]["spmv_us"],
-                       "pcg_iter": mat[0]["pcg_iter_us"]},
+                       "pcg_iter": mat[0]["pcg_iter_us"], "pcg_sr_iter": mat[0]["pcg_sr_iter_us"]},
     }
 
 

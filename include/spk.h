@@ -241,7 +241,9 @@ typedef struct {
     double *hist;         /* optional host double[hist_len]: ||r_k||_2 of the
                              recursive residual, k = 0..iterations */
     int32_t hist_len;
-    int32_t pad_;
+    int32_t single_reduction;  /* FP64 only: 1 selects the single-reduction
+                                  (Chronopoulos-Gear) recurrences, two kernels
+                                  per iteration instead of four (default 0) */
 } spk_ksp_opts;
 
 void spk_ksp_opts_default(spk_ksp_opts *o);

@@ -9,6 +9,7 @@
 
 #include "cheb.hpp"
 #include "krylov.hpp"
+#include "sr.hpp"
 #include "runtime.hpp"
 
 namespace spk {
@@ -39,6 +40,10 @@ void free_workspace(spk_mat *A)
     hipFree(w->p32);
     hipFree(w->q32);
     hipFree(w->d32);
+    hipFree(w->s);
+    hipFree(w->srp);
+    hipFree(w->sc);
+    if (w->gsr) hipGraphExecDestroy(w->gsr);
     hipHostFree(w->pdesc);
     hipHostFree(w->pst);
     hipHostFree(w->pstatus);
@@ -389,6 +394,151 @@ __global__ void k_zero64(int64_t m, double *__restrict__ a)
         a[i] = 0.0;
 }
 
+// ------------------------------------------------------------------ single reduction
+static SrDesc sr_desc(Workspace *w)
+{
+    SrDesc a;
+    a.d = w->hdesc;
+    a.s = w->s;
+    a.part = w->srp;
+    a.sc = (SrScal *)w->sc;
+    return a;
+}
+
+// A_i of the single-reduction iteration (m < 0: the SpMV of a (re)start).
+static int sr_spmv(spk_mat *A, Workspace *w, const SrDesc &a, int m, hipStream_t s)
+{
+    const dim3 g(A->nblk), t(kBlock);
+    if (A->kernel == SPK_KERNEL_SELL) {
+        with_sell_u(A->sell_u, [&](auto uc) {
+            constexpr int U = decltype(uc)::value;
+            if (A->sell_cw == 2) hipLaunchKernelGGL((k_sr_spmv_sell<int16_t, U>), g, t, 0, s, a, m);
+            else hipLaunchKernelGGL((k_sr_spmv_sell<int32_t, U>), g, t, 0, s, a, m);
+        });
+    } else if (A->kernel == SPK_KERNEL_STREAM) {
+        hipLaunchKernelGGL(k_sr_spmv_stream, g, t, 0, s, a, m);
+    } else {
+        SPK_TRY(launch_spmv<double>(A, A->val, w->z, w->q, s, w->st, kGateInner64));
+        hipLaunchKernelGGL(k_sr_dot, g, t, 0, s, a, m);
+    }
+    SPK_HIP(hipGetLastError());
+    return SPK_OK;
+}
+
+static int sr_batch(spk_mat *A, Workspace *w, const SrDesc &a, int K, hipStream_t s)
+{
+    for (int m = 0; m < K; ++m) {
+        hipLaunchKernelGGL(k_sr_update, dim3(A->nblk), dim3(kBlock), 0, s, a, m);
+        SPK_TRY(sr_spmv(A, w, a, m, s));
+    }
+    hipLaunchKernelGGL(k_sr_advance, dim3(1), dim3(64), 0, s, a.sc, K);
+    SPK_HIP(hipGetLastError());
+    return SPK_OK;
+}
+
+// (Re)start at iteration b from the residual in r: u, w and their partials.
+static int sr_start(spk_mat *A, Workspace *w, const SrDesc &a, int b, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_sr_rebase, dim3(1), dim3(64), 0, s, a.sc, b);
+    hipLaunchKernelGGL(k_sr_setup, dim3(A->nblk), dim3(kBlock), 0, s, a, b & 1);
+    SPK_HIP(hipGetLastError());
+    return sr_spmv(A, w, a, -1, s);
+}
+
+// FP64 single-reduction Jacobi-PCG on w->x (already initialised); the same
+// stopping rule, restarts and results as solve64.
+static int solve_sr(spk_mat *A, Workspace *w, const spk_ksp_opts &o, int hist_len, hipStream_t s,
+                    SolveOut *out)
+{
+    if (!w->s) {
+        SPK_HIP(hipMalloc((void **)&w->s, sizeof(double) * std::max(A->n, 1)));
+        SPK_HIP(hipMalloc((void **)&w->srp, sizeof(double) * 6 * std::max(A->nblk, 1)));
+        SPK_HIP(hipMalloc(&w->sc, sizeof(SrScal)));
+        w->bytes += 8 * (int64_t)std::max(A->n, 1) + 48 * (int64_t)std::max(A->nblk, 1) + sizeof(SrScal);
+    }
+    const SrDesc a = sr_desc(w);
+    const int K = o.graph_k > 0 ? o.graph_k : 8;
+    const bool use_graph = o.graph_k > 0;
+    hipLaunchKernelGGL(k_state_init, dim3(1), dim3(64), 0, s, w->st, o.rtol, o.atol, o.maxit, 0,
+                       o.inner_rtol, o.inner_maxit, o.max_outer, hist_len);
+    SPK_TRY(launch_resid(A, w, kResSetup, false, s));
+    SPK_TRY(sr_start(A, w, a, 0, s));
+    if (use_graph && (!w->gsr || w->gsr_k != K)) {
+        if (w->gsr) { hipGraphExecDestroy(w->gsr); w->gsr = nullptr; }
+        hipGraph_t graph = nullptr;
+        SPK_HIP(hipStreamBeginCapture(w->cap, hipStreamCaptureModeThreadLocal));
+        const int rc = sr_batch(A, w, a, K, w->cap);
+        const hipError_t e = hipStreamEndCapture(w->cap, &graph);
+        if (rc) { if (graph) hipGraphDestroy(graph); return rc; }
+        if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture", __FILE__, __LINE__);
+        const hipError_t e2 = hipGraphInstantiate(&w->gsr, graph, nullptr, nullptr, 0);
+        hipGraphDestroy(graph);
+        if (e2 != hipSuccess) { w->gsr = nullptr; return hip_fail(e2, "hipGraphInstantiate", __FILE__, __LINE__); }
+        w->gsr_k = K;
+    }
+    int restarts = 0;
+    for (;;) {
+        SPK_TRY(read_state(w, s));
+        if (w->pst->status == SPK_RUNNING) {
+            const int max_batches = (std::max(o.maxit - w->pst->iter, 0) + K - 1) / K + 2;
+            int launched = 0, checked = 0;
+            for (;;) {
+                if (launched - checked < 2 && launched < max_batches) {
+                    if (use_graph) SPK_HIP(hipGraphLaunch(w->gsr, s));
+                    else SPK_TRY(sr_batch(A, w, a, K, s));
+                    const int slot = launched % 4;
+                    hipLaunchKernelGGL(k_publish, dim3(1), dim3(64), 0, s, w->st, &w->pstatus[2 * slot]);
+                    SPK_HIP(hipEventRecord(w->ev[slot], s));
+                    ++launched;
+                    continue;
+                }
+                if (checked == launched) {
+                    SPK_HIP(hipStreamSynchronize(s));
+                    set_error("single-reduction solver did not stop within %d batches", max_batches);
+                    return SPK_EHIP;
+                }
+                const int slot = checked % 4;
+                SPK_HIP(hipEventSynchronize(w->ev[slot]));
+                ++checked;
+                if (w->pstatus[2 * slot] != SPK_RUNNING) break;
+            }
+            SPK_HIP(hipStreamSynchronize(s));
+        }
+        SPK_TRY(launch_resid(A, w, kResTrue, false, s));
+        SPK_TRY(read_state(w, s));
+        const SysState &S = *w->pst;
+        const bool conv = S.status == SPK_CONVERGED_RTOL || S.status == SPK_CONVERGED_ATOL;
+        if (conv && S.bnorm > 0 && S.iter > 0 && S.rnorm_true > S.thresh) {
+            if (restarts == 3) {
+                out->reason = SPK_DIVERGED_BREAKDOWN;
+                break;
+            }
+            ++restarts;
+            hipLaunchKernelGGL(k_state_restart, dim3(1), dim3(64), 0, s, w->st);
+            SPK_TRY(sr_start(A, w, a, S.iter, s));
+            continue;
+        }
+        out->reason = S.status;
+        if (conv && S.iter > 0)
+            out->reason = S.rnorm_true <= S.rtol * S.bnorm ? SPK_CONVERGED_RTOL : SPK_CONVERGED_ATOL;
+        break;
+    }
+    const SysState &S = *w->pst;
+    out->iterations = S.iter;
+    out->restarts = restarts;
+    out->rnorm0 = S.rnorm0;
+    out->rnorm = (S.status == SPK_CONVERGED_RTOL || S.status == SPK_CONVERGED_ATOL) && S.iter > 0
+                     ? S.rnorm_true : S.rnorm;
+    out->bnorm = S.bnorm;
+    out->rnorm_true = S.rnorm_true;
+    if (S.bnorm == 0.0) {
+        fill_zero(w->x, A->n, s);
+        out->rnorm_true = 0.0;
+        out->rnorm = 0.0;
+    }
+    return SPK_OK;
+}
+
 static void fill_zero(double *p, int64_t n, hipStream_t s)
 {
     if (n <= 0) return;
@@ -542,6 +692,10 @@ int spk_ksp_solve(spk_mat *A, const double *b, double *x, const spk_ksp_opts *op
         return SPK_OK;
     }
     const bool mixed = o.precision != SPK_PREC_FP64;
+    if (mixed && o.single_reduction) {
+        set_error("single_reduction needs precision SPK_PREC_FP64");
+        return SPK_EINVAL;
+    }
     if (mixed) SPK_TRY(ensure_f32(A, s));
     Workspace *w = nullptr;
     SPK_TRY(get_workspace(A, mixed, &w));
@@ -550,6 +704,7 @@ int spk_ksp_solve(spk_mat *A, const double *b, double *x, const spk_ksp_opts *op
         SPK_HIP(hipStreamSynchronize(s));
         if (w->g64) { hipGraphExecDestroy(w->g64); w->g64 = nullptr; }
         if (w->gmix) { hipGraphExecDestroy(w->gmix); w->gmix = nullptr; }
+        if (w->gsr) { hipGraphExecDestroy(w->gsr); w->gsr = nullptr; }
         if (w->hist) hipFree(w->hist);
         w->hist = nullptr;
         SPK_HIP(hipMalloc(&w->hist, sizeof(double) * o.hist_len));
@@ -580,6 +735,8 @@ int spk_ksp_solve(spk_mat *A, const double *b, double *x, const spk_ksp_opts *op
             out = o64;
             out.rnorm0 = r0;
         }
+    } else if (o.single_reduction) {
+        SPK_TRY(solve_sr(A, w, o, o.hist_len, s, &out));
     } else {
         SPK_TRY(solve64(A, w, o, false, o.hist_len, s, &out));
     }

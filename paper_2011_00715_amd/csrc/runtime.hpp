@@ -45,8 +45,12 @@ struct Workspace {
     double *b = nullptr;          // the solve's right-hand side (copied in)
     float *r32 = nullptr, *z32 = nullptr, *p32 = nullptr, *q32 = nullptr, *d32 = nullptr;
     hipStream_t cap = nullptr;    // private stream used only to capture graphs
-    hipGraphExec_t g64 = nullptr, gmix = nullptr;
-    int g64_k = 0, gmix_k = 0;
+    hipGraphExec_t g64 = nullptr, gmix = nullptr, gsr = nullptr;
+    int g64_k = 0, gmix_k = 0, gsr_k = 0;
+    // single-reduction solves (allocated on first use)
+    double *s = nullptr;          // s = A p
+    double *srp = nullptr;        // 2 sets x 3 partial arrays x nblk
+    void *sc = nullptr;           // device scalars of the single-reduction recurrences
     int64_t bytes = 0;
 };
 

@@ -61,7 +61,7 @@ class KspOpts(ctypes.Structure):
         ("rtol", dbl), ("atol", dbl), ("maxit", i32), ("precision", i32),
         ("x0_nonzero", i32), ("graph_k", i32), ("inner_rtol", dbl),
         ("inner_maxit", i32), ("max_outer", i32),
-        ("hist", ctypes.POINTER(dbl)), ("hist_len", i32), ("pad_", i32),
+        ("hist", ctypes.POINTER(dbl)), ("hist_len", i32), ("single_reduction", i32),
     ]
 
 

@@ -195,3 +195,58 @@ def test_pcg_repeat_bitwise():
     x3, r3, _ = _solve(spk, M, b, precision=spk.PREC_MIXED)
     x4, r4, _ = _solve(spk, M, b, precision=spk.PREC_MIXED)
     assert np.array_equal(x3, x4) and r3.inner_iterations == r4.inner_iterations
+
+
+@pytest.mark.parametrize("case", ["lap2d_64", "lap3d_24", "diff27_14", "powerlaw_20k"])
+@pytest.mark.parametrize("kernel", ["auto", "stream", "vector", "merge"])
+def test_pcg_single_reduction_parity(case, kernel):
+    """Single-reduction (Chronopoulos-Gear) solve against the single-reduction
+    oracle, with the same contract as the textbook solve."""
+    spk = need_gpu()
+    name, A, seed = [c for c in _cases() if c[0] == case][0]
+    M = mat_on_gpu(spk, A)
+    if kernel == "stream":
+        spk.mat_set_kernel(M, spk.KERNEL_STREAM, 0)
+    elif kernel == "vector":
+        spk.mat_set_kernel(M, spk.KERNEL_VECTOR, 8)
+    elif kernel == "merge":
+        spk.mat_set_kernel(M, spk.KERNEL_MERGE, 0)
+    b = spkgen.rhs_uniform(A.n, seed)
+    x, res, hist = _solve(spk, M, b, hist_len=4000, single_reduction=1)
+    xo, ro, ho = oracle.pcg(A, b, rtol=1e-8, hist_len=4000, single_reduction=True)
+    assert res.reason == spk.CONVERGED_RTOL, res.as_dict()
+    assert abs(res.iterations - ro["iterations"]) <= max(2, 0.01 * ro["iterations"])
+    k = min(20, res.iterations, ro["iterations"])
+    assert np.allclose(hist[:k + 1], ho[:k + 1], rtol=1e-10, atol=0), (hist[:k + 1], ho[:k + 1])
+    r = b - oracle.spmv(A, x)
+    assert oracle.nrm2(r) <= 1e-8 * oracle.nrm2(b) * (1 + 1e-6)
+    assert abs(res.true_rel_residual - oracle.nrm2(r) / oracle.nrm2(b)) <= 1e-12
+    assert np.linalg.norm(x - xo) <= 1e-5 * np.linalg.norm(xo)
+
+
+def test_pcg_single_reduction_graph_direct_and_reasons():
+    spk = need_gpu()
+    A = spkgen.diffusion3d27_lognormal(12, seed=3)
+    M = mat_on_gpu(spk, A)
+    b = spkgen.rhs_uniform(A.n, 0)
+    outs = []
+    for gk in (8, 0, 5):
+        x, res, _ = _solve(spk, M, b, graph_k=gk, single_reduction=1)
+        outs.append((x, res.iterations, res.rnorm))
+    for x, it, rn in outs[1:]:
+        assert np.array_equal(x, outs[0][0]) and it == outs[0][1] and rn == outs[0][2]
+    # the same matrix and right-hand side through the textbook solve
+    xt, rt, _ = _solve(spk, M, b)
+    assert abs(rt.iterations - outs[0][1]) <= 2
+    # maxit, b = 0, exact start
+    _, r, _ = _solve(spk, M, b, maxit=7, single_reduction=1)
+    assert r.reason == spk.DIVERGED_ITS and r.iterations == 7
+    x, r, _ = _solve(spk, M, np.zeros(A.n), single_reduction=1)
+    assert r.reason == spk.CONVERGED_ATOL and r.iterations == 0 and not x.any()
+    A2 = spkgen.laplace2d5(20)
+    M2 = mat_on_gpu(spk, A2)
+    xs = np.random.default_rng(0).integers(-5, 5, A2.n).astype(np.float64)
+    x, r, _ = _solve(spk, M2, oracle.spmv(A2, xs), x0=xs, single_reduction=1)
+    assert r.iterations == 0 and np.array_equal(x, xs)
+    with pytest.raises(spk.SpkError):
+        _solve(spk, M2, xs, single_reduction=1, precision=spk.PREC_MIXED)
