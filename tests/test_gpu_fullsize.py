@@ -156,3 +156,45 @@ def test_c5_served_requests_full_sizes():
         assert res.reason == spk.CONVERGED_RTOL
         assert oracle.nrm2(b - oracle.spmv(A, x)) <= 1e-8 * oracle.nrm2(b) * (1 + 1e-6)
     S.close()
+
+
+def test_c2_single_reduction_chebyshev_and_multi():
+    """The bench's extra C2 legs at full size: the single-reduction solve
+    against its oracle, the 8-step Chebyshev smoother against its oracle,
+    and 8 right-hand sides sharing each SpMM (oracle true residual of every
+    column; column 0 is the bench's right-hand side, 446 oracle iterations)."""
+    spk = need_gpu()
+    import torch
+
+    A = spkgen.laplace3d7(128)
+    M = mat_on_gpu(spk, A)
+    b = spkgen.rhs_uniform(A.n, 0)
+    bn = oracle.nrm2(b)
+    # single reduction
+    xs, rs = _solve(spk, M, b, single_reduction=1)
+    xo, ro, _ = oracle.pcg(A, b, single_reduction=True)
+    assert rs.reason == spk.CONVERGED_RTOL
+    assert abs(rs.iterations - ro["iterations"]) <= max(2, 0.01 * ro["iterations"])
+    assert oracle.nrm2(b - oracle.spmv(A, xs)) <= 1e-8 * bn * (1 + 1e-6)
+    assert np.linalg.norm(xs - xo) <= 1e-5 * np.linalg.norm(xo)
+    # Chebyshev, default interval [g/10, g]
+    g = oracle.gershgorin(A)
+    assert M.info.gershgorin == pytest.approx(g, rel=1e-14)
+    x = torch.zeros(A.n, dtype=torch.float64, device="cuda")
+    spk.pc_chebyshev(M, to_dev(b), x, 8)
+    xc, _ = oracle.chebyshev(A, b, 8, g / 10, g)
+    assert np.max(np.abs(x.cpu().numpy() - xc)) <= 1e-11 * np.max(np.abs(xc))
+    # 8 right-hand sides
+    k = 8
+    B = np.stack([spkgen.rhs_uniform(A.n, s) for s in range(k)], axis=1)
+    X = torch.zeros((A.n, k), dtype=torch.float64, device="cuda")
+    res = spk.ksp_solve_multi(M, torch.from_numpy(B).cuda(), X)
+    X = X.cpu().numpy()
+    # column 0 is the right-hand side of the textbook oracle solve above the
+    # single-reduction one: its count is pinned (446, SciPy agrees)
+    _, r0, _ = oracle.pcg(A, b)
+    assert abs(res[0].iterations - r0["iterations"]) <= max(2, 0.01 * r0["iterations"])
+    for j in range(k):
+        bj = B[:, j].copy()
+        assert res[j].reason == spk.CONVERGED_RTOL
+        assert oracle.nrm2(bj - oracle.spmv(A, X[:, j].copy())) <= 1e-8 * oracle.nrm2(bj) * (1 + 1e-6)
