@@ -506,6 +506,7 @@ def bench_serve(args):
     opts = spk.server_opts_default()
     opts.hbm_budget_bytes = 32 << 30
     opts.max_slots = 64
+    opts.pinned_bytes = 8 << 30  # room for the requests queued ahead of admission
     opts.graph_k = args.graph_k
     S = spk.server_create(opts)
     o = spk.ksp_opts(precision=spk.PREC_MIXED)

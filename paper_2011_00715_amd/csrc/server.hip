@@ -18,6 +18,7 @@
 #include <deque>
 #include <map>
 #include <mutex>
+#include <thread>
 #include <vector>
 
 #include "krylov.hpp"
@@ -725,27 +726,63 @@ int spk_server_submit(spk_server *S, int32_t n, int64_t nnz, const int32_t *rowp
         set_error("out of host memory");
         return SPK_ENOMEM;
     }
-    // one pass over the nonzeros: copy, check the columns, find the diagonal
+    // one pass over the nonzeros: copy, check the columns, find the diagonal;
+    // large systems split the rows over a few host threads (the copy into
+    // the pinned pool is what bounds admission when requests queue up)
     int rc = SPK_OK;
     memcpy(q->h_rowptr, rowptr, sizeof(int32_t) * ((size_t)n + 1));
-    for (int32_t i = 0; i < n && rc == SPK_OK; ++i) {
-        double d = 0.0;
-        for (int32_t k = rowptr[i]; k < rowptr[i + 1]; ++k) {
-            const int32_t c = colind[k];
-            const double v = values[k];
-            if (c < 0 || c >= n) {
-                set_error("column %d out of range in row %d", c, i);
-                rc = SPK_EINVAL;
-                break;
+    struct Bad {
+        int32_t row = INT32_MAX;
+        int32_t col = 0;
+        int code = SPK_OK;
+    };
+    auto check_rows = [&](int32_t i0, int32_t i1, Bad &bad) {
+        int32_t *__restrict__ hc = q->h_col;
+        double *__restrict__ hv = q->h_val;
+        for (int32_t i = i0; i < i1; ++i) {
+            const int32_t a = rowptr[i], e = rowptr[i + 1];
+            double d = 0.0;
+            int32_t lo = 0, hi = n - 1;  // min / max column of the row
+            for (int32_t k = a; k < e; ++k) {
+                const int32_t c = colind[k];
+                const double v = values[k];
+                hc[k] = c;
+                hv[k] = v;
+                lo = c < lo ? c : lo;
+                hi = c > hi ? c : hi;
+                d += c == i ? v : 0.0;
             }
-            q->h_col[k] = c;
-            q->h_val[k] = v;
-            if (c == i) d += v;
+            if (lo < 0 || hi >= n) {
+                for (int32_t k = a; k < e; ++k)
+                    if (colind[k] < 0 || colind[k] >= n) { bad = {i, colind[k], SPK_EINVAL}; return; }
+            }
+            if (d == 0.0) { bad = {i, 0, SPK_EZERODIAG}; return; }
         }
-        if (rc == SPK_OK && d == 0.0) {
-            set_error("row %d has no stored or a zero diagonal", i);
-            rc = SPK_EZERODIAG;
+    };
+    const int nthreads = nnz >= (1 << 20) ? 8 : 1;
+    std::vector<Bad> bad(nthreads);
+    if (nthreads == 1) {
+        check_rows(0, n, bad[0]);
+    } else {
+        std::vector<std::thread> th;
+        for (int t = 0; t < nthreads; ++t) {
+            // row ranges with about equal nonzero counts
+            const int64_t k0 = nnz * t / nthreads, k1 = nnz * (t + 1) / nthreads;
+            const int32_t i0 = t == 0 ? 0 : (int32_t)(std::upper_bound(rowptr, rowptr + n + 1, (int32_t)k0) - rowptr - 1);
+            const int32_t i1 = t == nthreads - 1 ? n : (int32_t)(std::upper_bound(rowptr, rowptr + n + 1, (int32_t)k1) - rowptr - 1);
+            th.emplace_back(check_rows, std::max(i0, 0), std::min(i1, n), std::ref(bad[t]));
         }
+        for (auto &x : th) x.join();
+    }
+    Bad first;
+    for (const Bad &x : bad)
+        if (x.code != SPK_OK && x.row < first.row) first = x;
+    if (first.code == SPK_EINVAL) {
+        set_error("column %d out of range in row %d", first.col, first.row);
+        rc = SPK_EINVAL;
+    } else if (first.code == SPK_EZERODIAG) {
+        set_error("row %d has no stored or a zero diagonal", first.row);
+        rc = SPK_EZERODIAG;
     }
     if (rc != SPK_OK) {
         if (q->pin_off >= 0) {
