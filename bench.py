@@ -551,15 +551,13 @@ def bench_serve(args):
             nxt = None
             i += 1
         spk.server_progress(S, 1)
-        for t, (t_arr, n) in list(pending.items()):
-            got = spk.server_poll(S, t, np.empty(n))
-            if got is not None:
-                res, tdone = got
-                lat.append(tdone - t_arr)
-                iters.append(res.inner_iterations + res.iterations)
-                worst_rel = max(worst_rel, res.true_rel_residual)
-                assert res.reason > 0, spk.reason_str(res.reason)
-                del pending[t]
+        for t in spk.server_completed(S):  # the completion queue: poll only finished requests
+            t_arr, n = pending.pop(t)
+            res, tdone = spk.server_poll(S, t, np.empty(n))
+            lat.append(tdone - t_arr)
+            iters.append(res.inner_iterations + res.iterations)
+            worst_rel = max(worst_rel, res.true_rel_residual)
+            assert res.reason > 0, spk.reason_str(res.reason)
     elapsed = spk.now() - t0
     S.close()
     seq = None

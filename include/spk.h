@@ -334,6 +334,12 @@ int spk_server_progress(spk_server *s, int32_t max_steps);
 int spk_server_poll(spk_server *s, uint64_t ticket, double *x_host, spk_ksp_result *res,
                     double *done_time);
 
+/* Completion queue: copies up to cap tickets of requests that finished since
+ * the last call (in completion order) and returns how many (>= 0), so a
+ * client polls only those.  Each ticket is reported once; spk_server_poll
+ * still collects it. */
+int spk_server_completed(spk_server *s, uint64_t *tickets, int32_t cap);
+
 int spk_server_destroy(spk_server *s);
 
 /* ---------------------------------------------------------------- misc */

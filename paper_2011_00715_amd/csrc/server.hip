@@ -159,6 +159,7 @@ struct spk_server {
     Arena pin_arena;
     std::deque<Request *> queue;
     std::map<uint64_t, Request *> tickets;
+    std::deque<uint64_t> done;  // finished tickets not yet reported by spk_server_completed
     uint64_t next_ticket = 1;
     std::mutex mu;
 };
@@ -531,6 +532,7 @@ static int end_retire(spk_server *S, int k, const SysState &st)
     q->t_done = spk_now();
     r.seconds = q->t_done - q->t_submit;
     q->state = kDone;
+    S->done.push_back(q->ticket);
     q->slot = -1;
     S->arena.release(sl.off, sl.len);
     sl.req = nullptr;
@@ -879,6 +881,18 @@ int spk_server_poll(spk_server *S, uint64_t ticket, double *x_host, spk_ksp_resu
     S->tickets.erase(it);
     delete q;
     return SPK_OK;
+}
+
+int spk_server_completed(spk_server *S, uint64_t *tickets, int32_t cap)
+{
+    if (!S || cap < 0 || (cap > 0 && !tickets)) { set_error("bad argument"); return SPK_EINVAL; }
+    std::lock_guard<std::mutex> lk(S->mu);
+    int32_t k = 0;
+    while (k < cap && !S->done.empty()) {
+        tickets[k++] = S->done.front();
+        S->done.pop_front();
+    }
+    return k;
 }
 
 int spk_server_destroy(spk_server *S)

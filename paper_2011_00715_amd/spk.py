@@ -120,6 +120,7 @@ _sig("spk_server_submit", ctypes.c_int, [P, i32, i64, P, P, P, P, ctypes.POINTER
 _sig("spk_server_progress", ctypes.c_int, [P, i32])
 _sig("spk_server_poll", ctypes.c_int, [P, u64, P, ctypes.POINTER(KspResult),
                                        ctypes.POINTER(dbl)])
+_sig("spk_server_completed", ctypes.c_int, [P, ctypes.POINTER(u64), i32])
 _sig("spk_server_destroy", ctypes.c_int, [P])
 _sig("spk_status_str", ctypes.c_char_p, [ctypes.c_int])
 _sig("spk_reason_str", ctypes.c_char_p, [ctypes.c_int])
@@ -134,7 +135,7 @@ EXPORTS = [
     "spk_mat_get_info", "spk_pc_jacobi_apply", "spk_pc_chebyshev", "spk_mat_destroy", "spk_vec_axpy",
     "spk_vec_aypx", "spk_vec_dot", "spk_vec_dot2", "spk_vec_nrm2", "spk_ksp_opts_default",
     "spk_ksp_solve", "spk_mat_mult_multi", "spk_ksp_solve_multi", "spk_server_opts_default", "spk_server_create", "spk_server_submit",
-    "spk_server_progress", "spk_server_poll", "spk_server_destroy", "spk_status_str",
+    "spk_server_progress", "spk_server_poll", "spk_server_completed", "spk_server_destroy", "spk_status_str",
     "spk_reason_str", "spk_last_error", "spk_now", "spk_runtime_version", "spk_bw_copy",
     "spk_cache_flush",
 ]
@@ -466,6 +467,15 @@ def server_poll(S: Server, ticket: int, x_host):
         return None
     _check(rc, "spk_server_poll")
     return res, tdone.value
+
+
+def server_completed(S: Server, cap: int = 256) -> list:
+    """Tickets of requests finished since the last call (each reported once)."""
+    buf = (u64 * cap)()
+    k = _lib.spk_server_completed(S.handle, buf, int(cap))
+    if k < 0:
+        raise SpkError(k, "spk_server_completed")
+    return list(buf[:k])
 
 
 def server_destroy(S: Server):

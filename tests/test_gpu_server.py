@@ -126,3 +126,28 @@ def test_server_failure_isolated():
     S1 = spk.server_create()
     alone = _run(spk, S1, [good[0]], spk.PREC_FP64)
     assert np.array_equal(alone[0][0], res[0][0])
+
+
+def test_server_completion_queue():
+    """spk_server_completed reports every finished ticket exactly once, and
+    only finished ones (each reported ticket can be collected at once)."""
+    spk = need_gpu()
+    items = _requests(10, seed=4)
+    opts = spk.server_opts_default()
+    opts.max_slots = 3
+    S = spk.server_create(opts)
+    tickets = [spk.server_submit(S, A.rowptr, A.col, A.val, b, spk.ksp_opts()) for _, A, b in items]
+    n_of = {t: A.n for t, (_, A, _) in zip(tickets, items)}
+    seen = []
+    for _ in range(100000):
+        spk.server_progress(S, 2)
+        for t in spk.server_completed(S, cap=4):
+            assert t in n_of and t not in seen
+            got = spk.server_poll(S, t, np.empty(n_of[t]))
+            assert got is not None and got[0].reason == spk.CONVERGED_RTOL
+            seen.append(t)
+        if len(seen) == len(tickets):
+            break
+    assert sorted(seen) == sorted(tickets)
+    assert spk.server_completed(S) == []
+    S.close()
