@@ -26,6 +26,9 @@
  *    preconditioner (CG is named in Sec. 5.5, Jacobi in Sec. 5.3).  The paper
  *    prints no CG algorithm, so this is the textbook preconditioned CG
  *    (Hestenes & Stiefel 1952), with the readings listed at orc_pcg().
+ *  - The multigrid functions (orc_mg_*) follow the geometric multigrid of
+ *    Sec. 5.3 (Chebyshev-Jacobi smoothing, direct coarsest solve), with the
+ *    aggregation reading of the grid transfers stated at orc_mg_coarse_shape().
  *
  * Every function is pinned by CPU tests against values fixed by mathematics
  * (closed-form eigenpairs, exact integer arithmetic, brute-force dense solves,
@@ -147,6 +150,13 @@ void orc_jacobi_apply(int32_t n, const double *dinv, const double *r, double *z)
 
 static int finite_d(double v) { return isfinite(v); }
 
+/* The preconditioner of orc_pcg: the Jacobi PCApply with ctx = dinv. */
+static int jacobi_pc(void *ctx, int32_t n, const double *r, double *z)
+{
+    orc_jacobi_apply(n, (const double *)ctx, r, z);
+    return 0;
+}
+
 /*
  * Jacobi-preconditioned conjugate gradient, FP64.
  *
@@ -170,14 +180,30 @@ int orc_pcg(int32_t n, const int32_t *rowptr, const int32_t *col,
 {
     memset(res, 0, sizeof(*res));
     double *dinv = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    if (!dinv) return ORC_ENOMEM;
+    int status = orc_diag_inv(n, rowptr, col, val, dinv);
+    if (!status)
+        status = orc_pcg_pc(n, rowptr, col, val, b, x, rtol, atol, maxit, x0_nonzero,
+                            jacobi_pc, dinv, hist, hist_len, res);
+    free(dinv);
+    return status;
+}
+
+/* The same iteration with the preconditioner given as z = pc(r) (a
+ * multigrid cycle, for instance); a non-zero return of pc ends the solve
+ * with that status. */
+int orc_pcg_pc(int32_t n, const int32_t *rowptr, const int32_t *col,
+               const double *val, const double *b, double *x, double rtol,
+               double atol, int32_t maxit, int32_t x0_nonzero, orc_pc_fn pc,
+               void *pc_ctx, double *hist, int32_t hist_len, orc_pcg_result *res)
+{
+    memset(res, 0, sizeof(*res));
     double *r = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
     double *z = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
     double *p = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
     double *q = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
     int status = 0;
-    if (!dinv || !r || !z || !p || !q) { status = ORC_ENOMEM; goto done; }
-    status = orc_diag_inv(n, rowptr, col, val, dinv);
-    if (status) goto done;
+    if (!r || !z || !p || !q) { status = ORC_ENOMEM; goto done; }
 
     double bnorm = orc_nrm2(n, b);
     res->bnorm = bnorm;
@@ -207,7 +233,7 @@ int orc_pcg(int32_t n, const int32_t *rowptr, const int32_t *col,
             res->reason = rnorm <= rtol * bnorm ? ORC_CONVERGED_RTOL : ORC_CONVERGED_ATOL;
             break;
         }
-        orc_jacobi_apply(n, dinv, r, z);
+        if ((status = pc(pc_ctx, n, r, z)) != 0) goto done;
         rho = orc_dot(n, r, z);
         if (!finite_d(rho)) { res->reason = ORC_DIVERGED_NANORINF; break; }
         if (rho < 0.0) { res->reason = ORC_DIVERGED_INDEFINITE_PC; break; }
@@ -245,7 +271,7 @@ int orc_pcg(int32_t n, const int32_t *rowptr, const int32_t *col,
                 break;
             }
             if (k >= maxit) { res->reason = ORC_DIVERGED_ITS; break; }
-            orc_jacobi_apply(n, dinv, r, z);
+            if ((status = pc(pc_ctx, n, r, z)) != 0) goto done;
             double rho_new = orc_dot(n, r, z);
             if (!finite_d(rho_new)) { res->reason = ORC_DIVERGED_NANORINF; break; }
             if (rho_new < 0.0) { res->reason = ORC_DIVERGED_INDEFINITE_PC; break; }
@@ -265,7 +291,7 @@ int orc_pcg(int32_t n, const int32_t *rowptr, const int32_t *col,
     res->true_rel_residual = orc_nrm2(n, r) / bnorm;
 
 done:
-    free(dinv); free(r); free(z); free(p); free(q);
+    free(r); free(z); free(p); free(q);
     return status;
 }
 
@@ -507,7 +533,9 @@ int orc_gershgorin(int32_t n, const int32_t *rowptr, const int32_t *col,
     return 0;
 }
 
-int orc_dense_cholesky_solve(int32_t n, double *A, double *b)
+/* Factor step alone: A (n*n, row-major) is overwritten by L in its lower
+ * triangle.  Returns 0, or -1 if A is not positive definite. */
+int orc_dense_cholesky_factor(int32_t n, double *A)
 {
     for (int32_t j = 0; j < n; ++j) {
         long double s = A[(size_t)j * n + j];
@@ -523,15 +551,171 @@ int orc_dense_cholesky_solve(int32_t n, double *A, double *b)
             A[(size_t)i * n + j] = (double)(t / ljj);
         }
     }
+    return 0;
+}
+
+/* Substitution step alone: b <- L^-T L^-1 b with L from orc_dense_cholesky_factor. */
+void orc_dense_cholesky_subst(int32_t n, const double *L, double *b)
+{
     for (int32_t i = 0; i < n; ++i) { /* L y = b */
         long double t = b[i];
-        for (int32_t k = 0; k < i; ++k) t -= (long double)A[(size_t)i * n + k] * b[k];
-        b[i] = (double)(t / A[(size_t)i * n + i]);
+        for (int32_t k = 0; k < i; ++k) t -= (long double)L[(size_t)i * n + k] * b[k];
+        b[i] = (double)(t / L[(size_t)i * n + i]);
     }
     for (int32_t i = n - 1; i >= 0; --i) { /* L^T x = y */
         long double t = b[i];
-        for (int32_t k = i + 1; k < n; ++k) t -= (long double)A[(size_t)k * n + i] * b[k];
-        b[i] = (double)(t / A[(size_t)i * n + i]);
+        for (int32_t k = i + 1; k < n; ++k) t -= (long double)L[(size_t)k * n + i] * b[k];
+        b[i] = (double)(t / L[(size_t)i * n + i]);
     }
+}
+
+int orc_dense_cholesky_solve(int32_t n, double *A, double *b)
+{
+    if (orc_dense_cholesky_factor(n, A)) return -1;
+    orc_dense_cholesky_subst(n, A, b);
     return 0;
+}
+
+/*
+ * Geometric multigrid on a logically structured grid (Sec. 5.3: the
+ * driven-cavity study runs PETSc's multigrid with Jacobi-preconditioned
+ * Chebyshev smoothers on every level but the coarsest, which is solved
+ * directly).  The paper fixes neither the grid transfers nor the coarse
+ * operators; the reading taken here is aggregation:
+ *  - a grid of shape (s_0, s_1, s_2) (s_0 fastest; unused dimensions 1)
+ *    coarsens to shape ceil(s_d / 2), and fine point (i_0, i_1, i_2) belongs
+ *    to the aggregate (floor(i_0/2), floor(i_1/2), floor(i_2/2));
+ *  - prolongation P is piecewise constant over the aggregates (P_iI = 1 when
+ *    i belongs to I), restriction is P^T, and the coarse operator is the
+ *    Galerkin product A_c = P^T A P.
+ * The cycle itself (smoothing, over-correction, V or W recursion, the direct
+ * coarsest solve) is composed from these functions by the Python wrapper.
+ */
+void orc_mg_coarse_shape(int32_t dim, const int32_t *shape, int32_t *cshape)
+{
+    for (int32_t d = 0; d < 3; ++d) cshape[d] = d < dim ? (shape[d] + 1) / 2 : 1;
+}
+
+/* Grid coordinates of row i (s_0 fastest). */
+static void grid_coords(int32_t dim, const int32_t *shape, int64_t i, int32_t *c)
+{
+    for (int32_t d = 0; d < 3; ++d) {
+        const int32_t s = d < dim ? shape[d] : 1;
+        c[d] = (int32_t)(i % s);
+        i /= s;
+    }
+}
+
+/* Coarse index of the aggregate that holds fine row i. */
+static int32_t aggregate_of(int32_t dim, const int32_t *shape, const int32_t *cshape, int64_t i)
+{
+    int32_t c[3];
+    grid_coords(dim, shape, i, c);
+    return (c[0] / 2) + cshape[0] * ((c[1] / 2) + cshape[1] * (c[2] / 2));
+}
+
+/*
+ * A_c = P^T A P:  (A_c)_IJ = sum of a_ij over fine i in I and j in J.
+ * Written out by definition: for each coarse row I the entries of its fine
+ * rows are accumulated (long double, rounded once) into the coarse columns
+ * they map to, with a sparse accumulator; every coarse column that receives
+ * at least one fine entry is stored, in ascending order, even if its sum is 0.
+ * The output arrays need room for nc + 1 row pointers and (at most) nnz
+ * entries.  Returns the coarse nnz, or a negative status (ORC_ENOMEM, or -1
+ * for n different from the grid's point count).
+ */
+int64_t orc_mg_galerkin(int32_t n, const int32_t *rowptr, const int32_t *col,
+                        const double *val, int32_t dim, const int32_t *shape,
+                        int32_t *crowptr, int32_t *ccol, double *cval)
+{
+    int32_t cs[3], s[3];
+    orc_mg_coarse_shape(dim, shape, cs);
+    for (int32_t d = 0; d < 3; ++d) s[d] = d < dim ? shape[d] : 1;
+    if ((int64_t)s[0] * s[1] * s[2] != n) return -1;
+    const int32_t nc = cs[0] * cs[1] * cs[2];
+    long double *acc = (long double *)malloc(sizeof(long double) * (size_t)(nc > 0 ? nc : 1));
+    int32_t *mark = (int32_t *)malloc(sizeof(int32_t) * (size_t)(nc > 0 ? nc : 1));
+    int32_t *list = (int32_t *)malloc(sizeof(int32_t) * (size_t)(nc > 0 ? nc : 1));
+    if (!acc || !mark || !list) {
+        free(acc); free(mark); free(list);
+        return ORC_ENOMEM;
+    }
+    for (int32_t J = 0; J < nc; ++J) mark[J] = -1;
+    int64_t nnz_c = 0;
+    crowptr[0] = 0;
+    for (int32_t I = 0; I < nc; ++I) {
+        int32_t c[3];
+        grid_coords(dim, cs, I, c);
+        int32_t cnt = 0;
+        /* the fine points of aggregate I: coordinates 2c_d and 2c_d + 1 where
+         * they exist */
+        for (int32_t a2 = 0; a2 < 2; ++a2)
+            for (int32_t a1 = 0; a1 < 2; ++a1)
+                for (int32_t a0 = 0; a0 < 2; ++a0) {
+                    const int32_t f0 = 2 * c[0] + a0, f1 = 2 * c[1] + a1, f2 = 2 * c[2] + a2;
+                    if (f0 >= s[0] || f1 >= s[1] || f2 >= s[2]) continue;
+                    const int32_t i = f0 + s[0] * (f1 + s[1] * f2);
+                    for (int32_t k = rowptr[i]; k < rowptr[i + 1]; ++k) {
+                        const int32_t J = aggregate_of(dim, shape, cs, col[k]);
+                        if (mark[J] != I) {
+                            mark[J] = I;
+                            acc[J] = 0.0L;
+                            list[cnt++] = J;
+                        }
+                        acc[J] += (long double)val[k];
+                    }
+                }
+        for (int32_t u = 1; u < cnt; ++u) { /* insertion sort of the columns */
+            const int32_t v = list[u];
+            int32_t w = u - 1;
+            while (w >= 0 && list[w] > v) {
+                list[w + 1] = list[w];
+                --w;
+            }
+            list[w + 1] = v;
+        }
+        for (int32_t u = 0; u < cnt; ++u) {
+            ccol[nnz_c] = list[u];
+            cval[nnz_c] = (double)acc[list[u]];
+            ++nnz_c;
+        }
+        crowptr[I + 1] = (int32_t)nnz_c;
+    }
+    free(acc); free(mark); free(list);
+    return nnz_c;
+}
+
+/* Restriction b_c = P^T r: the sum of the fine values of each aggregate
+ * (long double, rounded once). */
+void orc_mg_restrict(int32_t dim, const int32_t *shape, const double *r, double *bc)
+{
+    int32_t cs[3], s[3];
+    orc_mg_coarse_shape(dim, shape, cs);
+    for (int32_t d = 0; d < 3; ++d) s[d] = d < dim ? shape[d] : 1;
+    const int32_t nc = cs[0] * cs[1] * cs[2];
+    for (int32_t I = 0; I < nc; ++I) {
+        int32_t c[3];
+        grid_coords(dim, cs, I, c);
+        long double t = 0.0L;
+        for (int32_t a2 = 0; a2 < 2; ++a2)
+            for (int32_t a1 = 0; a1 < 2; ++a1)
+                for (int32_t a0 = 0; a0 < 2; ++a0) {
+                    const int32_t f0 = 2 * c[0] + a0, f1 = 2 * c[1] + a1, f2 = 2 * c[2] + a2;
+                    if (f0 >= s[0] || f1 >= s[1] || f2 >= s[2]) continue;
+                    t += r[f0 + s[0] * (f1 + s[1] * f2)];
+                }
+        bc[I] = (double)t;
+    }
+}
+
+/* Coarse-grid correction x <- x + omega P x_c (product and sum rounded once). */
+void orc_mg_prolong(int32_t dim, const int32_t *shape, double omega, const double *xc,
+                    double *x)
+{
+    int32_t cs[3], s[3];
+    orc_mg_coarse_shape(dim, shape, cs);
+    for (int32_t d = 0; d < 3; ++d) s[d] = d < dim ? shape[d] : 1;
+    const int64_t n = (int64_t)s[0] * s[1] * s[2];
+    for (int64_t i = 0; i < n; ++i)
+        x[i] = fma(omega, xc[aggregate_of(dim, shape, cs, i)], x[i]);
 }

@@ -47,6 +47,9 @@ void orc_aypx(int32_t n, double beta, const double *x, double *y);
 int orc_diag_inv(int32_t n, const int32_t *rowptr, const int32_t *col,
                  const double *val, double *dinv);
 void orc_jacobi_apply(int32_t n, const double *dinv, const double *r, double *z);
+/* z = M^-1 r for a preconditioner M; returns 0 or a status that ends the solve. */
+typedef int (*orc_pc_fn)(void *ctx, int32_t n, const double *r, double *z);
+
 int orc_pcg(int32_t n, const int32_t *rowptr, const int32_t *col,
             const double *val, const double *b, double *x, double rtol,
             double atol, int32_t maxit, int32_t x0_nonzero, double *hist,
@@ -60,6 +63,19 @@ int orc_pcg_sr(int32_t n, const int32_t *rowptr, const int32_t *col,
                const double *val, const double *b, double *x, double rtol,
                double atol, int32_t maxit, int32_t x0_nonzero, double *hist,
                int32_t hist_len, orc_pcg_result *res);
+int orc_pcg_pc(int32_t n, const int32_t *rowptr, const int32_t *col,
+               const double *val, const double *b, double *x, double rtol,
+               double atol, int32_t maxit, int32_t x0_nonzero, orc_pc_fn pc,
+               void *pc_ctx, double *hist, int32_t hist_len, orc_pcg_result *res);
 int orc_dense_cholesky_solve(int32_t n, double *A, double *b);
+int orc_dense_cholesky_factor(int32_t n, double *A);
+void orc_dense_cholesky_subst(int32_t n, const double *L, double *b);
+void orc_mg_coarse_shape(int32_t dim, const int32_t *shape, int32_t *cshape);
+int64_t orc_mg_galerkin(int32_t n, const int32_t *rowptr, const int32_t *col,
+                        const double *val, int32_t dim, const int32_t *shape,
+                        int32_t *crowptr, int32_t *ccol, double *cval);
+void orc_mg_restrict(int32_t dim, const int32_t *shape, const double *r, double *bc);
+void orc_mg_prolong(int32_t dim, const int32_t *shape, double omega, const double *xc,
+                    double *x);
 
 #endif

@@ -57,20 +57,24 @@ class CSR:
         return np.diff(self.rowptr)
 
 
-def _stencil_csr(N: int, dim: int, offsets, weights) -> CSR:
-    """Assemble a stencil on an N**dim grid with Dirichlet elimination.
+def _stencil_csr(N, dim: int, offsets, weights) -> CSR:
+    """Assemble a stencil on an N**dim grid (or a grid of shape N = (s_x, s_y
+    [, s_z]), x fastest) with Dirichlet elimination.
 
     ``offsets`` are integer tuples (dx, dy[, dz]); ``weights[m]`` is a scalar or
     an array of length n giving the entry of row i for offset m.  Offsets are
     sorted by their linear displacement so that columns come out ascending.
     """
-    n = N ** dim
+    ext = tuple(int(v) for v in N) if hasattr(N, "__len__") else (int(N),) * dim
+    assert len(ext) == dim
+    n = int(np.prod(ext))
     if n >= 2**31:
         raise ValueError("n does not fit int32 indices")
-    lin = [sum(o[d] * N ** d for d in range(dim)) for o in offsets]
+    stride = [int(np.prod(ext[:d])) for d in range(dim)]
+    lin = [sum(o[d] * stride[d] for d in range(dim)) for o in offsets]
     order = np.argsort(lin, kind="stable")
     m = len(offsets)
-    shape = (N,) * dim  # C order: the last axis is x (fastest)
+    shape = ext[::-1]  # C order: the last axis is x (fastest)
     mask = np.empty((n, m), dtype=bool)
     cols = np.empty((n, m), dtype=np.int32)
     vals = np.empty((n, m), dtype=np.float64)
@@ -82,7 +86,7 @@ def _stencil_csr(N: int, dim: int, offsets, weights) -> CSR:
             ax = dim - 1 - d
             sl = [slice(None)] * dim
             if o[d] > 0:
-                sl[ax] = slice(N - o[d], None)
+                sl[ax] = slice(ext[d] - o[d], None)
             elif o[d] < 0:
                 sl[ax] = slice(0, -o[d])
             else:
@@ -117,6 +121,19 @@ def laplace3d7(N: int, shift: float = 0.0) -> CSR:
     offs = [(0, 0, 0), (-1, 0, 0), (1, 0, 0), (0, -1, 0), (0, 1, 0), (0, 0, -1), (0, 0, 1)]
     w = [6.0 + shift] + [-1.0] * 6
     return _stencil_csr(N, 3, offs, w)
+
+
+def laplace_grid(shape, shift: float = 0.0) -> CSR:
+    """5-point (2D) or 7-point (3D) Laplacian on a grid of the given shape
+    (x fastest): diagonal 2 dim (+shift), off-diagonal -1, Dirichlet
+    elimination as in laplace2d5 / laplace3d7."""
+    dim = len(shape)
+    offs = [tuple(0 for _ in range(dim))]
+    for d in range(dim):
+        for sgn in (-1, 1):
+            offs.append(tuple(sgn if e == d else 0 for e in range(dim)))
+    w = [2.0 * dim + shift] + [-1.0] * (2 * dim)
+    return _stencil_csr(tuple(shape), dim, offs, w)
 
 
 def _canonical_dirs27():
