@@ -297,6 +297,87 @@ int spk_mat_mult_multi(const spk_mat *A, int32_t k, const double *X, double *Y, 
 int spk_ksp_solve_multi(spk_mat *A, int32_t k, const double *B, double *X,
                         const spk_ksp_opts *opts, spk_ksp_result *res, void *stream);
 
+/* ---------------------------------------------------------------- multigrid
+ * Geometric multigrid on a logically structured grid, as the preconditioner
+ * of CG (Sec. 5.3: the driven-cavity study runs multigrid with
+ * Jacobi-preconditioned Chebyshev smoothers on every level but the coarsest,
+ * which is solved directly, in V- and W-cycles).  The paper fixes neither the
+ * grid transfers nor the coarse operators; this library takes aggregation:
+ *  - rows are grid points numbered with the first dimension fastest; a grid
+ *    of extents (s_0, s_1, s_2) coarsens to ceil(s_d / 2), fine point
+ *    (i_0, i_1, i_2) belonging to coarse point (i_0/2, i_1/2, i_2/2);
+ *  - prolongation P is piecewise constant over these aggregates, restriction
+ *    is P^T, and the coarse matrix is the Galerkin product P^T A P, formed on
+ *    the device (the matrix may only couple points at most one grid step
+ *    apart in each direction: 3/5/7/9/27-point stencils);
+ *  - levels are added while the coarsest has more than coarse_max rows; the
+ *    coarsest (at most 4096 rows) is inverted densely at setup and solved by
+ *    one matrix-vector product.
+ * One cycle on level l for b_l from x_l (zero unless stated):
+ *   smooth_steps Chebyshev steps (spk_pc_chebyshev's recurrence on
+ *   [emin_frac g_l, g_l], g_l the Gershgorin bound of D^-1 A_l);
+ *   b_{l+1} = P^T (b_l - A_l x_l); x_{l+1} = cycle on level l+1 (a W-cycle
+ *   runs it twice, the second from the first's result, except on the
+ *   directly solved level); x_l += omega P x_{l+1}; smooth_steps Chebyshev
+ *   steps from x_l.
+ * The cycle is symmetric positive definite for every omega > 0, so CG may
+ * use it; omega = 2 offsets the factor 2 by which piecewise-constant
+ * prolongation underestimates the coarse correction of smooth errors.
+ */
+typedef struct spk_mg spk_mg;
+
+typedef struct {
+    int32_t max_levels;    /* levels including the finest, 1..16 (default 16) */
+    int32_t coarse_max;    /* coarsen while a level has more rows, 1..4096 (default 1000) */
+    int32_t smooth_steps;  /* Chebyshev steps before and after the coarse correction, 0..64 (default 2) */
+    int32_t cycle;         /* 1: V-cycle (default), 2: W-cycle */
+    double emin_frac;      /* smoother interval [emin_frac g, g], in (0, 1) (default 0.1) */
+    double omega;          /* coarse-grid correction x += omega P x_c, > 0 (default 2.0) */
+} spk_mg_opts;
+
+void spk_mg_opts_default(spk_mg_opts *o);
+
+typedef struct {
+    int32_t levels;
+    int32_t pad_;
+    int32_t n[16];          /* rows per level (0: finest) */
+    int64_t nnz[16];
+    int32_t shape[16][3];   /* grid extents per level (unused dimensions 1) */
+    int32_t kernel[16];     /* SPK_KERNEL_* of each level's SpMV */
+    double emax[16];        /* smoother interval [emin_frac emax, emax] per level */
+    int64_t device_bytes;   /* library-owned device memory of the hierarchy */
+} spk_mg_info;
+
+/* Builds the hierarchy for A on a grid of `dim` (1..3) extents shape[0..dim-1]
+ * whose product is A's row count.  A stays the caller's: it must outlive the
+ * hierarchy and keep its values.  opts NULL takes the defaults.  Errors:
+ * SPK_EINVAL (bad grid or options, a coupling beyond one grid step, a
+ * coarsest level above 4096 rows, a coarsest matrix that is not positive
+ * definite), SPK_EZERODIAG, SPK_ENOMEM / SPK_EHIP.  Synchronises `stream`. */
+int spk_mg_create(const spk_mat *A, int32_t dim, const int32_t *shape, const spk_mg_opts *opts,
+                  void *stream, spk_mg **out);
+int spk_mg_get_info(const spk_mg *M, spk_mg_info *info);
+/* Host copies of level `level`'s CSR arrays (n + 1, nnz and nnz entries from
+ * spk_mg_get_info); synchronises the device. */
+int spk_mg_copy_level(const spk_mg *M, int32_t level, int32_t *rowptr, int32_t *col, double *val);
+/* x = one cycle from zero for right-hand side b (device double[n], not
+ * overlapping).  Queued on `stream`; uses the hierarchy's vectors, so calls
+ * on one hierarchy must not overlap. */
+int spk_mg_apply(spk_mg *M, const double *b, double *x, void *stream);
+/* The same cycle `reps` times with events around each level's own kernels:
+ * level_ms[l] (host double[levels]) receives the mean milliseconds per cycle
+ * spent on level l (the per-level breakdown of the driven-cavity study).
+ * Synchronises `stream`. */
+int spk_mg_profile(spk_mg *M, const double *b, double *x, int32_t reps, double *level_ms, void *stream);
+/* CG preconditioned by one cycle per iteration, FP64, with the stopping
+ * rules, breakdown reasons, true-residual restarts and history of
+ * spk_ksp_solve (precision must be SPK_PREC_FP64 and single_reduction 0).
+ * graph_k iterations are captured per graph (0: no graph).  b, x: device
+ * double[n] as in spk_ksp_solve.  Returns when the result is known. */
+int spk_ksp_solve_mg(spk_mg *M, const double *b, double *x, const spk_ksp_opts *opts,
+                     spk_ksp_result *res, void *stream);
+int spk_mg_destroy(spk_mg *M);
+
 /* ---------------------------------------------------------------- server
  * Continuous-batching solve server (Response A6: many different-size
  * problems solved simultaneously on the GPU).  Requests are admitted while

@@ -18,7 +18,13 @@ struct ChebStep {
     double *x;
     const double *dinv;
     double c1, c2;
+    const SysState *gate = nullptr;  // inside a captured solve: run only while it iterates
 };
+
+__device__ __forceinline__ bool cheb_go(const SysState *gate)
+{
+    return !gate || gate_open(gate, kGateInner64);
+}
 
 __device__ __forceinline__ void cheb_row(const ChebStep &c, int i, double y)
 {
@@ -34,7 +40,7 @@ __global__ __launch_bounds__(kBlock) void k_cheb_sell(int n, SellView sv, const 
                                                       ChebStep c)
 {
     sell_slices<double, CI, U>(n, blockIdx.x * (kBlock / kWave) + (int)threadIdx.x / kWave,
-                               gridDim.x * (kBlock / kWave), sv, val, c.dk, [] { return true; },
+                               gridDim.x * (kBlock / kWave), sv, val, c.dk, [&] { return cheb_go(c.gate); },
                                [&](int i, double y) { cheb_row(c, i, y); });
 }
 
@@ -44,6 +50,7 @@ static __global__ __launch_bounds__(kBlock) void k_cheb_stream(int n, int R, int
                                                                const double *__restrict__ val,
                                                                ChebStep c)
 {
+    if (!cheb_go(c.gate)) return;
     __shared__ TileLds<double> sm;
     const int j = xcd_remap(blockIdx.x, nblk);
     int t0, t1;
@@ -59,6 +66,7 @@ static __global__ __launch_bounds__(kBlock) void k_cheb_stream(int n, int R, int
 // Other families: y = A d_k was written by the standalone SpMV.
 static __global__ void k_cheb_update(int n, const double *__restrict__ y, ChebStep c)
 {
+    if (!cheb_go(c.gate)) return;
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
         cheb_row(c, i, y[i]);
 }
@@ -68,8 +76,9 @@ static __global__ void k_cheb_update(int n, const double *__restrict__ y, ChebSt
 static __global__ void k_cheb_init(int n, const double *__restrict__ b, const double *__restrict__ ax,
                                    double *__restrict__ x, double *__restrict__ r,
                                    double *__restrict__ d0, const double *__restrict__ dinv,
-                                   double inv_theta)
+                                   double inv_theta, const SysState *gate)
 {
+    if (!cheb_go(gate)) return;
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
         double ri;
         if (ax) ri = b[i] - ax[i];
@@ -83,8 +92,10 @@ static __global__ void k_cheb_init(int n, const double *__restrict__ b, const do
 }
 
 // The last step without a residual: x += d.
-static __global__ void k_cheb_last(int n, const double *__restrict__ d, double *__restrict__ x)
+static __global__ void k_cheb_last(int n, const double *__restrict__ d, double *__restrict__ x,
+                                   const SysState *gate)
 {
+    if (!cheb_go(gate)) return;
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
         x[i] = x[i] + d[i];
 }

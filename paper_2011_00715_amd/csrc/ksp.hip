@@ -556,7 +556,7 @@ static int grid_n(int64_t n)
 
 // One Chebyshev step: fused SpMV + update for the SELL and stream families,
 // SpMV into tmp then the update pass for the others.
-static int cheb_step(spk_mat *A, const ChebStep &c, double *tmp, hipStream_t s)
+int cheb_step(spk_mat *A, const ChebStep &c, double *tmp, hipStream_t s)
 {
     const dim3 g(A->nblk), t(kBlock);
     if (A->kernel == SPK_KERNEL_SELL) {
@@ -574,7 +574,7 @@ static int cheb_step(spk_mat *A, const ChebStep &c, double *tmp, hipStream_t s)
         hipLaunchKernelGGL(k_cheb_stream, g, t, 0, s, A->n, A->R, A->ntiles, A->nblk, A->rowptr, A->col,
                            (const double *)A->val, c);
     } else {
-        SPK_TRY(launch_spmv<double>(A, A->val, c.dk, tmp, s, nullptr, kGateNone));
+        SPK_TRY(launch_spmv<double>(A, A->val, c.dk, tmp, s, c.gate, c.gate ? kGateInner64 : kGateNone));
         hipLaunchKernelGGL(k_cheb_update, dim3(grid_n(A->n)), t, 0, s, A->n, (const double *)tmp, c);
     }
     SPK_HIP(hipGetLastError());
@@ -621,14 +621,14 @@ int spk_pc_chebyshev(const spk_mat *Ac, const double *b, double *x, double *r_ou
     if (x0_nonzero) SPK_TRY(launch_spmv<double>(A, A->val, x, tmp, s, nullptr, kGateNone));
     hipLaunchKernelGGL(k_cheb_init, dim3(grid_n(n)), dim3(kBlock), 0, s, (int)n, b,
                        x0_nonzero ? (const double *)tmp : nullptr, x, r, dbuf[0], (const double *)A->dinv,
-                       1.0 / theta);
+                       1.0 / theta, nullptr);
     SPK_HIP(hipGetLastError());
     double rho = 1.0 / sigma;
     for (int k = 0; k < steps; ++k) {
         const bool last = k == steps - 1;
         if (last && !r_out) {  // the residual is not wanted: skip the last SpMV
             hipLaunchKernelGGL(k_cheb_last, dim3(grid_n(n)), dim3(kBlock), 0, s, (int)n,
-                               (const double *)dbuf[k & 1], x);
+                               (const double *)dbuf[k & 1], x, nullptr);
             SPK_HIP(hipGetLastError());
             break;
         }

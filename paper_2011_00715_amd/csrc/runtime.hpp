@@ -110,5 +110,8 @@ constexpr double kRuDelta = 0.05;  // default refinement trigger with reliable u
 double inner_rtol_of(const spk_ksp_opts &o);
 int ensure_f32(spk_mat *A, hipStream_t s);
 void free_multi(spk_mat *A);
+struct ChebStep;
+// One Chebyshev smoothing step on A (fused with its SpMV where the family allows).
+int cheb_step(spk_mat *A, const ChebStep &c, double *tmp, hipStream_t s);
 
 }  // namespace spk

@@ -86,6 +86,21 @@ class ServerOpts(ctypes.Structure):
     ]
 
 
+class MgOpts(ctypes.Structure):
+    _fields_ = [
+        ("max_levels", i32), ("coarse_max", i32), ("smooth_steps", i32), ("cycle", i32),
+        ("emin_frac", dbl), ("omega", dbl),
+    ]
+
+
+class MgInfo(ctypes.Structure):
+    _fields_ = [
+        ("levels", i32), ("pad_", i32), ("n", i32 * 16), ("nnz", i64 * 16),
+        ("shape", (i32 * 3) * 16), ("kernel", i32 * 16), ("emax", dbl * 16),
+        ("device_bytes", i64),
+    ]
+
+
 def _sig(name, res, args):
     f = getattr(_lib, name)
     f.restype = res
@@ -113,6 +128,14 @@ _sig("spk_ksp_solve", ctypes.c_int, [P, P, P, ctypes.POINTER(KspOpts),
 _sig("spk_mat_mult_multi", ctypes.c_int, [P, i32, P, P, P])
 _sig("spk_ksp_solve_multi", ctypes.c_int, [P, i32, P, P, ctypes.POINTER(KspOpts),
                                            ctypes.POINTER(KspResult), P])
+_sig("spk_mg_opts_default", None, [ctypes.POINTER(MgOpts)])
+_sig("spk_mg_create", ctypes.c_int, [P, i32, P, ctypes.POINTER(MgOpts), P, ctypes.POINTER(P)])
+_sig("spk_mg_get_info", ctypes.c_int, [P, ctypes.POINTER(MgInfo)])
+_sig("spk_mg_copy_level", ctypes.c_int, [P, i32, P, P, P])
+_sig("spk_mg_apply", ctypes.c_int, [P, P, P, P])
+_sig("spk_mg_profile", ctypes.c_int, [P, P, P, i32, P, P])
+_sig("spk_ksp_solve_mg", ctypes.c_int, [P, P, P, ctypes.POINTER(KspOpts), ctypes.POINTER(KspResult), P])
+_sig("spk_mg_destroy", ctypes.c_int, [P])
 _sig("spk_server_opts_default", None, [ctypes.POINTER(ServerOpts)])
 _sig("spk_server_create", ctypes.c_int, [ctypes.POINTER(ServerOpts), P, ctypes.POINTER(P)])
 _sig("spk_server_submit", ctypes.c_int, [P, i32, i64, P, P, P, P, ctypes.POINTER(KspOpts),
@@ -134,7 +157,9 @@ EXPORTS = [
     "spk_mat_create_csr", "spk_mat_set_kernel", "spk_mat_mult", "spk_mat_mult_f32",
     "spk_mat_get_info", "spk_pc_jacobi_apply", "spk_pc_chebyshev", "spk_mat_destroy", "spk_vec_axpy",
     "spk_vec_aypx", "spk_vec_dot", "spk_vec_dot2", "spk_vec_nrm2", "spk_ksp_opts_default",
-    "spk_ksp_solve", "spk_mat_mult_multi", "spk_ksp_solve_multi", "spk_server_opts_default", "spk_server_create", "spk_server_submit",
+    "spk_ksp_solve", "spk_mat_mult_multi", "spk_ksp_solve_multi", "spk_mg_opts_default",
+    "spk_mg_create", "spk_mg_get_info", "spk_mg_copy_level", "spk_mg_apply", "spk_mg_profile",
+    "spk_ksp_solve_mg", "spk_mg_destroy", "spk_server_opts_default", "spk_server_create", "spk_server_submit",
     "spk_server_progress", "spk_server_poll", "spk_server_completed", "spk_server_destroy", "spk_status_str",
     "spk_reason_str", "spk_last_error", "spk_now", "spk_runtime_version", "spk_bw_copy",
     "spk_cache_flush",
@@ -392,6 +417,112 @@ def ksp_solve(A: Mat, b, x, opts: KspOpts | None = None, hist=None, stream=None)
                               _dev(x, torch.float64, A.n, "x"), ctypes.byref(o),
                               ctypes.byref(res), _stream(stream)), "spk_ksp_solve")
     return res
+
+
+# ------------------------------------------------------------------ multigrid
+def mg_opts_default() -> MgOpts:
+    o = MgOpts()
+    _lib.spk_mg_opts_default(ctypes.byref(o))
+    return o
+
+
+def mg_opts(**kw) -> MgOpts:
+    o = mg_opts_default()
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise AttributeError(k)
+        setattr(o, k, v)
+    return o
+
+
+class Mg:
+    """Owns an spk_mg hierarchy; keeps the finest matrix alive with it."""
+
+    def __init__(self, handle: int, A: Mat):
+        self.handle = P(handle)
+        self.A = A
+        self.info = mg_get_info(self)
+        self.levels = self.info.levels
+
+    def close(self):
+        if self.handle:
+            _lib.spk_mg_destroy(self.handle)
+            self.handle = P()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+
+def mg_create(A: Mat, shape, opts: MgOpts | None = None, stream=None) -> Mg:
+    """Multigrid hierarchy of A on a grid of the given extents (first fastest)."""
+    sh = (i32 * 3)(*[int(v) for v in shape], *([1] * (3 - len(shape))))
+    out = P()
+    _check(_lib.spk_mg_create(A.handle, len(shape), sh, ctypes.byref(opts) if opts is not None else None,
+                              _stream(stream), ctypes.byref(out)), "spk_mg_create")
+    return Mg(out.value, A)
+
+
+def mg_get_info(M: Mg) -> MgInfo:
+    info = MgInfo()
+    _check(_lib.spk_mg_get_info(M.handle, ctypes.byref(info)), "spk_mg_get_info")
+    return info
+
+
+def mg_copy_level(M: Mg, level: int):
+    """(rowptr, col, val) NumPy copies of one level's matrix."""
+    import numpy as np
+
+    n, nnz = M.info.n[level], M.info.nnz[level]
+    rp = np.empty(n + 1, dtype=np.int32)
+    ci = np.empty(max(nnz, 1), dtype=np.int32)
+    va = np.empty(max(nnz, 1), dtype=np.float64)
+    _check(_lib.spk_mg_copy_level(M.handle, level, P(rp.ctypes.data), P(ci.ctypes.data), P(va.ctypes.data)),
+           "spk_mg_copy_level")
+    return rp, ci[:nnz], va[:nnz]
+
+
+def mg_apply(M: Mg, b: torch.Tensor, x: torch.Tensor, stream=None):
+    n = M.info.n[0]
+    _check(_lib.spk_mg_apply(M.handle, _dev(b, torch.float64, n, "b"), _dev(x, torch.float64, n, "x"),
+                             _stream(stream)), "spk_mg_apply")
+
+
+def mg_profile(M: Mg, b: torch.Tensor, x: torch.Tensor, reps: int = 10, stream=None) -> list:
+    """Mean milliseconds per cycle spent on each level's own kernels."""
+    n = M.info.n[0]
+    ms = (dbl * 16)()
+    _check(_lib.spk_mg_profile(M.handle, _dev(b, torch.float64, n, "b"), _dev(x, torch.float64, n, "x"),
+                               int(reps), ms, _stream(stream)), "spk_mg_profile")
+    return [ms[l] for l in range(M.levels)]
+
+
+def ksp_solve_mg(M: Mg, b, x, opts: KspOpts | None = None, hist=None, stream=None) -> KspResult:
+    """CG preconditioned by one multigrid cycle per iteration."""
+    n = M.info.n[0]
+    o = opts if opts is not None else ksp_opts_default()
+    if hist is not None:
+        import numpy as np
+
+        assert hist.dtype == np.float64 and hist.flags.c_contiguous
+        o.hist = hist.ctypes.data_as(ctypes.POINTER(dbl))
+        o.hist_len = hist.size
+    res = KspResult()
+    _check(_lib.spk_ksp_solve_mg(M.handle, _dev(b, torch.float64, n, "b"), _dev(x, torch.float64, n, "x"),
+                                 ctypes.byref(o), ctypes.byref(res), _stream(stream)), "spk_ksp_solve_mg")
+    return res
+
+
+def mg_destroy(M: Mg):
+    M.close()
 
 
 # ------------------------------------------------------------------ server

@@ -64,3 +64,21 @@ def test_host_side_validation_without_gpu(lib):
     # the smoother rejects a NULL handle before touching the device
     assert spk._lib.spk_pc_chebyshev(None, None, None, None, 2, 0.0, 0.0, 0, None) == spk.EINVAL
     assert "NULL" in spk.last_error()
+
+
+def test_multigrid_host_validation_without_gpu(lib):
+    from paper_2011_00715_amd import spk
+
+    o = spk.mg_opts_default()
+    assert (o.max_levels, o.coarse_max, o.smooth_steps, o.cycle, o.emin_frac, o.omega) == (16, 1000, 2, 1, 0.1, 2.0)
+    assert ctypes.sizeof(spk.MgInfo) == 592
+    out = ctypes.c_void_p()
+    shape = (ctypes.c_int32 * 3)(4, 4, 1)
+    assert spk._lib.spk_mg_create(None, 2, shape, None, None, ctypes.byref(out)) == spk.EINVAL
+    assert "NULL" in spk.last_error() and not out.value
+    info = spk.MgInfo()
+    assert spk._lib.spk_mg_get_info(None, ctypes.byref(info)) == spk.EINVAL
+    res = spk.KspResult()
+    assert spk._lib.spk_ksp_solve_mg(None, None, None, None, ctypes.byref(res), None) == spk.EINVAL
+    assert spk._lib.spk_mg_apply(None, None, None, None) == spk.EINVAL
+    assert spk._lib.spk_mg_destroy(None) == spk.OK
