@@ -198,3 +198,35 @@ def test_c2_single_reduction_chebyshev_and_multi():
         bj = B[:, j].copy()
         assert res[j].reason == spk.CONVERGED_RTOL
         assert oracle.nrm2(bj - oracle.spmv(A, X[:, j].copy())) <= 1e-8 * oracle.nrm2(bj) * (1 + 1e-6)
+
+
+def test_c2_multigrid_pcg():
+    """The bench's multigrid leg at full size: every coarse level bit-exact
+    against the oracle's Galerkin products (integer Laplacian), one V-cycle
+    against the oracle's cycle, and the V-cycle PCG solve (iterations within
+    one of the oracle's, the oracle's true residual of the GPU solution)."""
+    spk = need_gpu()
+    import torch
+
+    A = spkgen.laplace3d7(128)
+    M = mat_on_gpu(spk, A)
+    G = spk.mg_create(M, (128, 128, 128))
+    h = oracle.mg_setup(A, (128, 128, 128))
+    assert [G.info.n[l] for l in range(G.levels)] == [m.n for m in h.mats] == [128**3, 64**3, 32**3, 16**3, 8**3]
+    for l in range(1, G.levels):
+        rp, ci, va = spk.mg_copy_level(G, l)
+        assert np.array_equal(rp, h.mats[l].rowptr) and np.array_equal(ci, h.mats[l].col)
+        assert np.array_equal(va, h.mats[l].val)
+    b = spkgen.rhs_uniform(A.n, 0)
+    x = torch.zeros(A.n, dtype=torch.float64, device="cuda")
+    spk.mg_apply(G, to_dev(b), x)
+    xc = oracle.mg_cycle(h, b)
+    assert np.max(np.abs(x.cpu().numpy() - xc)) <= 1e-11 * np.max(np.abs(xc))
+    x.zero_()
+    res = spk.ksp_solve_mg(G, to_dev(b), x, spk.ksp_opts(graph_k=1))
+    xo, ro, _ = oracle.pcg_mg(A, h, b)
+    assert res.reason == spk.CONVERGED_RTOL and abs(res.iterations - ro["iterations"]) <= 1
+    xg = x.cpu().numpy()
+    bn = oracle.nrm2(b)
+    assert oracle.nrm2(b - oracle.spmv(A, xg)) <= 1e-8 * bn * (1 + 1e-6)
+    assert np.linalg.norm(xg - xo) <= 1e-5 * np.linalg.norm(xo)
