@@ -15,7 +15,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libspk.so")
 OBJDIR = os.path.join(HERE, "_build")
-SOURCES = ["mat.hip", "ksp.hip", "server.hip", "multi.hip", "mg.hip"]
+SOURCES = ["mat.hip", "ksp.hip", "server.hip", "multi.hip", "mg.hip", "xslice.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

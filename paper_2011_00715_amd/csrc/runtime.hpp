@@ -92,6 +92,13 @@ struct spk_mat {
     uint8_t *sell_len = nullptr;
     double *sell_val = nullptr;
     float *sell_val32 = nullptr;
+    // column-sliced copy (built when the SLICED family is selected): rows
+    // s*n + i hold row i's entries with columns in the s-th eighth of [0, n)
+    int32_t *xs_ptr = nullptr;   // 8n + 1 row pointers
+    int32_t *xs_col = nullptr;
+    double *xs_val = nullptr;
+    float *xs_val32 = nullptr;
+    void *xs_part = nullptr;     // 8n partial products (FP64 or FP32)
     spk::Workspace *ws = nullptr;
     spk::MultiWs *mws = nullptr;  // multi-right-hand-side solver workspace
     int64_t bytes = 0;
@@ -110,6 +117,14 @@ constexpr double kRuDelta = 0.05;  // default refinement trigger with reliable u
 double inner_rtol_of(const spk_ksp_opts &o);
 int ensure_f32(spk_mat *A, hipStream_t s);
 void free_multi(spk_mat *A);
+// column-sliced layout (xslice.hip)
+bool sliced_fits(const spk_mat *A);
+int sliced_lanes(const spk_mat *A);
+int setup_sliced(spk_mat *A, hipStream_t s);
+void free_sliced(spk_mat *A);
+int ensure_sliced_f32(spk_mat *A, hipStream_t s);
+template <class V>
+int launch_sliced(const spk_mat *A, const V *x, V *y, hipStream_t s, const SysState *gst, int gmode);
 struct ChebStep;
 // One Chebyshev smoothing step on A (fused with its SpMV where the family allows).
 int cheb_step(spk_mat *A, const ChebStep &c, double *tmp, hipStream_t s);

@@ -35,8 +35,8 @@ dbl = ctypes.c_double
 MEM_HOST, MEM_DEVICE = 0, 1
 PREC_FP64, PREC_MIXED, PREC_MIXED_IR = 0, 1, 2
 MAT_MIXED, MAT_VALIDATE, MAT_BORROW = 1, 2, 4
-KERNEL_AUTO, KERNEL_STREAM, KERNEL_VECTOR, KERNEL_MERGE, KERNEL_SELL = 0, 1, 2, 3, 4
-KERNEL_NAMES = {1: "stream", 2: "vector", 3: "merge", 4: "sell"}
+KERNEL_AUTO, KERNEL_STREAM, KERNEL_VECTOR, KERNEL_MERGE, KERNEL_SELL, KERNEL_SLICED = 0, 1, 2, 3, 4, 5
+KERNEL_NAMES = {1: "stream", 2: "vector", 3: "merge", 4: "sell", 5: "sliced"}
 OK, EINVAL, ENOMEM, EHIP, EZERODIAG, EBUSY, EBUDGET, ENOTFOUND = 0, -1, -2, -3, -4, -5, -6, -7
 CONVERGED_RTOL, CONVERGED_ATOL = 1, 2
 DIVERGED_ITS, DIVERGED_INDEFINITE_MAT, DIVERGED_INDEFINITE_PC = -1, -2, -3

@@ -109,23 +109,30 @@ def test_c4_powerlaw_spmv_all_kernels():
     A = spkgen.powerlaw_spd(4_000_000, seed=0)
     M = mat_on_gpu(spk, A, flags=spk.MAT_MIXED)
     assert spk.KERNEL_NAMES[M.info.kernel] == "merge"
+    spk.mat_set_kernel(M, spk.KERNEL_SLICED, 0)
+    assert M.info.lanes == 4
     assert M.info.row_max == A.row_lengths().max()
     rows = _sample_rows(A.n, 2)
     x = spkgen.rhs_uniform(A.n, 0)
     _spmv_sampled(spk, M, A, x, rows)  # the selected kernel meets 1e-14
-    for k, p, tol in ((spk.KERNEL_VECTOR, 32, 1e-14), (spk.KERNEL_VECTOR, 64, 1e-14)):
-        spk.mat_set_kernel(M, k, p)
-        _spmv_sampled(spk, M, A, x, rows, tol)
-    # FP32 values: per-row bound of the merge order in FP32
-    spk.mat_set_kernel(M, spk.KERNEL_MERGE, 0)
     x32 = x.astype(np.float32)
-    y32 = torch.empty(A.n, dtype=torch.float32, device="cuda")
-    spk.mat_mult_f32(M, to_dev(x32), y32)
     v32 = A.val.astype(np.float32)
     Af = spkgen.CSR(A.n, A.rowptr, A.col, v32.astype(np.float64))
-    yo, ya = oracle.spmv_rows(Af, x32.astype(np.float64), rows)
-    err = np.abs(y32.cpu().numpy()[rows].astype(np.float64) - yo)
-    assert np.all(err <= 30 * 2.0 ** -24 * ya)
+    yo32, ya32 = oracle.spmv_rows(Af, x32.astype(np.float64), rows)
+
+    def check_f32():  # per-row bound of the merge / sliced orders in FP32
+        y32 = torch.empty(A.n, dtype=torch.float32, device="cuda")
+        spk.mat_mult_f32(M, to_dev(x32), y32)
+        err = np.abs(y32.cpu().numpy()[rows].astype(np.float64) - yo32)
+        assert np.all(err <= 30 * 2.0 ** -24 * ya32), spk.KERNEL_NAMES[M.info.kernel]
+
+    check_f32()
+    for k, p, tol in ((spk.KERNEL_MERGE, 0, 1e-14), (spk.KERNEL_VECTOR, 32, 1e-14),
+                      (spk.KERNEL_VECTOR, 64, 1e-14), (spk.KERNEL_SLICED, 2, 1e-14)):
+        spk.mat_set_kernel(M, k, p)
+        _spmv_sampled(spk, M, A, x, rows, tol)
+    spk.mat_set_kernel(M, spk.KERNEL_MERGE, 0)
+    check_f32()
 
 
 def test_c5_served_requests_full_sizes():

@@ -12,14 +12,14 @@ from gpu_util import U32, U64, check_spmv, mat_on_gpu, need_gpu, spmv_bound_rows
 pytestmark = pytest.mark.gpu
 
 KERNELS = [("auto", 0), ("stream", 0), ("stream", 64), ("stream", 8), ("merge", 0), ("sell", 0),
-           ("sell", 32)] + [("vector", L) for L in (1, 2, 4, 8, 16, 32, 64)]
+           ("sell", 32), ("sliced", 0), ("sliced", 1), ("sliced", 16)] + [("vector", L) for L in (1, 2, 4, 8, 16, 32, 64)]
 
 
 def _set(spk, M, kernel, param):
     if kernel == "auto":
         return spk.KERNEL_NAMES[M.info.kernel], M.info.lanes
     k = {"stream": spk.KERNEL_STREAM, "vector": spk.KERNEL_VECTOR, "merge": spk.KERNEL_MERGE,
-         "sell": spk.KERNEL_SELL}[kernel]
+         "sell": spk.KERNEL_SELL, "sliced": spk.KERNEL_SLICED}[kernel]
     if kernel == "sell" and M.info.row_max > 255:
         # SELL stores row lengths in one byte: the library refuses such rows
         with pytest.raises(spk.SpkError, match="255"):
@@ -71,7 +71,7 @@ def test_spmv_parity_fp64(kernel, param):
 
 
 @pytest.mark.parametrize("kernel,param", [("auto", 0), ("stream", 0), ("merge", 0), ("vector", 4),
-                                          ("vector", 64), ("sell", 0)])
+                                          ("vector", 64), ("sell", 0), ("sliced", 0)])
 def test_spmv_parity_fp32(kernel, param):
     spk = need_gpu()
     for name, A, integer in _matrices():
@@ -117,7 +117,7 @@ def test_spmv_degenerate_sizes():
     spk.mat_mult(M0, e, e.clone())
     # all rows empty
     Z = spkgen.CSR(1000, np.zeros(1001, np.int32), np.zeros(0, np.int32), np.zeros(0))
-    for k in (spk.KERNEL_STREAM, spk.KERNEL_MERGE, spk.KERNEL_VECTOR, spk.KERNEL_SELL):
+    for k in (spk.KERNEL_STREAM, spk.KERNEL_MERGE, spk.KERNEL_VECTOR, spk.KERNEL_SELL, spk.KERNEL_SLICED):
         MZ = mat_on_gpu(spk, Z)
         spk.mat_set_kernel(MZ, k, 8 if k == spk.KERNEL_VECTOR else 0)
         y = torch.full((1000,), 5.0, dtype=torch.float64, device="cuda")
@@ -285,3 +285,60 @@ def test_jacobi_and_vector_kernels():
     xi = np.random.default_rng(3).integers(-1000, 1000, size=n).astype(np.float64)
     spk.vec_dot(to_dev(xi), to_dev(xi), res)
     assert res[0].item() == oracle.dot(xi, xi)
+
+
+@pytest.mark.parametrize("case", ["even_rows", "powerlaw"])
+def test_sliced_selection_solves_and_fp32(case):
+    """Scattered-column matrices whose x (4.8 MB) exceeds one XCD's L2: with
+    even row lengths (16 uniform picks per row, symmetrised) the
+    column-sliced family is selected, with power-law rows merge path stays
+    and the sliced family is forced; FP64 and FP32 products meet their
+    bounds, a one-lane launch is bit-exact on integers, and FP64 / mixed
+    Jacobi-PCG solves with it match the oracle's counts."""
+    spk = need_gpu()
+    import torch
+
+    if case == "even_rows":
+        A = spkgen.powerlaw_spd(600_000, seed=5, lo=16, hi=16)
+    else:
+        A = spkgen.powerlaw_spd(600_000, seed=5)
+    M = mat_on_gpu(spk, A, flags=spk.MAT_MIXED)
+    if case == "even_rows":
+        assert spk.KERNEL_NAMES[M.info.kernel] == "sliced" and M.info.lanes == 4
+    else:
+        assert spk.KERNEL_NAMES[M.info.kernel] == "merge"
+        spk.mat_set_kernel(M, spk.KERNEL_SLICED, 0)
+        assert M.info.lanes == 4
+    x = spkgen.rhs_uniform(A.n, 1)
+    y = torch.empty(A.n, dtype=torch.float64, device="cuda")
+    spk.mat_mult(M, to_dev(x), y)
+    scale = oracle.spmv_abs(A, x)
+    check_spmv(y.cpu().numpy(), oracle.spmv(A, x), scale, 1e-14, "sliced fp64")
+    x32 = x.astype(np.float32)
+    y32 = torch.empty(A.n, dtype=torch.float32, device="cuda")
+    spk.mat_mult_f32(M, to_dev(x32), y32)
+    v32 = A.val.astype(np.float32)
+    Af = spkgen.CSR(A.n, A.rowptr, A.col, v32.astype(np.float64))
+    bound = spmv_bound_rows(A, "sliced", 4, U32) + U32
+    check_spmv(y32.cpu().numpy().astype(np.float64), oracle.spmv_f32(A, x32, val32=v32).astype(np.float64),
+               oracle.spmv_abs(Af, x32.astype(np.float64)), bound, "sliced fp32")
+    # integer data: exact whatever the order
+    Ai = spkgen.CSR(A.n, A.rowptr, A.col, np.round(A.val * 4))
+    Mi = mat_on_gpu(spk, Ai)
+    spk.mat_set_kernel(Mi, spk.KERNEL_SLICED, 0)
+    xi = np.random.default_rng(2).integers(-20, 20, A.n).astype(np.float64)
+    spk.mat_mult(Mi, to_dev(xi), y)
+    assert np.array_equal(y.cpu().numpy(), oracle.spmv(Ai, xi))
+    spk.mat_set_kernel(Mi, spk.KERNEL_SLICED, 1)
+    spk.mat_mult(Mi, to_dev(xi), y)
+    assert np.array_equal(y.cpu().numpy(), oracle.spmv(Ai, xi))
+    # solves on the selected family
+    b = spkgen.rhs_uniform(A.n, 0)
+    _, ro, _ = oracle.pcg(A, b)
+    for prec in (spk.PREC_FP64, spk.PREC_MIXED):
+        xs = torch.zeros(A.n, dtype=torch.float64, device="cuda")
+        res = spk.ksp_solve(M, to_dev(b), xs, spk.ksp_opts(precision=prec))
+        assert res.reason == spk.CONVERGED_RTOL
+        it = res.iterations if prec == spk.PREC_FP64 else res.inner_iterations
+        assert abs(it - ro["iterations"]) <= max(2, 0.01 * ro["iterations"])
+        assert oracle.nrm2(b - oracle.spmv(A, xs.cpu().numpy())) <= 1e-8 * oracle.nrm2(b) * (1 + 1e-6)
