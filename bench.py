@@ -286,9 +286,10 @@ def bench_c2(args):
     # geometric multigrid as the CG preconditioner (the V- and W-cycles of
     # Sec. 5.3 with Chebyshev-Jacobi smoothing), outside the timed steps
     mg = {}
-    for name, cyc in (("v_cycle", 1), ("w_cycle", 2)):
+    for name, cyc, prec in (("v_cycle", 1, spk.PREC_FP64), ("w_cycle", 2, spk.PREC_FP64),
+                            ("v_cycle_fp32", 1, spk.PREC_MIXED), ("w_cycle_fp32", 2, spk.PREC_MIXED)):
         t0 = time.perf_counter()
-        G = spk.mg_create(M, (N, N, N), spk.mg_opts(cycle=cyc))
+        G = spk.mg_create(M, (N, N, N), spk.mg_opts(cycle=cyc, precision=prec))
         torch.cuda.synchronize()
         setup_ms = (time.perf_counter() - t0) * 1e3
         xg_ = torch.zeros_like(xs)
@@ -320,11 +321,15 @@ def bench_c2(args):
         if cyc == 1:
             xv = xg_.cpu().numpy()
             mg[name]["true_rel_residual_oracle"] = oracle.nrm2(b - oracle.spmv(A, xv)) / bn
+        if prec == spk.PREC_MIXED:
+            ref = mg[name.replace("_fp32", "")]
+            mg[name]["speedup_vs_fp64_cycle"] = ref["ms_p50"] / mg[name]["ms_p50"]
         G.close()
     mg["note"] = ("CG preconditioned by one cycle per iteration: aggregation (2x2x2) transfers, "
                   "Galerkin coarse operators, 2+2 Chebyshev-Jacobi steps on [g/10, g], omega 2, "
                   "dense inverse on the coarsest level (<= 1000 rows); level_us = each level's own "
-                  "kernels per cycle (the per-level breakdown of Sec. 5.3)")
+                  "kernels per cycle (the per-level breakdown of Sec. 5.3); *_fp32: the cycle in "
+                  "FP32 (values, vectors, arithmetic) inside the FP64 CG")
 
     out = {
         "metric": "CSR SpMV HBM GB/s; PCG solves/s to rtol 1e-8, FP64 vs mixed; p50/p99 lat",

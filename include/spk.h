@@ -342,6 +342,10 @@ typedef struct {
     int32_t cycle;         /* 1: V-cycle (default), 2: W-cycle */
     double emin_frac;      /* smoother interval [emin_frac g, g], in (0, 1) (default 0.1) */
     double omega;          /* coarse-grid correction x += omega P x_c, > 0 (default 2.0) */
+    int32_t precision;     /* SPK_PREC_FP64 (default), or SPK_PREC_MIXED: the cycle in FP32
+                              (values, vectors, arithmetic; FP32 copies of every level's
+                              values are made, the caller's matrix included) inside FP64 CG */
+    int32_t pad_;
 } spk_mg_opts;
 
 void spk_mg_opts_default(spk_mg_opts *o);

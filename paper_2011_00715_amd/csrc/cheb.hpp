@@ -11,13 +11,14 @@
 
 namespace spk {
 
+template <class V>
 struct ChebStep {
-    const double *dk;  // d_k (gathered)
-    double *dn;        // d_{k+1}, or null on the last step
-    double *r;
-    double *x;
-    const double *dinv;
-    double c1, c2;
+    const V *dk;  // d_k (gathered)
+    V *dn;        // d_{k+1}, or null on the last step
+    V *r;
+    V *x;
+    const V *dinv;
+    V c1, c2;
     const SysState *gate = nullptr;  // inside a captured solve: run only while it iterates
 };
 
@@ -26,45 +27,46 @@ __device__ __forceinline__ bool cheb_go(const SysState *gate)
     return !gate || gate_open(gate, kGateInner64);
 }
 
-__device__ __forceinline__ void cheb_row(const ChebStep &c, int i, double y)
+template <class V>
+__device__ __forceinline__ void cheb_row(const ChebStep<V> &c, int i, V y)
 {
-    const double ri = c.r[i] - y;
+    const V ri = c.r[i] - y;
     c.r[i] = ri;
-    const double di = c.dk[i];
+    const V di = c.dk[i];
     c.x[i] = c.x[i] + di;
     if (c.dn) c.dn[i] = fma(c.c1, di, c.c2 * (c.dinv[i] * ri));
 }
 
-template <class CI, int U>
-__global__ __launch_bounds__(kBlock) void k_cheb_sell(int n, SellView sv, const double *__restrict__ val,
-                                                      ChebStep c)
+template <class V, class CI, int U>
+__global__ __launch_bounds__(kBlock) void k_cheb_sell(int n, SellView sv, const V *__restrict__ val,
+                                                      ChebStep<V> c)
 {
-    sell_slices<double, CI, U>(n, blockIdx.x * (kBlock / kWave) + (int)threadIdx.x / kWave,
-                               gridDim.x * (kBlock / kWave), sv, val, c.dk, [&] { return cheb_go(c.gate); },
-                               [&](int i, double y) { cheb_row(c, i, y); });
+    sell_slices<V, CI, U>(n, blockIdx.x * (kBlock / kWave) + (int)threadIdx.x / kWave,
+                          gridDim.x * (kBlock / kWave), sv, val, c.dk, [&] { return cheb_go(c.gate); },
+                          [&](int i, V y) { cheb_row(c, i, y); });
 }
 
-static __global__ __launch_bounds__(kBlock) void k_cheb_stream(int n, int R, int ntiles, int nblk,
-                                                               const int32_t *__restrict__ rowptr,
-                                                               const int32_t *__restrict__ col,
-                                                               const double *__restrict__ val,
-                                                               ChebStep c)
+template <class V>
+__global__ __launch_bounds__(kBlock) void k_cheb_stream(int n, int R, int ntiles, int nblk,
+                                                        const int32_t *__restrict__ rowptr,
+                                                        const int32_t *__restrict__ col,
+                                                        const V *__restrict__ val, ChebStep<V> c)
 {
     if (!cheb_go(c.gate)) return;
-    __shared__ TileLds<double> sm;
+    __shared__ TileLds<V> sm;
     const int j = xcd_remap(blockIdx.x, nblk);
     int t0, t1;
     block_tiles(j, nblk, ntiles, t0, t1);
     for (int t = t0; t < t1; ++t) {
         const int r0 = t * R;
         const int r1 = min(r0 + R, n);
-        stream_tile<double>(r0, r1, rowptr, col, val, c.dk, sm,
-                            [&](int i, double y) { cheb_row(c, i, y); });
+        stream_tile<V>(r0, r1, rowptr, col, val, c.dk, sm, [&](int i, V y) { cheb_row(c, i, y); });
     }
 }
 
 // Other families: y = A d_k was written by the standalone SpMV.
-static __global__ void k_cheb_update(int n, const double *__restrict__ y, ChebStep c)
+template <class V>
+__global__ void k_cheb_update(int n, const V *__restrict__ y, ChebStep<V> c)
 {
     if (!cheb_go(c.gate)) return;
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
@@ -72,19 +74,23 @@ static __global__ void k_cheb_update(int n, const double *__restrict__ y, ChebSt
 }
 
 // r = b - A x (ax holds A x; null for x = 0, which is then stored), and
-// d_0 = D^-1 r / theta.
-static __global__ void k_cheb_init(int n, const double *__restrict__ b, const double *__restrict__ ax,
-                                   double *__restrict__ x, double *__restrict__ r,
-                                   double *__restrict__ d0, const double *__restrict__ dinv,
-                                   double inv_theta, const SysState *gate)
+// d_0 = D^-1 r / theta.  B is the right-hand side's type: a double b with
+// float vectors also stores the rounded b into bcopy (the FP32 cycle of a
+// multigrid preconditioner inside FP64 CG).
+template <class V, class B>
+__global__ void k_cheb_init(int n, const B *__restrict__ b, const V *__restrict__ ax, V *__restrict__ x,
+                            V *__restrict__ r, V *__restrict__ d0, const V *__restrict__ dinv, V inv_theta,
+                            const SysState *gate, V *__restrict__ bcopy)
 {
     if (!cheb_go(gate)) return;
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-        double ri;
-        if (ax) ri = b[i] - ax[i];
+        const V bi = (V)b[i];
+        if (bcopy) bcopy[i] = bi;
+        V ri;
+        if (ax) ri = bi - ax[i];
         else {
-            ri = b[i];
-            x[i] = 0.0;
+            ri = bi;
+            x[i] = V(0);
         }
         r[i] = ri;
         d0[i] = dinv[i] * ri * inv_theta;
@@ -92,8 +98,8 @@ static __global__ void k_cheb_init(int n, const double *__restrict__ b, const do
 }
 
 // The last step without a residual: x += d.
-static __global__ void k_cheb_last(int n, const double *__restrict__ d, double *__restrict__ x,
-                                   const SysState *gate)
+template <class V>
+__global__ void k_cheb_last(int n, const V *__restrict__ d, V *__restrict__ x, const SysState *gate)
 {
     if (!cheb_go(gate)) return;
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)

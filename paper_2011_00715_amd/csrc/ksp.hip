@@ -555,31 +555,40 @@ static int grid_n(int64_t n)
 }
 
 // One Chebyshev step: fused SpMV + update for the SELL and stream families,
-// SpMV into tmp then the update pass for the others.
-int cheb_step(spk_mat *A, const ChebStep &c, double *tmp, hipStream_t s)
+// SpMV into tmp then the update pass for the others (V = double, or float
+// with the handle's FP32 values).
+template <class V>
+int cheb_step(spk_mat *A, const ChebStep<V> &c, V *tmp, hipStream_t s)
 {
+    constexpr bool f64 = std::is_same<V, double>::value;
     const dim3 g(A->nblk), t(kBlock);
     if (A->kernel == SPK_KERNEL_SELL) {
         const SellView sv{A->sell_ptr, A->sell_col, A->sell_len};
         // up to one wavefront per slice (no partial sums to keep per block)
         const dim3 gs(std::max(1, std::min(ceil_div(ceil_div(A->n, kSell), kBlock / kWave), 16384)));
         const int n = A->n;
-        const double *sval = A->sell_val;
+        const V *sval = f64 ? (const V *)A->sell_val : (const V *)A->sell_val32;
+        if (!sval) { set_error("internal: no SELL values of this precision"); return SPK_EINVAL; }
         with_sell_u(A->sell_u, [&](auto uc) {
             constexpr int U = decltype(uc)::value;
-            if (A->sell_cw == 2) hipLaunchKernelGGL((k_cheb_sell<int16_t, U>), gs, t, 0, s, n, sv, sval, c);
-            else hipLaunchKernelGGL((k_cheb_sell<int32_t, U>), gs, t, 0, s, n, sv, sval, c);
+            if (A->sell_cw == 2) hipLaunchKernelGGL((k_cheb_sell<V, int16_t, U>), gs, t, 0, s, n, sv, sval, c);
+            else hipLaunchKernelGGL((k_cheb_sell<V, int32_t, U>), gs, t, 0, s, n, sv, sval, c);
         });
     } else if (A->kernel == SPK_KERNEL_STREAM) {
-        hipLaunchKernelGGL(k_cheb_stream, g, t, 0, s, A->n, A->R, A->ntiles, A->nblk, A->rowptr, A->col,
-                           (const double *)A->val, c);
+        const V *val = f64 ? (const V *)A->val : (const V *)A->val32;
+        hipLaunchKernelGGL((k_cheb_stream<V>), g, t, 0, s, A->n, A->R, A->ntiles, A->nblk, A->rowptr, A->col, val,
+                           c);
     } else {
-        SPK_TRY(launch_spmv<double>(A, A->val, c.dk, tmp, s, c.gate, c.gate ? kGateInner64 : kGateNone));
-        hipLaunchKernelGGL(k_cheb_update, dim3(grid_n(A->n)), t, 0, s, A->n, (const double *)tmp, c);
+        const V *val = f64 ? (const V *)A->val : (const V *)A->val32;
+        SPK_TRY(launch_spmv<V>(A, val, c.dk, tmp, s, c.gate, c.gate ? kGateInner64 : kGateNone));
+        hipLaunchKernelGGL((k_cheb_update<V>), dim3(grid_n(A->n)), t, 0, s, A->n, (const V *)tmp, c);
     }
     SPK_HIP(hipGetLastError());
     return SPK_OK;
 }
+
+template int cheb_step<double>(spk_mat *, const ChebStep<double> &, double *, hipStream_t);
+template int cheb_step<float>(spk_mat *, const ChebStep<float> &, float *, hipStream_t);
 
 }  // namespace spk
 
@@ -619,21 +628,21 @@ int spk_pc_chebyshev(const spk_mat *Ac, const double *b, double *x, double *r_ou
     double *dbuf[2] = {w->z, w->p};
     double *tmp = w->q;
     if (x0_nonzero) SPK_TRY(launch_spmv<double>(A, A->val, x, tmp, s, nullptr, kGateNone));
-    hipLaunchKernelGGL(k_cheb_init, dim3(grid_n(n)), dim3(kBlock), 0, s, (int)n, b,
+    hipLaunchKernelGGL((k_cheb_init<double, double>), dim3(grid_n(n)), dim3(kBlock), 0, s, (int)n, b,
                        x0_nonzero ? (const double *)tmp : nullptr, x, r, dbuf[0], (const double *)A->dinv,
-                       1.0 / theta, nullptr);
+                       1.0 / theta, (const SysState *)nullptr, (double *)nullptr);
     SPK_HIP(hipGetLastError());
     double rho = 1.0 / sigma;
     for (int k = 0; k < steps; ++k) {
         const bool last = k == steps - 1;
         if (last && !r_out) {  // the residual is not wanted: skip the last SpMV
-            hipLaunchKernelGGL(k_cheb_last, dim3(grid_n(n)), dim3(kBlock), 0, s, (int)n,
-                               (const double *)dbuf[k & 1], x, nullptr);
+            hipLaunchKernelGGL((k_cheb_last<double>), dim3(grid_n(n)), dim3(kBlock), 0, s, (int)n,
+                               (const double *)dbuf[k & 1], x, (const SysState *)nullptr);
             SPK_HIP(hipGetLastError());
             break;
         }
         const double rho_next = 1.0 / (2.0 * sigma - rho);
-        ChebStep c;
+        ChebStep<double> c;
         c.dk = dbuf[k & 1];
         c.dn = last ? nullptr : dbuf[(k + 1) & 1];
         c.r = r;

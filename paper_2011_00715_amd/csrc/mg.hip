@@ -22,8 +22,20 @@ struct MgLevel {
     Grid3 g{1, 1, 1};
     int n = 0;
     double emax = 0.0, emin = 0.0;
-    double *b = nullptr, *x = nullptr;  // level 0: set for each call
-    double *r = nullptr, *d0 = nullptr, *d1 = nullptr, *tmp = nullptr;
+    // vectors of the cycle's precision (double, or float for the FP32 cycle);
+    // level 0's b and x are the call's own arrays in an FP64 cycle
+    void *b = nullptr, *x = nullptr;
+    void *r = nullptr, *d0 = nullptr, *d1 = nullptr, *tmp = nullptr;
+};
+
+// Level 0's connection to the FP64 data of a call: the cycle's right-hand
+// side, where its result goes, and (inside CG) the partial sums of r . z.
+struct CycleIo {
+    const double *b64;
+    double *z64;
+    double *dotpart;  // null: no inner product
+    int *np;
+    const double *rcg;
 };
 
 // Events of a profiled cycle: (level, start, end) for each stretch of one
@@ -41,9 +53,11 @@ struct spk_mg {
     spk_mg_opts o{};
     int nlev = 0;
     spk::MgLevel lev[spk::kMgMaxLevels];
-    double *cinv = nullptr;  // dense inverse of the coarsest matrix, row-major
+    int f32 = 0;             // 1: the cycle runs in FP32 (values, vectors, arithmetic)
+    void *cinv = nullptr;    // dense inverse of the coarsest matrix, row-major, cycle precision
     // solve workspace (allocated on first solve)
     double *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr, *x = nullptr, *b = nullptr;
+    double *tmp64 = nullptr; // FP64 SpMV output of the unfused families
     double *part = nullptr;  // 4 x kMgMaxPart partial sums
     double *hist = nullptr;
     int hist_cap = 0;
@@ -85,37 +99,59 @@ static int mg_alloc(spk_mg *M, T **p, int64_t count)
     return SPK_OK;
 }
 
+// A cycle vector of n entries (8 or 4 bytes each).
+static int mg_vec(spk_mg *M, void **p, int64_t n)
+{
+    const size_t b = (M->f32 ? 4 : 8) * (size_t)(n > 0 ? n : 1);
+    SPK_HIP(hipMalloc(p, b));
+    M->bytes += (int64_t)b;
+    return SPK_OK;
+}
+
+template <class V>
+static const V *values_of(const spk_mat *A)
+{
+    return std::is_same<V, double>::value ? (const V *)A->val : (const V *)A->val32;
+}
+
+template <class V>
+static const V *dinv_of(const spk_mat *A)
+{
+    return std::is_same<V, double>::value ? (const V *)A->dinv : (const V *)A->dinv32;
+}
+
 static double *part_of(spk_mg *M, int slot) { return M->part + (size_t)slot * kMgMaxPart; }
 
 // One pass over the rows of A with y = A x handed to the epilogue f; the
 // number of partial sums written to `part` (if not null) goes to *np.
-template <class F>
-static int launch_rows(spk_mat *A, const double *x, F f, double *part, int *np, const SysState *gate,
-                       double *tmp, hipStream_t s)
+template <class V, class F>
+static int launch_rows(spk_mat *A, const V *x, F f, double *part, int *np, const SysState *gate, V *tmp,
+                       hipStream_t s)
 {
+    constexpr bool f64 = std::is_same<V, double>::value;
     const int n = A->n;
     if (A->kernel == SPK_KERNEL_SELL) {
         const SellView sv{A->sell_ptr, A->sell_col, A->sell_len};
         const int grid = std::max(1, std::min(ceil_div(ceil_div(n, kSell), kBlock / kWave), kMgMaxPart));
-        const double *sval = A->sell_val;
+        const V *sval = f64 ? (const V *)A->sell_val : (const V *)A->sell_val32;
         with_sell_u(A->sell_u, [&](auto uc) {
             constexpr int U = decltype(uc)::value;
             if (A->sell_cw == 2)
-                hipLaunchKernelGGL((k_mg_rows_sell<int16_t, U, F>), dim3(grid), dim3(kBlock), 0, s, n, sv, sval, x,
+                hipLaunchKernelGGL((k_mg_rows_sell<V, int16_t, U, F>), dim3(grid), dim3(kBlock), 0, s, n, sv, sval, x,
                                    f, part, gate);
             else
-                hipLaunchKernelGGL((k_mg_rows_sell<int32_t, U, F>), dim3(grid), dim3(kBlock), 0, s, n, sv, sval, x,
+                hipLaunchKernelGGL((k_mg_rows_sell<V, int32_t, U, F>), dim3(grid), dim3(kBlock), 0, s, n, sv, sval, x,
                                    f, part, gate);
         });
         if (np) *np = grid;
     } else if (A->kernel == SPK_KERNEL_STREAM) {
-        hipLaunchKernelGGL((k_mg_rows_stream<F>), dim3(A->nblk), dim3(kBlock), 0, s, n, A->R, A->ntiles, A->nblk,
-                           A->rowptr, A->col, (const double *)A->val, x, f, part, gate);
+        hipLaunchKernelGGL((k_mg_rows_stream<V, F>), dim3(A->nblk), dim3(kBlock), 0, s, n, A->R, A->ntiles, A->nblk,
+                           A->rowptr, A->col, values_of<V>(A), x, f, part, gate);
         if (np) *np = A->nblk;
     } else {
-        SPK_TRY(launch_spmv<double>(A, A->val, x, tmp, s, gate, gate ? kGateInner64 : kGateNone));
+        SPK_TRY(launch_spmv<V>(A, values_of<V>(A), x, tmp, s, gate, gate ? kGateInner64 : kGateNone));
         const int grid = grid_n(n);
-        hipLaunchKernelGGL((k_mg_rows_y<F>), dim3(grid), dim3(kBlock), 0, s, n, (const double *)tmp, f, part, gate);
+        hipLaunchKernelGGL((k_mg_rows_y<V, F>), dim3(grid), dim3(kBlock), 0, s, n, (const V *)tmp, f, part, gate);
         if (np) *np = grid;
     }
     SPK_HIP(hipGetLastError());
@@ -133,118 +169,143 @@ static int timer_mark(spk_mg *M, int level, hipStream_t s)
     return SPK_OK;
 }
 
+// Level 0's result z = x + d (d null: z = x) in FP64, with the r . z partial
+// sums when the call wants them.
+template <class V>
+static void finish(spk_mg *M, const V *d, const SysState *gate, const CycleIo *io, hipStream_t s)
+{
+    const MgLevel &L = M->lev[0];
+    const int g = grid_n(L.n);
+    hipLaunchKernelGGL((k_mg_finish<V>), dim3(g), dim3(kBlock), 0, s, L.n, d, (const V *)L.x, io->z64, io->rcg,
+                       io->dotpart, gate);
+    if (io->np) *io->np = g;
+}
+
 // Chebyshev smoothing of level l: `steps` steps from x (zero unless
 // x0_nonzero).  keep_r: the last step also updates r (its result is
-// restricted); otherwise it only adds d to x, and with dotpart set it also
-// forms the partial sums of rcg . x (the CG inner product r.z).
-static int smooth(spk_mg *M, int l, bool x0_nonzero, bool keep_r, double *dotpart, int *np,
-                  const double *rcg, const SysState *gate, hipStream_t s)
+// restricted); otherwise it only adds d to x.  On level 0 (io set) a start
+// from zero reads the FP64 right-hand side (an FP32 cycle keeps its rounded
+// copy in b), and the post-smoothing (final) ends with finish().
+template <class V>
+static int smooth(spk_mg *M, int l, bool x0_nonzero, bool keep_r, bool final, const CycleIo *io,
+                  const SysState *gate, hipStream_t s)
 {
+    constexpr bool f32 = std::is_same<V, float>::value;
     MgLevel &L = M->lev[l];
     spk_mat *A = L.A;
     const int n = L.n, steps = M->o.smooth_steps;
     const double theta = 0.5 * (L.emax + L.emin), delta = 0.5 * (L.emax - L.emin), sigma = theta / delta;
-    double *d[2] = {L.d0, L.d1};
+    V *b = (V *)L.b, *x = (V *)L.x, *r = (V *)L.r, *tmp = (V *)L.tmp;
+    V *d[2] = {(V *)L.d0, (V *)L.d1};
+    const V *dinv = dinv_of<V>(A);
+    const V inv_theta = (V)(1.0 / theta);
     const dim3 gn(grid_n(n)), tb(kBlock);
+    auto init = [&] {
+        if (f32 && l == 0)  // the FP64 right-hand side, rounded and kept
+            hipLaunchKernelGGL((k_cheb_init<V, double>), gn, tb, 0, s, n, io->b64, (const V *)nullptr, x, r, d[0],
+                               dinv, inv_theta, gate, b);
+        else
+            hipLaunchKernelGGL((k_cheb_init<V, V>), gn, tb, 0, s, n, (const V *)b, (const V *)nullptr, x, r, d[0],
+                               dinv, inv_theta, gate, (V *)nullptr);
+    };
     if (steps == 0) {
-        if (!x0_nonzero)
-            hipLaunchKernelGGL(k_cheb_init, gn, tb, 0, s, n, (const double *)L.b, (const double *)nullptr, L.x,
-                               L.r, L.d0, (const double *)A->dinv, 1.0 / theta, gate);
-        if (dotpart) {
-            hipLaunchKernelGGL(k_mg_dot, gn, tb, 0, s, n, rcg, (const double *)L.x, dotpart, gate);
-            *np = (int)gn.x;
-        }
+        if (!x0_nonzero) init();
+        if (final) finish<V>(M, (const V *)nullptr, gate, io, s);
         SPK_HIP(hipGetLastError());
         return SPK_OK;
     }
     if (x0_nonzero)
-        SPK_TRY(launch_rows(A, L.x, RowResid{L.b, L.r, L.d0, A->dinv, 1.0 / theta}, nullptr, nullptr, gate, L.tmp, s));
+        SPK_TRY(launch_rows<V>(A, x, RowResid<V>{b, r, d[0], dinv, inv_theta}, nullptr, nullptr, gate, tmp, s));
     else
-        hipLaunchKernelGGL(k_cheb_init, gn, tb, 0, s, n, (const double *)L.b, (const double *)nullptr, L.x, L.r,
-                           L.d0, (const double *)A->dinv, 1.0 / theta, gate);
+        init();
     double rho = 1.0 / sigma;
     for (int k = 0; k < steps; ++k) {
         const bool last = k == steps - 1;
         if (last && !keep_r) {
-            if (dotpart) {
-                hipLaunchKernelGGL(k_mg_last_dot, gn, tb, 0, s, n, (const double *)d[k & 1], L.x, rcg, dotpart,
-                                   gate);
-                *np = (int)gn.x;
-            } else {
-                hipLaunchKernelGGL(k_cheb_last, gn, tb, 0, s, n, (const double *)d[k & 1], L.x, gate);
-            }
+            if (final) finish<V>(M, (const V *)d[k & 1], gate, io, s);
+            else hipLaunchKernelGGL((k_cheb_last<V>), gn, tb, 0, s, n, (const V *)d[k & 1], x, gate);
             break;
         }
         const double rho_next = 1.0 / (2.0 * sigma - rho);
-        ChebStep c;
+        ChebStep<V> c;
         c.dk = d[k & 1];
         c.dn = last ? nullptr : d[(k + 1) & 1];
-        c.r = L.r;
-        c.x = L.x;
-        c.dinv = A->dinv;
-        c.c1 = rho_next * rho;
-        c.c2 = 2.0 * rho_next / delta;
+        c.r = r;
+        c.x = x;
+        c.dinv = dinv;
+        c.c1 = (V)(rho_next * rho);
+        c.c2 = (V)(2.0 * rho_next / delta);
         c.gate = gate;
-        SPK_TRY(cheb_step(A, c, L.tmp, s));
+        SPK_TRY(cheb_step<V>(A, c, tmp, s));
         rho = rho_next;
     }
     SPK_HIP(hipGetLastError());
     return SPK_OK;
 }
 
-// One cycle on level l: x_l from b_l (and from x_l when x0_nonzero).
+// One cycle on level l: x_l from b_l (and from x_l when x0_nonzero); io is
+// set on level 0 only.
+template <class V>
 static int enqueue_cycle(spk_mg *M, int l, bool x0_nonzero, const SysState *gate, hipStream_t s,
-                         double *dotpart, int *np, const double *rcg)
+                         const CycleIo *io)
 {
+    constexpr bool f32 = std::is_same<V, float>::value;
     MgLevel &L = M->lev[l];
     if (l == M->nlev - 1) {  // direct solve (x0 does not matter)
         SPK_TRY(timer_mark(M, l, s));
-        hipLaunchKernelGGL(k_mg_gemv, dim3(ceil_div(L.n, kBlock / kWave)), dim3(kBlock), 0, s, L.n,
-                           (const double *)M->cinv, (const double *)L.b, L.x, gate);
-        if (dotpart) {
-            const int g = grid_n(L.n);
-            hipLaunchKernelGGL(k_mg_dot, dim3(g), dim3(kBlock), 0, s, L.n, rcg, (const double *)L.x, dotpart, gate);
-            *np = g;
-        }
+        if (f32 && l == 0)
+            hipLaunchKernelGGL(k_mg_round, dim3(grid_n(L.n)), dim3(kBlock), 0, s, L.n, io->b64, (float *)L.b, gate);
+        hipLaunchKernelGGL((k_mg_gemv<V>), dim3(ceil_div(L.n, kBlock / kWave)), dim3(kBlock), 0, s, L.n,
+                           (const V *)M->cinv, (const V *)L.b, (V *)L.x, gate);
+        if (l == 0) finish<V>(M, (const V *)nullptr, gate, io, s);
         SPK_HIP(hipGetLastError());
         SPK_TRY(timer_mark(M, l, s));
         return SPK_OK;
     }
     MgLevel &C = M->lev[l + 1];
     SPK_TRY(timer_mark(M, l, s));
-    SPK_TRY(smooth(M, l, x0_nonzero, true, nullptr, nullptr, nullptr, gate, s));
-    hipLaunchKernelGGL(k_mg_restrict, dim3(grid_n(C.n)), dim3(kBlock), 0, s, L.g, C.g, (const double *)L.r, C.b,
-                       gate);
+    SPK_TRY(smooth<V>(M, l, x0_nonzero, true, false, io, gate, s));
+    hipLaunchKernelGGL((k_mg_restrict<V>), dim3(grid_n(C.n)), dim3(kBlock), 0, s, L.g, C.g, (const V *)L.r,
+                       (V *)C.b, gate);
     SPK_HIP(hipGetLastError());
     SPK_TRY(timer_mark(M, l, s));
-    SPK_TRY(enqueue_cycle(M, l + 1, false, gate, s, nullptr, nullptr, nullptr));
-    if (M->o.cycle == 2 && l + 1 < M->nlev - 1)
-        SPK_TRY(enqueue_cycle(M, l + 1, true, gate, s, nullptr, nullptr, nullptr));
+    SPK_TRY(enqueue_cycle<V>(M, l + 1, false, gate, s, nullptr));
+    if (M->o.cycle == 2 && l + 1 < M->nlev - 1) SPK_TRY(enqueue_cycle<V>(M, l + 1, true, gate, s, nullptr));
     SPK_TRY(timer_mark(M, l, s));
-    hipLaunchKernelGGL(k_mg_prolong, dim3(grid_n(L.n)), dim3(kBlock), 0, s, L.n, L.g, C.g, M->o.omega,
-                       (const double *)C.x, L.x, gate);
+    hipLaunchKernelGGL((k_mg_prolong<V>), dim3(grid_n(L.n)), dim3(kBlock), 0, s, L.n, L.g, C.g, (V)M->o.omega,
+                       (const V *)C.x, (V *)L.x, gate);
     SPK_HIP(hipGetLastError());
-    SPK_TRY(smooth(M, l, true, false, dotpart, np, rcg, gate, s));
+    SPK_TRY(smooth<V>(M, l, true, false, l == 0, io, gate, s));
     SPK_TRY(timer_mark(M, l, s));
     return SPK_OK;
+}
+
+// A whole cycle for the FP64 data of io, in the hierarchy's precision.
+static int run_cycle(spk_mg *M, const CycleIo &io, const SysState *gate, hipStream_t s)
+{
+    MgLevel &L0 = M->lev[0];
+    if (M->f32) return enqueue_cycle<float>(M, 0, false, gate, s, &io);
+    L0.b = const_cast<double *>(io.b64);
+    L0.x = io.z64;
+    return enqueue_cycle<double>(M, 0, false, gate, s, &io);
 }
 
 static int alloc_level_vectors(spk_mg *M, int l)
 {
     MgLevel &L = M->lev[l];
-    if (l > 0) {
-        SPK_TRY(mg_alloc(M, &L.b, L.n));
-        SPK_TRY(mg_alloc(M, &L.x, L.n));
+    if (l > 0 || M->f32) {  // an FP64 cycle uses the call's arrays on level 0
+        SPK_TRY(mg_vec(M, &L.b, L.n));
+        SPK_TRY(mg_vec(M, &L.x, L.n));
     }
     if (l < M->nlev - 1) {
-        SPK_TRY(mg_alloc(M, &L.r, L.n));
-        SPK_TRY(mg_alloc(M, &L.d0, L.n));
-        SPK_TRY(mg_alloc(M, &L.d1, L.n));
+        SPK_TRY(mg_vec(M, &L.r, L.n));
+        SPK_TRY(mg_vec(M, &L.d0, L.n));
+        SPK_TRY(mg_vec(M, &L.d1, L.n));
         // level 0's family may change later (spk_mat_set_kernel on the caller's matrix)
         if (l == 0 || (L.A->kernel != SPK_KERNEL_SELL && L.A->kernel != SPK_KERNEL_STREAM))
-            SPK_TRY(mg_alloc(M, &L.tmp, L.n));
+            SPK_TRY(mg_vec(M, &L.tmp, L.n));
     } else if (l == 0) {
-        SPK_TRY(mg_alloc(M, &L.tmp, L.n));
+        SPK_TRY(mg_vec(M, &L.tmp, L.n));
     }
     return SPK_OK;
 }
@@ -291,43 +352,61 @@ static int build_coarse(spk_mg *M, int l, const Grid3 &c, hipStream_t s, spk_mat
     return done(rc);
 }
 
-// Dense inverse of the coarsest matrix by Gauss-Jordan elimination.
+static __global__ void k_mg_narrow(int64_t m, const double *__restrict__ a, float *__restrict__ b)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x)
+        b[i] = (float)a[i];
+}
+
+// Dense inverse of the coarsest matrix by Gauss-Jordan elimination in FP64
+// (rounded to FP32 for an FP32 cycle).
 static int invert_coarsest(spk_mg *M, hipStream_t s)
 {
     const MgLevel &L = M->lev[M->nlev - 1];
     const int n = L.n;
-    SPK_TRY(mg_alloc(M, &M->cinv, (int64_t)n * n));
-    double *colk = nullptr;
-    int32_t *bad = nullptr;
-    SPK_HIP(hipMalloc(&colk, sizeof(double) * (size_t)n));
-    hipError_t e = hipMalloc(&bad, sizeof(int32_t));
-    if (e != hipSuccess) {
-        hipFree(colk);
-        return hip_fail(e, "hipMalloc", __FILE__, __LINE__);
-    }
-    int32_t hbad = 0;
     const int64_t nn = (int64_t)n * n;
-    hipLaunchKernelGGL(k_mg_zero, dim3(grid_n(nn)), dim3(kBlock), 0, s, nn, M->cinv);
+    double *inv = nullptr, *colk = nullptr;
+    int32_t *bad = nullptr;
+    auto done = [&](int code) {
+        hipFree(colk);
+        hipFree(bad);
+        if (inv != M->cinv) hipFree(inv);
+        return code;
+    };
+    hipError_t e = hipMalloc(&inv, sizeof(double) * (size_t)nn);
+    if (e == hipSuccess) e = hipMalloc(&colk, sizeof(double) * (size_t)n);
+    if (e == hipSuccess) e = hipMalloc(&bad, sizeof(int32_t));
+    if (e != hipSuccess) return done(hip_fail(e, "hipMalloc", __FILE__, __LINE__));
+    int32_t hbad = 0;
+    hipLaunchKernelGGL(k_mg_zero, dim3(grid_n(nn)), dim3(kBlock), 0, s, nn, inv);
     e = hipMemcpyAsync(bad, &hbad, sizeof(int32_t), hipMemcpyHostToDevice, s);
     hipLaunchKernelGGL(k_mg_dense, dim3(grid_n(n)), dim3(kBlock), 0, s, n, (const int32_t *)L.A->rowptr,
-                       (const int32_t *)L.A->col, (const double *)L.A->val, M->cinv);
+                       (const int32_t *)L.A->col, (const double *)L.A->val, inv);
     const dim3 gu(ceil_div(n, kBlock), n);
     for (int k = 0; k < n && e == hipSuccess; ++k) {
-        hipLaunchKernelGGL(k_gj_pivot, dim3(1), dim3(kBlock), 0, s, n, k, M->cinv, colk, bad);
-        hipLaunchKernelGGL(k_gj_update, gu, dim3(kBlock), 0, s, n, k, M->cinv, (const double *)colk);
+        hipLaunchKernelGGL(k_gj_pivot, dim3(1), dim3(kBlock), 0, s, n, k, inv, colk, bad);
+        hipLaunchKernelGGL(k_gj_update, gu, dim3(kBlock), 0, s, n, k, inv, (const double *)colk);
         e = hipGetLastError();
     }
-    if (e == hipSuccess) hipLaunchKernelGGL(k_mg_sym, gu, dim3(kBlock), 0, s, n, M->cinv);
+    if (e == hipSuccess) hipLaunchKernelGGL(k_mg_sym, gu, dim3(kBlock), 0, s, n, inv);
     if (e == hipSuccess) e = hipMemcpyAsync(&hbad, bad, sizeof(int32_t), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
-    hipFree(colk);
-    hipFree(bad);
-    if (e != hipSuccess) return hip_fail(e, "coarse inverse", __FILE__, __LINE__);
+    if (e != hipSuccess) return done(hip_fail(e, "coarse inverse", __FILE__, __LINE__));
     if (hbad) {
         set_error("the coarsest matrix (%d rows) is not positive definite", n);
-        return SPK_EINVAL;
+        return done(SPK_EINVAL);
     }
-    return SPK_OK;
+    if (!M->f32) {
+        M->cinv = inv;
+        M->bytes += 8 * nn;
+        return done(SPK_OK);
+    }
+    e = hipMalloc(&M->cinv, sizeof(float) * (size_t)nn);
+    if (e != hipSuccess) return done(hip_fail(e, "hipMalloc", __FILE__, __LINE__));
+    M->bytes += 4 * nn;
+    hipLaunchKernelGGL(k_mg_narrow, dim3(grid_n(nn)), dim3(kBlock), 0, s, nn, (const double *)inv, (float *)M->cinv);
+    e = hipStreamSynchronize(s);
+    return done(e == hipSuccess ? SPK_OK : hip_fail(e, "coarse inverse", __FILE__, __LINE__));
 }
 
 static void destroy_mg(spk_mg *M)
@@ -335,11 +414,11 @@ static void destroy_mg(spk_mg *M)
     hipDeviceSynchronize();
     for (int l = 0; l < M->nlev; ++l) {
         MgLevel &L = M->lev[l];
-        if (l > 0) {
+        if (l > 0 || M->f32) {
             hipFree(L.b);
             hipFree(L.x);
-            spk_mat_destroy(L.A);
         }
+        if (l > 0) spk_mat_destroy(L.A);
         hipFree(L.r);
         hipFree(L.d0);
         hipFree(L.d1);
@@ -352,6 +431,7 @@ static void destroy_mg(spk_mg *M)
     hipFree(M->q);
     hipFree(M->x);
     hipFree(M->b);
+    hipFree(M->tmp64);
     hipFree(M->part);
     hipFree(M->hist);
     hipFree(M->st);
@@ -419,6 +499,11 @@ static int setup(spk_mg *M, spk_mat *A, const int32_t *shape, hipStream_t s)
             set_error("level %d: no finite spectral bound", l);
             return SPK_EINVAL;
         }
+        if (M->f32 && l < M->nlev - 1) {  // FP32 values and D^-1 for the smoother (the caller's level 0 too)
+            SPK_TRY(ensure_f32(L.A, s));
+            SPK_HIP(hipStreamSynchronize(s));
+            L.A->info.has_f32 = 1;
+        }
         SPK_TRY(alloc_level_vectors(M, l));
     }
     SPK_TRY(invert_coarsest(M, s));
@@ -437,6 +522,7 @@ static int get_solve_ws(spk_mg *M, int hist_len)
         SPK_TRY(mg_alloc(M, &M->q, n));
         SPK_TRY(mg_alloc(M, &M->x, n));
         SPK_TRY(mg_alloc(M, &M->b, n));
+        SPK_TRY(mg_alloc(M, &M->tmp64, n));
         SPK_TRY(mg_alloc(M, &M->part, 4 * (int64_t)kMgMaxPart));
         SPK_TRY(mg_alloc(M, &M->st, 1));
         SPK_HIP(hipHostMalloc((void **)&M->pst, sizeof(SysState), hipHostMallocDefault));
@@ -462,14 +548,13 @@ static int enqueue_iteration(spk_mg *M, hipStream_t s)
     MgLevel &L0 = M->lev[0];
     const int n = L0.n;
     const SysState *gate = M->st;
-    L0.b = M->r;
-    L0.x = M->z;
     int np = 0;
-    SPK_TRY(enqueue_cycle(M, 0, false, gate, s, part_of(M, kPartRzMg), &np, M->r));
+    const CycleIo io{M->r, M->z, part_of(M, kPartRzMg), &np, M->r};
+    SPK_TRY(run_cycle(M, io, gate, s));
     hipLaunchKernelGGL(k_mg_fin_rho, dim3(1), dim3(kBlock), 0, s, M->st, (const double *)part_of(M, kPartRzMg), np);
     hipLaunchKernelGGL(k_mg_p, dim3(grid_n(n)), dim3(kBlock), 0, s, n, (const double *)M->z, M->p,
                        (const SysState *)M->st);
-    SPK_TRY(launch_rows(L0.A, M->p, RowPq{M->p, M->q}, part_of(M, kPartPqMg), &np, gate, L0.tmp, s));
+    SPK_TRY(launch_rows(L0.A, M->p, RowPq{M->p, M->q}, part_of(M, kPartPqMg), &np, gate, M->tmp64, s));
     hipLaunchKernelGGL(k_mg_fin_alpha, dim3(1), dim3(kBlock), 0, s, M->st, (const double *)part_of(M, kPartPqMg), np);
     const int g = grid_n(n);
     hipLaunchKernelGGL(k_mg_update, dim3(g), dim3(kBlock), 0, s, n, M->x, M->r, (const double *)M->p,
@@ -568,7 +653,7 @@ static int true_residual(spk_mg *M, hipStream_t s)
 {
     MgLevel &L0 = M->lev[0];
     int np = 0;
-    SPK_TRY(launch_rows(L0.A, M->x, RowTrue{M->b, M->r}, part_of(M, kPartRrMg), &np, nullptr, L0.tmp, s));
+    SPK_TRY(launch_rows(L0.A, M->x, RowTrue{M->b, M->r}, part_of(M, kPartRrMg), &np, nullptr, M->tmp64, s));
     hipLaunchKernelGGL(k_mg_fin_true, dim3(1), dim3(kBlock), 0, s, M->st, (const double *)part_of(M, kPartRrMg), np);
     SPK_HIP(hipGetLastError());
     return SPK_OK;
@@ -587,7 +672,7 @@ static int solve(spk_mg *M, const double *b, double *x, const spk_ksp_opts &o, s
                        o.x0_nonzero ? 0 : 1, part_of(M, kPartBbMg));
     int nrr = 0;
     if (o.x0_nonzero)
-        SPK_TRY(launch_rows(L0.A, M->x, RowTrue{M->b, M->r}, part_of(M, kPartRrMg), &nrr, nullptr, L0.tmp, s));
+        SPK_TRY(launch_rows(L0.A, M->x, RowTrue{M->b, M->r}, part_of(M, kPartRrMg), &nrr, nullptr, M->tmp64, s));
     hipLaunchKernelGGL(k_mg_fin_start, dim3(1), dim3(kBlock), 0, s, M->st, (const double *)part_of(M, kPartBbMg), g,
                        o.x0_nonzero ? (const double *)part_of(M, kPartRrMg) : (const double *)nullptr, nrr, M->hist);
     SPK_HIP(hipGetLastError());
@@ -711,6 +796,10 @@ int spk_mg_create(const spk_mat *Ac, int32_t dim, const int32_t *shape, const sp
         return SPK_EINVAL;
     }
     if (!(o.omega > 0.0) || !std::isfinite(o.omega)) { set_error("omega = %g: need > 0", o.omega); return SPK_EINVAL; }
+    if (o.precision != SPK_PREC_FP64 && o.precision != SPK_PREC_MIXED) {
+        set_error("precision = %d: need SPK_PREC_FP64 or SPK_PREC_MIXED", o.precision);
+        return SPK_EINVAL;
+    }
     if (A->stats.zero_diag) {
         set_error("%d rows without a nonzero diagonal", A->stats.zero_diag);
         return SPK_EZERODIAG;
@@ -719,6 +808,7 @@ int spk_mg_create(const spk_mat *Ac, int32_t dim, const int32_t *shape, const sp
     if (!M) { set_error("out of host memory"); return SPK_ENOMEM; }
     M->dim = dim;
     M->o = o;
+    M->f32 = o.precision == SPK_PREC_MIXED ? 1 : 0;
     hipGetDevice(&M->device);
     const int rc = setup(M, A, shape, (hipStream_t)stream);
     if (rc != SPK_OK) {
@@ -767,10 +857,8 @@ int spk_mg_apply(spk_mg *M, const double *b, double *x, void *stream)
     if (!M || !b || !x) { set_error("NULL argument"); return SPK_EINVAL; }
     const int64_t n = M->lev[0].n;
     if (b < x + n && x < b + n) { set_error("b and x must not overlap"); return SPK_EINVAL; }
-    MgLevel &L0 = M->lev[0];
-    L0.b = const_cast<double *>(b);
-    L0.x = x;
-    return enqueue_cycle(M, 0, false, nullptr, (hipStream_t)stream, nullptr, nullptr, nullptr);
+    const CycleIo io{b, x, nullptr, nullptr, nullptr};
+    return run_cycle(M, io, nullptr, (hipStream_t)stream);
 }
 
 int spk_mg_profile(spk_mg *M, const double *b, double *x, int32_t reps, double *level_ms, void *stream)
@@ -786,9 +874,8 @@ int spk_mg_profile(spk_mg *M, const double *b, double *x, int32_t reps, double *
     for (int r = 0; r < reps && rc == SPK_OK; ++r) {
         MgTimer t;
         M->timer = &t;
-        L0.b = const_cast<double *>(b);
-        L0.x = x;
-        rc = enqueue_cycle(M, 0, false, nullptr, s, nullptr, nullptr, nullptr);
+        const CycleIo io{b, x, nullptr, nullptr, nullptr};
+        rc = run_cycle(M, io, nullptr, s);
         M->timer = nullptr;
         hipError_t e = hipStreamSynchronize(s);
         if (rc == SPK_OK && e != hipSuccess) rc = hip_fail(e, "profiled cycle", __FILE__, __LINE__);

@@ -210,39 +210,43 @@ static __global__ void k_mg_sym(int n, double *__restrict__ M)
 }
 
 // ------------------------------------------------------------------ the cycle
+// Kernels of the cycle take V = double, or float for the FP32 cycle of a
+// mixed-precision preconditioner (FP32 values, vectors and arithmetic).
+
 // Coarsest level: x = A_c^-1 b with the stored inverse, one wavefront per row.
-static __global__ __launch_bounds__(kBlock) void k_mg_gemv(int n, const double *__restrict__ M,
-                                                           const double *__restrict__ b,
-                                                           double *__restrict__ x, const SysState *gate)
+template <class V>
+__global__ __launch_bounds__(kBlock) void k_mg_gemv(int n, const V *__restrict__ M, const V *__restrict__ b,
+                                                    V *__restrict__ x, const SysState *gate)
 {
     if (!mg_go(gate)) return;
     const int lane = threadIdx.x & (kWave - 1);
     const int i = blockIdx.x * (kBlock / kWave) + (int)threadIdx.x / kWave;
     if (i >= n) return;
-    const double *row = M + (size_t)i * n;
-    double s = 0.0;
+    const V *row = M + (size_t)i * n;
+    V s = V(0);
     for (int j = lane; j < n; j += kWave) s = fma(row[j], b[j], s);
     s = wave_sum(s);
     if (lane == 0) x[i] = s;
 }
 
 // b_c = P^T r: the sum over each aggregate, fine points in (z, y, x) order.
-static __global__ void k_mg_restrict(Grid3 g, Grid3 c, const double *__restrict__ r,
-                                     double *__restrict__ bc, const SysState *gate)
+template <class V>
+__global__ void k_mg_restrict(Grid3 g, Grid3 c, const V *__restrict__ r, V *__restrict__ bc,
+                              const SysState *gate)
 {
     if (!mg_go(gate)) return;
     const int nc = c.s0 * c.s1 * c.s2;
     for (int I = blockIdx.x * blockDim.x + threadIdx.x; I < nc; I += gridDim.x * blockDim.x) {
         int c0, c1, c2;
         grid_coords(c, I, c0, c1, c2);
-        double t = 0.0;
+        V t = V(0);
         for (int a2 = 0; a2 < 2; ++a2) {
             const int f2 = 2 * c2 + a2;
             if (f2 >= g.s2) continue;
             for (int a1 = 0; a1 < 2; ++a1) {
                 const int f1 = 2 * c1 + a1;
                 if (f1 >= g.s1) continue;
-                const double *rr = r + (size_t)g.s0 * (f1 + (size_t)g.s1 * f2);
+                const V *rr = r + (size_t)g.s0 * (f1 + (size_t)g.s1 * f2);
                 t += rr[2 * c0];
                 if (2 * c0 + 1 < g.s0) t += rr[2 * c0 + 1];
             }
@@ -252,8 +256,9 @@ static __global__ void k_mg_restrict(Grid3 g, Grid3 c, const double *__restrict_
 }
 
 // Coarse-grid correction x += omega P x_c.
-static __global__ void k_mg_prolong(int n, Grid3 g, Grid3 c, double omega, const double *__restrict__ xc,
-                                    double *__restrict__ x, const SysState *gate)
+template <class V>
+__global__ void k_mg_prolong(int n, Grid3 g, Grid3 c, V omega, const V *__restrict__ xc, V *__restrict__ x,
+                             const SysState *gate)
 {
     if (!mg_go(gate)) return;
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
@@ -263,19 +268,49 @@ static __global__ void k_mg_prolong(int n, Grid3 g, Grid3 c, double omega, const
     }
 }
 
+// Level-0 end of the cycle: z = x + d (the last smoothing step; d null when
+// there is none) in FP64, and, when part is set, the partial sums of r . z
+// (the CG inner product).  With V = double, x and z may be the same array.
+template <class V>
+__global__ __launch_bounds__(kBlock) void k_mg_finish(int n, const V *__restrict__ d, const V *x,
+                                                      double *z, const double *__restrict__ r, double *part,
+                                                      const SysState *gate)
+{
+    if (!mg_go(gate)) return;
+    double acc = 0.0;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const double zi = (double)(d ? x[i] + d[i] : x[i]);
+        z[i] = zi;
+        if (part) acc += r[i] * zi;
+    }
+    if (part) {
+        __shared__ double sh[kBlock / kWave];
+        const double s = block_sum(acc, sh);
+        if (threadIdx.x == 0) part[blockIdx.x] = s;
+    }
+}
+
+// FP64 right-hand side rounded into the FP32 cycle's level-0 vector.
+static __global__ void k_mg_round(int n, const double *__restrict__ a, float *__restrict__ b, const SysState *gate)
+{
+    if (!mg_go(gate)) return;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) b[i] = (float)a[i];
+}
+
 // ------------------------------------------------------------------ SpMV rows with an epilogue
 // Row epilogues: f(i, y = (A x)_i) stores what the row produces and returns
 // its contribution to an inner product (0 when none is wanted).
 
 // Smoother start from a nonzero x: r = b - A x, d_0 = D^-1 r / theta.
+template <class V>
 struct RowResid {
-    const double *b;
-    double *r, *d0;
-    const double *dinv;
-    double inv_theta;
-    __device__ double operator()(int i, double y) const
+    const V *b;
+    V *r, *d0;
+    const V *dinv;
+    V inv_theta;
+    __device__ double operator()(int i, V y) const
     {
-        const double ri = b[i] - y;
+        const V ri = b[i] - y;
         r[i] = ri;
         d0[i] = dinv[i] * ri * inv_theta;
         return 0.0;
@@ -312,30 +347,28 @@ __device__ __forceinline__ void store_partial(double acc, double *part)
     if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
 
-template <class CI, int U, class F>
-__global__ __launch_bounds__(kBlock) void k_mg_rows_sell(int n, SellView sv, const double *__restrict__ val,
-                                                         const double *__restrict__ x, F f,
-                                                         double *part, const SysState *gate)
+template <class V, class CI, int U, class F>
+__global__ __launch_bounds__(kBlock) void k_mg_rows_sell(int n, SellView sv, const V *__restrict__ val,
+                                                         const V *__restrict__ x, F f, double *part,
+                                                         const SysState *gate)
 {
     double acc = 0.0;
     bool run = true;
-    sell_slices<double, CI, U>(n, blockIdx.x * (kBlock / kWave) + (int)threadIdx.x / kWave,
-                               gridDim.x * (kBlock / kWave), sv, val, x,
-                               [&] { return run = mg_go(gate); },
-                               [&](int i, double y) { acc += f(i, y); });
+    sell_slices<V, CI, U>(n, blockIdx.x * (kBlock / kWave) + (int)threadIdx.x / kWave,
+                          gridDim.x * (kBlock / kWave), sv, val, x, [&] { return run = mg_go(gate); },
+                          [&](int i, V y) { acc += f(i, y); });
     if (part && run) store_partial(acc, part);
 }
 
-template <class F>
+template <class V, class F>
 __global__ __launch_bounds__(kBlock) void k_mg_rows_stream(int n, int R, int ntiles, int nblk,
                                                            const int32_t *__restrict__ rowptr,
                                                            const int32_t *__restrict__ col,
-                                                           const double *__restrict__ val,
-                                                           const double *__restrict__ x, F f,
-                                                           double *part, const SysState *gate)
+                                                           const V *__restrict__ val, const V *__restrict__ x,
+                                                           F f, double *part, const SysState *gate)
 {
     if (!mg_go(gate)) return;
-    __shared__ TileLds<double> sm;
+    __shared__ TileLds<V> sm;
     const int j = xcd_remap(blockIdx.x, nblk);
     int t0, t1;
     block_tiles(j, nblk, ntiles, t0, t1);
@@ -343,14 +376,14 @@ __global__ __launch_bounds__(kBlock) void k_mg_rows_stream(int n, int R, int nti
     for (int t = t0; t < t1; ++t) {
         const int r0 = t * R;
         const int r1 = min(r0 + R, n);
-        stream_tile<double>(r0, r1, rowptr, col, val, x, sm, [&](int i, double y) { acc += f(i, y); });
+        stream_tile<V>(r0, r1, rowptr, col, val, x, sm, [&](int i, V y) { acc += f(i, y); });
     }
     if (part) store_partial(acc, part);
 }
 
 // Other families: y = A x came from the standalone SpMV.
-template <class F>
-__global__ __launch_bounds__(kBlock) void k_mg_rows_y(int n, const double *__restrict__ y, F f, double *part,
+template <class V, class F>
+__global__ __launch_bounds__(kBlock) void k_mg_rows_y(int n, const V *__restrict__ y, F f, double *part,
                                                       const SysState *gate)
 {
     if (!mg_go(gate)) return;
@@ -410,32 +443,6 @@ static __global__ __launch_bounds__(kBlock) void k_mg_fin_start(SysState *st, co
     if (bn == 0.0) st->status = SPK_CONVERGED_ATOL;
     else if (!isfinite(rn)) st->status = SPK_DIVERGED_NANORINF;
     else if (rn <= thresh) st->status = rn <= st->rtol * bn ? SPK_CONVERGED_RTOL : SPK_CONVERGED_ATOL;
-}
-
-// Final step of the level-0 post-smoothing inside CG: z = x + d, and r.z.
-static __global__ __launch_bounds__(kBlock) void k_mg_last_dot(int n, const double *__restrict__ d,
-                                                               double *__restrict__ z,
-                                                               const double *__restrict__ r, double *part,
-                                                               const SysState *gate)
-{
-    if (!mg_go(gate)) return;
-    double acc = 0.0;
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-        const double zi = z[i] + d[i];
-        z[i] = zi;
-        acc += r[i] * zi;
-    }
-    store_partial(acc, part);
-}
-
-static __global__ __launch_bounds__(kBlock) void k_mg_dot(int n, const double *__restrict__ a,
-                                                          const double *__restrict__ b, double *part,
-                                                          const SysState *gate)
-{
-    if (!mg_go(gate)) return;
-    double acc = 0.0;
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) acc += a[i] * b[i];
-    store_partial(acc, part);
 }
 
 // rho' = r.z with its checks; beta = rho'/rho, or p = z after a (re)start.

@@ -125,8 +125,11 @@ void free_sliced(spk_mat *A);
 int ensure_sliced_f32(spk_mat *A, hipStream_t s);
 template <class V>
 int launch_sliced(const spk_mat *A, const V *x, V *y, hipStream_t s, const SysState *gst, int gmode);
+template <class V>
 struct ChebStep;
-// One Chebyshev smoothing step on A (fused with its SpMV where the family allows).
-int cheb_step(spk_mat *A, const ChebStep &c, double *tmp, hipStream_t s);
+// One Chebyshev smoothing step on A (fused with its SpMV where the family
+// allows); V = double, or float with the handle's FP32 values.
+template <class V>
+int cheb_step(spk_mat *A, const ChebStep<V> &c, V *tmp, hipStream_t s);
 
 }  // namespace spk

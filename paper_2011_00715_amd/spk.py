@@ -89,7 +89,7 @@ class ServerOpts(ctypes.Structure):
 class MgOpts(ctypes.Structure):
     _fields_ = [
         ("max_levels", i32), ("coarse_max", i32), ("smooth_steps", i32), ("cycle", i32),
-        ("emin_frac", dbl), ("omega", dbl),
+        ("emin_frac", dbl), ("omega", dbl), ("precision", i32), ("pad_", i32),
     ]
 
 

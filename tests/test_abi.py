@@ -70,7 +70,8 @@ def test_multigrid_host_validation_without_gpu(lib):
     from paper_2011_00715_amd import spk
 
     o = spk.mg_opts_default()
-    assert (o.max_levels, o.coarse_max, o.smooth_steps, o.cycle, o.emin_frac, o.omega) == (16, 1000, 2, 1, 0.1, 2.0)
+    assert (o.max_levels, o.coarse_max, o.smooth_steps, o.cycle, o.emin_frac, o.omega, o.precision) ==         (16, 1000, 2, 1, 0.1, 2.0, spk.PREC_FP64)
+    assert ctypes.sizeof(spk.MgOpts) == 40
     assert ctypes.sizeof(spk.MgInfo) == 592
     out = ctypes.c_void_p()
     shape = (ctypes.c_int32 * 3)(4, 4, 1)

@@ -237,3 +237,27 @@ def test_c2_multigrid_pcg():
     bn = oracle.nrm2(b)
     assert oracle.nrm2(b - oracle.spmv(A, xg)) <= 1e-8 * bn * (1 + 1e-6)
     assert np.linalg.norm(xg - xo) <= 1e-5 * np.linalg.norm(xo)
+
+
+def test_c2_multigrid_fp32_cycle():
+    """The bench's FP32-cycle leg: V-cycle PCG with the cycle in FP32 inside
+    FP64 CG on the 128^3 Laplacian; iterations within two of the oracle's
+    FP64-cycle solve (14), the oracle's true residual of the solution."""
+    spk = need_gpu()
+    import torch
+
+    A = spkgen.laplace3d7(128)
+    M = mat_on_gpu(spk, A)
+    G = spk.mg_create(M, (128, 128, 128), spk.mg_opts(precision=spk.PREC_MIXED))
+    h = oracle.mg_setup(A, (128, 128, 128))
+    b = spkgen.rhs_uniform(A.n, 0)
+    x = torch.zeros(A.n, dtype=torch.float64, device="cuda")
+    spk.mg_apply(G, to_dev(b), x)
+    xc = oracle.mg_cycle(h, b)
+    assert np.max(np.abs(x.cpu().numpy() - xc)) <= 1e-4 * np.max(np.abs(xc))
+    x.zero_()
+    res = spk.ksp_solve_mg(G, to_dev(b), x, spk.ksp_opts(graph_k=1))
+    _, ro, _ = oracle.pcg_mg(A, h, b)
+    assert res.reason == spk.CONVERGED_RTOL
+    assert ro["iterations"] - 1 <= res.iterations <= ro["iterations"] + 2
+    assert oracle.nrm2(b - oracle.spmv(A, x.cpu().numpy())) <= 1e-8 * oracle.nrm2(b) * (1 + 1e-6)

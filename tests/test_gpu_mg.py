@@ -42,6 +42,7 @@ def _hier(spk, case, kernel="auto", **kw):
     opts = spk.mg_opts(coarse_max=cmax, **kw)
     G = spk.mg_create(M, shape, opts)
     okw = dict(kw)
+    okw.pop("precision", None)  # the oracle is FP64
     if "smooth_steps" in okw:
         okw["steps"] = okw.pop("smooth_steps")
     h = oracle.mg_setup(A, shape, coarse_max=cmax, **okw)
@@ -224,3 +225,45 @@ def test_mg_profile_levels():
     ms = spk.mg_profile(G, b, x, reps=3)
     assert len(ms) == G.levels and all(t > 0 for t in ms)
     _close(x.cpu().numpy(), oracle.mg_cycle(h, b.cpu().numpy()), 1e-11, "profiled cycle")
+
+
+# ---------------------------------------------------------------- FP32 cycle inside FP64 CG
+# The FP32 cycle is the FP64 cycle's arithmetic in single precision: each
+# step is backward stable with u32 = 6e-8 per operation, and the result's
+# error relative to the FP64 cycle is that rounding amplified by at most the
+# coarsest matrix's condition number (below 1e3 here), hence 1e-4 of the
+# largest |x|.  CG stays FP64: the FP32 preconditioner may cost an iteration
+# or two, and the oracle's true residual of the solution is still 1e-8.
+
+@pytest.mark.parametrize("case", ["lap2d_64", "lap3d_13x9x11", "diff27_15", "line_1000"])
+@pytest.mark.parametrize("cycle", [1, 2])
+def test_fp32_cycle_and_solve(case, cycle):
+    spk = need_gpu()
+    import torch
+
+    A, M, G, h = _hier(spk, case, cycle=cycle, precision=spk.PREC_MIXED)
+    for seed in (0, 1):
+        b = spkgen.rhs_uniform(A.n, seed)
+        x = torch.full((A.n,), np.nan, dtype=torch.float64, device="cuda")
+        spk.mg_apply(G, to_dev(b), x)
+        _close(x.cpu().numpy(), oracle.mg_cycle(h, b), 1e-4, f"fp32 {case} seed {seed}")
+    b = spkgen.rhs_uniform(A.n, 2)
+    x = torch.zeros(A.n, dtype=torch.float64, device="cuda")
+    res = spk.ksp_solve_mg(G, to_dev(b), x)
+    _, ro, _ = oracle.pcg_mg(A, h, b)
+    assert res.reason == spk.CONVERGED_RTOL
+    assert ro["iterations"] - 1 <= res.iterations <= ro["iterations"] + 2
+    xg = x.cpu().numpy()
+    assert oracle.nrm2(b - oracle.spmv(A, xg)) <= 1e-8 * oracle.nrm2(b) * (1 + 1e-6)
+
+
+@pytest.mark.parametrize("kernel", ["stream", "vector", "merge"])
+def test_fp32_cycle_fine_families(kernel):
+    spk = need_gpu()
+    import torch
+
+    A, M, G, h = _hier(spk, "lap3d_24", kernel=kernel, precision=spk.PREC_MIXED)
+    b = spkgen.rhs_uniform(A.n, 5)
+    x = torch.zeros(A.n, dtype=torch.float64, device="cuda")
+    spk.mg_apply(G, to_dev(b), x)
+    _close(x.cpu().numpy(), oracle.mg_cycle(h, b), 1e-4, kernel)
