@@ -43,7 +43,7 @@ def parse():
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=10)
     p.add_argument("--warmup", type=int, default=2)
-    p.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "serve", "spectrum"])
+    p.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "serve", "spectrum", "mg"])
     p.add_argument("--spmvs", type=int, default=100)
     p.add_argument("--cold-spmvs", type=int, default=20,
                    help="SpMVs timed after evicting the Infinity Cache (after the timed steps)")
@@ -283,53 +283,7 @@ def bench_c2(args):
              "note": "SpMM bytes: CSR matrix once + k x (8n gather + 8n write); solves: k FP64 "
                      "Jacobi-PCG columns sharing each SpMM, per-column scalars and stopping"}
 
-    # geometric multigrid as the CG preconditioner (the V- and W-cycles of
-    # Sec. 5.3 with Chebyshev-Jacobi smoothing), outside the timed steps
-    mg = {}
-    for name, cyc, prec in (("v_cycle", 1, spk.PREC_FP64), ("w_cycle", 2, spk.PREC_FP64),
-                            ("v_cycle_fp32", 1, spk.PREC_MIXED), ("w_cycle_fp32", 2, spk.PREC_MIXED)):
-        t0 = time.perf_counter()
-        G = spk.mg_create(M, (N, N, N), spk.mg_opts(cycle=cyc, precision=prec))
-        torch.cuda.synchronize()
-        setup_ms = (time.perf_counter() - t0) * 1e3
-        xg_ = torch.zeros_like(xs)
-        og = spk.ksp_opts(graph_k=1)
-        spk.ksp_solve_mg(G, bd, xg_, og)
-        tg = []
-        for _ in range(5):
-            rg = spk.ksp_solve_mg(G, bd, xg_, og)
-            tg.append(rg.seconds)
-        xz = torch.zeros_like(xs)
-        spk.mg_apply(G, bd, xz)
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        for _ in range(20):
-            spk.mg_apply(G, bd, xz)
-        e1.record()
-        torch.cuda.synchronize()
-        level_ms = spk.mg_profile(G, bd, xz, reps=20)
-        tmed = float(np.median(tg))
-        mg[name] = {
-            "levels": [G.info.n[l] for l in range(G.levels)],
-            "setup_ms": setup_ms, "iterations": rg.iterations, "reason": spk.reason_str(rg.reason),
-            "solves_per_s": 1.0 / tmed, "ms_p50": tmed * 1e3, "us_per_iter": tmed * 1e6 / max(rg.iterations, 1),
-            "cycle_us": e0.elapsed_time(e1) * 1e3 / 20,
-            "level_us": [v * 1e3 for v in level_ms],
-            "true_rel_residual": rg.true_rel_residual,
-            "speedup_vs_jacobi_pcg": float(np.median(t64)) * 1e-3 / tmed,
-        }
-        if cyc == 1:
-            xv = xg_.cpu().numpy()
-            mg[name]["true_rel_residual_oracle"] = oracle.nrm2(b - oracle.spmv(A, xv)) / bn
-        if prec == spk.PREC_MIXED:
-            ref = mg[name.replace("_fp32", "")]
-            mg[name]["speedup_vs_fp64_cycle"] = ref["ms_p50"] / mg[name]["ms_p50"]
-        G.close()
-    mg["note"] = ("CG preconditioned by one cycle per iteration: aggregation (2x2x2) transfers, "
-                  "Galerkin coarse operators, 2+2 Chebyshev-Jacobi steps on [g/10, g], omega 2, "
-                  "dense inverse on the coarsest level (<= 1000 rows); level_us = each level's own "
-                  "kernels per cycle (the per-level breakdown of Sec. 5.3); *_fp32: the cycle in "
-                  "FP32 (values, vectors, arithmetic) inside the FP64 CG")
+    mg = mg_legs(spk, M, A, b, bd, N, float(np.median(t64)) * 1e-3)
 
     out = {
         "metric": "CSR SpMV HBM GB/s; PCG solves/s to rtol 1e-8, FP64 vs mixed; p50/p99 lat",
@@ -397,6 +351,98 @@ def bench_c2(args):
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(A, b, info, args.cpu_iters)
+    M.close()
+    return out
+
+
+def mg_legs(spk, M, A, b, bd, N, jacobi_s):
+    """Geometric multigrid as the CG preconditioner (the V- and W-cycles of
+    Sec. 5.3 with Chebyshev-Jacobi smoothing), FP64 and FP32 cycles, on the
+    N^3 Laplacian handle M; jacobi_s = the FP64 Jacobi-PCG solve time."""
+    import numpy as np
+    import torch
+
+    import oracle
+
+    bn = oracle.nrm2(b)
+    xs = bd
+    mg = {}
+    for name, cyc, prec in (("v_cycle", 1, spk.PREC_FP64), ("w_cycle", 2, spk.PREC_FP64),
+                            ("v_cycle_fp32", 1, spk.PREC_MIXED), ("w_cycle_fp32", 2, spk.PREC_MIXED)):
+        t0 = time.perf_counter()
+        G = spk.mg_create(M, (N, N, N), spk.mg_opts(cycle=cyc, precision=prec))
+        torch.cuda.synchronize()
+        setup_ms = (time.perf_counter() - t0) * 1e3
+        xg_ = torch.zeros_like(xs)
+        og = spk.ksp_opts(graph_k=1)
+        spk.ksp_solve_mg(G, bd, xg_, og)
+        tg = []
+        for _ in range(5):
+            rg = spk.ksp_solve_mg(G, bd, xg_, og)
+            tg.append(rg.seconds)
+        xz = torch.zeros_like(xs)
+        spk.mg_apply(G, bd, xz)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(20):
+            spk.mg_apply(G, bd, xz)
+        e1.record()
+        torch.cuda.synchronize()
+        level_ms = spk.mg_profile(G, bd, xz, reps=20)
+        tmed = float(np.median(tg))
+        mg[name] = {
+            "levels": [G.info.n[l] for l in range(G.levels)],
+            "setup_ms": setup_ms, "iterations": rg.iterations, "reason": spk.reason_str(rg.reason),
+            "solves_per_s": 1.0 / tmed, "ms_p50": tmed * 1e3, "us_per_iter": tmed * 1e6 / max(rg.iterations, 1),
+            "cycle_us": e0.elapsed_time(e1) * 1e3 / 20,
+            "level_us": [v * 1e3 for v in level_ms],
+            "true_rel_residual": rg.true_rel_residual,
+            "speedup_vs_jacobi_pcg": jacobi_s / tmed,
+        }
+        if cyc == 1:
+            xv = xg_.cpu().numpy()
+            mg[name]["true_rel_residual_oracle"] = oracle.nrm2(b - oracle.spmv(A, xv)) / bn
+        if prec == spk.PREC_MIXED:
+            ref = mg[name.replace("_fp32", "")]
+            mg[name]["speedup_vs_fp64_cycle"] = ref["ms_p50"] / mg[name]["ms_p50"]
+        G.close()
+    mg["note"] = ("CG preconditioned by one cycle per iteration: aggregation (2x2x2) transfers, "
+                  "Galerkin coarse operators, 2+2 Chebyshev-Jacobi steps on [g/10, g], omega 2, "
+                  "dense inverse on the coarsest level (<= 1000 rows); level_us = each level's own "
+                  "kernels per cycle (the per-level breakdown of Sec. 5.3); *_fp32: the cycle in "
+                  "FP32 (values, vectors, arithmetic) inside the FP64 CG")
+
+    return mg
+
+
+def bench_mg(args):
+    """Multigrid-preconditioned CG on the 128^3 Laplacian (the C2 system)."""
+    import numpy as np
+    import torch
+
+    import spkgen
+    from paper_2011_00715_amd import spk
+
+    N = 128
+    A = spkgen.laplace3d7(N)
+    b = spkgen.rhs_uniform(A.n, 0)
+    M = spk.mat_create_csr(dev(A.rowptr), dev(A.col), dev(A.val))
+    bd = dev(b)
+    x = torch.zeros_like(bd)
+    o = spk.ksp_opts(graph_k=args.graph_k)
+    spk.ksp_solve(M, bd, x, o)
+    tj = float(np.median([spk.ksp_solve(M, bd, x, o).seconds for _ in range(3)]))
+    mg = mg_legs(spk, M, A, b, bd, N, tj)
+    v = mg["v_cycle"]
+    out = {
+        "metric": "multigrid-preconditioned CG solves/s to rtol 1e-8",
+        "value": v["solves_per_s"], "unit": "solves/s", "n_gpus": 1, "steps": 5, "warmup": 1,
+        "ms_per_step": v["ms_p50"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64 (the *_fp32 legs: f32 cycle inside f64 CG)", "data": "synthetic",
+        "config": {"workload": "3D 7-point Laplacian 128^3, rhs uniform seed 0; CG preconditioned by one "
+                               "multigrid cycle per iteration, graph_k 1", "jacobi_pcg_ms": tj * 1e3},
+        "multigrid_pcg": mg,
+    }
     M.close()
     return out
 
@@ -743,7 +789,7 @@ def main():
     torch.cuda.set_device(0)
     calibration_copy()
     fn = {"c2": bench_c2, "c3": bench_c3, "c4": bench_c4, "serve": bench_serve,
-          "spectrum": bench_spectrum}[args.workload]
+          "spectrum": bench_spectrum, "mg": bench_mg}[args.workload]
     out = fn(args)
     print(json.dumps(out), flush=True)
 
