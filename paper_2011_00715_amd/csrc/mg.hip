@@ -26,6 +26,11 @@ struct MgLevel {
     // level 0's b and x are the call's own arrays in an FP64 cycle
     void *b = nullptr, *x = nullptr;
     void *r = nullptr, *d0 = nullptr, *d1 = nullptr, *tmp = nullptr;
+    void *x2 = nullptr;  // second x buffer of the levels between the finest and the coarsest
+    // where the level's x currently lives, and a last smoothing step d left
+    // for the parent to add (set while a cycle is enqueued)
+    void *xcur = nullptr;
+    const void *dpend = nullptr;
 };
 
 // Level 0's connection to the FP64 data of a call: the cycle's right-hand
@@ -82,6 +87,12 @@ namespace spk {
     } while (0)
 
 enum { kPartRzMg = 0, kPartPqMg = 1, kPartRrMg = 2, kPartBbMg = 3 };
+
+// Levels up to this many rows fold the prolongation into the post-smoother's
+// residual pass (a CSR pass that forms x + omega P x_c for every gathered
+// column); larger ones keep the two passes, whose SpMV uses the level's own
+// family (on 64^3 the folded CSR pass took 14.8 us against 4.9 + 3.5 us).
+constexpr int kMgFuseRows = 65536;
 
 static int grid_n(int64_t n)
 {
@@ -181,48 +192,34 @@ static void finish(spk_mg *M, const V *d, const SysState *gate, const CycleIo *i
     if (io->np) *io->np = g;
 }
 
-// Chebyshev smoothing of level l: `steps` steps from x (zero unless
-// x0_nonzero).  keep_r: the last step also updates r (its result is
-// restricted); otherwise it only adds d to x.  On level 0 (io set) a start
-// from zero reads the FP64 right-hand side (an FP32 cycle keeps its rounded
-// copy in b), and the post-smoothing (final) ends with finish().
+// Chebyshev steps on level l after the smoother's start (r, d_0 and the
+// level's current x set).  keep_r: the last step also updates r (its result
+// is restricted).  Otherwise the last step only adds d to x: on level 0 it
+// is finish() (z = x + d in FP64, with the CG partial sums), on a coarser
+// level with defer_last it is left to the parent's prolongation (L.dpend).
 template <class V>
-static int smooth(spk_mg *M, int l, bool x0_nonzero, bool keep_r, bool final, const CycleIo *io,
-                  const SysState *gate, hipStream_t s)
+static int cheb_steps(spk_mg *M, int l, bool keep_r, bool defer_last, const CycleIo *io, const SysState *gate,
+                      hipStream_t s)
 {
-    constexpr bool f32 = std::is_same<V, float>::value;
     MgLevel &L = M->lev[l];
     spk_mat *A = L.A;
     const int n = L.n, steps = M->o.smooth_steps;
     const double theta = 0.5 * (L.emax + L.emin), delta = 0.5 * (L.emax - L.emin), sigma = theta / delta;
-    V *b = (V *)L.b, *x = (V *)L.x, *r = (V *)L.r, *tmp = (V *)L.tmp;
+    V *x = (V *)L.xcur, *r = (V *)L.r, *tmp = (V *)L.tmp;
     V *d[2] = {(V *)L.d0, (V *)L.d1};
-    const V *dinv = dinv_of<V>(A);
-    const V inv_theta = (V)(1.0 / theta);
     const dim3 gn(grid_n(n)), tb(kBlock);
-    auto init = [&] {
-        if (f32 && l == 0)  // the FP64 right-hand side, rounded and kept
-            hipLaunchKernelGGL((k_cheb_init<V, double>), gn, tb, 0, s, n, io->b64, (const V *)nullptr, x, r, d[0],
-                               dinv, inv_theta, gate, b);
-        else
-            hipLaunchKernelGGL((k_cheb_init<V, V>), gn, tb, 0, s, n, (const V *)b, (const V *)nullptr, x, r, d[0],
-                               dinv, inv_theta, gate, (V *)nullptr);
-    };
+    L.dpend = nullptr;
     if (steps == 0) {
-        if (!x0_nonzero) init();
-        if (final) finish<V>(M, (const V *)nullptr, gate, io, s);
+        if (!keep_r && l == 0) finish<V>(M, (const V *)nullptr, gate, io, s);
         SPK_HIP(hipGetLastError());
         return SPK_OK;
     }
-    if (x0_nonzero)
-        SPK_TRY(launch_rows<V>(A, x, RowResid<V>{b, r, d[0], dinv, inv_theta}, nullptr, nullptr, gate, tmp, s));
-    else
-        init();
     double rho = 1.0 / sigma;
     for (int k = 0; k < steps; ++k) {
         const bool last = k == steps - 1;
         if (last && !keep_r) {
-            if (final) finish<V>(M, (const V *)d[k & 1], gate, io, s);
+            if (l == 0) finish<V>(M, (const V *)d[k & 1], gate, io, s);
+            else if (defer_last) L.dpend = d[k & 1];
             else hipLaunchKernelGGL((k_cheb_last<V>), gn, tb, 0, s, n, (const V *)d[k & 1], x, gate);
             break;
         }
@@ -232,7 +229,7 @@ static int smooth(spk_mg *M, int l, bool x0_nonzero, bool keep_r, bool final, co
         c.dn = last ? nullptr : d[(k + 1) & 1];
         c.r = r;
         c.x = x;
-        c.dinv = dinv;
+        c.dinv = dinv_of<V>(A);
         c.c1 = (V)(rho_next * rho);
         c.c2 = (V)(2.0 * rho_next / delta);
         c.gate = gate;
@@ -243,11 +240,57 @@ static int smooth(spk_mg *M, int l, bool x0_nonzero, bool keep_r, bool final, co
     return SPK_OK;
 }
 
-// One cycle on level l: x_l from b_l (and from x_l when x0_nonzero); io is
-// set on level 0 only.
+// Smoother start on level l: from zero (x = 0, r = b, d_0 = D^-1 b / theta;
+// on level 0 b comes from the call's FP64 right-hand side, which an FP32
+// cycle keeps rounded in L.b), or from the level's current x.
 template <class V>
-static int enqueue_cycle(spk_mg *M, int l, bool x0_nonzero, const SysState *gate, hipStream_t s,
-                         const CycleIo *io)
+static int smoother_start(spk_mg *M, int l, bool x0_nonzero, const CycleIo *io, const SysState *gate,
+                          hipStream_t s)
+{
+    constexpr bool f32 = std::is_same<V, float>::value;
+    MgLevel &L = M->lev[l];
+    spk_mat *A = L.A;
+    const int n = L.n;
+    const V inv_theta = (V)(1.0 / (0.5 * (L.emax + L.emin)));
+    V *b = (V *)L.b, *x = (V *)L.xcur, *r = (V *)L.r, *d0 = (V *)L.d0;
+    const V *dinv = dinv_of<V>(A);
+    const dim3 gn(grid_n(n)), tb(kBlock);
+    if (x0_nonzero)
+        SPK_TRY(launch_rows<V>(A, x, RowResid<V>{b, r, d0, dinv, inv_theta}, nullptr, nullptr, gate, (V *)L.tmp, s));
+    else if (f32 && l == 0)  // the FP64 right-hand side, rounded and kept
+        hipLaunchKernelGGL((k_cheb_init<V, double>), gn, tb, 0, s, n, io->b64, (const V *)nullptr, x, r, d0, dinv,
+                           inv_theta, gate, b);
+    else
+        hipLaunchKernelGGL((k_cheb_init<V, V>), gn, tb, 0, s, n, (const V *)b, (const V *)nullptr, x, r, d0, dinv,
+                           inv_theta, gate, (V *)nullptr);
+    SPK_HIP(hipGetLastError());
+    return SPK_OK;
+}
+
+template <class V, int Lanes>
+static void launch_resid_prolong(spk_mg *M, int l, const SysState *gate, hipStream_t s)
+{
+    MgLevel &L = M->lev[l];
+    const MgLevel &C = M->lev[l + 1];
+    spk_mat *A = L.A;
+    V *xout = (V *)(L.xcur == L.x ? L.x2 : L.x);
+    // one lane group per row: the pass is a few dependent gathers deep, so
+    // rows are not looped over (a grid-stride loop made 64^3 three times slower)
+    const int grid = std::max(1, std::min(ceil_div(L.n, kBlock / Lanes), kMgMaxPart));
+    hipLaunchKernelGGL((k_mg_resid_prolong<V, Lanes>), dim3(grid), dim3(kBlock), 0, s, L.n,
+                       (const int32_t *)A->rowptr, (const int32_t *)A->col, values_of<V>(A), dinv_of<V>(A),
+                       (const V *)L.b, (const V *)L.xcur, (const V *)C.xcur, (const V *)C.dpend, (V)M->o.omega, L.g,
+                       C.g, xout, (V *)L.r, (V *)L.d0, (V)(1.0 / (0.5 * (L.emax + L.emin))), gate);
+    L.xcur = xout;
+}
+
+// One cycle on level l: x_l from b_l, or from x_l when x0_nonzero.
+// pre_inited: the parent already formed this level's start from zero
+// together with the restriction.  defer_last: leave the last smoothing
+// step's x += d to the parent's prolongation.  io is set on level 0 only.
+template <class V>
+static int enqueue_cycle(spk_mg *M, int l, bool x0_nonzero, bool pre_inited, bool defer_last,
+                         const SysState *gate, hipStream_t s, const CycleIo *io)
 {
     constexpr bool f32 = std::is_same<V, float>::value;
     MgLevel &L = M->lev[l];
@@ -257,25 +300,46 @@ static int enqueue_cycle(spk_mg *M, int l, bool x0_nonzero, const SysState *gate
             hipLaunchKernelGGL(k_mg_round, dim3(grid_n(L.n)), dim3(kBlock), 0, s, L.n, io->b64, (float *)L.b, gate);
         hipLaunchKernelGGL((k_mg_gemv<V>), dim3(ceil_div(L.n, kBlock / kWave)), dim3(kBlock), 0, s, L.n,
                            (const V *)M->cinv, (const V *)L.b, (V *)L.x, gate);
+        L.xcur = L.x;
+        L.dpend = nullptr;
         if (l == 0) finish<V>(M, (const V *)nullptr, gate, io, s);
         SPK_HIP(hipGetLastError());
         SPK_TRY(timer_mark(M, l, s));
         return SPK_OK;
     }
     MgLevel &C = M->lev[l + 1];
+    const bool c_direct = l + 1 == M->nlev - 1;
     SPK_TRY(timer_mark(M, l, s));
-    SPK_TRY(smooth<V>(M, l, x0_nonzero, true, false, io, gate, s));
-    hipLaunchKernelGGL((k_mg_restrict<V>), dim3(grid_n(C.n)), dim3(kBlock), 0, s, L.g, C.g, (const V *)L.r,
-                       (V *)C.b, gate);
+    if (!pre_inited) {
+        if (!x0_nonzero) L.xcur = L.x;
+        SPK_TRY(smoother_start<V>(M, l, x0_nonzero, io, gate, s));
+    }
+    SPK_TRY(cheb_steps<V>(M, l, true, false, io, gate, s));
+    if (c_direct) {
+        hipLaunchKernelGGL((k_mg_restrict<V>), dim3(grid_n(C.n)), dim3(kBlock), 0, s, L.g, C.g, (const V *)L.r,
+                           (V *)C.b, gate);
+    } else {  // restriction and the coarse level's start from zero in one pass
+        C.xcur = C.x;
+        hipLaunchKernelGGL((k_mg_init_restrict<V>), dim3(grid_n(C.n)), dim3(kBlock), 0, s, L.g, C.g,
+                           (const V *)L.r, (V *)C.b, (V *)C.x, (V *)C.r, (V *)C.d0, dinv_of<V>(C.A),
+                           (V)(1.0 / (0.5 * (C.emax + C.emin))), gate);
+    }
     SPK_HIP(hipGetLastError());
     SPK_TRY(timer_mark(M, l, s));
-    SPK_TRY(enqueue_cycle<V>(M, l + 1, false, gate, s, nullptr));
-    if (M->o.cycle == 2 && l + 1 < M->nlev - 1) SPK_TRY(enqueue_cycle<V>(M, l + 1, true, gate, s, nullptr));
+    const bool twice = M->o.cycle == 2 && !c_direct;
+    SPK_TRY(enqueue_cycle<V>(M, l + 1, false, !c_direct, !twice, gate, s, nullptr));
+    if (twice) SPK_TRY(enqueue_cycle<V>(M, l + 1, true, false, true, gate, s, nullptr));
     SPK_TRY(timer_mark(M, l, s));
-    hipLaunchKernelGGL((k_mg_prolong<V>), dim3(grid_n(L.n)), dim3(kBlock), 0, s, L.n, L.g, C.g, (V)M->o.omega,
-                       (const V *)C.x, (V *)L.x, gate);
-    SPK_HIP(hipGetLastError());
-    SPK_TRY(smooth<V>(M, l, true, false, l == 0, io, gate, s));
+    if (l == 0 || L.n > kMgFuseRows) {  // large levels keep their family's SpMV: prolongation, then the residual pass
+        hipLaunchKernelGGL((k_mg_prolong<V>), dim3(grid_n(L.n)), dim3(kBlock), 0, s, L.n, L.g, C.g, (V)M->o.omega,
+                           (const V *)C.xcur, (const V *)C.dpend, (V *)L.xcur, gate);
+        SPK_HIP(hipGetLastError());
+        SPK_TRY(smoother_start<V>(M, l, true, io, gate, s));
+    } else {
+        launch_resid_prolong<V, 8>(M, l, gate, s);
+        SPK_HIP(hipGetLastError());
+    }
+    SPK_TRY(cheb_steps<V>(M, l, false, defer_last, io, gate, s));
     SPK_TRY(timer_mark(M, l, s));
     return SPK_OK;
 }
@@ -284,10 +348,10 @@ static int enqueue_cycle(spk_mg *M, int l, bool x0_nonzero, const SysState *gate
 static int run_cycle(spk_mg *M, const CycleIo &io, const SysState *gate, hipStream_t s)
 {
     MgLevel &L0 = M->lev[0];
-    if (M->f32) return enqueue_cycle<float>(M, 0, false, gate, s, &io);
+    if (M->f32) return enqueue_cycle<float>(M, 0, false, false, false, gate, s, &io);
     L0.b = const_cast<double *>(io.b64);
     L0.x = io.z64;
-    return enqueue_cycle<double>(M, 0, false, gate, s, &io);
+    return enqueue_cycle<double>(M, 0, false, false, false, gate, s, &io);
 }
 
 static int alloc_level_vectors(spk_mg *M, int l)
@@ -301,6 +365,7 @@ static int alloc_level_vectors(spk_mg *M, int l)
         SPK_TRY(mg_vec(M, &L.r, L.n));
         SPK_TRY(mg_vec(M, &L.d0, L.n));
         SPK_TRY(mg_vec(M, &L.d1, L.n));
+        if (l > 0) SPK_TRY(mg_vec(M, &L.x2, L.n));
         // level 0's family may change later (spk_mat_set_kernel on the caller's matrix)
         if (l == 0 || (L.A->kernel != SPK_KERNEL_SELL && L.A->kernel != SPK_KERNEL_STREAM))
             SPK_TRY(mg_vec(M, &L.tmp, L.n));
@@ -422,6 +487,7 @@ static void destroy_mg(spk_mg *M)
         hipFree(L.r);
         hipFree(L.d0);
         hipFree(L.d1);
+        hipFree(L.x2);
         hipFree(L.tmp);
     }
     hipFree(M->cinv);

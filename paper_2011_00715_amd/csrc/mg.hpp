@@ -255,16 +255,95 @@ __global__ void k_mg_restrict(Grid3 g, Grid3 c, const V *__restrict__ r, V *__re
     }
 }
 
+// Index of the aggregate holding fine point i.
+__device__ __forceinline__ int aggregate_of(const Grid3 &g, const Grid3 &c, int i)
+{
+    int i0, i1, i2;
+    grid_coords(g, i, i0, i1, i2);
+    return (i0 >> 1) + c.s0 * ((i1 >> 1) + c.s1 * (i2 >> 1));
+}
+
+// The coarse result x_c, plus the coarse level's last smoothing step d_c
+// when that step was left to this pass (dc null: already added).
+template <class V>
+__device__ __forceinline__ V coarse_value(const V *__restrict__ xc, const V *__restrict__ dc, int I)
+{
+    return dc ? xc[I] + dc[I] : xc[I];
+}
+
 // Coarse-grid correction x += omega P x_c.
 template <class V>
-__global__ void k_mg_prolong(int n, Grid3 g, Grid3 c, V omega, const V *__restrict__ xc, V *__restrict__ x,
-                             const SysState *gate)
+__global__ void k_mg_prolong(int n, Grid3 g, Grid3 c, V omega, const V *__restrict__ xc, const V *__restrict__ dc,
+                             V *__restrict__ x, const SysState *gate)
 {
     if (!mg_go(gate)) return;
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-        int i0, i1, i2;
-        grid_coords(g, i, i0, i1, i2);
-        x[i] = fma(omega, xc[(i0 >> 1) + c.s0 * ((i1 >> 1) + c.s1 * (i2 >> 1))], x[i]);
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+        x[i] = fma(omega, coarse_value(xc, dc, aggregate_of(g, c, i)), x[i]);
+}
+
+// Restriction fused with the coarse level's smoother start from zero:
+// b_c = P^T r (the sum over each aggregate, (z, y, x) order), x_c = 0,
+// r_c = b_c, d_0 = D_c^-1 b_c / theta_c.
+template <class V>
+__global__ void k_mg_init_restrict(Grid3 g, Grid3 c, const V *__restrict__ r, V *__restrict__ bc,
+                                   V *__restrict__ xc, V *__restrict__ rc, V *__restrict__ d0,
+                                   const V *__restrict__ dinv, V inv_theta, const SysState *gate)
+{
+    if (!mg_go(gate)) return;
+    const int nc = c.s0 * c.s1 * c.s2;
+    for (int I = blockIdx.x * blockDim.x + threadIdx.x; I < nc; I += gridDim.x * blockDim.x) {
+        int c0, c1, c2;
+        grid_coords(c, I, c0, c1, c2);
+        V t = V(0);
+        for (int a2 = 0; a2 < 2; ++a2) {
+            const int f2 = 2 * c2 + a2;
+            if (f2 >= g.s2) continue;
+            for (int a1 = 0; a1 < 2; ++a1) {
+                const int f1 = 2 * c1 + a1;
+                if (f1 >= g.s1) continue;
+                const V *rr = r + (size_t)g.s0 * (f1 + (size_t)g.s1 * f2);
+                t += rr[2 * c0];
+                if (2 * c0 + 1 < g.s0) t += rr[2 * c0 + 1];
+            }
+        }
+        bc[I] = t;
+        xc[I] = V(0);
+        rc[I] = t;
+        d0[I] = dinv[I] * t * inv_theta;
+    }
+}
+
+// Prolongation fused with the post-smoother's start on a coarse level (CSR,
+// L lanes per row): with x' = x + omega P x_c formed for every gathered
+// column, r = b - A x', d_0 = D^-1 r / theta, and x' of the row itself goes
+// to x2 (x stays unchanged: other blocks still gather it).
+template <class V, int L>
+__global__ __launch_bounds__(kBlock) void k_mg_resid_prolong(int n, const int32_t *__restrict__ rowptr,
+                                                             const int32_t *__restrict__ col,
+                                                             const V *__restrict__ val, const V *__restrict__ dinv,
+                                                             const V *__restrict__ b, const V *__restrict__ x,
+                                                             const V *__restrict__ xc, const V *__restrict__ dc,
+                                                             V omega, Grid3 g, Grid3 c, V *__restrict__ x2,
+                                                             V *__restrict__ r, V *__restrict__ d0, V inv_theta,
+                                                             const SysState *gate)
+{
+    if (!mg_go(gate)) return;
+    const int lane = threadIdx.x % L;
+    const int groups = gridDim.x * (kBlock / L);
+    for (int i = blockIdx.x * (kBlock / L) + (int)threadIdx.x / L; i < n; i += groups) {
+        V s = V(0);
+        for (int k = rowptr[i] + lane; k < rowptr[i + 1]; k += L) {
+            const int j = col[k];
+            s = fma(val[k], fma(omega, coarse_value(xc, dc, aggregate_of(g, c, j)), x[j]), s);
+        }
+#pragma unroll
+        for (int off = L / 2; off > 0; off >>= 1) s += __shfl_xor(s, off, L);
+        if (lane == 0) {
+            x2[i] = fma(omega, coarse_value(xc, dc, aggregate_of(g, c, i)), x[i]);
+            const V ri = b[i] - s;
+            r[i] = ri;
+            d0[i] = dinv[i] * ri * inv_theta;
+        }
     }
 }
 
