@@ -519,6 +519,8 @@ def bench_c3(args):
                   "error_vs_fp64": float(np.linalg.norm(xm - xg) / np.linalg.norm(xg))},
         "speedup_mixed_vs_fp64": m64 / mmx,
     }
+    log("multigrid")
+    out["multigrid_pcg"] = mg_legs(spk, M, A, b, bd, 160, m64)
     M.close()
     return out
 

@@ -261,3 +261,35 @@ def test_c2_multigrid_fp32_cycle():
     assert res.reason == spk.CONVERGED_RTOL
     assert ro["iterations"] - 1 <= res.iterations <= ro["iterations"] + 2
     assert oracle.nrm2(b - oracle.spmv(A, x.cpu().numpy())) <= 1e-8 * oracle.nrm2(b) * (1 + 1e-6)
+
+
+def test_c3_multigrid_pcg():
+    """Multigrid on the 27-point lognormal 160^3 system: the first coarse
+    level against the oracle's Galerkin product (within 1e-14 of the summed
+    |terms|), one V-cycle against the oracle's cycle, and the FP64- and
+    FP32-cycle solves through the oracle's true residual."""
+    spk = need_gpu()
+    import torch
+
+    A = spkgen.diffusion3d27_lognormal(160, seed=0)
+    M = mat_on_gpu(spk, A)
+    G = spk.mg_create(M, (160, 160, 160))
+    assert [G.info.n[l] for l in range(G.levels)] == [160**3, 80**3, 40**3, 20**3, 10**3]
+    A1 = oracle.galerkin(A, (160, 160, 160))
+    rp, ci, va = spk.mg_copy_level(G, 1)
+    assert np.array_equal(rp, A1.rowptr) and np.array_equal(ci, A1.col)
+    scale = oracle.galerkin(spkgen.CSR(A.n, A.rowptr, A.col, np.abs(A.val)), (160, 160, 160)).val
+    assert np.all(np.abs(va - A1.val) <= 1e-14 * scale)
+    h = oracle.mg_setup(A, (160, 160, 160))
+    b = spkgen.rhs_uniform(A.n, 0)
+    x = torch.zeros(A.n, dtype=torch.float64, device="cuda")
+    spk.mg_apply(G, to_dev(b), x)
+    xc = oracle.mg_cycle(h, b)
+    assert np.max(np.abs(x.cpu().numpy() - xc)) <= 1e-11 * np.max(np.abs(xc))
+    bn = oracle.nrm2(b)
+    for prec in (spk.PREC_FP64, spk.PREC_MIXED):
+        Gp = G if prec == spk.PREC_FP64 else spk.mg_create(M, (160, 160, 160), spk.mg_opts(precision=prec))
+        x.zero_()
+        res = spk.ksp_solve_mg(Gp, to_dev(b), x, spk.ksp_opts(graph_k=1))
+        assert res.reason == spk.CONVERGED_RTOL and res.iterations <= 30
+        assert oracle.nrm2(b - oracle.spmv(A, x.cpu().numpy())) <= 1e-8 * bn * (1 + 1e-6)
