@@ -548,7 +548,8 @@ def bench_c4(args):
     rows = np.random.default_rng(0).integers(0, A.n, 2000)
     yo, ya = oracle.spmv_rows(A, xh, rows)
     res = {}
-    for name, k, p in [("sliced", spk.KERNEL_SLICED, 0), ("merge", spk.KERNEL_MERGE, 0),
+    for name, k, p in [("sliced", spk.KERNEL_SLICED, 2048), ("sliced_lanes4", spk.KERNEL_SLICED, 4),
+                       ("merge", spk.KERNEL_MERGE, 0),
                        ("vector32", spk.KERNEL_VECTOR, 32), ("vector8", spk.KERNEL_VECTOR, 8),
                        ("stream", spk.KERNEL_STREAM, 0)]:
         spk.mat_set_kernel(M, k, p)
@@ -587,7 +588,7 @@ def bench_c4(args):
                 "median launch time; the sliced family also moves 4(8n+1) row pointers and writes and "
                 "reads 8n partial products (format_bytes_f64)",
     }
-    spk.mat_set_kernel(M, spk.KERNEL_SLICED, 0)
+    spk.mat_set_kernel(M, spk.KERNEL_SLICED, 2048)
     out["format_bytes_f64"] = M.info.format_bytes_spmv_f64
     out["kernels"]["sliced"]["format_gbps"] = M.info.format_bytes_spmv_f64 / res["sliced"]["us"] / 1e3
     M.close()

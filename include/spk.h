@@ -81,10 +81,12 @@ enum {
                                entries of each row split by which eighth of
                                [0, n) their column falls in; XCD s computes
                                the products of slice s (its eighth of x stays
-                               in its own L2) into 8 partial vectors that a
-                               second pass sums per row in slice order.  A
-                               copy of the matrix built at selection
-                               (12 nnz + 4 (8n + 1) bytes + 8n partials) */
+                               in its own L2; a merge path over the stacked
+                               slices, or lanes per slice row) into 8 partial
+                               vectors that a second pass sums per row in
+                               slice order.  A copy of the matrix built at
+                               selection (12 nnz + 4 (8n + 1) bytes + 8n
+                               partials) */
 };
 
 /* status codes */
@@ -170,8 +172,10 @@ int spk_mat_create_csr(int32_t n, int64_t nnz, const int32_t *rowptr,
 /* Force an SpMV kernel family (testing and A/B runs).  param: lanes per row
  * for VECTOR (1..64, power of two), rows per tile for STREAM (0 = automatic),
  * column-offset bits for SELL (0 = automatic, 16 or 32; SPK_EINVAL when the
- * rows exceed 255 entries or the offsets do not fit), lanes per slice row for
- * SLICED (0 = automatic, else a power of two in 1..64), ignored for MERGE.
+ * rows exceed 255 entries or the offsets do not fit), for SLICED 0
+ * (automatic: the merge path over the slices when 8n + nnz < 2^31, else
+ * lanes per slice row), a power of two in 1..64 (lanes per slice row) or
+ * 2048 (merge path over the slices), ignored for MERGE.
  * Invalidates cached solver graphs. */
 int spk_mat_set_kernel(spk_mat *A, int kernel, int32_t param);
 

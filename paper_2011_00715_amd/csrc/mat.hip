@@ -358,7 +358,8 @@ void update_info(spk_mat *A)
     I.n = A->n;
     I.nnz = A->nnz;
     I.kernel = A->kernel;
-    I.lanes = A->kernel == SPK_KERNEL_VECTOR || A->kernel == SPK_KERNEL_SLICED ? A->lanes
+    I.lanes = A->kernel == SPK_KERNEL_SLICED ? (A->xs_merge ? kMergeItems : A->lanes)
+              : A->kernel == SPK_KERNEL_VECTOR ? A->lanes
               : A->kernel == SPK_KERNEL_STREAM ? A->R
               : A->kernel == SPK_KERNEL_SELL ? 8 * A->sell_cw : kMergeItems;
     I.has_f32 = A->val32 != nullptr;
@@ -444,17 +445,17 @@ static bool merge_fits(const spk_mat *A) { return (int64_t)A->n + A->nnz < 0x7ff
 
 // Row-length statistics -> kernel family (stream for short, even rows; vector
 // for long, even rows; merge-path for skewed lengths).
-// The sliced layout pays when x does not fit one XCD's 4 MB L2, rows reach
-// across it (scattered columns) and row lengths are even: 1.43 against
-// 2.01 ms (SELL) and 2.13 ms (merge) for 4M rows of 32 uniform random
-// columns.  With skewed rows (the power-law C4 matrix) the long slice rows
-// leave it no faster than merge path (1.95 against 1.92 ms), and banded
+// The sliced layout pays when x does not fit one XCD's 4 MB L2 and rows
+// reach across it (scattered columns).  With the merge path over the slices:
+// 1.15 ms against 2.02 ms (SELL) and 2.13 ms (merge) for 4M rows of 32
+// uniform random columns, 1.16 against 1.94 ms (merge) for the skewed
+// power-law C4 rows; lanes per slice row take 1.44 and 1.95 ms.  Banded
 // matrices keep their x window in L2 anyway.
 static bool sliced_wanted(const spk_mat *A)
 {
     const double mean = A->n ? (double)A->stats.sum_len / A->n : 0.0;
     return sliced_fits(A) && A->n >= (1 << 19) && mean >= 8.0 &&
-           (int64_t)A->stats.max_delta * kXcd >= A->n && A->stats.max_len <= 8 * mean + 8;
+           (int64_t)A->stats.max_delta * kXcd >= A->n && (!sliced_skewed(A) || sliced_merge_fits(A));
 }
 
 static void choose_kernel(spk_mat *A, bool allow_sell = true, bool allow_sliced = true)
@@ -489,6 +490,7 @@ static void choose_kernel(spk_mat *A, bool allow_sell = true, bool allow_sliced 
     if (allow_sliced && sliced_wanted(A)) {
         A->kernel = SPK_KERNEL_SLICED;
         A->lanes = sliced_lanes(A);
+        A->xs_merge = sliced_merge_fits(A) ? 1 : 0;
         A->R = 256;
     }
 }
@@ -772,7 +774,8 @@ static int create_impl(int32_t n, int64_t nnz, const int32_t *rowptr, const int3
     }
     if (A->kernel != SPK_KERNEL_STREAM) A->R = 256;
     if (A->kernel == SPK_KERNEL_STREAM && A->R == 0) A->R = 32;
-    if (A->kernel == SPK_KERNEL_SLICED && setup_sliced(A, s) != SPK_OK) {
+    if (A->kernel == SPK_KERNEL_SLICED &&
+        (setup_sliced(A, s) != SPK_OK || (A->xs_merge && setup_sliced_merge(A, s) != SPK_OK))) {
         choose_kernel(A, true, false);  // no room for the copy: the unsliced family
         if (A->kernel != SPK_KERNEL_STREAM) A->R = 256;
     }
@@ -894,14 +897,21 @@ int spk_mat_set_kernel(spk_mat *A, int kernel, int32_t param)
         break;
     }
     case SPK_KERNEL_SLICED: {
-        if (param != 0 && (param < 1 || param > 64 || (param & (param - 1)))) {
-            set_error("lanes %d not 0 or a power of two in [1, 64]", param);
+        const bool lanes_ok = param >= 1 && param <= 64 && !(param & (param - 1));
+        if (param != 0 && param != kMergeItems && !lanes_ok) {
+            set_error("sliced parameter %d: 0, a power of two in [1, 64] or %d (merge path)", param, kMergeItems);
             return SPK_EINVAL;
         }
-        const int rc = setup_sliced(A, nullptr);
+        int rc = setup_sliced(A, nullptr);
         if (rc) return rc;
+        const int merge = param == kMergeItems || (param == 0 && sliced_merge_fits(A));
+        if (merge) {
+            rc = setup_sliced_merge(A, nullptr);
+            if (rc) return rc;
+        }
         A->kernel = SPK_KERNEL_SLICED;
-        A->lanes = param ? param : sliced_lanes(A);
+        A->xs_merge = merge;
+        A->lanes = lanes_ok ? param : sliced_lanes(A);
         A->R = 256;
         break;
     }
@@ -915,7 +925,7 @@ int spk_mat_set_kernel(spk_mat *A, int kernel, int32_t param)
         SPK_HIP(hipStreamSynchronize(nullptr));
     }
     if (kernel == SPK_KERNEL_AUTO && A->kernel == SPK_KERNEL_SLICED) {
-        if (setup_sliced(A, nullptr) != SPK_OK) {
+        if (setup_sliced(A, nullptr) != SPK_OK || (A->xs_merge && setup_sliced_merge(A, nullptr) != SPK_OK)) {
             choose_kernel(A, true, false);
             if (A->kernel == SPK_KERNEL_MERGE) {
                 const int r2 = setup_merge(A, nullptr);

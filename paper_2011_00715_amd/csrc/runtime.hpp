@@ -99,6 +99,12 @@ struct spk_mat {
     double *xs_val = nullptr;
     float *xs_val32 = nullptr;
     void *xs_part = nullptr;     // 8n partial products (FP64 or FP32)
+    int xs_merge = 0;            // 1: merge path over the stacked slices, 0: lanes per slice row
+    int xs_tiles = 0;            // merge-path tiles of the stacked slices (0: not built)
+    int xs_tile_grid = 0;        // blocks of the merge launch (8 x the most tiles of a slice)
+    int32_t *xs_tile_row = nullptr, *xs_tile_k = nullptr, *xs_carry_row = nullptr;
+    int32_t *xs_slice_tile = nullptr;  // kSlices + 1 tile ranges
+    void *xs_carry_val = nullptr;
     spk::Workspace *ws = nullptr;
     spk::MultiWs *mws = nullptr;  // multi-right-hand-side solver workspace
     int64_t bytes = 0;
@@ -123,6 +129,9 @@ int sliced_lanes(const spk_mat *A);
 int setup_sliced(spk_mat *A, hipStream_t s);
 void free_sliced(spk_mat *A);
 int ensure_sliced_f32(spk_mat *A, hipStream_t s);
+int setup_sliced_merge(spk_mat *A, hipStream_t s);
+bool sliced_skewed(const spk_mat *A);
+bool sliced_merge_fits(const spk_mat *A);
 template <class V>
 int launch_sliced(const spk_mat *A, const V *x, V *y, hipStream_t s, const SysState *gst, int gmode);
 template <class V>

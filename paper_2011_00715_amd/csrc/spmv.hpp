@@ -372,24 +372,18 @@ struct MergeLds {
     int32_t sk[kBlock];
 };
 
-// One merge-path tile per block.  Rows that end inside the tile are written
-// (complete rows directly, rows split across lanes after a segmented scan);
-// the partial of the row still open at the tile end goes to carry_{row,val}.
+// Merge-path tile t, computed by one block.  Rows that end inside the tile
+// are written (complete rows directly, rows split across lanes after a
+// segmented scan); the partial of the row still open at the tile end goes to
+// carry_{row,val}.
 template <class V>
-__global__ __launch_bounds__(kBlock) void k_spmv_merge(int n, int nnz,
-                                                       const int32_t *__restrict__ rowptr,
-                                                       const int32_t *__restrict__ col,
-                                                       const V *__restrict__ val,
-                                                       const V *__restrict__ x, V *__restrict__ y,
-                                                       const int32_t *__restrict__ tile_row,
-                                                       const int32_t *__restrict__ tile_k,
-                                                       int32_t *__restrict__ carry_row,
-                                                       V *__restrict__ carry_val,
-                                                       const SysState *gate_st, int gate_mode)
+__device__ __forceinline__ void merge_tile(int t, int n, const int32_t *__restrict__ rowptr,
+                                           const int32_t *__restrict__ col, const V *__restrict__ val,
+                                           const V *__restrict__ x, V *__restrict__ y,
+                                           const int32_t *__restrict__ tile_row,
+                                           const int32_t *__restrict__ tile_k, int32_t *__restrict__ carry_row,
+                                           V *__restrict__ carry_val, MergeLds<V> &sm)
 {
-    if (gate_st && !gate_open(gate_st, gate_mode)) return;
-    __shared__ MergeLds<V> sm;
-    const int t = blockIdx.x;
     const int i0 = tile_row[t], k0 = tile_k[t];
     const int i1 = tile_row[t + 1], k1 = tile_k[t + 1];
     const int nrows = i1 - i0;   // row ends inside the tile
@@ -468,6 +462,25 @@ __global__ __launch_bounds__(kBlock) void k_spmv_merge(int n, int nnz,
         carry_row[t] = i0 + r;
         carry_val[t] = sm.sv[cur][threadIdx.x];
     }
+}
+
+// One merge-path tile per block.
+template <class V>
+__global__ __launch_bounds__(kBlock) void k_spmv_merge(int n, int nnz,
+                                                       const int32_t *__restrict__ rowptr,
+                                                       const int32_t *__restrict__ col,
+                                                       const V *__restrict__ val,
+                                                       const V *__restrict__ x, V *__restrict__ y,
+                                                       const int32_t *__restrict__ tile_row,
+                                                       const int32_t *__restrict__ tile_k,
+                                                       int32_t *__restrict__ carry_row,
+                                                       V *__restrict__ carry_val,
+                                                       const SysState *gate_st, int gate_mode)
+{
+    if (gate_st && !gate_open(gate_st, gate_mode)) return;
+    (void)nnz;
+    __shared__ MergeLds<V> sm;
+    merge_tile<V>(blockIdx.x, n, rowptr, col, val, x, y, tile_row, tile_k, carry_row, carry_val, sm);
 }
 
 // Adds the carries of rows that span tiles, in tile order; one lane per chain.

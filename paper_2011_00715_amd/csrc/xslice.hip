@@ -30,8 +30,79 @@ int sliced_lanes(const spk_mat *A)
     return L >= 4 ? L / 2 : 2;           // halved: short slice rows leave half the lanes idle otherwise
 }
 
+// The merge path over the stacked slices has int32 diagonals.
+bool sliced_merge_fits(const spk_mat *A) { return (int64_t)kSlices * A->n + A->nnz < 0x7fff0000LL; }
+
+// Rows too uneven for a fixed number of lanes per slice row.
+bool sliced_skewed(const spk_mat *A)
+{
+    const double mean = A->n ? (double)A->nnz / A->n : 0.0;
+    return A->stats.max_len > 8 * mean + 8;
+}
+
+static void free_sliced_merge(spk_mat *A)
+{
+    hipFree(A->xs_tile_row);
+    hipFree(A->xs_tile_k);
+    hipFree(A->xs_carry_row);
+    hipFree(A->xs_carry_val);
+    hipFree(A->xs_slice_tile);
+    A->xs_tile_row = A->xs_tile_k = A->xs_carry_row = A->xs_slice_tile = nullptr;
+    A->xs_carry_val = nullptr;
+    if (A->xs_tiles) A->bytes -= 20 * ((int64_t)A->xs_tiles + 1);
+    A->xs_tiles = 0;
+}
+
+// Merge-path partition of the stacked slices (8n rows, nnz entries) and each
+// slice's tile range.
+int setup_sliced_merge(spk_mat *A, hipStream_t s)
+{
+    if (A->xs_tiles) return SPK_OK;
+    if (!A->xs_ptr) { set_error("internal: no sliced layout"); return SPK_EINVAL; }
+    const int n = A->n;
+    const int64_t rows = (int64_t)kSlices * n;
+    const int64_t items = rows + A->nnz;
+    if (items >= 0x7fff0000LL) { set_error("merge path over the slices needs 8n + nnz < 2^31"); return SPK_EINVAL; }
+    const int T = (int)((items + kMergeItems - 1) / kMergeItems);
+    int32_t head[kSlices] = {};
+    for (int q = 0; q < kSlices; ++q)
+        SPK_HIP(hipMemcpyAsync(&head[q], A->xs_ptr + (size_t)q * n, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    SPK_HIP(hipStreamSynchronize(s));
+    int32_t st[kSlices + 1];
+    int most = 0;
+    for (int q = 0; q < kSlices; ++q) {
+        const int64_t d = (int64_t)q * n + head[q];  // merge-path diagonal where slice q starts
+        st[q] = (int32_t)((d + kMergeItems - 1) / kMergeItems);
+    }
+    st[kSlices] = T;
+    for (int q = 0; q < kSlices; ++q) most = std::max(most, st[q + 1] - st[q]);
+    hipError_t e = hipMalloc(&A->xs_tile_row, sizeof(int32_t) * ((size_t)T + 1));
+    if (e == hipSuccess) e = hipMalloc(&A->xs_tile_k, sizeof(int32_t) * ((size_t)T + 1));
+    if (e == hipSuccess) e = hipMalloc(&A->xs_carry_row, sizeof(int32_t) * (size_t)T);
+    if (e == hipSuccess) e = hipMalloc(&A->xs_carry_val, sizeof(double) * (size_t)T);
+    if (e == hipSuccess) e = hipMalloc(&A->xs_slice_tile, sizeof(int32_t) * (kSlices + 1));
+    if (e == hipSuccess) e = hipMemcpyAsync(A->xs_slice_tile, st, sizeof(st), hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) {
+        free_sliced_merge(A);
+        return hip_fail(e, "sliced merge setup", __FILE__, __LINE__);
+    }
+    A->xs_tiles = T;
+    A->xs_tile_grid = std::max(1, most) * kSlices;
+    A->bytes += 20 * ((int64_t)T + 1);
+    hipLaunchKernelGGL(k_merge_partition, dim3(ceil_div(T + 1, kBlock)), dim3(kBlock), 0, s, (int)rows,
+                       (int)A->nnz, (const int32_t *)A->xs_ptr, T, A->xs_tile_row, A->xs_tile_k);
+    e = hipGetLastError();
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+        free_sliced_merge(A);
+        return hip_fail(e, "sliced merge partition", __FILE__, __LINE__);
+    }
+    return SPK_OK;
+}
+
 void free_sliced(spk_mat *A)
 {
+    free_sliced_merge(A);
     if (A->xs_ptr) {
         A->bytes -= 4 * ((int64_t)kSlices * A->n + 1) + 12 * A->nnz + 8 * (int64_t)kSlices * A->n;
         if (A->xs_val32) A->bytes -= 4 * A->nnz;
@@ -127,6 +198,17 @@ int launch_sliced(const spk_mat *A, const V *x, V *y, hipStream_t s, const SysSt
         return SPK_EINVAL;
     }
     V *part = (V *)A->xs_part;
+    if (A->xs_merge) {
+        if (!A->xs_tiles) { set_error("internal: no merge partition of the slices"); return SPK_EINVAL; }
+        const int rows = kSlices * A->n;
+        V *cv = (V *)A->xs_carry_val;
+        hipLaunchKernelGGL((k_spmv_xs_merge<V>), dim3(A->xs_tile_grid), dim3(kBlock), 0, s, rows,
+                           (const int32_t *)A->xs_ptr, (const int32_t *)A->xs_col, xval, x, part,
+                           (const int32_t *)A->xs_tile_row, (const int32_t *)A->xs_tile_k, A->xs_carry_row, cv,
+                           (const int32_t *)A->xs_slice_tile, gst, gmode);
+        hipLaunchKernelGGL((k_merge_fixup<V>), dim3(ceil_div(A->xs_tiles, kBlock)), dim3(kBlock), 0, s, rows,
+                           A->xs_tiles, (const int32_t *)A->xs_carry_row, (const V *)cv, part, gst, gmode);
+    } else {
     switch (A->lanes) {
     case 1: launch_xs_l<V, 1>(A, xval, x, part, s, gst, gmode); break;
     case 2: launch_xs_l<V, 2>(A, xval, x, part, s, gst, gmode); break;
@@ -135,6 +217,7 @@ int launch_sliced(const spk_mat *A, const V *x, V *y, hipStream_t s, const SysSt
     case 16: launch_xs_l<V, 16>(A, xval, x, part, s, gst, gmode); break;
     case 32: launch_xs_l<V, 32>(A, xval, x, part, s, gst, gmode); break;
     default: launch_xs_l<V, 64>(A, xval, x, part, s, gst, gmode); break;
+    }
     }
     hipLaunchKernelGGL((k_xs_reduce<V>), dim3(grid_rows(A->n)), dim3(kBlock), 0, s, A->n, (const V *)part, y, gst,
                        gmode);

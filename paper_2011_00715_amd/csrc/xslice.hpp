@@ -84,6 +84,28 @@ __global__ __launch_bounds__(kBlock) void k_spmv_xs(int n, const int32_t *__rest
     }
 }
 
+// The stacked slices as one merge path (for skewed rows, whose long slice
+// rows leave lane-per-row groups unbalanced): the tiles whose start lies in
+// slice s are tiles slice_tile[s] .. slice_tile[s+1]-1, and block b takes the
+// (b / 8)-th of them for s = b % 8, so a slice's tiles stay on its XCD.
+template <class V>
+__global__ __launch_bounds__(kBlock) void k_spmv_xs_merge(int rows, const int32_t *__restrict__ xptr,
+                                                          const int32_t *__restrict__ xcol,
+                                                          const V *__restrict__ xval, const V *__restrict__ x,
+                                                          V *__restrict__ part, const int32_t *__restrict__ tile_row,
+                                                          const int32_t *__restrict__ tile_k,
+                                                          int32_t *__restrict__ carry_row, V *__restrict__ carry_val,
+                                                          const int32_t *__restrict__ slice_tile,
+                                                          const SysState *gate_st, int gate_mode)
+{
+    if (gate_st && !gate_open(gate_st, gate_mode)) return;
+    const int s = blockIdx.x % kSlices;
+    const int t = slice_tile[s] + (int)blockIdx.x / kSlices;
+    if (t >= slice_tile[s + 1]) return;
+    __shared__ MergeLds<V> sm;
+    merge_tile<V>(t, rows, xptr, xcol, xval, x, part, tile_row, tile_k, carry_row, carry_val, sm);
+}
+
 // y_i = sum over s = 0..7 of part[s * n + i], in that order.
 template <class V>
 __global__ __launch_bounds__(kBlock) void k_xs_reduce(int n, const V *__restrict__ part, V *__restrict__ y,

@@ -43,6 +43,8 @@ def spmv_bound_rows(A, kernel, lanes, u):
         f = L + 1
     elif kernel == "vector":
         f = np.ceil(L / lanes) + math.log2(lanes) + 2
+    elif kernel == "sliced" and lanes == 2048:  # merge path over the slices, then 8 partials
+        f = 8 + 8 + np.ceil(L / 2048) + 4 + 8
     elif kernel == "sliced":  # vector order within each of 8 column slices, then 8 partials in order
         f = np.ceil(L / lanes) + math.log2(lanes) + 8 + 2
     else:

@@ -108,9 +108,8 @@ def test_c4_powerlaw_spmv_all_kernels():
 
     A = spkgen.powerlaw_spd(4_000_000, seed=0)
     M = mat_on_gpu(spk, A, flags=spk.MAT_MIXED)
-    assert spk.KERNEL_NAMES[M.info.kernel] == "merge"
-    spk.mat_set_kernel(M, spk.KERNEL_SLICED, 0)
-    assert M.info.lanes == 4
+    assert spk.KERNEL_NAMES[M.info.kernel] == "sliced"
+    assert M.info.lanes == 2048  # skewed rows: merge path over the slices
     assert M.info.row_max == A.row_lengths().max()
     rows = _sample_rows(A.n, 2)
     x = spkgen.rhs_uniform(A.n, 0)
@@ -128,7 +127,8 @@ def test_c4_powerlaw_spmv_all_kernels():
 
     check_f32()
     for k, p, tol in ((spk.KERNEL_MERGE, 0, 1e-14), (spk.KERNEL_VECTOR, 32, 1e-14),
-                      (spk.KERNEL_VECTOR, 64, 1e-14), (spk.KERNEL_SLICED, 2, 1e-14)):
+                      (spk.KERNEL_VECTOR, 64, 1e-14), (spk.KERNEL_SLICED, 2, 1e-14),
+                      (spk.KERNEL_SLICED, 4, 1e-14)):
         spk.mat_set_kernel(M, k, p)
         _spmv_sampled(spk, M, A, x, rows, tol)
     spk.mat_set_kernel(M, spk.KERNEL_MERGE, 0)

@@ -12,7 +12,7 @@ from gpu_util import U32, U64, check_spmv, mat_on_gpu, need_gpu, spmv_bound_rows
 pytestmark = pytest.mark.gpu
 
 KERNELS = [("auto", 0), ("stream", 0), ("stream", 64), ("stream", 8), ("merge", 0), ("sell", 0),
-           ("sell", 32), ("sliced", 0), ("sliced", 1), ("sliced", 16)] + [("vector", L) for L in (1, 2, 4, 8, 16, 32, 64)]
+           ("sell", 32), ("sliced", 0), ("sliced", 1), ("sliced", 16), ("sliced", 2048)] + [("vector", L) for L in (1, 2, 4, 8, 16, 32, 64)]
 
 
 def _set(spk, M, kernel, param):
@@ -71,7 +71,7 @@ def test_spmv_parity_fp64(kernel, param):
 
 
 @pytest.mark.parametrize("kernel,param", [("auto", 0), ("stream", 0), ("merge", 0), ("vector", 4),
-                                          ("vector", 64), ("sell", 0), ("sliced", 0)])
+                                          ("vector", 64), ("sell", 0), ("sliced", 0), ("sliced", 2048)])
 def test_spmv_parity_fp32(kernel, param):
     spk = need_gpu()
     for name, A, integer in _matrices():
@@ -289,12 +289,12 @@ def test_jacobi_and_vector_kernels():
 
 @pytest.mark.parametrize("case", ["even_rows", "powerlaw"])
 def test_sliced_selection_solves_and_fp32(case):
-    """Scattered-column matrices whose x (4.8 MB) exceeds one XCD's L2: with
-    even row lengths (16 uniform picks per row, symmetrised) the
-    column-sliced family is selected, with power-law rows merge path stays
-    and the sliced family is forced; FP64 and FP32 products meet their
-    bounds, a one-lane launch is bit-exact on integers, and FP64 / mixed
-    Jacobi-PCG solves with it match the oracle's counts."""
+    """Scattered-column matrices whose x (4.8 MB) exceeds one XCD's L2, with
+    even row lengths (16 uniform picks per row, symmetrised) or power-law
+    rows, select the column-sliced family (merge path over the slices);
+    FP64 and FP32 products meet their bounds, one-lane, four-lane and merge
+    launches are bit-exact on integers, and FP64 / mixed Jacobi-PCG solves
+    with it match the oracle's counts."""
     spk = need_gpu()
     import torch
 
@@ -303,12 +303,7 @@ def test_sliced_selection_solves_and_fp32(case):
     else:
         A = spkgen.powerlaw_spd(600_000, seed=5)
     M = mat_on_gpu(spk, A, flags=spk.MAT_MIXED)
-    if case == "even_rows":
-        assert spk.KERNEL_NAMES[M.info.kernel] == "sliced" and M.info.lanes == 4
-    else:
-        assert spk.KERNEL_NAMES[M.info.kernel] == "merge"
-        spk.mat_set_kernel(M, spk.KERNEL_SLICED, 0)
-        assert M.info.lanes == 4
+    assert spk.KERNEL_NAMES[M.info.kernel] == "sliced" and M.info.lanes == 2048  # merge path over the slices
     x = spkgen.rhs_uniform(A.n, 1)
     y = torch.empty(A.n, dtype=torch.float64, device="cuda")
     spk.mat_mult(M, to_dev(x), y)
@@ -319,7 +314,7 @@ def test_sliced_selection_solves_and_fp32(case):
     spk.mat_mult_f32(M, to_dev(x32), y32)
     v32 = A.val.astype(np.float32)
     Af = spkgen.CSR(A.n, A.rowptr, A.col, v32.astype(np.float64))
-    bound = spmv_bound_rows(A, "sliced", 4, U32) + U32
+    bound = spmv_bound_rows(A, "sliced", M.info.lanes, U32) + U32
     check_spmv(y32.cpu().numpy().astype(np.float64), oracle.spmv_f32(A, x32, val32=v32).astype(np.float64),
                oracle.spmv_abs(Af, x32.astype(np.float64)), bound, "sliced fp32")
     # integer data: exact whatever the order
@@ -329,9 +324,10 @@ def test_sliced_selection_solves_and_fp32(case):
     xi = np.random.default_rng(2).integers(-20, 20, A.n).astype(np.float64)
     spk.mat_mult(Mi, to_dev(xi), y)
     assert np.array_equal(y.cpu().numpy(), oracle.spmv(Ai, xi))
-    spk.mat_set_kernel(Mi, spk.KERNEL_SLICED, 1)
-    spk.mat_mult(Mi, to_dev(xi), y)
-    assert np.array_equal(y.cpu().numpy(), oracle.spmv(Ai, xi))
+    for p in (1, 4, 2048):
+        spk.mat_set_kernel(Mi, spk.KERNEL_SLICED, p)
+        spk.mat_mult(Mi, to_dev(xi), y)
+        assert np.array_equal(y.cpu().numpy(), oracle.spmv(Ai, xi))
     # solves on the selected family
     b = spkgen.rhs_uniform(A.n, 0)
     _, ro, _ = oracle.pcg(A, b)
