@@ -558,6 +558,23 @@ static int drain_one_step(spk_server *S)
     return SPK_OK;
 }
 
+// Writes one byte per page of a fresh pinned allocation, with several host
+// threads, so that its pages are mapped before submissions copy into them:
+// the first CPU write to a page costs a fault (copying a 74 MB system took
+// 4.9 ms into untouched pinned pages against 0.96 ms into touched ones).
+static void touch_pages(char *p, int64_t bytes)
+{
+    constexpr int64_t kPage = 4096;
+    const int nt = 8;
+    std::vector<std::thread> th;
+    for (int t = 0; t < nt; ++t)
+        th.emplace_back([=] {
+            const int64_t a = bytes * t / nt / kPage * kPage, e = bytes * (t + 1) / nt;
+            for (int64_t o = a; o < e; o += kPage) p[o] = 0;
+        });
+    for (auto &x : th) x.join();
+}
+
 }  // namespace spk
 
 extern "C" {
@@ -628,10 +645,12 @@ int spk_server_create(const spk_server_opts *opts, void *stream, spk_server **ou
     }
     if (o.pinned_bytes > 0 && rc == SPK_OK) {
         // best effort: without the pool, submissions use pageable memory
-        if (hipHostMalloc((void **)&S->pin_base, o.pinned_bytes, hipHostMallocDefault) == hipSuccess)
+        if (hipHostMalloc((void **)&S->pin_base, o.pinned_bytes, hipHostMallocDefault) == hipSuccess) {
             S->pin_arena.init(o.pinned_bytes);
-        else
+            touch_pages(S->pin_base, o.pinned_bytes);
+        } else {
             S->pin_base = nullptr;
+        }
     }
     if (rc == SPK_OK) {
         for (int i = 0; i < kTableRing; ++i) chk(hipEventRecord(S->ev_table[i], S->s), "event record");
