@@ -58,10 +58,19 @@ enum {
                               spk_mat_mult_f32 and mixed-precision solves) */
     SPK_MAT_VALIDATE = 2,  /* check the CSR on the device (monotone rowptr,
                               columns in range and strictly ascending) */
-    SPK_MAT_BORROW = 4     /* SPK_MEM_DEVICE only: keep the caller's rowptr,
+    SPK_MAT_BORROW = 4,    /* SPK_MEM_DEVICE only: keep the caller's rowptr,
                               col and values instead of copying them; the
                               caller keeps them alive and unchanged until
                               spk_mat_destroy */
+    SPK_MAT_STREAM = 8     /* read the SELL layout with nontemporal loads
+                              whatever its size.  Default: ordinary loads when
+                              its entries, slice offsets and row lengths take
+                              at most 192 MB in the precision of the product
+                              (they then stay in the 256 MB Infinity Cache
+                              from one product to the next), nontemporal
+                              loads above (a matrix that cannot stay cached
+                              must not evict the vectors).  Changes speed
+                              only: the products are the same bits. */
 };
 
 /* SpMV kernel families (selected from row-length statistics at create) */
@@ -133,7 +142,10 @@ typedef struct {
     int64_t bytes_pcg_iter_f32;  /* one FP32 inner iteration: 8 nnz + 4 (n+1) + 48 n */
     int64_t device_bytes;    /* device memory held by the handle */
     int32_t zero_diag_rows;  /* rows without a nonzero diagonal */
-    int32_t pad_;
+    int32_t cached_loads;    /* SELL layout read with ordinary (cache-allocating)
+                                loads: bit 0 by FP64 products, bit 1 by FP32
+                                products; otherwise nontemporal (see
+                                SPK_MAT_STREAM); 0 for the other kernels */
     int64_t format_bytes_spmv_f64;  /* algorithmic bytes of one FP64 SpMV in the
                                        storage the selected kernel reads (equal
                                        to bytes_spmv_f64 except for SELL:
@@ -450,8 +462,11 @@ double spk_now(void);
 int spk_runtime_version(void);
 
 /* Measurement helpers (Sec. 5.1: work-time spectrum of vector copies):
- * stream-copy n doubles from src to dst, and write `bytes` of scratch to
- * evict the Infinity Cache before a cold measurement. */
+ * stream-copy n doubles from src to dst, and read `bytes` of scratch to
+ * evict the Infinity Cache before a cold measurement (the cache then holds
+ * clean scratch lines: the next kernel reads from HBM and writes back
+ * nothing for the eviction).  scratch is device memory of at least `bytes`
+ * bytes; its contents are left unchanged. */
 int spk_bw_copy(int64_t n, const double *src, double *dst, void *stream);
 int spk_cache_flush(void *scratch, int64_t bytes, void *stream);
 

@@ -80,6 +80,7 @@ struct SysDesc {
     double *hist;                     // device history (hist_len) or null
     // SELL-64 copy of the matrix (used when `sell_cw` is nonzero)
     int32_t sell_cw;
+    int32_t sell_plain;  // kSellPlain64/32 load-policy bits
     const int32_t *sell_ptr;
     const void *sell_col;
     const uint8_t *sell_len;

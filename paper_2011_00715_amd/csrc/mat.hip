@@ -254,11 +254,20 @@ __global__ __launch_bounds__(kBlock) void k_copy(int64_t m, const dvec2 *__restr
     }
 }
 
-__global__ __launch_bounds__(kBlock) void k_scribble(int64_t m, dvec2 *__restrict__ b, double v)
+// Cache eviction by reading: the Infinity Cache ends up holding clean lines
+// of the scratch buffer, so the next kernel finds none of its data cached and
+// pays no write-back of dirty lines left by the eviction itself.  The store
+// only happens for a sum no real buffer of finite values produces; it keeps
+// the loads from being optimised away.
+__global__ __launch_bounds__(kBlock) void k_evict(int64_t m, dvec2 *__restrict__ b)
 {
+    double s = 0.0;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < m;
-         i += (int64_t)gridDim.x * blockDim.x)
-        b[i] = dvec2{v, v};
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const dvec2 v = b[i];
+        s += v.x + v.y;
+    }
+    if (s == -1.0e308) b[0] = dvec2{s, s};
 }
 
 // ------------------------------------------------------------------ SpMV dispatch
@@ -304,7 +313,7 @@ int launch_spmv(const spk_mat *A, const V *val, const V *x, V *y, hipStream_t s,
             set_error("internal: gated SELL SpMV or no SELL layout");
             return SPK_EINVAL;
         }
-        const SellView sv{A->sell_ptr, A->sell_col, A->sell_len};
+        const SellView sv{A->sell_ptr, A->sell_col, A->sell_len, A->sell_plain};
         const V *sval = std::is_same<V, double>::value ? (const V *)A->sell_val : (const V *)A->sell_val32;
         (void)val;
         // up to one wavefront per slice
@@ -386,6 +395,7 @@ void update_info(spk_mat *A)
     I.bytes_pcg_iter_f32 = 8 * nz + 4 * (nn + 1) + 48 * nn;
     I.device_bytes = A->bytes + (A->ws ? A->ws->bytes : 0);
     I.zero_diag_rows = S.zero_diag;
+    I.cached_loads = A->kernel == SPK_KERNEL_SELL ? A->sell_plain : 0;
     double g = 0.0;
     memcpy(&g, &S.gersh_bits, sizeof g);  // bits of a non-negative double
     I.gershgorin = S.zero_diag ? 0.0 : g;
@@ -540,6 +550,22 @@ static void free_sell(spk_mat *A)
     A->sell_val32 = nullptr;
     A->sell_cw = 0;
     A->sell_nnz = 0;
+    A->sell_plain = 0;
+}
+
+// Ordinary (cache-allocating) loads for a SELL layout whose entries, slice
+// offsets and row lengths take at most kSellPlainMax bytes in that precision
+// (three quarters of the 256 MB Infinity Cache, leaving room for the vectors
+// an SpMV or a Krylov iteration touches beside it); nontemporal loads above.
+constexpr int64_t kSellPlainMax = 192ll << 20;
+
+static int sell_load_policy(int64_t stored, int cw, int nslices, int n)
+{
+    const int64_t fixed = 4 * ((int64_t)nslices + 1) + n;
+    int bits = 0;
+    if ((8 + cw) * stored + fixed <= kSellPlainMax) bits |= kSellPlain64;
+    if ((4 + cw) * stored + fixed <= kSellPlainMax) bits |= kSellPlain32;
+    return bits;
 }
 
 // Build the SELL-64 copy: slice widths from rowptr on the host (setup only),
@@ -591,6 +617,7 @@ static int setup_sell(spk_mat *A, hipStream_t s, int cw)
     A->sell_cw = cw;
     A->sell_u = pick_sell_u(wmax);
     A->sell_nnz = acc;
+    A->sell_plain = A->stream_loads ? 0 : sell_load_policy(acc, cw, ns, n);
     A->bytes += 4 * ((int64_t)ns + 1) + (int64_t)(cw + 8) * acc + n;
     if (A->val32) {
         SPK_HIP(hipMalloc(&A->sell_val32, sizeof(float) * m));
@@ -663,6 +690,7 @@ static int create_impl(int32_t n, int64_t nnz, const int32_t *rowptr, const int3
 {
     A->n = n;
     A->nnz = nnz;
+    A->stream_loads = (flags & SPK_MAT_STREAM) != 0;
     SPK_HIP(hipGetDevice(&A->device));
     const bool borrow = (flags & SPK_MAT_BORROW) != 0;
     const size_t nzb = nnz > 0 ? (size_t)nnz : 1;
@@ -826,7 +854,7 @@ int spk_mat_create_csr(int32_t n, int64_t nnz, const int32_t *rowptr, const int3
         set_error("SPK_MAT_BORROW needs SPK_MEM_DEVICE");
         return SPK_EINVAL;
     }
-    if (flags & ~(uint32_t)(SPK_MAT_MIXED | SPK_MAT_VALIDATE | SPK_MAT_BORROW)) {
+    if (flags & ~(uint32_t)(SPK_MAT_MIXED | SPK_MAT_VALIDATE | SPK_MAT_BORROW | SPK_MAT_STREAM)) {
         set_error("unknown flags 0x%x", flags);
         return SPK_EINVAL;
     }
@@ -1105,8 +1133,7 @@ int spk_cache_flush(void *scratch, int64_t bytes, void *stream)
     const int64_t m = bytes / 16;
     int64_t g = (m + kBlock - 1) / kBlock;
     if (g > 8192) g = 8192;
-    hipLaunchKernelGGL(k_scribble, dim3((int)g), dim3(kBlock), 0, (hipStream_t)stream, m,
-                       (dvec2 *)scratch, 1.0);
+    hipLaunchKernelGGL(k_evict, dim3((int)g), dim3(kBlock), 0, (hipStream_t)stream, m, (dvec2 *)scratch);
     SPK_HIP(hipGetLastError());
     return SPK_OK;
 }

@@ -209,7 +209,15 @@ struct SellView {
     const int32_t *ptr;    // element offset of each slice (nslices + 1)
     const void *col;       // int16 or int32 row-relative column offsets
     const uint8_t *len;    // row lengths
+    int plain;             // load policy of offsets and values, see kSellPlain64/32
 };
+
+// Load policy of the SELL entries.  A matrix whose stored entries fit well
+// inside the 256 MB Infinity Cache is read with ordinary loads, so that it
+// stays resident from one SpMV (or Krylov iteration) to the next; a larger
+// one is streamed with nontemporal loads, which keep it from evicting the
+// vectors that do fit.  One bit per value precision (FP64 / FP32 kernels).
+constexpr int kSellPlain64 = 1, kSellPlain32 = 2;
 
 // Row sum of lane `lane` of the slice starting at element b with slen
 // entries per row; the row has rlen of them.  Entries in column order, FMA.
@@ -219,7 +227,7 @@ struct SellView {
 // entry and padding has offset 0, so every gather reads a valid element of
 // x; only the row's own entries are multiplied.  U is chosen per matrix from
 // the widest slice (7 for a 7-point stencil: no wasted load).
-template <class V, class CI, int U>
+template <class V, class CI, int U, bool NT>
 __device__ __forceinline__ V sell_row(const SellView &sv, const V *__restrict__ val,
                                       const V *__restrict__ x, int32_t b, int slen, int rlen,
                                       int lane, int row)
@@ -233,8 +241,8 @@ __device__ __forceinline__ V sell_row(const SellView &sv, const V *__restrict__ 
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int j = j0 + u < slen ? j0 + u : slen - 1;
-            c[u] = ld_stream(col + (size_t)j * kSell);
-            a[u] = ld_stream(v + (size_t)j * kSell);
+            c[u] = NT ? ld_stream(col + (size_t)j * kSell) : col[(size_t)j * kSell];
+            a[u] = NT ? ld_stream(v + (size_t)j * kSell) : v[(size_t)j * kSell];
         }
         V xv[U];
 #pragma unroll
@@ -252,10 +260,10 @@ __device__ __forceinline__ V sell_row(const SellView &sv, const V *__restrict__ 
 // flight at any moment are adjacent in memory (one DRAM stream front rather
 // than one per block).  The first slice's header is loaded before go() is
 // asked whether to run (go holds no barrier: waves may own different counts).
-template <class V, class CI, int U, class Go, class Fn>
-__device__ __forceinline__ void sell_slices(int n, int s, int stride, const SellView &sv,
-                                            const V *__restrict__ val, const V *__restrict__ x,
-                                            Go &&go, Fn &&fn)
+template <class V, class CI, int U, bool NT, class Go, class Fn>
+__device__ __forceinline__ void sell_slices_run(int n, int s, int stride, const SellView &sv,
+                                                const V *__restrict__ val, const V *__restrict__ x,
+                                                Go &&go, Fn &&fn)
 {
     const int lane = threadIdx.x & (kWave - 1);
     const int ns = (n + kSell - 1) / kSell;
@@ -271,7 +279,7 @@ __device__ __forceinline__ void sell_slices(int n, int s, int stride, const Sell
     while (s < ns) {
         const int row = s * kSell + lane;
         const int slen = (e - b) / kSell;
-        if (row < n) fn(row, sell_row<V, CI, U>(sv, val, x, b, slen, rlen, lane, row));
+        if (row < n) fn(row, sell_row<V, CI, U, NT>(sv, val, x, b, slen, rlen, lane, row));
         s += stride;
         if (s >= ns) break;
         b = sv.ptr[s];
@@ -279,6 +287,20 @@ __device__ __forceinline__ void sell_slices(int n, int s, int stride, const Sell
         const int nrow = s * kSell + lane;
         rlen = nrow < n ? sv.len[nrow] : 0;
     }
+}
+
+// The load policy is chosen here, around the whole slice loop, so that the
+// two variants stay separate code (a branch inside the round lets the
+// compiler merge the loads and drop the nontemporal hint).
+template <class V, class CI, int U, class Go, class Fn>
+__device__ __forceinline__ void sell_slices(int n, int s, int stride, const SellView &sv,
+                                            const V *__restrict__ val, const V *__restrict__ x,
+                                            Go &&go, Fn &&fn)
+{
+    if (sv.plain & (sizeof(V) == 4 ? kSellPlain32 : kSellPlain64))
+        sell_slices_run<V, CI, U, false>(n, s, stride, sv, val, x, go, fn);
+    else
+        sell_slices_run<V, CI, U, true>(n, s, stride, sv, val, x, go, fn);
 }
 
 // Standalone SELL SpMV; the grid has up to one wavefront per slice.

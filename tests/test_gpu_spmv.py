@@ -237,6 +237,42 @@ def test_host_memtype_and_borrow_match():
     assert np.array_equal(y1.cpu().numpy(), y2.cpu().numpy())
 
 
+
+def test_sell_load_policy_same_bits():
+    """The SELL load policy (ordinary loads for a layout that fits the
+    Infinity Cache, nontemporal loads above it or with MAT_STREAM) changes
+    speed only: FP64 and FP32 products and FP64 / mixed solves give the same
+    bits either way, and both match the oracle."""
+    spk = need_gpu()
+    import torch
+
+    A = spkgen.diffusion3d27_lognormal(17, seed=6)
+    Mc = mat_on_gpu(spk, A, flags=spk.MAT_MIXED)
+    Ms = mat_on_gpu(spk, A, flags=spk.MAT_MIXED | spk.MAT_STREAM)
+    assert spk.KERNEL_NAMES[Mc.info.kernel] == "sell" == spk.KERNEL_NAMES[Ms.info.kernel]
+    assert Mc.info.cached_loads == 3 and Ms.info.cached_loads == 0
+    x = spkgen.rhs_uniform(A.n, 2)
+    ys = []
+    for M in (Mc, Ms):
+        y = to_dev(np.zeros(A.n))
+        spk.mat_mult(M, to_dev(x), y)
+        y32 = to_dev(np.zeros(A.n), torch.float32)
+        spk.mat_mult_f32(M, to_dev(x, torch.float32), y32)
+        ys.append((y.cpu().numpy(), y32.cpu().numpy()))
+    assert np.array_equal(ys[0][0], ys[1][0]) and np.array_equal(ys[0][1], ys[1][1])
+    scale = oracle.spmv_abs(A, x)
+    check_spmv(ys[0][0], oracle.spmv(A, x), scale, spmv_bound_rows(A, "sell", 0, U64), "sell fp64")
+    b = spkgen.rhs_uniform(A.n, 3)
+    for prec in (spk.PREC_FP64, spk.PREC_MIXED):
+        o = spk.ksp_opts_default()
+        o.rtol, o.precision = 1e-8, prec
+        sols = []
+        for M in (Mc, Ms):
+            xs = to_dev(np.zeros(A.n))
+            res = spk.ksp_solve(M, to_dev(b), xs, o)
+            sols.append((res.iterations, xs.cpu().numpy()))
+        assert sols[0][0] == sols[1][0] and np.array_equal(sols[0][1], sols[1][1])
+
 def test_spmv_deterministic_repeat():
     spk = need_gpu()
     A = spkgen.powerlaw_spd(20000, seed=5)
