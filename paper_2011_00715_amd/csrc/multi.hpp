@@ -200,6 +200,33 @@ __device__ __forceinline__ void flat_walk(const MultiDesc &d, int j, Fn &&fn)
     }
 }
 
+// flat_walk with every load of a chunk issued before its stores: ld(e)
+// returns what element e needs, st(e, v) writes it back.  Used where a store
+// is conditional per lane, which otherwise keeps the compiler from moving
+// the next element's loads above it.
+template <int K, class Ld, class St>
+__device__ __forceinline__ void flat_walk_batched(const MultiDesc &d, int j, Ld &&ld, St &&st)
+{
+    int t0, t1;
+    block_tiles(j, d.nblk, d.ntiles, t0, t1);
+    const int64_t e0 = (int64_t)t0 * d.R * K, e1 = (int64_t)min(t1 * d.R, d.n) * K;
+    constexpr int U = 4;
+    using T = decltype(ld(int64_t(0)));
+    for (int64_t eb = e0 + threadIdx.x; eb < e1; eb += (int64_t)kBlock * U) {
+        T v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t e = eb + (int64_t)u * kBlock;
+            if (e < e1) v[u] = ld(e);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t e = eb + (int64_t)u * kBlock;
+            if (e < e1) st(e, v[u]);
+        }
+    }
+}
+
 __device__ __forceinline__ int multi_block(const MultiDesc &d, int &j)
 {
     if ((int)blockIdx.x >= d.nblk) return -1;
@@ -474,11 +501,15 @@ __global__ __launch_bounds__(kBlock) void k_m_px(MultiDesc d)
     double *__restrict__ X = d.X;
     double *__restrict__ P = d.P;
     const double *__restrict__ Z = d.Z;
-    flat_walk<K>(d, j, [&](int64_t e, int) {
-        const double pi = P[e];
-        X[e] = fma(al, pi, X[e]);
-        if (cm == 2) P[e] = fma(be, pi, Z[e]);
-    });
+    struct PXZ {
+        double p, x, z;
+    };
+    flat_walk_batched<K>(
+        d, j, [&](int64_t e) { return PXZ{P[e], X[e], Z[e]}; },
+        [&](int64_t e, const PXZ &v) {
+            X[e] = fma(al, v.p, v.x);
+            if (cm == 2) P[e] = fma(be, v.p, v.z);
+        });
 }
 
 // Per-column state for a new solve (FP64, one thread per column), all
