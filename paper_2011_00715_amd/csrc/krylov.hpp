@@ -150,6 +150,28 @@ __device__ __forceinline__ void rows_prefetched(int rb, int re, L &&load, Mid &&
     }
 }
 
+// reduce_partials in two halves for nblk <= kBlock * 8 (one chunk per
+// thread): the loads first, the sum later, in the same order and so with the
+// same bits.  Vector loads complete in issue order, so partials loaded after
+// a kernel's row loads could only be summed once every row had arrived;
+// loaded before them, their sum and the block reduction overlap the rows.
+constexpr int kPartChunk = 8;
+__device__ __forceinline__ void partials_load(const double *part, int nblk, double v[kPartChunk])
+{
+#pragma unroll
+    for (int u = 0; u < kPartChunk; ++u) {
+        const int i = (int)threadIdx.x + u * kBlock;
+        v[u] = i < nblk ? part[i] : 0.0;
+    }
+}
+__device__ __forceinline__ double partials_sum(const double v[kPartChunk], double *sh)
+{
+    double s = 0.0;
+#pragma unroll
+    for (int u = 0; u < kPartChunk; ++u) s += v[u];
+    return block_sum(s, sh);
+}
+
 template <class V> struct Trio {
     V a, b, c;
 };
@@ -607,12 +629,16 @@ __global__ __launch_bounds__(kBlock) void k_pcg_update(B a)
     V nalpha = V(0);
     V rz = V(0), rr = V(0);
     bool run = false;
+    const double *pq = d.partials + kPartPq * d.nblk;
+    const bool one_chunk = d.nblk <= kBlock * kPartChunk;
+    double pv[kPartChunk];
+    if (one_chunk) partials_load(pq, d.nblk, pv);
     rows_prefetched(
         rb, re, [&](int i) { return Trio<V>{r[i], q[i], dinv[i]}; },
         [&]() {
             const Gate g = load_gate(st);
             const double rho = st->rho;
-            const double eta = reduce_partials(d.partials + kPartPq * d.nblk, d.nblk, red);
+            const double eta = one_chunk ? partials_sum(pv, red) : reduce_partials(pq, d.nblk, red);
             if (!gate_ok(g, Vecs<V>::gate) || !(eta > 0.0) || !finite(eta)) return false;
             nalpha = (V)(-(rho / eta));
             run = true;
