@@ -151,3 +151,30 @@ def test_server_completion_queue():
     assert sorted(seen) == sorted(tickets)
     assert spk.server_completed(S) == []
     S.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_server_system_over_more_blocks_than_one_partial_chunk(prec):
+    """max_blocks_per_system above 2048 (allowed up to 8192): a 760^2 system
+    then spans 2256 blocks, more partials than the update pass loads in one
+    chunk per thread, so every block takes the looped partial sum.  The
+    result matches the oracle, and the same system over the default 256
+    blocks converges in the same number of iterations within one."""
+    spk = need_gpu()
+    p = spk.PREC_FP64 if prec == "fp64" else spk.PREC_MIXED
+    A = spkgen.laplace2d5(760, shift=0.5)
+    b = spkgen.rhs_uniform(A.n, 9)
+    xo, _, _ = oracle.pcg(A, b, rtol=1e-8)
+    its = []
+    for blocks in (4096, 256):
+        opts = spk.server_opts_default()
+        opts.max_blocks_per_system = blocks
+        S = spk.server_create(opts)
+        (x, res), = _run(spk, S, [(None, A, b)], p)
+        assert res.reason == spk.CONVERGED_RTOL, res.as_dict()
+        rel = oracle.nrm2(b - oracle.spmv(A, x)) / oracle.nrm2(b)
+        assert rel <= 1e-8 * (1 + 1e-6), rel
+        assert np.linalg.norm(x - xo) <= 1e-6 * np.linalg.norm(xo)
+        its.append(res.iterations)
+        S.close()
+    assert abs(its[0] - its[1]) <= 1, its

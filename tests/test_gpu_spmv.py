@@ -374,3 +374,18 @@ def test_sliced_selection_solves_and_fp32(case):
         it = res.iterations if prec == spk.PREC_FP64 else res.inner_iterations
         assert abs(it - ro["iterations"]) <= max(2, 0.01 * ro["iterations"])
         assert oracle.nrm2(b - oracle.spmv(A, xs.cpu().numpy())) <= 1e-8 * oracle.nrm2(b) * (1 + 1e-6)
+
+
+def test_cache_flush_reads_only():
+    """The cache eviction helper reads its scratch buffer and leaves it as it
+    was (the bench's cold SpMV measurement relies on a clean eviction)."""
+    spk = need_gpu()
+    import torch
+
+    s = torch.arange(1 << 20, dtype=torch.float64, device="cuda")
+    ref = s.clone()
+    spk.cache_flush(s)
+    torch.cuda.synchronize()
+    assert torch.equal(s, ref)
+    with pytest.raises(spk.SpkError):
+        spk.cache_flush(s[:1])  # fewer than 16 bytes
