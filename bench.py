@@ -611,7 +611,10 @@ def bench_serve(args):
     opts = spk.server_opts_default()
     opts.hbm_budget_bytes = 32 << 30
     opts.max_slots = 64
-    opts.pinned_bytes = 8 << 30  # room for the requests queued ahead of admission
+    # pinned pool: room for the requests queued ahead of admission (a closed
+    # loop queues them all at once: its host arrays, capped at 48 GiB)
+    need = sum(12 * spkgen.serve_matrix(r).nnz + 20 * spkgen.serve_matrix(r).n for r in reqs) if args.serve_closed else 0
+    opts.pinned_bytes = max(8 << 30, min(int(need * 1.05), 48 << 30))
     opts.graph_k = args.graph_k
     S = spk.server_create(opts)
     o = spk.ksp_opts(precision=spk.PREC_MIXED)
@@ -668,24 +671,28 @@ def bench_serve(args):
     seq = None
     if closed:
         # the same requests one at a time through spk_ksp_solve (matrix
-        # upload, mixed solve, x back to the host), for the batching gain
+        # upload, solve, x back to the host): mixed precision as served, and
+        # plain FP64, for the batching gain
         import torch
 
-        log("sequential baseline")
-        tseq = 0.0
-        for r in reqs:
-            A = spkgen.serve_matrix(r)  # input formation is not timed (as for the server)
-            b = spkgen.rhs_uniform(A.n, r.rhs_seed % (2**31))
-            ts = spk.now()
-            M = spk.mat_create_csr(A.rowptr, A.col, A.val, flags=spk.MAT_MIXED)
-            x = torch.zeros(A.n, dtype=torch.float64, device="cuda")
-            res = spk.ksp_solve(M, dev(b), x, o)
-            x.cpu()
-            M.close()
-            tseq += spk.now() - ts
-            assert res.reason > 0
-        seq = {"solves_per_s": len(reqs) / tseq, "seconds": tseq,
-               "batching_gain": (len(lat) / elapsed) / (len(reqs) / tseq)}
+        seq = {}
+        for name, prec, flags in (("mixed", spk.PREC_MIXED, spk.MAT_MIXED), ("fp64", spk.PREC_FP64, 0)):
+            log(f"sequential baseline ({name})")
+            os_ = spk.ksp_opts(graph_k=args.graph_k, precision=prec)
+            tseq = 0.0
+            for r in reqs:
+                A = spkgen.serve_matrix(r)  # input formation is not timed (as for the server)
+                b = spkgen.rhs_uniform(A.n, r.rhs_seed % (2**31))
+                ts = spk.now()
+                M = spk.mat_create_csr(A.rowptr, A.col, A.val, flags=flags)
+                x = torch.zeros(A.n, dtype=torch.float64, device="cuda")
+                res = spk.ksp_solve(M, dev(b), x, os_)
+                x.cpu()
+                M.close()
+                tseq += spk.now() - ts
+                assert res.reason > 0
+            seq[name] = {"solves_per_s": len(reqs) / tseq, "seconds": tseq,
+                         "batching_gain": (len(lat) / elapsed) / (len(reqs) / tseq)}
     return {
         "metric": "served PCG solves/s to rtol 1e-8; p50/p99 latency",
         "value": len(lat) / elapsed, "unit": "solves/s", "n_gpus": 1, "steps": len(lat),
