@@ -84,6 +84,36 @@ def test_c2_spmv_and_pcg():
     assert rm.inner_iterations <= 1.1 * ro["iterations"]
 
 
+
+def test_sell_load_policy_split_by_precision():
+    """150^3 7-point: the SELL entries take 236 MB in FP64 (above the 192 MB
+    limit: nontemporal loads) and 142 MB with FP32 values (ordinary loads),
+    so the handle reports cached_loads == 2.  Both products are bit-exact on
+    integer data and within 1e-14 (FP64) of the oracle on the rhs, and the
+    FP32 product matches the oracle's FP32 product to 16 FP32 ulps of the
+    row's absolute sum."""
+    spk = need_gpu()
+    import torch
+
+    A = spkgen.laplace3d7(150)
+    M = mat_on_gpu(spk, A, flags=spk.MAT_MIXED)
+    assert spk.KERNEL_NAMES[M.info.kernel] == "sell"
+    assert M.info.cached_loads == 2
+    rows = _sample_rows(A.n)
+    xi = np.random.default_rng(5).integers(-100, 100, A.n).astype(np.float64)
+    yg, yo = _spmv_sampled(spk, M, A, xi, rows, tol=0.0)
+    assert np.array_equal(yg, yo)
+    b = spkgen.rhs_uniform(A.n, 1)
+    _spmv_sampled(spk, M, A, b, rows)
+    y32 = torch.empty(A.n, dtype=torch.float32, device="cuda")
+    spk.mat_mult_f32(M, to_dev(xi, torch.float32), y32)
+    assert np.array_equal(y32.cpu().numpy(), oracle.spmv_f32(A, xi.astype(np.float32)))
+    spk.mat_mult_f32(M, to_dev(b, torch.float32), y32)
+    b32 = b.astype(np.float32)
+    yo32 = oracle.spmv_f32(A, b32)
+    scale = oracle.spmv_abs(A, b32.astype(np.float64))
+    assert np.all(np.abs(y32.cpu().numpy().astype(np.float64) - yo32) <= 16 * 2.0**-24 * scale + 1e-30)
+
 def test_c3_fp64_and_mixed():
     spk = need_gpu()
     A = spkgen.diffusion3d27_lognormal(160, seed=0)
