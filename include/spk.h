@@ -64,13 +64,16 @@ enum {
                               spk_mat_destroy */
     SPK_MAT_STREAM = 8     /* read the SELL layout with nontemporal loads
                               whatever its size.  Default: ordinary loads when
-                              its entries, slice offsets and row lengths take
-                              at most 192 MB in the precision of the product
-                              (they then stay in the 256 MB Infinity Cache
-                              from one product to the next), nontemporal
-                              loads above (a matrix that cannot stay cached
-                              must not evict the vectors).  Changes speed
-                              only: the products are the same bits. */
+                              the layout (entries, slice offsets, row lengths
+                              in the precision of the product) and the
+                              vectors beside it fit the 256 MB Infinity Cache
+                              -- 256 MiB with the 6 vectors of a Krylov
+                              iteration, 288 MiB with x and y of a standalone
+                              product -- so that it stays cached from one
+                              product to the next; nontemporal loads above (a
+                              matrix that cannot stay cached must not evict
+                              the vectors).  Changes speed only: the results
+                              are the same bits. */
 };
 
 /* SpMV kernel families (selected from row-length statistics at create) */
@@ -143,9 +146,10 @@ typedef struct {
     int64_t device_bytes;    /* device memory held by the handle */
     int32_t zero_diag_rows;  /* rows without a nonzero diagonal */
     int32_t cached_loads;    /* SELL layout read with ordinary (cache-allocating)
-                                loads: bit 0 by FP64 products, bit 1 by FP32
-                                products; otherwise nontemporal (see
-                                SPK_MAT_STREAM); 0 for the other kernels */
+                                loads: bit 0 / 1 by the FP64 / FP32 Krylov and
+                                smoother kernels, bit 2 / 3 by the FP64 / FP32
+                                standalone products; otherwise nontemporal
+                                (see SPK_MAT_STREAM); 0 for the other kernels */
     int64_t format_bytes_spmv_f64;  /* algorithmic bytes of one FP64 SpMV in the
                                        storage the selected kernel reads (equal
                                        to bytes_spmv_f64 except for SELL:

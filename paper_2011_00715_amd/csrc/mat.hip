@@ -302,7 +302,7 @@ int launch_spmv(const spk_mat *A, const V *val, const V *x, V *y, hipStream_t s,
             set_error("internal: gated SELL SpMV or no SELL layout");
             return SPK_EINVAL;
         }
-        const SellView sv{A->sell_ptr, A->sell_col, A->sell_len, A->sell_plain};
+        const SellView sv{A->sell_ptr, A->sell_col, A->sell_len, A->sell_plain_spmv};
         const V *sval = std::is_same<V, double>::value ? (const V *)A->sell_val : (const V *)A->sell_val32;
         (void)val;
         // up to one wavefront per slice
@@ -396,7 +396,7 @@ void update_info(spk_mat *A)
     I.bytes_pcg_iter_f32 = 8 * nz + 4 * (nn + 1) + 48 * nn;
     I.device_bytes = A->bytes + (A->ws ? A->ws->bytes : 0);
     I.zero_diag_rows = S.zero_diag;
-    I.cached_loads = A->kernel == SPK_KERNEL_SELL ? A->sell_plain : 0;
+    I.cached_loads = A->kernel == SPK_KERNEL_SELL ? A->sell_plain | A->sell_plain_spmv << 2 : 0;
     double g = 0.0;
     memcpy(&g, &S.gersh_bits, sizeof g);  // bits of a non-negative double
     I.gershgorin = S.zero_diag ? 0.0 : g;
@@ -552,20 +552,25 @@ static void free_sell(spk_mat *A)
     A->sell_cw = 0;
     A->sell_nnz = 0;
     A->sell_plain = 0;
+    A->sell_plain_spmv = 0;
 }
 
-// Ordinary (cache-allocating) loads for a SELL layout whose entries, slice
-// offsets and row lengths take at most kSellPlainMax bytes in that precision
-// (three quarters of the 256 MB Infinity Cache, leaving room for the vectors
-// an SpMV or a Krylov iteration touches beside it); nontemporal loads above.
-constexpr int64_t kSellPlainMax = 192ll << 20;
+// Load policy of the SELL entries: ordinary (cache-allocating) loads when
+// the layout (entries, slice offsets, row lengths in that precision) and the
+// n-vectors a pass touches beside it fit the 256 MB Infinity Cache,
+// nontemporal loads above.  Measured on 3D 7-point Laplacians: a PCG
+// iteration (6 vectors: x, r, z, p, q, dinv) gains from ordinary loads at
+// 128^3 (249 MB in all) and loses from 134^3 (285 MB) on; back-to-back
+// products (x and y) gain up to 150^3 (293 MB) and lose at 160^3 (355 MB).
+constexpr int64_t kIterCacheBudget = 256ll << 20;
+constexpr int64_t kSpmvCacheBudget = 288ll << 20;
 
-static int sell_load_policy(int64_t stored, int cw, int nslices, int n)
+static int sell_load_policy(int64_t stored, int cw, int nslices, int n, int vectors, int64_t budget)
 {
     const int64_t fixed = 4 * ((int64_t)nslices + 1) + n;
     int bits = 0;
-    if ((8 + cw) * stored + fixed <= kSellPlainMax) bits |= kSellPlain64;
-    if ((4 + cw) * stored + fixed <= kSellPlainMax) bits |= kSellPlain32;
+    if ((8 + cw) * stored + fixed + 8ll * vectors * n <= budget) bits |= kSellPlain64;
+    if ((4 + cw) * stored + fixed + 4ll * vectors * n <= budget) bits |= kSellPlain32;
     return bits;
 }
 
@@ -618,7 +623,8 @@ static int setup_sell(spk_mat *A, hipStream_t s, int cw)
     A->sell_cw = cw;
     A->sell_u = pick_sell_u(wmax);
     A->sell_nnz = acc;
-    A->sell_plain = A->stream_loads ? 0 : sell_load_policy(acc, cw, ns, n);
+    A->sell_plain = A->stream_loads ? 0 : sell_load_policy(acc, cw, ns, n, 6, kIterCacheBudget);
+    A->sell_plain_spmv = A->stream_loads ? 0 : sell_load_policy(acc, cw, ns, n, 2, kSpmvCacheBudget);
     A->bytes += 4 * ((int64_t)ns + 1) + (int64_t)(cw + 8) * acc + n;
     if (A->val32) {
         SPK_HIP(hipMalloc(&A->sell_val32, sizeof(float) * m));

@@ -87,7 +87,8 @@ struct spk_mat {
     int sell_cw = 0;           // column offset width: 2 (int16) or 4 (int32), 0 = none
     int sell_u = 8;            // entries per load round of the SELL kernels (from the widest slice)
     int64_t sell_nnz = 0;      // stored entries including padding
-    int sell_plain = 0;        // kSellPlain64/32 bits: SELL entries read with ordinary loads
+    int sell_plain = 0;        // kSellPlain64/32 bits: ordinary loads in the Krylov and smoother kernels
+    int sell_plain_spmv = 0;   // the same for the standalone products
     bool stream_loads = false; // SPK_MAT_STREAM: always nontemporal
     int32_t *sell_ptr = nullptr;
     void *sell_col = nullptr;

@@ -85,20 +85,34 @@ def test_c2_spmv_and_pcg():
 
 
 
+def _cached_bits(A, vectors, budget):
+    """The load-policy bits the library documents: ordinary loads when the
+    SELL layout and `vectors` n-vectors fit `budget` bytes (per precision)."""
+    lens = np.diff(A.rowptr)
+    lens = np.concatenate([lens, np.zeros(-A.n % 64, lens.dtype)])
+    stored = 64 * int(lens.reshape(-1, 64).max(axis=1).sum())
+    fixed = 4 * ((A.n + 63) // 64 + 1) + A.n
+    b64 = 10 * stored + fixed + 8 * vectors * A.n <= budget
+    b32 = 6 * stored + fixed + 4 * vectors * A.n <= budget
+    return int(b64) | int(b32) << 1
+
+
 def test_sell_load_policy_split_by_precision():
-    """150^3 7-point: the SELL entries take 236 MB in FP64 (above the 192 MB
-    limit: nontemporal loads) and 142 MB with FP32 values (ordinary loads),
-    so the handle reports cached_loads == 2.  Both products are bit-exact on
-    integer data and within 1e-14 (FP64) of the oracle on the rhs, and the
-    FP32 product matches the oracle's FP32 product to 16 FP32 ulps of the
-    row's absolute sum."""
+    """150^3 7-point: with the 6 vectors of a Krylov iteration the FP64
+    layout (236 MB) does not fit the 256 MiB budget and the FP32 one does;
+    with the x and y of a standalone product both fit 288 MiB.  Both products
+    are bit-exact on integer data and within 1e-14 (FP64) of the oracle on the
+    rhs, and the FP32 product matches the oracle's FP32 product to 16 FP32
+    ulps of the row's absolute sum."""
     spk = need_gpu()
     import torch
 
     A = spkgen.laplace3d7(150)
     M = mat_on_gpu(spk, A, flags=spk.MAT_MIXED)
     assert spk.KERNEL_NAMES[M.info.kernel] == "sell"
-    assert M.info.cached_loads == 2
+    it, sp = _cached_bits(A, 6, 256 << 20), _cached_bits(A, 2, 288 << 20)
+    assert (it, sp) == (2, 3)
+    assert M.info.cached_loads == it | sp << 2
     rows = _sample_rows(A.n)
     xi = np.random.default_rng(5).integers(-100, 100, A.n).astype(np.float64)
     yg, yo = _spmv_sampled(spk, M, A, xi, rows, tol=0.0)

@@ -250,7 +250,7 @@ def test_sell_load_policy_same_bits():
     Mc = mat_on_gpu(spk, A, flags=spk.MAT_MIXED)
     Ms = mat_on_gpu(spk, A, flags=spk.MAT_MIXED | spk.MAT_STREAM)
     assert spk.KERNEL_NAMES[Mc.info.kernel] == "sell" == spk.KERNEL_NAMES[Ms.info.kernel]
-    assert Mc.info.cached_loads == 3 and Ms.info.cached_loads == 0
+    assert Mc.info.cached_loads == 15 and Ms.info.cached_loads == 0
     x = spkgen.rhs_uniform(A.n, 2)
     ys = []
     for M in (Mc, Ms):
