@@ -588,6 +588,47 @@ __global__ __launch_bounds__(kBlock) void k_pcg_spmv_sell(B a)
     if (threadIdx.x == 0) d.partials[kPartPq * d.nblk + j] = blk;
 }
 
+// A for large SELL matrices: one wavefront per slice (ceil(slices / 4)
+// blocks, each slice once) and one p.q partial per block in wpart, which
+// k_fin_pq folds.  The persistent grid above walks many slices per wave and
+// streams a large matrix slower (160^3 27-point: 245 against 226 us).
+template <class V, class CI, int U>
+__global__ __launch_bounds__(kBlock) void k_pcg_spmv_sell_wide(One a, double *__restrict__ wpart)
+{
+    __shared__ double red[kBlock / kWave];
+    const SysDesc &d = a.d;
+    const Gate g = load_gate(d.st);
+    const V *__restrict__ p = Vecs<V>::p(d);
+    V *__restrict__ q = Vecs<V>::q(d);
+    const V *__restrict__ val = sell_vals<V>(d);
+    const SellView sv{d.sell_ptr, d.sell_col, d.sell_len, d.sell_plain};
+    V acc = V(0);
+    const bool run = gate_ok(g, Vecs<V>::gate);
+    sell_slices<V, CI, U>(
+        d.n, sell_first((int)blockIdx.x), (int)gridDim.x * (kBlock / kWave), sv, val, p, [&] { return run; },
+        [&](int i, V y) {
+            q[i] = y;
+            acc = fma(y, p[i], acc);
+        });
+    if (!run) return;
+    const double blk = block_sum((double)acc, red);
+    if (threadIdx.x == 0) wpart[blockIdx.x] = blk;
+}
+
+// The wide A's nw partials summed in block order into slot 0 of the p.q
+// partials and zeros into the other nblk - 1 slots, so that the update pass
+// and F_B, which sum those slots, both get exactly this sum.
+template <class V>
+__global__ __launch_bounds__(kBlock) void k_fin_pq(One a, const double *__restrict__ wpart, int nw)
+{
+    __shared__ double red[kBlock / kWave];
+    const SysDesc &d = a.d;
+    if (!gate_ok(load_gate(d.st), Vecs<V>::gate)) return;
+    const double eta = reduce_partials(wpart, nw, red);
+    double *pq = d.partials + kPartPq * d.nblk;
+    for (int i = threadIdx.x; i < d.nblk; i += kBlock) pq[i] = i == 0 ? eta : 0.0;
+}
+
 // A (other SpMV kernels): q already holds A p; per-block p.q.
 template <class V, class B>
 __global__ __launch_bounds__(kBlock) void k_pcg_pq(B a)

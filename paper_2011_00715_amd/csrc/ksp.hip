@@ -35,6 +35,7 @@ void free_workspace(spk_mat *A)
     hipFree(w->q);
     hipFree(w->x);
     hipFree(w->b);
+    hipFree(w->wpart);
     hipFree(w->r32);
     hipFree(w->z32);
     hipFree(w->p32);
@@ -66,6 +67,11 @@ static int dalloc(T **p, int64_t count, Workspace *w)
         if (rc_ != SPK_OK) return rc_; \
     } while (0)
 
+// Persistent-grid passes over the slices above which the PCG product runs
+// one wavefront per slice instead (the 128^3 7-point matrix makes exactly 4
+// passes, the 160^3 27-point one 7.8).
+constexpr int kWidePasses = 6;
+
 static int get_workspace(spk_mat *A, bool mixed, Workspace **out)
 {
     Workspace *w = A->ws;
@@ -84,6 +90,15 @@ static int get_workspace(spk_mat *A, bool mixed, Workspace **out)
         SPK_TRY(dalloc(&w->q, A->n, w));
         SPK_TRY(dalloc(&w->x, A->n, w));
         SPK_TRY(dalloc(&w->b, A->n, w));
+        // SELL matrices of more than kWidePasses slices per wavefront of the
+        // persistent grid take the wide product (one wavefront per slice)
+        if (A->kernel == SPK_KERNEL_SELL && A->sell_cw) {
+            const int64_t slices = ceil_div(A->n, kSell);
+            if (slices > (int64_t)kWidePasses * (kBlock / kWave) * A->nblk) {
+                w->nwpart = ceil_div(slices, kBlock / kWave);
+                SPK_TRY(dalloc(&w->wpart, w->nwpart, w));
+            }
+        }
         SPK_HIP(hipHostMalloc((void **)&w->pdesc, sizeof(SysDesc), hipHostMallocDefault));
         SPK_HIP(hipHostMalloc((void **)&w->pst, sizeof(SysState), hipHostMallocDefault));
         SPK_HIP(hipHostMalloc((void **)&w->pstatus, sizeof(int32_t) * 8, hipHostMallocDefault));
@@ -180,6 +195,14 @@ static int enqueue_iteration(spk_mat *A, Workspace *w, hipStream_t s)
     const dim3 g(A->nblk), t(kBlock), one(1);
     if (A->kernel == SPK_KERNEL_STREAM) {
         hipLaunchKernelGGL((k_pcg_spmv_stream<V, One>), g, t, 0, s, b);
+    } else if (A->kernel == SPK_KERNEL_SELL && w->wpart) {
+        const dim3 gw(w->nwpart);
+        with_sell_u(A->sell_u, [&](auto uc) {
+            constexpr int U = decltype(uc)::value;
+            if (A->sell_cw == 2) hipLaunchKernelGGL((k_pcg_spmv_sell_wide<V, int16_t, U>), gw, t, 0, s, b, w->wpart);
+            else hipLaunchKernelGGL((k_pcg_spmv_sell_wide<V, int32_t, U>), gw, t, 0, s, b, w->wpart);
+        });
+        hipLaunchKernelGGL((k_fin_pq<V>), one, t, 0, s, b, (const double *)w->wpart, w->nwpart);
     } else if (A->kernel == SPK_KERNEL_SELL) {
         with_sell_u(A->sell_u, [&](auto uc) {
             constexpr int U = decltype(uc)::value;

@@ -40,6 +40,8 @@ struct Workspace {
     double *hist = nullptr;
     int hist_cap = 0;
     double *partials = nullptr;
+    double *wpart = nullptr;      // partials of the wide SELL product (large matrices), or null
+    int nwpart = 0;
     double *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr;
     double *x = nullptr;          // the solve's iterate (copied in and out)
     double *b = nullptr;          // the solve's right-hand side (copied in)
