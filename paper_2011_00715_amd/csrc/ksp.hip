@@ -67,10 +67,14 @@ static int dalloc(T **p, int64_t count, Workspace *w)
         if (rc_ != SPK_OK) return rc_; \
     } while (0)
 
-// Persistent-grid passes over the slices above which the PCG product runs
-// one wavefront per slice instead (the 128^3 7-point matrix makes exactly 4
-// passes, the 160^3 27-point one 7.8).
-constexpr int kWidePasses = 6;
+// The PCG product runs one wavefront per slice (plus the one-block fold of
+// its partials, ~4.6 us) instead of the persistent grid when each lane of
+// the persistent grid would stream more than this many SELL entries:
+// 160^3 27-point makes 210 (FP64 iteration 313 -> 306 us, FP32 inner
+// 181 -> 177 us with the wide product), the 7-point matrices of 150^3 and
+// 160^3 45 and 55 (FP32 inner iterations 65 -> 70 and 79 -> 83 us slower),
+// 128^3 28.
+constexpr int64_t kWideEntriesPerLane = 96;
 
 static int get_workspace(spk_mat *A, bool mixed, Workspace **out)
 {
@@ -90,14 +94,11 @@ static int get_workspace(spk_mat *A, bool mixed, Workspace **out)
         SPK_TRY(dalloc(&w->q, A->n, w));
         SPK_TRY(dalloc(&w->x, A->n, w));
         SPK_TRY(dalloc(&w->b, A->n, w));
-        // SELL matrices of more than kWidePasses slices per wavefront of the
-        // persistent grid take the wide product (one wavefront per slice)
-        if (A->kernel == SPK_KERNEL_SELL && A->sell_cw) {
-            const int64_t slices = ceil_div(A->n, kSell);
-            if (slices > (int64_t)kWidePasses * (kBlock / kWave) * A->nblk) {
-                w->nwpart = ceil_div(slices, kBlock / kWave);
-                SPK_TRY(dalloc(&w->wpart, w->nwpart, w));
-            }
+        // large SELL matrices take the wide product (one wavefront per slice)
+        if (A->kernel == SPK_KERNEL_SELL && A->sell_cw && A->nblk > 0 &&
+            A->sell_nnz > kWideEntriesPerLane * kBlock * A->nblk) {
+            w->nwpart = ceil_div(ceil_div(A->n, kSell), kBlock / kWave);
+            SPK_TRY(dalloc(&w->wpart, w->nwpart, w));
         }
         SPK_HIP(hipHostMalloc((void **)&w->pdesc, sizeof(SysDesc), hipHostMallocDefault));
         SPK_HIP(hipHostMalloc((void **)&w->pst, sizeof(SysState), hipHostMallocDefault));
