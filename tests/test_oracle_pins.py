@@ -83,6 +83,44 @@ def test_spmv_f32_rounded_once(orc):
         assert abs(float(y[i]) - ex) <= np.spacing(np.float32(abs(ex))) * 1.0001
 
 
+@pytest.mark.parametrize("seed", range(3))
+def test_spmv_abs_exact_on_integers(orc, seed):
+    """The tolerance scale sum_j |a_ij| |x_j| against Python's exact integer
+    arithmetic on a nonsymmetric integer matrix and x of both signs.  The
+    same data tells the absolute sum from |A x| (rows cancel), from
+    |A|^T |x| (a transposed operand) and from sum_j |a_ij| (x dropped), so
+    a scale that is inflated, deflated or taken over the wrong operand fails."""
+    n = 37
+    A, D = random_int_csr(n, seed)
+    x = np.random.default_rng(200 + seed).integers(-1000, 1000, size=n).astype(np.float64)
+    ya = oracle.spmv_abs(A, x)
+    exact = [sum(abs(int(D[i, j])) * abs(int(x[j])) for j in range(n)) for i in range(n)]
+    assert np.array_equal(ya, np.array(exact, dtype=np.float64))
+    assert not np.array_equal(ya, np.abs(oracle.spmv(A, x)))
+    assert not np.array_equal(ya, np.abs(D).T @ np.abs(x))
+    assert not np.array_equal(ya, np.abs(D).sum(axis=1).astype(np.float64))
+
+
+@pytest.mark.parametrize("case", ["powerlaw", "diff27"])
+def test_spmv_abs_vs_dense_and_fsum(orc, case):
+    """Real data: the oracle's scale equals numpy's dense |A| @ |x| within
+    the error of an n-term sum of nonnegative terms ((n - 1) u relative, no
+    cancellation is possible), and math.fsum's exactly rounded sum of the
+    exact products within one ulp on sampled rows."""
+    A = spkgen.powerlaw_spd(700, seed=3) if case == "powerlaw" else spkgen.diffusion3d27_lognormal(9, seed=2)
+    x = spkgen.rhs_uniform(A.n, 7) * 1e3
+    ya = oracle.spmv_abs(A, x)
+    D = spkgen.to_dense(A)
+    dense = np.abs(D) @ np.abs(x)
+    assert np.all(np.abs(ya - dense) <= (A.n - 1) * 2.0 ** -53 * dense)
+    for i in range(0, A.n, 13):
+        ks = range(A.rowptr[i], A.rowptr[i + 1])
+        ex = math.fsum(abs(float(A.val[k]) * float(x[A.col[k]])) for k in ks)
+        assert abs(ya[i] - ex) <= np.spacing(ex)
+    # a row sum of |a_ij x_j| is at least |(A x)_i| and equals it only without cancellation
+    assert np.all(ya >= np.abs(oracle.spmv(A, x)))
+
+
 @pytest.mark.parametrize("dim,N,ks", [(2, 64, (1, 1)), (2, 64, (7, 40)), (3, 12, (1, 2, 3)),
                                       (3, 16, (16, 1, 9))])
 def test_spmv_closed_form_eigenpairs(orc, dim, N, ks):
@@ -348,6 +386,46 @@ def test_pcg_iteration_count_vs_scipy_c1(orc):
     b = spkgen.rhs_uniform(A.n, 0)
     _, res, _ = oracle.pcg(A, b, rtol=1e-8)
     assert res["iterations"] == 193
+
+
+def test_pcg_iteration_count_vs_scipy_c2(orc):
+    """3D 7-point 128^3 with the rhs of seed 0 (the configuration the bench
+    solves): the oracle takes 446 iterations, and SciPy's Jacobi-preconditioned
+    CG with the same stopping rule (rtol 1e-8 on the unpreconditioned
+    residual, atol 0) agrees within 2."""
+    import scipy.sparse as sp
+    import scipy.sparse.linalg as sla
+
+    A = spkgen.laplace3d7(128)
+    b = spkgen.rhs_uniform(A.n, 0)
+    _, res, _ = oracle.pcg(A, b, rtol=1e-8)
+    assert res["reason_str"] == "CONVERGED_RTOL" and res["iterations"] == 446
+    assert res["true_rel_residual"] <= 1e-8
+    S = sp.csr_matrix((A.val, A.col, A.rowptr), shape=(A.n, A.n))
+    it = [0]
+
+    def cb(_):
+        it[0] += 1
+
+    _, info = sla.cg(S, b, rtol=1e-8, atol=0.0, M=sp.diags(1.0 / S.diagonal()), callback=cb, maxiter=10000)
+    assert info == 0 and abs(res["iterations"] - it[0]) <= 2
+
+
+def test_pcg_manufactured_solution_c2(orc):
+    """128^3 7-point, integer x*, b = A x* exact: the error obeys
+    ||x - x*|| / ||x*|| <= kappa ||b - A x|| / ||b|| with the closed-form
+    condition number of the 3D Dirichlet Laplacian (6743.68)."""
+    N = 128
+    A = spkgen.laplace3d7(N)
+    xs = np.random.default_rng(1).integers(-5, 6, size=A.n).astype(np.float64)
+    b = oracle.spmv(A, xs)
+    assert np.array_equal(b, np.rint(b))
+    x, res, _ = oracle.pcg(A, b, rtol=1e-8)
+    kappa = lap_kappa(N, 3)
+    assert kappa == pytest.approx(6743.68, abs=0.01)
+    assert res["reason_str"] == "CONVERGED_RTOL" and res["true_rel_residual"] <= 1e-8
+    err = np.linalg.norm(x - xs) / np.linalg.norm(xs)
+    assert err <= kappa * res["true_rel_residual"] * 1.0001
 
 
 def test_pcg_variable_diagonal_vs_scipy(orc):
