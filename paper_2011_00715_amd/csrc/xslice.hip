@@ -1,7 +1,7 @@
 // Column-sliced CSR: layout setup on the device (per-slice row counts, one
 // exclusive scan, scatter) and the two-pass SpMV launch.
-#include <hipcub/hipcub.hpp>
 
+#include "scan.hpp"
 #include "xslice.hpp"
 #include "runtime.hpp"
 
@@ -140,29 +140,25 @@ int setup_sliced(spk_mat *A, hipStream_t s)
     const int n = A->n;
     const int rows = kSlices * n;  // rows of the stacked slices
     int32_t *cnt = nullptr;
-    void *tmp = nullptr;
-    size_t tmp_bytes = 0;
+    long long *bsum = nullptr;
     int rc = SPK_OK;
     auto fail = [&](hipError_t e, const char *what) {
         hipFree(cnt);
-        hipFree(tmp);
+        hipFree(bsum);
         free_sliced(A);
         return hip_fail(e, what, __FILE__, __LINE__);
     };
-    hipError_t e = hipMalloc(&cnt, sizeof(int32_t) * ((size_t)rows + 1));
+    hipError_t e = hipMalloc(&cnt, sizeof(int32_t) * (size_t)rows);
+    if (e == hipSuccess) e = hipMalloc(&bsum, sizeof(long long) * ((size_t)scan_blocks(rows) + 1));
     if (e == hipSuccess) e = hipMalloc(&A->xs_ptr, sizeof(int32_t) * ((size_t)rows + 1));
     if (e == hipSuccess) e = hipMalloc(&A->xs_col, sizeof(int32_t) * (size_t)std::max<int64_t>(A->nnz, 1));
     if (e == hipSuccess) e = hipMalloc(&A->xs_val, sizeof(double) * (size_t)std::max<int64_t>(A->nnz, 1));
     if (e == hipSuccess) e = hipMalloc(&A->xs_part, sizeof(double) * (size_t)rows);
     if (e != hipSuccess) return fail(e, "hipMalloc");
     A->bytes += 4 * ((int64_t)rows + 1) + 12 * A->nnz + 8 * (int64_t)rows;
-    e = hipMemsetAsync(cnt + rows, 0, sizeof(int32_t), s);
-    if (e != hipSuccess) return fail(e, "hipMemsetAsync");
     hipLaunchKernelGGL(k_xs_count, dim3(grid_rows(n)), dim3(kBlock), 0, s, n, (const int32_t *)A->rowptr,
                        (const int32_t *)A->col, cnt);
-    e = hipcub::DeviceScan::ExclusiveSum(nullptr, tmp_bytes, cnt, A->xs_ptr, rows + 1, s);
-    if (e == hipSuccess) e = hipMalloc(&tmp, tmp_bytes > 0 ? tmp_bytes : 1);
-    if (e == hipSuccess) e = hipcub::DeviceScan::ExclusiveSum(tmp, tmp_bytes, cnt, A->xs_ptr, rows + 1, s);
+    e = scan_exclusive(rows, cnt, A->xs_ptr, bsum, s);
     if (e != hipSuccess) return fail(e, "slice scan");
     hipLaunchKernelGGL(k_xs_fill, dim3(grid_rows(n)), dim3(kBlock), 0, s, n, (const int32_t *)A->rowptr,
                        (const int32_t *)A->col, (const double *)A->val, (const int32_t *)A->xs_ptr, A->xs_col,
@@ -171,7 +167,7 @@ int setup_sliced(spk_mat *A, hipStream_t s)
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return fail(e, "slice fill");
     hipFree(cnt);
-    hipFree(tmp);
+    hipFree(bsum);
     if (A->val32) rc = ensure_sliced_f32(A, s);
     return rc;
 }

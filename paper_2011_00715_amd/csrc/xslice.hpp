@@ -22,37 +22,42 @@ constexpr int kSlices = kXcd;
 
 __device__ __forceinline__ int slice_of(int c, int n) { return (int)(((int64_t)c * kSlices) / n); }
 
-// cnt[s * n + i] = entries of row i in column range s (columns ascending).
+// cnt[s * n + i] = entries of row i in column range s.  Rows need not be
+// sorted: every entry is counted where its column falls.
 static __global__ void k_xs_count(int n, const int32_t *__restrict__ rowptr, const int32_t *__restrict__ col,
                                   int32_t *__restrict__ cnt)
 {
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-        int k = rowptr[i];
-        const int e = rowptr[i + 1];
-        for (int s = 0; s < kSlices; ++s) {
-            const int start = k;
-            while (k < e && slice_of(col[k], n) == s) ++k;
-            cnt[(size_t)s * n + i] = k - start;
+        int c[kSlices] = {};
+        for (int k = rowptr[i]; k < rowptr[i + 1]; ++k) {
+            const int s = slice_of(col[k], n);
+#pragma unroll
+            for (int t = 0; t < kSlices; ++t) c[t] += t == s;
         }
+#pragma unroll
+        for (int s = 0; s < kSlices; ++s) cnt[(size_t)s * n + i] = c[s];
     }
 }
 
-// Scatter each row's entries to its slices' rows (xptr: exclusive scan of cnt).
+// Scatter each row's entries to its slices' rows (xptr: exclusive scan of
+// cnt), keeping their order within the row.
 static __global__ void k_xs_fill(int n, const int32_t *__restrict__ rowptr, const int32_t *__restrict__ col,
                                  const double *__restrict__ val, const int32_t *__restrict__ xptr,
                                  int32_t *__restrict__ xcol, double *__restrict__ xval)
 {
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-        int k = rowptr[i];
-        const int e = rowptr[i + 1];
-        for (int s = 0; s < kSlices; ++s) {
-            int d = xptr[(size_t)s * n + i];
-            while (k < e && slice_of(col[k], n) == s) {
-                xcol[d] = col[k];
-                xval[d] = val[k];
-                ++d;
-                ++k;
-            }
+        int d[kSlices];
+#pragma unroll
+        for (int s = 0; s < kSlices; ++s) d[s] = xptr[(size_t)s * n + i];
+        for (int k = rowptr[i]; k < rowptr[i + 1]; ++k) {
+            const int c = col[k];
+            const int s = slice_of(c, n);
+            int pos = 0;
+#pragma unroll
+            for (int t = 0; t < kSlices; ++t)
+                if (t == s) pos = d[t]++;
+            xcol[pos] = c;
+            xval[pos] = val[k];
         }
     }
 }

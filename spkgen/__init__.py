@@ -271,6 +271,42 @@ def powerlaw_spd(n: int, seed: int = 0, a: float = 1.8, lo: int = 3, hi: int = 4
     return CSR(n, rowptr.astype(np.int32), col, val)
 
 
+def banded_spd(n: int, offsets, seed: int = 0, margin: float = 1.0, negative: bool = False) -> CSR:
+    """SPD matrix whose row i couples to i + d for every positive d in
+    ``offsets`` that stays inside [0, n) and, by symmetry, to i - d: one
+    N(0,1) value g per coupled pair (-|g| with ``negative``: a weighted graph
+    Laplacian, whose near-constant vectors make it ill-conditioned),
+    diagonal = row abs-sum + ``margin`` (strictly diagonally dominant for
+    margin > 0, hence SPD).  Columns are
+    ascending within a row.  Draw order: standard_normal(n * len(offsets)),
+    entry (i, i + d_k) takes draw i * len(offsets) + k."""
+    d = np.unique(np.asarray(offsets, dtype=np.int64))
+    if d.size == 0 or d[0] <= 0:
+        raise ValueError("offsets must be positive")
+    rng = np.random.default_rng(seed)
+    draws = rng.standard_normal(n * d.size).reshape(n, d.size)
+    if negative:
+        draws = -np.abs(draws)
+    i = np.arange(n, dtype=np.int64)
+    up_ok = (i[:, None] + d[None, :]) < n          # entry (i, i + d_k) exists
+    up = np.where(up_ok, draws, 0.0)
+    # lower entry (i, i - d_k) holds the value of (i - d_k, i)
+    lo_ok = (i[:, None] - d[None, :]) >= 0
+    lo = np.zeros_like(up)
+    for k, dk in enumerate(d):
+        lo[dk:, k] = up[: n - dk, k]
+    diag = np.abs(up).sum(axis=1) + np.abs(lo).sum(axis=1) + margin
+    # row layout: lower entries by descending d (ascending column), diagonal,
+    # upper entries by ascending d
+    cols = np.concatenate([i[:, None] - d[None, ::-1], i[:, None], i[:, None] + d[None, :]], axis=1)
+    vals = np.concatenate([lo[:, ::-1], diag[:, None], up], axis=1)
+    keep = np.concatenate([lo_ok[:, ::-1], np.ones((n, 1), bool), up_ok], axis=1)
+    counts = keep.sum(axis=1)
+    rowptr = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(counts, out=rowptr[1:])
+    return CSR(n, rowptr.astype(np.int32), cols[keep].astype(np.int32), vals[keep].astype(np.float64))
+
+
 def rhs_uniform(n: int, seed: int) -> np.ndarray:
     """Right-hand side with entries uniform in [-1, 1), float64."""
     return np.random.default_rng(seed).uniform(-1.0, 1.0, n)

@@ -1,5 +1,5 @@
 """Parity at the configurations' full sizes, in the launch configuration the
-bench times: SpMV checked on sampled rows the oracle computes one by one,
+bench times: every row of every SpMV compared with the oracle's product,
 solves checked through the oracle's own true residual of the GPU solution and
 its FP64 iteration counts."""
 
@@ -12,23 +12,46 @@ from gpu_util import mat_on_gpu, need_gpu, to_dev
 
 pytestmark = [pytest.mark.gpu, pytest.mark.slow]
 
-ROWS = 4096
+
+class _Ref:
+    """The oracle's product y = A x and its per-row scale sum_j |a_ij x_j|,
+    computed once per (A, x) and compared with every kernel run on them."""
+
+    def __init__(self, A, x):
+        self.x = np.ascontiguousarray(x, dtype=np.float64)
+        self.y = oracle.spmv(A, self.x)
+        self.scale = oracle.spmv_abs(A, self.x)
 
 
-def _sample_rows(n, seed=0):
-    rows = np.random.default_rng(seed).integers(0, n, ROWS)
-    return np.unique(np.concatenate([rows, [0, n - 1]]))
-
-
-def _spmv_sampled(spk, M, A, x, rows, tol=1e-14):
+def _spmv_all(spk, M, A, ref, tol=1e-14):
+    """Every row of the FP64 product against the oracle: |dy_i| <= tol * sum_j
+    |a_ij x_j| (tol = 0: bit-exact)."""
     import torch
 
     y = torch.empty(A.n, dtype=torch.float64, device="cuda")
-    spk.mat_mult(M, to_dev(x), y)
-    yg = y.cpu().numpy()[rows]
-    yo, ya = oracle.spmv_rows(A, x, rows)
-    assert np.all(np.abs(yg - yo) <= tol * ya), float(np.max(np.abs(yg - yo) / ya))
-    return yg, yo
+    spk.mat_mult(M, to_dev(ref.x), y)
+    yg = y.cpu().numpy()
+    err = np.abs(yg - ref.y)
+    bad = err > tol * ref.scale
+    if bad.any():
+        i = int(np.argmax(err / np.maximum(ref.scale, 1e-300)))
+        raise AssertionError(f"{int(bad.sum())} of {A.n} rows exceed {tol}; worst row {i}: "
+                             f"gpu {yg[i]!r} oracle {ref.y[i]!r} scale {ref.scale[i]!r}")
+    return yg
+
+
+def _spmv_f32_all(spk, M, A, x32, yo32, scale, ulps):
+    """Every row of the FP32-value product against the oracle's exact product
+    of the FP32-rounded values and x: |dy_i| <= ulps * 2^-24 * sum_j |a_ij x_j|
+    (ulps = 0: bit-exact)."""
+    import torch
+
+    y32 = torch.empty(A.n, dtype=torch.float32, device="cuda")
+    spk.mat_mult_f32(M, to_dev(x32), y32)
+    yg = y32.cpu().numpy().astype(np.float64)
+    err = np.abs(yg - yo32)
+    bad = err > ulps * 2.0**-24 * scale
+    assert not bad.any(), (int(bad.sum()), float(np.max(err / np.maximum(scale, 1e-300))))
 
 
 def _solve(spk, M, b, **kw):
@@ -54,23 +77,33 @@ def test_c1_all_seeds(seed):
 
 def test_c2_spmv_and_pcg():
     spk = need_gpu()
+    import torch
+
     A = spkgen.laplace3d7(128)
     assert (A.n, A.nnz) == (2097152, 14581760)
     M = mat_on_gpu(spk, A, flags=spk.MAT_MIXED)
     assert spk.KERNEL_NAMES[M.info.kernel] == "sell" and M.info.lanes == 16  # int16 offsets
-    rows = _sample_rows(A.n)
-    # bit-exact on integer data, 1e-14 on the bench's x (rhs of seed 0)
+    # bit-exact on integer data, 1e-14 on the bench's x (rhs of seed 0); FP32
+    # values bit-exact on integers, 16 FP32 ulps of the row scale on the rhs
     xi = np.random.default_rng(3).integers(-100, 100, A.n).astype(np.float64)
-    yg, yo = _spmv_sampled(spk, M, A, xi, rows, tol=0.0)
-    assert np.array_equal(yg, yo)
     b = spkgen.rhs_uniform(A.n, 0)
-    _spmv_sampled(spk, M, A, b, rows)
+    ri, rb = _Ref(A, xi), _Ref(A, b)
+    b32 = b.astype(np.float32)
+    yo32, sc32 = oracle.spmv_f32(A, b32), oracle.spmv_abs(A, b32.astype(np.float64))
+
+    def check_all():
+        _spmv_all(spk, M, A, ri, tol=0.0)
+        _spmv_all(spk, M, A, rb)
+        _spmv_f32_all(spk, M, A, xi.astype(np.float32), ri.y, ri.scale, 0)
+        _spmv_f32_all(spk, M, A, b32, yo32, sc32, 16)
+
+    check_all()
     # the stream family on the same matrix, then back to the selected one
     spk.mat_set_kernel(M, spk.KERNEL_STREAM, 0)
-    assert np.array_equal(_spmv_sampled(spk, M, A, xi, rows, tol=0.0)[0], yo)
-    _spmv_sampled(spk, M, A, b, rows)
+    check_all()
     spk.mat_set_kernel(M, spk.KERNEL_AUTO, 0)
     assert spk.KERNEL_NAMES[M.info.kernel] == "sell"
+    check_all()
     x64, r64 = _solve(spk, M, b)
     xo, ro, ho = oracle.pcg(A, b, hist_len=40)
     assert r64.reason == spk.CONVERGED_RTOL
@@ -113,20 +146,15 @@ def test_sell_load_policy_split_by_precision():
     it, sp = _cached_bits(A, 6, 256 << 20), _cached_bits(A, 2, 288 << 20)
     assert (it, sp) == (2, 3)
     assert M.info.cached_loads == it | sp << 2
-    rows = _sample_rows(A.n)
     xi = np.random.default_rng(5).integers(-100, 100, A.n).astype(np.float64)
-    yg, yo = _spmv_sampled(spk, M, A, xi, rows, tol=0.0)
-    assert np.array_equal(yg, yo)
     b = spkgen.rhs_uniform(A.n, 1)
-    _spmv_sampled(spk, M, A, b, rows)
-    y32 = torch.empty(A.n, dtype=torch.float32, device="cuda")
-    spk.mat_mult_f32(M, to_dev(xi, torch.float32), y32)
-    assert np.array_equal(y32.cpu().numpy(), oracle.spmv_f32(A, xi.astype(np.float32)))
-    spk.mat_mult_f32(M, to_dev(b, torch.float32), y32)
+    ri = _Ref(A, xi)
+    _spmv_all(spk, M, A, ri, tol=0.0)
+    _spmv_all(spk, M, A, _Ref(A, b))
+    _spmv_f32_all(spk, M, A, xi.astype(np.float32), ri.y, ri.scale, 0)
     b32 = b.astype(np.float32)
-    yo32 = oracle.spmv_f32(A, b32)
-    scale = oracle.spmv_abs(A, b32.astype(np.float64))
-    assert np.all(np.abs(y32.cpu().numpy().astype(np.float64) - yo32) <= 16 * 2.0**-24 * scale + 1e-30)
+    _spmv_f32_all(spk, M, A, b32, oracle.spmv_f32(A, b32), oracle.spmv_abs(A, b32.astype(np.float64)), 16)
+
 
 def test_c3_fp64_and_mixed():
     spk = need_gpu()
@@ -135,7 +163,12 @@ def test_c3_fp64_and_mixed():
     M = mat_on_gpu(spk, A, flags=spk.MAT_MIXED)
     assert spk.KERNEL_NAMES[M.info.kernel] == "sell"
     b = spkgen.rhs_uniform(A.n, 0)
-    _spmv_sampled(spk, M, A, b, _sample_rows(A.n, 1))
+    _spmv_all(spk, M, A, _Ref(A, b))
+    b32 = b.astype(np.float32)
+    # a sequential FMA chain over a 27-entry row: at most 28 FP32 units of
+    # the row scale (the FP64 check's 1e-14 has the same origin)
+    _spmv_f32_all(spk, M, A, b32, oracle.spmv_f32(A, b32), oracle.spmv_abs(A, b32.astype(np.float64)),
+                  int(A.row_lengths().max()) + 1)
     bn = oracle.nrm2(b)
     x64, r64 = _solve(spk, M, b)
     xm, rm = _solve(spk, M, b, precision=spk.PREC_MIXED)
@@ -155,26 +188,23 @@ def test_c4_powerlaw_spmv_all_kernels():
     assert spk.KERNEL_NAMES[M.info.kernel] == "sliced"
     assert M.info.lanes == 2048  # skewed rows: merge path over the slices
     assert M.info.row_max == A.row_lengths().max()
-    rows = _sample_rows(A.n, 2)
     x = spkgen.rhs_uniform(A.n, 0)
-    _spmv_sampled(spk, M, A, x, rows)  # the selected kernel meets 1e-14
+    ref = _Ref(A, x)
+    _spmv_all(spk, M, A, ref)  # the selected kernel meets 1e-14
     x32 = x.astype(np.float32)
-    v32 = A.val.astype(np.float32)
-    Af = spkgen.CSR(A.n, A.rowptr, A.col, v32.astype(np.float64))
-    yo32, ya32 = oracle.spmv_rows(Af, x32.astype(np.float64), rows)
+    Af = spkgen.CSR(A.n, A.rowptr, A.col, A.val.astype(np.float32).astype(np.float64))
+    yo32 = oracle.spmv(Af, x32.astype(np.float64))
+    sc32 = oracle.spmv_abs(Af, x32.astype(np.float64))
 
     def check_f32():  # per-row bound of the merge / sliced orders in FP32
-        y32 = torch.empty(A.n, dtype=torch.float32, device="cuda")
-        spk.mat_mult_f32(M, to_dev(x32), y32)
-        err = np.abs(y32.cpu().numpy()[rows].astype(np.float64) - yo32)
-        assert np.all(err <= 30 * 2.0 ** -24 * ya32), spk.KERNEL_NAMES[M.info.kernel]
+        _spmv_f32_all(spk, M, A, x32, yo32, sc32, 30)
 
     check_f32()
     for k, p, tol in ((spk.KERNEL_MERGE, 0, 1e-14), (spk.KERNEL_VECTOR, 32, 1e-14),
                       (spk.KERNEL_VECTOR, 64, 1e-14), (spk.KERNEL_SLICED, 2, 1e-14),
                       (spk.KERNEL_SLICED, 4, 1e-14)):
         spk.mat_set_kernel(M, k, p)
-        _spmv_sampled(spk, M, A, x, rows, tol)
+        _spmv_all(spk, M, A, ref, tol)
     spk.mat_set_kernel(M, spk.KERNEL_MERGE, 0)
     check_f32()
 

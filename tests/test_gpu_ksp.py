@@ -64,6 +64,42 @@ def test_pcg_fp64_parity(case, kernel):
     assert err <= 1e-5, err  # both within kappa * 1e-8 of the solution
 
 
+@pytest.mark.parametrize("width", [16, 32])
+def test_pcg_wide_sell_product(width):
+    """Rows of about 110 entries forced onto SELL: each lane of the
+    persistent grid would stream more than 96 stored entries, so the PCG
+    product runs one wavefront per slice and a one-block fold of its partials
+    (the path the 160^3 27-point system takes).  int16 column offsets (band
+    +-55) and int32 offsets (a +-40000 coupling).  FP64: the first 20
+    residual norms within 1e-10 of the oracle's, the iteration count, the
+    oracle's true residual; mixed: the oracle's true residual and the
+    solution error."""
+    spk = need_gpu()
+    n = 65536
+    offs = list(range(1, 56)) if width == 16 else list(range(1, 55)) + [40000]
+    A = spkgen.banded_spd(n, offs, seed=width, negative=True)
+    M = mat_on_gpu(spk, A, flags=spk.MAT_MIXED)
+    spk.mat_set_kernel(M, spk.KERNEL_SELL, width)
+    assert spk.KERNEL_NAMES[M.info.kernel] == "sell" and M.info.lanes == width
+    nblk = n // 256  # tiles of 256 rows, one block each (fewer than 2048)
+    assert M.info.stored_nnz > 96 * 256 * nblk  # the wide product's rule
+    b = spkgen.rhs_uniform(n, 4)
+    x, res, hist = _solve(spk, M, b, hist_len=400)
+    xo, ro, ho = oracle.pcg(A, b, rtol=1e-8, hist_len=400)
+    assert res.reason == spk.CONVERGED_RTOL, res.as_dict()
+    assert ro["iterations"] >= 20
+    assert abs(res.iterations - ro["iterations"]) <= max(2, 0.01 * ro["iterations"])
+    assert np.allclose(hist[:21], ho[:21], rtol=1e-10, atol=0), (hist[:21], ho[:21])
+    bn = oracle.nrm2(b)
+    assert oracle.nrm2(b - oracle.spmv(A, x)) <= 1e-8 * bn * (1 + 1e-6)
+    assert np.linalg.norm(x - xo) <= 1e-5 * np.linalg.norm(xo)
+    xm, rm, _ = _solve(spk, M, b, precision=spk.PREC_MIXED)
+    assert rm.reason == spk.CONVERGED_RTOL and rm.fallback_fp64 == 0, rm.as_dict()
+    assert oracle.nrm2(b - oracle.spmv(A, xm)) <= 1e-8 * bn * (1 + 1e-6)
+    assert np.linalg.norm(xm - xo) <= 1e-5 * np.linalg.norm(xo)
+    assert rm.inner_iterations <= 1.1 * ro["iterations"] + 2
+
+
 def test_pcg_graph_and_direct_launch_identical():
     spk = need_gpu()
     A = spkgen.diffusion3d27_lognormal(12, seed=3)

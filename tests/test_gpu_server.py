@@ -81,6 +81,59 @@ def test_server_alone_equals_mixed_batch(prec):
             (r.iterations, r.inner_iterations, r.outer_steps)
 
 
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_server_midflight_admission_alone_equals_batch(prec):
+    """Continuous admission: 10 requests submitted one at a time between
+    server_progress calls, with 3 slots, so each one enters while earlier
+    ones are still iterating (checked) and, once the slots are taken, waits
+    for and takes a slot another request has just freed.  Every result is
+    bitwise the one the same request gets alone, with the same iteration
+    counts."""
+    spk = need_gpu()
+    p = spk.PREC_FP64 if prec == "fp64" else spk.PREC_MIXED
+    items = _requests(10, seed=5)
+    opts = spk.server_opts_default()
+    opts.max_slots = 3
+    opts.graph_k = 2
+    S = spk.server_create(opts)
+    tickets, results = [], [None] * len(items)
+
+    def collect():
+        for i, t in enumerate(tickets):
+            if results[i] is None:
+                x = np.empty(items[i][1].n)
+                got = spk.server_poll(S, t, x)
+                if got is not None:
+                    results[i] = (x, got[0])
+
+    in_flight_at_submit = []
+    for _, A, b in items:
+        collect()
+        in_flight_at_submit.append(sum(r is None for r in results[:len(tickets)]))
+        tickets.append(spk.server_submit(S, A.rowptr, A.col, A.val, b, spk.ksp_opts(precision=p)))
+        spk.server_progress(S, 1)
+    rounds = 0
+    while any(r is None for r in results):
+        spk.server_progress(S, 1)
+        collect()
+        rounds += 1
+        assert rounds < 100000
+    S.close()
+    # every request after the first arrived while others were on the GPU, and
+    # more arrived than there are slots
+    assert all(k > 0 for k in in_flight_at_submit[1:]), in_flight_at_submit
+    assert max(in_flight_at_submit) >= opts.max_slots, in_flight_at_submit
+    for i, item in enumerate(items):
+        S1 = spk.server_create()
+        (x1, r1), = _run(spk, S1, [item], p)
+        S1.close()
+        x, r = results[i]
+        assert r.reason == spk.CONVERGED_RTOL
+        assert np.array_equal(x1, x), f"request {i} differs alone vs admitted mid-flight"
+        assert (r1.iterations, r1.inner_iterations, r1.outer_steps) == \
+            (r.iterations, r.inner_iterations, r.outer_steps)
+
+
 def test_server_budget_and_errors():
     spk = need_gpu()
     opts = spk.server_opts_default()

@@ -147,6 +147,37 @@ def test_spmv_one_long_row():
         assert np.array_equal(y.cpu().numpy(), ref)
 
 
+def _shuffle_rows(A, seed):
+    """The same matrix with the entries of every row in random order."""
+    rng = np.random.default_rng(seed)
+    key = np.repeat(np.arange(A.n), np.diff(A.rowptr)) * 2.0 + rng.random(A.nnz)
+    perm = np.argsort(key, kind="stable")
+    return spkgen.CSR(A.n, A.rowptr, A.col[perm].copy(), A.val[perm].copy())
+
+
+def test_spmv_unsorted_rows_every_family():
+    """Rows need not be sorted (only SPK_MAT_VALIDATE asks for it): a
+    power-law matrix of 2^19 rows with wide columns (the automatic choice is
+    the column-sliced layout, whose setup splits each row by column range)
+    and its rows shuffled gives the oracle's product, bit-exact on integer
+    values, with every kernel family."""
+    spk = need_gpu()
+    B = spkgen.powerlaw_spd(1 << 19, seed=4, hi=200)
+    vals = np.random.default_rng(2).integers(-9, 10, B.nnz).astype(np.float64)
+    A = _shuffle_rows(spkgen.CSR(B.n, B.rowptr, B.col, vals), 5)
+    assert np.any(np.diff(A.col[A.rowptr[0]:A.rowptr[1]]) < 0) or np.any(np.diff(A.col) < 0)
+    x = np.random.default_rng(3).integers(-50, 50, A.n).astype(np.float64)
+    ref = oracle.spmv(A, x)
+    M = mat_on_gpu(spk, A)
+    assert spk.KERNEL_NAMES[M.info.kernel] == "sliced"
+    for k, p in ((spk.KERNEL_AUTO, 0), (spk.KERNEL_SLICED, 8), (spk.KERNEL_SLICED, 2048),
+                 (spk.KERNEL_MERGE, 0), (spk.KERNEL_VECTOR, 16), (spk.KERNEL_STREAM, 0), (spk.KERNEL_SELL, 32)):
+        spk.mat_set_kernel(M, k, p)
+        y = to_dev(np.full(A.n, np.nan))
+        spk.mat_mult(M, to_dev(x), y)
+        assert np.array_equal(y.cpu().numpy(), ref), spk.KERNEL_NAMES[M.info.kernel]
+
+
 def _sell_stored(A):
     lens = np.diff(A.rowptr)
     pad = (-A.n) % 64
