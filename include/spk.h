@@ -253,6 +253,20 @@ int spk_vec_dot2(int32_t n, const double *x, const double *y, const double *w,
                  double *result, void *stream); /* result[0] = x.y, result[1] = x.w, one pass */
 int spk_vec_nrm2(int32_t n, const double *x, double *result, void *stream);
 
+/* spk_vec_dot2 without any allocation, for callers that cannot allocate
+ * device memory: code under HIP graph capture, tight serving loops, hosts
+ * that forbid hipMalloc.  Same arguments, kernels and result bits as
+ * spk_vec_dot2; it calls no hipMalloc/hipFree or allocating routine.  Its
+ * per-block partial sums live in a fixed array of 2 x 2048 doubles (32 KiB)
+ * compiled into the library, one copy per GPU, held until the process ends;
+ * a launch never has more than 2048 blocks, so every n >= 0 fits (a grid
+ * beyond it would be refused with SPK_EINVAL).  Every call on one GPU shares
+ * that GPU's array and leaves its partials in it: calls that overlap on one
+ * GPU (different streams, or threads without ordering) race and may return
+ * wrong sums; order them on one stream.  Devices 0..63. */
+int spk_vec_dot2_noalloc(int32_t n, const double *x, const double *y, const double *w,
+                         double *result, void *stream);
+
 /* ---------------------------------------------------------------- solver */
 typedef struct {
     double rtol;          /* default 1e-8 */

@@ -1077,6 +1077,20 @@ struct DotScratch {
 static std::mutex g_dot_mu;
 static std::map<std::pair<int, void *>, DotScratch> g_dot;
 
+// The two dot kernels on partials `part` (2 x kMaxBlocksSingle doubles).
+static int dot_enqueue(int32_t n, const double *x, const double *y, const double *w, int mode,
+                       double *result, double *part, void *stream)
+{
+    int grid = grid_for(n > 0 ? n : 1);
+    if (grid >= kXcd) grid -= grid % kXcd;
+    hipLaunchKernelGGL(k_dot, dim3(grid), dim3(kBlock), 0, (hipStream_t)stream, n, x,
+                       mode == 2 ? x : y, w, part);
+    hipLaunchKernelGGL(k_dot_fin, dim3(1), dim3(kBlock), 0, (hipStream_t)stream, grid,
+                       w ? 1 : 0, mode, part, result);
+    SPK_HIP(hipGetLastError());
+    return SPK_OK;
+}
+
 static int dot_launch(int32_t n, const double *x, const double *y, const double *w, int mode,
                       double *result, void *stream)
 {
@@ -1094,13 +1108,37 @@ static int dot_launch(int32_t n, const double *x, const double *y, const double 
             sc = it->second;
         }
     }
-    int grid = grid_for(n > 0 ? n : 1);
-    if (grid >= kXcd) grid -= grid % kXcd;
-    hipLaunchKernelGGL(k_dot, dim3(grid), dim3(kBlock), 0, (hipStream_t)stream, n, x,
-                       mode == 2 ? x : y, w, sc.part);
-    hipLaunchKernelGGL(k_dot_fin, dim3(1), dim3(kBlock), 0, (hipStream_t)stream, grid,
-                       w ? 1 : 0, mode, sc.part, result);
-    SPK_HIP(hipGetLastError());
+    return dot_enqueue(n, x, y, w, mode, result, sc.part, stream);
+}
+
+// Partials of the allocation-free fused dot: one launch has at most
+// kMaxBlocksSingle blocks and two sums per block, so every n fits.  Each GPU
+// holds its own copy for the life of the process; host code never passes this
+// name to a kernel (on the host it is a stand-in, not a device address) but
+// the address hipGetSymbolAddress returns for the current device.
+constexpr int kScratchDoubles = 2 * kMaxBlocksSingle;
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static double *g_scratch_ptr[kMaxDevices];  // device -> its copy of `scratch`
+
+static int scratch_on_device(double **out)
+{
+    int dev = 0;
+    SPK_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) {
+        set_error("device %d: the allocation-free entry points serve devices 0..%d", dev, kMaxDevices - 1);
+        return SPK_EINVAL;
+    }
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        SPK_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) { set_error("hipGetSymbolAddress returned no address for the scratch array"); return SPK_EHIP; }
+        g_scratch_ptr[dev] = (double *)p;
+    }
+    *out = g_scratch_ptr[dev];
     return SPK_OK;
 }
 
@@ -1114,6 +1152,22 @@ int spk_vec_dot2(int32_t n, const double *x, const double *y, const double *w, d
 {
     if (!w) { set_error("w is NULL"); return SPK_EINVAL; }
     return dot_launch(n, x, y, w, 1, result, stream);
+}
+
+int spk_vec_dot2_noalloc(int32_t n, const double *x, const double *y, const double *w, double *result,
+                         void *stream)
+{
+    if (n < 0 || !x || !y || !w || !result) { set_error("bad argument"); return SPK_EINVAL; }
+    const int grid = grid_for(n > 0 ? n : 1);
+    if (2 * grid > kScratchDoubles) {  // cannot happen while grid_for caps the grid
+        set_error("n = %d needs %d partials, more than the %d of the static scratch", n, 2 * grid,
+                  kScratchDoubles);
+        return SPK_EINVAL;
+    }
+    double *part = nullptr;
+    const int rc = scratch_on_device(&part);
+    if (rc != SPK_OK) return rc;
+    return dot_enqueue(n, x, y, w, 1, result, part, stream);
 }
 
 int spk_vec_nrm2(int32_t n, const double *x, double *result, void *stream)

@@ -121,6 +121,7 @@ _sig("spk_vec_axpy", ctypes.c_int, [i32, dbl, P, P, P])
 _sig("spk_vec_aypx", ctypes.c_int, [i32, dbl, P, P, P])
 _sig("spk_vec_dot", ctypes.c_int, [i32, P, P, P, P])
 _sig("spk_vec_dot2", ctypes.c_int, [i32, P, P, P, P, P])
+_sig("spk_vec_dot2_noalloc", ctypes.c_int, [i32, P, P, P, P, P])
 _sig("spk_vec_nrm2", ctypes.c_int, [i32, P, P, P])
 _sig("spk_ksp_opts_default", None, [ctypes.POINTER(KspOpts)])
 _sig("spk_ksp_solve", ctypes.c_int, [P, P, P, ctypes.POINTER(KspOpts),
@@ -156,7 +157,7 @@ _sig("spk_cache_flush", ctypes.c_int, [P, i64, P])
 EXPORTS = [
     "spk_mat_create_csr", "spk_mat_set_kernel", "spk_mat_mult", "spk_mat_mult_f32",
     "spk_mat_get_info", "spk_pc_jacobi_apply", "spk_pc_chebyshev", "spk_mat_destroy", "spk_vec_axpy",
-    "spk_vec_aypx", "spk_vec_dot", "spk_vec_dot2", "spk_vec_nrm2", "spk_ksp_opts_default",
+    "spk_vec_aypx", "spk_vec_dot", "spk_vec_dot2", "spk_vec_dot2_noalloc", "spk_vec_nrm2", "spk_ksp_opts_default",
     "spk_ksp_solve", "spk_mat_mult_multi", "spk_ksp_solve_multi", "spk_mg_opts_default",
     "spk_mg_create", "spk_mg_get_info", "spk_mg_copy_level", "spk_mg_apply", "spk_mg_profile",
     "spk_ksp_solve_mg", "spk_mg_destroy", "spk_server_opts_default", "spk_server_create", "spk_server_submit",
@@ -344,6 +345,14 @@ def vec_dot2(x, y, w, result, stream=None):
                              _dev(w, torch.float64, n, "w"),
                              _dev(result, torch.float64, None, "result"), _stream(stream)),
            "spk_vec_dot2")
+
+
+def vec_dot2_noalloc(x, y, w, result, stream=None):
+    n = x.numel()
+    _check(_lib.spk_vec_dot2_noalloc(n, _dev(x, torch.float64, n, "x"), _dev(y, torch.float64, n, "y"),
+                                     _dev(w, torch.float64, n, "w"),
+                                     _dev(result, torch.float64, None, "result"), _stream(stream)),
+           "spk_vec_dot2_noalloc")
 
 
 def vec_nrm2(x, result, stream=None):
