@@ -13,8 +13,11 @@
  *    accessor model of Response A4);
  *  - every call takes the caller's stream, so that the library and the
  *    application share one queue (Challenge / Response A6);
- *  - no call synchronises the device, and only the solve calls wait for their
- *    own stream, once per batch of iterations (Response A1).
+ *  - no call synchronises the device: the solve calls wait for their own
+ *    stream, once per batch of iterations (Response A1); setup calls wait
+ *    for the stream they were given; only the release of device memory in
+ *    the *_destroy calls and when a handle re-plans (spk_mat_set_kernel)
+ *    goes through hipFree, which HIP documents as waiting for the device.
  *
  * Conventions for every entry point:
  *  - `stream` is a hipStream_t passed as `void*`; NULL means the null stream.
@@ -25,7 +28,10 @@
  *    message for the last failing call on the calling thread.
  *  - The caller owns every pointer it passes; the library never frees caller
  *    memory.  Handles own what they allocate and free it in *_destroy.
- *  - A handle may be used from one thread / one stream at a time.
+ *  - A handle may be used from one thread / one stream at a time.  It
+ *    remembers the stream of its latest call; before moving a handle to
+ *    another stream the caller orders the two streams (an event, or a
+ *    synchronisation), as with any stream-ordered resource.
  */
 #ifndef SPK_H
 #define SPK_H
@@ -140,9 +146,11 @@ typedef struct {
     int64_t bytes_spmv_f64;  /* algorithmic bytes of one FP64 SpMV:
                                 12 nnz + 4 (n+1) + 16 n */
     int64_t bytes_spmv_f32;  /* FP32 values and vectors: 8 nnz + 4 (n+1) + 8 n */
-    int64_t bytes_pcg_iter_f64;  /* one FP64 PCG iteration as implemented:
-                                    12 nnz + 4 (n+1) + 96 n */
-    int64_t bytes_pcg_iter_f32;  /* one FP32 inner iteration: 8 nnz + 4 (n+1) + 48 n */
+    int64_t bytes_pcg_iter_f64;  /* one FP64 PCG iteration, algorithmic: the
+                                    matrix once and 11 vector passes,
+                                    12 nnz + 4 (n+1) + 88 n (the kernels move
+                                    96 n: z is stored and read once) */
+    int64_t bytes_pcg_iter_f32;  /* one FP32 inner iteration: 8 nnz + 4 (n+1) + 44 n */
     int64_t device_bytes;    /* device memory held by the handle */
     int32_t zero_diag_rows;  /* rows without a nonzero diagonal */
     int32_t cached_loads;    /* SELL layout read with ordinary (cache-allocating)
@@ -192,8 +200,11 @@ int spk_mat_create_csr(int32_t n, int64_t nnz, const int32_t *rowptr,
  * (automatic: the merge path over the slices when 8n + nnz < 2^31, else
  * lanes per slice row), a power of two in 1..64 (lanes per slice row) or
  * 2048 (merge path over the slices), ignored for MERGE.
- * Invalidates cached solver graphs. */
-int spk_mat_set_kernel(spk_mat *A, int kernel, int32_t param);
+ * Waits for the handle's earlier work (the stream of its latest call), then
+ * builds the layout the family needs on `stream` and returns once it is
+ * built (it synchronises `stream` only).  Invalidates cached solver graphs
+ * and releases the solver workspaces, which the next solve re-creates. */
+int spk_mat_set_kernel(spk_mat *A, int kernel, int32_t param, void *stream);
 
 /* y = A x (Sec. 4: MatMult on an AIJ matrix).  x, y: device double[n],
  * must not overlap.  Queued on `stream`; no synchronisation. */
@@ -236,7 +247,8 @@ int spk_pc_chebyshev(const spk_mat *A, const double *b, double *x, double *r_out
                      int32_t steps, double emin, double emax, int32_t x0_nonzero,
                      void *stream);
 
-/* Waits for the handle's queued work, then frees everything it owns. */
+/* Waits for the handle's queued work (the stream of its latest call), then
+ * frees everything it owns. */
 int spk_mat_destroy(spk_mat *A);
 
 /* ---------------------------------------------------------------- vectors
@@ -286,7 +298,13 @@ typedef struct {
     int32_t hist_len;
     int32_t single_reduction;  /* FP64 only: 1 selects the single-reduction
                                   (Chronopoulos-Gear) recurrences, two kernels
-                                  per iteration instead of four (default 0) */
+                                  per iteration instead of three (default 0) */
+    int32_t profile;      /* 1: time the SpMV product of every iteration (FP64,
+                             or FP32 inner for mixed) with a HIP event pair on
+                             `stream`; kernels are then launched one
+                             iteration at a time without graphs.  Results in
+                             spk_ksp_result.product_*.  Not with
+                             single_reduction (default 0) */
 } spk_ksp_opts;
 
 void spk_ksp_opts_default(spk_ksp_opts *o);
@@ -301,6 +319,11 @@ typedef struct {
     double rnorm0, rnorm, bnorm;
     double true_rel_residual;  /* ||b - A x|| / ||b|| from a fresh FP64 SpMV */
     double seconds;            /* host wall time of the call */
+    double product_ms;         /* opts.profile: summed event time of the
+                                  product launches of the counted iterations
+                                  (launches after the solve stopped excluded) */
+    int32_t product_launches;  /* opts.profile: the launches product_ms covers */
+    int32_t pad_;
 } spk_ksp_result;
 
 /*

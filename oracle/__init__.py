@@ -35,12 +35,34 @@ REASONS = {
 }
 
 
+_LIB_OMP = os.path.join(_HERE, "liboracle_omp.so")
+
+
 def build(extra_flags=()) -> str:
-    """Compile liboracle.so with gcc (always recompiles)."""
+    """Compile liboracle.so with gcc (always recompiles), and the same source
+    with OpenMP as liboracle_omp.so (used only to time the oracle on all host
+    cores)."""
     cmd = ["gcc", "-O2", "-ffp-contract=off", "-fPIC", "-shared", "-std=c11",
            *extra_flags, _SRC, "-o", _LIB, "-lm"]
     subprocess.run(cmd, check=True, cwd=_HERE)
+    cmd = ["gcc", "-O2", "-ffp-contract=off", "-fPIC", "-shared", "-std=c11", "-fopenmp",
+           *extra_flags, _SRC, "-o", _LIB_OMP, "-lm"]
+    subprocess.run(cmd, check=True, cwd=_HERE)
     return _LIB
+
+
+_lib_omp = None
+
+
+def load_omp():
+    """The OpenMP build of the same oracle (parallel loops, fixed-order
+    chunked inner products); threads from OMP_NUM_THREADS or all cores."""
+    global _lib_omp
+    if _lib_omp is None:
+        if not os.path.exists(_LIB_OMP):
+            build()
+        _lib_omp = load(_LIB_OMP)
+    return _lib_omp
 
 
 class _PcgResult(ctypes.Structure):

@@ -33,6 +33,13 @@
  * Every function is pinned by CPU tests against values fixed by mathematics
  * (closed-form eigenpairs, exact integer arithmetic, brute-force dense solves,
  * finite termination), not against itself.
+ *
+ * Parallel build (only for timing the oracle on all host cores): the same
+ * file compiled with -fopenmp runs the row and vector loops of the SpMV, the
+ * vector updates and the PCG with "omp parallel for" (static schedule), and
+ * forms each inner product as fixed chunks of ORC_CHUNK entries summed in long
+ * double, then the chunk sums in chunk order (the same bits for any thread
+ * count).  The serial build ignores the pragmas and keeps one long double sum.
  */
 #include <math.h>
 #include <stdint.h>
@@ -41,10 +48,33 @@
 
 #include "oracle.h"
 
+#ifdef _OPENMP
+#define ORC_CHUNK 32768
+/* sum_i x_i y_i over fixed chunks (parallel build only). */
+static long double chunked_dot(int32_t n, const double *x, const double *y)
+{
+    const int32_t nc = (n + ORC_CHUNK - 1) / ORC_CHUNK;
+    long double *part = (long double *)malloc(sizeof(long double) * (size_t)(nc > 0 ? nc : 1));
+    if (!part) return NAN;
+#pragma omp parallel for schedule(static)
+    for (int32_t c = 0; c < nc; ++c) {
+        const int32_t e = (c + 1) * (int64_t)ORC_CHUNK < n ? (c + 1) * ORC_CHUNK : n;
+        long double s = 0.0L;
+        for (int32_t i = c * ORC_CHUNK; i < e; ++i) s += (long double)x[i] * (long double)y[i];
+        part[c] = s;
+    }
+    long double s = 0.0L;
+    for (int32_t c = 0; c < nc; ++c) s += part[c];
+    free(part);
+    return s;
+}
+#endif
+
 /* y_i = sum_k val[k] * x[col[k]] over k in [rowptr[i], rowptr[i+1]). */
 void orc_spmv(int32_t n, const int32_t *rowptr, const int32_t *col,
               const double *val, const double *x, double *y)
 {
+#pragma omp parallel for schedule(static)
     for (int32_t i = 0; i < n; ++i) {
         long double s = 0.0L;
         for (int32_t k = rowptr[i]; k < rowptr[i + 1]; ++k)
@@ -99,6 +129,9 @@ void orc_spmv_rows(int32_t nrows, const int32_t *rows, const int32_t *rowptr,
 
 double orc_dot(int32_t n, const double *x, const double *y)
 {
+#ifdef _OPENMP
+    return (double)chunked_dot(n, x, y);
+#endif
     long double s = 0.0L;
     for (int32_t i = 0; i < n; ++i)
         s += (long double)x[i] * (long double)y[i];
@@ -107,6 +140,9 @@ double orc_dot(int32_t n, const double *x, const double *y)
 
 double orc_nrm2(int32_t n, const double *x)
 {
+#ifdef _OPENMP
+    return (double)sqrtl(chunked_dot(n, x, x));
+#endif
     long double s = 0.0L;
     for (int32_t i = 0; i < n; ++i)
         s += (long double)x[i] * (long double)x[i];
@@ -116,6 +152,7 @@ double orc_nrm2(int32_t n, const double *x)
 /* y <- alpha x + y, exact product-plus-sum rounded once. */
 void orc_axpy(int32_t n, double alpha, const double *x, double *y)
 {
+#pragma omp parallel for schedule(static)
     for (int32_t i = 0; i < n; ++i)
         y[i] = fma(alpha, x[i], y[i]);
 }
@@ -123,6 +160,7 @@ void orc_axpy(int32_t n, double alpha, const double *x, double *y)
 /* y <- x + beta y, exact product-plus-sum rounded once. */
 void orc_aypx(int32_t n, double beta, const double *x, double *y)
 {
+#pragma omp parallel for schedule(static)
     for (int32_t i = 0; i < n; ++i)
         y[i] = fma(beta, y[i], x[i]);
 }
@@ -145,6 +183,7 @@ int orc_diag_inv(int32_t n, const int32_t *rowptr, const int32_t *col,
 /* Jacobi PCApply: z_i = dinv_i * r_i. */
 void orc_jacobi_apply(int32_t n, const double *dinv, const double *r, double *z)
 {
+#pragma omp parallel for schedule(static)
     for (int32_t i = 0; i < n; ++i) z[i] = dinv[i] * r[i];
 }
 
@@ -216,8 +255,10 @@ int orc_pcg_pc(int32_t n, const int32_t *rowptr, const int32_t *col,
     }
     if (x0_nonzero) {
         orc_spmv(n, rowptr, col, val, x, q);
+#pragma omp parallel for schedule(static)
         for (int32_t i = 0; i < n; ++i) r[i] = b[i] - q[i];
     } else {
+#pragma omp parallel for schedule(static)
         for (int32_t i = 0; i < n; ++i) { x[i] = 0.0; r[i] = b[i]; }
     }
     double rnorm = orc_nrm2(n, r);
@@ -257,6 +298,7 @@ int orc_pcg_pc(int32_t n, const int32_t *rowptr, const int32_t *col,
             if (rnorm <= thresh) {
                 /* recursive test passed: confirm with the true residual */
                 orc_spmv(n, rowptr, col, val, x, q);
+#pragma omp parallel for schedule(static)
                 for (int32_t i = 0; i < n; ++i) r[i] = b[i] - q[i];
                 double tn = orc_nrm2(n, r);
                 if (tn <= thresh) {
@@ -287,6 +329,7 @@ int orc_pcg_pc(int32_t n, const int32_t *rowptr, const int32_t *col,
     res->rnorm = rnorm;
     /* report the true relative residual from a fresh accurate product */
     orc_spmv(n, rowptr, col, val, x, q);
+#pragma omp parallel for schedule(static)
     for (int32_t i = 0; i < n; ++i) r[i] = b[i] - q[i];
     res->true_rel_residual = orc_nrm2(n, r) / bnorm;
 

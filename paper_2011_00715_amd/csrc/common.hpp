@@ -31,9 +31,11 @@ enum : int32_t {
 // Slots of the per-block partial sums (each B doubles).
 enum { kPartPq = 0, kPartRz = 1, kPartRr = 2, kPartBb = 3, kNumPart = 4 };
 
-// Device-resident scalars of one system.  Written only by the one-block
-// finalize kernels (and the one-thread init kernel); read by every block of
-// the next kernels, which turn into no-ops once `status` is no longer
+// Device-resident scalars of one system.  Written by one block only: the
+// one-block finalize kernels, the one-thread init kernel, block 0 of the
+// PCG update pass (the snap_* fields) and block 0 of the p/x pass (the rest);
+// no kernel's blocks read a field that a block of the same kernel writes.
+// Every later kernel turns into a no-op once `status` is no longer
 // SPK_RUNNING.
 struct SysState {
     int32_t status;       // SPK_RUNNING or a reason
@@ -50,6 +52,9 @@ struct SysState {
     int32_t hist_len;
     int32_t ru;           // mixed: 1 keeps p across refinements (reliable updates)
     int32_t fresh_p;      // mixed: the next refinement starts p from z
+    // the scalars of the current iteration as the update pass saw them: the
+    // p/x pass decides from these while its block 0 rewrites the live ones
+    int32_t snap_status, snap_phase, snap_iter, snap_inner_iter;
     double scale;         // mixed: r32 = r / scale, x += scale d
     double rho, alpha, beta, eta;
     double rnorm, rnorm0, bnorm, thresh, rtol, atol;
@@ -57,6 +62,7 @@ struct SysState {
     double s;             // mixed: ||r|| of the current outer residual
     double s_prev;        // mixed: previous outer ||r||
     double rnorm_true;    // result of the last true-residual kernel
+    double snap_rho, snap_eta;
 };
 
 // One linear system as seen by the batched kernels.

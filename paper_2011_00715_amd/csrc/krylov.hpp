@@ -9,13 +9,16 @@
 // system itself, never on the rest of the batch.
 //
 // One PCG iteration (textbook preconditioned CG; the paper names CG in
-// Sec. 5.5 and the Jacobi smoother in Sec. 5.3):
+// Sec. 5.5 and the Jacobi smoother in Sec. 5.3), three kernels:
 //   A   q = A p, per-block p.q
-//   B   eta = p.q and alpha = rho / eta    F_B  breakdown and convergence
-//       (each block sums A's partials),         tests, beta, and what C
-//       r -= alpha q, z = D^-1 r, per-block     must do next
-//       r.z and r.r (one pass; Sec. 4 Response F3: fused inner products)
-//   C   x += alpha p, p = z + beta p
+//   B   eta = p.q and alpha = rho / eta (each block sums A's partials in the
+//       same fixed order), r -= alpha q, z = D^-1 r, per-block r.z and r.r
+//       (one pass; Sec. 4 Response F3: fused inner products); block 0 also
+//       records the scalars it used (state snap_*)
+//   C   every block sums B's r.z and r.r partials in the same fixed order
+//       and takes the same decision from the recorded scalars (convergence
+//       and breakdown tests, beta); block 0 stores it; then x += alpha p and,
+//       while iterating, p = z + beta p
 // Scalars live on the device and every kernel is a no-op once its system has
 // stopped, so a captured graph of many iterations replays without host round
 // trips (Challenge A1: fusion, graphs, pipelining).
@@ -671,7 +674,9 @@ __global__ __launch_bounds__(kBlock) void k_pcg_pq(B a)
 // B: eta = p.q and alpha = rho / eta (every block sums the p.q partials
 // itself, in the same fixed order, so all blocks hold the same bits), then
 // r -= alpha q, z = D^-1 r, per-block r.z and r.r.  With eta <= 0 or not
-// finite the block changes nothing; F_B records the reason.
+// finite the block changes nothing; C records the reason.  Block 0 records
+// the gate, iteration counts, rho and eta it used for C (every B launch of
+// the system's precision does, gate open or not).
 template <class V, class B>
 __global__ __launch_bounds__(kBlock) void k_pcg_update(B a)
 {
@@ -700,6 +705,16 @@ __global__ __launch_bounds__(kBlock) void k_pcg_update(B a)
             const Gate g = load_gate(st);
             const double rho = st->rho;
             const double eta = one_chunk ? partials_sum(pv, red) : reduce_partials(pq, d.nblk, red);
+            if (j == 0 && threadIdx.x == 0 && g.mixed == Vecs<V>::mixed) {
+                // what C decides from: C's block 0 rewrites the live fields
+                SysState *w = d.st;
+                w->snap_status = g.status;
+                w->snap_phase = g.phase;
+                w->snap_iter = st->iter;
+                w->snap_inner_iter = st->inner_iter;
+                w->snap_rho = rho;
+                w->snap_eta = eta;
+            }
             if (!gate_ok(g, Vecs<V>::gate) || !(eta > 0.0) || !finite(eta)) return false;
             nalpha = (V)(-(rho / eta));
             run = true;
@@ -722,73 +737,133 @@ __global__ __launch_bounds__(kBlock) void k_pcg_update(B a)
     }
 }
 
-// F_B: convergence test and beta; cmode tells C what to do: 2 = x and p
-// updates, 1 = the last x update only, 0 = nothing.  F_B runs every
-// iteration so that it can reset cmode after the last update.
-template <class V, class B>
-__global__ __launch_bounds__(kBlock) void k_fin_update(B a)
+// The decision of one iteration from B's recorded scalars and the r.z, r.r
+// sums; identical in every block of C.  cmode: 2 = x and p updates, 1 = the
+// last x update only, 0 = nothing.
+struct Step {
+    int cmode = 0;
+    int status = SPK_RUNNING;  // new status (SPK_RUNNING: unchanged)
+    int to_update = 0;         // mixed: the inner solve ends, refine next
+    int fresh_p = 0;           // mixed: the next refinement restarts p from z
+    double alpha = 0.0, beta = 0.0, rn = 0.0;
+};
+
+__device__ __forceinline__ Step pcg_decide(int mixed, int iter, int inner_iter, double rho, double eta,
+                                           double RZ, double RR, const SysState *st)
 {
-    __shared__ double red[kBlock / kWave];
-    SysDesc d;
-    if (!fin_locate(a, d)) return;
-    SysState *st = d.st;
-    // the state and the three partial arrays are loaded in one round trip
-    const Gate g = load_gate(st);
-    const double rho = st->rho, thresh = st->thresh, rtol = st->rtol, bnorm = st->bnorm;
-    const double inner_thresh = st->inner_thresh;
-    const int iter = st->iter, inner_iter = st->inner_iter, maxit = st->maxit;
-    const int inner_maxit = st->inner_maxit, hist_len = st->hist_len;
-    double eta, RZ, RR;
-    reduce_partials3(d.partials + kPartPq * d.nblk, d.partials + kPartRz * d.nblk,
-                     d.partials + kPartRr * d.nblk, d.nblk, red, eta, RZ, RR);
-    if (g.mixed != Vecs<V>::mixed) return;
-    if (!gate_ok(g, Vecs<V>::gate)) {
-        if (threadIdx.x == 0) st->cmode = 0;
-        return;
-    }
-    if (threadIdx.x != 0) return;
-    st->eta = eta;
-    st->cmode = 0;
-    if (!finite(eta)) { st->status = SPK_DIVERGED_NANORINF; return; }
+    Step t;
+    if (!finite(eta)) { t.status = SPK_DIVERGED_NANORINF; return t; }
     if (eta <= 0.0) {
-        if (g.mixed) {  // inner breakdown: refine from here with a fresh p
-            st->phase = kPhaseUpdate;
-            st->fresh_p = 1;
-        } else st->status = SPK_DIVERGED_INDEFINITE_MAT;
-        return;
+        if (mixed) { t.to_update = 1; t.fresh_p = 1; }  // inner breakdown: refine, fresh p
+        else t.status = SPK_DIVERGED_INDEFINITE_MAT;
+        return t;
     }
-    st->alpha = rho / eta;
+    t.alpha = rho / eta;
     const int k = iter + 1;
-    st->iter = k;
-    const double rn = sqrt(RR);
-    st->cmode = 1;  // stop unless the tests below continue
-    if (!g.mixed) {
-        st->rnorm = rn;
-        if (d.hist && k < hist_len) d.hist[k] = rn;
-        if (!finite(rn)) st->status = SPK_DIVERGED_NANORINF;
-        else if (rn <= thresh)
-            st->status = rn <= rtol * bnorm ? SPK_CONVERGED_RTOL : SPK_CONVERGED_ATOL;
-        else if (k >= maxit) st->status = SPK_DIVERGED_ITS;
-        else if (!finite(RZ)) st->status = SPK_DIVERGED_NANORINF;
-        else if (RZ < 0.0) st->status = SPK_DIVERGED_INDEFINITE_PC;
-        else if (RZ == 0.0) st->status = SPK_DIVERGED_BREAKDOWN;
-        else { st->beta = RZ / rho; st->rho = RZ; st->cmode = 2; }
+    t.rn = sqrt(RR);
+    t.cmode = 1;  // stop unless the tests below continue
+    if (!mixed) {
+        if (!finite(t.rn)) t.status = SPK_DIVERGED_NANORINF;
+        else if (t.rn <= st->thresh)
+            t.status = t.rn <= st->rtol * st->bnorm ? SPK_CONVERGED_RTOL : SPK_CONVERGED_ATOL;
+        else if (k >= st->maxit) t.status = SPK_DIVERGED_ITS;
+        else if (!finite(RZ)) t.status = SPK_DIVERGED_NANORINF;
+        else if (RZ < 0.0) t.status = SPK_DIVERGED_INDEFINITE_PC;
+        else if (RZ == 0.0) t.status = SPK_DIVERGED_BREAKDOWN;
+        else { t.beta = RZ / rho; t.cmode = 2; }
     } else {
         const int ki = inner_iter + 1;
-        st->inner_iter = ki;
-        if (!finite(rn) || !finite(RZ)) st->status = SPK_DIVERGED_NANORINF;
-        else if (rn <= inner_thresh || ki >= inner_maxit || k >= maxit || RZ <= 0.0) {
-            st->phase = kPhaseUpdate;
-            if (RZ <= 0.0) st->fresh_p = 1;
-        } else { st->beta = RZ / rho; st->rho = RZ; st->cmode = 2; }
+        if (!finite(t.rn) || !finite(RZ)) t.status = SPK_DIVERGED_NANORINF;
+        else if (t.rn <= st->inner_thresh || ki >= st->inner_maxit || k >= st->maxit || RZ <= 0.0) {
+            t.to_update = 1;
+            t.fresh_p = RZ <= 0.0;
+        } else { t.beta = RZ / rho; t.cmode = 2; }
     }
+    return t;
 }
 
-// C: x += alpha p (d for mixed) and, while iterating, p = z + beta p.
-// With `prelude` set it only serves cmode 3 (the p update that continues CG
-// after a reliable update); otherwise it serves cmodes 1 and 2.
+// C: the iteration's decision (see pcg_decide), stored by block 0, then
+// x += alpha p (d for mixed) and, while iterating, p = z + beta p.
 template <class V, class B>
-__global__ __launch_bounds__(kBlock) void k_pcg_px(B a, int prelude)
+__global__ __launch_bounds__(kBlock) void k_pcg_px(B a)
+{
+    __shared__ double red[kBlock / kWave];
+    int j;
+    SysDesc d;
+    if (!locate(a, j, d)) return;
+    if (!Vecs<V>::present(d)) return;
+    SysState *st = d.st;
+    int rb, re;
+    row_range(d, j, rb, re);
+    V *__restrict__ x = Vecs<V>::x(d);
+    V *__restrict__ p = Vecs<V>::p(d);
+    const V *__restrict__ z = Vecs<V>::z(d);
+    const double *prz = d.partials + kPartRz * d.nblk;
+    const double *prr = d.partials + kPartRr * d.nblk;
+    const bool one_chunk = d.nblk <= kBlock * kPartChunk;
+    double vz[kPartChunk], vr[kPartChunk];
+    if (one_chunk) {
+        partials_load(prz, d.nblk, vz);
+        partials_load(prr, d.nblk, vr);
+    }
+    int cm = 0;
+    V alpha = V(0), beta = V(0);
+    rows_prefetched(
+        rb, re, [&](int i) { return Trio<V>{p[i], z[i], x[i]}; },
+        [&]() {
+            // B's record of this iteration; block 0 below writes only the
+            // live fields, which no block of this kernel reads
+            const int mixed = st->mixed;
+            const Gate g{st->snap_status, st->snap_phase, mixed};
+            const int iter = st->snap_iter, inner_iter = st->snap_inner_iter;
+            const double rho = st->snap_rho, eta = st->snap_eta;
+            double RZ, RR;
+            if (one_chunk) {
+                RZ = partials_sum(vz, red);
+                RR = partials_sum(vr, red);
+            } else {
+                reduce_partials2(prz, prr, d.nblk, red, RZ, RR);
+            }
+            if (mixed != Vecs<V>::mixed || !gate_ok(g, Vecs<V>::gate)) return false;
+            const Step t = pcg_decide(mixed, iter, inner_iter, rho, eta, RZ, RR, st);
+            if (j == 0 && threadIdx.x == 0) {
+                st->cmode = 0;  // a pending p continuation has been served
+                st->eta = eta;
+                if (t.status != SPK_RUNNING) st->status = t.status;
+                if (t.to_update) {
+                    st->phase = kPhaseUpdate;
+                    if (t.fresh_p) st->fresh_p = 1;
+                }
+                if (eta > 0.0 && finite(eta)) {
+                    const int k = iter + 1;
+                    st->alpha = t.alpha;
+                    st->iter = k;
+                    if (mixed) st->inner_iter = inner_iter + 1;
+                    else {
+                        st->rnorm = t.rn;
+                        if (d.hist && k < st->hist_len) d.hist[k] = t.rn;
+                    }
+                    if (t.cmode == 2) {
+                        st->beta = t.beta;
+                        st->rho = RZ;
+                    }
+                }
+            }
+            cm = t.cmode;
+            alpha = (V)t.alpha;
+            beta = (V)t.beta;
+            return cm != 0;
+        },
+        [&](int i, const Trio<V> &v) {
+            x[i] = fma(alpha, v.a, v.c);
+            if (cm == 2) p[i] = fma(beta, v.a, v.b);
+        });
+}
+
+// p = z + beta p where the last refinement asked for it (cmode 3: CG
+// continues after a reliable update, with beta from k_fin_setup32).
+template <class V, class B>
+__global__ __launch_bounds__(kBlock) void k_pcg_p_continue(B a)
 {
     int j;
     SysDesc d;
@@ -797,29 +872,16 @@ __global__ __launch_bounds__(kBlock) void k_pcg_px(B a, int prelude)
     const SysState *st = d.st;
     int rb, re;
     row_range(d, j, rb, re);
-    V *__restrict__ x = Vecs<V>::x(d);
     V *__restrict__ p = Vecs<V>::p(d);
     const V *__restrict__ z = Vecs<V>::z(d);
-    int cm = 0;
-    V alpha = V(0), beta = V(0);
+    V beta = V(0);
     rows_prefetched(
-        rb, re, [&](int i) { return Trio<V>{p[i], z[i], x[i]}; },
+        rb, re, [&](int i) { return Trio<V>{p[i], z[i], V(0)}; },
         [&]() {
-            const int mixed = st->mixed;
-            cm = st->cmode;
-            alpha = (V)st->alpha;
             beta = (V)st->beta;
-            if (mixed != Vecs<V>::mixed) return false;
-            return cm != 0 && (cm == 3) == (prelude != 0);
+            return st->mixed == Vecs<V>::mixed && st->status == SPK_RUNNING && st->cmode == 3;
         },
-        [&](int i, const Trio<V> &v) {
-            if (cm == 3) {  // p only: CG continues after a reliable update
-                p[i] = fma(beta, v.a, v.b);
-            } else {
-                x[i] = fma(alpha, v.a, v.c);
-                if (cm == 2) p[i] = fma(beta, v.a, v.b);
-            }
-        });
+        [&](int i, const Trio<V> &v) { p[i] = fma(beta, v.a, v.b); });
 }
 
 }  // namespace spk

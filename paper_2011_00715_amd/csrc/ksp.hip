@@ -18,7 +18,7 @@ void free_workspace(spk_mat *A)
 {
     Workspace *w = A->ws;
     if (!w) return;
-    hipDeviceSynchronize();
+    hipStreamSynchronize(A->stream);
     if (w->g64) hipGraphExecDestroy(w->g64);
     if (w->gmix) hipGraphExecDestroy(w->gmix);
     for (auto &e : w->ev)
@@ -45,6 +45,8 @@ void free_workspace(spk_mat *A)
     hipFree(w->srp);
     hipFree(w->sc);
     if (w->gsr) hipGraphExecDestroy(w->gsr);
+    for (auto &e : w->pev)
+        if (e) hipEventDestroy(e);
     hipHostFree(w->pdesc);
     hipHostFree(w->pst);
     hipHostFree(w->pstatus);
@@ -76,7 +78,16 @@ static int dalloc(T **p, int64_t count, Workspace *w)
 // 128^3 28.
 constexpr int64_t kWideEntriesPerLane = 96;
 
-static int get_workspace(spk_mat *A, bool mixed, Workspace **out)
+static __global__ void k_ws_init(int32_t *blk_start, int nblk, SysState *st)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        blk_start[0] = 0;
+        blk_start[1] = nblk;
+        *st = SysState{};
+    }
+}
+
+static int get_workspace(spk_mat *A, bool mixed, Workspace **out, hipStream_t s)
 {
     Workspace *w = A->ws;
     if (!w) {
@@ -105,9 +116,8 @@ static int get_workspace(spk_mat *A, bool mixed, Workspace **out)
         SPK_HIP(hipHostMalloc((void **)&w->pstatus, sizeof(int32_t) * 8, hipHostMallocDefault));
         for (auto &e : w->ev) SPK_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
         SPK_HIP(hipStreamCreateWithFlags(&w->cap, hipStreamNonBlocking));
-        const int32_t bs[2] = {0, A->nblk};
-        SPK_HIP(hipMemcpy(w->blk_start, bs, sizeof(bs), hipMemcpyHostToDevice));
-        SPK_HIP(hipMemset(w->st, 0, sizeof(SysState)));
+        hipLaunchKernelGGL(k_ws_init, dim3(1), dim3(64), 0, s, w->blk_start, A->nblk, w->st);
+        SPK_HIP(hipGetLastError());
         SysDesc &d = w->hdesc;
         d.n = A->n;
         d.R = A->R;
@@ -189,11 +199,33 @@ static int launch_resid(spk_mat *A, Workspace *w, int purpose, bool gated, hipSt
     return SPK_OK;
 }
 
+// The next event pair of a profiled solve (created on first use).
+static int prof_pair(Workspace *w, hipEvent_t *e0, hipEvent_t *e1)
+{
+    const size_t k = 2 * (size_t)w->pev_used;
+    while (w->pev.size() < k + 2) {
+        hipEvent_t e = nullptr;
+        SPK_HIP(hipEventCreate(&e));
+        w->pev.push_back(e);
+    }
+    if (w->alive.size() < (size_t)w->pev_used + 1) w->alive.resize(w->pev_used + 1);
+    w->alive[w->pev_used] = 1;
+    *e0 = w->pev[k];
+    *e1 = w->pev[k + 1];
+    ++w->pev_used;
+    return SPK_OK;
+}
+
 template <class V>
 static int enqueue_iteration(spk_mat *A, Workspace *w, hipStream_t s)
 {
     const One b = batch_of(w);
     const dim3 g(A->nblk), t(kBlock), one(1);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (w->prof) {
+        SPK_TRY(prof_pair(w, &e0, &e1));
+        SPK_HIP(hipEventRecord(e0, s));
+    }
     if (A->kernel == SPK_KERNEL_STREAM) {
         hipLaunchKernelGGL((k_pcg_spmv_stream<V, One>), g, t, 0, s, b);
     } else if (A->kernel == SPK_KERNEL_SELL && w->wpart) {
@@ -217,9 +249,9 @@ static int enqueue_iteration(spk_mat *A, Workspace *w, hipStream_t s)
         SPK_TRY(launch_spmv<V>(A, val, p, q, s, w->st, Vecs<V>::gate));
         hipLaunchKernelGGL((k_pcg_pq<V, One>), g, t, 0, s, b);
     }
+    if (e1) SPK_HIP(hipEventRecord(e1, s));
     hipLaunchKernelGGL((k_pcg_update<V, One>), g, t, 0, s, b);
-    hipLaunchKernelGGL((k_fin_update<V, One>), one, t, 0, s, b);
-    hipLaunchKernelGGL((k_pcg_px<V, One>), g, t, 0, s, b, 0);
+    hipLaunchKernelGGL((k_pcg_px<V, One>), g, t, 0, s, b);
     SPK_HIP(hipGetLastError());
     return SPK_OK;
 }
@@ -233,7 +265,7 @@ static int enqueue_batch(spk_mat *A, Workspace *w, bool mixed, int K, hipStream_
         SPK_TRY(launch_resid(A, w, kResOuter, true, s));
         hipLaunchKernelGGL(k_setup32<One>, dim3(A->nblk), dim3(kBlock), 0, s, b);
         hipLaunchKernelGGL(k_fin_setup32<One>, dim3(1), dim3(kBlock), 0, s, b);
-        hipLaunchKernelGGL((k_pcg_px<float, One>), dim3(A->nblk), dim3(kBlock), 0, s, b, 1);
+        hipLaunchKernelGGL((k_pcg_p_continue<float, One>), dim3(A->nblk), dim3(kBlock), 0, s, b);
         for (int k = 0; k < K; ++k) SPK_TRY(enqueue_iteration<float>(A, w, s));
     } else {
         for (int k = 0; k < K; ++k) SPK_TRY(enqueue_iteration<double>(A, w, s));
@@ -303,6 +335,13 @@ static int run_batches(spk_mat *A, Workspace *w, bool mixed, int K, bool use_gra
         if (w->pstatus[2 * slot] != SPK_RUNNING) break;
     }
     SPK_HIP(hipStreamSynchronize(s));
+    if (w->prof) {
+        // one iteration per batch: the batches queued after the one that
+        // stopped the solve ran gated no-op products
+        const int dead = launched - checked;
+        for (int i = w->pev_used - dead; i < w->pev_used; ++i)
+            if (i >= 0) w->alive[i] = 0;
+    }
     return SPK_OK;
 }
 
@@ -333,8 +372,8 @@ static int solve64(spk_mat *A, Workspace *w, const spk_ksp_opts &o, bool x_given
                    int hist_len, hipStream_t s, SolveOut *out)
 {
     (void)x_given_residual;
-    const int K = o.graph_k > 0 ? o.graph_k : 8;
-    const bool use_graph = o.graph_k > 0;
+    const int K = w->prof ? 1 : o.graph_k > 0 ? o.graph_k : 8;
+    const bool use_graph = o.graph_k > 0 && !w->prof;
     hipLaunchKernelGGL(k_state_init, dim3(1), dim3(64), 0, s, w->st, o.rtol, o.atol, o.maxit, 0,
                        o.inner_rtol, o.inner_maxit, o.max_outer, hist_len);
     SPK_TRY(launch_resid(A, w, kResSetup, false, s));
@@ -387,8 +426,8 @@ static int solve64(spk_mat *A, Workspace *w, const spk_ksp_opts &o, bool x_given
 static int solve_mixed(spk_mat *A, Workspace *w, const spk_ksp_opts &o, int hist_len,
                        hipStream_t s, SolveOut *out, int *inner, int *outer)
 {
-    const int K = o.graph_k > 0 ? o.graph_k : 8;
-    const bool use_graph = o.graph_k > 0;
+    const int K = w->prof ? 1 : o.graph_k > 0 ? o.graph_k : 8;
+    const bool use_graph = o.graph_k > 0 && !w->prof;
     hipLaunchKernelGGL(k_state_init, dim3(1), dim3(64), 0, s, w->st, o.rtol, o.atol, o.maxit,
                        o.precision, inner_rtol_of(o), o.inner_maxit, o.max_outer, hist_len);
     SPK_HIP(hipGetLastError());
@@ -646,8 +685,9 @@ int spk_pc_chebyshev(const spk_mat *Ac, const double *b, double *x, double *r_ou
     }
     if (n == 0) return SPK_OK;
     hipStream_t s = (hipStream_t)stream;
+    A->stream = s;
     Workspace *w = nullptr;
-    SPK_TRY(get_workspace(A, false, &w));
+    SPK_TRY(get_workspace(A, false, &w, s));
     const double theta = 0.5 * (emax + emin), delta = 0.5 * (emax - emin), sigma = theta / delta;
     double *r = r_out ? r_out : w->r;
     double *dbuf[2] = {w->z, w->p};
@@ -720,6 +760,7 @@ int spk_ksp_solve(spk_mat *A, const double *b, double *x, const spk_ksp_opts *op
         return SPK_EZERODIAG;
     }
     hipStream_t s = (hipStream_t)stream;
+    A->stream = s;
     if (A->n == 0) {
         res->reason = SPK_CONVERGED_ATOL;
         res->seconds = spk_now() - t0;
@@ -730,9 +771,13 @@ int spk_ksp_solve(spk_mat *A, const double *b, double *x, const spk_ksp_opts *op
         set_error("single_reduction needs precision SPK_PREC_FP64");
         return SPK_EINVAL;
     }
+    if (o.profile && o.single_reduction) {
+        set_error("profile is not available with single_reduction");
+        return SPK_EINVAL;
+    }
     if (mixed) SPK_TRY(ensure_f32(A, s));
     Workspace *w = nullptr;
-    SPK_TRY(get_workspace(A, mixed, &w));
+    SPK_TRY(get_workspace(A, mixed, &w, s));
     if (o.hist_len > w->hist_cap) {
         // the history buffer is part of the descriptor baked into the graphs
         SPK_HIP(hipStreamSynchronize(s));
@@ -754,6 +799,8 @@ int spk_ksp_solve(spk_mat *A, const double *b, double *x, const spk_ksp_opts *op
 
     SolveOut out;
     int inner = 0, outer = 0, fallback = 0;
+    w->prof = o.profile != 0;
+    w->pev_used = 0;
     if (mixed) {
         SPK_TRY(solve_mixed(A, w, o, o.hist_len, s, &out, &inner, &outer));
         if (out.reason == SPK_DIVERGED_STAGNATION) {
@@ -778,6 +825,21 @@ int spk_ksp_solve(spk_mat *A, const double *b, double *x, const spk_ksp_opts *op
     if (o.hist_len > 0 && !fallback)
         SPK_HIP(hipMemcpyAsync(o.hist, w->hist, sizeof(double) * o.hist_len, hipMemcpyDeviceToHost, s));
     SPK_HIP(hipStreamSynchronize(s));
+    if (w->prof) {
+        // the product launches of the counted iterations, in launch order
+        int want = mixed && !fallback ? inner : out.iterations, got = 0;
+        double ms = 0.0;
+        for (int i = 0; i < w->pev_used && got < want; ++i) {
+            if (!w->alive[i]) continue;
+            float e = 0.f;
+            SPK_HIP(hipEventElapsedTime(&e, w->pev[2 * i], w->pev[2 * i + 1]));
+            ms += e;
+            ++got;
+        }
+        res->product_ms = ms;
+        res->product_launches = got;
+        w->prof = false;
+    }
     res->reason = out.reason;
     res->iterations = out.iterations;
     res->inner_iterations = inner;

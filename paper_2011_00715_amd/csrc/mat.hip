@@ -392,8 +392,8 @@ void update_info(spk_mat *A)
     const int64_t nn = A->n, nz = A->nnz;
     I.bytes_spmv_f64 = 12 * nz + 4 * (nn + 1) + 16 * nn;
     I.bytes_spmv_f32 = 8 * nz + 4 * (nn + 1) + 8 * nn;
-    I.bytes_pcg_iter_f64 = 12 * nz + 4 * (nn + 1) + 96 * nn;
-    I.bytes_pcg_iter_f32 = 8 * nz + 4 * (nn + 1) + 48 * nn;
+    I.bytes_pcg_iter_f64 = 12 * nz + 4 * (nn + 1) + 88 * nn;
+    I.bytes_pcg_iter_f32 = 8 * nz + 4 * (nn + 1) + 44 * nn;
     I.device_bytes = A->bytes + (A->ws ? A->ws->bytes : 0);
     I.zero_diag_rows = S.zero_diag;
     I.cached_loads = A->kernel == SPK_KERNEL_SELL ? A->sell_plain | A->sell_plain_spmv << 2 : 0;
@@ -874,6 +874,7 @@ int spk_mat_create_csr(int32_t n, int64_t nnz, const int32_t *rowptr, const int3
     }
     spk_mat *A = new (std::nothrow) spk_mat();
     if (!A) { set_error("out of host memory"); return SPK_ENOMEM; }
+    A->stream = (hipStream_t)stream;
     const int rc = create_impl(n, nnz, rowptr, colind, values, memtype, flags,
                                (hipStream_t)stream, A);
     if (rc) {
@@ -884,9 +885,15 @@ int spk_mat_create_csr(int32_t n, int64_t nnz, const int32_t *rowptr, const int3
     return SPK_OK;
 }
 
-int spk_mat_set_kernel(spk_mat *A, int kernel, int32_t param)
+int spk_mat_set_kernel(spk_mat *A, int kernel, int32_t param, void *stream)
 {
     if (!A) { set_error("A is NULL"); return SPK_EINVAL; }
+    hipStream_t s = (hipStream_t)stream;
+    // solver graphs and partials depend on the partition: release them after
+    // the handle's earlier work has finished
+    free_workspace(A);
+    free_multi(A);
+    A->stream = s;
     switch (kernel) {
     case SPK_KERNEL_AUTO: choose_kernel(A); break;
     case SPK_KERNEL_STREAM: {
@@ -920,12 +927,12 @@ int spk_mat_set_kernel(spk_mat *A, int kernel, int32_t param)
             set_error("SELL column width %d not in {0, 16, 32}", param);
             return SPK_EINVAL;
         }
-        const int rc = setup_sell(A, nullptr, param / 8);
+        const int rc = setup_sell(A, s, param / 8);
         if (rc) return rc;
         if (A->val32) {
-            const int r2 = ensure_f32(A, nullptr);
+            const int r2 = ensure_f32(A, s);
             if (r2) return r2;
-            SPK_HIP(hipStreamSynchronize(nullptr));
+            SPK_HIP(hipStreamSynchronize(s));
         }
         A->kernel = SPK_KERNEL_SELL;
         A->R = 256;
@@ -937,11 +944,11 @@ int spk_mat_set_kernel(spk_mat *A, int kernel, int32_t param)
             set_error("sliced parameter %d: 0, a power of two in [1, 64] or %d (merge path)", param, kMergeItems);
             return SPK_EINVAL;
         }
-        int rc = setup_sliced(A, nullptr);
+        int rc = setup_sliced(A, s);
         if (rc) return rc;
         const int merge = param == kMergeItems || (param == 0 && sliced_merge_fits(A));
         if (merge) {
-            rc = setup_sliced_merge(A, nullptr);
+            rc = setup_sliced_merge(A, s);
             if (rc) return rc;
         }
         A->kernel = SPK_KERNEL_SLICED;
@@ -955,37 +962,35 @@ int spk_mat_set_kernel(spk_mat *A, int kernel, int32_t param)
         return SPK_EINVAL;
     }
     if (A->kernel == SPK_KERNEL_MERGE) {
-        const int rc = setup_merge(A, nullptr);
+        const int rc = setup_merge(A, s);
         if (rc) return rc;
-        SPK_HIP(hipStreamSynchronize(nullptr));
+        SPK_HIP(hipStreamSynchronize(s));
     }
     if (kernel == SPK_KERNEL_AUTO && A->kernel == SPK_KERNEL_SLICED) {
-        if (setup_sliced(A, nullptr) != SPK_OK || (A->xs_merge && setup_sliced_merge(A, nullptr) != SPK_OK)) {
+        if (setup_sliced(A, s) != SPK_OK || (A->xs_merge && setup_sliced_merge(A, s) != SPK_OK)) {
             choose_kernel(A, true, false);
             if (A->kernel == SPK_KERNEL_MERGE) {
-                const int r2 = setup_merge(A, nullptr);
+                const int r2 = setup_merge(A, s);
                 if (r2) return r2;
-                SPK_HIP(hipStreamSynchronize(nullptr));
+                SPK_HIP(hipStreamSynchronize(s));
             }
         }
     }
     if (kernel == SPK_KERNEL_AUTO && A->kernel == SPK_KERNEL_SELL) {
-        int rc = setup_sell(A, nullptr, 0);
-        if (rc == SPK_OK && A->val32) rc = ensure_f32(A, nullptr);
-        if (rc == SPK_OK) rc = hipStreamSynchronize(nullptr) == hipSuccess ? SPK_OK : SPK_EHIP;
+        int rc = setup_sell(A, s, 0);
+        if (rc == SPK_OK && A->val32) rc = ensure_f32(A, s);
+        if (rc == SPK_OK) rc = hipStreamSynchronize(s) == hipSuccess ? SPK_OK : SPK_EHIP;
         if (rc) {
             free_sell(A);
             choose_kernel(A, false);
             if (A->kernel == SPK_KERNEL_MERGE) {
-                const int r2 = setup_merge(A, nullptr);
+                const int r2 = setup_merge(A, s);
                 if (r2) return r2;
-                SPK_HIP(hipStreamSynchronize(nullptr));
+                SPK_HIP(hipStreamSynchronize(s));
             }
         }
     }
     apply_partition(A);
-    free_workspace(A);  // graphs and partials depend on the partition
-    free_multi(A);
     update_info(A);
     return SPK_OK;
 }
@@ -994,6 +999,7 @@ int spk_mat_mult(const spk_mat *A, const double *x, double *y, void *stream)
 {
     if (!A || (A->n > 0 && (!x || !y))) { set_error("NULL argument"); return SPK_EINVAL; }
     if (x == y && A->n > 0) { set_error("x and y must not alias"); return SPK_EINVAL; }
+    A->stream = (hipStream_t)stream;
     return launch_spmv<double>(A, A->val, x, y, (hipStream_t)stream, nullptr, 0);
 }
 
@@ -1001,6 +1007,7 @@ int spk_mat_mult_f32(const spk_mat *A, const float *x, float *y, void *stream)
 {
     if (!A || (A->n > 0 && (!x || !y))) { set_error("NULL argument"); return SPK_EINVAL; }
     if (x == y && A->n > 0) { set_error("x and y must not alias"); return SPK_EINVAL; }
+    A->stream = (hipStream_t)stream;
     if (!A->val32 && A->n > 0) { set_error("matrix has no FP32 values (create with SPK_MAT_MIXED)"); return SPK_EINVAL; }
     return launch_spmv<float>(A, A->val32, x, y, (hipStream_t)stream, nullptr, 0);
 }
@@ -1021,6 +1028,7 @@ int spk_pc_jacobi_apply(const spk_mat *A, const double *r, double *z, void *stre
         set_error("%d rows have no stored or a zero diagonal", A->stats.zero_diag);
         return SPK_EZERODIAG;
     }
+    A->stream = (hipStream_t)stream;
     hipLaunchKernelGGL(k_pmul, dim3(grid_stream(A->n)), dim3(kBlock), 0, (hipStream_t)stream, A->n,
                        A->dinv, r, z);
     SPK_HIP(hipGetLastError());
@@ -1030,7 +1038,9 @@ int spk_pc_jacobi_apply(const spk_mat *A, const double *r, double *z, void *stre
 int spk_mat_destroy(spk_mat *A)
 {
     if (!A) return SPK_OK;
-    hipDeviceSynchronize();
+    // the handle's work is queued on the stream of its last call; HIP's
+    // hipFree below waits for the device as HIP documents
+    hipStreamSynchronize(A->stream);
     free_workspace(A);
     free_multi(A);
     if (A->own_csr) {

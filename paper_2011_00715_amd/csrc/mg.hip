@@ -76,6 +76,7 @@ struct spk_mg {
     const void *g_sell = nullptr;
     spk::MgTimer *timer = nullptr;  // set while a profiled cycle is enqueued
     int64_t bytes = 0;
+    hipStream_t stream = nullptr;   // stream of the latest call that queued work
 };
 
 namespace spk {
@@ -476,7 +477,7 @@ static int invert_coarsest(spk_mg *M, hipStream_t s)
 
 static void destroy_mg(spk_mg *M)
 {
-    hipDeviceSynchronize();
+    hipStreamSynchronize(M->stream);
     for (int l = 0; l < M->nlev; ++l) {
         MgLevel &L = M->lev[l];
         if (l > 0 || M->f32) {
@@ -876,6 +877,7 @@ int spk_mg_create(const spk_mat *Ac, int32_t dim, const int32_t *shape, const sp
     M->o = o;
     M->f32 = o.precision == SPK_PREC_MIXED ? 1 : 0;
     hipGetDevice(&M->device);
+    M->stream = (hipStream_t)stream;
     const int rc = setup(M, A, shape, (hipStream_t)stream);
     if (rc != SPK_OK) {
         destroy_mg(M);
@@ -909,12 +911,14 @@ int spk_mg_copy_level(const spk_mg *M, int32_t level, int32_t *rowptr, int32_t *
     if (!M || !rowptr || !col || !val) { set_error("NULL argument"); return SPK_EINVAL; }
     if (level < 0 || level >= M->nlev) { set_error("level %d outside [0, %d)", level, M->nlev); return SPK_EINVAL; }
     const spk_mat *A = M->lev[level].A;
-    SPK_HIP(hipDeviceSynchronize());
-    SPK_HIP(hipMemcpy(rowptr, A->rowptr, sizeof(int32_t) * ((size_t)A->n + 1), hipMemcpyDeviceToHost));
+    // after the hierarchy's queued work, on its own stream
+    hipStream_t s = M->stream;
+    SPK_HIP(hipMemcpyAsync(rowptr, A->rowptr, sizeof(int32_t) * ((size_t)A->n + 1), hipMemcpyDeviceToHost, s));
     if (A->nnz > 0) {
-        SPK_HIP(hipMemcpy(col, A->col, sizeof(int32_t) * (size_t)A->nnz, hipMemcpyDeviceToHost));
-        SPK_HIP(hipMemcpy(val, A->val, sizeof(double) * (size_t)A->nnz, hipMemcpyDeviceToHost));
+        SPK_HIP(hipMemcpyAsync(col, A->col, sizeof(int32_t) * (size_t)A->nnz, hipMemcpyDeviceToHost, s));
+        SPK_HIP(hipMemcpyAsync(val, A->val, sizeof(double) * (size_t)A->nnz, hipMemcpyDeviceToHost, s));
     }
+    SPK_HIP(hipStreamSynchronize(s));
     return SPK_OK;
 }
 
@@ -924,6 +928,7 @@ int spk_mg_apply(spk_mg *M, const double *b, double *x, void *stream)
     const int64_t n = M->lev[0].n;
     if (b < x + n && x < b + n) { set_error("b and x must not overlap"); return SPK_EINVAL; }
     const CycleIo io{b, x, nullptr, nullptr, nullptr};
+    M->stream = (hipStream_t)stream;
     return run_cycle(M, io, nullptr, (hipStream_t)stream);
 }
 
@@ -934,6 +939,7 @@ int spk_mg_profile(spk_mg *M, const double *b, double *x, int32_t reps, double *
     const int64_t n = M->lev[0].n;
     if (b < x + n && x < b + n) { set_error("b and x must not overlap"); return SPK_EINVAL; }
     hipStream_t s = (hipStream_t)stream;
+    M->stream = s;
     for (int l = 0; l < M->nlev; ++l) level_ms[l] = 0.0;
     MgLevel &L0 = M->lev[0];
     int rc = SPK_OK;
@@ -976,6 +982,7 @@ int spk_ksp_solve_mg(spk_mg *M, const double *b, double *x, const spk_ksp_opts *
     const int64_t n = M->lev[0].n;
     if (b < x + n && x < b + n) { set_error("b and x must not overlap"); return SPK_EINVAL; }
     memset(res, 0, sizeof(*res));
+    M->stream = (hipStream_t)stream;
     const int rc = solve(M, b, x, o, res, (hipStream_t)stream);
     res->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     return rc;

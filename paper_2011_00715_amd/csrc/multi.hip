@@ -28,6 +28,7 @@ void free_multi(spk_mat *A)
 {
     MultiWs *w = A->mws;
     if (!w) return;
+    hipStreamSynchronize(A->stream);
     if (w->g) hipGraphExecDestroy(w->g);
     for (auto &e : w->ev)
         if (e) hipEventDestroy(e);
@@ -228,6 +229,7 @@ int spk_mat_mult_multi(const spk_mat *A, int32_t k, const double *X, double *Y, 
     if (X < Y + nk && Y < X + nk) { set_error("X and Y must not overlap"); return SPK_EINVAL; }
     const MultiDesc d = multi_desc(A, k);
     hipStream_t s = (hipStream_t)stream;
+    A->stream = s;
     with_multi(A, k, [&](auto ct, auto kc) {
         using CI = decltype(ct);
         constexpr int K = decltype(kc)::value;
@@ -262,6 +264,7 @@ int spk_ksp_solve_multi(spk_mat *A, int32_t k, const double *B, double *X, const
         return SPK_EZERODIAG;
     }
     hipStream_t s = (hipStream_t)stream;
+    A->stream = s;
     MultiWs *w = nullptr;
     int rc = get_multi(A, k, &w);
     if (rc) return rc;

@@ -2,6 +2,7 @@
 #pragma once
 
 #include <mutex>
+#include <vector>
 
 #include "common.hpp"
 
@@ -54,6 +55,13 @@ struct Workspace {
     double *srp = nullptr;        // 2 sets x 3 partial arrays x nblk
     void *sc = nullptr;           // device scalars of the single-reduction recurrences
     int64_t bytes = 0;
+    // profiled solves: one event pair around each iteration's product, in
+    // launch order; `alive` is cleared for launches queued after the solve
+    // had stopped
+    bool prof = false;
+    std::vector<hipEvent_t> pev;
+    std::vector<char> alive;
+    int pev_used = 0;
 };
 
 }  // namespace spk
@@ -113,6 +121,9 @@ struct spk_mat {
     spk::Workspace *ws = nullptr;
     spk::MultiWs *mws = nullptr;  // multi-right-hand-side solver workspace
     int64_t bytes = 0;
+    // stream of the latest call that queued work on the handle: destroy and
+    // re-planning wait for it (and nothing else) before releasing buffers
+    mutable hipStream_t stream = nullptr;
 };
 
 namespace spk {

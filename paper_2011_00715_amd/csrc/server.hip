@@ -428,20 +428,18 @@ static int enqueue_step(spk_server *S)
         hipLaunchKernelGGL((k_fin_resid<kGateResid, Batch>), f, t, 0, S->s, b, (int)kResOuter);
         hipLaunchKernelGGL(k_setup32<Batch>, g, t, 0, S->s, b);
         hipLaunchKernelGGL(k_fin_setup32<Batch>, f, t, 0, S->s, b);
-        hipLaunchKernelGGL((k_pcg_px<float, Batch>), g, t, 0, S->s, b, 1);
+        hipLaunchKernelGGL((k_pcg_p_continue<float, Batch>), g, t, 0, S->s, b);
     }
     for (int k = 0; k < K; ++k) {
         if (S->n_fp64) {
             hipLaunchKernelGGL((k_pcg_spmv_stream<double, Batch>), g, t, 0, S->s, b);
             hipLaunchKernelGGL((k_pcg_update<double, Batch>), g, t, 0, S->s, b);
-            hipLaunchKernelGGL((k_fin_update<double, Batch>), f, t, 0, S->s, b);
-            hipLaunchKernelGGL((k_pcg_px<double, Batch>), g, t, 0, S->s, b, 0);
+            hipLaunchKernelGGL((k_pcg_px<double, Batch>), g, t, 0, S->s, b);
         }
         if (S->n_mixed) {
             hipLaunchKernelGGL((k_pcg_spmv_stream<float, Batch>), g, t, 0, S->s, b);
             hipLaunchKernelGGL((k_pcg_update<float, Batch>), g, t, 0, S->s, b);
-            hipLaunchKernelGGL((k_fin_update<float, Batch>), f, t, 0, S->s, b);
-            hipLaunchKernelGGL((k_pcg_px<float, Batch>), g, t, 0, S->s, b, 0);
+            hipLaunchKernelGGL((k_pcg_px<float, Batch>), g, t, 0, S->s, b);
         }
     }
     SPK_HIP(hipGetLastError());

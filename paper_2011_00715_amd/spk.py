@@ -62,6 +62,7 @@ class KspOpts(ctypes.Structure):
         ("x0_nonzero", i32), ("graph_k", i32), ("inner_rtol", dbl),
         ("inner_maxit", i32), ("max_outer", i32),
         ("hist", ctypes.POINTER(dbl)), ("hist_len", i32), ("single_reduction", i32),
+        ("profile", i32),
     ]
 
 
@@ -71,6 +72,7 @@ class KspResult(ctypes.Structure):
         ("outer_steps", i32), ("restarts", i32), ("fallback_fp64", i32),
         ("rnorm0", dbl), ("rnorm", dbl), ("bnorm", dbl),
         ("true_rel_residual", dbl), ("seconds", dbl),
+        ("product_ms", dbl), ("product_launches", i32), ("pad_", i32),
     ]
 
     def as_dict(self):
@@ -110,7 +112,7 @@ def _sig(name, res, args):
 
 _sig("spk_mat_create_csr", ctypes.c_int, [i32, i64, P, P, P, ctypes.c_int, u32, P,
                                           ctypes.POINTER(P)])
-_sig("spk_mat_set_kernel", ctypes.c_int, [P, ctypes.c_int, i32])
+_sig("spk_mat_set_kernel", ctypes.c_int, [P, ctypes.c_int, i32, P])
 _sig("spk_mat_mult", ctypes.c_int, [P, P, P, P])
 _sig("spk_mat_mult_f32", ctypes.c_int, [P, P, P, P])
 _sig("spk_mat_get_info", ctypes.c_int, [P, ctypes.POINTER(MatInfo)])
@@ -276,8 +278,8 @@ def mat_create_csr(rowptr, colind, values, flags: int = 0, stream=None) -> Mat:
     return Mat(out.value, keep)
 
 
-def mat_set_kernel(A: Mat, kernel: int, param: int = 0):
-    _check(_lib.spk_mat_set_kernel(A.handle, kernel, param), "spk_mat_set_kernel")
+def mat_set_kernel(A: Mat, kernel: int, param: int = 0, stream=None):
+    _check(_lib.spk_mat_set_kernel(A.handle, kernel, param, _stream(stream)), "spk_mat_set_kernel")
     A.info = mat_get_info(A)
 
 

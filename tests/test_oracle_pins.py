@@ -713,3 +713,26 @@ def test_pcg_sr_reasons(orc):
     Dm[np.arange(0, A.n, 2), np.arange(0, A.n, 2)] *= -1
     _, r, _ = oracle.pcg(spkgen.dense_to_csr(Dm), b, **SR)
     assert r["reason_str"] in ("DIVERGED_INDEFINITE_PC", "DIVERGED_INDEFINITE_MAT")
+
+
+def test_parallel_oracle_build_matches_serial():
+    """The OpenMP build (used only to time the oracle on all host cores) runs
+    the same loops: products bit-identical to the serial build, inner products
+    equal up to the long-double rounding of its fixed chunks, and the same
+    PCG iteration count and solution on the 64^2 Laplacian."""
+    import oracle
+
+    lo = oracle.load_omp()
+    A = spkgen.laplace3d7(40)
+    x = spkgen.rhs_uniform(A.n, 3)
+    assert np.array_equal(oracle.spmv(A, x), oracle.spmv(A, x, lib=lo))
+    y = spkgen.rhs_uniform(A.n, 4)
+    d0, d1 = oracle.dot(x, y), oracle.dot(x, y, lib=lo)
+    assert abs(d0 - d1) <= 1e-15 * float(np.abs(x) @ np.abs(y))
+    assert oracle.nrm2(x, lib=lo) == pytest.approx(oracle.nrm2(x), rel=1e-15)
+    B = spkgen.laplace2d5(64)
+    b = spkgen.rhs_uniform(B.n, 0)
+    xs, rs, _ = oracle.pcg(B, b)
+    xp, rp, _ = oracle.pcg(B, b, lib=lo)
+    assert rp["iterations"] == rs["iterations"] == 193
+    assert np.linalg.norm(xp - xs) <= 1e-12 * np.linalg.norm(xs)
