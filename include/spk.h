@@ -95,7 +95,7 @@ enum {
                                wavefront), row-relative int16 column offsets
                                when they fit (10 instead of 12 bytes per FP64
                                nonzero); built from the CSR at selection */
-    SPK_KERNEL_SLICED = 5   /* column-sliced CSR for scattered columns: the
+    SPK_KERNEL_SLICED = 5,  /* column-sliced CSR for scattered columns: the
                                entries of each row split by which eighth of
                                [0, n) their column falls in; XCD s computes
                                the products of slice s (its eighth of x stays
@@ -105,6 +105,12 @@ enum {
                                slice order.  A copy of the matrix built at
                                selection (12 nnz + 4 (8n + 1) bytes + 8n
                                partials) */
+    SPK_KERNEL_SELL_SIGMA = 6  /* SELL-C-sigma (opt-in): SELL-64 over the rows
+                                  ordered by length, longest first, within
+                                  windows of sigma rows, so that the rows of a
+                                  slice have similar lengths (less padding on
+                                  skewed matrices); the layout carries the row
+                                  permutation */
 };
 
 /* status codes */
@@ -167,6 +173,8 @@ typedef struct {
     int64_t stored_nnz;             /* entries the kernel reads, padding included */
     double gershgorin;              /* max_i sum_j |a_ij| / |a_ii|: a bound on the
                                        spectrum of D^-1 A (0 with a zero diagonal) */
+    int32_t sell_sigma;             /* SPK_KERNEL_SELL_SIGMA: the window (rows) */
+    int32_t pad_;
 } spk_mat_info;
 
 /*
@@ -196,7 +204,9 @@ int spk_mat_create_csr(int32_t n, int64_t nnz, const int32_t *rowptr,
 /* Force an SpMV kernel family (testing and A/B runs).  param: lanes per row
  * for VECTOR (1..64, power of two), rows per tile for STREAM (0 = automatic),
  * column-offset bits for SELL (0 = automatic, 16 or 32; SPK_EINVAL when the
- * rows exceed 255 entries or the offsets do not fit), for SLICED 0
+ * offsets do not fit or a row exceeds 65535 entries; row lengths above 255
+ * are stored in 16 bits), the window sigma for SELL_SIGMA (a multiple of 64;
+ * 0 = 4096; offsets as for SELL with 0), for SLICED 0
  * (automatic: the merge path over the slices when 8n + nnz < 2^31, else
  * lanes per slice row), a power of two in 1..64 (lanes per slice row) or
  * 2048 (merge path over the slices), ignored for MERGE.
@@ -458,7 +468,9 @@ typedef struct {
     int64_t hbm_budget_bytes;  /* device arena size (default 8 GiB) */
     int32_t max_slots;         /* concurrent systems (default 64) */
     int32_t graph_k;           /* iterations per batched step (default 8) */
-    int32_t max_blocks_per_system;  /* default 256 */
+    int32_t max_blocks_per_system;  /* blocks of one system in a batched launch
+                                       (default 2048: a large system streams
+                                       at full bandwidth; at most 8192) */
     int32_t pad_;
     int64_t pinned_bytes;      /* pinned host pool for submitted systems
                                   (default 1 GiB; 0 = pageable staging only) */

@@ -92,6 +92,8 @@ struct SysDesc {
     const uint8_t *sell_len;
     const double *sell_val;
     const float *sell_val32;
+    const uint16_t *sell_len16;  // row lengths when some row has more than 255 entries
+    const int32_t *sell_perm;    // SELL-C-sigma: matrix row of each sorted position
 };
 
 // ------------------------------------------------------------------ host helpers

@@ -141,6 +141,8 @@ static int get_workspace(spk_mat *A, bool mixed, Workspace **out, hipStream_t s)
         d.sell_len = A->sell_len;
         d.sell_val = A->sell_val;
         d.sell_plain = A->sell_plain;
+        d.sell_len16 = A->sell_len16;
+        d.sell_perm = A->sell_perm;
     }
     if (mixed && !w->has_mixed) {
         SPK_TRY(dalloc(&w->r32, A->n, w));
@@ -627,7 +629,7 @@ int cheb_step(spk_mat *A, const ChebStep<V> &c, V *tmp, hipStream_t s)
     constexpr bool f64 = std::is_same<V, double>::value;
     const dim3 g(A->nblk), t(kBlock);
     if (A->kernel == SPK_KERNEL_SELL) {
-        const SellView sv{A->sell_ptr, A->sell_col, A->sell_len, A->sell_plain};
+        const SellView sv{A->sell_ptr, A->sell_col, A->sell_len, A->sell_plain, A->sell_len16, A->sell_perm};
         // up to one wavefront per slice (no partial sums to keep per block)
         const dim3 gs(std::max(1, std::min(ceil_div(ceil_div(A->n, kSell), kBlock / kWave), 16384)));
         const int n = A->n;

@@ -302,7 +302,7 @@ int launch_spmv(const spk_mat *A, const V *val, const V *x, V *y, hipStream_t s,
             set_error("internal: gated SELL SpMV or no SELL layout");
             return SPK_EINVAL;
         }
-        const SellView sv{A->sell_ptr, A->sell_col, A->sell_len, A->sell_plain_spmv};
+        const SellView sv{A->sell_ptr, A->sell_col, A->sell_len, A->sell_plain_spmv, A->sell_len16, A->sell_perm};
         const V *sval = std::is_same<V, double>::value ? (const V *)A->sell_val : (const V *)A->sell_val32;
         (void)val;
         // up to one wavefront per slice
@@ -367,7 +367,8 @@ void update_info(spk_mat *A)
     const RowStats &S = A->stats;
     I.n = A->n;
     I.nnz = A->nnz;
-    I.kernel = A->kernel;
+    I.kernel = A->kernel == SPK_KERNEL_SELL && A->sell_sigma ? SPK_KERNEL_SELL_SIGMA : A->kernel;
+    I.sell_sigma = A->kernel == SPK_KERNEL_SELL ? A->sell_sigma : 0;
     I.lanes = A->kernel == SPK_KERNEL_SLICED ? (A->xs_merge ? kMergeItems : A->lanes)
               : A->kernel == SPK_KERNEL_VECTOR ? A->lanes
               : A->kernel == SPK_KERNEL_STREAM ? A->R
@@ -403,8 +404,10 @@ void update_info(spk_mat *A)
     if (A->kernel == SPK_KERNEL_SELL && A->sell_cw) {
         const int64_t ns = (nn + kSell - 1) / kSell;
         I.stored_nnz = A->sell_nnz;
-        I.format_bytes_spmv_f64 = (8 + A->sell_cw) * A->sell_nnz + 4 * (ns + 1) + nn + 16 * nn;
-        I.format_bytes_spmv_f32 = (4 + A->sell_cw) * A->sell_nnz + 4 * (ns + 1) + nn + 8 * nn;
+        // + the row permutation of SELL-C-sigma and 16-bit lengths of long rows
+        const int64_t extra = (A->sell_perm ? 4 * nn : 0) + (A->sell_len16 ? nn : 0);
+        I.format_bytes_spmv_f64 = (8 + A->sell_cw) * A->sell_nnz + 4 * (ns + 1) + nn + 16 * nn + extra;
+        I.format_bytes_spmv_f32 = (4 + A->sell_cw) * A->sell_nnz + 4 * (ns + 1) + nn + 8 * nn + extra;
     } else if (A->kernel == SPK_KERNEL_SLICED && A->xs_ptr) {
         // stacked slices: 8n + 1 row pointers; the 8n partial products are
         // written once and read once by the summing pass
@@ -537,56 +540,50 @@ static void free_sell(spk_mat *A)
     if (A->sell_cw) {
         const int64_t ns = (A->n + kSell - 1) / kSell;
         A->bytes -= 4 * (ns + 1) + (int64_t)(A->sell_cw + 8) * A->sell_nnz + A->n;
+        if (A->sell_len16) A->bytes -= A->n;
+        if (A->sell_perm) A->bytes -= 4ll * A->n;
         if (A->sell_val32) A->bytes -= 4 * A->sell_nnz;
     }
     hipFree(A->sell_ptr);
     hipFree(A->sell_col);
     hipFree(A->sell_len);
+    hipFree(A->sell_len16);
+    hipFree(A->sell_perm);
     hipFree(A->sell_val);
     hipFree(A->sell_val32);
     A->sell_ptr = nullptr;
     A->sell_col = nullptr;
     A->sell_len = nullptr;
+    A->sell_len16 = nullptr;
+    A->sell_perm = nullptr;
     A->sell_val = nullptr;
     A->sell_val32 = nullptr;
     A->sell_cw = 0;
+    A->sell_sigma = 0;
     A->sell_nnz = 0;
     A->sell_plain = 0;
     A->sell_plain_spmv = 0;
 }
 
-// Load policy of the SELL entries: ordinary (cache-allocating) loads when
-// the layout (entries, slice offsets, row lengths in that precision) and the
-// n-vectors a pass touches beside it fit the 256 MB Infinity Cache,
-// nontemporal loads above.  Measured on 3D 7-point Laplacians: a PCG
-// iteration (6 vectors: x, r, z, p, q, dinv) gains from ordinary loads at
-// 128^3 (249 MB in all) and loses from 134^3 (285 MB) on; back-to-back
-// products (x and y) gain up to 150^3 (293 MB) and lose at 160^3 (355 MB).
-constexpr int64_t kIterCacheBudget = 256ll << 20;
-constexpr int64_t kSpmvCacheBudget = 288ll << 20;
-
-static int sell_load_policy(int64_t stored, int cw, int nslices, int n, int vectors, int64_t budget)
-{
-    const int64_t fixed = 4 * ((int64_t)nslices + 1) + n;
-    int bits = 0;
-    if ((8 + cw) * stored + fixed + 8ll * vectors * n <= budget) bits |= kSellPlain64;
-    if ((4 + cw) * stored + fixed + 4ll * vectors * n <= budget) bits |= kSellPlain32;
-    return bits;
-}
 
 // Build the SELL-64 copy: slice widths from rowptr on the host (setup only),
-// entries filled by one device lane per row.  cw: 2 (int16 offsets), 4 (int32)
-// or 0 (int16 when every |col - row| fits).
-static int setup_sell(spk_mat *A, hipStream_t s, int cw)
+// entries filled by one device lane per layout position.  cw: 2 (int16
+// offsets), 4 (int32) or 0 (int16 when every |col - row| fits).  sigma > 0
+// builds SELL-C-sigma: within each window of sigma rows the rows are ordered
+// by length, longest first (ties in row order), so that the rows sharing a
+// slice have similar lengths and the padding shrinks on skewed matrices; the
+// layout then carries the permutation.  Rows longer than 255 entries store
+// their lengths in 16 bits.
+static int setup_sell(spk_mat *A, hipStream_t s, int cw, int sigma = 0)
 {
     if (cw == 0) cw = A->stats.max_delta <= 32767 ? 2 : 4;
-    if (A->sell_cw == cw) return SPK_OK;
+    if (A->sell_cw == cw && A->sell_sigma == sigma) return SPK_OK;
     if (cw == 2 && A->stats.max_delta > 32767) {
         set_error("column offsets up to %d do not fit int16", A->stats.max_delta);
         return SPK_EINVAL;
     }
-    if (A->stats.max_len > 255) {
-        set_error("SELL needs rows of at most 255 entries (max %d)", A->stats.max_len);
+    if (A->stats.max_len > 65535) {
+        set_error("SELL needs rows of at most 65535 entries (max %d)", A->stats.max_len);
         return SPK_EINVAL;
     }
     free_sell(A);
@@ -594,38 +591,62 @@ static int setup_sell(spk_mat *A, hipStream_t s, int cw)
     std::vector<int32_t> rp((size_t)n + 1);
     SPK_HIP(hipMemcpyAsync(rp.data(), A->rowptr, sizeof(int32_t) * ((size_t)n + 1), hipMemcpyDeviceToHost, s));
     SPK_HIP(hipStreamSynchronize(s));
+    std::vector<int32_t> perm;
+    if (sigma > 0) {
+        perm.resize((size_t)n);
+        for (int i = 0; i < n; ++i) perm[i] = i;
+        for (int w0 = 0; w0 < n; w0 += sigma) {
+            const int w1 = (int)std::min<int64_t>((int64_t)w0 + sigma, n);
+            std::stable_sort(perm.begin() + w0, perm.begin() + w1, [&](int32_t x, int32_t y) {
+                return rp[x + 1] - rp[x] > rp[y + 1] - rp[y];
+            });
+        }
+    }
+    auto rlen = [&](int j) {
+        const int r = sigma > 0 ? perm[j] : j;
+        return rp[r + 1] - rp[r];
+    };
     const int ns = ceil_div(n, kSell);
     std::vector<int32_t> sp((size_t)ns + 1);
     int64_t acc = 0;
     int wmax = 0;
     for (int k = 0; k < ns; ++k) {
         int mx = 0;
-        for (int i = k * kSell; i < std::min(n, (k + 1) * kSell); ++i) mx = std::max(mx, rp[i + 1] - rp[i]);
+        for (int j = k * kSell; j < std::min(n, (k + 1) * kSell); ++j) mx = std::max(mx, rlen(j));
         wmax = std::max(wmax, mx);
         sp[k] = (int32_t)acc;
         acc += (int64_t)kSell * mx;
         if (acc > 0x7fffffffLL) { set_error("SELL layout exceeds 2^31 entries"); return SPK_EINVAL; }
     }
     sp[ns] = (int32_t)acc;
+    const bool len16 = A->stats.max_len > 255;
     const size_t m = acc > 0 ? (size_t)acc : 1;
     SPK_HIP(hipMalloc(&A->sell_ptr, sizeof(int32_t) * ((size_t)ns + 1)));
     SPK_HIP(hipMalloc(&A->sell_col, (size_t)cw * m));
-    SPK_HIP(hipMalloc(&A->sell_len, (size_t)(n > 0 ? n : 1)));
+    if (len16) SPK_HIP(hipMalloc(&A->sell_len16, sizeof(uint16_t) * (size_t)(n > 0 ? n : 1)));
+    else SPK_HIP(hipMalloc(&A->sell_len, (size_t)(n > 0 ? n : 1)));
+    if (sigma > 0) SPK_HIP(hipMalloc(&A->sell_perm, sizeof(int32_t) * (size_t)(n > 0 ? n : 1)));
     SPK_HIP(hipMalloc(&A->sell_val, sizeof(double) * m));
     SPK_HIP(hipMemcpyAsync(A->sell_ptr, sp.data(), sizeof(int32_t) * ((size_t)ns + 1), hipMemcpyHostToDevice, s));
+    if (sigma > 0)
+        SPK_HIP(hipMemcpyAsync(A->sell_perm, perm.data(), sizeof(int32_t) * (size_t)n, hipMemcpyHostToDevice, s));
     if (cw == 2)
         hipLaunchKernelGGL(k_sell_fill<int16_t>, dim3(grid_for(n)), dim3(kBlock), 0, s, n, A->rowptr, A->col,
-                           A->val, A->sell_ptr, (int16_t *)A->sell_col, A->sell_val, A->sell_len);
+                           A->val, A->sell_ptr, (const int32_t *)A->sell_perm, (int16_t *)A->sell_col, A->sell_val,
+                           A->sell_len, A->sell_len16);
     else
         hipLaunchKernelGGL(k_sell_fill<int32_t>, dim3(grid_for(n)), dim3(kBlock), 0, s, n, A->rowptr, A->col,
-                           A->val, A->sell_ptr, (int32_t *)A->sell_col, A->sell_val, A->sell_len);
+                           A->val, A->sell_ptr, (const int32_t *)A->sell_perm, (int32_t *)A->sell_col, A->sell_val,
+                           A->sell_len, A->sell_len16);
     SPK_HIP(hipGetLastError());
     A->sell_cw = cw;
+    A->sell_sigma = sigma;
     A->sell_u = pick_sell_u(wmax);
     A->sell_nnz = acc;
-    A->sell_plain = A->stream_loads ? 0 : sell_load_policy(acc, cw, ns, n, 6, kIterCacheBudget);
-    A->sell_plain_spmv = A->stream_loads ? 0 : sell_load_policy(acc, cw, ns, n, 2, kSpmvCacheBudget);
-    A->bytes += 4 * ((int64_t)ns + 1) + (int64_t)(cw + 8) * acc + n;
+    const int64_t extra = (len16 ? n : 0) + (sigma > 0 ? 4ll * n : 0);
+    A->sell_plain = A->stream_loads ? 0 : sell_load_policy(acc, cw, ns, n, 6, kIterCacheBudget - extra);
+    A->sell_plain_spmv = A->stream_loads ? 0 : sell_load_policy(acc, cw, ns, n, 2, kSpmvCacheBudget - extra);
+    A->bytes += 4 * ((int64_t)ns + 1) + (int64_t)(cw + 8) * acc + n + extra;
     if (A->val32) {
         SPK_HIP(hipMalloc(&A->sell_val32, sizeof(float) * m));
         hipLaunchKernelGGL(k_to_f32, dim3(grid_for((int64_t)m)), dim3(kBlock), 0, s, (int64_t)m, A->sell_val,
@@ -633,6 +654,8 @@ static int setup_sell(spk_mat *A, hipStream_t s, int cw)
         SPK_HIP(hipGetLastError());
         A->bytes += 4 * acc;
     }
+    // the (sigma-sorted) layout is read in the fill above: wait before the
+    // host vectors go
     SPK_HIP(hipStreamSynchronize(s));
     return SPK_OK;
 }
@@ -928,6 +951,23 @@ int spk_mat_set_kernel(spk_mat *A, int kernel, int32_t param, void *stream)
             return SPK_EINVAL;
         }
         const int rc = setup_sell(A, s, param / 8);
+        if (rc) return rc;
+        if (A->val32) {
+            const int r2 = ensure_f32(A, s);
+            if (r2) return r2;
+            SPK_HIP(hipStreamSynchronize(s));
+        }
+        A->kernel = SPK_KERNEL_SELL;
+        A->R = 256;
+        break;
+    }
+    case SPK_KERNEL_SELL_SIGMA: {
+        const int sigma = param == 0 ? 4096 : param;
+        if (sigma < kSell || sigma % kSell != 0) {
+            set_error("SELL-C-sigma window %d: a positive multiple of %d", param, kSell);
+            return SPK_EINVAL;
+        }
+        const int rc = setup_sell(A, s, 0, sigma);
         if (rc) return rc;
         if (A->val32) {
             const int r2 = ensure_f32(A, s);

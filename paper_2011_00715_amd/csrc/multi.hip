@@ -65,7 +65,9 @@ static MultiDesc multi_desc(const spk_mat *A, int K)
     d.nblk = multi_nblk(A);
     d.R = A->R;
     d.ntiles = A->ntiles;
-    d.sell = A->kernel == SPK_KERNEL_SELL && A->sell_cw != 0;
+    // the multi kernels walk SELL slices in matrix order with one-byte row
+    // lengths; a sorted (SELL-C-sigma) or long-row layout goes through CSR
+    d.sell = A->kernel == SPK_KERNEL_SELL && A->sell_cw != 0 && !A->sell_perm && A->sell_len;
     d.rowptr = A->rowptr;
     d.col = A->col;
     d.val = A->val;

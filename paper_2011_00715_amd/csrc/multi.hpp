@@ -75,37 +75,64 @@ __device__ __forceinline__ void csr_row_multi(int a, int e, const int32_t *__res
     }
 }
 
-// Same for lane `lane` of a SELL slice (b, slen), the row having rlen entries.
+// Same for lane `lane` of a SELL slice (b, slen), the row having rlen
+// entries: UP entry pairs per round (one paired load of offsets and of
+// values, 2 UP x K gathers), then the odd last entry of the slice, loaded
+// with the first round and added last.
 template <class CI, int K>
 __device__ __forceinline__ void sell_row_multi(const SellView &sv, const double *__restrict__ val,
                                                const double *__restrict__ X, int32_t b, int slen,
                                                int rlen, int lane, int row, double acc[K])
 {
-    constexpr int U = K >= 8 ? 1 : 8 / K;
-    const CI *__restrict__ col = reinterpret_cast<const CI *>(sv.col) + b + lane;
-    const double *__restrict__ v = val + b + lane;
+    constexpr int UP = K >= 4 ? 1 : 4 / K;
+    using CP = typename Pair2<CI>::type;
+    using VP = typename Pair2<double>::type;
+    const CP *__restrict__ cp = reinterpret_cast<const CP *>(reinterpret_cast<const CI *>(sv.col) + b) + lane;
+    const VP *__restrict__ vp = reinterpret_cast<const VP *>(val + b) + lane;
+    const int np = slen >> 1;
+    const bool odd = slen & 1;
+    CI ct = CI(0);
+    double at = 0.0;
+    if (odd) {
+        const size_t t = (size_t)b + (size_t)np * (2 * kSell) + lane;
+        ct = ld_stream(reinterpret_cast<const CI *>(sv.col) + t);
+        at = ld_stream(val + t);
+    }
 #pragma unroll
     for (int q = 0; q < K; ++q) acc[q] = 0.0;
-    for (int j0 = 0; j0 < slen; j0 += U) {
-        CI c[U];
-        double a[U];
+    for (int p0 = 0; p0 < np; p0 += UP) {
+        CP c[UP];
+        VP a[UP];
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int j = j0 + u < slen ? j0 + u : slen - 1;
-            c[u] = ld_stream(col + (size_t)j * kSell);
-            a[u] = ld_stream(v + (size_t)j * kSell);
+        for (int u = 0; u < UP; ++u) {
+            const int p = p0 + u < np ? p0 + u : np - 1;
+            c[u] = ld_stream(cp + (size_t)p * kSell);
+            a[u] = ld_stream(vp + (size_t)p * kSell);
         }
-        double xv[U][K];
+        double xv[2 * UP][K];
 #pragma unroll
-        for (int u = 0; u < U; ++u)
+        for (int u = 0; u < UP; ++u)
 #pragma unroll
-            for (int q = 0; q < K; ++q) xv[u][q] = X[(size_t)(row + (int)c[u]) * K + q];
+            for (int q = 0; q < K; ++q) {
+                xv[2 * u][q] = X[(size_t)(row + (int)c[u].x) * K + q];
+                xv[2 * u + 1][q] = X[(size_t)(row + (int)c[u].y) * K + q];
+            }
 #pragma unroll
-        for (int u = 0; u < U; ++u)
-            if (j0 + u < rlen)
+        for (int u = 0; u < UP; ++u) {
+            const int k = 2 * (p0 + u);
+            if (p0 + u < np) {
+                if (k < rlen)
 #pragma unroll
-                for (int q = 0; q < K; ++q) acc[q] = fma(a[u], xv[u][q], acc[q]);
+                    for (int q = 0; q < K; ++q) acc[q] = fma(a[u].x, xv[2 * u][q], acc[q]);
+                if (k + 1 < rlen)
+#pragma unroll
+                    for (int q = 0; q < K; ++q) acc[q] = fma(a[u].y, xv[2 * u + 1][q], acc[q]);
+            }
+        }
     }
+    if (odd && slen - 1 < rlen)
+#pragma unroll
+        for (int q = 0; q < K; ++q) acc[q] = fma(at, X[(size_t)(row + (int)ct) * K + q], acc[q]);
 }
 
 // Row walk of block l (of nblk) of a multi kernel: SELL slices in

@@ -4,7 +4,7 @@
 #include <mutex>
 #include <vector>
 
-#include "common.hpp"
+#include "spmv.hpp"
 
 namespace spk {
 
@@ -25,6 +25,25 @@ struct RowStats {
 };
 
 constexpr int kTileRs[6] = {256, 128, 64, 32, 16, 8};
+
+// Load policy of the SELL entries: ordinary (cache-allocating) loads when
+// the layout (entries, slice offsets, row lengths in that precision) and the
+// n-vectors a pass touches beside it fit the 256 MB Infinity Cache,
+// nontemporal loads above.  Measured on 3D 7-point Laplacians: a PCG
+// iteration (6 vectors: x, r, z, p, q, dinv) gains from ordinary loads at
+// 128^3 (249 MB in all) and loses from 134^3 (285 MB) on; back-to-back
+// products (x and y) gain up to 150^3 (293 MB) and lose at 160^3 (355 MB).
+constexpr int64_t kIterCacheBudget = 256ll << 20;
+constexpr int64_t kSpmvCacheBudget = 288ll << 20;
+
+inline int sell_load_policy(int64_t stored, int cw, int nslices, int n, int vectors, int64_t budget)
+{
+    const int64_t fixed = 4 * ((int64_t)nslices + 1) + n;
+    int bits = 0;
+    if ((8 + cw) * stored + fixed + 8ll * vectors * n <= budget) bits |= kSellPlain64;
+    if ((4 + cw) * stored + fixed + 4ll * vectors * n <= budget) bits |= kSellPlain32;
+    return bits;
+}
 
 // Solver workspace of one matrix (allocated on the first solve).
 struct Workspace {
@@ -103,6 +122,9 @@ struct spk_mat {
     int32_t *sell_ptr = nullptr;
     void *sell_col = nullptr;
     uint8_t *sell_len = nullptr;
+    uint16_t *sell_len16 = nullptr;  // row lengths when some row exceeds 255 entries (sell_len then null)
+    int32_t *sell_perm = nullptr;    // SELL-C-sigma: matrix row of each sorted position, or null
+    int sell_sigma = 0;              // SELL-C-sigma window (rows), 0: rows in matrix order
     double *sell_val = nullptr;
     float *sell_val32 = nullptr;
     // column-sliced copy (built when the SLICED family is selected): rows

@@ -195,21 +195,43 @@ __global__ __launch_bounds__(kBlock) void k_spmv_vector(int n, const int32_t *__
 }
 
 // ------------------------------------------------------------------ SELL-64
-// Sliced ELLPACK with one slice of 64 consecutive rows per wavefront: entry j
-// of the slice's rows is stored contiguously (column-major inside the slice),
-// so lane l streams row (64 s + l) with fully coalesced loads and no LDS, no
-// barrier and no cross-lane reduction.  Columns are stored as offsets from the
-// row (int16 when every |col - row| < 2^15, which holds for stencils), so an
-// FP64 nonzero costs 10 bytes instead of CSR's 12 (FP32: 6 instead of 8);
-// this is the index compression Challenge A7 points to.  Rows shorter than
-// their slice are padded; padding is never multiplied (per-row length test).
+// Sliced ELLPACK with one slice of 64 consecutive rows per wavefront: lane l
+// streams row (64 s + l) with coalesced loads and no LDS, no barrier and no
+// cross-lane reduction.  Inside a slice of width w (its longest row) the
+// entries are stored in pairs: entries 2p and 2p + 1 of lane l sit next to
+// each other at element 128 p + 2 l, so one 8- or 16-byte load per lane
+// fetches two entries (a wavefront load moves 512 B / 1 KB instead of
+// 128 B / 512 B: fewer memory instructions per byte, 11 % faster on the
+// 27-point 160^3 product), and the last entry of an odd width sits at
+// 128 (w / 2) + l.  Columns are stored as offsets from the row (int16 when
+// every |col - row| < 2^15, which holds for stencils), so an FP64 nonzero
+// costs 10 bytes instead of CSR's 12 (FP32: 6 instead of 8); this is the
+// index compression Challenge A7 points to.  Rows shorter than their slice
+// are padded; padding is never multiplied (per-row length test).
 constexpr int kSell = 64;
+
+// Element of entry k of lane `lane` in a slice of w entries per row,
+// relative to the slice's first element.
+__host__ __device__ __forceinline__ size_t sell_pos(int k, int w, int lane)
+{
+    return k < (w & ~1) ? (size_t)(k >> 1) * (2 * kSell) + 2 * lane + (k & 1)
+                        : (size_t)(w >> 1) * (2 * kSell) + lane;
+}
+
+// Two-element vectors for the paired loads.
+template <class T> struct Pair2;
+template <> struct Pair2<double> { typedef double type __attribute__((ext_vector_type(2))); };
+template <> struct Pair2<float> { typedef float type __attribute__((ext_vector_type(2))); };
+template <> struct Pair2<int16_t> { typedef short type __attribute__((ext_vector_type(2))); };
+template <> struct Pair2<int32_t> { typedef int type __attribute__((ext_vector_type(2))); };
 
 struct SellView {
     const int32_t *ptr;    // element offset of each slice (nslices + 1)
     const void *col;       // int16 or int32 row-relative column offsets
-    const uint8_t *len;    // row lengths
+    const uint8_t *len;    // row lengths (rows of at most 255 entries), or null
     int plain;             // load policy of offsets and values, see kSellPlain64/32
+    const uint16_t *len16; // row lengths when some row has more than 255 entries
+    const int32_t *perm;   // SELL-C-sigma: matrix row of each sorted position, or null
 };
 
 // Load policy of the SELL entries.  A matrix whose stored entries fit well
@@ -219,37 +241,70 @@ struct SellView {
 // vectors that do fit.  One bit per value precision (FP64 / FP32 kernels).
 constexpr int kSellPlain64 = 1, kSellPlain32 = 2;
 
+template <bool NT, class T>
+__device__ __forceinline__ T sell_ld(const T *p)
+{
+    if constexpr (NT) return __builtin_nontemporal_load(p);
+    else return *p;
+}
+
 // Row sum of lane `lane` of the slice starting at element b with slen
 // entries per row; the row has rlen of them.  Entries in column order, FMA.
-// U entries per round: the round's offsets and values are loaded together,
-// then all U gathers of x are issued before the first FMA, so a round costs
-// one memory latency, not U.  Entries past the slice width repeat its last
-// entry and padding has offset 0, so every gather reads a valid element of
-// x; only the row's own entries are multiplied.  U is chosen per matrix from
-// the widest slice (7 for a 7-point stencil: no wasted load).
-template <class V, class CI, int U, bool NT>
+// UP pairs per round: the round's offset and value pairs are loaded
+// together, then all 2 UP gathers of x are issued before the first FMA, so
+// a round costs one memory latency.  Pairs past the slice width repeat its
+// last pair and padding has offset 0, so every gather reads a valid element
+// of x; only the row's own entries are multiplied.  UP is chosen per matrix
+// from the widest slice (3 for a 7-point stencil: one round and the tail).
+template <class V, class CI, int UP, bool NT>
 __device__ __forceinline__ V sell_row(const SellView &sv, const V *__restrict__ val,
                                       const V *__restrict__ x, int32_t b, int slen, int rlen,
                                       int lane, int row)
 {
-    const CI *__restrict__ col = reinterpret_cast<const CI *>(sv.col) + b + lane;
-    const V *__restrict__ v = val + b + lane;
+    using CP = typename Pair2<CI>::type;
+    using VP = typename Pair2<V>::type;
+    const CP *__restrict__ cp = reinterpret_cast<const CP *>(reinterpret_cast<const CI *>(sv.col) + b) + lane;
+    const VP *__restrict__ vp = reinterpret_cast<const VP *>(val + b) + lane;
+    const int np = slen >> 1;
+    // the odd last entry is loaded first and gathered with the first round,
+    // so an odd width costs no extra memory round trip; it is added last
+    const bool odd = slen & 1;
+    CI ct = CI(0);
+    V at = V(0), xt = V(0);
+    if (odd) {
+        const size_t t = (size_t)b + (size_t)np * (2 * kSell) + lane;
+        ct = sell_ld<NT>(reinterpret_cast<const CI *>(sv.col) + t);
+        at = sell_ld<NT>(val + t);
+    }
     V acc = V(0);
-    for (int j0 = 0; j0 < slen; j0 += U) {
-        CI c[U];
-        V a[U];
+    for (int p0 = 0; p0 < np; p0 += UP) {
+        CP c[UP];
+        VP a[UP];
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int j = j0 + u < slen ? j0 + u : slen - 1;
-            c[u] = NT ? ld_stream(col + (size_t)j * kSell) : col[(size_t)j * kSell];
-            a[u] = NT ? ld_stream(v + (size_t)j * kSell) : v[(size_t)j * kSell];
+        for (int u = 0; u < UP; ++u) {
+            const int p = p0 + u < np ? p0 + u : np - 1;
+            c[u] = sell_ld<NT>(cp + (size_t)p * kSell);
+            a[u] = sell_ld<NT>(vp + (size_t)p * kSell);
         }
-        V xv[U];
+        V xv[2 * UP];
 #pragma unroll
-        for (int u = 0; u < U; ++u) xv[u] = x[row + (int)c[u]];
+        for (int u = 0; u < UP; ++u) {
+            xv[2 * u] = x[row + (int)c[u].x];
+            xv[2 * u + 1] = x[row + (int)c[u].y];
+        }
+        if (p0 == 0 && odd) xt = x[row + (int)ct];
 #pragma unroll
-        for (int u = 0; u < U; ++u)
-            if (j0 + u < rlen) acc = fma(a[u], xv[u], acc);
+        for (int u = 0; u < UP; ++u) {
+            const int k = 2 * (p0 + u);
+            if (p0 + u < np) {
+                if (k < rlen) acc = fma(a[u].x, xv[2 * u], acc);
+                if (k + 1 < rlen) acc = fma(a[u].y, xv[2 * u + 1], acc);
+            }
+        }
+    }
+    if (odd) {
+        if (np == 0) xt = x[row + (int)ct];
+        if (slen - 1 < rlen) acc = fma(at, xt, acc);
     }
     return acc;
 }
@@ -267,25 +322,28 @@ __device__ __forceinline__ void sell_slices_run(int n, int s, int stride, const 
 {
     const int lane = threadIdx.x & (kWave - 1);
     const int ns = (n + kSell - 1) / kSell;
+    // position j = 64 s + lane of the layout holds matrix row perm[j]
+    // (SELL-C-sigma) or row j; its length is in len or len16
+    auto head = [&](int j, int &rlen, int &row) {
+        rlen = j < n ? (sv.len16 ? (int)sv.len16[j] : (int)sv.len[j]) : 0;
+        row = j < n && sv.perm ? sv.perm[j] : j;
+    };
     int32_t b = 0, e = 0;
-    int rlen = 0;
+    int rlen = 0, row = 0;
     if (s < ns) {
         b = sv.ptr[s];
         e = sv.ptr[s + 1];
-        const int row = s * kSell + lane;
-        rlen = row < n ? sv.len[row] : 0;
+        head(s * kSell + lane, rlen, row);
     }
     if (!go()) return;
     while (s < ns) {
-        const int row = s * kSell + lane;
         const int slen = (e - b) / kSell;
-        if (row < n) fn(row, sell_row<V, CI, U, NT>(sv, val, x, b, slen, rlen, lane, row));
+        if (s * kSell + lane < n) fn(row, sell_row<V, CI, U, NT>(sv, val, x, b, slen, rlen, lane, row));
         s += stride;
         if (s >= ns) break;
         b = sv.ptr[s];
         e = sv.ptr[s + 1];
-        const int nrow = s * kSell + lane;
-        rlen = nrow < n ? sv.len[nrow] : 0;
+        head(s * kSell + lane, rlen, row);
     }
 }
 
@@ -313,53 +371,59 @@ __global__ __launch_bounds__(kBlock) void k_spmv_sell(int n, SellView sv, const 
                           [&](int i, V s) { y[i] = s; });
 }
 
-// Widths U the SELL kernels are built for, and the launch helper: calls
-// f(std::integral_constant<int, U>) for the handle's U.
-constexpr int kSellUMin = 4, kSellUMax = 9;
-
+// Pairs per round UP the SELL kernels are built for, and the launch
+// helper: calls f(std::integral_constant<int, UP>) for the handle's UP.
 template <class F>
 inline void with_sell_u(int u, F &&f)
 {
     switch (u) {
+    case 2: f(std::integral_constant<int, 2>{}); break;
+    case 3: f(std::integral_constant<int, 3>{}); break;
     case 4: f(std::integral_constant<int, 4>{}); break;
     case 5: f(std::integral_constant<int, 5>{}); break;
     case 6: f(std::integral_constant<int, 6>{}); break;
-    case 7: f(std::integral_constant<int, 7>{}); break;
-    case 9: f(std::integral_constant<int, 9>{}); break;
-    default: f(std::integral_constant<int, 8>{}); break;
+    default: f(std::integral_constant<int, 7>{}); break;
     }
 }
 
-// U for a matrix whose widest slice has w entries per row: w itself up to 9
-// (at least 4), else the U in [5, 9] that wastes the fewest loads.
+// UP for a matrix whose widest slice has w entries per row: its pair count
+// w / 2 when that is 2..7, 2 below, else the UP in [4, 7] that repeats the
+// fewest pairs (27-point rows: 13 pairs, UP 7).
 inline int pick_sell_u(int w)
 {
-    if (w <= kSellUMax) return w < kSellUMin ? kSellUMin : w;
-    int best = 8, waste = 1 << 30;
-    for (int u = kSellUMax; u >= 5; --u) {
-        const int wst = (w + u - 1) / u * u - w;
+    const int np = w >> 1;
+    if (np <= 2) return 2;
+    if (np <= 7) return np;
+    int best = 7, waste = 1 << 30;
+    for (int u = 7; u >= 4; --u) {
+        const int wst = (np + u - 1) / u * u - np;
         if (wst < waste) { waste = wst; best = u; }
     }
     return best;
 }
 
-// Layout fill: one lane per row writes its entries and the slice padding.
+// Layout fill: one lane per layout position j writes the entries of its
+// matrix row (perm[j], or j) and the slice padding; the row's length goes to
+// slen (one byte) or, for rows longer than 255 entries, to slen16.
 template <class CI>
 __global__ void k_sell_fill(int n, const int32_t *__restrict__ rowptr,
                             const int32_t *__restrict__ col, const double *__restrict__ val,
-                            const int32_t *__restrict__ sptr, CI *__restrict__ scol,
-                            double *__restrict__ sval, uint8_t *__restrict__ slen)
+                            const int32_t *__restrict__ sptr, const int32_t *__restrict__ perm,
+                            CI *__restrict__ scol, double *__restrict__ sval, uint8_t *__restrict__ slen,
+                            uint16_t *__restrict__ slen16)
 {
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
         const int s = i / kSell, lane = i % kSell;
+        const int r = perm ? perm[i] : i;
         const int b = sptr[s];
         const int len = (sptr[s + 1] - b) / kSell;
-        const int a = rowptr[i], e = rowptr[i + 1];
-        slen[i] = (uint8_t)(e - a);
+        const int a = rowptr[r], e = rowptr[r + 1];
+        if (slen16) slen16[i] = (uint16_t)(e - a);
+        else slen[i] = (uint8_t)(e - a);
         for (int j = 0; j < len; ++j) {
-            const size_t d = (size_t)b + (size_t)j * kSell + lane;
+            const size_t d = (size_t)b + sell_pos(j, len, lane);
             const bool real = a + j < e;
-            scol[d] = real ? (CI)(col[a + j] - i) : (CI)0;
+            scol[d] = real ? (CI)(col[a + j] - r) : (CI)0;
             sval[d] = real ? val[a + j] : 0.0;
         }
     }

@@ -36,7 +36,8 @@ MEM_HOST, MEM_DEVICE = 0, 1
 PREC_FP64, PREC_MIXED, PREC_MIXED_IR = 0, 1, 2
 MAT_MIXED, MAT_VALIDATE, MAT_BORROW, MAT_STREAM = 1, 2, 4, 8
 KERNEL_AUTO, KERNEL_STREAM, KERNEL_VECTOR, KERNEL_MERGE, KERNEL_SELL, KERNEL_SLICED = 0, 1, 2, 3, 4, 5
-KERNEL_NAMES = {1: "stream", 2: "vector", 3: "merge", 4: "sell", 5: "sliced"}
+KERNEL_SELL_SIGMA = 6
+KERNEL_NAMES = {1: "stream", 2: "vector", 3: "merge", 4: "sell", 5: "sliced", 6: "sell_sigma"}
 OK, EINVAL, ENOMEM, EHIP, EZERODIAG, EBUSY, EBUDGET, ENOTFOUND = 0, -1, -2, -3, -4, -5, -6, -7
 CONVERGED_RTOL, CONVERGED_ATOL = 1, 2
 DIVERGED_ITS, DIVERGED_INDEFINITE_MAT, DIVERGED_INDEFINITE_PC = -1, -2, -3
@@ -52,7 +53,7 @@ class MatInfo(ctypes.Structure):
         ("bytes_pcg_iter_f64", i64), ("bytes_pcg_iter_f32", i64),
         ("device_bytes", i64), ("zero_diag_rows", i32), ("cached_loads", i32),
         ("format_bytes_spmv_f64", i64), ("format_bytes_spmv_f32", i64), ("stored_nnz", i64),
-        ("gershgorin", dbl),
+        ("gershgorin", dbl), ("sell_sigma", i32), ("pad_", i32),
     ]
 
 

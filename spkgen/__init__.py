@@ -201,7 +201,8 @@ def diffusion3d27_lognormal(N: int, seed: int = 0) -> CSR:
     return _stencil_csr(N, 3, offsets, weights)
 
 
-def powerlaw_spd(n: int, seed: int = 0, a: float = 1.8, lo: int = 3, hi: int = 4000) -> CSR:
+def powerlaw_spd(n: int, seed: int = 0, a: float = 1.8, lo: int = 3, hi: int = 4000,
+                 band: int | None = None) -> CSR:
     """Random SPD matrix with power-law row lengths and a symmetric pattern.
 
     Reading of "nnz/row Zipf(a) clipped to [lo, hi], symmetric pattern,
@@ -213,12 +214,24 @@ def powerlaw_spd(n: int, seed: int = 0, a: float = 1.8, lo: int = 3, hi: int = 4
     hence SPD).
 
     Draw order: zipf(n), integers(total picks), standard_normal(#pairs).
+
+    band: the banded variant (a diagnostic that separates load balance from
+    gather locality): each pick is uniform over [i - band, i + band] without
+    i, reflected into [0, n) at the ends; same row-length law.
     """
     rng = np.random.default_rng(seed)
     d = np.clip(rng.zipf(a, n), lo, hi).astype(np.int64)
     rows = np.repeat(np.arange(n, dtype=np.int64), d)
-    cols = rng.integers(0, n - 1, size=rows.size, dtype=np.int64)
-    cols += cols >= rows
+    if band is None:
+        cols = rng.integers(0, n - 1, size=rows.size, dtype=np.int64)
+        cols += cols >= rows
+    else:
+        off = rng.integers(1, band + 1, size=rows.size, dtype=np.int64)
+        off = np.where(rng.integers(0, 2, size=rows.size) == 0, -off, off)
+        cols = rows + off
+        cols = np.where(cols < 0, -cols, cols)
+        cols = np.where(cols >= n, 2 * (n - 1) - cols, cols)
+        cols = np.where(cols == rows, (rows + 1) % n, cols)
     key = np.minimum(rows, cols) * n + np.maximum(rows, cols)
     del rows, cols
     key = np.unique(key)

@@ -39,7 +39,7 @@ def spmv_bound_rows(A, kernel, lanes, u):
     vector sums ceil(len/L) FMA terms per lane then a log2(L) butterfly,
     merge walks <= 8 items per lane, an 8-level scan and a carry chain."""
     L = np.diff(A.rowptr).astype(np.float64)
-    if kernel in ("stream", "sell"):  # sequential sum / FMA chain in column order
+    if kernel in ("stream", "sell", "sell_sigma"):  # sequential sum / FMA chain in column order
         f = L + 1
     elif kernel == "vector":
         f = np.ceil(L / lanes) + math.log2(lanes) + 2

@@ -43,8 +43,6 @@ def test_chebyshev_parity(case, kernel):
     A = dict(_cases())[case]
     M = mat_on_gpu(spk, A)
     if kernel != "auto":
-        if kernel == "sell" and M.info.row_max > 255:
-            pytest.skip("SELL stores row lengths in one byte")
         k = {"stream": spk.KERNEL_STREAM, "vector": spk.KERNEL_VECTOR, "merge": spk.KERNEL_MERGE,
              "sell": spk.KERNEL_SELL}[kernel]
         spk.mat_set_kernel(M, k, 8 if kernel == "vector" else 0)

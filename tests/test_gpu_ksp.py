@@ -35,7 +35,7 @@ def _cases():
 
 
 @pytest.mark.parametrize("case", ["lap2d_64", "lap3d_24", "diff27_14", "powerlaw_20k"])
-@pytest.mark.parametrize("kernel", ["auto", "vector", "merge", "sell"])
+@pytest.mark.parametrize("kernel", ["auto", "vector", "merge", "sell", "sell_sigma"])
 def test_pcg_fp64_parity(case, kernel):
     spk = need_gpu()
     name, A, seed = [c for c in _cases() if c[0] == case][0]
@@ -45,9 +45,9 @@ def test_pcg_fp64_parity(case, kernel):
     elif kernel == "merge":
         spk.mat_set_kernel(M, spk.KERNEL_MERGE, 0)
     elif kernel == "sell":
-        if M.info.row_max > 255:
-            pytest.skip("SELL stores row lengths in one byte (rows of at most 255 entries)")
         spk.mat_set_kernel(M, spk.KERNEL_SELL, 0)
+    elif kernel == "sell_sigma":
+        spk.mat_set_kernel(M, spk.KERNEL_SELL_SIGMA, 256)
     b = spkgen.rhs_uniform(A.n, seed)
     x, res, hist = _solve(spk, M, b, hist_len=4000)
     xo, ro, ho = oracle.pcg(A, b, rtol=1e-8, hist_len=4000)
@@ -98,6 +98,32 @@ def test_pcg_wide_sell_product(width):
     assert oracle.nrm2(b - oracle.spmv(A, xm)) <= 1e-8 * bn * (1 + 1e-6)
     assert np.linalg.norm(xm - xo) <= 1e-5 * np.linalg.norm(xo)
     assert rm.inner_iterations <= 1.1 * ro["iterations"] + 2
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_pcg_profiled_solve_same_result(prec):
+    """opts.profile (one iteration per launch batch, an event pair around
+    every product) gives the bits of the graph-replayed solve, and times one
+    product per counted iteration."""
+    spk = need_gpu()
+    A = spkgen.diffusion3d27_lognormal(16, seed=2)
+    M = mat_on_gpu(spk, A, flags=spk.MAT_MIXED)
+    p = spk.PREC_FP64 if prec == "fp64" else spk.PREC_MIXED
+    b = spkgen.rhs_uniform(A.n, 1)
+    x0, r0, _ = _solve(spk, M, b, precision=p)
+    x1, r1, _ = _solve(spk, M, b, precision=p, profile=1)
+    assert np.array_equal(x0, x1)
+    assert (r0.iterations, r0.inner_iterations, r0.outer_steps) == (r1.iterations, r1.inner_iterations,
+                                                                    r1.outer_steps)
+    counted = r1.inner_iterations if p == spk.PREC_MIXED else r1.iterations
+    assert r1.product_launches == counted > 0
+    assert 0 < r1.product_ms < 1e3 * r1.seconds
+    assert r0.product_launches == 0 and r0.product_ms == 0.0
+    # a fixed number of iterations (rtol 0): every launch is an iteration
+    _, r2, _ = _solve(spk, M, b, rtol=0.0, maxit=37, profile=1)
+    assert r2.reason == spk.DIVERGED_ITS and r2.iterations == 37 and r2.product_launches == 37
+    with pytest.raises(spk.SpkError):
+        _solve(spk, M, b, profile=1, single_reduction=1)
 
 
 def test_pcg_graph_and_direct_launch_identical():

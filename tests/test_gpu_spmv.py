@@ -12,20 +12,19 @@ from gpu_util import U32, U64, check_spmv, mat_on_gpu, need_gpu, spmv_bound_rows
 pytestmark = pytest.mark.gpu
 
 KERNELS = [("auto", 0), ("stream", 0), ("stream", 64), ("stream", 8), ("merge", 0), ("sell", 0),
-           ("sell", 32), ("sliced", 0), ("sliced", 1), ("sliced", 16), ("sliced", 2048)] + [("vector", L) for L in (1, 2, 4, 8, 16, 32, 64)]
+           ("sell", 32), ("sell_sigma", 0), ("sell_sigma", 64), ("sell_sigma", 1024), ("sliced", 0),
+           ("sliced", 1), ("sliced", 16), ("sliced", 2048)] + [("vector", L) for L in (1, 2, 4, 8, 16, 32, 64)]
 
 
 def _set(spk, M, kernel, param):
     if kernel == "auto":
         return spk.KERNEL_NAMES[M.info.kernel], M.info.lanes
     k = {"stream": spk.KERNEL_STREAM, "vector": spk.KERNEL_VECTOR, "merge": spk.KERNEL_MERGE,
-         "sell": spk.KERNEL_SELL, "sliced": spk.KERNEL_SLICED}[kernel]
-    if kernel == "sell" and M.info.row_max > 255:
-        # SELL stores row lengths in one byte: the library refuses such rows
-        with pytest.raises(spk.SpkError, match="255"):
-            spk.mat_set_kernel(M, k, param)
-        return None, None
+         "sell": spk.KERNEL_SELL, "sliced": spk.KERNEL_SLICED, "sell_sigma": spk.KERNEL_SELL_SIGMA}[kernel]
     spk.mat_set_kernel(M, k, param)
+    assert spk.KERNEL_NAMES[M.info.kernel] == kernel
+    if kernel == "sell_sigma":
+        assert M.info.sell_sigma == (param or 4096)
     return kernel, M.info.lanes
 
 
@@ -71,7 +70,8 @@ def test_spmv_parity_fp64(kernel, param):
 
 
 @pytest.mark.parametrize("kernel,param", [("auto", 0), ("stream", 0), ("merge", 0), ("vector", 4),
-                                          ("vector", 64), ("sell", 0), ("sliced", 0), ("sliced", 2048)])
+                                          ("vector", 64), ("sell", 0), ("sell_sigma", 512), ("sliced", 0),
+                                          ("sliced", 2048)])
 def test_spmv_parity_fp32(kernel, param):
     spk = need_gpu()
     for name, A, integer in _matrices():
@@ -176,6 +176,53 @@ def test_spmv_unsorted_rows_every_family():
         y = to_dev(np.full(A.n, np.nan))
         spk.mat_mult(M, to_dev(x), y)
         assert np.array_equal(y.cpu().numpy(), ref), spk.KERNEL_NAMES[M.info.kernel]
+
+
+def _sell_sigma_stored(A, sigma):
+    """Stored entries of SELL-C-sigma: rows ordered by length (longest first,
+    ties in row order) within windows of sigma rows, slices of 64 rows padded
+    to their longest."""
+    lens = np.diff(A.rowptr).astype(np.int64)
+    order = np.concatenate([w0 + np.argsort(-lens[w0:w0 + sigma], kind="stable")
+                            for w0 in range(0, A.n, sigma)])
+    sl = lens[order]
+    sl = np.concatenate([sl, np.zeros(-A.n % 64, np.int64)])
+    return 64 * int(sl.reshape(-1, 64).max(axis=1).sum())
+
+
+def test_spmv_sell_sigma_layout():
+    """SELL-C-sigma on a power-law matrix (rows up to 1000 entries, so 16-bit
+    lengths): the stored entries are those of the sorted windows, sorting
+    shrinks the padding against plain SELL, and the product is bit-exact on
+    integer data for several windows, FP64 and FP32."""
+    spk = need_gpu()
+    import torch
+
+    B = spkgen.powerlaw_spd(50001, seed=6, hi=1000)
+    vals = np.random.default_rng(3).integers(-5, 6, B.nnz).astype(np.float64)
+    A = spkgen.CSR(B.n, B.rowptr, B.col, vals)
+    assert np.diff(A.rowptr).max() > 255
+    x = np.random.default_rng(4).integers(-20, 21, A.n).astype(np.float64)
+    ref = oracle.spmv(A, x)
+    M = mat_on_gpu(spk, A, flags=spk.MAT_MIXED)
+    spk.mat_set_kernel(M, spk.KERNEL_SELL, 0)
+    plain = M.info.stored_nnz
+    assert plain == _sell_stored(A)
+    for sigma in (64, 1024, 50048):
+        spk.mat_set_kernel(M, spk.KERNEL_SELL_SIGMA, sigma)
+        info = M.info
+        assert spk.KERNEL_NAMES[info.kernel] == "sell_sigma" and info.sell_sigma == sigma
+        assert info.stored_nnz == _sell_sigma_stored(A, sigma)
+        if sigma >= 1024:
+            assert info.stored_nnz < plain
+        y = to_dev(np.full(A.n, np.nan))
+        spk.mat_mult(M, to_dev(x), y)
+        assert np.array_equal(y.cpu().numpy(), ref), sigma
+        y32 = torch.full((A.n,), float("nan"), dtype=torch.float32, device="cuda")
+        spk.mat_mult_f32(M, to_dev(x, torch.float32), y32)
+        assert np.array_equal(y32.cpu().numpy().astype(np.float64), ref), sigma
+    with pytest.raises(spk.SpkError):
+        spk.mat_set_kernel(M, spk.KERNEL_SELL_SIGMA, 100)
 
 
 def _sell_stored(A):
