@@ -43,6 +43,11 @@ struct Request {
     spk_ksp_opts opts{};
     int mixed = 0;
     int R = 256, ntiles = 0, nblk = 0;
+    // SELL-64 copy for large systems (built on the device at admission from
+    // the uploaded CSR; slice offsets computed here at submit)
+    int sell = 0, sell_u = 2;
+    int64_t sell_nnz = 0;
+    std::vector<int32_t> sell_ptr;
     int64_t bytes = 0;
     int state = kQueued;
     int slot = -1;
@@ -102,8 +107,10 @@ struct Slot {
     int restarts = 0;
     int fallback = 0;
     int mixed = 0;
-    double *px = nullptr;  // pinned download buffer
+    double *px = nullptr;  // pinned download buffer (when the pool has no room)
     int64_t px_cap = 0;
+    int64_t x_off = -1;    // download block in the pinned pool, or -1
+    double *x_dst = nullptr;
     hipEvent_t ev = nullptr;
     int64_t first_step = 0;  // first batched step that includes this system
     hipEvent_t ev_up = nullptr;      // upload from the pinned pool done
@@ -140,7 +147,10 @@ struct spk_server {
     SysDesc *p_slotdesc = nullptr;            // pinned source of d_slotdesc
     int32_t *p_slotblk = nullptr;
     SysState *p_slotstate = nullptr;          // pinned state copy taken at retirement
-    SysDesc *d_table = nullptr;               // batched table
+    // batched tables, three sections of max_slots entries (blk: max_slots + 1):
+    // every active system, those with the stream-tile product, those with
+    // the SELL product
+    SysDesc *d_table = nullptr;
     int32_t *d_blk = nullptr;
     SysDesc *p_table[kTableRing] = {};
     int32_t *p_blk[kTableRing] = {};
@@ -152,6 +162,8 @@ struct spk_server {
     std::deque<int64_t> inflight_id;
     bool table_dirty = true;
     int nsys = 0, nblocks = 0, n_mixed = 0, n_fp64 = 0;
+    int nsys_st = 0, nblk_st = 0;             // stream-tile product section
+    int nsys_sl = 0, nblk_sl = 0, u_sl = 2;   // SELL product section
     char *stage[2] = {nullptr, nullptr};
     hipEvent_t ev_stage[2] = {nullptr, nullptr};
     int stage_i = 0;
@@ -168,6 +180,17 @@ namespace spk {
 
 static int64_t align256(int64_t b) { return (b + 255) & ~int64_t(255); }
 
+// A served system gets the SELL-64 product (int16 offsets) from this many
+// rows on, when its rows are short (<= 64), its slices pad by at most 15 %
+// and every |col - row| fits int16; smaller systems are launch-bound and keep
+// the stream-tile product, which needs no extra layout.
+constexpr int32_t kServeSellRows = 1 << 16;
+
+static int sell_plain_bits(int64_t stored, int nslices, int n)
+{
+    return sell_load_policy(stored, 2, nslices, n, 6, kIterCacheBudget);
+}
+
 // Device bytes a request occupies in the arena.
 static int64_t request_bytes(const Request &q)
 {
@@ -176,6 +199,11 @@ static int64_t request_bytes(const Request &q)
                 align256(8 * n) /*b*/ + align256(8 * n) /*x*/ + 4 * align256(8 * n) /*r z p q*/ +
                 align256(8 * kNumPart * (int64_t)std::max(q.nblk, 1));
     if (q.mixed) b += align256(4 * nz) + align256(4 * n) + 5 * align256(4 * n);
+    if (q.sell) {
+        const int64_t ns = (n + kSell - 1) / kSell;
+        b += align256(4 * (ns + 1)) + align256(2 * q.sell_nnz) + align256(n) + align256(8 * q.sell_nnz);
+        if (q.mixed) b += align256(4 * q.sell_nnz);
+    }
     return b;
 }
 
@@ -289,6 +317,28 @@ static int admit(spk_server *S, Request *q, int k, int64_t off)
         d.q32 = (float *)take(4 * n);
         d.d32 = (float *)take(4 * n);
     }
+    int32_t *sell_ptr = nullptr;
+    int16_t *sell_col = nullptr;
+    uint8_t *sell_len = nullptr;
+    double *sell_val = nullptr;
+    float *sell_val32 = nullptr;
+    if (q->sell) {
+        const int64_t ns = (n + kSell - 1) / kSell;
+        sell_ptr = (int32_t *)take(4 * (ns + 1));
+        sell_col = (int16_t *)take(2 * q->sell_nnz);
+        sell_len = (uint8_t *)take(n);
+        sell_val = (double *)take(8 * q->sell_nnz);
+        if (q->mixed) sell_val32 = (float *)take(4 * q->sell_nnz);
+        d.sell_cw = 2;
+        d.sell_ptr = sell_ptr;
+        d.sell_col = sell_col;
+        d.sell_len = sell_len;
+        d.sell_val = sell_val;
+        d.sell_val32 = sell_val32;
+        // ordinary loads when the layout and the iteration's vectors fit the
+        // Infinity Cache (the handle's rule), else nontemporal
+        d.sell_plain = sell_plain_bits(q->sell_nnz, (int)ns, q->n);
+    }
     d.rowptr = rowptr;
     d.col = col;
     d.val = val;
@@ -315,6 +365,9 @@ static int admit(spk_server *S, Request *q, int k, int64_t off)
         if (nz) SPK_TRY_RC(upload(S, val, q->h_val, 8 * nz));
         SPK_TRY_RC(upload(S, b, q->h_b, 8 * n));
     }
+    if (q->sell)  // the request keeps sell_ptr until it is collected
+        SPK_HIP(hipMemcpyAsync(sell_ptr, q->sell_ptr.data(), sizeof(int32_t) * q->sell_ptr.size(),
+                               hipMemcpyHostToDevice, S->cs));
     // per-slot descriptor and block table for the single-system launches (the
     // pinned source of slot k is only rewritten after its previous occupant
     // retired, i.e. after this copy of the previous admission completed)
@@ -330,6 +383,13 @@ static int admit(spk_server *S, Request *q, int k, int64_t off)
                        dinv, dinv32);
     if (q->mixed && nz)
         hipLaunchKernelGGL(k_srv_f32, dim3(grid1(nz)), dim3(kBlock), 0, S->s, nz, val, val32);
+    if (q->sell) {
+        hipLaunchKernelGGL(k_sell_fill<int16_t>, dim3(grid1(n)), dim3(kBlock), 0, S->s, q->n, rowptr, col, val,
+                           sell_ptr, (const int32_t *)nullptr, sell_col, sell_val, sell_len, (uint16_t *)nullptr);
+        if (q->mixed)
+            hipLaunchKernelGGL(k_srv_f32, dim3(grid1(q->sell_nnz)), dim3(kBlock), 0, S->s, q->sell_nnz,
+                               (const double *)sell_val, sell_val32);
+    }
     hipLaunchKernelGGL(k_srv_zero, dim3(grid1(n)), dim3(kBlock), 0, S->s, n, d.x);
     SPK_HIP(hipGetLastError());
     const spk_ksp_opts &o = q->opts;
@@ -382,26 +442,46 @@ static int rebuild_table(spk_server *S)
     const int i = S->table_buf;
     S->table_buf = (S->table_buf + 1) % kTableRing;
     SPK_HIP(hipEventSynchronize(S->ev_table[i]));
+    const int ms = (int)S->slots.size();
     SysDesc *pt = S->p_table[i];
     int32_t *pb = S->p_blk[i];
-    int ns = 0, nb = 0, nm = 0, nf = 0;
-    for (int k = 0; k < (int)S->slots.size(); ++k) {
+    // section c: table entries pt[c ms ...], block starts pb[c (ms + 1) ...]
+    int ns[3] = {0, 0, 0}, nb[3] = {0, 0, 0};
+    int nm = 0, nf = 0, u = 2;
+    auto put = [&](int c, const SysDesc &d) {
+        pt[c * ms + ns[c]] = d;
+        pb[c * (ms + 1) + ns[c]] = nb[c];
+        nb[c] += (d.nblk + kXcd - 1) / kXcd * kXcd;  // XCD-aligned start of the next system
+        ++ns[c];
+    };
+    for (int k = 0; k < ms; ++k) {
         const Slot &sl = S->slots[k];
         if (!sl.req || sl.req->state != kActive) continue;
-        pt[ns] = sl.desc;
-        pb[ns] = nb;
-        nb += (sl.desc.nblk + kXcd - 1) / kXcd * kXcd;  // XCD-aligned start of the next system
-        ++ns;
+        put(0, sl.desc);
+        if (sl.desc.sell_cw) {
+            put(2, sl.desc);
+            u = std::max(u, sl.req->sell_u);
+        } else {
+            put(1, sl.desc);
+        }
         if (sl.mixed) ++nm; else ++nf;
     }
-    pb[ns] = nb;
-    S->nsys = ns;
-    S->nblocks = nb;
+    for (int c = 0; c < 3; ++c) pb[c * (ms + 1) + ns[c]] = nb[c];
+    S->nsys = ns[0];
+    S->nblocks = nb[0];
+    S->nsys_st = ns[1];
+    S->nblk_st = nb[1];
+    S->nsys_sl = ns[2];
+    S->nblk_sl = nb[2];
+    S->u_sl = u;
     S->n_mixed = nm;
     S->n_fp64 = nf;
-    if (ns) {
-        SPK_HIP(hipMemcpyAsync(S->d_table, pt, sizeof(SysDesc) * ns, hipMemcpyHostToDevice, S->s));
-        SPK_HIP(hipMemcpyAsync(S->d_blk, pb, sizeof(int32_t) * (ns + 1), hipMemcpyHostToDevice, S->s));
+    for (int c = 0; c < 3; ++c) {
+        if (!ns[c]) continue;
+        SPK_HIP(hipMemcpyAsync(S->d_table + c * ms, pt + c * ms, sizeof(SysDesc) * ns[c], hipMemcpyHostToDevice,
+                               S->s));
+        SPK_HIP(hipMemcpyAsync(S->d_blk + c * (ms + 1), pb + c * (ms + 1), sizeof(int32_t) * (ns[c] + 1),
+                               hipMemcpyHostToDevice, S->s));
     }
     SPK_HIP(hipEventRecord(S->ev_table[i], S->s));
     S->table_dirty = false;
@@ -416,30 +496,51 @@ static __global__ void k_snapshot(const int2 *__restrict__ src, int2 *__restrict
     if (i < words) dst[i] = src[i];
 }
 
-// One batched step: K iterations of every active system.
+// One batched step: K iterations of every active system.  The products run
+// per section (stream tiles, SELL), the rest over the whole table.  (A step
+// captured as a hipGraph over tables padded to max_slots was measured
+// slower: replaying it costs the host more than these launches.)
 static int enqueue_step(spk_server *S)
 {
+    const int ms = (int)S->slots.size();
     const Batch b{S->d_table, S->d_blk, S->nsys};
-    const dim3 g(S->nblocks), t(kBlock), f(S->nsys);
+    const Batch bst{S->d_table + ms, S->d_blk + (ms + 1), S->nsys_st};
+    const Batch bsl{S->d_table + 2 * ms, S->d_blk + 2 * (ms + 1), S->nsys_sl};
+    const dim3 g(S->nblocks), t(kBlock), f(S->nsys), gst(S->nblk_st), gsl(S->nblk_sl);
     const int K = S->o.graph_k > 0 ? S->o.graph_k : 8;
+    hipStream_t st = S->s;
+    auto products = [&](auto vtag) {
+        using V = decltype(vtag);
+        if (S->nsys_st) hipLaunchKernelGGL((k_pcg_spmv_stream<V, Batch>), gst, t, 0, st, bst);
+        if (S->nsys_sl)
+            with_sell_u(S->u_sl, [&](auto uc) {
+                constexpr int U = decltype(uc)::value;
+                hipLaunchKernelGGL((k_pcg_spmv_sell<V, int16_t, U, Batch>), gsl, t, 0, st, bsl);
+            });
+    };
     if (S->n_mixed) {
-        hipLaunchKernelGGL(k_update_x<Batch>, g, t, 0, S->s, b);
-        hipLaunchKernelGGL((k_resid_stream<kGateResid, Batch>), g, t, 0, S->s, b);
-        hipLaunchKernelGGL((k_fin_resid<kGateResid, Batch>), f, t, 0, S->s, b, (int)kResOuter);
-        hipLaunchKernelGGL(k_setup32<Batch>, g, t, 0, S->s, b);
-        hipLaunchKernelGGL(k_fin_setup32<Batch>, f, t, 0, S->s, b);
-        hipLaunchKernelGGL((k_pcg_p_continue<float, Batch>), g, t, 0, S->s, b);
+        hipLaunchKernelGGL(k_update_x<Batch>, g, t, 0, st, b);
+        if (S->nsys_st) hipLaunchKernelGGL((k_resid_stream<kGateResid, Batch>), gst, t, 0, st, bst);
+        if (S->nsys_sl)
+            with_sell_u(S->u_sl, [&](auto uc) {
+                constexpr int U = decltype(uc)::value;
+                hipLaunchKernelGGL((k_resid_sell<kGateResid, int16_t, U, Batch>), gsl, t, 0, st, bsl);
+            });
+        hipLaunchKernelGGL((k_fin_resid<kGateResid, Batch>), f, t, 0, st, b, (int)kResOuter);
+        hipLaunchKernelGGL(k_setup32<Batch>, g, t, 0, st, b);
+        hipLaunchKernelGGL(k_fin_setup32<Batch>, f, t, 0, st, b);
+        hipLaunchKernelGGL((k_pcg_p_continue<float, Batch>), g, t, 0, st, b);
     }
     for (int k = 0; k < K; ++k) {
         if (S->n_fp64) {
-            hipLaunchKernelGGL((k_pcg_spmv_stream<double, Batch>), g, t, 0, S->s, b);
-            hipLaunchKernelGGL((k_pcg_update<double, Batch>), g, t, 0, S->s, b);
-            hipLaunchKernelGGL((k_pcg_px<double, Batch>), g, t, 0, S->s, b);
+            products(double());
+            hipLaunchKernelGGL((k_pcg_update<double, Batch>), g, t, 0, st, b);
+            hipLaunchKernelGGL((k_pcg_px<double, Batch>), g, t, 0, st, b);
         }
         if (S->n_mixed) {
-            hipLaunchKernelGGL((k_pcg_spmv_stream<float, Batch>), g, t, 0, S->s, b);
-            hipLaunchKernelGGL((k_pcg_update<float, Batch>), g, t, 0, S->s, b);
-            hipLaunchKernelGGL((k_pcg_px<float, Batch>), g, t, 0, S->s, b);
+            products(float());
+            hipLaunchKernelGGL((k_pcg_update<float, Batch>), g, t, 0, st, b);
+            hipLaunchKernelGGL((k_pcg_px<float, Batch>), g, t, 0, st, b);
         }
     }
     SPK_HIP(hipGetLastError());
@@ -454,14 +555,28 @@ static int begin_retire(spk_server *S, int k)
     hipLaunchKernelGGL((k_resid_stream<kGateNone, One>), dim3(sl.desc.nblk), dim3(kBlock), 0, S->s, b);
     hipLaunchKernelGGL((k_fin_resid<kGateNone, One>), dim3(1), dim3(kBlock), 0, S->s, b, (int)kResTrue);
     SPK_HIP(hipGetLastError());
-    if (sl.px_cap < q->n) {
-        if (sl.px) hipHostFree(sl.px);
-        sl.px = nullptr;
-        const int64_t cap = std::max<int64_t>(q->n, 1 << 16);
-        SPK_HIP(hipHostMalloc((void **)&sl.px, sizeof(double) * cap, hipHostMallocDefault));
-        sl.px_cap = cap;
+    // x lands in a block of the pinned pool (no allocation on this path);
+    // only when the pool is full does the slot's own buffer grow, and
+    // freeing pinned memory waits for the device
+    sl.x_dst = nullptr;
+    if (S->pin_base) {
+        const int64_t off = S->pin_arena.alloc(sizeof(double) * (int64_t)q->n);
+        if (off >= 0) {
+            sl.x_off = off;
+            sl.x_dst = (double *)(S->pin_base + off);
+        }
     }
-    SPK_HIP(hipMemcpyAsync(sl.px, sl.desc.x, sizeof(double) * q->n, hipMemcpyDeviceToHost, S->s));
+    if (!sl.x_dst) {
+        if (sl.px_cap < q->n) {
+            if (sl.px) hipHostFree(sl.px);
+            sl.px = nullptr;
+            const int64_t cap = std::max<int64_t>(q->n, 1 << 16);
+            SPK_HIP(hipHostMalloc((void **)&sl.px, sizeof(double) * cap, hipHostMallocDefault));
+            sl.px_cap = cap;
+        }
+        sl.x_dst = sl.px;
+    }
+    SPK_HIP(hipMemcpyAsync(sl.x_dst, sl.desc.x, sizeof(double) * q->n, hipMemcpyDeviceToHost, S->s));
     SPK_HIP(hipMemcpyAsync(S->p_slotstate + k, S->d_states + k, sizeof(SysState), hipMemcpyDeviceToHost, S->s));
     SPK_HIP(hipEventRecord(sl.ev, S->s));
     q->state = kRetiring;
@@ -471,6 +586,13 @@ static int begin_retire(spk_server *S, int k)
 
 // Slot k's retirement copies have landed: check the true residual, then
 // finish the request or restart / fall back.
+static void release_x(spk_server *S, Slot &sl, int32_t n)
+{
+    if (sl.x_off >= 0) S->pin_arena.release(sl.x_off, sizeof(double) * (int64_t)n);
+    sl.x_off = -1;
+    sl.x_dst = nullptr;
+}
+
 static int end_retire(spk_server *S, int k, const SysState &st)
 {
     Slot &sl = S->slots[k];
@@ -478,6 +600,7 @@ static int end_retire(spk_server *S, int k, const SysState &st)
     const bool conv = st.status == SPK_CONVERGED_RTOL || st.status == SPK_CONVERGED_ATOL;
     if (!sl.mixed && conv && st.bnorm > 0 && st.iter > 0 && st.rnorm_true > st.thresh &&
         sl.restarts < 3) {
+        release_x(S, sl, q->n);
         ++sl.restarts;  // true residual drifted: restart from it
         hipLaunchKernelGGL(k_state_restart, dim3(1), dim3(64), 0, S->s, sl.desc.st);
         hipLaunchKernelGGL(k_setup64<One>, dim3(sl.desc.nblk), dim3(kBlock), 0, S->s, slot_batch(S, k));
@@ -489,6 +612,7 @@ static int end_retire(spk_server *S, int k, const SysState &st)
         return SPK_OK;
     }
     if (sl.mixed && st.status == SPK_DIVERGED_STAGNATION) {
+        release_x(S, sl, q->n);
         // finish in FP64 from the current x
         sl.mixed = 0;
         sl.fallback = 1;
@@ -504,7 +628,8 @@ static int end_retire(spk_server *S, int k, const SysState &st)
         S->table_dirty = true;
         return SPK_OK;
     }
-    q->x.assign(sl.px, sl.px + q->n);
+    q->x.assign(sl.x_dst, sl.x_dst + q->n);
+    release_x(S, sl, q->n);
     spk_ksp_result &r = q->res;
     r.reason = st.status;
     if (!sl.mixed && conv && st.iter > 0 && st.rnorm_true > st.thresh) r.reason = SPK_DIVERGED_BREAKDOWN;
@@ -584,7 +709,7 @@ void spk_server_opts_default(spk_server_opts *o)
     o->hbm_budget_bytes = 8ll << 30;
     o->max_slots = 64;
     o->graph_k = 8;
-    o->max_blocks_per_system = 256;
+    o->max_blocks_per_system = 2048;
     o->pinned_bytes = 1ll << 30;
 }
 
@@ -619,8 +744,8 @@ int spk_server_create(const spk_server_opts *opts, void *stream, spk_server **ou
     chk(hipMalloc(&S->d_states, sizeof(SysState) * ms), "states");
     chk(hipMalloc(&S->d_slotdesc, sizeof(SysDesc) * ms), "slot descs");
     chk(hipMalloc(&S->d_slotblk, sizeof(int32_t) * 2 * ms), "slot blocks");
-    chk(hipMalloc(&S->d_table, sizeof(SysDesc) * ms), "table");
-    chk(hipMalloc(&S->d_blk, sizeof(int32_t) * (ms + 1)), "table blocks");
+    chk(hipMalloc(&S->d_table, sizeof(SysDesc) * 3 * ms), "table");
+    chk(hipMalloc(&S->d_blk, sizeof(int32_t) * 3 * (ms + 1)), "table blocks");
     chk(hipHostMalloc((void **)&S->p_slotdesc, sizeof(SysDesc) * ms, hipHostMallocDefault), "pinned descs");
     chk(hipHostMalloc((void **)&S->p_slotblk, sizeof(int32_t) * 2 * ms, hipHostMallocDefault), "pinned blocks");
     chk(hipHostMalloc((void **)&S->p_slotstate, sizeof(SysState) * ms, hipHostMallocDefault), "pinned states");
@@ -633,8 +758,9 @@ int spk_server_create(const spk_server_opts *opts, void *stream, spk_server **ou
         chk(hipEventCreateWithFlags(&S->ev_stage[i], hipEventDisableTiming), "event");
     }
     for (int i = 0; i < kTableRing; ++i) {
-        chk(hipHostMalloc((void **)&S->p_table[i], sizeof(SysDesc) * ms, hipHostMallocDefault), "pinned table");
-        chk(hipHostMalloc((void **)&S->p_blk[i], sizeof(int32_t) * (ms + 1), hipHostMallocDefault), "pinned blocks");
+        chk(hipHostMalloc((void **)&S->p_table[i], sizeof(SysDesc) * 3 * ms, hipHostMallocDefault), "pinned table");
+        chk(hipHostMalloc((void **)&S->p_blk[i], sizeof(int32_t) * 3 * (ms + 1), hipHostMallocDefault),
+            "pinned blocks");
         chk(hipEventCreateWithFlags(&S->ev_table[i], hipEventDisableTiming), "event");
     }
     for (auto &sl : S->slots) {
@@ -703,6 +829,27 @@ int spk_server_submit(spk_server *S, int32_t n, int64_t nnz, const int32_t *rowp
         if (maxtile[t] <= TileLds<double>::kCap) { q->R = kTileRs[t]; break; }
     q->ntiles = ceil_div(n, q->R);
     q->nblk = pick_nblk(q->ntiles, S->o.max_blocks_per_system);
+    if (n >= kServeSellRows) {
+        // slice widths from the row pointers; the offsets are checked below
+        const int32_t ns = ceil_div(n, kSell);
+        int64_t acc = 0;
+        int wmax = 0;
+        std::vector<int32_t> sp((size_t)ns + 1);
+        for (int32_t k = 0; k < ns; ++k) {
+            int mx = 0;
+            for (int32_t i = k * kSell; i < std::min(n, (k + 1) * kSell); ++i) mx = std::max(mx, rowptr[i + 1] - rowptr[i]);
+            wmax = std::max(wmax, mx);
+            sp[k] = (int32_t)std::min<int64_t>(acc, 0x7fffffff);
+            acc += (int64_t)kSell * mx;
+        }
+        sp[ns] = (int32_t)std::min<int64_t>(acc, 0x7fffffff);
+        if (wmax <= 64 && (double)acc <= 1.15 * (double)nnz && acc < 0x7fff0000LL) {
+            q->sell = 1;
+            q->sell_u = pick_sell_u(wmax);
+            q->sell_nnz = acc;
+            q->sell_ptr.swap(sp);
+        }
+    }
     q->bytes = request_bytes(*q);
     if (q->bytes > S->o.hbm_budget_bytes) {
         set_error("system needs %lld bytes, budget is %lld", (long long)q->bytes,
@@ -754,6 +901,7 @@ int spk_server_submit(spk_server *S, int32_t n, int64_t nnz, const int32_t *rowp
         int32_t row = INT32_MAX;
         int32_t col = 0;
         int code = SPK_OK;
+        int32_t maxd = 0;  // largest |col - row|
     };
     auto check_rows = [&](int32_t i0, int32_t i1, Bad &bad) {
         int32_t *__restrict__ hc = q->h_col;
@@ -761,7 +909,7 @@ int spk_server_submit(spk_server *S, int32_t n, int64_t nnz, const int32_t *rowp
         for (int32_t i = i0; i < i1; ++i) {
             const int32_t a = rowptr[i], e = rowptr[i + 1];
             double d = 0.0;
-            int32_t lo = 0, hi = n - 1;  // min / max column of the row
+            int32_t lo = i, hi = i;  // min / max column of the row (and i)
             for (int32_t k = a; k < e; ++k) {
                 const int32_t c = colind[k];
                 const double v = values[k];
@@ -771,6 +919,7 @@ int spk_server_submit(spk_server *S, int32_t n, int64_t nnz, const int32_t *rowp
                 hi = c > hi ? c : hi;
                 d += c == i ? v : 0.0;
             }
+            bad.maxd = std::max(bad.maxd, std::max(i - lo, hi - i));
             if (lo < 0 || hi >= n) {
                 for (int32_t k = a; k < e; ++k)
                     if (colind[k] < 0 || colind[k] >= n) { bad = {i, colind[k], SPK_EINVAL}; return; }
@@ -802,6 +951,14 @@ int spk_server_submit(spk_server *S, int32_t n, int64_t nnz, const int32_t *rowp
     } else if (first.code == SPK_EZERODIAG) {
         set_error("row %d has no stored or a zero diagonal", first.row);
         rc = SPK_EZERODIAG;
+    }
+    int32_t maxd = 0;
+    for (const Bad &x : bad) maxd = std::max(maxd, x.maxd);
+    if (q->sell && maxd > 32767) {  // offsets do not fit int16: stream tiles
+        q->sell = 0;
+        q->sell_nnz = 0;
+        std::vector<int32_t>().swap(q->sell_ptr);
+        q->bytes = request_bytes(*q);
     }
     if (rc != SPK_OK) {
         if (q->pin_off >= 0) {

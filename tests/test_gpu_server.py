@@ -134,6 +134,30 @@ def test_server_midflight_admission_alone_equals_batch(prec):
             (r.iterations, r.inner_iterations, r.outer_steps)
 
 
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_server_large_systems_sell_product(prec):
+    """Systems of at least 65,536 rows take the SELL-64 product (layout built
+    on the device at admission), beside small ones on stream tiles in the same
+    batch: every result meets the oracle's true residual and is bitwise the
+    one the same request gets alone."""
+    spk = need_gpu()
+    p = spk.PREC_FP64 if prec == "fp64" else spk.PREC_MIXED
+    items = [(None, spkgen.laplace2d5(260, shift=0.3), None), (None, spkgen.laplace3d7(42, shift=0.2), None),
+             (None, spkgen.laplace2d5(30, shift=0.1), None), (None, spkgen.laplace3d7(12, shift=0.5), None)]
+    items = [(r, A, spkgen.rhs_uniform(A.n, 11 + i)) for i, (r, A, _) in enumerate(items)]
+    S = spk.server_create()
+    mixed = _run(spk, S, items, p)
+    S.close()
+    for i, ((_, A, b), (x, res)) in enumerate(zip(items, mixed)):
+        assert res.reason == spk.CONVERGED_RTOL, res.as_dict()
+        assert oracle.nrm2(b - oracle.spmv(A, x)) <= 1e-8 * oracle.nrm2(b) * (1 + 1e-6)
+        S1 = spk.server_create()
+        (x1, r1), = _run(spk, S1, [items[i]], p)
+        S1.close()
+        assert np.array_equal(x1, x), f"request {i} differs alone vs in the batch"
+        assert (r1.iterations, r1.inner_iterations) == (res.iterations, res.inner_iterations)
+
+
 def test_server_budget_and_errors():
     spk = need_gpu()
     opts = spk.server_opts_default()
@@ -211,7 +235,7 @@ def test_server_system_over_more_blocks_than_one_partial_chunk(prec):
     """max_blocks_per_system above 2048 (allowed up to 8192): a 760^2 system
     then spans 2256 blocks, more partials than the update pass loads in one
     chunk per thread, so every block takes the looped partial sum.  The
-    result matches the oracle, and the same system over the default 256
+    result matches the oracle, and the same system over 256
     blocks converges in the same number of iterations within one."""
     spk = need_gpu()
     p = spk.PREC_FP64 if prec == "fp64" else spk.PREC_MIXED
