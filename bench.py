@@ -1,19 +1,26 @@
 """Benchmark of the CSR SpMV / Jacobi-PCG hot path on one MI355X.
 
-Default workload: 3D 7-point Laplacian on a 128^3 grid (n = 2,097,152,
-nnz = 14,581,760), FP64 CSR with int32 indices, rhs uniform[-1, 1) from seed 0.
-One step = one FP64 Jacobi-PCG solve to rtol 1e-8 + one mixed-precision solve
-(FP32 inner CG, FP64 refinement) to rtol 1e-8 + 100 standalone FP64 SpMVs,
-all through the C ABI of libspk.so on the current torch stream.
+Default line (no flags): one step is
+  - C2, 3D 7-point Laplacian 128^3 (n = 2,097,152, nnz = 14,581,760): one FP64
+    and one mixed-precision Jacobi-PCG solve to rtol 1e-8 and 100 standalone
+    FP64 SpMVs;
+  - C3, 3D 27-point lognormal diffusion 160^3 (n = 4,096,000,
+    nnz = 109,215,352): one FP64 and one mixed solve to rtol 1e-8, and a
+    100-iteration FP64 PCG run whose SpMV products are each timed with a HIP
+    event pair on the solve stream (the roofline of the PCG product).
+All inputs are resident in HBM before the clock starts; every call goes
+through the C ABI of libspk.so on the current torch stream.  `value` is the
+step's algorithmic HBM traffic (SpMV 12 nnz + 4(n+1) + 16n bytes, PCG
+iteration 12 nnz + 4(n+1) + 88n, FP32 inner iteration 8 nnz + 4(n+1) + 44n,
+refinement steps and setup/true-residual products) divided by its wall time.
+After the timed steps, outside the clock: the C2 SpMV after evicting the
+Infinity Cache, the served stream (C5: Poisson arrivals, p50/p99 latency, a
+closed loop for solves/s against one-at-a-time solves), the single-reduction,
+Chebyshev, multi-right-hand-side and multigrid legs, and the CPU oracle
+(serial and all host cores).
 
-Prints one JSON line.  `value` is the whole step's algorithmic HBM traffic
-divided by its wall time (GB/s); solves/s, solve latency percentiles and the
-SpMV rate are reported beside it.  `roofline` covers the SpMV kernel, timed
-with HIP events around each launch on the stream it runs on.
-
-Other workloads (one JSON line each): --workload c3 (27-point lognormal
-160^3, FP64 vs mixed), c4 (power-law n = 4M SpMV by kernel family), serve
-(served solve stream).
+Other workloads (one JSON line each): --workload c2 (the C2 part alone),
+c3, c4 (power-law n = 4M SpMV by kernel family), serve, spectrum, mg.
 """
 
 from __future__ import annotations
@@ -43,7 +50,7 @@ def parse():
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=10)
     p.add_argument("--warmup", type=int, default=2)
-    p.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "serve", "spectrum", "mg"])
+    p.add_argument("--workload", default="all", choices=["all", "c2", "c3", "c4", "serve", "spectrum", "mg"])
     p.add_argument("--spmvs", type=int, default=100)
     p.add_argument("--cold-spmvs", type=int, default=20,
                    help="SpMVs timed after evicting the Infinity Cache (after the timed steps)")
@@ -54,6 +61,18 @@ def parse():
     p.add_argument("--serve-rate", type=float, default=200.0)
     p.add_argument("--serve-closed", type=int, default=0,
                    help="closed-loop saturation run with this many requests queued at t=0")
+    p.add_argument("--c5-seconds", type=float, default=20.0,
+                   help="default line: seconds of the open-loop served stream")
+    p.add_argument("--c5-closed", type=int, default=500,
+                   help="default line: requests of the closed-loop run (0: none)")
+    p.add_argument("--c3-probe-iters", type=int, default=100,
+                   help="default line: FP64 PCG iterations whose products are event-timed on C3")
+    p.add_argument("--no-extras", action="store_true",
+                   help="default line: skip the single-reduction, Chebyshev, multi-RHS and multigrid legs")
+    p.add_argument("--c4-band", type=int, default=0,
+                   help="c4 workload: columns within +-band of the row (the banded diagnostic variant)")
+    p.add_argument("--cpu-c5-seconds", type=float, default=15.0,
+                   help="CPU oracle floor of the served stream: seconds of sequential solves")
     return p.parse_args()
 
 
@@ -67,9 +86,9 @@ def pct(a, q):
     return float(np.percentile(np.asarray(a), q)) if len(a) else None
 
 
-def source_hash():
+def source_hash(files=("spmv.hpp", "common.hpp")):
     h = hashlib.sha256()
-    for f in ("spmv.hpp", "common.hpp"):
+    for f in files:
         with open(os.path.join(ROOT, "paper_2011_00715_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -77,14 +96,15 @@ def source_hash():
 
 def traffic_from_profiles(kernel_key, bytes_per_launch):
     """HBM bytes per launch from committed rocprofv3 PMC summaries, or None if
-    absent or taken on a different kernel source."""
+    absent or taken on a different kernel source (the entry lists the source
+    files its kernel is built from)."""
     path = os.path.join(ROOT, "profiles", "traffic_counters.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
         d = json.load(f)
     e = d.get(kernel_key)
-    if not e or e.get("source_hash") != source_hash():
+    if not e or e.get("source_hash") != source_hash(tuple(e.get("sources", ("spmv.hpp", "common.hpp")))):
         return None
     return e.get("hbm_bytes_per_launch")
 
@@ -114,7 +134,28 @@ def solve_bytes(info, res):
     return res.iterations * info.bytes_pcg_iter_f64 + 2 * info.bytes_spmv_f64
 
 
+def cpu_info():
+    import os
+
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count()
+    return {"nproc": os.cpu_count(), "usable_cpus": usable, "model": model}
+
+
 def cpu_baseline(A, b, info, iters):
+    """The serial oracle on a bounded sample: `iters` FP64 PCG iterations of
+    the C2 system (plus its setup and final residual products)."""
     import oracle
 
     t = time.perf_counter()
@@ -131,6 +172,141 @@ def cpu_baseline(A, b, info, iters):
                   f"{dt / max(r['iterations'], 1) * 1e3:.1f} ms per iteration",
         "seconds": dt,
     }
+
+
+def cpu_baselines(A1, A2, b2, info2, serve_reqs, args):
+    """The oracle timed on the host: the OpenMP build on every core it is
+    given (full C2 and C1 solves, and a sequential floor of the served
+    stream), and the serial build on a bounded C2 sample."""
+    import numpy as np
+
+    import oracle
+    import spkgen
+
+    lo = oracle.load_omp()
+    threads = oracle.threads(lo)
+    t = time.perf_counter()
+    _, r2, _ = oracle.pcg(A2, b2, lib=lo)
+    dt2 = time.perf_counter() - t
+    bytes2 = r2["iterations"] * info2.bytes_pcg_iter_f64 + 2 * info2.bytes_spmv_f64
+    c1 = []
+    for seed in range(5):
+        b1 = spkgen.rhs_uniform(A1.n, seed)
+        t = time.perf_counter()
+        _, r1, _ = oracle.pcg(A1, b1, lib=lo)
+        c1.append((time.perf_counter() - t, r1["iterations"]))
+    serial = cpu_baseline(A2, b2, info2, args.cpu_iters)
+    # served stream, one request after the other (FP64 oracle solve of each),
+    # for at most cpu_c5_seconds
+    lat, t_all = [], time.perf_counter()
+    for r in serve_reqs:
+        if time.perf_counter() - t_all > args.cpu_c5_seconds:
+            break
+        A = spkgen.serve_matrix(r)
+        bq = spkgen.rhs_uniform(A.n, r.rhs_seed % (2**31))
+        t = time.perf_counter()
+        _, rq, _ = oracle.pcg(A, bq, lib=lo)
+        lat.append(time.perf_counter() - t)
+        assert rq["reason"] > 0
+    span = time.perf_counter() - t_all
+    return {
+        "value": bytes2 / dt2 / 1e9,
+        "unit": "GB/s",
+        "cores": threads,
+        "kind": "oracle",
+        "sample": (f"one full FP64 Jacobi-PCG solve of the 128^3 7-point system to rtol 1e-8 "
+                   f"({r2['iterations']} iterations, {dt2:.2f} s, {1 / dt2:.2f} solves/s), OpenMP build of "
+                   f"the oracle on {threads} threads"),
+        "host": cpu_info(),
+        "c2_solve": {"seconds": dt2, "solves_per_s": 1 / dt2, "iterations": r2["iterations"],
+                     "ms_per_iter": dt2 * 1e3 / max(r2["iterations"], 1)},
+        "c1_solves": {"ms_p50": float(np.median([c[0] for c in c1])) * 1e3,
+                      "solves_per_s": 1 / float(np.median([c[0] for c in c1])),
+                      "iterations": [c[1] for c in c1]},
+        "c5_sequential": {"requests": len(lat), "seconds": span,
+                          "solves_per_s": len(lat) / span if span > 0 else None,
+                          "solve_ms_p50": pct(lat, 50) * 1e3 if lat else None,
+                          "solve_ms_p99": pct(lat, 99) * 1e3 if lat else None,
+                          "note": "the first requests of the closed-loop set, solved one after the other "
+                                  "(FP64 oracle PCG to rtol 1e-8)"},
+        "serial_1_core": serial,
+    }
+
+
+def c2_extra_legs(spk, M, A, b, bd, xs, info, args, jacobi_s):
+    """The C2 legs of the other hot-path rows, outside the timed steps:
+    Chebyshev-Jacobi smoother, single-reduction CG, multiple right-hand
+    sides, multigrid-preconditioned CG."""
+    import numpy as np
+    import torch
+
+    import spkgen
+
+    # Chebyshev-Jacobi smoother (multigrid smoothing of Sec. 5.3), default
+    # interval [g/10, g] from the Gershgorin bound; outside the timed steps
+    cheb = {}
+    xc = torch.zeros_like(xs)
+    mat_bytes = 12 * info.nnz + 4 * (info.n + 1)
+    for steps in (2, 8):
+        us = []
+        for _ in range(20):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            spk.pc_chebyshev(M, bd, xc, steps)
+            e1.record()
+            torch.cuda.synchronize()
+            us.append(e0.elapsed_time(e1) * 1e3)
+        nb = 40 * info.n + (steps - 1) * (mat_bytes + 56 * info.n) + 24 * info.n
+        t = float(np.median(us))
+        cheb[f"steps_{steps}"] = {"us_p50": t, "bytes": nb, "gbps": nb / (t * 1e-6) / 1e9}
+    cheb["note"] = ("x0 = 0, no residual output: 40n (init) + (steps-1) x (12 nnz + 4(n+1) + 56n) "
+                    "fused SpMV+update passes + 24n (last x += d)")
+
+    # single-reduction (Chronopoulos-Gear) FP64 solve of the same system
+    osr = spk.ksp_opts(graph_k=args.graph_k, single_reduction=1)
+    xsr = torch.zeros_like(xs)
+    rsr = spk.ksp_solve(M, bd, xsr, osr)
+    tsr = []
+    for _ in range(3):
+        rsr = spk.ksp_solve(M, bd, xsr, osr)
+        tsr.append(rsr.seconds)
+    sr = {"solves_per_s": 1.0 / float(np.median(tsr)), "ms_p50": float(np.median(tsr)) * 1e3,
+          "iterations": rsr.iterations, "us_per_iter": float(np.median(tsr)) * 1e6 / max(rsr.iterations, 1),
+          "true_rel_residual": rsr.true_rel_residual, "reason": spk.reason_str(rsr.reason)}
+
+    # multiple right-hand sides (k = 8): SpMM, and 8 solves sharing each SpMM
+    kk = 8
+    Xm = torch.stack([xs] * kk, dim=1).contiguous()
+    Ym = torch.empty_like(Xm)
+    spk.mat_mult_multi(M, Xm, Ym)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(20):
+        spk.mat_mult_multi(M, Xm, Ym)
+    e1.record()
+    torch.cuda.synchronize()
+    spmm_us = e0.elapsed_time(e1) * 1e3 / 20
+    Bm = torch.stack([dev(spkgen.rhs_uniform(A.n, sd)) for sd in range(kk)], dim=1).contiguous()
+    Xs = torch.zeros_like(Bm)
+    spk.ksp_solve_multi(M, Bm, Xs, spk.ksp_opts(graph_k=args.graph_k))
+    ts = []
+    for _ in range(3):
+        Xs.zero_()
+        rs = spk.ksp_solve_multi(M, Bm, Xs, spk.ksp_opts(graph_k=args.graph_k))
+        ts.append(rs[0].seconds)
+    tm = float(np.median(ts))
+    spmm_bytes = 12 * info.nnz + 4 * (info.n + 1) + 16 * kk * info.n
+    multi = {"k": kk, "spmm_us": spmm_us, "spmm_bytes": spmm_bytes,
+             "spmm_gbps": spmm_bytes / (spmm_us * 1e-6) / 1e9,
+             "spmm_us_per_rhs": spmm_us / kk,
+             "solve_ms": tm * 1e3, "rhs_solved_per_s": kk / tm,
+             "iterations": [r.iterations for r in rs],
+             "worst_true_rel_residual": max(r.true_rel_residual for r in rs),
+             "note": "SpMM bytes: CSR matrix once + k x (8n gather + 8n write); solves: k FP64 "
+                     "Jacobi-PCG columns sharing each SpMM, per-column scalars and stopping"}
+
+    mg = mg_legs(spk, M, A, b, bd, 128, jacobi_s)
+    return cheb, sr, multi, mg
 
 
 def bench_c2(args):
@@ -220,70 +396,7 @@ def bench_c2(args):
     del scratch
     cold_avg = float(np.mean(cold_us)) if cold_us else float("nan")
 
-    # Chebyshev-Jacobi smoother (multigrid smoothing of Sec. 5.3), default
-    # interval [g/10, g] from the Gershgorin bound; outside the timed steps
-    cheb = {}
-    xc = torch.zeros_like(xs)
-    mat_bytes = 12 * info.nnz + 4 * (info.n + 1)
-    for steps in (2, 8):
-        us = []
-        for _ in range(20):
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            e0.record()
-            spk.pc_chebyshev(M, bd, xc, steps)
-            e1.record()
-            torch.cuda.synchronize()
-            us.append(e0.elapsed_time(e1) * 1e3)
-        nb = 40 * info.n + (steps - 1) * (mat_bytes + 56 * info.n) + 24 * info.n
-        t = float(np.median(us))
-        cheb[f"steps_{steps}"] = {"us_p50": t, "bytes": nb, "gbps": nb / (t * 1e-6) / 1e9}
-    cheb["note"] = ("x0 = 0, no residual output: 40n (init) + (steps-1) x (12 nnz + 4(n+1) + 56n) "
-                    "fused SpMV+update passes + 24n (last x += d)")
-
-    # single-reduction (Chronopoulos-Gear) FP64 solve of the same system
-    osr = spk.ksp_opts(graph_k=args.graph_k, single_reduction=1)
-    xsr = torch.zeros_like(xs)
-    rsr = spk.ksp_solve(M, bd, xsr, osr)
-    tsr = []
-    for _ in range(3):
-        rsr = spk.ksp_solve(M, bd, xsr, osr)
-        tsr.append(rsr.seconds)
-    sr = {"solves_per_s": 1.0 / float(np.median(tsr)), "ms_p50": float(np.median(tsr)) * 1e3,
-          "iterations": rsr.iterations, "us_per_iter": float(np.median(tsr)) * 1e6 / max(rsr.iterations, 1),
-          "true_rel_residual": rsr.true_rel_residual, "reason": spk.reason_str(rsr.reason)}
-
-    # multiple right-hand sides (k = 8): SpMM, and 8 solves sharing each SpMM
-    kk = 8
-    Xm = torch.stack([xs] * kk, dim=1).contiguous()
-    Ym = torch.empty_like(Xm)
-    spk.mat_mult_multi(M, Xm, Ym)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(20):
-        spk.mat_mult_multi(M, Xm, Ym)
-    e1.record()
-    torch.cuda.synchronize()
-    spmm_us = e0.elapsed_time(e1) * 1e3 / 20
-    Bm = torch.stack([dev(spkgen.rhs_uniform(A.n, sd)) for sd in range(kk)], dim=1).contiguous()
-    Xs = torch.zeros_like(Bm)
-    spk.ksp_solve_multi(M, Bm, Xs, spk.ksp_opts(graph_k=args.graph_k))
-    ts = []
-    for _ in range(3):
-        Xs.zero_()
-        rs = spk.ksp_solve_multi(M, Bm, Xs, spk.ksp_opts(graph_k=args.graph_k))
-        ts.append(rs[0].seconds)
-    tm = float(np.median(ts))
-    spmm_bytes = 12 * info.nnz + 4 * (info.n + 1) + 16 * kk * info.n
-    multi = {"k": kk, "spmm_us": spmm_us, "spmm_bytes": spmm_bytes,
-             "spmm_gbps": spmm_bytes / (spmm_us * 1e-6) / 1e9,
-             "spmm_us_per_rhs": spmm_us / kk,
-             "solve_ms": tm * 1e3, "rhs_solved_per_s": kk / tm,
-             "iterations": [r.iterations for r in rs],
-             "worst_true_rel_residual": max(r.true_rel_residual for r in rs),
-             "note": "SpMM bytes: CSR matrix once + k x (8n gather + 8n write); solves: k FP64 "
-                     "Jacobi-PCG columns sharing each SpMM, per-column scalars and stopping"}
-
-    mg = mg_legs(spk, M, A, b, bd, N, float(np.median(t64)) * 1e-3)
+    cheb, sr, multi, mg = c2_extra_legs(spk, M, A, b, bd, xs, info, args, float(np.median(t64)) * 1e-3)
 
     out = {
         "metric": "CSR SpMV HBM GB/s; PCG solves/s to rtol 1e-8, FP64 vs mixed; p50/p99 lat",
@@ -352,6 +465,227 @@ def bench_c2(args):
         log("cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(A, b, info, args.cpu_iters)
     M.close()
+    return out
+
+
+def wide_product(info):
+    """Whether the PCG runs the one-wavefront-per-slice SELL product (the
+    library's rule: more than 96 stored entries per lane of a grid of
+    min(2048, ceil(n / 256)) blocks, rounded down to a multiple of 8)."""
+    tiles = (info.n + 255) // 256
+    nblk = tiles if tiles < 8 else min(tiles, 2048) - min(tiles, 2048) % 8
+    return info.kernel == 4 and info.stored_nnz > 96 * 256 * nblk  # 4 = SPK_KERNEL_SELL
+
+
+def bench_all(args):
+    """The default line (see the module docstring)."""
+    import numpy as np
+    import torch
+
+    import oracle
+    import spkgen
+    from paper_2011_00715_amd import spk
+
+    log("generating C2 (7-point 128^3) and C3 (27-point lognormal 160^3)")
+    A2 = spkgen.laplace3d7(128)
+    b2 = spkgen.rhs_uniform(A2.n, 0)
+    A3 = spkgen.diffusion3d27_lognormal(160, seed=0)
+    b3 = spkgen.rhs_uniform(A3.n, 0)
+    M2 = spk.mat_create_csr(dev(A2.rowptr), dev(A2.col), dev(A2.val), flags=spk.MAT_MIXED)
+    M3 = spk.mat_create_csr(dev(A3.rowptr), dev(A3.col), dev(A3.val), flags=spk.MAT_MIXED)
+    i2, i3 = M2.info, M3.info
+    assert spk.KERNEL_NAMES[i3.kernel] == "sell" and i3.lanes == 16 and wide_product(i3)
+    bd2, bd3 = dev(b2), dev(b3)
+    xs2 = dev(b2)
+    ys2 = torch.empty_like(xs2)
+    x64_2, xmx_2 = torch.zeros_like(xs2), torch.zeros_like(xs2)
+    x64_3, xmx_3, xpr_3 = torch.zeros_like(bd3), torch.zeros_like(bd3), torch.zeros_like(bd3)
+    o64 = spk.ksp_opts(graph_k=args.graph_k)
+    omx = spk.ksp_opts(graph_k=args.graph_k, precision=spk.PREC_MIXED)
+    P = args.c3_probe_iters
+    oprobe = spk.ksp_opts(rtol=0.0, atol=0.0, maxit=P, profile=1)
+    S = args.spmvs
+    ev = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+
+    def step(record):
+        r = {"c2_64": spk.ksp_solve(M2, bd2, x64_2, o64), "c2_mx": spk.ksp_solve(M2, bd2, xmx_2, omx)}
+        if record:
+            ev[0].record()
+        for _ in range(S):
+            spk.mat_mult(M2, xs2, ys2)
+        if record:
+            ev[1].record()
+        r["c3_64"] = spk.ksp_solve(M3, bd3, x64_3, o64)
+        r["c3_mx"] = spk.ksp_solve(M3, bd3, xmx_3, omx)
+        r["c3_probe"] = spk.ksp_solve(M3, bd3, xpr_3, oprobe)
+        return r
+
+    def step_bytes(r):
+        return (solve_bytes(i2, r["c2_64"]) + solve_bytes(i2, r["c2_mx"]) + S * i2.bytes_spmv_f64
+                + solve_bytes(i3, r["c3_64"]) + solve_bytes(i3, r["c3_mx"]) + solve_bytes(i3, r["c3_probe"]))
+
+    log("warmup")
+    for _ in range(args.warmup):
+        step(False)
+    torch.cuda.synchronize()
+    log("timed steps")
+    step_ms, spmv_us, bytes_total = [], [], 0
+    rec = {k: [] for k in ("c2_64", "c2_mx", "c3_64", "c3_mx", "c3_probe")}
+    t_all = time.perf_counter()
+    for _ in range(args.steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = step(True)
+        torch.cuda.synchronize()
+        step_ms.append((time.perf_counter() - t0) * 1e3)
+        spmv_us.append(ev[0].elapsed_time(ev[1]) * 1e3 / S)
+        bytes_total += step_bytes(r)
+        for k in rec:
+            rec[k].append(r[k])
+    elapsed = time.perf_counter() - t_all
+    last = {k: v[-1] for k, v in rec.items()}
+
+    # the products of the C3 probe: an event pair around each launch
+    prod_ms = sum(x.product_ms for x in rec["c3_probe"])
+    prod_n = sum(x.product_launches for x in rec["c3_probe"])
+    prod_us = prod_ms * 1e3 / max(prod_n, 1)
+    achieved = i3.bytes_spmv_f64 / (prod_us * 1e-6) / 1e9
+
+    log("oracle checks of the last solutions")
+    res = {}
+    for cfg, A, b, M_info, xk in (("c2", A2, b2, i2, (x64_2, xmx_2)), ("c3", A3, b3, i3, (x64_3, xmx_3))):
+        bn = oracle.nrm2(b)
+        xg, xm = xk[0].cpu().numpy(), xk[1].cpu().numpy()
+        res[cfg] = (oracle.nrm2(b - oracle.spmv(A, xg)) / bn, oracle.nrm2(b - oracle.spmv(A, xm)) / bn,
+                    float(np.linalg.norm(xm - xg) / np.linalg.norm(xg)))
+
+    def solve_entry(cfg, info, lst64, lstmx):
+        t64 = [x.seconds for x in lst64]
+        tmx = [x.seconds for x in lstmx]
+        r64, rmx = lst64[-1], lstmx[-1]
+        m64, mmx = float(np.median(t64)), float(np.median(tmx))
+        return {
+            "fp64": {"solves_per_s": 1 / m64, "ms_p50": m64 * 1e3, "ms_p99": pct(t64, 99) * 1e3,
+                     "iterations": r64.iterations, "us_per_iter": m64 * 1e6 / max(r64.iterations, 1),
+                     "iter_gbps": info.bytes_pcg_iter_f64 * r64.iterations / m64 / 1e9,
+                     "solve_gbps": solve_bytes(info, r64) / m64 / 1e9,
+                     "true_rel_residual_oracle": res[cfg][0], "reason": spk.reason_str(r64.reason)},
+            "mixed": {"solves_per_s": 1 / mmx, "ms_p50": mmx * 1e3, "ms_p99": pct(tmx, 99) * 1e3,
+                      "inner_iterations": rmx.inner_iterations, "outer_steps": rmx.outer_steps,
+                      "fallback_fp64": rmx.fallback_fp64,
+                      "us_per_inner_iter": mmx * 1e6 / max(rmx.inner_iterations, 1),
+                      "solve_gbps": solve_bytes(info, rmx) / mmx / 1e9,
+                      "true_rel_residual_oracle": res[cfg][1], "error_vs_fp64": res[cfg][2],
+                      "reason": spk.reason_str(rmx.reason)},
+            "speedup_mixed_vs_fp64": m64 / mmx,
+        }
+
+    c2 = solve_entry("c2", i2, rec["c2_64"], rec["c2_mx"])
+    c3 = solve_entry("c3", i3, rec["c3_64"], rec["c3_mx"])
+
+    # C2 SpMV with a cold Infinity Cache: each launch after reading 1 GiB
+    log("cold SpMVs")
+    scratch = torch.zeros((1 << 30) // 8, dtype=torch.float64, device="cuda")
+    cold_us = []
+    for _ in range(args.cold_spmvs):
+        spk.cache_flush(scratch)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        spk.mat_mult(M2, xs2, ys2)
+        e1.record()
+        torch.cuda.synchronize()
+        cold_us.append(e0.elapsed_time(e1) * 1e3)
+    del scratch
+    warm = float(np.mean(spmv_us))
+    cold = float(np.mean(cold_us)) if cold_us else float("nan")
+    c2["spmv"] = {
+        "kernel": SPMV_KERNELS[spk.KERNEL_NAMES[i2.kernel]], "bytes": i2.bytes_spmv_f64,
+        "format_bytes": i2.format_bytes_spmv_f64,
+        "cold_us_avg": cold, "cold_gbps": i2.bytes_spmv_f64 / cold / 1e3,
+        "cold_frac": i2.bytes_spmv_f64 / cold / 1e3 / HBM_PEAK_GBS,
+        "warm_us_avg": warm, "warm_gbps": i2.bytes_spmv_f64 / warm / 1e3,
+        "warm_frac": i2.bytes_spmv_f64 / warm / 1e3 / HBM_PEAK_GBS,
+        "traffic_warm": traffic_from_profiles(SPMV_KERNELS[spk.KERNEL_NAMES[i2.kernel]] + "@c2",
+                                              i2.bytes_spmv_f64),
+        "note": "cold: an event pair around each launch after 1 GiB of scratch was read (the 182 MB SELL "
+                "layout no longer in the 256 MB Infinity Cache; includes one launch's dispatch); warm: one "
+                "event pair around the step's 100 back-to-back launches",
+    }
+
+    extras = None
+    if not args.no_extras:
+        log("extra legs (single reduction, Chebyshev, multi-RHS, multigrid)")
+        cheb, sr, multi, mg = c2_extra_legs(spk, M2, A2, b2, bd2, xs2, i2, args, c2["fp64"]["ms_p50"] * 1e-3)
+        extras = {"c2_single_reduction": sr, "c2_chebyshev": cheb, "c2_multi_rhs": multi, "c2_multigrid_pcg": mg}
+    M3.close()
+
+    serve = None
+    reqs_closed = []
+    if args.c5_seconds > 0 or args.c5_closed > 0:
+        serve = {}
+        if args.c5_seconds > 0:
+            reqs = spkgen.serve_stream(seed=0, rate=args.serve_rate, duration=args.c5_seconds)
+            log(f"served stream, open loop: {len(reqs)} requests over {args.c5_seconds:g} s")
+            serve["open_loop"] = serve_run(spk, reqs, False, args.graph_k)
+            serve["open_loop"]["workload"] = f"Poisson {args.serve_rate:g} req/s for {args.c5_seconds:g} s, seed 0"
+        if args.c5_closed > 0:
+            reqs_closed = spkgen.serve_stream(seed=0, rate=args.serve_rate, duration=60.0, count=args.c5_closed)
+            log(f"served stream, closed loop: {len(reqs_closed)} requests")
+            serve["closed_loop"] = serve_run(spk, reqs_closed, True, args.graph_k)
+            for name, prec, flags in (("mixed", spk.PREC_MIXED, spk.MAT_MIXED), ("fp64", spk.PREC_FP64, 0)):
+                log(f"one request at a time ({name})")
+                seq = sequential_run(spk, reqs_closed, prec, flags, args.graph_k)
+                seq["batching_gain"] = serve["closed_loop"]["solves_per_s"] / seq["solves_per_s"]
+                serve["closed_loop"]["sequential_" + name] = seq
+        serve["mix"] = SERVE_MIX
+
+    out = {
+        "metric": "CSR SpMV HBM GB/s; PCG solves/s to rtol 1e-8, FP64 vs mixed; p50/p99 lat",
+        "value": bytes_total / elapsed / 1e9,
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": float(np.mean(step_ms)),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64 (mixed solves: f32 inner / f64 outer)",
+        "data": "synthetic",
+        "config": {
+            "workload": ("step = C2 3D 7-point Laplacian 128^3 (n=2097152, nnz=14581760): FP64 and mixed "
+                         f"Jacobi-PCG to rtol 1e-8 + {S} FP64 SpMVs; C3 3D 27-point lognormal diffusion 160^3 "
+                         "(n=4096000, nnz=109215352): FP64 and mixed Jacobi-PCG to rtol 1e-8 + a "
+                         f"{P}-iteration FP64 PCG run with event-timed products; FP64 CSR int32, rhs "
+                         "uniform[-1,1) seed 0"),
+            "value": ("algorithmic HBM GB/s of the timed steps: SpMV 12nnz+4(n+1)+16n, PCG iteration "
+                      "12nnz+4(n+1)+88n, FP32 inner iteration 8nnz+4(n+1)+44n, refinement steps and "
+                      "setup/true-residual products, summed over the steps / their wall time"),
+            "c2_kernel": spk.KERNEL_NAMES[i2.kernel], "c3_kernel": spk.KERNEL_NAMES[i3.kernel],
+            "c3_kernel_param": i3.lanes, "graph_k": args.graph_k,
+        },
+        "c2": c2,
+        "c3": c3,
+        "c5_served": serve,
+        "roofline": {
+            "kernel": "k_pcg_spmv_sell_wide<double, short> + k_fin_pq<double> (C3 FP64 PCG product)",
+            "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": traffic_from_profiles("k_pcg_spmv_sell_wide<double, short>@c3", i3.bytes_spmv_f64),
+            "bytes_per_launch": i3.bytes_spmv_f64, "format_bytes_per_launch": i3.format_bytes_spmv_f64,
+            "us_avg": prod_us, "launches_timed": prod_n,
+            "note": "achieved = 12 nnz + 4(n+1) + 16n algorithmic bytes of one C3 FP64 product (q = A p with "
+                    "the p.q partials and their one-block fold) / its average duration: an event pair on "
+                    "the solve stream around each of the probe's product launches in the timed steps; the "
+                    "1.1 GB SELL layout is 4x the 256 MB Infinity Cache, so the bytes come from HBM",
+        },
+        "extras": extras,
+    }
+    if not args.no_cpu_baseline:
+        log("cpu baselines (oracle)")
+        A1 = spkgen.laplace2d5(64)
+        out["cpu_baseline"] = cpu_baselines(A1, A2, b2, i2, reqs_closed, args)
+    M2.close()
     return out
 
 
@@ -534,8 +868,8 @@ def bench_c4(args):
     import spkgen
     from paper_2011_00715_amd import spk
 
-    log("generating power-law n=4M")
-    A = spkgen.powerlaw_spd(4_000_000, seed=0)
+    log("generating power-law n=4M" + (f", columns within +-{args.c4_band}" if args.c4_band else ""))
+    A = spkgen.powerlaw_spd(4_000_000, seed=0, band=args.c4_band or None)
     log(f"nnz {A.nnz}; timing kernels")
     M = spk.mat_create_csr(dev(A.rowptr), dev(A.col), dev(A.val), flags=spk.MAT_MIXED)
     info = M.info
@@ -548,11 +882,19 @@ def bench_c4(args):
     rows = np.random.default_rng(0).integers(0, A.n, 2000)
     yo, ya = oracle.spmv_rows(A, xh, rows)
     res = {}
-    for name, k, p in [("sliced", spk.KERNEL_SLICED, 2048), ("sliced_lanes4", spk.KERNEL_SLICED, 4),
+    for name, k, p in [("auto", spk.KERNEL_AUTO, 0),
+                       ("sliced", spk.KERNEL_SLICED, 2048), ("sliced_lanes4", spk.KERNEL_SLICED, 4),
                        ("merge", spk.KERNEL_MERGE, 0),
                        ("vector32", spk.KERNEL_VECTOR, 32), ("vector8", spk.KERNEL_VECTOR, 8),
-                       ("stream", spk.KERNEL_STREAM, 0)]:
-        spk.mat_set_kernel(M, k, p)
+                       ("stream", spk.KERNEL_STREAM, 0), ("sell", spk.KERNEL_SELL, 0),
+                       ("sell_sigma_4096", spk.KERNEL_SELL_SIGMA, 4096),
+                       ("sell_sigma_65536", spk.KERNEL_SELL_SIGMA, 65536),
+                       ("sell_sigma_all", spk.KERNEL_SELL_SIGMA, (A.n + 63) // 64 * 64)]:
+        try:
+            spk.mat_set_kernel(M, k, p)
+        except spk.SpkError as e:
+            res[name] = {"refused": str(e)}
+            continue
         for _ in range(args.warmup + 1):
             spk.mat_mult(M, x, y)
         ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
@@ -572,15 +914,21 @@ def bench_c4(args):
             e1.record()
         torch.cuda.synchronize()
         us32 = float(np.median([e0.elapsed_time(e1) * 1e3 for e0, e1 in ev]))
+        mi = M.info
         res[name] = {"us": us, "gbps": info.bytes_spmv_f64 / us / 1e3, "max_err_rel_abs_sum": err,
-                     "f32_us": us32, "f32_gbps": info.bytes_spmv_f32 / us32 / 1e3}
+                     "f32_us": us32, "f32_gbps": info.bytes_spmv_f32 / us32 / 1e3,
+                     "kernel": spk.KERNEL_NAMES[mi.kernel], "param": mi.lanes,
+                     "stored_nnz": mi.stored_nnz, "format_bytes_f64": mi.format_bytes_spmv_f64,
+                     "format_gbps": mi.format_bytes_spmv_f64 / us / 1e3}
     out = {
         "metric": "CSR SpMV HBM GB/s (algorithmic), power-law rows",
-        "value": res[auto]["gbps"], "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": res[auto]["us"] / 1e3, "higher_is_better": True,
+        "value": res["auto"]["gbps"], "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": res["auto"]["us"] / 1e3, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": f"random SPD, n=4000000, nnz={info.nnz}, Zipf(1.8) row picks clipped "
-                               "to [3,4000], symmetric pattern", "auto_kernel": auto,
+                               "to [3,4000], symmetric pattern"
+                               + (f", columns within +-{args.c4_band} of the row" if args.c4_band else
+                                  ", uniform columns"), "auto_kernel": auto,
                    "row_mean": info.row_mean, "row_max": info.row_max, "row_cv": info.row_cv},
         "kernels": res,
         "bytes_f64": info.bytes_spmv_f64, "bytes_f32": info.bytes_spmv_f32,
@@ -588,41 +936,34 @@ def bench_c4(args):
                 "median launch time; the sliced family also moves 4(8n+1) row pointers and writes and "
                 "reads 8n partial products (format_bytes_f64)",
     }
-    spk.mat_set_kernel(M, spk.KERNEL_SLICED, 2048)
-    out["format_bytes_f64"] = M.info.format_bytes_spmv_f64
-    out["kernels"]["sliced"]["format_gbps"] = M.info.format_bytes_spmv_f64 / res["sliced"]["us"] / 1e3
     M.close()
     return out
 
 
-def bench_serve(args):
-    """Served solve stream: Poisson arrivals of shifted 2D/3D Laplacians."""
+def serve_run(spk, reqs, closed, graph_k, pinned_bytes=None):
+    """Serve `reqs` through one spk_server: open loop (each request submitted
+    at its arrival time) or closed (all queued at t = 0).  Latency = finish
+    - scheduled arrival (host clock).  The client forms each request before
+    it arrives (producer thread); patterns are built before the clock."""
+    import queue
+    import threading
+
     import numpy as np
 
     import spkgen
-    from paper_2011_00715_amd import spk
 
-    reqs = spkgen.serve_stream(seed=0, rate=args.serve_rate, duration=args.serve_seconds,
-                               count=args.serve_closed or None)
-    log(f"{len(reqs)} requests; building patterns")
-    for r in reqs:  # build the patterns before the clock starts
+    for r in reqs:
         spkgen.serve_matrix(r)
-    log("serving")
     opts = spk.server_opts_default()
     opts.hbm_budget_bytes = 32 << 30
     opts.max_slots = 64
     # pinned pool: room for the requests queued ahead of admission (a closed
     # loop queues them all at once: its host arrays, capped at 48 GiB)
-    need = sum(12 * spkgen.serve_matrix(r).nnz + 20 * spkgen.serve_matrix(r).n for r in reqs) if args.serve_closed else 0
-    opts.pinned_bytes = max(8 << 30, min(int(need * 1.05), 48 << 30))
-    opts.graph_k = args.graph_k
+    need = sum(12 * spkgen.serve_matrix(r).nnz + 20 * spkgen.serve_matrix(r).n for r in reqs) if closed else 0
+    opts.pinned_bytes = pinned_bytes or max(8 << 30, min(int(need * 1.05), 48 << 30))
+    opts.graph_k = graph_k
     S = spk.server_create(opts)
     o = spk.ksp_opts(precision=spk.PREC_MIXED)
-    import queue
-    import threading
-
-    # the client forms each request before it arrives (producer thread);
-    # latency is measured from the scheduled arrival time
     prepared = queue.Queue(maxsize=512)
 
     def producer():
@@ -634,7 +975,6 @@ def bench_serve(args):
     pending = {}
     lat, iters = [], []
     worst_rel = 0.0
-    closed = bool(args.serve_closed)
     if closed:  # queue everything at t = 0
         while prepared.qsize() < min(len(reqs), 512) and prepared.qsize() < len(reqs):
             time.sleep(0.01)
@@ -668,42 +1008,65 @@ def bench_serve(args):
             assert res.reason > 0, spk.reason_str(res.reason)
     elapsed = spk.now() - t0
     S.close()
+    return {"requests": len(lat), "seconds": elapsed, "solves_per_s": len(lat) / elapsed,
+            "latency_ms": {"p50": pct(lat, 50) * 1e3, "p99": pct(lat, 99) * 1e3, "max": max(lat) * 1e3},
+            "iterations_mean": float(np.mean(iters)), "worst_true_rel_residual": worst_rel}
+
+
+def sequential_run(spk, reqs, prec, flags, graph_k):
+    """The same requests one at a time through spk_ksp_solve (matrix upload,
+    solve, x back to the host); input formation is not timed."""
+    import torch
+
+    import spkgen
+
+    os_ = spk.ksp_opts(graph_k=graph_k, precision=prec)
+    tseq = 0.0
+    for r in reqs:
+        A = spkgen.serve_matrix(r)
+        b = spkgen.rhs_uniform(A.n, r.rhs_seed % (2**31))
+        ts = spk.now()
+        M = spk.mat_create_csr(A.rowptr, A.col, A.val, flags=flags)
+        x = torch.zeros(A.n, dtype=torch.float64, device="cuda")
+        res = spk.ksp_solve(M, dev(b), x, os_)
+        x.cpu()
+        M.close()
+        tseq += spk.now() - ts
+        assert res.reason > 0
+    return {"solves_per_s": len(reqs) / tseq, "seconds": tseq}
+
+
+SERVE_MIX = "2D 5-point side 32-256 / 3D 7-point side 16-96, diagonal shift U[0,1), rhs U[-1,1)"
+
+
+def bench_serve(args):
+    """Served solve stream: Poisson arrivals of shifted 2D/3D Laplacians."""
+    import spkgen
+    from paper_2011_00715_amd import spk
+
+    reqs = spkgen.serve_stream(seed=0, rate=args.serve_rate, duration=args.serve_seconds,
+                               count=args.serve_closed or None)
+    log(f"{len(reqs)} requests; serving")
+    closed = bool(args.serve_closed)
+    run = serve_run(spk, reqs, closed, args.graph_k)
     seq = None
     if closed:
-        # the same requests one at a time through spk_ksp_solve (matrix
-        # upload, solve, x back to the host): mixed precision as served, and
-        # plain FP64, for the batching gain
-        import torch
-
+        # mixed precision as served, and plain FP64, for the batching gain
         seq = {}
         for name, prec, flags in (("mixed", spk.PREC_MIXED, spk.MAT_MIXED), ("fp64", spk.PREC_FP64, 0)):
             log(f"sequential baseline ({name})")
-            os_ = spk.ksp_opts(graph_k=args.graph_k, precision=prec)
-            tseq = 0.0
-            for r in reqs:
-                A = spkgen.serve_matrix(r)  # input formation is not timed (as for the server)
-                b = spkgen.rhs_uniform(A.n, r.rhs_seed % (2**31))
-                ts = spk.now()
-                M = spk.mat_create_csr(A.rowptr, A.col, A.val, flags=flags)
-                x = torch.zeros(A.n, dtype=torch.float64, device="cuda")
-                res = spk.ksp_solve(M, dev(b), x, os_)
-                x.cpu()
-                M.close()
-                tseq += spk.now() - ts
-                assert res.reason > 0
-            seq[name] = {"solves_per_s": len(reqs) / tseq, "seconds": tseq,
-                         "batching_gain": (len(lat) / elapsed) / (len(reqs) / tseq)}
+            seq[name] = sequential_run(spk, reqs, prec, flags, args.graph_k)
+            seq[name]["batching_gain"] = run["solves_per_s"] / seq[name]["solves_per_s"]
     return {
         "metric": "served PCG solves/s to rtol 1e-8; p50/p99 latency",
-        "value": len(lat) / elapsed, "unit": "solves/s", "n_gpus": 1, "steps": len(lat),
-        "warmup": 0, "ms_per_step": elapsed * 1e3 / max(len(lat), 1), "higher_is_better": True,
+        "value": run["solves_per_s"], "unit": "solves/s", "n_gpus": 1, "steps": run["requests"],
+        "warmup": 0, "ms_per_step": run["seconds"] * 1e3 / max(run["requests"], 1), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32 inner / f64 outer", "data": "synthetic",
         "config": {"workload": ("closed loop: %d requests queued at t=0" % len(reqs)) if closed else
                    f"open loop: Poisson {args.serve_rate:g} req/s for {args.serve_seconds:g} s",
-                   "requests": len(reqs), "mix": "2D 5-point side 32-256 / 3D 7-point side 16-96, "
-                   "diagonal shift U[0,1), rhs U[-1,1)", "graph_k": args.graph_k},
-        "latency_ms": {"p50": pct(lat, 50) * 1e3, "p99": pct(lat, 99) * 1e3, "max": max(lat) * 1e3},
-        "iterations_mean": float(np.mean(iters)), "worst_true_rel_residual": worst_rel,
+                   "requests": len(reqs), "mix": SERVE_MIX, "graph_k": args.graph_k},
+        "latency_ms": run["latency_ms"], "iterations_mean": run["iterations_mean"],
+        "worst_true_rel_residual": run["worst_true_rel_residual"],
         "sequential": seq,
     }
 
@@ -798,7 +1161,7 @@ def main():
         sys.exit(1)
     torch.cuda.set_device(0)
     calibration_copy()
-    fn = {"c2": bench_c2, "c3": bench_c3, "c4": bench_c4, "serve": bench_serve,
+    fn = {"all": bench_all, "c2": bench_c2, "c3": bench_c3, "c4": bench_c4, "serve": bench_serve,
           "spectrum": bench_spectrum, "mg": bench_mg}[args.workload]
     out = fn(args)
     print(json.dumps(out), flush=True)

@@ -132,9 +132,15 @@ def load(path: str | None = None):
     lib.orc_mg_galerkin.restype = ctypes.c_int64
     lib.orc_mg_restrict.argtypes = [i32, P, P, P]
     lib.orc_mg_prolong.argtypes = [i32, P, d, P, P]
+    lib.orc_threads.restype = ctypes.c_int
     if path is None:
         _lib = lib
     return lib
+
+
+def threads(lib=None) -> int:
+    """Threads the library's loops run on (1 for the serial build)."""
+    return int((lib or load()).orc_threads())
 
 
 def _ptr(a: np.ndarray):

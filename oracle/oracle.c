@@ -49,6 +49,20 @@
 #include "oracle.h"
 
 #ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* Threads the loops run on: 1 in the serial build. */
+int orc_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+#ifdef _OPENMP
 #define ORC_CHUNK 32768
 /* sum_i x_i y_i over fixed chunks (parallel build only). */
 static long double chunked_dot(int32_t n, const double *x, const double *y)

@@ -77,5 +77,7 @@ int64_t orc_mg_galerkin(int32_t n, const int32_t *rowptr, const int32_t *col,
 void orc_mg_restrict(int32_t dim, const int32_t *shape, const double *r, double *bc);
 void orc_mg_prolong(int32_t dim, const int32_t *shape, double omega, const double *xc,
                     double *x);
+/* Threads of the parallel build's loops (1 in the serial build). */
+int orc_threads(void);
 
 #endif
