@@ -229,13 +229,15 @@ int spk_mat_mult_multi(const spk_mat *A, int32_t k, const double *X, double *Y, 
     if (!X || !Y) { set_error("NULL X or Y"); return SPK_EINVAL; }
     const size_t nk = (size_t)A->n * k;
     if (X < Y + nk && Y < X + nk) { set_error("X and Y must not overlap"); return SPK_EINVAL; }
-    const MultiDesc d = multi_desc(A, k);
+    MultiDesc d = multi_desc(A, k);
+    // SELL: up to one wavefront per slice (no partial sums to keep per block)
+    if (d.sell) d.nblk = std::max(1, std::min(ceil_div(ceil_div(A->n, kSell), kBlock / kWave), 16384));
     hipStream_t s = (hipStream_t)stream;
     A->stream = s;
     with_multi(A, k, [&](auto ct, auto kc) {
         using CI = decltype(ct);
         constexpr int K = decltype(kc)::value;
-        hipLaunchKernelGGL((k_spmm<CI, K>), dim3(multi_nblk(A)), dim3(kBlock), 0, s, d, X, Y);
+        hipLaunchKernelGGL((k_spmm<CI, K>), dim3(d.nblk), dim3(kBlock), 0, s, d, X, Y);
     });
     SPK_HIP(hipGetLastError());
     return SPK_OK;
