@@ -940,11 +940,15 @@ def bench_c4(args):
     return out
 
 
+SERVE_CLIENTS = 8  # client threads submitting to the server
+
+
 def serve_run(spk, reqs, closed, graph_k, pinned_bytes=None):
     """Serve `reqs` through one spk_server: open loop (each request submitted
     at its arrival time) or closed (all queued at t = 0).  Latency = finish
     - scheduled arrival (host clock).  The client forms each request before
-    it arrives (producer thread); patterns are built before the clock."""
+    it arrives (producer thread); patterns are built before the clock.
+    SERVE_CLIENTS client threads submit, the main thread drives the server."""
     import queue
     import threading
 
@@ -972,40 +976,70 @@ def serve_run(spk, reqs, closed, graph_k, pinned_bytes=None):
             prepared.put((r, A, spkgen.rhs_uniform(A.n, r.rhs_seed % (2**31))))
 
     threading.Thread(target=producer, daemon=True).start()
-    pending = {}
-    lat, iters = [], []
-    worst_rel = 0.0
     if closed:  # queue everything at t = 0
         while prepared.qsize() < min(len(reqs), 512) and prepared.qsize() < len(reqs):
             time.sleep(0.01)
+    # client threads submit the requests at their arrival times (the copy of
+    # a large system runs there, outside the server's lock, and a small
+    # request is not held behind a large one's copy) while this thread keeps
+    # the GPU fed: progress, the completion queue, collection
+    lock, take = threading.Lock(), threading.Lock()
+    pending, early, err = {}, [], []
+    lat, iters = [], []
+    worst_rel = 0.0
+    old_si = sys.getswitchinterval()
+    sys.setswitchinterval(0.0005)
     t0 = spk.now()
-    i = 0
-    nxt = None
-    while i < len(reqs) or pending:
-        now = spk.now() - t0
-        for _ in range(16):  # interleave submissions with progress
-            if i >= len(reqs):
-                break
-            if nxt is None:
-                try:
-                    nxt = prepared.get(block=closed)
-                except queue.Empty:
-                    break
-            r, A, b = nxt
-            if not closed and r.t_arrival > now:
-                break
-            t_arr = t0 + (0.0 if closed else r.t_arrival)
-            pending[spk.server_submit(S, A.rowptr, A.col, A.val, b, o)] = (t_arr, A.n)
-            nxt = None
-            i += 1
-        spk.server_progress(S, 1)
-        for t in spk.server_completed(S):  # the completion queue: poll only finished requests
-            t_arr, n = pending.pop(t)
-            res, tdone = spk.server_poll(S, t, np.empty(n))
-            lat.append(tdone - t_arr)
-            iters.append(res.inner_iterations + res.iterations)
-            worst_rel = max(worst_rel, res.true_rel_residual)
-            assert res.reason > 0, spk.reason_str(res.reason)
+
+    def submitter():
+        try:
+            while True:
+                with take:  # the next arrival, in order
+                    if not left_to_take[0]:
+                        return
+                    left_to_take[0] -= 1
+                    r, A, b = prepared.get()
+                if not closed:
+                    delay = r.t_arrival - (spk.now() - t0)
+                    if delay > 0:
+                        time.sleep(delay)
+                t_arr = t0 + (0.0 if closed else r.t_arrival)
+                t = spk.server_submit(S, A.rowptr, A.col, A.val, b, o)
+                with lock:
+                    pending[t] = (t_arr, A.n)
+        except BaseException as e:  # noqa: BLE001 - re-raised on the main thread
+            err.append(e)
+
+    left_to_take = [len(reqs)]
+    ths = [threading.Thread(target=submitter, daemon=True) for _ in range(SERVE_CLIENTS)]
+    for th in ths:
+        th.start()
+    try:
+        while len(lat) < len(reqs):
+            if err:
+                raise err[0]
+            left = spk.server_progress(S, 1)
+            done = spk.server_completed(S)
+            if early:  # finished before the client thread recorded the ticket
+                done, early = early + done, []
+            for t in done:
+                with lock:
+                    ent = pending.pop(t, None)
+                if ent is None:
+                    early.append(t)
+                    continue
+                t_arr, n = ent
+                res, tdone = spk.server_poll(S, t, np.empty(n))
+                lat.append(tdone - t_arr)
+                iters.append(res.inner_iterations + res.iterations)
+                worst_rel = max(worst_rel, res.true_rel_residual)
+                assert res.reason > 0, spk.reason_str(res.reason)
+            if left == 0 and not done:
+                time.sleep(5e-5)
+    finally:
+        sys.setswitchinterval(old_si)
+    for th in ths:
+        th.join()
     elapsed = spk.now() - t0
     S.close()
     return {"requests": len(lat), "seconds": elapsed, "solves_per_s": len(lat) / elapsed,

@@ -481,7 +481,12 @@ void spk_server_opts_default(spk_server_opts *o);
 int spk_server_create(const spk_server_opts *o, void *stream, spk_server **out);
 
 /* Submit A x = b from host CSR (copied before return).  opts may be NULL.
- * ticket: out, identifies the request.  SPK_EBUDGET if it can never fit. */
+ * ticket: out, identifies the request.  SPK_EBUDGET if it can never fit.
+ * Thread safety (the exception to the one-thread-per-handle rule): the
+ * server calls serialise on a lock inside the server, and submit validates
+ * and copies the system outside it, so client threads may submit while one
+ * service thread calls spk_server_progress / completed / poll; the copy of
+ * a large system (tens of MB) then does not hold back the batched steps. */
 int spk_server_submit(spk_server *s, int32_t n, int64_t nnz, const int32_t *rowptr,
                       const int32_t *colind, const double *values, const double *b,
                       const spk_ksp_opts *opts, uint64_t *ticket);
