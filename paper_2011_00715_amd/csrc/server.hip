@@ -180,11 +180,13 @@ namespace spk {
 
 static int64_t align256(int64_t b) { return (b + 255) & ~int64_t(255); }
 
-// A served system gets the SELL-64 product (int16 offsets) from this many
-// rows on, when its rows are short (<= 64), its slices pad by at most 15 %
-// and every |col - row| fits int16; smaller systems are launch-bound and keep
-// the stream-tile product, which needs no extra layout.
-constexpr int32_t kServeSellRows = 1 << 16;
+// A served system gets the SELL-64 product (int16 offsets) when its rows are
+// short (<= 64), its slices pad by at most 15 % and every |col - row| fits
+// int16, whatever its size: when every active system takes the same product
+// kernel, an iteration of the batched step is three launches instead of four
+// (the stream-tile section then holds only the systems SELL cannot take).
+// Launches, not bytes, bound the small systems, so the layout's build at
+// admission (two small kernels) pays for itself within a step.
 
 static int sell_plain_bits(int64_t stored, int nslices, int n)
 {
@@ -437,6 +439,12 @@ static int admit_queued(spk_server *S)
     return SPK_OK;
 }
 
+// Bytes of a batched table of max_slots ms.
+static size_t table_bytes(int ms)
+{
+    return sizeof(SysDesc) * 3 * (size_t)ms + sizeof(int32_t) * 3 * ((size_t)ms + 1);
+}
+
 static int rebuild_table(spk_server *S)
 {
     const int i = S->table_buf;
@@ -476,13 +484,9 @@ static int rebuild_table(spk_server *S)
     S->u_sl = u;
     S->n_mixed = nm;
     S->n_fp64 = nf;
-    for (int c = 0; c < 3; ++c) {
-        if (!ns[c]) continue;
-        SPK_HIP(hipMemcpyAsync(S->d_table + c * ms, pt + c * ms, sizeof(SysDesc) * ns[c], hipMemcpyHostToDevice,
-                               S->s));
-        SPK_HIP(hipMemcpyAsync(S->d_blk + c * (ms + 1), pb + c * (ms + 1), sizeof(int32_t) * (ns[c] + 1),
-                               hipMemcpyHostToDevice, S->s));
-    }
+    // one upload of the whole table (each copy on the compute stream is a
+    // blit kernel of its own: one instead of up to six per rebuild)
+    SPK_HIP(hipMemcpyAsync(S->d_table, pt, table_bytes(ms), hipMemcpyHostToDevice, S->s));
     SPK_HIP(hipEventRecord(S->ev_table[i], S->s));
     S->table_dirty = false;
     return SPK_OK;
@@ -744,8 +748,11 @@ int spk_server_create(const spk_server_opts *opts, void *stream, spk_server **ou
     chk(hipMalloc(&S->d_states, sizeof(SysState) * ms), "states");
     chk(hipMalloc(&S->d_slotdesc, sizeof(SysDesc) * ms), "slot descs");
     chk(hipMalloc(&S->d_slotblk, sizeof(int32_t) * 2 * ms), "slot blocks");
-    chk(hipMalloc(&S->d_table, sizeof(SysDesc) * 3 * ms), "table");
-    chk(hipMalloc(&S->d_blk, sizeof(int32_t) * 3 * (ms + 1)), "table blocks");
+    // batched table: 3 ms descriptors, then 3 (ms + 1) block starts, in one
+    // buffer so that a rebuild is one upload
+    const size_t tbytes = table_bytes((int)ms);
+    chk(hipMalloc(&S->d_table, tbytes), "table");
+    if (S->d_table) S->d_blk = (int32_t *)(S->d_table + 3 * ms);
     chk(hipHostMalloc((void **)&S->p_slotdesc, sizeof(SysDesc) * ms, hipHostMallocDefault), "pinned descs");
     chk(hipHostMalloc((void **)&S->p_slotblk, sizeof(int32_t) * 2 * ms, hipHostMallocDefault), "pinned blocks");
     chk(hipHostMalloc((void **)&S->p_slotstate, sizeof(SysState) * ms, hipHostMallocDefault), "pinned states");
@@ -758,9 +765,8 @@ int spk_server_create(const spk_server_opts *opts, void *stream, spk_server **ou
         chk(hipEventCreateWithFlags(&S->ev_stage[i], hipEventDisableTiming), "event");
     }
     for (int i = 0; i < kTableRing; ++i) {
-        chk(hipHostMalloc((void **)&S->p_table[i], sizeof(SysDesc) * 3 * ms, hipHostMallocDefault), "pinned table");
-        chk(hipHostMalloc((void **)&S->p_blk[i], sizeof(int32_t) * 3 * (ms + 1), hipHostMallocDefault),
-            "pinned blocks");
+        chk(hipHostMalloc((void **)&S->p_table[i], tbytes, hipHostMallocDefault), "pinned table");
+        if (S->p_table[i]) S->p_blk[i] = (int32_t *)(S->p_table[i] + 3 * ms);
         chk(hipEventCreateWithFlags(&S->ev_table[i], hipEventDisableTiming), "event");
     }
     for (auto &sl : S->slots) {
@@ -829,7 +835,7 @@ int spk_server_submit(spk_server *S, int32_t n, int64_t nnz, const int32_t *rowp
         if (maxtile[t] <= TileLds<double>::kCap) { q->R = kTileRs[t]; break; }
     q->ntiles = ceil_div(n, q->R);
     q->nblk = pick_nblk(q->ntiles, S->o.max_blocks_per_system);
-    if (n >= kServeSellRows) {
+    {
         // slice widths from the row pointers; the offsets are checked below
         const int32_t ns = ceil_div(n, kSell);
         int64_t acc = 0;
@@ -1088,7 +1094,6 @@ int spk_server_destroy(spk_server *S)
     }
     for (int i = 0; i < kTableRing; ++i) {
         hipHostFree(S->p_table[i]);
-        hipHostFree(S->p_blk[i]);
         if (S->ev_table[i]) hipEventDestroy(S->ev_table[i]);
     }
     hipHostFree(S->p_slotdesc);
@@ -1102,7 +1107,6 @@ int spk_server_destroy(spk_server *S)
     hipFree(S->d_slotdesc);
     hipFree(S->d_slotblk);
     hipFree(S->d_table);
-    hipFree(S->d_blk);
     delete S;
     return SPK_OK;
 }

@@ -136,14 +136,16 @@ def test_server_midflight_admission_alone_equals_batch(prec):
 
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
 def test_server_large_systems_sell_product(prec):
-    """Systems of at least 65,536 rows take the SELL-64 product (layout built
-    on the device at admission), beside small ones on stream tiles in the same
-    batch: every result meets the oracle's true residual and is bitwise the
-    one the same request gets alone."""
+    """Systems with short rows take the SELL-64 product (layout built on the
+    device at admission), whatever their size; a power-law system (rows far
+    over 64 entries) takes the stream-tile product in the same batch, so
+    both product sections run in one step.  Every result meets the oracle's
+    true residual and is bitwise the one the same request gets alone."""
     spk = need_gpu()
     p = spk.PREC_FP64 if prec == "fp64" else spk.PREC_MIXED
     items = [(None, spkgen.laplace2d5(260, shift=0.3), None), (None, spkgen.laplace3d7(42, shift=0.2), None),
-             (None, spkgen.laplace2d5(30, shift=0.1), None), (None, spkgen.laplace3d7(12, shift=0.5), None)]
+             (None, spkgen.laplace2d5(30, shift=0.1), None), (None, spkgen.laplace3d7(12, shift=0.5), None),
+             (None, spkgen.powerlaw_spd(20000, seed=2), None)]
     items = [(r, A, spkgen.rhs_uniform(A.n, 11 + i)) for i, (r, A, _) in enumerate(items)]
     S = spk.server_create()
     mixed = _run(spk, S, items, p)
