@@ -471,9 +471,9 @@ def bench_c2(args):
 def wide_product(info):
     """Whether the PCG runs the one-wavefront-per-slice SELL product (the
     library's rule: more than 96 stored entries per lane of a grid of
-    min(2048, ceil(n / 256)) blocks, rounded down to a multiple of 8)."""
+    min(1024, ceil(n / 256)) blocks, rounded down to a multiple of 8)."""
     tiles = (info.n + 255) // 256
-    nblk = tiles if tiles < 8 else min(tiles, 2048) - min(tiles, 2048) % 8
+    nblk = tiles if tiles < 8 else min(tiles, 1024) - min(tiles, 1024) % 8
     return info.kernel == 4 and info.stored_nnz > 96 * 256 * nblk  # 4 = SPK_KERNEL_SELL
 
 
@@ -668,16 +668,17 @@ def bench_all(args):
         "c3": c3,
         "c5_served": serve,
         "roofline": {
-            "kernel": "k_pcg_spmv_sell_wide<double, short> + k_fin_pq<double> (C3 FP64 PCG product)",
+            "kernel": "k_pcg_spmv_sell_wide<double, short> (C3 FP64 PCG product q = A p with p.q partials)",
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": traffic_from_profiles("k_pcg_spmv_sell_wide<double, short>@c3", i3.bytes_spmv_f64),
             "bytes_per_launch": i3.bytes_spmv_f64, "format_bytes_per_launch": i3.format_bytes_spmv_f64,
             "us_avg": prod_us, "launches_timed": prod_n,
             "note": "achieved = 12 nnz + 4(n+1) + 16n algorithmic bytes of one C3 FP64 product (q = A p with "
-                    "the p.q partials and their one-block fold) / its average duration: an event pair on "
-                    "the solve stream around each of the probe's product launches in the timed steps; the "
-                    "1.1 GB SELL layout is 4x the 256 MB Infinity Cache, so the bytes come from HBM",
+                    "the per-block p.q partials) / its average duration: an event pair on the solve stream "
+                    "around each of the probe's product kernels in the timed steps (the one-block fold of the "
+                    "partials, about 4.6 us, runs after the pair); the 1.1 GB SELL layout is 4x the 256 MB "
+                    "Infinity Cache, so the bytes come from HBM",
         },
         "extras": extras,
     }

@@ -311,8 +311,11 @@ typedef struct {
                                   per iteration instead of three (default 0) */
     int32_t profile;      /* 1: time the SpMV product of every iteration (FP64,
                              or FP32 inner for mixed) with a HIP event pair on
-                             `stream`; kernels are then launched one
-                             iteration at a time without graphs.  Results in
+                             `stream` (around the product kernel; the
+                             one-wavefront-per-slice SELL product's one-block
+                             fold of its partials is outside the pair);
+                             kernels are then launched one iteration at a
+                             time without graphs.  Results in
                              spk_ksp_result.product_*.  Not with
                              single_reduction (default 0) */
 } spk_ksp_opts;

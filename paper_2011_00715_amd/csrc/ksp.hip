@@ -237,6 +237,12 @@ static int enqueue_iteration(spk_mat *A, Workspace *w, hipStream_t s)
             if (A->sell_cw == 2) hipLaunchKernelGGL((k_pcg_spmv_sell_wide<V, int16_t, U>), gw, t, 0, s, b, w->wpart);
             else hipLaunchKernelGGL((k_pcg_spmv_sell_wide<V, int32_t, U>), gw, t, 0, s, b, w->wpart);
         });
+        // the pair times the slice kernel, which moves the bytes; the fold
+        // of its per-block partials (one block, a few microseconds) is outside
+        if (e1) {
+            SPK_HIP(hipEventRecord(e1, s));
+            e1 = nullptr;
+        }
         hipLaunchKernelGGL((k_fin_pq<V>), one, dim3(kFinPqThreads), 0, s, b, (const double *)w->wpart, w->nwpart);
     } else if (A->kernel == SPK_KERNEL_SELL) {
         with_sell_u(A->sell_u, [&](auto uc) {
