@@ -55,6 +55,13 @@ struct SysState {
     // the scalars of the current iteration as the update pass saw them: the
     // p/x pass decides from these while its block 0 rewrites the live ones
     int32_t snap_status, snap_phase, snap_iter, snap_inner_iter;
+    // fused p/x + product kernel (F): p lives in one of two buffers, pbuf
+    // (written by F's block 0) naming the current one; snap_pbuf is the
+    // copy F's blocks read.  snap_mode says what the next F does: 1 take the
+    // decision recorded by the update pass, then (while iterating) the
+    // product with p = z + beta p; 0 start: p = z; 3 continue after a
+    // reliable update: p = z + beta p with beta from the refinement
+    int32_t pbuf, snap_pbuf, snap_mode, pad_f;
     double scale;         // mixed: r32 = r / scale, x += scale d
     double rho, alpha, beta, eta;
     double rnorm, rnorm0, bnorm, thresh, rtol, atol;
@@ -81,6 +88,8 @@ struct SysDesc {
     double *x;
     double *r, *z, *p, *q;            // FP64 Krylov vectors
     float *r32, *z32, *p32, *q32, *d32;  // FP32 inner vectors (mixed)
+    double *p2;                       // second p buffer of the fused kernels
+    float *p2_32;                     //   (null: the three-kernel iteration)
     double *partials;                 // kNumPart * nblk
     SysState *st;
     double *hist;                     // device history (hist_len) or null

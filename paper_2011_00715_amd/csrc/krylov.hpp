@@ -19,6 +19,8 @@
 //       and takes the same decision from the recorded scalars (convergence
 //       and breakdown tests, beta); block 0 stores it; then x += alpha p and,
 //       while iterating, p = z + beta p
+// Systems with the SELL product on the persistent grid fuse C into the next
+// iteration's A (kernel F, see k_pcg_fused_sell): two kernels per iteration.
 // Scalars live on the device and every kernel is a no-op once its system has
 // stopped, so a captured graph of many iterations replays without host round
 // trips (Challenge A1: fusion, graphs, pipelining).
@@ -50,6 +52,7 @@ template <> struct Vecs<double> {
     __device__ static double *p(const SysDesc &d) { return d.p; }
     __device__ static double *q(const SysDesc &d) { return d.q; }
     __device__ static double *x(const SysDesc &d) { return d.x; }
+    __device__ static double *p2(const SysDesc &d) { return d.p2; }
     __device__ static bool present(const SysDesc &) { return true; }
     static constexpr int gate = kGateInner64;
     static constexpr int mixed = 0;
@@ -62,6 +65,7 @@ template <> struct Vecs<float> {
     __device__ static float *p(const SysDesc &d) { return d.p32; }
     __device__ static float *q(const SysDesc &d) { return d.q32; }
     __device__ static float *x(const SysDesc &d) { return d.d32; }
+    __device__ static float *p2(const SysDesc &d) { return d.p2_32; }
     // FP64 systems of a mixed batch have no FP32 vectors
     __device__ static bool present(const SysDesc &d) { return d.r32 != nullptr; }
     static constexpr int gate = kGateInner32;
@@ -211,6 +215,10 @@ static __global__ void k_state_init(SysState *st, double rtol, double atol, int 
     st->inner_thresh = 0.0;
     st->s = st->s_prev = 0.0;
     st->rnorm_true = 0.0;
+    // fused iteration: p in buffer 0, nothing to start or decide yet
+    st->pbuf = st->snap_pbuf = 0;
+    st->snap_mode = 1;
+    st->snap_status = SPK_DIVERGED_BREAKDOWN;
 }
 
 // Restart from the true residual already in r (FP64 solves).
@@ -438,6 +446,8 @@ __global__ __launch_bounds__(kBlock) void k_fin_setup64(B a)
     else if (RZ == 0.0) st->status = SPK_DIVERGED_BREAKDOWN;
     else if (st->iter >= st->maxit) { st->status = SPK_DIVERGED_ITS; st->rho = RZ; }
     else st->rho = RZ;
+    st->snap_mode = 0;  // the fused iteration starts with p = z
+    st->snap_pbuf = st->pbuf;
 }
 
 __device__ __forceinline__ bool in_phase(const SysState *st, int phase)
@@ -508,11 +518,14 @@ __global__ __launch_bounds__(kBlock) void k_fin_setup32(B a)
     else if (RZ < 0.0) st->status = SPK_DIVERGED_INDEFINITE_PC;
     else if (RZ == 0.0) st->status = SPK_DIVERGED_BREAKDOWN;
     else {
+        st->snap_mode = 0;  // fused iteration: p32 = z32 ...
         if (st->ru && !st->fresh_p) {
             // reliable update: continue the same CG with the true residual
             st->beta = RZ / st->rho;
-            st->cmode = 3;  // p32 = z32 + beta p32 before the next SpMV
+            st->cmode = 3;      // p32 = z32 + beta p32 before the next SpMV
+            st->snap_mode = 3;  // ... or the same inside the fused product
         }
+        st->snap_pbuf = st->pbuf;
         st->fresh_p = 0;
         st->rho = RZ;
         st->phase = kPhaseInner;
@@ -619,8 +632,8 @@ __global__ __launch_bounds__(kBlock) void k_pcg_spmv_sell_wide(One a, double *__
 }
 
 // The wide A's nw partials summed into slot 0 of the p.q partials and zeros
-// into the other nblk - 1 slots, so that the update pass and F_B, which sum
-// those slots, both get exactly this sum.  One block of 1024 threads: lane t
+// into the other nblk - 1 slots, so that the update pass, which sums those
+// slots, gets exactly this sum.  One block of 1024 threads: lane t
 // sums partials t, t + 1024, ... in order, then the 16 wave sums in order
 // (a 256-thread block took 6.6 us for the 16,000 partials of C3).
 constexpr int kFinPqThreads = 1024;
@@ -714,6 +727,8 @@ __global__ __launch_bounds__(kBlock) void k_pcg_update(B a)
                 w->snap_inner_iter = st->inner_iter;
                 w->snap_rho = rho;
                 w->snap_eta = eta;
+                w->snap_mode = 1;
+                w->snap_pbuf = st->pbuf;
             }
             if (!gate_ok(g, Vecs<V>::gate) || !(eta > 0.0) || !finite(eta)) return false;
             nalpha = (V)(-(rho / eta));
@@ -782,6 +797,78 @@ __device__ __forceinline__ Step pcg_decide(int mixed, int iter, int inner_iter, 
     return t;
 }
 
+// The scalars B recorded for the decision of its iteration (read by C / F,
+// whose block 0 rewrites only the live fields).
+struct Snap {
+    int mixed;
+    Gate g;
+    int iter, inner_iter;
+    double rho, eta;
+};
+
+__device__ __forceinline__ Snap load_snap(const SysState *st)
+{
+    Snap s;
+    s.mixed = st->mixed;
+    s.g = Gate{st->snap_status, st->snap_phase, s.mixed};
+    s.iter = st->snap_iter;
+    s.inner_iter = st->snap_inner_iter;
+    s.rho = st->snap_rho;
+    s.eta = st->snap_eta;
+    return s;
+}
+
+// Block 0 of C / F: store decision t into the live fields.
+__device__ __forceinline__ void pcg_store(SysState *st, const SysDesc &d, const Snap &sn, const Step &t,
+                                          double RZ)
+{
+    st->cmode = 0;  // a pending p continuation has been served
+    st->eta = sn.eta;
+    if (t.status != SPK_RUNNING) st->status = t.status;
+    if (t.to_update) {
+        st->phase = kPhaseUpdate;
+        if (t.fresh_p) st->fresh_p = 1;
+    }
+    if (sn.eta > 0.0 && finite(sn.eta)) {
+        const int k = sn.iter + 1;
+        st->alpha = t.alpha;
+        st->iter = k;
+        if (sn.mixed) st->inner_iter = sn.inner_iter + 1;
+        else {
+            st->rnorm = t.rn;
+            if (d.hist && k < st->hist_len) d.hist[k] = t.rn;
+        }
+        if (t.cmode == 2) {
+            st->beta = t.beta;
+            st->rho = RZ;
+        }
+    }
+}
+
+// B's r.z and r.r partial sums, identical in every block: loads first
+// (before the caller's row loads), sums later.
+struct RzRr {
+    double vz[kPartChunk], vr[kPartChunk];
+    bool one_chunk;
+    __device__ __forceinline__ void load(const SysDesc &d)
+    {
+        one_chunk = d.nblk <= kBlock * kPartChunk;
+        if (one_chunk) {
+            partials_load(d.partials + kPartRz * d.nblk, d.nblk, vz);
+            partials_load(d.partials + kPartRr * d.nblk, d.nblk, vr);
+        }
+    }
+    __device__ __forceinline__ void sum(const SysDesc &d, double *red, double &RZ, double &RR)
+    {
+        if (one_chunk) {
+            RZ = partials_sum(vz, red);
+            RR = partials_sum(vr, red);
+        } else {
+            reduce_partials2(d.partials + kPartRz * d.nblk, d.partials + kPartRr * d.nblk, d.nblk, red, RZ, RR);
+        }
+    }
+};
+
 // C: the iteration's decision (see pcg_decide), stored by block 0, then
 // x += alpha p (d for mixed) and, while iterating, p = z + beta p.
 template <class V, class B>
@@ -791,64 +878,26 @@ __global__ __launch_bounds__(kBlock) void k_pcg_px(B a)
     int j;
     SysDesc d;
     if (!locate(a, j, d)) return;
-    if (!Vecs<V>::present(d)) return;
+    if (!Vecs<V>::present(d) || Vecs<V>::p2(d)) return;  // fused systems: F does it
     SysState *st = d.st;
     int rb, re;
     row_range(d, j, rb, re);
     V *__restrict__ x = Vecs<V>::x(d);
     V *__restrict__ p = Vecs<V>::p(d);
     const V *__restrict__ z = Vecs<V>::z(d);
-    const double *prz = d.partials + kPartRz * d.nblk;
-    const double *prr = d.partials + kPartRr * d.nblk;
-    const bool one_chunk = d.nblk <= kBlock * kPartChunk;
-    double vz[kPartChunk], vr[kPartChunk];
-    if (one_chunk) {
-        partials_load(prz, d.nblk, vz);
-        partials_load(prr, d.nblk, vr);
-    }
+    RzRr part;
+    part.load(d);
     int cm = 0;
     V alpha = V(0), beta = V(0);
     rows_prefetched(
         rb, re, [&](int i) { return Trio<V>{p[i], z[i], x[i]}; },
         [&]() {
-            // B's record of this iteration; block 0 below writes only the
-            // live fields, which no block of this kernel reads
-            const int mixed = st->mixed;
-            const Gate g{st->snap_status, st->snap_phase, mixed};
-            const int iter = st->snap_iter, inner_iter = st->snap_inner_iter;
-            const double rho = st->snap_rho, eta = st->snap_eta;
+            const Snap sn = load_snap(st);
             double RZ, RR;
-            if (one_chunk) {
-                RZ = partials_sum(vz, red);
-                RR = partials_sum(vr, red);
-            } else {
-                reduce_partials2(prz, prr, d.nblk, red, RZ, RR);
-            }
-            if (mixed != Vecs<V>::mixed || !gate_ok(g, Vecs<V>::gate)) return false;
-            const Step t = pcg_decide(mixed, iter, inner_iter, rho, eta, RZ, RR, st);
-            if (j == 0 && threadIdx.x == 0) {
-                st->cmode = 0;  // a pending p continuation has been served
-                st->eta = eta;
-                if (t.status != SPK_RUNNING) st->status = t.status;
-                if (t.to_update) {
-                    st->phase = kPhaseUpdate;
-                    if (t.fresh_p) st->fresh_p = 1;
-                }
-                if (eta > 0.0 && finite(eta)) {
-                    const int k = iter + 1;
-                    st->alpha = t.alpha;
-                    st->iter = k;
-                    if (mixed) st->inner_iter = inner_iter + 1;
-                    else {
-                        st->rnorm = t.rn;
-                        if (d.hist && k < st->hist_len) d.hist[k] = t.rn;
-                    }
-                    if (t.cmode == 2) {
-                        st->beta = t.beta;
-                        st->rho = RZ;
-                    }
-                }
-            }
+            part.sum(d, red, RZ, RR);
+            if (sn.mixed != Vecs<V>::mixed || !gate_ok(sn.g, Vecs<V>::gate)) return false;
+            const Step t = pcg_decide(sn.mixed, sn.iter, sn.inner_iter, sn.rho, sn.eta, RZ, RR, st);
+            if (j == 0 && threadIdx.x == 0) pcg_store(st, d, sn, t, RZ);
             cm = t.cmode;
             alpha = (V)t.alpha;
             beta = (V)t.beta;
@@ -860,6 +909,86 @@ __global__ __launch_bounds__(kBlock) void k_pcg_px(B a)
         });
 }
 
+// F: C of iteration k fused with A of iteration k + 1, for systems with the
+// SELL product on the persistent grid and a second p buffer (p2).  An
+// iteration is then two kernels (B, F) and moves 88n vector bytes, the
+// lower bound (the p update rides in the product's gather), instead of 96n
+// and a third launch.  The p of iteration k + 1 is formed wherever the
+// product gathers it, p' = z + beta p, the same FMA as C's and so the same
+// bits in every block that forms element j, and the lane that owns row j
+// stores it into the other buffer, so p of iteration k stays intact while
+// other blocks still gather it.  The results are those of A, B, C bit for
+// bit.  kStart: the first product of a CG sequence, launched after the setup
+// finalizers (snap_mode 0: p' = z; 3: p' = z + beta p after a reliable
+// update, beta from the refinement); otherwise snap_mode 1: B's recorded
+// decision, then x += alpha p and, while iterating, the product.
+template <class V, class CI, int U, bool kStart, class B>
+__global__ __launch_bounds__(kBlock) void k_pcg_fused_sell(B a)
+{
+    __shared__ double red[kBlock / kWave];
+    int j;
+    SysDesc d;
+    if (!locate(a, j, d)) return;
+    if (!Vecs<V>::present(d) || !Vecs<V>::p2(d)) return;
+    SysState *st = d.st;
+    // written by B and the setup finalizers only, never by this kernel
+    const int mode = st->snap_mode;
+    if (kStart ? mode == 1 : mode != 1) return;
+    RzRr part;
+    if (!kStart) part.load(d);
+    const int pb = st->snap_pbuf;
+    int cm = 2;  // 2: (x update and) product; 1: the last x update
+    bool fresh = false;
+    V alpha = V(0), beta = V(0);
+    if (kStart) {
+        if (!gate_ok(load_gate(st), Vecs<V>::gate)) return;
+        fresh = mode == 0;
+        beta = fresh ? V(0) : (V)st->beta;  // the finalizer's beta (F stores beta only when deciding)
+        if (j == 0 && threadIdx.x == 0) {
+            st->pbuf = pb ^ 1;
+            st->cmode = 0;
+        }
+    } else {
+        const Snap sn = load_snap(st);
+        double RZ, RR;
+        part.sum(d, red, RZ, RR);
+        if (sn.mixed != Vecs<V>::mixed || !gate_ok(sn.g, Vecs<V>::gate)) return;
+        const Step t = pcg_decide(sn.mixed, sn.iter, sn.inner_iter, sn.rho, sn.eta, RZ, RR, st);
+        if (j == 0 && threadIdx.x == 0) {
+            pcg_store(st, d, sn, t, RZ);
+            if (t.cmode == 2) st->pbuf = pb ^ 1;
+        }
+        cm = t.cmode;
+        if (cm == 0) return;
+        alpha = (V)t.alpha;
+        beta = (V)t.beta;
+    }
+    const V *__restrict__ pold = pb ? Vecs<V>::p2(d) : Vecs<V>::p(d);
+    V *__restrict__ pnew = pb ? Vecs<V>::p(d) : Vecs<V>::p2(d);
+    const V *__restrict__ z = Vecs<V>::z(d);
+    V *__restrict__ x = Vecs<V>::x(d);
+    V *__restrict__ q = Vecs<V>::q(d);
+    if (cm == 1) {  // the solve (or the inner solve) stops: x update only
+        int rb, re;
+        row_range(d, j, rb, re);
+        rows_unrolled(rb, re, [&](int i) { x[i] = fma(alpha, pold[i], x[i]); });
+        return;
+    }
+    auto pn = [&](int c) -> V { return fresh ? z[c] : fma(beta, pold[c], z[c]); };
+    const SellView sv{d.sell_ptr, d.sell_col, d.sell_len, d.sell_plain, d.sell_len16, d.sell_perm};
+    V acc = V(0);
+    sell_slices_g<V, CI, U>(d.n, sell_first(local_block(a)), d.nblk * (kBlock / kWave), sv, sell_vals<V>(d), pn,
+                            [] { return true; }, [&](int i, V y) {
+                                const V pi = pn(i);
+                                if (!kStart) x[i] = fma(alpha, pold[i], x[i]);
+                                pnew[i] = pi;
+                                q[i] = y;
+                                acc = fma(y, pi, acc);
+                            });
+    const double blk = block_sum((double)acc, red);
+    if (threadIdx.x == 0) d.partials[kPartPq * d.nblk + j] = blk;
+}
+
 // p = z + beta p where the last refinement asked for it (cmode 3: CG
 // continues after a reliable update, with beta from k_fin_setup32).
 template <class V, class B>
@@ -868,7 +997,7 @@ __global__ __launch_bounds__(kBlock) void k_pcg_p_continue(B a)
     int j;
     SysDesc d;
     if (!locate(a, j, d)) return;
-    if (!Vecs<V>::present(d)) return;
+    if (!Vecs<V>::present(d) || Vecs<V>::p2(d)) return;  // fused systems: F does it
     const SysState *st = d.st;
     int rb, re;
     row_range(d, j, rb, re);

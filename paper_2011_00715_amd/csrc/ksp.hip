@@ -41,6 +41,8 @@ void free_workspace(spk_mat *A)
     hipFree(w->p32);
     hipFree(w->q32);
     hipFree(w->d32);
+    hipFree(w->p2);
+    hipFree(w->p2_32);
     hipFree(w->s);
     hipFree(w->srp);
     hipFree(w->sc);
@@ -87,6 +89,28 @@ static __global__ void k_ws_init(int32_t *blk_start, int nblk, SysState *st)
     }
 }
 
+// Whether the fused iteration pays for one precision (kSellPlain64 / 32):
+// it moves 8n (FP32: 4n) bytes less per iteration and saves a launch, but
+// its kernel F holds one more vector (the second p buffer) besides the
+// matrix.  When the three-kernel iteration's working set (the layout and
+// six vectors) fits the Infinity Cache and the fused one's does not, the
+// product loses its cache hits.  The 7-point 128^3 FP64 iteration (249 MB
+// three-kernel, 266 MB fused, against a 268 MB cache) took 70.4 us fused
+// and 64.4 us in three kernels, so the fused set must leave kFusedMargin of
+// the cache free; its FP32 inner iteration (157 MB fused) went 44.1 ->
+// 41.7 us.
+constexpr int64_t kFusedMargin = 16ll << 20;
+static bool fused_pays(const spk_mat *A, int bit)
+{
+    const int ns = ceil_div(A->n, kSell);
+    const int64_t extra = (A->sell_len16 ? A->n : 0) + (A->sell_perm ? 4ll * A->n : 0);
+    if (A->stream_loads) return true;
+    const int six = sell_load_policy(A->sell_nnz, A->sell_cw, ns, A->n, 6, kIterCacheBudget - extra);
+    const int seven =
+        sell_load_policy(A->sell_nnz, A->sell_cw, ns, A->n, 7, kIterCacheBudget - extra - kFusedMargin);
+    return !((six & bit) && !(seven & bit));
+}
+
 static int get_workspace(spk_mat *A, bool mixed, Workspace **out, hipStream_t s)
 {
     Workspace *w = A->ws;
@@ -111,6 +135,12 @@ static int get_workspace(spk_mat *A, bool mixed, Workspace **out, hipStream_t s)
             w->nwpart = ceil_div(ceil_div(A->n, kSell), kBlock / kWave);
             SPK_TRY(dalloc(&w->wpart, w->nwpart, w));
         }
+        // the SELL product on the persistent grid takes the fused iteration
+        if (A->kernel == SPK_KERNEL_SELL && A->sell_cw && A->nblk > 0 && !w->wpart) {
+            w->fused64 = fused_pays(A, kSellPlain64);
+            w->fused32 = fused_pays(A, kSellPlain32);
+        }
+        if (w->fused64) SPK_TRY(dalloc(&w->p2, A->n, w));
         SPK_HIP(hipHostMalloc((void **)&w->pdesc, sizeof(SysDesc), hipHostMallocDefault));
         SPK_HIP(hipHostMalloc((void **)&w->pst, sizeof(SysState), hipHostMallocDefault));
         SPK_HIP(hipHostMalloc((void **)&w->pstatus, sizeof(int32_t) * 8, hipHostMallocDefault));
@@ -143,6 +173,7 @@ static int get_workspace(spk_mat *A, bool mixed, Workspace **out, hipStream_t s)
         d.sell_plain = A->sell_plain;
         d.sell_len16 = A->sell_len16;
         d.sell_perm = A->sell_perm;
+        d.p2 = w->p2;
     }
     if (mixed && !w->has_mixed) {
         SPK_TRY(dalloc(&w->r32, A->n, w));
@@ -150,6 +181,7 @@ static int get_workspace(spk_mat *A, bool mixed, Workspace **out, hipStream_t s)
         SPK_TRY(dalloc(&w->p32, A->n, w));
         SPK_TRY(dalloc(&w->q32, A->n, w));
         SPK_TRY(dalloc(&w->d32, A->n, w));
+        if (w->fused32) SPK_TRY(dalloc(&w->p2_32, A->n, w));
         w->has_mixed = 1;
         SysDesc &d = w->hdesc;
         d.val32 = A->val32;
@@ -159,6 +191,7 @@ static int get_workspace(spk_mat *A, bool mixed, Workspace **out, hipStream_t s)
         d.p32 = w->p32;
         d.q32 = w->q32;
         d.d32 = w->d32;
+        d.p2_32 = w->p2_32;
         d.sell_val32 = A->sell_val32;
     }
     *out = w;
@@ -167,8 +200,17 @@ static int get_workspace(spk_mat *A, bool mixed, Workspace **out, hipStream_t s)
 
 // Every pointer of the descriptor is owned by the workspace (b is copied in),
 // so the descriptor travels by value in the kernel arguments and captured
-// graphs stay valid from one solve to the next.
-static One batch_of(Workspace *w) { return One{w->hdesc}; }
+// graphs stay valid from one solve to the next.  A profiled solve times the
+// product kernel alone, so it runs the three-kernel iteration: its
+// descriptor has no second p buffer (the results are the same bits).
+static bool use_fused(const Workspace *w, bool mixed) { return (mixed ? w->fused32 : w->fused64) && !w->prof; }
+static One batch_of(Workspace *w)
+{
+    One b{w->hdesc};
+    if (!use_fused(w, false)) b.d.p2 = nullptr;
+    if (!use_fused(w, true)) b.d.p2_32 = nullptr;
+    return b;
+}
 
 // r = b - A x for the handle's kernel family.
 static int launch_resid(spk_mat *A, Workspace *w, int purpose, bool gated, hipStream_t s)
@@ -264,9 +306,48 @@ static int enqueue_iteration(spk_mat *A, Workspace *w, hipStream_t s)
     return SPK_OK;
 }
 
+// F of the fused iteration (the C part, then the next product).
+template <class V, bool kStart>
+static void launch_fused(spk_mat *A, Workspace *w, hipStream_t s)
+{
+    const One b = batch_of(w);
+    const dim3 g(A->nblk), t(kBlock);
+    with_sell_u(A->sell_u, [&](auto uc) {
+        constexpr int U = decltype(uc)::value;
+        if (A->sell_cw == 2) hipLaunchKernelGGL((k_pcg_fused_sell<V, int16_t, U, kStart, One>), g, t, 0, s, b);
+        else hipLaunchKernelGGL((k_pcg_fused_sell<V, int32_t, U, kStart, One>), g, t, 0, s, b);
+    });
+}
+
 // One batch of K iterations (mixed: preceded by the refinement kernels).
+// Fused: a start kernel (a no-op unless a setup finalizer just ran) and K
+// times B, F; F of the batch's last iteration holds its decision, which the
+// next batch's refinement kernels (gated on the phase it sets) follow.
 static int enqueue_batch(spk_mat *A, Workspace *w, bool mixed, int K, hipStream_t s)
 {
+    if (use_fused(w, mixed)) {
+        const One b = batch_of(w);
+        const dim3 g(A->nblk), t(kBlock);
+        if (mixed) {
+            hipLaunchKernelGGL(k_update_x<One>, g, t, 0, s, b);
+            SPK_TRY(launch_resid(A, w, kResOuter, true, s));
+            hipLaunchKernelGGL(k_setup32<One>, g, t, 0, s, b);
+            hipLaunchKernelGGL(k_fin_setup32<One>, dim3(1), t, 0, s, b);
+            launch_fused<float, true>(A, w, s);
+            for (int k = 0; k < K; ++k) {
+                hipLaunchKernelGGL((k_pcg_update<float, One>), g, t, 0, s, b);
+                launch_fused<float, false>(A, w, s);
+            }
+        } else {
+            launch_fused<double, true>(A, w, s);
+            for (int k = 0; k < K; ++k) {
+                hipLaunchKernelGGL((k_pcg_update<double, One>), g, t, 0, s, b);
+                launch_fused<double, false>(A, w, s);
+            }
+        }
+        SPK_HIP(hipGetLastError());
+        return SPK_OK;
+    }
     if (mixed) {
         const One b = batch_of(w);
         hipLaunchKernelGGL(k_update_x<One>, dim3(A->nblk), dim3(kBlock), 0, s, b);

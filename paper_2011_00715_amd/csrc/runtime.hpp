@@ -66,6 +66,12 @@ struct Workspace {
     double *x = nullptr;          // the solve's iterate (copied in and out)
     double *b = nullptr;          // the solve's right-hand side (copied in)
     float *r32 = nullptr, *z32 = nullptr, *p32 = nullptr, *q32 = nullptr, *d32 = nullptr;
+    // fused iteration (SELL product on the persistent grid): the second p
+    // buffers; fused64 / fused32 say which precisions take it (profiled
+    // solves do not)
+    bool fused64 = false, fused32 = false;
+    double *p2 = nullptr;
+    float *p2_32 = nullptr;
     hipStream_t cap = nullptr;    // private stream used only to capture graphs
     hipGraphExec_t g64 = nullptr, gmix = nullptr, gsr = nullptr;
     int g64_k = 0, gmix_k = 0, gsr_k = 0;

@@ -204,7 +204,8 @@ static int64_t request_bytes(const Request &q)
     if (q.sell) {
         const int64_t ns = (n + kSell - 1) / kSell;
         b += align256(4 * (ns + 1)) + align256(2 * q.sell_nnz) + align256(n) + align256(8 * q.sell_nnz);
-        if (q.mixed) b += align256(4 * q.sell_nnz);
+        b += align256(8 * n);  // second p buffer of the fused iteration
+        if (q.mixed) b += align256(4 * q.sell_nnz) + align256(4 * n);
     }
     return b;
 }
@@ -331,6 +332,10 @@ static int admit(spk_server *S, Request *q, int k, int64_t off)
         sell_len = (uint8_t *)take(n);
         sell_val = (double *)take(8 * q->sell_nnz);
         if (q->mixed) sell_val32 = (float *)take(4 * q->sell_nnz);
+        // SELL systems take the fused iteration (B, then the p/x pass fused
+        // into the next product): its second p buffers
+        d.p2 = (double *)take(8 * n);
+        if (q->mixed) d.p2_32 = (float *)take(4 * n);
         d.sell_cw = 2;
         d.sell_ptr = sell_ptr;
         d.sell_col = sell_col;
@@ -500,9 +505,11 @@ static __global__ void k_snapshot(const int2 *__restrict__ src, int2 *__restrict
     if (i < words) dst[i] = src[i];
 }
 
-// One batched step: K iterations of every active system.  The products run
-// per section (stream tiles, SELL), the rest over the whole table.  (A step
-// captured as a hipGraph over tables padded to max_slots was measured
+// One batched step: K iterations of every active system.  SELL systems run
+// the fused iteration (B, then F: the p/x pass fused into the next product;
+// a start F after the refinement kernels begins a new CG sequence), the
+// stream-tile systems the three kernels A, B, C; B covers all of them.  (A
+// step captured as a hipGraph over tables padded to max_slots was measured
 // slower: replaying it costs the host more than these launches.)
 static int enqueue_step(spk_server *S)
 {
@@ -513,14 +520,20 @@ static int enqueue_step(spk_server *S)
     const dim3 g(S->nblocks), t(kBlock), f(S->nsys), gst(S->nblk_st), gsl(S->nblk_sl);
     const int K = S->o.graph_k > 0 ? S->o.graph_k : 8;
     hipStream_t st = S->s;
-    auto products = [&](auto vtag) {
+    auto fused = [&](auto vtag, auto start) {
+        using V = decltype(vtag);
+        constexpr bool kStart = decltype(start)::value;
+        with_sell_u(S->u_sl, [&](auto uc) {
+            constexpr int U = decltype(uc)::value;
+            hipLaunchKernelGGL((k_pcg_fused_sell<V, int16_t, U, kStart, Batch>), gsl, t, 0, st, bsl);
+        });
+    };
+    auto iteration = [&](auto vtag) {
         using V = decltype(vtag);
         if (S->nsys_st) hipLaunchKernelGGL((k_pcg_spmv_stream<V, Batch>), gst, t, 0, st, bst);
-        if (S->nsys_sl)
-            with_sell_u(S->u_sl, [&](auto uc) {
-                constexpr int U = decltype(uc)::value;
-                hipLaunchKernelGGL((k_pcg_spmv_sell<V, int16_t, U, Batch>), gsl, t, 0, st, bsl);
-            });
+        hipLaunchKernelGGL((k_pcg_update<V, Batch>), g, t, 0, st, b);
+        if (S->nsys_st) hipLaunchKernelGGL((k_pcg_px<V, Batch>), gst, t, 0, st, bst);
+        if (S->nsys_sl) fused(V(), std::false_type{});
     };
     if (S->n_mixed) {
         hipLaunchKernelGGL(k_update_x<Batch>, g, t, 0, st, b);
@@ -533,19 +546,15 @@ static int enqueue_step(spk_server *S)
         hipLaunchKernelGGL((k_fin_resid<kGateResid, Batch>), f, t, 0, st, b, (int)kResOuter);
         hipLaunchKernelGGL(k_setup32<Batch>, g, t, 0, st, b);
         hipLaunchKernelGGL(k_fin_setup32<Batch>, f, t, 0, st, b);
-        hipLaunchKernelGGL((k_pcg_p_continue<float, Batch>), g, t, 0, st, b);
+        if (S->nsys_st) hipLaunchKernelGGL((k_pcg_p_continue<float, Batch>), gst, t, 0, st, bst);
+    }
+    if (S->nsys_sl) {  // first products of the sequences that start here
+        if (S->n_fp64) fused(double(), std::true_type{});
+        if (S->n_mixed) fused(float(), std::true_type{});
     }
     for (int k = 0; k < K; ++k) {
-        if (S->n_fp64) {
-            products(double());
-            hipLaunchKernelGGL((k_pcg_update<double, Batch>), g, t, 0, st, b);
-            hipLaunchKernelGGL((k_pcg_px<double, Batch>), g, t, 0, st, b);
-        }
-        if (S->n_mixed) {
-            products(float());
-            hipLaunchKernelGGL((k_pcg_update<float, Batch>), g, t, 0, st, b);
-            hipLaunchKernelGGL((k_pcg_px<float, Batch>), g, t, 0, st, b);
-        }
+        if (S->n_fp64) iteration(double());
+        if (S->n_mixed) iteration(float());
     }
     SPK_HIP(hipGetLastError());
     return SPK_OK;

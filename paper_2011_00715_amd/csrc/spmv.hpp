@@ -256,10 +256,11 @@ __device__ __forceinline__ T sell_ld(const T *p)
 // last pair and padding has offset 0, so every gather reads a valid element
 // of x; only the row's own entries are multiplied.  UP is chosen per matrix
 // from the widest slice (3 for a 7-point stencil: one round and the tail).
-template <class V, class CI, int UP, bool NT>
-__device__ __forceinline__ V sell_row(const SellView &sv, const V *__restrict__ val,
-                                      const V *__restrict__ x, int32_t b, int slen, int rlen,
-                                      int lane, int row)
+// gat(j) is the gathered operand at column j: x[j] for a plain product; the
+// fused PCG kernels form p = z + beta p there.
+template <class V, class CI, int UP, bool NT, class G>
+__device__ __forceinline__ V sell_row(const SellView &sv, const V *__restrict__ val, G &&gat,
+                                      int32_t b, int slen, int rlen, int lane, int row)
 {
     using CP = typename Pair2<CI>::type;
     using VP = typename Pair2<V>::type;
@@ -289,10 +290,10 @@ __device__ __forceinline__ V sell_row(const SellView &sv, const V *__restrict__ 
         V xv[2 * UP];
 #pragma unroll
         for (int u = 0; u < UP; ++u) {
-            xv[2 * u] = x[row + (int)c[u].x];
-            xv[2 * u + 1] = x[row + (int)c[u].y];
+            xv[2 * u] = gat(row + (int)c[u].x);
+            xv[2 * u + 1] = gat(row + (int)c[u].y);
         }
-        if (p0 == 0 && odd) xt = x[row + (int)ct];
+        if (p0 == 0 && odd) xt = gat(row + (int)ct);
 #pragma unroll
         for (int u = 0; u < UP; ++u) {
             const int k = 2 * (p0 + u);
@@ -303,7 +304,7 @@ __device__ __forceinline__ V sell_row(const SellView &sv, const V *__restrict__ 
         }
     }
     if (odd) {
-        if (np == 0) xt = x[row + (int)ct];
+        if (np == 0) xt = gat(row + (int)ct);
         if (slen - 1 < rlen) acc = fma(at, xt, acc);
     }
     return acc;
@@ -315,10 +316,9 @@ __device__ __forceinline__ V sell_row(const SellView &sv, const V *__restrict__ 
 // flight at any moment are adjacent in memory (one DRAM stream front rather
 // than one per block).  The first slice's header is loaded before go() is
 // asked whether to run (go holds no barrier: waves may own different counts).
-template <class V, class CI, int U, bool NT, class Go, class Fn>
+template <class V, class CI, int U, bool NT, class G, class Go, class Fn>
 __device__ __forceinline__ void sell_slices_run(int n, int s, int stride, const SellView &sv,
-                                                const V *__restrict__ val, const V *__restrict__ x,
-                                                Go &&go, Fn &&fn)
+                                                const V *__restrict__ val, G &&gat, Go &&go, Fn &&fn)
 {
     const int lane = threadIdx.x & (kWave - 1);
     const int ns = (n + kSell - 1) / kSell;
@@ -338,7 +338,7 @@ __device__ __forceinline__ void sell_slices_run(int n, int s, int stride, const 
     if (!go()) return;
     while (s < ns) {
         const int slen = (e - b) / kSell;
-        if (s * kSell + lane < n) fn(row, sell_row<V, CI, U, NT>(sv, val, x, b, slen, rlen, lane, row));
+        if (s * kSell + lane < n) fn(row, sell_row<V, CI, U, NT>(sv, val, gat, b, slen, rlen, lane, row));
         s += stride;
         if (s >= ns) break;
         b = sv.ptr[s];
@@ -350,15 +350,23 @@ __device__ __forceinline__ void sell_slices_run(int n, int s, int stride, const 
 // The load policy is chosen here, around the whole slice loop, so that the
 // two variants stay separate code (a branch inside the round lets the
 // compiler merge the loads and drop the nontemporal hint).
+template <class V, class CI, int U, class G, class Go, class Fn>
+__device__ __forceinline__ void sell_slices_g(int n, int s, int stride, const SellView &sv,
+                                              const V *__restrict__ val, G &&gat, Go &&go, Fn &&fn)
+{
+    if (sv.plain & (sizeof(V) == 4 ? kSellPlain32 : kSellPlain64))
+        sell_slices_run<V, CI, U, false>(n, s, stride, sv, val, gat, go, fn);
+    else
+        sell_slices_run<V, CI, U, true>(n, s, stride, sv, val, gat, go, fn);
+}
+
+// The plain product: the gathered operand is x.
 template <class V, class CI, int U, class Go, class Fn>
 __device__ __forceinline__ void sell_slices(int n, int s, int stride, const SellView &sv,
                                             const V *__restrict__ val, const V *__restrict__ x,
                                             Go &&go, Fn &&fn)
 {
-    if (sv.plain & (sizeof(V) == 4 ? kSellPlain32 : kSellPlain64))
-        sell_slices_run<V, CI, U, false>(n, s, stride, sv, val, x, go, fn);
-    else
-        sell_slices_run<V, CI, U, true>(n, s, stride, sv, val, x, go, fn);
+    sell_slices_g<V, CI, U>(n, s, stride, sv, val, [x](int j) { return x[j]; }, go, fn);
 }
 
 // Standalone SELL SpMV; the grid has up to one wavefront per slice.

@@ -126,6 +126,35 @@ def test_pcg_profiled_solve_same_result(prec):
         _solve(spk, M, b, profile=1, single_reduction=1)
 
 
+@pytest.mark.parametrize("prec", ["fp64", "mixed", "mixed_ir"])
+@pytest.mark.parametrize("case", ["lap3d_30", "lap2d_90", "diff27_14"])
+def test_pcg_fused_iteration_equals_three_kernels(case, prec):
+    """SELL on the persistent grid takes the fused iteration (B, then F: the
+    p/x pass fused into the next product, p in two alternating buffers); a
+    profiled solve runs the three-kernel iteration on the same matrix.  Both
+    give the same bits, iteration counts and refinement steps, in FP64 and
+    in both mixed-precision readings, and meet the oracle's true residual."""
+    spk = need_gpu()
+    A = {"lap3d_30": spkgen.laplace3d7(30, shift=0.05), "lap2d_90": spkgen.laplace2d5(90),
+         "diff27_14": spkgen.diffusion3d27_lognormal(14, seed=4)}[case]
+    M = mat_on_gpu(spk, A, flags=spk.MAT_MIXED)
+    spk.mat_set_kernel(M, spk.KERNEL_SELL, 0)
+    p = {"fp64": spk.PREC_FP64, "mixed": spk.PREC_MIXED, "mixed_ir": spk.PREC_MIXED_IR}[prec]
+    b = spkgen.rhs_uniform(A.n, 7)
+    xf, rf, hf = _solve(spk, M, b, precision=p, hist_len=64)
+    xt, rt, ht = _solve(spk, M, b, precision=p, hist_len=64, profile=1)
+    assert rf.reason == spk.CONVERGED_RTOL, rf.as_dict()
+    assert np.array_equal(xf, xt)
+    assert (rf.iterations, rf.inner_iterations, rf.outer_steps, rf.restarts) == \
+        (rt.iterations, rt.inner_iterations, rt.outer_steps, rt.restarts)
+    assert np.array_equal(hf, ht, equal_nan=True)
+    bn = oracle.nrm2(b)
+    assert oracle.nrm2(b - oracle.spmv(A, xf)) <= 1e-8 * bn * (1 + 1e-6)
+    # and a second solve on the same handle (buffers left by the first)
+    xf2, rf2, _ = _solve(spk, M, b, precision=p, hist_len=64)
+    assert np.array_equal(xf2, xf) and rf2.iterations == rf.iterations
+
+
 def test_pcg_graph_and_direct_launch_identical():
     spk = need_gpu()
     A = spkgen.diffusion3d27_lognormal(12, seed=3)
