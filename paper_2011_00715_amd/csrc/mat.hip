@@ -509,19 +509,21 @@ static void choose_kernel(spk_mat *A, bool allow_sell = true, bool allow_sliced 
     }
 }
 
-// Blocks of the PCG kernels of one system (product with its p.q partials,
-// update, p/x pass).  Every block of the update and p/x passes sums all
-// blocks' partials, so fewer, larger blocks cut that L2 traffic; measured on
-// the 7-point 128^3 / 27-point 160^3 systems against caps of 512, 1536 and
-// 2048 (same box, two rounds each): 1024 gave the fastest FP64 and FP32
-// iterations overall (FP64 66.3 -> 64.4 us and 288.4 -> 286.0 us per
-// iteration against 2048).
-constexpr int kPcgBlocks = 1024;
+// Blocks of the PCG kernels of one SELL system (product with its p.q
+// partials, update, p/x pass).  Every block of the update and p/x passes
+// sums all blocks' partials, so fewer, larger blocks cut that L2 traffic;
+// measured on the 7-point 128^3 / 27-point 160^3 systems against caps of
+// 512, 1536 and 2048 (same box, two rounds each): 1024 gave the fastest FP64
+// and FP32 iterations overall (FP64 66.3 -> 64.4 us and 288.4 -> 286.0 us
+// per iteration against 2048).  The other families keep 2048: their
+// products use the block count too, and the stream-tile SpMV of the
+// power-law matrix took 2693 us on 1024 blocks against 2138 us on 2048.
+constexpr int kPcgBlocksSell = 1024;
 
 static int apply_partition(spk_mat *A)
 {
     A->ntiles = ceil_div(A->n, A->R);
-    A->nblk = pick_nblk(A->ntiles, kPcgBlocks);
+    A->nblk = pick_nblk(A->ntiles, A->kernel == SPK_KERNEL_SELL ? kPcgBlocksSell : kMaxBlocksSingle);
     return SPK_OK;
 }
 
