@@ -390,22 +390,27 @@ inline void with_sell_u(int u, F &&f)
     case 4: f(std::integral_constant<int, 4>{}); break;
     case 5: f(std::integral_constant<int, 5>{}); break;
     case 6: f(std::integral_constant<int, 6>{}); break;
+    case 9: f(std::integral_constant<int, 9>{}); break;
+    case 13: f(std::integral_constant<int, 13>{}); break;
     default: f(std::integral_constant<int, 7>{}); break;
     }
 }
 
-// UP for a matrix whose widest slice has w entries per row: its pair count
-// w / 2 when that is 2..7, 2 below, else the UP in [4, 7] that repeats the
-// fewest pairs (27-point rows: 13 pairs, UP 7).
+// UP for a matrix whose widest slice has w entries per row: the fewest
+// rounds, then the fewest repeated pairs, among the built values (2 below 3
+// pairs).  One round beats register room: the 27-point rows (13 pairs) in
+// one round of 13 (FP64 140 VGPRs, 3 wavefronts per SIMD) took the 160^3
+// PCG product from 225.7 to 216.3 us against two rounds of 7 (95 VGPRs,
+// 5 per SIMD); rounds of 5 and 4 (6 and 7 per SIMD) took 231.7 and 233.1.
 inline int pick_sell_u(int w)
 {
     const int np = w >> 1;
     if (np <= 2) return 2;
-    if (np <= 7) return np;
-    int best = 7, waste = 1 << 30;
-    for (int u = 7; u >= 4; --u) {
-        const int wst = (np + u - 1) / u * u - np;
-        if (wst < waste) { waste = wst; best = u; }
+    constexpr int kBuilt[] = {3, 4, 5, 6, 7, 9, 13};
+    int best = 13, rounds = 1 << 30, waste = 1 << 30;
+    for (const int u : kBuilt) {
+        const int r = (np + u - 1) / u, wst = r * u - np;
+        if (r < rounds || (r == rounds && wst < waste)) { best = u; rounds = r; waste = wst; }
     }
     return best;
 }
