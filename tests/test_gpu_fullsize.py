@@ -115,6 +115,14 @@ def test_c2_spmv_and_pcg():
     assert rm.reason == spk.CONVERGED_RTOL and rm.fallback_fp64 == 0
     assert oracle.nrm2(b - oracle.spmv(A, xm)) <= 1e-8 * bn * (1 + 1e-6)
     assert rm.inner_iterations <= 1.1 * ro["iterations"]
+    # the fused FP32 inner iteration at this size against the three-kernel
+    # iteration of a profiled solve: the same bits (FP64 runs three kernels
+    # here either way: its fused working set would not fit the cache)
+    for prec, xf, rf in ((spk.PREC_FP64, x64, r64), (spk.PREC_MIXED, xm, rm)):
+        xt, rt = _solve(spk, M, b, precision=prec, profile=1)
+        assert np.array_equal(xt, xf)
+        assert (rt.iterations, rt.inner_iterations, rt.outer_steps) == (rf.iterations, rf.inner_iterations,
+                                                                        rf.outer_steps)
 
 
 

@@ -155,6 +155,32 @@ def test_pcg_fused_iteration_equals_three_kernels(case, prec):
     assert np.array_equal(xf2, xf) and rf2.iterations == rf.iterations
 
 
+@pytest.mark.parametrize("edge", ["maxit_5", "restarts", "x0"])
+def test_pcg_fused_iteration_edge_cases(edge):
+    """The fused and three-kernel iterations agree bit for bit where a solve
+    stops inside a batch (maxit), through the true-residual restarts (an
+    unreachable rtol: the fused start kernel after every re-setup), and from
+    a nonzero initial guess."""
+    spk = need_gpu()
+    A = spkgen.laplace2d5(32)
+    M = mat_on_gpu(spk, A)
+    spk.mat_set_kernel(M, spk.KERNEL_SELL, 0)
+    b = spkgen.rhs_uniform(A.n, 0)
+    kw = {"maxit_5": dict(maxit=5), "restarts": dict(rtol=1e-17, maxit=100000),
+          "x0": dict(x0=spkgen.rhs_uniform(A.n, 5))}[edge]
+    xf, rf, hf = _solve(spk, M, b, hist_len=4000, **dict(kw))
+    xt, rt, ht = _solve(spk, M, b, hist_len=4000, profile=1, **dict(kw))
+    assert np.array_equal(xf, xt)
+    assert (rf.reason, rf.iterations, rf.restarts) == (rt.reason, rt.iterations, rt.restarts)
+    assert np.array_equal(hf, ht, equal_nan=True)
+    if edge == "maxit_5":
+        assert rf.reason == spk.DIVERGED_ITS and rf.iterations == 5
+        xo, _, _ = oracle.pcg(A, b, maxit=5)
+        assert np.allclose(xf, xo, rtol=1e-12, atol=1e-14)
+    if edge == "restarts":
+        assert rf.restarts >= 1
+
+
 def test_pcg_graph_and_direct_launch_identical():
     spk = need_gpu()
     A = spkgen.diffusion3d27_lognormal(12, seed=3)
