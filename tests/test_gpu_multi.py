@@ -23,6 +23,16 @@ def _mats():
     yield "lap3d_23", spkgen.laplace3d7(23), True
     yield "diff27_13", spkgen.diffusion3d27_lognormal(13, seed=1), False
     yield "powerlaw_20k", spkgen.powerlaw_spd(20000, seed=3), False
+    # 130 diagonal-only rows (slices of one entry per row, no pairs) ahead of
+    # a 2D Laplacian (slices of at most two pairs and a tail): on SELL the
+    # SpMM takes its general loop for the one-entry slices and the pipelined
+    # pairs for the others
+    L = spkgen.laplace2d5(21)
+    m = 130
+    rowptr = np.concatenate([np.arange(m + 1), m + L.rowptr[1:]]).astype(np.int32)
+    col = np.concatenate([np.arange(m), L.col + m]).astype(np.int32)
+    val = np.concatenate([np.full(m, 3.0), L.val])
+    yield "diag_then_lap2d", spkgen.CSR(m + L.n, rowptr, col, val), True
 
 
 def _dev2(a):
