@@ -84,9 +84,17 @@ __device__ __forceinline__ void csr_row_multi(int a, int e, const int32_t *__res
 // 118 -> 95 us with the staged stores below).  K = 16 keeps one pair in
 // registers at a time (double buffering would take 128 more VGPRs).  Sums
 // run in column order either way.
+//
+// kOneRound (standalone SpMM): a slice of at most kOneRoundPairs pairs loads
+// them and issues every gather (the odd entry's too) before the first FMA,
+// one memory round trip per slice at the cost of holding all gathered rows
+// (K = 8: 152 VGPRs, three wavefronts per SIMD).  The product inside the
+// multi-RHS solve keeps the pipelined walk: there the extra registers cost
+// more than the round trips they save.
 constexpr int kMultiPairs = 4;
+constexpr int kOneRoundPairs = 3;
 
-template <class CI, int K>
+template <class CI, int K, bool kOneRound = false>
 __device__ __forceinline__ void sell_row_multi(const SellView &sv, const double *__restrict__ val,
                                                const double *__restrict__ X, int32_t b, int slen,
                                                int rlen, int lane, int row, double acc[K])
@@ -115,6 +123,40 @@ __device__ __forceinline__ void sell_row_multi(const SellView &sv, const double 
 #pragma unroll
         for (int q = 0; q < K; ++q) acc[q] = fma(a, xr[q], acc[q]);
     };
+    if (kOneRound && K <= 8 && np <= kOneRoundPairs) {
+        // every pair index is clamped into the slice (a slice without pairs
+        // loads none: its gathers then fetch the lane's own row, unused)
+        constexpr int P1 = kOneRoundPairs;
+        CP c[P1];
+        VP a[P1];
+#pragma unroll
+        for (int u = 0; u < P1; ++u) {
+            c[u].x = c[u].y = CI(0);
+            a[u].x = a[u].y = 0.0;
+        }
+        if (np > 0)
+#pragma unroll
+            for (int u = 0; u < P1; ++u) {
+                const int p = u < np ? u : np - 1;
+                c[u] = ld_stream(cp + (size_t)p * kSell);
+                a[u] = ld_stream(vp + (size_t)p * kSell);
+            }
+        double xv[2 * P1 + 1][K];
+#pragma unroll
+        for (int u = 0; u < P1; ++u) {
+            gather((int)c[u].x, xv[2 * u]);
+            gather((int)c[u].y, xv[2 * u + 1]);
+        }
+        gather((int)ct, xv[2 * P1]);
+#pragma unroll
+        for (int u = 0; u < P1; ++u)
+            if (u < np) {
+                if (2 * u < rlen) madd(a[u].x, xv[2 * u]);
+                if (2 * u + 1 < rlen) madd(a[u].y, xv[2 * u + 1]);
+            }
+        if (odd && slen - 1 < rlen) madd(at, xv[2 * P1]);
+        return;
+    }
     if (PM > 1 && np >= 1 && np <= PM) {
         // the slice's pairs in one load round, gathers one pair ahead
         CP c[PM];
@@ -164,15 +206,16 @@ __device__ __forceinline__ void sell_row_multi(const SellView &sv, const double 
 }
 
 // SELL slices of block l with the K products of each row staged in LDS
-// (stage: this wave's 64 x K doubles), then handed out flat: fn(e, v) for
-// every element e of the slice's rows in the row-major n x K layout, lane t
-// getting elements t, t + 64, ... (so always column t % K, as 64 % K == 0).
-// A lane's K products are 8K contiguous bytes, so storing them from the
-// lanes directly writes 64 partial segments per instruction; the flat pass
-// writes whole ones (K = 8: 118 -> 99 us on the 7-point 128^3 product).
-template <class CI, int K, class Fn>
+// (stage: this wave's 64 x K doubles), then handed out flat: flat(e0, cnt)
+// for the slice's cnt elements starting at element e0 of the row-major
+// n x K layout, which the caller walks with lane t taking elements t, t + 64,
+// ... of the stage (so always column t % K, as 64 % K == 0).  A lane's K
+// products are 8K contiguous bytes, so storing them from the lanes directly
+// writes 64 partial segments per instruction; the flat pass writes whole
+// ones (K = 8: 118 -> 99 us on the 7-point 128^3 product).
+template <class CI, int K, bool kOneRound, class Flat>
 __device__ __forceinline__ void multi_sell_staged(const MultiDesc &d, int l, const double *__restrict__ X,
-                                                  double *stage, Fn &&fn)
+                                                  double *stage, Flat &&flat)
 {
     const int lane = threadIdx.x & (kWave - 1);
     const int ns = (d.n + kSell - 1) / kSell;
@@ -181,16 +224,15 @@ __device__ __forceinline__ void multi_sell_staged(const MultiDesc &d, int l, con
         const int row = s * kSell + lane;
         if (row < d.n) {
             double acc[K];
-            sell_row_multi<CI, K>(d.sv, d.sell_val, X, b, (e - b) / kSell, d.sv.len[row], lane, row, acc);
+            sell_row_multi<CI, K, kOneRound>(d.sv, d.sell_val, X, b, (e - b) / kSell, d.sv.len[row], lane, row,
+                                             acc);
 #pragma unroll
             for (int q = 0; q < K; ++q) stage[lane * K + q] = acc[q];
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        const int64_t e0 = (int64_t)s * kSell * K;
-        const int cnt = (min(d.n, (s + 1) * kSell) - s * kSell) * K;
-        for (int t = lane; t < cnt; t += kWave) fn(e0 + t, stage[t]);
+        flat((int64_t)s * kSell * K, (min(d.n, (s + 1) * kSell) - s * kSell) * K);
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -332,8 +374,15 @@ __global__ __launch_bounds__(kBlock) void k_spmm(MultiDesc d, const double *__re
     const int l = multi_block(d, j);
     if (l < 0) return;
     if (d.sell && K > 1) {
-        multi_sell_staged<CI, K>(d, l, X, stage + (threadIdx.x / kWave) * kWave * K,
-                                 [&](int64_t e, double v) { Y[e] = v; });
+        // flat stores of two elements (K is even): 1 KB per instruction
+        using VP = typename Pair2<double>::type;
+        const int lane = threadIdx.x & (kWave - 1);
+        double *st = stage + (threadIdx.x / kWave) * kWave * K;
+        multi_sell_staged<CI, K, true>(d, l, X, st, [&](int64_t e0, int cnt) {
+            const VP *src = reinterpret_cast<const VP *>(st);
+            VP *dst = reinterpret_cast<VP *>(Y + e0);
+            for (int t = lane; t < cnt / 2; t += kWave) __builtin_nontemporal_store(src[t], dst + t);
+        });
         return;
     }
     multi_rows<CI, K>(d, l, j, X, [&](int row, const double *acc) {
@@ -491,11 +540,16 @@ __global__ __launch_bounds__(kBlock) void k_m_spmm_pq(MultiDesc d)
     if (d.sell && K > 1) {
         // flat pass: lane t always holds column t % K
         double pqv = 0.0;
-        multi_sell_staged<CI, K>(d, l, P, stage + (threadIdx.x / kWave) * kWave * K, [&](int64_t e, double v) {
-            const double pe = P[e];
-            Q[e] = v;
-            pqv = fma(v, pe, pqv);
-        });
+        const int lane = threadIdx.x & (kWave - 1);
+        const double *st = stage + (threadIdx.x / kWave) * kWave * K;
+        multi_sell_staged<CI, K, false>(d, l, P, stage + (threadIdx.x / kWave) * kWave * K,
+                                        [&](int64_t e0, int cnt) {
+                                            for (int t = lane; t < cnt; t += kWave) {
+                                                const double v = st[t], pe = P[e0 + t];
+                                                Q[e0 + t] = v;
+                                                pqv = fma(v, pe, pqv);
+                                            }
+                                        });
         block_partials_flat<K>(pqv, sh, d.partials + (size_t)kPartPq * K * d.nblk, d.nblk, j);
         return;
     }
