@@ -596,6 +596,8 @@ def bench_all(args):
         torch.cuda.synchronize()
         cold_us.append(e0.elapsed_time(e1) * 1e3)
     del scratch
+    log("streaming bandwidth (copy, read)")
+    stream_bw = measured_stream_gbps()
     warm = float(np.mean(spmv_us))
     cold = float(np.mean(cold_us)) if cold_us else float("nan")
     c2["spmv"] = {
@@ -674,6 +676,8 @@ def bench_all(args):
             "traffic": traffic_from_profiles("k_pcg_spmv_sell_wide<double, short>@c3", i3.bytes_spmv_f64),
             "bytes_per_launch": i3.bytes_spmv_f64, "format_bytes_per_launch": i3.format_bytes_spmv_f64,
             "us_avg": prod_us, "launches_timed": prod_n,
+            "measured_gbps": stream_bw, "frac_of_copy": achieved / stream_bw["copy"],
+            "frac_of_axpy": achieved / stream_bw["axpy"],
             "note": "achieved = 12 nnz + 4(n+1) + 16n algorithmic bytes of one C3 FP64 product (q = A p with "
                     "the per-block p.q partials) / its average duration: an event pair on the solve stream "
                     "around each of the probe's product kernels in the timed steps (the one-block fold of the "
@@ -779,6 +783,46 @@ def bench_mg(args):
         "multigrid_pcg": mg,
     }
     M.close()
+    return out
+
+
+def measured_stream_gbps(reps=10):
+    """Bandwidth plain streaming kernels reach on this GPU, for the roofline
+    beside the 8 TB/s spec peak: the library's copy (1 GiB into 1 GiB, 2 GiB
+    moved) and its AXPY y = a x + y (two 1 GiB inputs, 3 GiB moved, the
+    paper's VecAXPY), 4-12x the Infinity Cache; GB/s of the median of `reps`
+    event-timed launches."""
+    import statistics
+
+    import torch
+
+    from paper_2011_00715_amd import spk
+
+    n = (1 << 30) // 8
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    c = torch.zeros_like(a)
+
+    def timed(fn):
+        for _ in range(2):
+            fn()
+        ts = []
+        for _ in range(reps):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn()
+            e1.record()
+            e1.synchronize()
+            ts.append(e0.elapsed_time(e1) * 1e-3)
+        return statistics.median(ts)
+
+    t_copy = timed(lambda: spk.bw_copy(a, c))
+    t_axpy = timed(lambda: spk.vec_axpy(0.5, a, c))
+    out = {"copy": 2 * n * 8 / t_copy / 1e9, "axpy": 3 * n * 8 / t_axpy / 1e9,
+           "note": "copy 1 GiB -> 1 GiB (read + written bytes) and AXPY over 1 GiB vectors (2 reads + "
+                   "1 write), median of %d launches; the product's bytes are almost all reads, which "
+                   "HBM serves faster than a read/write mix" % reps}
+    del a, c
     return out
 
 
