@@ -39,10 +39,20 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 # rocprofv3 names of the standalone FP64 SpMV kernel of each family
 SPMV_KERNELS = {
     "stream": "k_spmv_stream<double>",
-    "sell": "k_spmv_sell<double, short>",
+    "sell": "k_spmv_sell<double, CI>",
     "vector": "k_spmv_vector<double, L>",
     "merge": "k_spmv_merge<double> + k_merge_fixup<double>",
 }
+
+
+def sell_ci(info):
+    """Offset type in the SELL kernels' names: int16 per lane ("short"), or
+    int32 (per lane, or shared per slice: info.lanes 0)."""
+    return "short" if info.lanes == 16 else "int"
+
+
+def spmv_kernel_name(spk, info):
+    return SPMV_KERNELS[spk.KERNEL_NAMES[info.kernel]].replace("CI", sell_ci(info))
 
 
 def parse():
@@ -378,7 +388,7 @@ def bench_c2(args):
     spmv_avg_us = float(np.mean(spmv_us))
     achieved = info.bytes_spmv_f64 / (spmv_avg_us * 1e-6) / 1e9
     kname = spk.KERNEL_NAMES[info.kernel]
-    spmv_kernel = SPMV_KERNELS[kname]
+    spmv_kernel = spmv_kernel_name(spk, info)
     traffic = traffic_from_profiles(spmv_kernel + "@c2", info.bytes_spmv_f64)
 
     # cold Infinity Cache: each SpMV after reading 1 GiB of scratch (outside
@@ -601,17 +611,16 @@ def bench_all(args):
     warm = float(np.mean(spmv_us))
     cold = float(np.mean(cold_us)) if cold_us else float("nan")
     c2["spmv"] = {
-        "kernel": SPMV_KERNELS[spk.KERNEL_NAMES[i2.kernel]], "bytes": i2.bytes_spmv_f64,
+        "kernel": spmv_kernel_name(spk, i2), "bytes": i2.bytes_spmv_f64,
         "format_bytes": i2.format_bytes_spmv_f64,
         "cold_us_avg": cold, "cold_gbps": i2.bytes_spmv_f64 / cold / 1e3,
         "cold_frac": i2.bytes_spmv_f64 / cold / 1e3 / HBM_PEAK_GBS,
         "warm_us_avg": warm, "warm_gbps": i2.bytes_spmv_f64 / warm / 1e3,
         "warm_frac": i2.bytes_spmv_f64 / warm / 1e3 / HBM_PEAK_GBS,
-        "traffic_warm": traffic_from_profiles(SPMV_KERNELS[spk.KERNEL_NAMES[i2.kernel]] + "@c2",
-                                              i2.bytes_spmv_f64),
-        "note": "cold: an event pair around each launch after 1 GiB of scratch was read (the 182 MB SELL "
-                "layout no longer in the 256 MB Infinity Cache; includes one launch's dispatch); warm: one "
-                "event pair around the step's 100 back-to-back launches",
+        "traffic_warm": traffic_from_profiles(spmv_kernel_name(spk, i2) + "@c2", i2.bytes_spmv_f64),
+        "note": "cold: an event pair around each launch after 1 GiB of scratch was read (the SELL layout, "
+                "%.0f MB, no longer in the 256 MB Infinity Cache; includes one launch's dispatch); warm: one "
+                "event pair around the step's 100 back-to-back launches" % (i2.format_bytes_spmv_f64 / 1e6),
     }
 
     extras = None
@@ -670,10 +679,12 @@ def bench_all(args):
         "c3": c3,
         "c5_served": serve,
         "roofline": {
-            "kernel": "k_pcg_spmv_sell_wide<double, short> (C3 FP64 PCG product q = A p with p.q partials)",
+            "kernel": "k_pcg_spmv_sell_wide<double, %s> (C3 FP64 PCG product q = A p with p.q partials%s)"
+                      % (sell_ci(i3), ", column offsets shared per slice" if i3.lanes == 0 else ""),
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": traffic_from_profiles("k_pcg_spmv_sell_wide<double, short>@c3", i3.bytes_spmv_f64),
+            "traffic": traffic_from_profiles("k_pcg_spmv_sell_wide<double, %s>@c3" % sell_ci(i3),
+                                             i3.bytes_spmv_f64),
             "bytes_per_launch": i3.bytes_spmv_f64, "format_bytes_per_launch": i3.format_bytes_spmv_f64,
             "us_avg": prod_us, "launches_timed": prod_n,
             "measured_gbps": stream_bw, "frac_of_copy": achieved / stream_bw["copy"],
@@ -681,8 +692,9 @@ def bench_all(args):
             "note": "achieved = 12 nnz + 4(n+1) + 16n algorithmic bytes of one C3 FP64 product (q = A p with "
                     "the per-block p.q partials) / its average duration: an event pair on the solve stream "
                     "around each of the probe's product kernels in the timed steps (the one-block fold of the "
-                    "partials, about 4.6 us, runs after the pair); the 1.1 GB SELL layout is 4x the 256 MB "
-                    "Infinity Cache, so the bytes come from HBM",
+                    "partials, about 4.6 us, runs after the pair); the SELL layout (format_bytes_per_launch "
+                    "with p and q) is several times the 256 MB Infinity Cache, so the bytes come from HBM; "
+                    "format bytes below the algorithmic ones are the layout's index compression",
         },
         "extras": extras,
     }

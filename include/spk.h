@@ -144,7 +144,9 @@ typedef struct {
     int32_t kernel;          /* SPK_KERNEL_* in use */
     int64_t nnz;
     int32_t lanes;           /* VECTOR: lanes per row; STREAM: rows per tile;
-                                MERGE: items per tile */
+                                MERGE: items per tile; SELL: column-offset
+                                bits per entry (16 or 32), 0 with offsets
+                                shared per slice */
     int32_t has_f32;         /* FP32 value copy present */
     int32_t row_min, row_max;
     int32_t row_p50, row_p99;  /* upper bounds from a log2 histogram */
@@ -168,7 +170,10 @@ typedef struct {
                                        storage the selected kernel reads (equal
                                        to bytes_spmv_f64 except for SELL:
                                        (8 + w) padded_nnz + 4 slices + n + 16 n,
-                                       w = 2 or 4 bytes per column offset) */
+                                       w = 2 or 4 bytes per column offset;
+                                       with shared offsets 8 padded_nnz +
+                                       4 slices + 4 (offset-list entries) +
+                                       4 n (masks) + 16 n) */
     int64_t format_bytes_spmv_f32;  /* same for FP32 values and vectors */
     int64_t stored_nnz;             /* entries the kernel reads, padding included */
     double gershgorin;              /* max_i sum_j |a_ij| / |a_ii|: a bound on the
@@ -203,9 +208,16 @@ int spk_mat_create_csr(int32_t n, int64_t nnz, const int32_t *rowptr,
 
 /* Force an SpMV kernel family (testing and A/B runs).  param: lanes per row
  * for VECTOR (1..64, power of two), rows per tile for STREAM (0 = automatic),
- * column-offset bits for SELL (0 = automatic, 16 or 32; SPK_EINVAL when the
- * offsets do not fit or a row exceeds 65535 entries; row lengths above 255
- * are stored in 16 bits), the window sigma for SELL_SIGMA (a multiple of 64;
+ * column offsets for SELL: 16 or 32 (bits per entry, one offset per lane;
+ * SPK_EINVAL when the offsets do not fit or a row exceeds 65535 entries; row
+ * lengths above 255 are stored in 16 bits), 1 (shared: each 64-row slice
+ * stores its sorted list of distinct offsets once and each row a 32-bit mask
+ * of the list positions it uses, the other positions holding zeros that are
+ * never multiplied; SPK_EINVAL unless every row has strictly increasing
+ * columns, every slice's rows use at most 32 distinct offsets and the
+ * stored entries grow by at most 1/16) or 0 (automatic: shared when the
+ * matrix qualifies, which stencils do, else 16 when the offsets fit, else
+ * 32), the window sigma for SELL_SIGMA (a multiple of 64;
  * 0 = 4096; offsets as for SELL with 0), for SLICED 0
  * (automatic: the merge path over the slices when 8n + nnz < 2^31, else
  * lanes per slice row), a power of two in 1..64 (lanes per slice row) or

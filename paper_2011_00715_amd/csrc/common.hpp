@@ -103,6 +103,7 @@ struct SysDesc {
     const float *sell_val32;
     const uint16_t *sell_len16;  // row lengths when some row has more than 255 entries
     const int32_t *sell_perm;    // SELL-C-sigma: matrix row of each sorted position
+    const uint32_t *sell_mask;   // shared offsets: per-row position masks, or null
 };
 
 // ------------------------------------------------------------------ host helpers

@@ -300,7 +300,7 @@ __global__ __launch_bounds__(kBlock) void k_resid_sell(B a)
     if (kGate != kGateNone && !gate_open(d.st, kGate)) return;
     const double *__restrict__ b = d.b;
     double *__restrict__ r = d.r;
-    const SellView sv{d.sell_ptr, d.sell_col, d.sell_len, d.sell_plain, d.sell_len16, d.sell_perm};
+    const SellView sv{d.sell_ptr, d.sell_col, d.sell_len, d.sell_plain, d.sell_len16, d.sell_perm, d.sell_mask};
     double rr = 0.0, bb = 0.0;
     sell_slices<double, CI, U>(d.n, sell_first(local_block(a)), d.nblk * (kBlock / kWave), sv,
                                d.sell_val, d.x, [] { return true; }, [&](int i, double y) {
@@ -590,7 +590,7 @@ __global__ __launch_bounds__(kBlock) void k_pcg_spmv_sell(B a)
     const V *__restrict__ p = Vecs<V>::p(d);
     V *__restrict__ q = Vecs<V>::q(d);
     const V *__restrict__ val = sell_vals<V>(d);
-    const SellView sv{d.sell_ptr, d.sell_col, d.sell_len, d.sell_plain, d.sell_len16, d.sell_perm};
+    const SellView sv{d.sell_ptr, d.sell_col, d.sell_len, d.sell_plain, d.sell_len16, d.sell_perm, d.sell_mask};
     V acc = V(0);
     const bool run = gate_ok(g, Vecs<V>::gate);
     sell_slices<V, CI, U>(
@@ -617,7 +617,7 @@ __global__ __launch_bounds__(kBlock) void k_pcg_spmv_sell_wide(One a, double *__
     const V *__restrict__ p = Vecs<V>::p(d);
     V *__restrict__ q = Vecs<V>::q(d);
     const V *__restrict__ val = sell_vals<V>(d);
-    const SellView sv{d.sell_ptr, d.sell_col, d.sell_len, d.sell_plain, d.sell_len16, d.sell_perm};
+    const SellView sv{d.sell_ptr, d.sell_col, d.sell_len, d.sell_plain, d.sell_len16, d.sell_perm, d.sell_mask};
     V acc = V(0);
     const bool run = gate_ok(g, Vecs<V>::gate);
     sell_slices<V, CI, U>(
@@ -975,7 +975,7 @@ __global__ __launch_bounds__(kBlock) void k_pcg_fused_sell(B a)
         return;
     }
     auto pn = [&](int c) -> V { return fresh ? z[c] : fma(beta, pold[c], z[c]); };
-    const SellView sv{d.sell_ptr, d.sell_col, d.sell_len, d.sell_plain, d.sell_len16, d.sell_perm};
+    const SellView sv{d.sell_ptr, d.sell_col, d.sell_len, d.sell_plain, d.sell_len16, d.sell_perm, d.sell_mask};
     V acc = V(0);
     sell_slices_g<V, CI, U>(d.n, sell_first(local_block(a)), d.nblk * (kBlock / kWave), sv, sell_vals<V>(d), pn,
                             [] { return true; }, [&](int i, V y) {

@@ -103,11 +103,14 @@ constexpr int64_t kFusedMargin = 16ll << 20;
 static bool fused_pays(const spk_mat *A, int bit)
 {
     const int ns = ceil_div(A->n, kSell);
-    const int64_t extra = (A->sell_len16 ? A->n : 0) + (A->sell_perm ? 4ll * A->n : 0);
+    // index bytes beyond the policy's own count (cw per entry, one per row):
+    // 16-bit lengths, or shared offsets with row masks, and a permutation
+    const int cw = A->sell_mask ? 0 : A->sell_cw;
+    const int64_t extra =
+        A->sell_idx_bytes - (int64_t)cw * A->sell_nnz - A->n + (A->sell_perm ? 4ll * A->n : 0);
     if (A->stream_loads) return true;
-    const int six = sell_load_policy(A->sell_nnz, A->sell_cw, ns, A->n, 6, kIterCacheBudget - extra);
-    const int seven =
-        sell_load_policy(A->sell_nnz, A->sell_cw, ns, A->n, 7, kIterCacheBudget - extra - kFusedMargin);
+    const int six = sell_load_policy(A->sell_nnz, cw, ns, A->n, 6, kIterCacheBudget - extra);
+    const int seven = sell_load_policy(A->sell_nnz, cw, ns, A->n, 7, kIterCacheBudget - extra - kFusedMargin);
     return !((six & bit) && !(seven & bit));
 }
 
@@ -173,6 +176,7 @@ static int get_workspace(spk_mat *A, bool mixed, Workspace **out, hipStream_t s)
         d.sell_plain = A->sell_plain;
         d.sell_len16 = A->sell_len16;
         d.sell_perm = A->sell_perm;
+        d.sell_mask = A->sell_mask;
         d.p2 = w->p2;
     }
     if (mixed && !w->has_mixed) {
@@ -716,7 +720,7 @@ int cheb_step(spk_mat *A, const ChebStep<V> &c, V *tmp, hipStream_t s)
     constexpr bool f64 = std::is_same<V, double>::value;
     const dim3 g(A->nblk), t(kBlock);
     if (A->kernel == SPK_KERNEL_SELL) {
-        const SellView sv{A->sell_ptr, A->sell_col, A->sell_len, A->sell_plain, A->sell_len16, A->sell_perm};
+        const SellView sv{A->sell_ptr, A->sell_col, A->sell_len, A->sell_plain, A->sell_len16, A->sell_perm, A->sell_mask};
         // up to one wavefront per slice (no partial sums to keep per block)
         const dim3 gs(std::max(1, std::min(ceil_div(ceil_div(A->n, kSell), kBlock / kWave), 16384)));
         const int n = A->n;

@@ -302,7 +302,8 @@ int launch_spmv(const spk_mat *A, const V *val, const V *x, V *y, hipStream_t s,
             set_error("internal: gated SELL SpMV or no SELL layout");
             return SPK_EINVAL;
         }
-        const SellView sv{A->sell_ptr, A->sell_col, A->sell_len, A->sell_plain_spmv, A->sell_len16, A->sell_perm};
+        const SellView sv{A->sell_ptr, A->sell_col, A->sell_len, A->sell_plain_spmv, A->sell_len16, A->sell_perm,
+                          A->sell_mask};
         const V *sval = std::is_same<V, double>::value ? (const V *)A->sell_val : (const V *)A->sell_val32;
         (void)val;
         // up to one wavefront per slice
@@ -372,7 +373,7 @@ void update_info(spk_mat *A)
     I.lanes = A->kernel == SPK_KERNEL_SLICED ? (A->xs_merge ? kMergeItems : A->lanes)
               : A->kernel == SPK_KERNEL_VECTOR ? A->lanes
               : A->kernel == SPK_KERNEL_STREAM ? A->R
-              : A->kernel == SPK_KERNEL_SELL ? 8 * A->sell_cw : kMergeItems;
+              : A->kernel == SPK_KERNEL_SELL ? (A->sell_mask ? 0 : 8 * A->sell_cw) : kMergeItems;
     I.has_f32 = A->val32 != nullptr;
     I.row_min = A->n ? S.min_len : 0;
     I.row_max = S.max_len;
@@ -404,10 +405,11 @@ void update_info(spk_mat *A)
     if (A->kernel == SPK_KERNEL_SELL && A->sell_cw) {
         const int64_t ns = (nn + kSell - 1) / kSell;
         I.stored_nnz = A->sell_nnz;
-        // + the row permutation of SELL-C-sigma and 16-bit lengths of long rows
-        const int64_t extra = (A->sell_perm ? 4 * nn : 0) + (A->sell_len16 ? nn : 0);
-        I.format_bytes_spmv_f64 = (8 + A->sell_cw) * A->sell_nnz + 4 * (ns + 1) + nn + 16 * nn + extra;
-        I.format_bytes_spmv_f32 = (4 + A->sell_cw) * A->sell_nnz + 4 * (ns + 1) + nn + 8 * nn + extra;
+        // offsets and row lengths (or shared offsets and row masks), plus the
+        // row permutation of SELL-C-sigma
+        const int64_t extra = A->sell_idx_bytes + (A->sell_perm ? 4 * nn : 0);
+        I.format_bytes_spmv_f64 = 8 * A->sell_nnz + 4 * (ns + 1) + 16 * nn + extra;
+        I.format_bytes_spmv_f32 = 4 * A->sell_nnz + 4 * (ns + 1) + 8 * nn + extra;
     } else if (A->kernel == SPK_KERNEL_SLICED && A->xs_ptr) {
         // stacked slices: 8n + 1 row pointers; the 8n partial products are
         // written once and read once by the summing pass
@@ -550,11 +552,14 @@ static void free_sell(spk_mat *A)
 {
     if (A->sell_cw) {
         const int64_t ns = (A->n + kSell - 1) / kSell;
-        A->bytes -= 4 * (ns + 1) + (int64_t)(A->sell_cw + 8) * A->sell_nnz + A->n;
-        if (A->sell_len16) A->bytes -= A->n;
+        A->bytes -= 4 * (ns + 1) + 8 * A->sell_nnz + A->sell_idx_bytes;
         if (A->sell_perm) A->bytes -= 4ll * A->n;
         if (A->sell_val32) A->bytes -= 4 * A->sell_nnz;
     }
+    hipFree(A->sell_mask);
+    A->sell_mask = nullptr;
+    A->sell_idx_bytes = 0;
+    A->sell_req = -1;
     hipFree(A->sell_ptr);
     hipFree(A->sell_col);
     hipFree(A->sell_len);
@@ -577,18 +582,135 @@ static void free_sell(spk_mat *A)
 }
 
 
+// Shared offsets for a SELL-64 layout of rows in matrix order: every slice's
+// rows must have strictly increasing columns and use between them at most
+// kSellSharedMax distinct offsets, and the padding may grow by at most 1/16
+// over the per-lane layout.  On success: slice widths u (the list sizes),
+// the concatenated offset lists and each row's position mask.
+static bool shared_offsets(const std::vector<int32_t> &rp, const std::vector<int32_t> &cl, int n,
+                           std::vector<int32_t> &u, std::vector<int32_t> &offs, std::vector<uint32_t> &mask)
+{
+    const int ns = ceil_div(n, kSell);
+    u.assign((size_t)ns, 0);
+    offs.clear();
+    mask.assign((size_t)n, 0u);
+    int64_t shared = 0, lane = 0;
+    std::vector<int32_t> un, tmp;
+    un.reserve(2 * kSellSharedMax);
+    tmp.reserve(2 * kSellSharedMax);
+    for (int k = 0; k < ns; ++k) {
+        const int r0 = k * kSell, r1 = std::min(n, r0 + kSell);
+        un.clear();
+        int mx = 0;
+        for (int r = r0; r < r1; ++r) {
+            const int a = rp[r], e = rp[r + 1];
+            mx = std::max(mx, e - a);
+            // merge the row's sorted offsets into the slice's list
+            tmp.clear();
+            size_t i = 0;
+            for (int j = a; j < e; ++j) {
+                if (j > a && cl[j] <= cl[j - 1]) return false;  // unsorted or repeated column
+                const int32_t o = cl[j] - r;
+                while (i < un.size() && un[i] < o) tmp.push_back(un[i++]);
+                if (i < un.size() && un[i] == o) ++i;
+                tmp.push_back(o);
+            }
+            while (i < un.size()) tmp.push_back(un[i++]);
+            un.swap(tmp);
+            if ((int)un.size() > kSellSharedMax) return false;
+        }
+        for (int r = r0; r < r1; ++r) {
+            uint32_t m = 0;
+            size_t i = 0;
+            for (int j = rp[r]; j < rp[r + 1]; ++j) {
+                const int32_t o = cl[j] - r;
+                while (un[i] != o) ++i;
+                m |= 1u << i;
+            }
+            mask[(size_t)r] = m;
+        }
+        u[(size_t)k] = (int32_t)un.size();
+        offs.insert(offs.end(), un.begin(), un.end());
+        shared += (int64_t)un.size();
+        lane += mx;
+    }
+    return shared * 16 <= lane * 17;
+}
+
+// The shared-offset layout from shared_offsets' result: slice s spans
+// 64 u[s] elements; its offsets sit at element sell_ptr[s] / 64 of sell_col
+// (int32); values are filled on the device from the row masks.
+static int build_sell_shared(spk_mat *A, hipStream_t s, const std::vector<int32_t> &u,
+                             const std::vector<int32_t> &offs, const std::vector<uint32_t> &mask)
+{
+    const int n = A->n;
+    const int ns = ceil_div(n, kSell);
+    std::vector<int32_t> sp((size_t)ns + 1);
+    int64_t acc = 0;
+    int wmax = 0;
+    for (int k = 0; k < ns; ++k) {
+        sp[k] = (int32_t)acc;
+        acc += (int64_t)kSell * u[(size_t)k];
+        wmax = std::max(wmax, u[(size_t)k]);
+        if (acc > 0x7fffffffLL) { set_error("SELL layout exceeds 2^31 entries"); return SPK_EINVAL; }
+    }
+    sp[ns] = (int32_t)acc;
+    const size_t m = acc > 0 ? (size_t)acc : 1;
+    const size_t no = offs.size() > 0 ? offs.size() : 1;
+    SPK_HIP(hipMalloc(&A->sell_ptr, sizeof(int32_t) * ((size_t)ns + 1)));
+    SPK_HIP(hipMalloc(&A->sell_col, sizeof(int32_t) * no));
+    SPK_HIP(hipMalloc(&A->sell_mask, sizeof(uint32_t) * (size_t)n));
+    SPK_HIP(hipMalloc(&A->sell_val, sizeof(double) * m));
+    SPK_HIP(hipMemcpyAsync(A->sell_ptr, sp.data(), sizeof(int32_t) * ((size_t)ns + 1), hipMemcpyHostToDevice, s));
+    if (!offs.empty())
+        SPK_HIP(hipMemcpyAsync(A->sell_col, offs.data(), sizeof(int32_t) * offs.size(), hipMemcpyHostToDevice, s));
+    SPK_HIP(hipMemcpyAsync(A->sell_mask, mask.data(), sizeof(uint32_t) * (size_t)n, hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(k_sell_fill_shared, dim3(grid_for(n)), dim3(kBlock), 0, s, n, A->rowptr, A->val,
+                       A->sell_ptr, A->sell_mask, A->sell_val);
+    SPK_HIP(hipGetLastError());
+    A->sell_cw = 4;
+    A->sell_sigma = 0;
+    A->sell_u = pick_sell_u(wmax);
+    A->sell_nnz = acc;
+    A->sell_idx_bytes = 4 * (int64_t)offs.size() + 4ll * n;
+    // the load policy counts cw bytes per entry plus one byte per row:
+    // here no bytes per entry and the rest of the index bytes in the budget
+    const int64_t extra = A->sell_idx_bytes - n;
+    A->sell_plain = A->stream_loads ? 0 : sell_load_policy(acc, 0, ns, n, 6, kIterCacheBudget - extra);
+    A->sell_plain_spmv = A->stream_loads ? 0 : sell_load_policy(acc, 0, ns, n, 2, kSpmvCacheBudget - extra);
+    A->bytes += 4 * ((int64_t)ns + 1) + 8 * acc + A->sell_idx_bytes;
+    if (A->val32) {
+        SPK_HIP(hipMalloc(&A->sell_val32, sizeof(float) * m));
+        hipLaunchKernelGGL(k_to_f32, dim3(grid_for((int64_t)m)), dim3(kBlock), 0, s, (int64_t)m, A->sell_val,
+                           A->sell_val32);
+        SPK_HIP(hipGetLastError());
+        A->bytes += 4 * acc;
+    }
+    // the host vectors are read by the copies above
+    SPK_HIP(hipStreamSynchronize(s));
+    return SPK_OK;
+}
+
 // Build the SELL-64 copy: slice widths from rowptr on the host (setup only),
 // entries filled by one device lane per layout position.  cw: 2 (int16
-// offsets), 4 (int32) or 0 (int16 when every |col - row| fits).  sigma > 0
-// builds SELL-C-sigma: within each window of sigma rows the rows are ordered
-// by length, longest first (ties in row order), so that the rows sharing a
-// slice have similar lengths and the padding shrinks on skewed matrices; the
-// layout then carries the permutation.  Rows longer than 255 entries store
-// their lengths in 16 bits.
+// offsets), 4 (int32), 1 (offsets shared per slice; SPK_EINVAL when the
+// matrix does not qualify) or 0 (shared when the matrix qualifies, else int16
+// when every |col - row| fits, else int32).  sigma > 0 builds SELL-C-sigma:
+// within each window of sigma rows the rows are ordered by length, longest
+// first (ties in row order), so that the rows sharing a slice have similar
+// lengths and the padding shrinks on skewed matrices; the layout then
+// carries the permutation.  Rows longer than 255 entries store their
+// lengths in 16 bits.
 static int setup_sell(spk_mat *A, hipStream_t s, int cw, int sigma = 0)
 {
-    if (cw == 0) cw = A->stats.max_delta <= 32767 ? 2 : 4;
-    if (A->sell_cw == cw && A->sell_sigma == sigma) return SPK_OK;
+    if (A->sell_cw && A->sell_req == cw && A->sell_sigma == sigma) return SPK_OK;
+    const int req = cw;
+    const bool try_shared = (cw == 0 || cw == 1) && sigma == 0 && A->n > 0 && A->stats.max_len <= kSellSharedMax;
+    if (cw == 1 && !try_shared) {
+        set_error("shared SELL offsets need rows in matrix order of at most %d entries", kSellSharedMax);
+        return SPK_EINVAL;
+    }
+    if (cw == 0 || cw == 1) cw = A->stats.max_delta <= 32767 ? 2 : 4;
     if (cw == 2 && A->stats.max_delta > 32767) {
         set_error("column offsets up to %d do not fit int16", A->stats.max_delta);
         return SPK_EINVAL;
@@ -602,6 +724,24 @@ static int setup_sell(spk_mat *A, hipStream_t s, int cw, int sigma = 0)
     std::vector<int32_t> rp((size_t)n + 1);
     SPK_HIP(hipMemcpyAsync(rp.data(), A->rowptr, sizeof(int32_t) * ((size_t)n + 1), hipMemcpyDeviceToHost, s));
     SPK_HIP(hipStreamSynchronize(s));
+    if (try_shared) {
+        std::vector<int32_t> cl((size_t)A->nnz), u, offs;
+        std::vector<uint32_t> mask;
+        if (A->nnz > 0) {
+            SPK_HIP(hipMemcpyAsync(cl.data(), A->col, sizeof(int32_t) * (size_t)A->nnz, hipMemcpyDeviceToHost, s));
+            SPK_HIP(hipStreamSynchronize(s));
+        }
+        if (shared_offsets(rp, cl, n, u, offs, mask)) {
+            const int rc = build_sell_shared(A, s, u, offs, mask);
+            if (rc == SPK_OK) A->sell_req = req;
+            return rc;
+        }
+        if (req == 1) {
+            set_error("the rows of a slice use more than %d distinct column offsets (or are unsorted)",
+                      kSellSharedMax);
+            return SPK_EINVAL;
+        }
+    }
     std::vector<int32_t> perm;
     if (sigma > 0) {
         perm.resize((size_t)n);
@@ -651,13 +791,15 @@ static int setup_sell(spk_mat *A, hipStream_t s, int cw, int sigma = 0)
                            A->sell_len, A->sell_len16);
     SPK_HIP(hipGetLastError());
     A->sell_cw = cw;
+    A->sell_req = req;
     A->sell_sigma = sigma;
     A->sell_u = pick_sell_u(wmax);
     A->sell_nnz = acc;
+    A->sell_idx_bytes = (int64_t)cw * acc + n + (len16 ? n : 0);
     const int64_t extra = (len16 ? n : 0) + (sigma > 0 ? 4ll * n : 0);
     A->sell_plain = A->stream_loads ? 0 : sell_load_policy(acc, cw, ns, n, 6, kIterCacheBudget - extra);
     A->sell_plain_spmv = A->stream_loads ? 0 : sell_load_policy(acc, cw, ns, n, 2, kSpmvCacheBudget - extra);
-    A->bytes += 4 * ((int64_t)ns + 1) + (int64_t)(cw + 8) * acc + n + extra;
+    A->bytes += 4 * ((int64_t)ns + 1) + 8 * acc + A->sell_idx_bytes + (sigma > 0 ? 4ll * n : 0);
     if (A->val32) {
         SPK_HIP(hipMalloc(&A->sell_val32, sizeof(float) * m));
         hipLaunchKernelGGL(k_to_f32, dim3(grid_for((int64_t)m)), dim3(kBlock), 0, s, (int64_t)m, A->sell_val,
@@ -957,11 +1099,11 @@ int spk_mat_set_kernel(spk_mat *A, int kernel, int32_t param, void *stream)
         A->R = 256;
         break;
     case SPK_KERNEL_SELL: {
-        if (param != 0 && param != 16 && param != 32) {
-            set_error("SELL column width %d not in {0, 16, 32}", param);
+        if (param != 0 && param != 1 && param != 16 && param != 32) {
+            set_error("SELL column offsets %d not in {0, 1, 16, 32}", param);
             return SPK_EINVAL;
         }
-        const int rc = setup_sell(A, s, param / 8);
+        const int rc = setup_sell(A, s, param == 1 ? 1 : param / 8);
         if (rc) return rc;
         if (A->val32) {
             const int r2 = ensure_f32(A, s);

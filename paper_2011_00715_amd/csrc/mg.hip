@@ -143,7 +143,7 @@ static int launch_rows(spk_mat *A, const V *x, F f, double *part, int *np, const
     constexpr bool f64 = std::is_same<V, double>::value;
     const int n = A->n;
     if (A->kernel == SPK_KERNEL_SELL) {
-        const SellView sv{A->sell_ptr, A->sell_col, A->sell_len, A->sell_plain, A->sell_len16, A->sell_perm};
+        const SellView sv{A->sell_ptr, A->sell_col, A->sell_len, A->sell_plain, A->sell_len16, A->sell_perm, A->sell_mask};
         const int grid = std::max(1, std::min(ceil_div(ceil_div(n, kSell), kBlock / kWave), kMgMaxPart));
         const V *sval = f64 ? (const V *)A->sell_val : (const V *)A->sell_val32;
         with_sell_u(A->sell_u, [&](auto uc) {

@@ -67,12 +67,12 @@ static MultiDesc multi_desc(const spk_mat *A, int K)
     d.ntiles = A->ntiles;
     // the multi kernels walk SELL slices in matrix order with one-byte row
     // lengths; a sorted (SELL-C-sigma) or long-row layout goes through CSR
-    d.sell = A->kernel == SPK_KERNEL_SELL && A->sell_cw != 0 && !A->sell_perm && A->sell_len;
+    d.sell = A->kernel == SPK_KERNEL_SELL && A->sell_cw != 0 && !A->sell_perm && (A->sell_len || A->sell_mask);
     d.rowptr = A->rowptr;
     d.col = A->col;
     d.val = A->val;
     d.dinv = A->dinv;
-    d.sv = SellView{A->sell_ptr, A->sell_col, A->sell_len};
+    d.sv = SellView{A->sell_ptr, A->sell_col, A->sell_len, 0, nullptr, nullptr, A->sell_mask};
     d.sell_val = A->sell_val;
     return d;
 }

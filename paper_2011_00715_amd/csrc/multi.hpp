@@ -94,30 +94,53 @@ __device__ __forceinline__ void csr_row_multi(int a, int e, const int32_t *__res
 constexpr int kMultiPairs = 4;
 constexpr int kOneRoundPairs = 3;
 
-template <class CI, int K, bool kOneRound = false>
+//
+// SH: shared offsets (see the SELL-64 notes): offsets from the slice's list,
+// rlen the row's position mask, gathered rows clamped into [0, n).
+template <class CI, int K, bool kOneRound = false, bool SH = false>
 __device__ __forceinline__ void sell_row_multi(const SellView &sv, const double *__restrict__ val,
                                                const double *__restrict__ X, int32_t b, int slen,
-                                               int rlen, int lane, int row, double acc[K])
+                                               int rlen, int lane, int row, int n, double acc[K])
 {
+    static_assert(!SH || std::is_same<CI, int32_t>::value, "shared offsets are int32");
     constexpr int PM = K <= 8 ? kMultiPairs : 1;
     using CP = typename Pair2<CI>::type;
     using VP = typename Pair2<double>::type;
     const CP *__restrict__ cp = reinterpret_cast<const CP *>(reinterpret_cast<const CI *>(sv.col) + b) + lane;
+    const int32_t *__restrict__ ou =
+        reinterpret_cast<const int32_t *>(sv.col) + (__builtin_amdgcn_readfirstlane(b) >> 6);
     const VP *__restrict__ vp = reinterpret_cast<const VP *>(val + b) + lane;
+    auto offsets = [&](int p) -> CP {
+        if constexpr (SH) {
+            CP c;
+            c.x = ou[2 * p];
+            c.y = ou[2 * p + 1];
+            return c;
+        } else {
+            return ld_stream(cp + (size_t)p * kSell);
+        }
+    };
+    auto real = [&](int k) -> bool {
+        if constexpr (SH) return ((unsigned)rlen >> k) & 1u;
+        else return k < rlen;
+    };
     const int np = slen >> 1;
     const bool odd = slen & 1;
     CI ct = CI(0);
     double at = 0.0;
     if (odd) {
         const size_t t = (size_t)b + (size_t)np * (2 * kSell) + lane;
-        ct = ld_stream(reinterpret_cast<const CI *>(sv.col) + t);
+        if constexpr (SH) ct = ou[2 * np];
+        else ct = ld_stream(reinterpret_cast<const CI *>(sv.col) + t);
         at = ld_stream(val + t);
     }
 #pragma unroll
     for (int q = 0; q < K; ++q) acc[q] = 0.0;
     auto gather = [&](int off, double xr[K]) {
+        int j = row + off;
+        if constexpr (SH) j = min(max(j, 0), n - 1);
 #pragma unroll
-        for (int q = 0; q < K; ++q) xr[q] = X[(size_t)(row + off) * K + q];
+        for (int q = 0; q < K; ++q) xr[q] = X[(size_t)j * K + q];
     };
     auto madd = [&](double a, const double xr[K]) {
 #pragma unroll
@@ -138,7 +161,7 @@ __device__ __forceinline__ void sell_row_multi(const SellView &sv, const double 
 #pragma unroll
             for (int u = 0; u < P1; ++u) {
                 const int p = u < np ? u : np - 1;
-                c[u] = ld_stream(cp + (size_t)p * kSell);
+                c[u] = offsets(p);
                 a[u] = ld_stream(vp + (size_t)p * kSell);
             }
         double xv[2 * P1 + 1][K];
@@ -151,10 +174,10 @@ __device__ __forceinline__ void sell_row_multi(const SellView &sv, const double 
 #pragma unroll
         for (int u = 0; u < P1; ++u)
             if (u < np) {
-                if (2 * u < rlen) madd(a[u].x, xv[2 * u]);
-                if (2 * u + 1 < rlen) madd(a[u].y, xv[2 * u + 1]);
+                if (real(2 * u)) madd(a[u].x, xv[2 * u]);
+                if (real(2 * u + 1)) madd(a[u].y, xv[2 * u + 1]);
             }
-        if (odd && slen - 1 < rlen) madd(at, xv[2 * P1]);
+        if (odd && real(slen - 1)) madd(at, xv[2 * P1]);
         return;
     }
     if (PM > 1 && np >= 1 && np <= PM) {
@@ -164,7 +187,7 @@ __device__ __forceinline__ void sell_row_multi(const SellView &sv, const double 
 #pragma unroll
         for (int u = 0; u < PM; ++u) {
             const int p = u < np ? u : np - 1;
-            c[u] = ld_stream(cp + (size_t)p * kSell);
+            c[u] = offsets(p);
             a[u] = ld_stream(vp + (size_t)p * kSell);
         }
         double xa[2][K], xb[2][K];
@@ -177,8 +200,8 @@ __device__ __forceinline__ void sell_row_multi(const SellView &sv, const double 
                 gather((int)c[u + 1].y, xb[1]);
             }
             if (u < np) {
-                if (2 * u < rlen) madd(a[u].x, xa[0]);
-                if (2 * u + 1 < rlen) madd(a[u].y, xa[1]);
+                if (real(2 * u)) madd(a[u].x, xa[0]);
+                if (real(2 * u + 1)) madd(a[u].y, xa[1]);
             }
 #pragma unroll
             for (int q = 0; q < K; ++q) {
@@ -189,16 +212,16 @@ __device__ __forceinline__ void sell_row_multi(const SellView &sv, const double 
     } else {
         // wide slices (or K = 16): one pair per round
         for (int p = 0; p < np; ++p) {
-            const CP c = ld_stream(cp + (size_t)p * kSell);
+            const CP c = offsets(p);
             const VP a = ld_stream(vp + (size_t)p * kSell);
             double x0[K], x1[K];
             gather((int)c.x, x0);
             gather((int)c.y, x1);
-            if (2 * p < rlen) madd(a.x, x0);
-            if (2 * p + 1 < rlen) madd(a.y, x1);
+            if (real(2 * p)) madd(a.x, x0);
+            if (real(2 * p + 1)) madd(a.y, x1);
         }
     }
-    if (odd && slen - 1 < rlen) {
+    if (odd && real(slen - 1)) {
         double xt[K];
         gather((int)ct, xt);
         madd(at, xt);
@@ -213,9 +236,9 @@ __device__ __forceinline__ void sell_row_multi(const SellView &sv, const double 
 // products are 8K contiguous bytes, so storing them from the lanes directly
 // writes 64 partial segments per instruction; the flat pass writes whole
 // ones (K = 8: 118 -> 99 us on the 7-point 128^3 product).
-template <class CI, int K, bool kOneRound, class Flat>
-__device__ __forceinline__ void multi_sell_staged(const MultiDesc &d, int l, const double *__restrict__ X,
-                                                  double *stage, Flat &&flat)
+template <class CI, int K, bool kOneRound, bool SH, class Flat>
+__device__ __forceinline__ void multi_sell_walk(const MultiDesc &d, int l, const double *__restrict__ X,
+                                                double *stage, Flat &&flat)
 {
     const int lane = threadIdx.x & (kWave - 1);
     const int ns = (d.n + kSell - 1) / kSell;
@@ -224,8 +247,9 @@ __device__ __forceinline__ void multi_sell_staged(const MultiDesc &d, int l, con
         const int row = s * kSell + lane;
         if (row < d.n) {
             double acc[K];
-            sell_row_multi<CI, K, kOneRound>(d.sv, d.sell_val, X, b, (e - b) / kSell, d.sv.len[row], lane, row,
-                                             acc);
+            const int rl = SH ? (int)d.sv.mask[row] : (int)d.sv.len[row];
+            sell_row_multi<CI, K, kOneRound, SH>(d.sv, d.sell_val, X, b, (e - b) / kSell, rl, lane, row, d.n,
+                                                 acc);
 #pragma unroll
             for (int q = 0; q < K; ++q) stage[lane * K + q] = acc[q];
         }
@@ -237,6 +261,19 @@ __device__ __forceinline__ void multi_sell_staged(const MultiDesc &d, int l, con
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
+}
+
+template <class CI, int K, bool kOneRound, class Flat>
+__device__ __forceinline__ void multi_sell_staged(const MultiDesc &d, int l, const double *__restrict__ X,
+                                                  double *stage, Flat &&flat)
+{
+    if constexpr (std::is_same<CI, int32_t>::value) {
+        if (d.sv.mask) {
+            multi_sell_walk<CI, K, kOneRound, true>(d, l, X, stage, flat);
+            return;
+        }
+    }
+    multi_sell_walk<CI, K, kOneRound, false>(d, l, X, stage, flat);
 }
 
 // Row walk of block l (of nblk) of a multi kernel: SELL slices in
@@ -254,7 +291,15 @@ __device__ __forceinline__ void multi_rows(const MultiDesc &d, int l, int j, con
             const int32_t b = d.sv.ptr[s], e = d.sv.ptr[s + 1];
             const int row = s * kSell + lane;
             if (row < d.n) {
-                sell_row_multi<CI, K>(d.sv, d.sell_val, X, b, (e - b) / kSell, d.sv.len[row], lane, row, acc);
+                if constexpr (std::is_same<CI, int32_t>::value) {
+                    if (d.sv.mask) {
+                        sell_row_multi<CI, K, false, true>(d.sv, d.sell_val, X, b, (e - b) / kSell,
+                                                           (int)d.sv.mask[row], lane, row, d.n, acc);
+                        fn(row, acc);
+                        continue;
+                    }
+                }
+                sell_row_multi<CI, K>(d.sv, d.sell_val, X, b, (e - b) / kSell, d.sv.len[row], lane, row, d.n, acc);
                 fn(row, acc);
             }
         }

@@ -131,6 +131,10 @@ struct spk_mat {
     uint16_t *sell_len16 = nullptr;  // row lengths when some row exceeds 255 entries (sell_len then null)
     int32_t *sell_perm = nullptr;    // SELL-C-sigma: matrix row of each sorted position, or null
     int sell_sigma = 0;              // SELL-C-sigma window (rows), 0: rows in matrix order
+    uint32_t *sell_mask = nullptr;   // shared offsets: per-row position masks (sell_col then
+                                     // holds each slice's int32 offsets; sell_len is null)
+    int64_t sell_idx_bytes = 0;      // bytes of offsets and row lengths / masks
+    int sell_req = -1;               // the offset request the layout was built for (setup_sell's cw)
     double *sell_val = nullptr;
     float *sell_val32 = nullptr;
     // column-sliced copy (built when the SLICED family is selected): rows

@@ -208,7 +208,18 @@ __global__ __launch_bounds__(kBlock) void k_spmv_vector(int n, const int32_t *__
 // costs 10 bytes instead of CSR's 12 (FP32: 6 instead of 8); this is the
 // index compression Challenge A7 points to.  Rows shorter than their slice
 // are padded; padding is never multiplied (per-row length test).
+//
+// Shared offsets (stencil-like matrices): when the rows of every slice use
+// between them at most 32 distinct column offsets, each slice stores its
+// sorted offset list once (int32, one per position) and each row a 32-bit
+// mask of the positions it occupies, the other positions holding zeros.
+// An FP64 nonzero then costs 8 bytes plus 4 per row and 4 per slice
+// position (FP32: 4), a row's entries still sit in column order and only
+// masked positions are multiplied, so the sums are the same as with
+// per-lane offsets.  Gathers of unmasked positions read a clamped valid
+// element of x and are discarded.
 constexpr int kSell = 64;
+constexpr int kSellSharedMax = 32;
 
 // Element of entry k of lane `lane` in a slice of w entries per row,
 // relative to the slice's first element.
@@ -232,6 +243,8 @@ struct SellView {
     int plain;             // load policy of offsets and values, see kSellPlain64/32
     const uint16_t *len16; // row lengths when some row has more than 255 entries
     const int32_t *perm;   // SELL-C-sigma: matrix row of each sorted position, or null
+    const uint32_t *mask;  // shared offsets: per-row position masks (col then holds
+                           // each slice's int32 offsets at element ptr[s] / 64), or null
 };
 
 // Load policy of the SELL entries.  A matrix whose stored entries fit well
@@ -258,14 +271,39 @@ __device__ __forceinline__ T sell_ld(const T *p)
 // from the widest slice (3 for a 7-point stencil: one round and the tail).
 // gat(j) is the gathered operand at column j: x[j] for a plain product; the
 // fused PCG kernels form p = z + beta p there.
-template <class V, class CI, int UP, bool NT, class G>
+//
+// SH (shared offsets, CI = int32): the offsets come from the slice's list
+// (wave-uniform, scalar loads), rlen is the row's position mask, and gathered
+// columns are clamped into [0, n) for the positions the row does not use.
+template <class V, class CI, int UP, bool NT, bool SH, class G>
 __device__ __forceinline__ V sell_row(const SellView &sv, const V *__restrict__ val, G &&gat,
-                                      int32_t b, int slen, int rlen, int lane, int row)
+                                      int32_t b, int slen, int rlen, int lane, int row, int n)
 {
+    static_assert(!SH || std::is_same<CI, int32_t>::value, "shared offsets are int32");
     using CP = typename Pair2<CI>::type;
     using VP = typename Pair2<V>::type;
     const CP *__restrict__ cp = reinterpret_cast<const CP *>(reinterpret_cast<const CI *>(sv.col) + b) + lane;
+    const int32_t *__restrict__ ou =
+        reinterpret_cast<const int32_t *>(sv.col) + (__builtin_amdgcn_readfirstlane(b) >> 6);
     const VP *__restrict__ vp = reinterpret_cast<const VP *>(val + b) + lane;
+    auto offsets = [&](int p) -> CP {
+        if constexpr (SH) {
+            CP c;
+            c.x = ou[2 * p];
+            c.y = ou[2 * p + 1];
+            return c;
+        } else {
+            return sell_ld<NT>(cp + (size_t)p * kSell);
+        }
+    };
+    auto column = [&](int off) -> int {
+        if constexpr (SH) return min(max(row + off, 0), n - 1);
+        else return row + off;
+    };
+    auto real = [&](int k) -> bool {
+        if constexpr (SH) return ((unsigned)rlen >> k) & 1u;
+        else return k < rlen;
+    };
     const int np = slen >> 1;
     // the odd last entry is loaded first and gathered with the first round,
     // so an odd width costs no extra memory round trip; it is added last
@@ -274,7 +312,8 @@ __device__ __forceinline__ V sell_row(const SellView &sv, const V *__restrict__ 
     V at = V(0), xt = V(0);
     if (odd) {
         const size_t t = (size_t)b + (size_t)np * (2 * kSell) + lane;
-        ct = sell_ld<NT>(reinterpret_cast<const CI *>(sv.col) + t);
+        if constexpr (SH) ct = ou[2 * np];
+        else ct = sell_ld<NT>(reinterpret_cast<const CI *>(sv.col) + t);
         at = sell_ld<NT>(val + t);
     }
     V acc = V(0);
@@ -284,28 +323,28 @@ __device__ __forceinline__ V sell_row(const SellView &sv, const V *__restrict__ 
 #pragma unroll
         for (int u = 0; u < UP; ++u) {
             const int p = p0 + u < np ? p0 + u : np - 1;
-            c[u] = sell_ld<NT>(cp + (size_t)p * kSell);
+            c[u] = offsets(p);
             a[u] = sell_ld<NT>(vp + (size_t)p * kSell);
         }
         V xv[2 * UP];
 #pragma unroll
         for (int u = 0; u < UP; ++u) {
-            xv[2 * u] = gat(row + (int)c[u].x);
-            xv[2 * u + 1] = gat(row + (int)c[u].y);
+            xv[2 * u] = gat(column((int)c[u].x));
+            xv[2 * u + 1] = gat(column((int)c[u].y));
         }
-        if (p0 == 0 && odd) xt = gat(row + (int)ct);
+        if (p0 == 0 && odd) xt = gat(column((int)ct));
 #pragma unroll
         for (int u = 0; u < UP; ++u) {
             const int k = 2 * (p0 + u);
             if (p0 + u < np) {
-                if (k < rlen) acc = fma(a[u].x, xv[2 * u], acc);
-                if (k + 1 < rlen) acc = fma(a[u].y, xv[2 * u + 1], acc);
+                if (real(k)) acc = fma(a[u].x, xv[2 * u], acc);
+                if (real(k + 1)) acc = fma(a[u].y, xv[2 * u + 1], acc);
             }
         }
     }
     if (odd) {
-        if (np == 0) xt = gat(row + (int)ct);
-        if (slen - 1 < rlen) acc = fma(at, xt, acc);
+        if (np == 0) xt = gat(column((int)ct));
+        if (real(slen - 1)) acc = fma(at, xt, acc);
     }
     return acc;
 }
@@ -316,16 +355,18 @@ __device__ __forceinline__ V sell_row(const SellView &sv, const V *__restrict__ 
 // flight at any moment are adjacent in memory (one DRAM stream front rather
 // than one per block).  The first slice's header is loaded before go() is
 // asked whether to run (go holds no barrier: waves may own different counts).
-template <class V, class CI, int U, bool NT, class G, class Go, class Fn>
+template <class V, class CI, int U, bool NT, bool SH, class G, class Go, class Fn>
 __device__ __forceinline__ void sell_slices_run(int n, int s, int stride, const SellView &sv,
                                                 const V *__restrict__ val, G &&gat, Go &&go, Fn &&fn)
 {
     const int lane = threadIdx.x & (kWave - 1);
     const int ns = (n + kSell - 1) / kSell;
     // position j = 64 s + lane of the layout holds matrix row perm[j]
-    // (SELL-C-sigma) or row j; its length is in len or len16
+    // (SELL-C-sigma) or row j; its length is in len or len16 (its position
+    // mask in mask with shared offsets)
     auto head = [&](int j, int &rlen, int &row) {
-        rlen = j < n ? (sv.len16 ? (int)sv.len16[j] : (int)sv.len[j]) : 0;
+        if constexpr (SH) rlen = j < n ? (int)sv.mask[j] : 0;
+        else rlen = j < n ? (sv.len16 ? (int)sv.len16[j] : (int)sv.len[j]) : 0;
         row = j < n && sv.perm ? sv.perm[j] : j;
     };
     int32_t b = 0, e = 0;
@@ -338,7 +379,7 @@ __device__ __forceinline__ void sell_slices_run(int n, int s, int stride, const 
     if (!go()) return;
     while (s < ns) {
         const int slen = (e - b) / kSell;
-        if (s * kSell + lane < n) fn(row, sell_row<V, CI, U, NT>(sv, val, gat, b, slen, rlen, lane, row));
+        if (s * kSell + lane < n) fn(row, sell_row<V, CI, U, NT, SH>(sv, val, gat, b, slen, rlen, lane, row, n));
         s += stride;
         if (s >= ns) break;
         b = sv.ptr[s];
@@ -354,10 +395,16 @@ template <class V, class CI, int U, class G, class Go, class Fn>
 __device__ __forceinline__ void sell_slices_g(int n, int s, int stride, const SellView &sv,
                                               const V *__restrict__ val, G &&gat, Go &&go, Fn &&fn)
 {
-    if (sv.plain & (sizeof(V) == 4 ? kSellPlain32 : kSellPlain64))
-        sell_slices_run<V, CI, U, false>(n, s, stride, sv, val, gat, go, fn);
-    else
-        sell_slices_run<V, CI, U, true>(n, s, stride, sv, val, gat, go, fn);
+    const bool plain = sv.plain & (sizeof(V) == 4 ? kSellPlain32 : kSellPlain64);
+    if constexpr (std::is_same<CI, int32_t>::value) {
+        if (sv.mask) {
+            if (plain) sell_slices_run<V, CI, U, false, true>(n, s, stride, sv, val, gat, go, fn);
+            else sell_slices_run<V, CI, U, true, true>(n, s, stride, sv, val, gat, go, fn);
+            return;
+        }
+    }
+    if (plain) sell_slices_run<V, CI, U, false, false>(n, s, stride, sv, val, gat, go, fn);
+    else sell_slices_run<V, CI, U, true, false>(n, s, stride, sv, val, gat, go, fn);
 }
 
 // The plain product: the gathered operand is x.
@@ -438,6 +485,28 @@ __global__ void k_sell_fill(int n, const int32_t *__restrict__ rowptr,
             const bool real = a + j < e;
             scol[d] = real ? (CI)(col[a + j] - r) : (CI)0;
             sval[d] = real ? val[a + j] : 0.0;
+        }
+    }
+}
+
+// Shared-offset fill: row i (no permutation) has the positions of the set
+// bits of mask[i] in its slice's offset list, in column order; its k-th
+// entry goes to the position of the k-th set bit, the other positions get
+// zeros.
+static __global__ void k_sell_fill_shared(int n, const int32_t *__restrict__ rowptr,
+                                          const double *__restrict__ val, const int32_t *__restrict__ sptr,
+                                          const uint32_t *__restrict__ mask, double *__restrict__ sval)
+{
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const int s = i / kSell, lane = i % kSell;
+        const int b = sptr[s];
+        const int w = (sptr[s + 1] - b) / kSell;
+        const uint32_t m = mask[i];
+        int k = rowptr[i];
+        for (int j = 0; j < w; ++j) {
+            const bool real = (m >> j) & 1u;
+            sval[(size_t)b + sell_pos(j, w, lane)] = real ? val[k] : 0.0;
+            k += real;
         }
     }
 }

@@ -86,7 +86,7 @@ __global__ __launch_bounds__(kBlock) void k_sr_spmv_sell(SrDesc a, int m)
     const int i = a.sc->base + m;
     const double *__restrict__ u = d.z;
     double *__restrict__ w = d.q;
-    const SellView sv{d.sell_ptr, d.sell_col, d.sell_len, d.sell_plain, d.sell_len16, d.sell_perm};
+    const SellView sv{d.sell_ptr, d.sell_col, d.sell_len, d.sell_plain, d.sell_len16, d.sell_perm, d.sell_mask};
     const bool run = gate_ok(g, kGateInner64);
     double wu = 0.0;
     sell_slices<double, CI, U>(d.n, sell_first((int)blockIdx.x), d.nblk * (kBlock / kWave), sv, d.sell_val, u,

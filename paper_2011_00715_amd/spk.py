@@ -37,6 +37,8 @@ PREC_FP64, PREC_MIXED, PREC_MIXED_IR = 0, 1, 2
 MAT_MIXED, MAT_VALIDATE, MAT_BORROW, MAT_STREAM = 1, 2, 4, 8
 KERNEL_AUTO, KERNEL_STREAM, KERNEL_VECTOR, KERNEL_MERGE, KERNEL_SELL, KERNEL_SLICED = 0, 1, 2, 3, 4, 5
 KERNEL_SELL_SIGMA = 6
+# spk_mat_set_kernel parameter of SPK_KERNEL_SELL: column offsets shared per slice
+SELL_SHARED = 1
 KERNEL_NAMES = {1: "stream", 2: "vector", 3: "merge", 4: "sell", 5: "sliced", 6: "sell_sigma"}
 OK, EINVAL, ENOMEM, EHIP, EZERODIAG, EBUSY, EBUDGET, ENOTFOUND = 0, -1, -2, -3, -4, -5, -6, -7
 CONVERGED_RTOL, CONVERGED_ATOL = 1, 2

@@ -82,7 +82,7 @@ def test_c2_spmv_and_pcg():
     A = spkgen.laplace3d7(128)
     assert (A.n, A.nnz) == (2097152, 14581760)
     M = mat_on_gpu(spk, A, flags=spk.MAT_MIXED)
-    assert spk.KERNEL_NAMES[M.info.kernel] == "sell" and M.info.lanes == 16  # int16 offsets
+    assert spk.KERNEL_NAMES[M.info.kernel] == "sell" and M.info.lanes == 0  # offsets shared per slice
     # bit-exact on integer data, 1e-14 on the bench's x (rhs of seed 0); FP32
     # values bit-exact on integers, 16 FP32 ulps of the row scale on the rhs
     xi = np.random.default_rng(3).integers(-100, 100, A.n).astype(np.float64)

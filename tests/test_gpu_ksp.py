@@ -155,6 +155,40 @@ def test_pcg_fused_iteration_equals_three_kernels(case, prec):
     assert np.array_equal(xf2, xf) and rf2.iterations == rf.iterations
 
 
+@pytest.mark.parametrize("case", ["lap3d_30", "lap2d_90", "diff27_14", "diff27_100_wide"])
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_pcg_shared_offsets_same_bits(case, prec):
+    """The shared-offset SELL layout (the automatic choice on stencils) and
+    per-lane int16 offsets give the same solves bit for bit, in FP64 and
+    mixed precision, on the fused iteration, the three-kernel one and (27-point
+    100^3: more stored entries than 1024 blocks' lanes take 96 each) the wide
+    product."""
+    spk = need_gpu()
+    A = {"lap3d_30": spkgen.laplace3d7(30, shift=0.05), "lap2d_90": spkgen.laplace2d5(90),
+         "diff27_14": spkgen.diffusion3d27_lognormal(14, seed=4),
+         "diff27_100_wide": spkgen.diffusion3d27_lognormal(100, seed=2)}[case]
+    p = {"fp64": spk.PREC_FP64, "mixed": spk.PREC_MIXED}[prec]
+    b = spkgen.rhs_uniform(A.n, 3)
+    res = []
+    for param in (spk.SELL_SHARED, 16):
+        M = mat_on_gpu(spk, A, flags=spk.MAT_MIXED)
+        spk.mat_set_kernel(M, spk.KERNEL_SELL, param)
+        assert (M.info.lanes == 0) == (param == spk.SELL_SHARED)
+        if case.endswith("_wide"):
+            assert M.info.stored_nnz > 96 * 256 * 1024  # the wide product's rule
+        for prof in (0, 1):
+            x, r, h = _solve(spk, M, b, precision=p, hist_len=64, profile=prof)
+            res.append((x, (r.reason, r.iterations, r.inner_iterations, r.outer_steps), h))
+        M.close()
+    x0, r0, h0 = res[0]
+    assert r0[0] == spk.CONVERGED_RTOL
+    for x, r, h in res[1:]:
+        assert np.array_equal(x, x0) and r == r0
+        assert np.array_equal(h, h0, equal_nan=True)
+    bn = oracle.nrm2(b)
+    assert oracle.nrm2(b - oracle.spmv(A, x0)) <= 1e-8 * bn * (1 + 1e-6)
+
+
 @pytest.mark.parametrize("edge", ["maxit_5", "restarts", "x0"])
 def test_pcg_fused_iteration_edge_cases(edge):
     """The fused and three-kernel iterations agree bit for bit where a solve

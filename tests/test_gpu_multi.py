@@ -41,19 +41,20 @@ def _dev2(a):
     return torch.from_numpy(np.ascontiguousarray(a)).cuda()
 
 
-@pytest.mark.parametrize("kernel", ["auto", "sell", "sell32"])
+@pytest.mark.parametrize("kernel", ["auto", "sell", "sell16", "sell32"])
 @pytest.mark.parametrize("k", [1, 2, 4, 8, 16])
 def test_spmm_parity(k, kernel):
-    """kernel "sell": the SELL-64 walk with int16 offsets (slices of up to
+    """kernel "sell": the SELL-64 walk with the automatic offsets (shared per
+    slice on the stencils, int16 per lane on the others; slices of up to
     three pairs gathered in one round, wider ones pipelined; LDS-staged
-    stores); "sell32": the same with int32 offsets."""
+    stores); "sell16" / "sell32": per-lane int16 / int32 offsets."""
     spk = need_gpu()
     import torch
 
     for name, A, integer in _mats():
         M = mat_on_gpu(spk, A)
         if kernel != "auto":
-            spk.mat_set_kernel(M, spk.KERNEL_SELL, 32 if kernel == "sell32" else 0)
+            spk.mat_set_kernel(M, spk.KERNEL_SELL, {"sell": 0, "sell16": 16, "sell32": 32}[kernel])
         rng = np.random.default_rng(k)
         if integer:
             X = rng.integers(-50, 50, size=(A.n, k)).astype(np.float64)
@@ -79,12 +80,13 @@ def _cases():
     yield "powerlaw_20k", spkgen.powerlaw_spd(20000, seed=1)
 
 
-@pytest.mark.parametrize("kernel", ["auto", "sell", "sell32"])
+@pytest.mark.parametrize("kernel", ["auto", "sell", "sell16", "sell32"])
 @pytest.mark.parametrize("case", ["lap2d_64", "lap3d_24", "diff27_14", "powerlaw_20k"])
 def test_multi_solve_parity(case, kernel):
-    """auto: k = 4 on the automatic kernel; sell / sell32: k = 8 on the
-    SELL-64 layout with int16 / int32 offsets (the pipelined, staged product
-    and its flat p.q partials)."""
+    """auto: k = 4 on the automatic kernel; sell / sell16 / sell32: k = 8 on
+    the SELL-64 layout with automatic (shared on the stencils) / int16 /
+    int32 offsets (the pipelined, staged product and its flat p.q
+    partials)."""
     spk = need_gpu()
     import torch
 
@@ -92,7 +94,7 @@ def test_multi_solve_parity(case, kernel):
     M = mat_on_gpu(spk, A)
     k = 4
     if kernel != "auto":
-        spk.mat_set_kernel(M, spk.KERNEL_SELL, 32 if kernel == "sell32" else 0)
+        spk.mat_set_kernel(M, spk.KERNEL_SELL, {"sell": 0, "sell16": 16, "sell32": 32}[kernel])
         k = 8
     B = np.stack([spkgen.rhs_uniform(A.n, s) for s in range(k)], axis=1)
     X = torch.zeros((A.n, k), dtype=torch.float64, device="cuda")

@@ -12,7 +12,7 @@ from gpu_util import U32, U64, check_spmv, mat_on_gpu, need_gpu, spmv_bound_rows
 pytestmark = pytest.mark.gpu
 
 KERNELS = [("auto", 0), ("stream", 0), ("stream", 64), ("stream", 8), ("merge", 0), ("sell", 0),
-           ("sell", 32), ("sell_sigma", 0), ("sell_sigma", 64), ("sell_sigma", 1024), ("sliced", 0),
+           ("sell", 1), ("sell", 16), ("sell", 32), ("sell_sigma", 0), ("sell_sigma", 64), ("sell_sigma", 1024), ("sliced", 0),
            ("sliced", 1), ("sliced", 16), ("sliced", 2048)] + [("vector", L) for L in (1, 2, 4, 8, 16, 32, 64)]
 
 
@@ -21,8 +21,19 @@ def _set(spk, M, kernel, param):
         return spk.KERNEL_NAMES[M.info.kernel], M.info.lanes
     k = {"stream": spk.KERNEL_STREAM, "vector": spk.KERNEL_VECTOR, "merge": spk.KERNEL_MERGE,
          "sell": spk.KERNEL_SELL, "sliced": spk.KERNEL_SLICED, "sell_sigma": spk.KERNEL_SELL_SIGMA}[kernel]
+    if kernel == "sell" and param == spk.SELL_SHARED:
+        # shared offsets: refused (EINVAL) where a slice's rows use more than 32 offsets
+        try:
+            spk.mat_set_kernel(M, k, param)
+        except spk.SpkError as e:
+            assert e.status == spk.EINVAL
+            return None, None
+        assert M.info.lanes == 0
+        return kernel, 0
     spk.mat_set_kernel(M, k, param)
     assert spk.KERNEL_NAMES[M.info.kernel] == kernel
+    if kernel == "sell" and param:
+        assert M.info.lanes == param
     if kernel == "sell_sigma":
         assert M.info.sell_sigma == (param or 4096)
     return kernel, M.info.lanes
@@ -70,8 +81,8 @@ def test_spmv_parity_fp64(kernel, param):
 
 
 @pytest.mark.parametrize("kernel,param", [("auto", 0), ("stream", 0), ("merge", 0), ("vector", 4),
-                                          ("vector", 64), ("sell", 0), ("sell_sigma", 512), ("sliced", 0),
-                                          ("sliced", 2048)])
+                                          ("vector", 64), ("sell", 0), ("sell", 1), ("sell", 16),
+                                          ("sell_sigma", 512), ("sliced", 0), ("sliced", 2048)])
 def test_spmv_parity_fp32(kernel, param):
     spk = need_gpu()
     for name, A, integer in _matrices():
@@ -467,3 +478,91 @@ def test_cache_flush_reads_only():
     assert torch.equal(s, ref)
     with pytest.raises(spk.SpkError):
         spk.cache_flush(s[:1])  # fewer than 16 bytes
+
+
+def _shared_layout(A):
+    """Slice widths and offset lists of the shared-offset layout, or None when
+    a slice's rows use more than 32 distinct offsets (host restatement of the
+    layout's definition, for the byte and entry counts)."""
+    widths, nlist = [], 0
+    for s0 in range(0, A.n, 64):
+        offs = set()
+        for r in range(s0, min(A.n, s0 + 64)):
+            offs.update(int(c) - r for c in A.col[A.rowptr[r]:A.rowptr[r + 1]])
+        if len(offs) > 32:
+            return None
+        widths.append(len(offs))
+        nlist += len(offs)
+    return widths, nlist
+
+
+def test_spmv_sell_shared_offsets():
+    """Shared offsets (one offset list per slice, a position mask per row)
+    against per-lane int16 offsets on the same matrices: the same bits in
+    FP64 and FP32 (the row's entries in the same order, unused positions
+    never multiplied), stored entries and format bytes as the layout defines
+    them; gathers of unused positions near row 0 and row n - 1 stay in
+    bounds (ragged last slice); matrices whose slices need more than 32
+    offsets or whose rows are unsorted keep per-lane offsets under the
+    automatic choice and are refused when shared offsets are forced."""
+    spk = need_gpu()
+    mats = [("lap2d_61_ragged", spkgen.laplace2d5(61)), ("lap3d_23", spkgen.laplace3d7(23)),
+            ("diff27_13", spkgen.diffusion3d27_lognormal(13, seed=1))]
+    for name, A in mats:
+        lay = _shared_layout(A)
+        assert lay is not None, name
+        widths, nlist = lay
+        x = spkgen.rhs_uniform(A.n, 4)
+        outs = []
+        for param in (spk.SELL_SHARED, 16):
+            M = mat_on_gpu(spk, A, flags=spk.MAT_MIXED)
+            spk.mat_set_kernel(M, spk.KERNEL_SELL, param)
+            info = M.info
+            if param == spk.SELL_SHARED:
+                assert info.lanes == 0
+                stored = 64 * sum(widths)
+                assert info.stored_nnz == stored
+                ns = (A.n + 63) // 64
+                assert info.format_bytes_spmv_f64 == 8 * stored + 4 * (ns + 1) + 16 * A.n + 4 * nlist + 4 * A.n
+            y = to_dev(np.full(A.n, np.nan))
+            spk.mat_mult(M, to_dev(x), y)
+            y32 = to_dev(np.full(A.n, np.nan, dtype=np.float32))
+            spk.mat_mult_f32(M, to_dev(x.astype(np.float32)), y32)
+            outs.append((y.cpu().numpy(), y32.cpu().numpy()))
+            M.close()
+        assert np.array_equal(outs[0][0].view(np.int64), outs[1][0].view(np.int64)), name
+        assert np.array_equal(outs[0][1].view(np.int32), outs[1][1].view(np.int32)), name
+        scale = oracle.spmv_abs(A, x)
+        check_spmv(outs[0][0], oracle.spmv(A, x), scale, spmv_bound_rows(A, "sell", 0, U64), name)
+    # a slice whose rows use more than 32 offsets between them
+    rng = np.random.default_rng(3)
+    A = spkgen.powerlaw_spd(3000, seed=2)
+    assert _shared_layout(A) is None
+    M = mat_on_gpu(spk, A)
+    with pytest.raises(spk.SpkError) as e:
+        spk.mat_set_kernel(M, spk.KERNEL_SELL, spk.SELL_SHARED)
+    assert e.value.status == spk.EINVAL
+    spk.mat_set_kernel(M, spk.KERNEL_SELL, 0)
+    assert M.info.lanes == 16
+    M.close()
+    # unsorted rows: per-lane offsets keep each row's own order
+    L = spkgen.laplace2d5(20)
+    col = L.col.copy()
+    for r in range(0, L.n, 7):
+        a, b = L.rowptr[r], L.rowptr[r + 1]
+        col[a:b] = col[a:b][::-1]
+    val = L.val.copy()
+    for r in range(0, L.n, 7):
+        a, b = L.rowptr[r], L.rowptr[r + 1]
+        val[a:b] = val[a:b][::-1]
+    U = spkgen.CSR(L.n, L.rowptr, col, val)
+    M = mat_on_gpu(spk, U)
+    with pytest.raises(spk.SpkError):
+        spk.mat_set_kernel(M, spk.KERNEL_SELL, spk.SELL_SHARED)
+    spk.mat_set_kernel(M, spk.KERNEL_SELL, 0)
+    assert M.info.lanes == 16
+    xi = rng.integers(-9, 10, size=U.n).astype(np.float64)
+    y = to_dev(np.full(U.n, np.nan))
+    spk.mat_mult(M, to_dev(xi), y)
+    assert np.array_equal(y.cpu().numpy(), oracle.spmv(U, xi))
+    M.close()
