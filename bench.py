@@ -504,7 +504,7 @@ def bench_all(args):
     M2 = spk.mat_create_csr(dev(A2.rowptr), dev(A2.col), dev(A2.val), flags=spk.MAT_MIXED)
     M3 = spk.mat_create_csr(dev(A3.rowptr), dev(A3.col), dev(A3.val), flags=spk.MAT_MIXED)
     i2, i3 = M2.info, M3.info
-    assert spk.KERNEL_NAMES[i3.kernel] == "sell" and i3.lanes == 16 and wide_product(i3)
+    assert spk.KERNEL_NAMES[i3.kernel] == "sell" and i3.lanes in (0, 16) and wide_product(i3)
     bd2, bd3 = dev(b2), dev(b3)
     xs2 = dev(b2)
     ys2 = torch.empty_like(xs2)

@@ -570,7 +570,7 @@ static __global__ void k_m_restart(MultiDesc d, int32_t mask)
 // A: Q = A P, per-column per-block p.q (columns that stopped are multiplied
 // too: the matrix is read once either way; their partials are ignored).
 template <class CI, int K>
-__global__ __launch_bounds__(kBlock) void k_m_spmm_pq(MultiDesc d)
+__global__ __launch_bounds__(kBlock, K <= 8 ? 4 : 1) void k_m_spmm_pq(MultiDesc d)
 {
     __shared__ double sh[(kBlock / kWave) * K];
     __shared__ double stage[(kBlock / kWave) * kWave * (K > 1 ? K : 1)];
