@@ -411,14 +411,28 @@ __device__ __forceinline__ int multi_block(const MultiDesc &d, int &j)
 }
 
 // ------------------------------------------------------------------ SpMM
+// Physical block l runs on XCD l % 8.  Logical blocks in runs of R per XCD:
+// ((l / 8) / R) 8R + (l % 8) R + (l / 8) % R, a bijection when nblk is a
+// multiple of 8R (else the identity), so that R consecutive logical blocks
+// (4R consecutive slices for the SpMM) share an L2.
+__device__ __forceinline__ int xcd_runs(int l, int nblk, int R)
+{
+    if (nblk % (kXcd * R)) return l;
+    const int x = l % kXcd, k = l / kXcd;
+    return (k / R) * (kXcd * R) + x * R + k % R;
+}
+
 template <class CI, int K>
 __global__ __launch_bounds__(kBlock) void k_spmm(MultiDesc d, const double *__restrict__ X, double *__restrict__ Y)
 {
     __shared__ double stage[(kBlock / kWave) * kWave * (K > 1 ? K : 1)];
     int j;
-    const int l = multi_block(d, j);
+    int l = multi_block(d, j);
     if (l < 0) return;
     if (d.sell && K > 1) {
+        // runs of 4 blocks (16 slices) per XCD keep the +-1-line gathers of
+        // neighbouring slices in one L2
+        l = xcd_runs(l, d.nblk, 4);
         // flat stores of two elements (K is even): 1 KB per instruction
         using VP = typename Pair2<double>::type;
         const int lane = threadIdx.x & (kWave - 1);
