@@ -139,6 +139,9 @@ static MultiDesc solve_desc(const spk_mat *A, MultiWs *w)
 static void enqueue_multi_iter(const spk_mat *A, const MultiDesc &d, hipStream_t s)
 {
     const dim3 g(multi_nblk(A)), t(kBlock), cols(d.K);  // finalize: one block per column
+    // the p/x pass: about 1024 elements per block, at most kMultiPxBlocks
+    const dim3 gpx((unsigned)std::max<int64_t>(
+        1, std::min<int64_t>(kMultiPxBlocks, ((int64_t)A->n * d.K + 1023) / 1024)));
     with_multi(A, d.K, [&](auto ct, auto kc) {
         using CI = decltype(ct);
         constexpr int K = decltype(kc)::value;
@@ -146,7 +149,7 @@ static void enqueue_multi_iter(const spk_mat *A, const MultiDesc &d, hipStream_t
         hipLaunchKernelGGL(k_m_fin_pq, cols, t, 0, s, d);
         hipLaunchKernelGGL((k_m_update<K>), g, t, 0, s, d);
         hipLaunchKernelGGL(k_m_fin_update, cols, t, 0, s, d);
-        hipLaunchKernelGGL((k_m_px<K>), g, t, 0, s, d);
+        hipLaunchKernelGGL((k_m_px<K>), gpx, t, 0, s, d);
     });
 }
 

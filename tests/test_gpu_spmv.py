@@ -502,12 +502,26 @@ def test_spmv_sell_shared_offsets():
     FP64 and FP32 (the row's entries in the same order, unused positions
     never multiplied), stored entries and format bytes as the layout defines
     them; gathers of unused positions near row 0 and row n - 1 stay in
-    bounds (ragged last slice); matrices whose slices need more than 32
+    bounds (ragged last slice, a 3-row matrix); empty rows and an empty
+    slice give zeros; matrices whose slices need more than 32
     offsets or whose rows are unsorted keep per-lane offsets under the
     automatic choice and are refused when shared offsets are forced."""
     spk = need_gpu()
+    # rows emptied out of a 2D Laplacian: scattered empty rows and one whole
+    # empty slice (rows 640..703), which then has no offsets at all
+    L = spkgen.laplace2d5(40)
+    keep = np.ones(L.n, bool)
+    keep[::37] = False
+    keep[640:704] = False
+    lens = np.where(keep, np.diff(L.rowptr), 0)
+    rp = np.zeros(L.n + 1, np.int32)
+    rp[1:] = np.cumsum(lens)
+    sel = np.repeat(keep, np.diff(L.rowptr))
+    holes = spkgen.CSR(L.n, rp, L.col[sel].astype(np.int32), L.val[sel])
+    tri3 = spkgen.dense_to_csr(np.array([[4.0, -1, 0], [-1, 4, -1], [0, -1, 4]]))
     mats = [("lap2d_61_ragged", spkgen.laplace2d5(61)), ("lap3d_23", spkgen.laplace3d7(23)),
-            ("diff27_13", spkgen.diffusion3d27_lognormal(13, seed=1))]
+            ("diff27_13", spkgen.diffusion3d27_lognormal(13, seed=1)), ("lap2d_40_holes", holes),
+            ("tridiag_3", tri3)]
     for name, A in mats:
         lay = _shared_layout(A)
         assert lay is not None, name
