@@ -483,9 +483,11 @@ static void choose_kernel(spk_mat *A, bool allow_sell = true, bool allow_sliced 
     for (int t = 0; t < 6; ++t)
         if (S.tile_max[t] <= cap) { R = kTileRs[t]; break; }
     // SELL-64: short rows of similar length within each slice (stencils).
-    // No LDS staging, and with a band of +-32767 int16 offsets: 10 bytes per
-    // FP64 nonzero instead of 12 (wider bands keep int32 offsets and still
-    // beat the stream kernel: 171 against 195 us on a 200^3 7-point stencil)
+    // No LDS staging; column offsets shared per slice where the slices' rows
+    // use at most 32 of them (8 bytes per FP64 nonzero and 4 per row instead
+    // of CSR's 12), else int16 offsets per entry in a band of +-32767 (10
+    // bytes; wider bands keep int32 offsets and still beat the stream
+    // kernel: 171 against 195 us on a 200^3 7-point stencil)
     const bool sell_ok = allow_sell && A->n >= kSell && S.max_len <= 64 &&
                          (double)S.sell_padded <= 1.15 * (double)A->nnz &&
                          S.sell_padded < 0x7fff0000ULL;

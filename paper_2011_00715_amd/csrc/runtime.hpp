@@ -119,7 +119,7 @@ struct spk_mat {
     int32_t *tile_row = nullptr, *tile_k = nullptr, *carry_row = nullptr;
     double *carry_val = nullptr;
     // SELL-64 copy (built when the SELL family is selected)
-    int sell_cw = 0;           // column offset width: 2 (int16) or 4 (int32), 0 = none
+    int sell_cw = 0;           // column offset width: 2 (int16) or 4 (int32; shared offsets too), 0 = none
     int sell_u = 8;            // entries per load round of the SELL kernels (from the widest slice)
     int64_t sell_nnz = 0;      // stored entries including padding
     int sell_plain = 0;        // kSellPlain64/32 bits: ordinary loads in the Krylov and smoother kernels

@@ -238,7 +238,8 @@ template <> struct Pair2<int32_t> { typedef int type __attribute__((ext_vector_t
 
 struct SellView {
     const int32_t *ptr;    // element offset of each slice (nslices + 1)
-    const void *col;       // int16 or int32 row-relative column offsets
+    const void *col;       // int16 or int32 row-relative column offsets (per entry, or
+                           // per slice position with shared offsets)
     const uint8_t *len;    // row lengths (rows of at most 255 entries), or null
     int plain;             // load policy of offsets and values, see kSellPlain64/32
     const uint16_t *len16; // row lengths when some row has more than 255 entries
