@@ -840,7 +840,9 @@ def measured_stream_gbps(reps=10):
 
 def calibration_copy():
     """One plain copy of 256 MiB (known traffic: 256 MiB read + 256 MiB
-    written), so PMC byte counters can be scaled against it."""
+    written), so PMC byte counters can be scaled against it: the smallest
+    k_copy dispatch of a run (the streaming-bandwidth figure of the roofline
+    copies 1 GiB)."""
     import torch
 
     from paper_2011_00715_amd import spk
