@@ -217,8 +217,10 @@ int spk_mat_create_csr(int32_t n, int64_t nnz, const int32_t *rowptr,
  * columns, every slice's rows use at most 32 distinct offsets and the
  * stored entries grow by at most 1/16) or 0 (automatic: shared when the
  * matrix qualifies, which stencils do, else 16 when the offsets fit, else
- * 32), the window sigma for SELL_SIGMA (a multiple of 64;
- * 0 = 4096; offsets as for SELL with 0), for SLICED 0
+ * 32; deciding reads the column indices back to host memory once, 4 nnz
+ * bytes, when no row exceeds 32 entries), the window sigma for SELL_SIGMA
+ * (a multiple of 64; 0 = 4096; offsets per lane, 16 bits when they fit,
+ * else 32), for SLICED 0
  * (automatic: the merge path over the slices when 8n + nnz < 2^31, else
  * lanes per slice row), a power of two in 1..64 (lanes per slice row) or
  * 2048 (merge path over the slices), ignored for MERGE.
