@@ -58,8 +58,8 @@ def spmv_kernel_name(spk, info):
 def parse():
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
-    p.add_argument("--steps", type=int, default=10)
-    p.add_argument("--warmup", type=int, default=2)
+    p.add_argument("--steps", type=int, default=20)
+    p.add_argument("--warmup", type=int, default=5)
     p.add_argument("--workload", default="all", choices=["all", "c2", "c3", "c4", "serve", "spectrum", "mg"])
     p.add_argument("--spmvs", type=int, default=100)
     p.add_argument("--cold-spmvs", type=int, default=20,
