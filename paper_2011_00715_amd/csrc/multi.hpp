@@ -97,10 +97,16 @@ constexpr int kOneRoundPairs = 3;
 //
 // SH: shared offsets (see the SELL-64 notes): offsets from the slice's list,
 // rlen the row's position mask, gathered rows clamped into [0, n).
+//
+// pdiag (the pipelined walk only; null otherwise): where to keep the row's
+// own gathered X row, the gather of its diagonal entry (offset 0; the
+// solve's matrices have one in every row), so that the caller need not read
+// it again.
 template <class CI, int K, bool kOneRound = false, bool SH = false>
 __device__ __forceinline__ void sell_row_multi(const SellView &sv, const double *__restrict__ val,
                                                const double *__restrict__ X, int32_t b, int slen,
-                                               int rlen, int lane, int row, int n, double acc[K])
+                                               int rlen, int lane, int row, int n, double acc[K],
+                                               double *pdiag = nullptr)
 {
     static_assert(!SH || std::is_same<CI, int32_t>::value, "shared offsets are int32");
     constexpr int PM = K <= 8 ? kMultiPairs : 1;
@@ -145,6 +151,11 @@ __device__ __forceinline__ void sell_row_multi(const SellView &sv, const double 
     auto madd = [&](double a, const double xr[K]) {
 #pragma unroll
         for (int q = 0; q < K; ++q) acc[q] = fma(a, xr[q], acc[q]);
+    };
+    auto keep = [&](int off, const double xr[K]) {
+        if (pdiag && off == 0)
+#pragma unroll
+            for (int q = 0; q < K; ++q) pdiag[q] = xr[q];
     };
     if (kOneRound && K <= 8 && np <= kOneRoundPairs) {
         // every pair index is clamped into the slice (a slice without pairs
@@ -200,8 +211,14 @@ __device__ __forceinline__ void sell_row_multi(const SellView &sv, const double 
                 gather((int)c[u + 1].y, xb[1]);
             }
             if (u < np) {
-                if (real(2 * u)) madd(a[u].x, xa[0]);
-                if (real(2 * u + 1)) madd(a[u].y, xa[1]);
+                if (real(2 * u)) {
+                    madd(a[u].x, xa[0]);
+                    keep((int)c[u].x, xa[0]);
+                }
+                if (real(2 * u + 1)) {
+                    madd(a[u].y, xa[1]);
+                    keep((int)c[u].y, xa[1]);
+                }
             }
 #pragma unroll
             for (int q = 0; q < K; ++q) {
@@ -217,14 +234,21 @@ __device__ __forceinline__ void sell_row_multi(const SellView &sv, const double 
             double x0[K], x1[K];
             gather((int)c.x, x0);
             gather((int)c.y, x1);
-            if (real(2 * p)) madd(a.x, x0);
-            if (real(2 * p + 1)) madd(a.y, x1);
+            if (real(2 * p)) {
+                madd(a.x, x0);
+                keep((int)c.x, x0);
+            }
+            if (real(2 * p + 1)) {
+                madd(a.y, x1);
+                keep((int)c.y, x1);
+            }
         }
     }
     if (odd && real(slen - 1)) {
         double xt[K];
         gather((int)ct, xt);
         madd(at, xt);
+        keep((int)ct, xt);
     }
 }
 
@@ -238,7 +262,7 @@ __device__ __forceinline__ void sell_row_multi(const SellView &sv, const double 
 // ones (K = 8: 118 -> 99 us on the 7-point 128^3 product).
 template <class CI, int K, bool kOneRound, bool SH, class Flat>
 __device__ __forceinline__ void multi_sell_walk(const MultiDesc &d, int l, const double *__restrict__ X,
-                                                double *stage, Flat &&flat)
+                                                double *stage, double *pstage, Flat &&flat)
 {
     const int lane = threadIdx.x & (kWave - 1);
     const int ns = (d.n + kSell - 1) / kSell;
@@ -249,7 +273,7 @@ __device__ __forceinline__ void multi_sell_walk(const MultiDesc &d, int l, const
             double acc[K];
             const int rl = SH ? (int)d.sv.mask[row] : (int)d.sv.len[row];
             sell_row_multi<CI, K, kOneRound, SH>(d.sv, d.sell_val, X, b, (e - b) / kSell, rl, lane, row, d.n,
-                                                 acc);
+                                                 acc, pstage ? pstage + lane * K : nullptr);
 #pragma unroll
             for (int q = 0; q < K; ++q) stage[lane * K + q] = acc[q];
         }
@@ -265,15 +289,15 @@ __device__ __forceinline__ void multi_sell_walk(const MultiDesc &d, int l, const
 
 template <class CI, int K, bool kOneRound, class Flat>
 __device__ __forceinline__ void multi_sell_staged(const MultiDesc &d, int l, const double *__restrict__ X,
-                                                  double *stage, Flat &&flat)
+                                                  double *stage, double *pstage, Flat &&flat)
 {
     if constexpr (std::is_same<CI, int32_t>::value) {
         if (d.sv.mask) {
-            multi_sell_walk<CI, K, kOneRound, true>(d, l, X, stage, flat);
+            multi_sell_walk<CI, K, kOneRound, true>(d, l, X, stage, pstage, flat);
             return;
         }
     }
-    multi_sell_walk<CI, K, kOneRound, false>(d, l, X, stage, flat);
+    multi_sell_walk<CI, K, kOneRound, false>(d, l, X, stage, pstage, flat);
 }
 
 // Row walk of block l (of nblk) of a multi kernel: SELL slices in
@@ -437,7 +461,7 @@ __global__ __launch_bounds__(kBlock) void k_spmm(MultiDesc d, const double *__re
         using VP = typename Pair2<double>::type;
         const int lane = threadIdx.x & (kWave - 1);
         double *st = stage + (threadIdx.x / kWave) * kWave * K;
-        multi_sell_staged<CI, K, true>(d, l, X, st, [&](int64_t e0, int cnt) {
+        multi_sell_staged<CI, K, true>(d, l, X, st, nullptr, [&](int64_t e0, int cnt) {
             const VP *src = reinterpret_cast<const VP *>(st);
             VP *dst = reinterpret_cast<VP *>(Y + e0);
             for (int t = lane; t < cnt / 2; t += kWave) __builtin_nontemporal_store(src[t], dst + t);
@@ -588,6 +612,11 @@ __global__ __launch_bounds__(kBlock, K <= 8 ? 4 : 1) void k_m_spmm_pq(MultiDesc 
 {
     __shared__ double sh[(kBlock / kWave) * K];
     __shared__ double stage[(kBlock / kWave) * kWave * (K > 1 ? K : 1)];
+    // each row's own P row, kept from its diagonal gather (every row of a
+    // solved matrix has one): the flat pass's p.q reads it here instead of
+    // fetching P a second time (the rows were gathered moments before, but
+    // read again from memory they cost a third of the kernel's traffic)
+    __shared__ double pstage[(kBlock / kWave) * kWave * (K > 1 ? K : 1)];
     int j;
     const int l = multi_block(d, j);
     if (l < 0) return;
@@ -601,10 +630,12 @@ __global__ __launch_bounds__(kBlock, K <= 8 ? 4 : 1) void k_m_spmm_pq(MultiDesc 
         double pqv = 0.0;
         const int lane = threadIdx.x & (kWave - 1);
         const double *st = stage + (threadIdx.x / kWave) * kWave * K;
+        const double *pst = pstage + (threadIdx.x / kWave) * kWave * K;
         multi_sell_staged<CI, K, false>(d, l, P, stage + (threadIdx.x / kWave) * kWave * K,
+                                        pstage + (threadIdx.x / kWave) * kWave * K,
                                         [&](int64_t e0, int cnt) {
                                             for (int t = lane; t < cnt; t += kWave) {
-                                                const double v = st[t], pe = P[e0 + t];
+                                                const double v = st[t], pe = pst[t];
                                                 Q[e0 + t] = v;
                                                 pqv = fma(v, pe, pqv);
                                             }
